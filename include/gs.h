@@ -1,0 +1,239 @@
+/*
+ * gs.h - C ABI of libgsmi, an MI355X (gfx950) differentiable tile-based
+ * 3D Gaussian rasterizer.
+ *
+ * The library implements the rendering function R(M, T) that GEVO evaluates
+ * to re-render past keyframes from the Gaussian map instead of storing them
+ * (Sec. I; Sec. III-B2, the photometric-consistency loss E_pc over rendered
+ * past views), and the gradients of a photometric loss with respect to the
+ * map and the camera pose that the local and global mapping objectives
+ * minimise over (Eq. 2 and Eq. 3).  The renderer itself is the Gaussian
+ * splatting rasterizer the paper builds on (Sec. I, Sec. IV-C); the exact
+ * definition implemented here is:
+ *
+ *   activations   s = exp(log_scale), q / |q|, o = sigmoid(opacity_logit)
+ *   covariance    Sigma = (R(q) diag(s)) (R(q) diag(s))^T
+ *   view          p = R_cw mu + t_cw; culled if p_z <= 0.2
+ *   projection    u = fx p_x / p_z + cx, v = fy p_y / p_z + cy;
+ *                 pixel (i, j) is sampled at its centre (i + 1/2, j + 1/2)
+ *   EWA           Sigma' = J R_cw Sigma R_cw^T J^T + 0.3 I, with p_x/p_z and
+ *                 p_y/p_z clamped to +-1.3 W/(2 fx), +-1.3 H/(2 fy) inside J;
+ *                 conic Q = Sigma'^-1
+ *   extent        r = ceil(3 sqrt(lambda_max(Sigma'))) pixels
+ *   tiles         every tile holding a pixel centre in [u-r, u+r] x [v-r, v+r]
+ *   colour        real spherical harmonics (degree 0..3, Condon-Shortley
+ *                 phase, ordered l, m = -l..l) of the unit direction from the
+ *                 camera centre to mu, plus 1/2, clamped below at 0
+ *   order         per tile ascending (camera-frame depth, Gaussian index)
+ *   blending      front to back: power = -1/2 d^T Q d (skip if > 0),
+ *                 alpha = min(0.99, o e^power) (skip if < 1/255), stop before
+ *                 the transmittance would fall below 1e-4;
+ *                 C = sum_i alpha_i T_i c_i + T_final bg.
+ *                 alpha_i T_i is the blending weight w(g, u) of Sec. III-B2.
+ *
+ * Conventions
+ *   - Every entry point returns a gs_status; no exception crosses the ABI.
+ *     On GS_ERR_HIP the HIP error text is available from gs_last_error()
+ *     (thread-local).
+ *   - The caller owns all memory.  The library allocates no device memory:
+ *     scratch comes from *_workspace_size() followed by a caller pointer
+ *     (device memory, 256-byte aligned).
+ *   - Pointers named *_dev and every array inside the structs below are
+ *     device pointers unless stated otherwise.
+ *   - Work is enqueued asynchronously on the caller's stream.  The only call
+ *     that synchronises is gs_bin_sort with a non-NULL n_keys_host.
+ *   - Arguments are validated before anything is enqueued; a failed call
+ *     enqueues nothing.
+ *   - Gradient outputs are accumulated (+=) so that several calls (views)
+ *     sum; the caller zeroes them.
+ *   - Calls are reentrant; calls that share output or workspace buffers on
+ *     different streams race.
+ *   - Floating-point work is IEEE float32 (pose gradients are reduced in
+ *     float64).
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* hipStream_t; NULL selects the null stream. */
+typedef struct ihipStream_t* gs_stream_t;
+
+typedef enum gs_status {
+  GS_OK = 0,
+  GS_ERR_INVALID_ARGUMENT = 1, /* null pointer, bad size, bad enum            */
+  GS_ERR_CAPACITY = 2,         /* caller buffer too small; size reported      */
+  GS_ERR_HIP = 3,              /* HIP runtime error; see gs_last_error()      */
+  GS_ERR_UNSUPPORTED = 4       /* valid but unsupported configuration         */
+} gs_status;
+
+#define GS_MAX_VIEWS 64
+#define GS_MAX_SH_DEGREE 3
+
+/* Pinhole camera (80 bytes).  R is world->camera, row-major; (R, t) maps a
+ * world point mu to p = R mu + t with x right, y down, z forward. */
+typedef struct gs_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  int32_t pad[2];
+} gs_camera;
+
+/* Gaussian map, structure of arrays, component-major float32 (device):
+ *   means [3][n], log_scales [3][n], quats [4][n] in (w, x, y, z) order (not
+ *   necessarily normalised), opacity_logits [n], sh [3][K][n] with
+ *   K = (sh_degree + 1)^2.  Non-finite parameters or a zero quaternion cull
+ *   the Gaussian. */
+typedef struct gs_gaussians {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const float* sh;
+  int64_t n;
+  int32_t sh_degree;
+} gs_gaussians;
+
+/* A batch of views.  cams_host (host memory) supplies image sizes, which fix
+ * the tile layout; cams_dev (device memory, same contents) supplies poses and
+ * intrinsics to the kernels, so a caller may update poses on the device
+ * between launches as long as sizes do not change.  Views are packed in
+ * order: global tile ids start at sum of previous views' tile counts, pixel
+ * buffers at sum of previous views' W*H.  tile_size must be 16. */
+typedef struct gs_views {
+  const gs_camera* cams_host;
+  const gs_camera* cams_dev;
+  int32_t n_views;   /* 1 .. GS_MAX_VIEWS */
+  int32_t tile_size; /* 16 */
+} gs_views;
+
+/* Per-(view, Gaussian) screen-space splats, [V][n] each (device):
+ *   xy            float2: u, v
+ *   conic_opacity float4: Q00, Q01, Q11, o
+ *   rgb_depth     float4: r, g, b, camera-frame z
+ *   radius        int32:  r in pixels, 0 = culled */
+typedef struct gs_projected {
+  float* xy;
+  float* conic_opacity;
+  float* rgb_depth;
+  int32_t* radius;
+} gs_projected;
+
+/* Tile binning result (device):
+ *   keys   [capacity] uint64 (global tile << 32) | float32 bits of depth,
+ *          ascending; ties ordered by value
+ *   values [capacity] uint32 view * n + Gaussian index
+ *   ranges [n_tiles][2] uint32 [start, end) into keys/values per global tile
+ *   n_keys [1] uint32 number of keys emitted (may exceed capacity, in which
+ *          case the call reported or flagged overflow and keys are partial) */
+typedef struct gs_bins {
+  uint64_t* keys;
+  uint32_t* values;
+  uint32_t* ranges;
+  uint32_t* n_keys;
+  int64_t capacity;
+} gs_bins;
+
+/* Gradients, same layouts as gs_gaussians, accumulated (+=).  xi [V][6]
+ * float32 is dL/dxi for a left perturbation T_cw <- Exp(xi) T_cw at xi = 0,
+ * xi = (rho, phi), translation first.  Any pointer may be NULL only when the
+ * corresponding flag excludes it (see gs_render_bwd). */
+typedef struct gs_grads {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* sh;
+  float* xi;
+} gs_grads;
+
+enum {
+  GS_BWD_NO_POSE = 1u,   /* skip the pose gradient (xi may be NULL)            */
+  GS_BWD_POSE_ONLY = 2u  /* only the pose gradient (map grads may be NULL)      */
+};
+
+/* Short name of a status code (static string). */
+const char* gs_status_string(int status);
+/* Text of the last GS_ERR_* raised on this thread (static per-thread buffer). */
+const char* gs_last_error(void);
+/* Library version string. */
+const char* gs_version(void);
+
+/* Total tiles and pixels of a view batch (host-only, validates views; < 0 on
+ * invalid input). */
+int64_t gs_num_tiles(const gs_views* views);
+int64_t gs_num_pixels(const gs_views* views);
+
+/* Projection of every Gaussian into every view (the activations, covariance,
+ * view transform, projection, EWA, extent and colour steps above).
+ * out arrays hold [n_views][n] entries.  Culled entries get radius 0 and
+ * zeroed splat fields. */
+int gs_preprocess(const gs_gaussians* g, const gs_views* views, gs_projected* out,
+                  gs_stream_t stream);
+
+/* Scratch for gs_bin_sort (bytes). */
+size_t gs_bin_sort_workspace_size(int64_t n, const gs_views* views, int64_t capacity);
+
+/* Tile binning and sorting of the splats in p ([n_views][n]): counts the
+ * tiles of each splat's rectangle, scans, emits one key per (splat, tile)
+ * in splat-major, row-major order, radix-sorts keys ascending (stable, so
+ * equal keys keep ascending value order) and writes per-tile ranges.
+ * n_keys_host != NULL: synchronises once to read the key count; if it
+ * exceeds bins->capacity, *n_keys_host holds the required capacity, nothing
+ * further is enqueued and GS_ERR_CAPACITY is returned.
+ * n_keys_host == NULL: no synchronisation (capture-safe); keys beyond the
+ * capacity are dropped and bins->n_keys reports the full count, which the
+ * caller must check against the capacity after the stream completes. */
+int gs_bin_sort(const gs_projected* p, int64_t n, const gs_views* views, gs_bins* bins,
+                uint32_t* n_keys_host, void* workspace, size_t workspace_bytes,
+                gs_stream_t stream);
+
+/* Forward compositing of every tile of every view.
+ * image [3][H][W] per view (planar, views packed), final_T [H][W] and
+ * n_contrib [H][W] (1 + list position of the last blended splat, 0 if none)
+ * per view; depth (optional, may be NULL) = sum_i w_i z_i per pixel.
+ * bg: host pointer to 3 floats, or NULL for black. */
+int gs_render_fwd(const gs_projected* p, int64_t n, const gs_bins* bins, const gs_views* views,
+                  const float* bg, float* image, float* final_T, uint32_t* n_contrib,
+                  float* depth, gs_stream_t stream);
+
+/* Scratch for gs_render_bwd (bytes). */
+size_t gs_render_bwd_workspace_size(int64_t n, const gs_views* views);
+
+/* Backward of gs_render_fwd and gs_preprocess: given dL/dimage (layout of
+ * image) and the forward's final_T and n_contrib, walks each tile's list in
+ * reverse recovering the transmittance, reduces per-splat gradients over each
+ * wavefront and accumulates them with atomics, then chains them per Gaussian
+ * to the map parameters (summed over views) and to each view's pose tangent.
+ * flags: 0 or GS_BWD_NO_POSE or GS_BWD_POSE_ONLY. */
+int gs_render_bwd(const gs_gaussians* g, const gs_projected* p, const gs_bins* bins,
+                  const gs_views* views, const float* bg, const float* dL_dimage,
+                  const float* final_T, const uint32_t* n_contrib, gs_grads* grads,
+                  uint32_t flags, void* workspace, size_t workspace_bytes, gs_stream_t stream);
+
+/* One bias-corrected Adam step over n float32 parameters, in place:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * mask (optional, uint8 [n]): entries with mask 0 are left untouched (the
+ * hook for optimising only an active subset of Gaussians, Sec. III-B2). */
+int gs_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                 float beta1, float beta2, float eps, int32_t step, const uint8_t* mask,
+                 gs_stream_t stream);
+
+/* L1 photometric loss L = sum over views of mean |C - C*| over 3 H W, and
+ * dL/dC = sign(C - C*) / (3 H W) (sign(0) = 0), for every view (layouts of
+ * image).  loss (optional, device float64 [1]) is overwritten with L. */
+int gs_l1_loss_grad(const float* image, const float* target, const gs_views* views,
+                    float* dL_dimage, double* loss, gs_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

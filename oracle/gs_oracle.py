@@ -368,27 +368,33 @@ def _tile_pixels(cam, tile_size, tx, ty):
 
 def composite(rows: torch.Tensor, depth: torch.Tensor, vals: np.ndarray, ranges: np.ndarray,
               bases, cams, tile_size: int, bg, dL_dimage=None, with_mask=True,
-              tile_mask=None):
+              tile_mask=None, tiles=None):
     """Composite every tile of every view.
 
     rows: (V*N, 9) float64 (u, v, Q00, Q01, Q11, o, r, g, b), a leaf if
     gradients are wanted; depth (V*N,) float64.  dL_dimage: per-view (3,H,W)
     arrays or None.  Per-tile backward accumulates into rows.grad.
     tile_mask: optional per-view (TY, TX) bool arrays of tiles to flag.
+    tiles: optional per-view collections of (ty, tx) to composite; pixels of
+    other tiles are left NaN (image, T_final, depth) / -1 (n_contrib).
     Returns per-view lists: image (3,H,W), T_final, n_contrib, depth, mask."""
     bg_t = _t(bg)
     out = []
     for vi, cam in enumerate(cams):
         W, H = int(cam.width), int(cam.height)
         TX, TY = tile_grid(cam, tile_size)
-        img = np.zeros((3, H, W))
-        Tf = np.ones((H, W))
-        nc = np.zeros((H, W), np.int64)
-        dimg = np.zeros((H, W))
+        fill = np.nan if tiles is not None else 0.0
+        img = np.full((3, H, W), fill)
+        Tf = np.full((H, W), np.nan if tiles is not None else 1.0)
+        nc = np.full((H, W), -1 if tiles is not None else 0, np.int64)
+        dimg = np.full((H, W), fill)
         msk = np.zeros((H, W), bool)
         g = None if dL_dimage is None else _t(dL_dimage[vi])
+        want = None if tiles is None else set(tiles[vi])
         for ty in range(TY):
             for tx in range(TX):
+                if want is not None and (ty, tx) not in want:
+                    continue
                 gt = bases[vi] + ty * TX + tx
                 s0, s1 = int(ranges[gt, 0]), int(ranges[gt, 1])
                 xx, yy = _tile_pixels(cam, tile_size, tx, ty)
@@ -483,7 +489,7 @@ def _ambiguous_tiles(P, cam, tile_size):
 
 
 def render(gmap, cams, tile_size: int = 16, bg=(0.0, 0.0, 0.0), dL_dimage=None,
-           with_mask=True, want_pose_grad=True):
+           with_mask=True, want_pose_grad=True, tiles=None):
     """Full pipeline from Gaussian parameters (scenes.GaussianMap, float32
     arrays read as float64) for a list of cameras.
 
@@ -520,7 +526,8 @@ def render(gmap, cams, tile_size: int = 16, bg=(0.0, 0.0, 0.0), dL_dimage=None,
     dz = [P["z"].detach().numpy().astype(np.float32) for P in projs]
     keys, vals, ranges, bases, _ = bin_splats(xy, dz, radius, cams, tile_size)
     tmask = [_ambiguous_tiles(P, cam, tile_size) for P, cam in zip(projs, cams)] if with_mask else None
-    res = composite(rows, depth, vals, ranges, bases, cams, tile_size, bg, dL_dimage, with_mask, tmask)
+    res = composite(rows, depth, vals, ranges, bases, cams, tile_size, bg, dL_dimage, with_mask, tmask,
+                    tiles)
     result = dict(views=res, keys=keys, values=vals, ranges=ranges, bases=bases,
                   proj=[{k: (val.detach().numpy() if torch.is_tensor(val) else val) for k, val in P.items()}
                         for P in projs])

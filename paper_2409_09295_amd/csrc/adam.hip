@@ -1,0 +1,127 @@
+// gs_adam_step and gs_l1_loss_grad: elementwise, HBM-bound kernels.
+//
+// Adam streams p, g, m, v once (16 B read, 12 B written per parameter) with
+// 16-byte vector accesses when the four arrays are 16-byte aligned.
+#include "gs_internal.h"
+
+namespace gsmi {
+
+namespace {
+
+struct AdamCoef {
+  float lr, b1, b2, eps, inv_bc1, inv_bc2;
+};
+
+__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, const AdamCoef& c) {
+  m = c.b1 * m + (1.0f - c.b1) * g;
+  v = c.b2 * v + (1.0f - c.b2) * g * g;
+  const float mhat = m * c.inv_bc1;
+  const float vhat = v * c.inv_bc2;
+  p -= c.lr * mhat / (sqrtf(vhat) + c.eps);
+}
+
+__global__ __launch_bounds__(256) void adam_vec4_kernel(float4* __restrict__ p,
+                                                        const float4* __restrict__ g,
+                                                        float4* __restrict__ m,
+                                                        float4* __restrict__ v, int64_t n4,
+                                                        AdamCoef c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n4) return;
+  float4 pp = p[i], gg = g[i], mm = m[i], vv = v[i];
+  adam_one(pp.x, gg.x, mm.x, vv.x, c);
+  adam_one(pp.y, gg.y, mm.y, vv.y, c);
+  adam_one(pp.z, gg.z, mm.z, vv.z, c);
+  adam_one(pp.w, gg.w, mm.w, vv.w, c);
+  p[i] = pp;
+  m[i] = mm;
+  v[i] = vv;
+}
+
+__global__ __launch_bounds__(256) void adam_scalar_kernel(float* __restrict__ p,
+                                                          const float* __restrict__ g,
+                                                          float* __restrict__ m,
+                                                          float* __restrict__ v, int64_t begin,
+                                                          int64_t n, const uint8_t* __restrict__ mask,
+                                                          AdamCoef c) {
+  const int64_t i = begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (mask && mask[i] == 0) return;
+  float pp = p[i], mm = m[i], vv = v[i];
+  adam_one(pp, g[i], mm, vv, c);
+  p[i] = pp;
+  m[i] = mm;
+  v[i] = vv;
+}
+
+__global__ __launch_bounds__(256) void l1_grad_kernel(const float* __restrict__ image,
+                                                      const float* __restrict__ target,
+                                                      ViewTable vt, float* __restrict__ grad,
+                                                      double* __restrict__ loss) {
+  __shared__ float s_wave[4];
+  const int v = blockIdx.y;
+  const ViewInfo& vi = vt.v[v];
+  const int64_t count = 3 * (int64_t)vi.width * vi.height;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float a = 0.0f;
+  if (i < count) {
+    const int64_t o = 3 * vi.pix_base + i;
+    const float d = image[o] - target[o];
+    const float inv = 1.0f / (float)count;
+    grad[o] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
+    a = fabsf(d);
+  }
+  if (loss == nullptr) return;
+  if ((int64_t)blockIdx.x * blockDim.x >= count) return;   // whole block idle (uniform)
+  for (int d = 32; d > 0; d >>= 1) a += __shfl_xor(a, d, 64);
+  if ((threadIdx.x & 63) == 0) s_wave[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double sum = (double)s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    atomicAdd(loss, sum / (double)count);
+  }
+}
+
+__global__ void zero_f64_kernel(double* p) { *p = 0.0; }
+
+}  // namespace
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                       float beta1, float beta2, float eps, int32_t step, const uint8_t* mask,
+                       hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  AdamCoef c;
+  c.lr = lr;
+  c.b1 = beta1;
+  c.b2 = beta2;
+  c.eps = eps;
+  c.inv_bc1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
+  c.inv_bc2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
+  const bool aligned = ((reinterpret_cast<uintptr_t>(p) | reinterpret_cast<uintptr_t>(g) |
+                         reinterpret_cast<uintptr_t>(m) | reinterpret_cast<uintptr_t>(v)) & 15) == 0;
+  int64_t begin = 0;
+  if (aligned && mask == nullptr) {
+    const int64_t n4 = n / 4;
+    if (n4 > 0)
+      hipLaunchKernelGGL(adam_vec4_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
+                         reinterpret_cast<float4*>(p), reinterpret_cast<const float4*>(g),
+                         reinterpret_cast<float4*>(m), reinterpret_cast<float4*>(v), n4, c);
+    begin = n4 * 4;
+  }
+  if (begin < n)
+    hipLaunchKernelGGL(adam_scalar_kernel, dim3((unsigned)((n - begin + 255) / 256)), dim3(256), 0,
+                       s, p, g, m, v, begin, n, mask, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_l1_loss_grad(const float* image, const float* target, const ViewTable& vt,
+                               float* dL_dimage, double* loss, hipStream_t s) {
+  int64_t max_count = 0;
+  for (int v = 0; v < vt.n_views; ++v)
+    max_count = std::max<int64_t>(max_count, 3 * (int64_t)vt.v[v].width * vt.v[v].height);
+  if (loss) hipLaunchKernelGGL(zero_f64_kernel, dim3(1), dim3(1), 0, s, loss);
+  hipLaunchKernelGGL(l1_grad_kernel, dim3((unsigned)((max_count + 255) / 256), vt.n_views),
+                     dim3(256), 0, s, image, target, vt, dL_dimage, loss);
+  return hipGetLastError();
+}
+
+}  // namespace gsmi

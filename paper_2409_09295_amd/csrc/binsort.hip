@@ -1,0 +1,455 @@
+// gs_bin_sort: tile binning and (tile, depth) ordering of the splats.
+//
+//   count     one lane per (view, splat): tile rectangle (float64 from the
+//             float32 centre) -> number of tiles
+//   scan      device-wide exclusive scan of the counts (reduce / scan
+//             partials / down-sweep), total in 64 bits
+//   emit      wave-cooperative emission: the 64 splats of a wave own a
+//             contiguous key range; the wave walks that range 64 keys at a
+//             time and each lane locates its owner by binary search over the
+//             wave's 64 start offsets, so stores are contiguous and big
+//             rectangles do not serialise one lane
+//   sort      LSD radix sort, 8-bit digits over the used key bits
+//             (32 depth bits + ceil(log2 tiles) tile bits).  Per pass: block
+//             histograms, a scan of the digit-major histogram, then a
+//             down-sweep that ranks keys within the block with wave ballots
+//             (stable), stages them in LDS in digit order and writes each
+//             digit run contiguously
+//   ranges    [start, end) per global tile from tile boundaries in the
+//             sorted keys
+#include "gs_internal.h"
+
+namespace gsmi {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanChunk = kScanThreads * kScanItems;   // 4096
+constexpr int kSortItems = 8;
+constexpr int kSortChunk = 256 * kSortItems;            // 2048
+constexpr int kPartThreads = 1024;
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
+
+// Inclusive scan over the 64 lanes of a wave.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const T y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block; returns the
+// exclusive prefix and writes the block total to *total (all threads).
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T x, T* s_wave, T& total) {
+  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  const T inc = wave_inclusive_scan(x);
+  if (lane == 63) s_wave[w] = inc;
+  __syncthreads();
+  T pre = 0, tot = 0;
+  for (uint32_t k = 0; k < 4; ++k) {
+    const T s = s_wave[k];
+    pre += (k < w) ? s : (T)0;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + inc - x;
+}
+
+// ---------------------------------------------------------------------------
+// generic exclusive scan of uint32 values (out may alias in)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in,
+                                                                   int64_t n,
+                                                                   uint64_t* __restrict__ partial) {
+  __shared__ uint64_t s_wave[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint64_t acc = 0;
+#pragma unroll
+  for (int r = 0; r < kScanItems; ++r) {
+    const int64_t idx = base + r * kScanThreads + threadIdx.x;
+    acc += (idx < n) ? in[idx] : 0u;
+  }
+  uint64_t tot;
+  block_exclusive_scan<uint64_t>(acc, s_wave, tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// One block: exclusive scan of nb partials in place; total to *total and,
+// if n_keys != nullptr, min(total, 2^32 - 1) to *n_keys.
+__global__ __launch_bounds__(kPartThreads) void scan_partials_kernel(uint64_t* __restrict__ partial,
+                                                                     int64_t nb,
+                                                                     uint64_t* __restrict__ total,
+                                                                     uint32_t* __restrict__ n_keys) {
+  __shared__ uint64_t s_wave[kPartThreads / 64];
+  const int64_t per = (nb + kPartThreads - 1) / kPartThreads;
+  const int64_t lo = threadIdx.x * per, hi = min(lo + per, nb);
+  uint64_t sum = 0;
+  for (int64_t k = lo; k < hi; ++k) sum += partial[k];
+  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  const uint64_t inc = wave_inclusive_scan(sum);
+  if (lane == 63) s_wave[w] = inc;
+  __syncthreads();
+  uint64_t pre = 0, tot = 0;
+  for (uint32_t k = 0; k < kPartThreads / 64; ++k) {
+    pre += (k < w) ? s_wave[k] : 0;
+    tot += s_wave[k];
+  }
+  uint64_t run = pre + inc - sum;
+  for (int64_t k = lo; k < hi; ++k) {
+    const uint64_t x = partial[k];
+    partial[k] = run;
+    run += x;
+  }
+  if (threadIdx.x == 0) {
+    *total = tot;
+    if (n_keys) *n_keys = tot > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tot;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t* in, int64_t n,
+                                                                 const uint64_t* __restrict__ partial,
+                                                                 uint32_t* out) {
+  __shared__ uint32_t s_wave[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  uint32_t carry = (uint32_t)partial[blockIdx.x];
+  for (int r = 0; r < kScanItems; ++r) {
+    const int64_t idx = base + r * kScanThreads + threadIdx.x;
+    const uint32_t x = (idx < n) ? in[idx] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<uint32_t>(x, s_wave, tot);
+    if (idx < n) out[idx] = carry + ex;
+    carry += tot;
+  }
+}
+
+void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint64_t* partial, uint64_t* total,
+              uint32_t* n_keys, hipStream_t s) {
+  const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+  if (nb > 0)
+    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n,
+                       partial);
+  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kPartThreads), 0, s, partial, nb, total,
+                     n_keys);
+  if (nb > 0)
+    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n,
+                       partial, out);
+}
+
+// ---------------------------------------------------------------------------
+// count / emit
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t value,
+                                                       int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+__global__ __launch_bounds__(256) void count_kernel(const float2* __restrict__ xy,
+                                                    const int32_t* __restrict__ radius,
+                                                    int64_t n_entries, int64_t n, ViewTable vt,
+                                                    uint32_t* __restrict__ counts) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_entries) return;
+  const int v = (int)(e / n);
+  const ViewInfo& vi = vt.v[v];
+  Rect rc;
+  const float2 c = xy[e];
+  const bool ok = tile_rect(c.x, c.y, radius[e], vi.width, vi.height, rc);
+  counts[e] = ok ? (uint32_t)((rc.x1 - rc.x0) * (rc.y1 - rc.y0)) : 0u;
+}
+
+__global__ __launch_bounds__(256) void emit_kernel(const float2* __restrict__ xy,
+                                                   const int32_t* __restrict__ radius,
+                                                   const float4* __restrict__ rd,
+                                                   const uint32_t* __restrict__ offsets,
+                                                   int64_t n_entries, int64_t n, ViewTable vt,
+                                                   const uint64_t* __restrict__ total,
+                                                   int64_t capacity, uint64_t* __restrict__ keys,
+                                                   uint32_t* __restrict__ vals) {
+  if (*total > (uint64_t)capacity) return;  // overflow: nothing is emitted
+  __shared__ uint32_t s_start[4][64];
+  __shared__ uint32_t s_t0[4][64];
+  __shared__ uint32_t s_w[4][64];
+  __shared__ uint32_t s_tx[4][64];
+  __shared__ uint32_t s_db[4][64];
+  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t start = 0xFFFFFFFFu, cnt = 0, t0 = 0, rw = 1, tx = 1, db = 0;
+  if (e < n_entries) {
+    const int v = (int)(e / n);
+    const ViewInfo& vi = vt.v[v];
+    Rect rc;
+    const float2 c = xy[e];
+    const bool ok = tile_rect(c.x, c.y, radius[e], vi.width, vi.height, rc);
+    start = offsets[e];
+    if (ok) {
+      cnt = (uint32_t)((rc.x1 - rc.x0) * (rc.y1 - rc.y0));
+      t0 = (uint32_t)(vi.tile_base + rc.y0 * vi.tiles_x + rc.x0);
+      rw = (uint32_t)(rc.x1 - rc.x0);
+      tx = (uint32_t)vi.tiles_x;
+      db = __float_as_uint(rd[e].w);
+    }
+  }
+  s_start[w][lane] = start;
+  s_t0[w][lane] = t0;
+  s_w[w][lane] = rw;
+  s_tx[w][lane] = tx;
+  s_db[w][lane] = db;
+  // wave range [first start, last end)
+  const bool valid = e < n_entries;
+  const uint64_t vmask = __ballot(valid);
+  if (vmask == 0) return;
+  const uint32_t wbase = __shfl(start, 0, 64);
+  const uint32_t last = 63 - __clzll(vmask);
+  const uint32_t wend = __shfl(start + cnt, last, 64);
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int64_t ebase = (int64_t)blockIdx.x * blockDim.x + w * 64;
+  for (uint32_t pos = wbase + lane; pos < wend; pos += 64) {
+    int lo = 0, hi = (int)last;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_start[w][mid] <= pos) lo = mid; else hi = mid - 1;
+    }
+    const uint32_t j = pos - s_start[w][lo];
+    const uint32_t width = s_w[w][lo];
+    const uint32_t row = j / width;
+    const uint32_t tile = s_t0[w][lo] + row * s_tx[w][lo] + (j - row * width);
+    keys[pos] = ((uint64_t)tile << 32) | (uint64_t)s_db[w][lo];
+    vals[pos] = (uint32_t)(ebase + lo);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// radix sort
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t valid_keys(const uint32_t* n_keys, int64_t capacity) {
+  const uint32_t n = *n_keys;
+  return ((int64_t)n <= capacity) ? n : 0u;
+}
+
+__global__ __launch_bounds__(256) void radix_upsweep_kernel(const uint64_t* __restrict__ keys,
+                                                            const uint32_t* __restrict__ n_keys,
+                                                            int64_t capacity, int shift,
+                                                            uint32_t* __restrict__ hist,
+                                                            uint32_t nblocks) {
+  __shared__ uint32_t h[4][256];
+  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  for (int k = threadIdx.x; k < 4 * 256; k += 256) (&h[0][0])[k] = 0;
+  __syncthreads();
+  const uint32_t n = valid_keys(n_keys, capacity);
+  const int64_t base = (int64_t)blockIdx.x * kSortChunk + w * (kSortChunk / 4);
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t idx = base + j * 64 + lane;
+    if (idx < n) atomicAdd(&h[w][(uint32_t)(keys[idx] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  const uint32_t t = threadIdx.x;
+  hist[(int64_t)t * nblocks + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
+}
+
+__global__ __launch_bounds__(256) void radix_downsweep_kernel(
+    const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+    const uint32_t* __restrict__ n_keys, int64_t capacity, int shift,
+    const uint32_t* __restrict__ hist, uint32_t nblocks) {
+  __shared__ uint32_t s_wcnt[4][256];
+  __shared__ uint32_t s_wpre[4][256];
+  __shared__ uint32_t s_dstart[256];
+  __shared__ uint32_t s_gbase[256];
+  __shared__ uint32_t s_wave[4];
+  __shared__ uint64_t s_keys[kSortChunk];
+  __shared__ uint32_t s_vals[kSortChunk];
+  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  for (int k = threadIdx.x; k < 4 * 256; k += 256) (&s_wcnt[0][0])[k] = 0;
+  __syncthreads();
+  const uint32_t n = valid_keys(n_keys, capacity);
+  const int64_t bstart = (int64_t)blockIdx.x * kSortChunk;
+  const int64_t base = bstart + w * (kSortChunk / 4);
+  uint64_t key[kSortItems];
+  uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t idx = base + j * 64 + lane;
+    const bool valid = idx < n;
+    key[j] = valid ? keys_in[idx] : 0ull;
+    val[j] = valid ? vals_in[idx] : 0u;
+    const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
+    dig[j] = d;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t r_in = (uint32_t)__popcll(peers & lt);
+    uint32_t before = 0;
+    if (valid) before = s_wcnt[w][d];
+    __builtin_amdgcn_wave_barrier();
+    if (valid && r_in == 0) s_wcnt[w][d] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    rank[j] = before + r_in;
+  }
+  __syncthreads();
+  {
+    const uint32_t t = threadIdx.x;
+    const uint32_t c0 = s_wcnt[0][t], c1 = s_wcnt[1][t], c2 = s_wcnt[2][t], c3 = s_wcnt[3][t];
+    s_wpre[0][t] = 0;
+    s_wpre[1][t] = c0;
+    s_wpre[2][t] = c0 + c1;
+    s_wpre[3][t] = c0 + c1 + c2;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<uint32_t>(c0 + c1 + c2 + c3, s_wave, tot);
+    s_dstart[t] = ex;
+    s_gbase[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const int64_t idx = base + j * 64 + lane;
+    if (idx < n) {
+      const uint32_t lp = s_dstart[dig[j]] + s_wpre[w][dig[j]] + rank[j];
+      s_keys[lp] = key[j];
+      s_vals[lp] = val[j];
+    }
+  }
+  __syncthreads();
+  const int64_t nb_valid = min((int64_t)kSortChunk, (int64_t)n - bstart);
+#pragma unroll
+  for (int q = 0; q < kSortItems; ++q) {
+    const int pos = q * 256 + threadIdx.x;
+    if (pos < nb_valid) {
+      const uint64_t k = s_keys[pos];
+      const uint32_t d = (uint32_t)(k >> shift) & 255u;
+      const uint32_t o = s_gbase[d] + (uint32_t)pos - s_dstart[d];
+      keys_out[o] = k;
+      vals_out[o] = s_vals[pos];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void ranges_kernel(const uint64_t* __restrict__ keys,
+                                                     const uint32_t* __restrict__ n_keys,
+                                                     int64_t capacity, uint32_t* __restrict__ ranges) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t n = valid_keys(n_keys, capacity);
+  if (i >= n) return;
+  const uint32_t tile = (uint32_t)(keys[i] >> 32);
+  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != tile) ranges[2 * (int64_t)tile] = (uint32_t)i;
+  if (i == (int64_t)n - 1 || (uint32_t)(keys[i + 1] >> 32) != tile)
+    ranges[2 * (int64_t)tile + 1] = (uint32_t)(i + 1);
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, value,
+                     n);
+  return hipGetLastError();
+}
+
+BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity) {
+  BinSortPlan P{};
+  P.n_entries = n * vt.n_views;
+  P.capacity = capacity;
+  P.n_tiles = vt.n_tiles;
+  int tile_bits = 0;
+  while ((int64_t(1) << tile_bits) < (int64_t)vt.n_tiles) ++tile_bits;
+  P.passes = (32 + tile_bits + 7) / 8;
+  P.scan_blocks = (P.n_entries + kScanChunk - 1) / kScanChunk;
+  P.sort_blocks = (capacity + kSortChunk - 1) / kSortChunk;
+  const int64_t hist_n = 256 * std::max<int64_t>(P.sort_blocks, 1);
+  const int64_t hist_part = (hist_n + kScanChunk - 1) / kScanChunk;
+  size_t off = 0;
+  P.off_counts = off;    off += align_up(sizeof(uint32_t) * P.n_entries);
+  P.off_offsets = off;   off += align_up(sizeof(uint32_t) * P.n_entries);
+  P.off_scan_part = off; off += align_up(sizeof(uint64_t) * (P.scan_blocks + 1));
+  P.off_keys_alt = off;  off += align_up(sizeof(uint64_t) * capacity);
+  P.off_vals_alt = off;  off += align_up(sizeof(uint32_t) * capacity);
+  P.off_hist = off;      off += align_up(sizeof(uint32_t) * hist_n);
+  P.off_hist_part = off; off += align_up(sizeof(uint64_t) * (hist_part + 1));
+  P.off_flag = off;      off += align_up(sizeof(uint64_t) * 4);
+  P.total = off;
+  return P;
+}
+
+int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs_bins& bins,
+                 uint32_t* n_keys_host, char* ws, const BinSortPlan& P, hipStream_t s) {
+  auto* counts = reinterpret_cast<uint32_t*>(ws + P.off_counts);
+  auto* offsets = reinterpret_cast<uint32_t*>(ws + P.off_offsets);
+  auto* part = reinterpret_cast<uint64_t*>(ws + P.off_scan_part);
+  auto* keys_alt = reinterpret_cast<uint64_t*>(ws + P.off_keys_alt);
+  auto* vals_alt = reinterpret_cast<uint32_t*>(ws + P.off_vals_alt);
+  auto* hist = reinterpret_cast<uint32_t*>(ws + P.off_hist);
+  auto* hist_part = reinterpret_cast<uint64_t*>(ws + P.off_hist_part);
+  auto* flag = reinterpret_cast<uint64_t*>(ws + P.off_flag);   // [0] total keys, [1] scratch
+  const auto* xy = reinterpret_cast<const float2*>(p.xy);
+  const auto* rd = reinterpret_cast<const float4*>(p.rgb_depth);
+  hipError_t e;
+
+  if ((e = launch_fill_u32(bins.ranges, 0u, 2 * (int64_t)vt.n_tiles, s)) != hipSuccess)
+    return hip_fail(e, "fill ranges");
+  if (P.n_entries > 0)
+    hipLaunchKernelGGL(count_kernel, dim3((unsigned)((P.n_entries + 255) / 256)), dim3(256), 0, s,
+                       xy, p.radius, P.n_entries, n, vt, counts);
+  scan_u32(counts, offsets, P.n_entries, part, flag, bins.n_keys, s);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "count/scan launch");
+
+  int64_t n_sort = P.capacity;   // keys the sort grid covers
+  if (n_keys_host) {
+    uint64_t total = 0;
+    if ((e = hipMemcpyAsync(&total, flag, sizeof(uint64_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return hip_fail(e, "read key count");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "synchronise key count");
+    *n_keys_host = total > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)total;
+    if (total > (uint64_t)P.capacity) {
+      set_error("gs_bin_sort: %llu keys exceed capacity %lld", (unsigned long long)total,
+                (long long)P.capacity);
+      return GS_ERR_CAPACITY;
+    }
+    n_sort = (int64_t)total;
+  }
+  if (n_sort == 0) return GS_OK;
+
+  uint64_t* kA = (P.passes % 2 == 0) ? bins.keys : keys_alt;
+  uint32_t* vA = (P.passes % 2 == 0) ? bins.values : vals_alt;
+  uint64_t* kB = (P.passes % 2 == 0) ? keys_alt : bins.keys;
+  uint32_t* vB = (P.passes % 2 == 0) ? vals_alt : bins.values;
+  if (P.n_entries > 0)
+    hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((P.n_entries + 255) / 256)), dim3(256), 0, s,
+                       xy, p.radius, rd, offsets, P.n_entries, n, vt, flag, P.capacity, kA, vA);
+  const uint32_t nblocks = (uint32_t)((n_sort + kSortChunk - 1) / kSortChunk);
+  for (int pass = 0; pass < P.passes; ++pass) {
+    const int shift = 8 * pass;
+    hipLaunchKernelGGL(radix_upsweep_kernel, dim3(nblocks), dim3(256), 0, s, kA, bins.n_keys,
+                       P.capacity, shift, hist, nblocks);
+    scan_u32(hist, hist, 256 * (int64_t)nblocks, hist_part, flag + 1, nullptr, s);
+    hipLaunchKernelGGL(radix_downsweep_kernel, dim3(nblocks), dim3(256), 0, s, kA, vA, kB, vB,
+                       bins.n_keys, P.capacity, shift, hist, nblocks);
+    std::swap(kA, kB);
+    std::swap(vA, vB);
+  }
+  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((n_sort + 255) / 256)), dim3(256), 0, s,
+                     bins.keys, bins.n_keys, P.capacity, bins.ranges);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "bin sort launch");
+  return GS_OK;
+}
+
+}  // namespace gsmi

@@ -1,0 +1,257 @@
+// C ABI of libgsmi: argument validation, workspace planning and launches.
+// Every entry point validates all arguments before enqueuing anything.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "gs_internal.h"
+
+namespace gsmi {
+
+namespace {
+thread_local char g_last_error[512] = "";
+}
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  set_error("%s: %s", what, hipGetErrorString(e));
+  return GS_ERR_HIP;
+}
+
+namespace {
+
+int invalid(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return GS_ERR_INVALID_ARGUMENT;
+}
+
+constexpr int32_t kMaxImageSide = 16384;
+
+// Builds the per-view layout table from host cameras; returns a status.
+int build_view_table(const gs_views* views, ViewTable& vt) {
+  if (!views) return invalid("views is NULL");
+  if (views->n_views < 1 || views->n_views > GS_MAX_VIEWS)
+    return invalid("n_views = %d outside [1, %d]", views->n_views, GS_MAX_VIEWS);
+  if (!views->cams_host) return invalid("views->cams_host is NULL");
+  if (!views->cams_dev) return invalid("views->cams_dev is NULL");
+  if (views->tile_size != kTile) {
+    set_error("tile_size %d unsupported (16 only)", views->tile_size);
+    return GS_ERR_UNSUPPORTED;
+  }
+  std::memset(&vt, 0, sizeof(vt));
+  vt.n_views = views->n_views;
+  int64_t tiles = 0, pixels = 0;
+  for (int v = 0; v < views->n_views; ++v) {
+    const gs_camera& c = views->cams_host[v];
+    if (c.width < 1 || c.height < 1 || c.width > kMaxImageSide || c.height > kMaxImageSide)
+      return invalid("view %d: image size %dx%d outside [1, %d]", v, c.width, c.height,
+                     kMaxImageSide);
+    if (!(std::isfinite(c.fx) && std::isfinite(c.fy) && c.fx > 0.f && c.fy > 0.f &&
+          std::isfinite(c.cx) && std::isfinite(c.cy)))
+      return invalid("view %d: intrinsics must be finite with fx, fy > 0", v);
+    ViewInfo& vi = vt.v[v];
+    vi.width = c.width;
+    vi.height = c.height;
+    vi.tiles_x = (c.width + kTile - 1) / kTile;
+    vi.tiles_y = (c.height + kTile - 1) / kTile;
+    vi.tile_base = (int32_t)tiles;
+    vi.pix_base = pixels;
+    tiles += (int64_t)vi.tiles_x * vi.tiles_y;
+    pixels += (int64_t)c.width * c.height;
+  }
+  if (tiles > 0x7FFFFFFF) return invalid("too many tiles (%lld)", (long long)tiles);
+  vt.n_tiles = (int32_t)tiles;
+  vt.n_pixels = pixels;
+  return GS_OK;
+}
+
+int check_gaussians(const gs_gaussians* g, int n_views) {
+  if (!g) return invalid("gaussians is NULL");
+  if (g->n < 0) return invalid("n = %lld < 0", (long long)g->n);
+  if (g->sh_degree < 0 || g->sh_degree > GS_MAX_SH_DEGREE)
+    return invalid("sh_degree = %d outside [0, %d]", g->sh_degree, GS_MAX_SH_DEGREE);
+  if ((uint64_t)g->n * (uint64_t)n_views > 0xFFFFFFFFull)
+    return invalid("n * n_views = %lld exceeds 2^32 - 1", (long long)g->n * n_views);
+  if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
+    return invalid("a Gaussian parameter pointer is NULL");
+  return GS_OK;
+}
+
+int check_projected(const gs_projected* p, int64_t n) {
+  if (!p) return invalid("projected is NULL");
+  if (n > 0 && (!p->xy || !p->conic_opacity || !p->rgb_depth || !p->radius))
+    return invalid("a projected-splat pointer is NULL");
+  return GS_OK;
+}
+
+int check_bins(const gs_bins* b, bool need_keys) {
+  if (!b) return invalid("bins is NULL");
+  if (!b->ranges || !b->n_keys || !b->values || (need_keys && !b->keys))
+    return invalid("a bins pointer is NULL");
+  if (b->capacity < 0 || b->capacity > 0xFFFFFFFFll)
+    return invalid("capacity = %lld outside [0, 2^32 - 1]", (long long)b->capacity);
+  return GS_OK;
+}
+
+int check_workspace(const void* ws, size_t have, size_t need) {
+  if (have < need) {
+    set_error("workspace of %zu bytes is smaller than the %zu required", have, need);
+    return GS_ERR_CAPACITY;
+  }
+  if (need > 0 && !ws) return invalid("workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return invalid("workspace is not 256-byte aligned");
+  return GS_OK;
+}
+
+float3 read_bg(const float* bg) {
+  return bg ? make_float3(bg[0], bg[1], bg[2]) : make_float3(0.f, 0.f, 0.f);
+}
+
+}  // namespace
+}  // namespace gsmi
+
+using namespace gsmi;
+
+extern "C" {
+
+const char* gs_status_string(int status) {
+  switch (status) {
+    case GS_OK: return "GS_OK";
+    case GS_ERR_INVALID_ARGUMENT: return "GS_ERR_INVALID_ARGUMENT";
+    case GS_ERR_CAPACITY: return "GS_ERR_CAPACITY";
+    case GS_ERR_HIP: return "GS_ERR_HIP";
+    case GS_ERR_UNSUPPORTED: return "GS_ERR_UNSUPPORTED";
+    default: return "GS_ERR_UNKNOWN";
+  }
+}
+
+const char* gs_last_error(void) { return g_last_error; }
+
+const char* gs_version(void) { return "gsmi 0.1 (gfx950)"; }
+
+int64_t gs_num_tiles(const gs_views* views) {
+  ViewTable vt;
+  if (build_view_table(views, vt) != GS_OK) return -1;
+  return vt.n_tiles;
+}
+
+int64_t gs_num_pixels(const gs_views* views) {
+  ViewTable vt;
+  if (build_view_table(views, vt) != GS_OK) return -1;
+  return vt.n_pixels;
+}
+
+int gs_preprocess(const gs_gaussians* g, const gs_views* views, gs_projected* out,
+                  gs_stream_t stream) {
+  ViewTable vt;
+  int st = build_view_table(views, vt);
+  if (st) return st;
+  if ((st = check_gaussians(g, vt.n_views))) return st;
+  if ((st = check_projected(out, g->n))) return st;
+  const hipError_t e = launch_preprocess(*g, views->cams_dev, vt.n_views, *out, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_preprocess");
+}
+
+size_t gs_bin_sort_workspace_size(int64_t n, const gs_views* views, int64_t capacity) {
+  ViewTable vt;
+  if (n < 0 || capacity < 0 || build_view_table(views, vt) != GS_OK) return 0;
+  return make_bin_sort_plan(n, vt, capacity).total;
+}
+
+int gs_bin_sort(const gs_projected* p, int64_t n, const gs_views* views, gs_bins* bins,
+                uint32_t* n_keys_host, void* workspace, size_t workspace_bytes,
+                gs_stream_t stream) {
+  ViewTable vt;
+  int st = build_view_table(views, vt);
+  if (st) return st;
+  if (n < 0) return invalid("n = %lld < 0", (long long)n);
+  if ((uint64_t)n * (uint64_t)vt.n_views > 0xFFFFFFFFull)
+    return invalid("n * n_views exceeds 2^32 - 1");
+  if ((st = check_projected(p, n))) return st;
+  if ((st = check_bins(bins, true))) return st;
+  const BinSortPlan plan = make_bin_sort_plan(n, vt, bins->capacity);
+  if ((st = check_workspace(workspace, workspace_bytes, plan.total))) return st;
+  return run_bin_sort(*p, n, vt, *bins, n_keys_host, static_cast<char*>(workspace), plan, stream);
+}
+
+int gs_render_fwd(const gs_projected* p, int64_t n, const gs_bins* bins, const gs_views* views,
+                  const float* bg, float* image, float* final_T, uint32_t* n_contrib,
+                  float* depth, gs_stream_t stream) {
+  ViewTable vt;
+  int st = build_view_table(views, vt);
+  if (st) return st;
+  if (n < 0) return invalid("n = %lld < 0", (long long)n);
+  if ((st = check_projected(p, n))) return st;
+  if ((st = check_bins(bins, false))) return st;
+  if (!image || !final_T || !n_contrib) return invalid("an output pointer is NULL");
+  const hipError_t e =
+      launch_render_fwd(*p, *bins, vt, read_bg(bg), image, final_T, n_contrib, depth, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_render_fwd");
+}
+
+size_t gs_render_bwd_workspace_size(int64_t n, const gs_views* views) {
+  ViewTable vt;
+  if (n < 0 || build_view_table(views, vt) != GS_OK) return 0;
+  return make_bwd_plan(n, vt).total;
+}
+
+int gs_render_bwd(const gs_gaussians* g, const gs_projected* p, const gs_bins* bins,
+                  const gs_views* views, const float* bg, const float* dL_dimage,
+                  const float* final_T, const uint32_t* n_contrib, gs_grads* grads,
+                  uint32_t flags, void* workspace, size_t workspace_bytes, gs_stream_t stream) {
+  ViewTable vt;
+  int st = build_view_table(views, vt);
+  if (st) return st;
+  if ((st = check_gaussians(g, vt.n_views))) return st;
+  if ((st = check_projected(p, g->n))) return st;
+  if ((st = check_bins(bins, false))) return st;
+  if (flags & ~(uint32_t)(GS_BWD_NO_POSE | GS_BWD_POSE_ONLY)) return invalid("unknown flags");
+  if ((flags & GS_BWD_NO_POSE) && (flags & GS_BWD_POSE_ONLY))
+    return invalid("GS_BWD_NO_POSE and GS_BWD_POSE_ONLY are exclusive");
+  if (!dL_dimage || !final_T || !n_contrib || !grads) return invalid("an input pointer is NULL");
+  if (!(flags & GS_BWD_POSE_ONLY) && g->n > 0 &&
+      (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
+       !grads->sh))
+    return invalid("a map-gradient pointer is NULL");
+  if (!(flags & GS_BWD_NO_POSE) && !grads->xi) return invalid("grads->xi is NULL");
+  const BwdPlan plan = make_bwd_plan(g->n, vt);
+  if ((st = check_workspace(workspace, workspace_bytes, plan.total))) return st;
+  const hipError_t e =
+      launch_render_bwd(*g, *p, *bins, views->cams_dev, vt, read_bg(bg), dL_dimage, final_T,
+                        n_contrib, *grads, flags, static_cast<char*>(workspace), plan, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_render_bwd");
+}
+
+int gs_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr, float beta1,
+                 float beta2, float eps, int32_t step, const uint8_t* mask, gs_stream_t stream) {
+  if (n < 0) return invalid("n = %lld < 0", (long long)n);
+  if (n > 0 && (!p || !g || !m || !v)) return invalid("a parameter pointer is NULL");
+  if (step < 1) return invalid("step = %d < 1", step);
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f))
+    return invalid("betas must lie in [0, 1)");
+  if (!(eps >= 0.f) || !std::isfinite(lr)) return invalid("eps must be >= 0 and lr finite");
+  const hipError_t e = launch_adam(p, g, m, v, n, lr, beta1, beta2, eps, step, mask, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_adam_step");
+}
+
+int gs_l1_loss_grad(const float* image, const float* target, const gs_views* views,
+                    float* dL_dimage, double* loss, gs_stream_t stream) {
+  ViewTable vt;
+  int st = build_view_table(views, vt);
+  if (st) return st;
+  if (!image || !target || !dL_dimage) return invalid("an image pointer is NULL");
+  const hipError_t e = launch_l1_loss_grad(image, target, vt, dL_dimage, loss, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_l1_loss_grad");
+}
+
+}  // extern "C"

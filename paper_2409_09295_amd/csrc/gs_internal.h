@@ -1,0 +1,159 @@
+// Internal definitions shared by the libgsmi kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <utility>
+
+#include "gs.h"
+
+namespace gsmi {
+
+// Renderer constants (see gs.h for the definition they belong to).
+constexpr float kZNear = 0.2f;          // near-plane cull on camera-frame z
+constexpr float kDilation = 0.3f;       // screen-space covariance dilation, px^2
+constexpr float kAlphaMax = 0.99f;      // opacity clamp
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kTMin = 1e-4f;          // early-termination transmittance
+constexpr float kGuard = 1.3f;          // frustum guard on x/z, y/z inside J
+constexpr float kLog2e = 1.4426950408889634f;
+
+constexpr int kTile = 16;               // tile edge in pixels
+constexpr int kBlock = 256;             // threads per tile block (one per pixel)
+
+// Per-view layout derived on the host from gs_views::cams_host and passed to
+// kernels by value (it lands in the kernel-argument segment, read with scalar
+// loads, and is captured by value in a hipGraph).
+struct ViewInfo {
+  int32_t tile_base;   // first global tile id of the view
+  int32_t tiles_x;
+  int32_t tiles_y;
+  int32_t width;
+  int32_t height;
+  int32_t pad;
+  int64_t pix_base;    // first pixel of the view in packed [H][W] buffers
+};
+
+struct ViewTable {
+  int32_t n_views;
+  int32_t n_tiles;     // total over views
+  int64_t n_pixels;    // total over views
+  ViewInfo v[GS_MAX_VIEWS];
+};
+
+// Global tile id -> view (tiles of view v occupy [tile_base, tile_base + tiles_x*tiles_y)).
+__device__ __forceinline__ int find_view(const ViewTable& vt, int tile) {
+  int v = 0;
+  for (int i = 1; i < vt.n_views; ++i) v = (tile >= vt.v[i].tile_base) ? i : v;
+  return v;
+}
+
+// Half-open tile rectangle of a splat: tiles that hold a pixel centre
+// i + 1/2 with |i + 1/2 - u| <= r (and likewise in y), clamped to the image.
+// Evaluated in float64 from the float32 centre so that the integer result is
+// exact for the stored inputs.  Returns false (and an empty rect) when no
+// pixel centre is covered.
+struct Rect {
+  int32_t x0, x1, y0, y1;
+};
+
+__device__ __forceinline__ bool tile_rect(float uf, float vf, int32_t r, int32_t W, int32_t H,
+                                          Rect& out) {
+  out.x0 = out.x1 = out.y0 = out.y1 = 0;
+  if (r <= 0) return false;
+  const double u = (double)uf, v = (double)vf, rd = (double)r;
+  if (!(isfinite(u) && isfinite(v))) return false;
+  const double ilo = ceil(u - rd - 0.5), ihi = floor(u + rd - 0.5);
+  const double jlo = ceil(v - rd - 0.5), jhi = floor(v + rd - 0.5);
+  if (!(ilo <= ihi && jlo <= jhi && ihi >= 0.0 && ilo <= (double)(W - 1) && jhi >= 0.0 &&
+        jlo <= (double)(H - 1)))
+    return false;
+  const int32_t i0 = (int32_t)fmax(ilo, 0.0), i1 = (int32_t)fmin(ihi, (double)(W - 1));
+  const int32_t j0 = (int32_t)fmax(jlo, 0.0), j1 = (int32_t)fmin(jhi, (double)(H - 1));
+  out.x0 = i0 / kTile;
+  out.x1 = i1 / kTile + 1;
+  out.y0 = j0 / kTile;
+  out.y1 = j1 / kTile + 1;
+  return true;
+}
+
+// Splat record staged in LDS by the compositing kernels.  The conic is
+// pre-scaled so that log2 of the Gaussian falloff is
+//   p2 = a dx^2 + b dx dy + c dy^2,
+// a = -log2(e)/2 Q00, b = -log2(e) Q01, c = -log2(e)/2 Q11, i.e. p2 = log2(e) * power.
+struct StagedSplat {
+  float4 geo;   // u, v, a, b
+  float4 app;   // c, opacity, depth, (unused)
+  float4 col;   // r, g, b, (value index as bits)
+};
+
+// Blending decision shared bit-for-bit by the forward and backward kernels:
+// returns false if the splat is skipped at this pixel (power > 0 or
+// alpha < 1/255); otherwise alpha, the unclamped o*G and G = e^power.
+__device__ __forceinline__ bool eval_alpha(const float4& geo, const float4& app, float px,
+                                           float py, float& alpha, float& raw, float& G,
+                                           float& dx, float& dy) {
+  dx = px - geo.x;
+  dy = py - geo.y;
+  const float t1 = geo.w * dy;                 // b dy
+  const float t2 = __builtin_fmaf(geo.z, dx, t1);  // a dx + b dy
+  const float t3 = app.x * dy;                 // c dy
+  const float t4 = t3 * dy;                    // c dy^2
+  const float p2 = __builtin_fmaf(dx, t2, t4); // a dx^2 + b dx dy + c dy^2
+  if (p2 > 0.0f) return false;
+  G = __builtin_amdgcn_exp2f(p2);
+  raw = app.y * G;
+  alpha = fminf(kAlphaMax, raw);
+  return alpha >= kAlphaMin;
+}
+
+// Error reporting (thread-local buffer behind gs_last_error()).
+void set_error(const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+// ---- kernel launchers (host functions, one per .hip translation unit) -----
+
+hipError_t launch_preprocess(const gs_gaussians& g, const gs_camera* cams_dev, int n_views,
+                             const gs_projected& out, hipStream_t s);
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s);
+
+struct BinSortPlan {
+  int64_t n_entries;     // V * n
+  int64_t capacity;
+  int32_t n_tiles;
+  int32_t passes;        // radix passes of 8 bits
+  int64_t scan_blocks;   // blocks of the entry scan
+  int64_t sort_blocks;   // blocks of the radix sort at capacity
+  // workspace layout (byte offsets)
+  size_t off_counts, off_offsets, off_scan_part, off_keys_alt, off_vals_alt, off_hist,
+      off_hist_part, off_flag, total;
+};
+BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity);
+int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs_bins& bins,
+                 uint32_t* n_keys_host, char* ws, const BinSortPlan& plan, hipStream_t s);
+
+hipError_t launch_render_fwd(const gs_projected& p, const gs_bins& bins, const ViewTable& vt,
+                             float3 bg, float* image, float* final_T, uint32_t* n_contrib,
+                             float* depth, hipStream_t s);
+
+struct BwdPlan {
+  size_t off_grad2d, off_pose, total;
+};
+BwdPlan make_bwd_plan(int64_t n, const ViewTable& vt);
+hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const gs_bins& bins,
+                             const gs_camera* cams_dev, const ViewTable& vt, float3 bg,
+                             const float* dL_dimage, const float* final_T,
+                             const uint32_t* n_contrib, const gs_grads& grads, uint32_t flags,
+                             char* ws, const BwdPlan& plan, hipStream_t s);
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                       float beta1, float beta2, float eps, int32_t step, const uint8_t* mask,
+                       hipStream_t s);
+
+hipError_t launch_l1_loss_grad(const float* image, const float* target, const ViewTable& vt,
+                               float* dL_dimage, double* loss, hipStream_t s);
+
+}  // namespace gsmi

@@ -1,0 +1,71 @@
+// gs_preprocess: project every Gaussian into every view of a batch.
+//
+// One lane per Gaussian.  The Gaussian's parameters are read once with
+// coalesced component-major loads (lane i reads element i of each component
+// array) and reused for all views, so a batch of V views costs one read of
+// the map plus V writes of 52 bytes per Gaussian.  Camera records are
+// wave-uniform.
+#include "project.h"
+
+namespace gsmi {
+
+template <int DEG>
+__global__ __launch_bounds__(256) void preprocess_kernel(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ ologit,
+    const float* __restrict__ sh, int64_t n, const gs_camera* __restrict__ cams, int n_views,
+    float2* __restrict__ xy, float4* __restrict__ co, float4* __restrict__ rd,
+    int32_t* __restrict__ radius) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  GaussState G;
+  load_gauss(means, log_scales, quats, ologit, n, i, G);
+  for (int v = 0; v < n_views; ++v) {
+    const gs_camera cam = cams[v];
+    ViewState S;
+    project_view<DEG>(G, cam, sh, n, i, S);
+    const int64_t o = (int64_t)v * n + i;
+    if (S.visible) {
+      xy[o] = make_float2(S.u, S.v);
+      co[o] = make_float4(S.q0, S.q1, S.q2, G.o);
+      rd[o] = make_float4(S.rgb[0], S.rgb[1], S.rgb[2], S.p[2]);
+      radius[o] = S.radius;
+    } else {
+      xy[o] = make_float2(0.f, 0.f);
+      co[o] = make_float4(0.f, 0.f, 0.f, 0.f);
+      rd[o] = make_float4(0.f, 0.f, 0.f, 0.f);
+      radius[o] = 0;
+    }
+  }
+}
+
+hipError_t launch_preprocess(const gs_gaussians& g, const gs_camera* cams_dev, int n_views,
+                             const gs_projected& out, hipStream_t s) {
+  if (g.n == 0) return hipSuccess;
+  const dim3 block(256);
+  const dim3 grid((unsigned)((g.n + 255) / 256));
+  auto* xy = reinterpret_cast<float2*>(out.xy);
+  auto* co = reinterpret_cast<float4*>(out.conic_opacity);
+  auto* rd = reinterpret_cast<float4*>(out.rgb_depth);
+  switch (g.sh_degree) {
+    case 0:
+      hipLaunchKernelGGL(preprocess_kernel<0>, grid, block, 0, s, g.means, g.log_scales, g.quats,
+                         g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius);
+      break;
+    case 1:
+      hipLaunchKernelGGL(preprocess_kernel<1>, grid, block, 0, s, g.means, g.log_scales, g.quats,
+                         g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius);
+      break;
+    case 2:
+      hipLaunchKernelGGL(preprocess_kernel<2>, grid, block, 0, s, g.means, g.log_scales, g.quats,
+                         g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius);
+      break;
+    default:
+      hipLaunchKernelGGL(preprocess_kernel<3>, grid, block, 0, s, g.means, g.log_scales, g.quats,
+                         g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gsmi

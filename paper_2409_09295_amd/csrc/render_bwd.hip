@@ -1,0 +1,415 @@
+// gs_render_bwd: backward of compositing and projection.
+//
+// Pass 1 (per tile, 256 threads, same pixel mapping as the forward): each
+// pixel starts at its last blended splat (n_contrib) with T = final_T and the
+// normalised colour behind it S = bg, and walks the tile list in reverse,
+// recovering the transmittance before splat i as T_i = T_{i+1} / (1 - a_i).
+// For each splat the 9 screen-space partials (u, v, Q00, Q01, Q11, o, r, g, b)
+// are summed over the wavefront with DPP row operations and added to a
+// per-(view, splat) accumulator with one 9-lane atomic.
+//
+// Pass 2 (per Gaussian, all views): re-evaluates the projection and chains
+// the screen-space partials to the map parameters (summed over views in
+// registers) and to each view's pose tangent; pose partials are reduced per
+// workgroup in float64 and summed over workgroups by a final small kernel.
+#include "project.h"
+
+namespace gsmi {
+
+namespace {
+
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ float dpp_or_zero(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, BANK_MASK, false));
+}
+
+// Sum over the 64 lanes of a wavefront; the total lands in lane 63.
+__device__ __forceinline__ float wave_sum_to_lane63(float x) {
+  x += dpp_or_zero<0xb1, 0xf, 0xf>(x);   // quad_perm [1,0,3,2]
+  x += dpp_or_zero<0x4e, 0xf, 0xf>(x);   // quad_perm [2,3,0,1]
+  x += dpp_or_zero<0x124, 0xf, 0xf>(x);  // row_ror:4
+  x += dpp_or_zero<0x128, 0xf, 0xf>(x);  // row_ror:8 -> every lane holds its row sum
+  x += dpp_or_zero<0x142, 0xa, 0xf>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_or_zero<0x143, 0xc, 0xf>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ float lane63(float x) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+__device__ __forceinline__ void stage_splat(uint32_t g, const float2* __restrict__ xy,
+                                            const float4* __restrict__ co,
+                                            const float4* __restrict__ rd, StagedSplat& out) {
+  const float2 m = xy[g];
+  const float4 c = co[g];
+  const float4 r = rd[g];
+  out.geo = make_float4(m.x, m.y, -0.5f * kLog2e * c.x, -kLog2e * c.y);
+  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.w, 0.0f);
+  out.col = make_float4(r.x, r.y, r.z, __uint_as_float(g));
+}
+
+__global__ __launch_bounds__(kBlock) void render_bwd_kernel(
+    ViewTable vt, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
+    const float2* __restrict__ xy, const float4* __restrict__ co, const float4* __restrict__ rd,
+    float3 bg, const float* __restrict__ dL_dimage, const float* __restrict__ final_T,
+    const uint32_t* __restrict__ n_contrib, float* __restrict__ grad2d) {
+  __shared__ StagedSplat s_splat[kBlock];
+  __shared__ uint32_t s_maxlast;
+  const int tile = blockIdx.x;
+  const int v = find_view(vt, tile);
+  const ViewInfo& vi = vt.v[v];
+  const int lt = tile - vi.tile_base;
+  const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int px = tx * kTile + (w & 1) * 8 + (lane & 7);
+  const int py = ty * kTile + (w >> 1) * 8 + (lane >> 3);
+  const bool inside = px < vi.width && py < vi.height;
+  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+
+  float T = 1.0f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
+  float S0 = bg.x, S1 = bg.y, S2 = bg.z;
+  uint32_t last = 0;
+  if (inside) {
+    const int64_t pix = vi.pix_base + (int64_t)py * vi.width + px;
+    const int64_t plane = (int64_t)vi.width * vi.height;
+    const int64_t off = (int64_t)py * vi.width + px;
+    const float* g = dL_dimage + 3 * vi.pix_base;
+    dC0 = g[off];
+    dC1 = g[plane + off];
+    dC2 = g[2 * plane + off];
+    T = final_T[pix];
+    last = n_contrib[pix];
+  }
+  if (threadIdx.x == 0) s_maxlast = 0;
+  __syncthreads();
+  if (last) atomicMax(&s_maxlast, last);
+  __syncthreads();
+  const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
+  // n_contrib never exceeds the tile's list length for a matching forward;
+  // the clamp keeps every list read inside [s, e) regardless.
+  const int64_t list_len = (int64_t)e - (int64_t)s;
+  const int64_t maxlast = min((int64_t)s_maxlast, max(list_len, (int64_t)0));
+
+  for (int64_t bend = maxlast; bend > 0; bend -= kBlock) {
+    const int64_t bstart = max((int64_t)0, bend - kBlock);
+    __syncthreads();
+    const int64_t k = bstart + (int64_t)threadIdx.x;
+    if (k < bend) stage_splat(values[s + (uint32_t)k], xy, co, rd, s_splat[threadIdx.x]);
+    __syncthreads();
+    for (int j = (int)(bend - bstart) - 1; j >= 0; --j) {
+      const int64_t pos = bstart + j;
+      float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, g4 = 0.f, g5 = 0.f, g6 = 0.f, g7 = 0.f,
+            g8 = 0.f;
+      bool contrib = false;
+      const float4 geo = s_splat[j].geo;
+      const float4 app = s_splat[j].app;
+      if (pos < (int64_t)last) {
+        float alpha, raw, G, dx, dy;
+        if (eval_alpha(geo, app, fpx, fpy, alpha, raw, G, dx, dy)) {
+          contrib = true;
+          const float4 col = s_splat[j].col;
+          const float Tk = T / (1.0f - alpha);
+          const float wgt = alpha * Tk;
+          g6 = wgt * dC0;
+          g7 = wgt * dC1;
+          g8 = wgt * dC2;
+          const float dalpha = Tk * ((col.x - S0) * dC0 + (col.y - S1) * dC1 + (col.z - S2) * dC2);
+          S0 = alpha * col.x + (1.0f - alpha) * S0;
+          S1 = alpha * col.y + (1.0f - alpha) * S1;
+          S2 = alpha * col.z + (1.0f - alpha) * S2;
+          T = Tk;
+          if (raw <= kAlphaMax) {
+            g5 = G * dalpha;
+            const float gP = alpha * dalpha;   // dL/dpower
+            g0 = gP * (2.0f * geo.z * dx + geo.w * dy);
+            g1 = gP * (geo.w * dx + 2.0f * app.x * dy);
+            g2 = gP * dx * dx;
+            g3 = gP * dx * dy;
+            g4 = gP * dy * dy;
+          }
+        }
+      }
+      if (__ballot(contrib)) {
+        const float r0 = lane63(wave_sum_to_lane63(g0)) * (-1.0f / kLog2e);
+        const float r1 = lane63(wave_sum_to_lane63(g1)) * (-1.0f / kLog2e);
+        const float r2 = lane63(wave_sum_to_lane63(g2)) * -0.5f;
+        const float r3 = lane63(wave_sum_to_lane63(g3)) * -1.0f;
+        const float r4 = lane63(wave_sum_to_lane63(g4)) * -0.5f;
+        const float r5 = lane63(wave_sum_to_lane63(g5));
+        const float r6 = lane63(wave_sum_to_lane63(g6));
+        const float r7 = lane63(wave_sum_to_lane63(g7));
+        const float r8 = lane63(wave_sum_to_lane63(g8));
+        if (lane < 9) {
+          const float val = lane == 0 ? r0 : lane == 1 ? r1 : lane == 2 ? r2 : lane == 3 ? r3
+                          : lane == 4 ? r4 : lane == 5 ? r5 : lane == 6 ? r6 : lane == 7 ? r7 : r8;
+          const uint32_t gidx = __float_as_uint(s_splat[j].col.w);
+          unsafeAtomicAdd(&grad2d[(int64_t)gidx * 9 + lane], val);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-Gaussian backward through the projection
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float wave_sum_all(float x) {
+  return lane63(wave_sum_to_lane63(x));
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void project_bwd_kernel(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ ologit,
+    const float* __restrict__ sh, int64_t n, const gs_camera* __restrict__ cams, int n_views,
+    const int32_t* __restrict__ radius, const float* __restrict__ grad2d,
+    float* __restrict__ g_means, float* __restrict__ g_log_scales, float* __restrict__ g_quats,
+    float* __restrict__ g_ologit, float* __restrict__ g_sh, double* __restrict__ pose_part,
+    uint32_t flags) {
+  constexpr int K = SHDim<DEG>::K;
+  __shared__ double s_pose[4][6];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = i < n;
+  const bool want_pose = !(flags & GS_BWD_NO_POSE);
+  const bool want_map = !(flags & GS_BWD_POSE_ONLY);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  GaussState G;
+  if (valid) load_gauss(means, log_scales, quats, ologit, n, i, G);
+  else G.ok = false;
+  float gmu[3] = {0.f, 0.f, 0.f}, gRq[9] = {0.f}, gsc[3] = {0.f, 0.f, 0.f}, gol = 0.f;
+  float gf[3 * K];
+  for (int k = 0; k < 3 * K; ++k) gf[k] = 0.f;
+
+  for (int v = 0; v < n_views; ++v) {
+    float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int64_t o = (int64_t)v * n + i;
+    float g2[9];
+    bool active = valid && G.ok && radius[o] > 0;
+    if (active) {
+      bool nz = false;
+      for (int k = 0; k < 9; ++k) {
+        g2[k] = grad2d[o * 9 + k];
+        nz = nz || g2[k] != 0.0f;
+      }
+      active = nz;
+    }
+    if (active) {
+      const gs_camera cam = cams[v];
+      ViewState S;
+      project_view<DEG>(G, cam, sh, n, i, S);
+      const float* W = cam.R;
+      const float* t = cam.t;
+      float GW[9] = {0.f}, gt[3] = {0.f, 0.f, 0.f}, gp[3];
+      // opacity
+      gol += G.o * (1.0f - G.o) * g2[5];
+      // colour -> SH coefficients and view direction
+      float Y[K];
+      sh_basis<DEG>(S.dir[0], S.dir[1], S.dir[2], Y);
+      const float grgb[3] = {S.rgb_pos[0] ? g2[6] : 0.f, S.rgb_pos[1] ? g2[7] : 0.f,
+                             S.rgb_pos[2] ? g2[8] : 0.f};
+      float wk[K];
+      for (int k = 0; k < K; ++k) wk[k] = 0.f;
+      for (int ch = 0; ch < 3; ++ch)
+        for (int k = 0; k < K; ++k) {
+          gf[ch * K + k] += grgb[ch] * Y[k];
+          wk[k] += grgb[ch] * sh[(ch * K + k) * n + i];
+        }
+      float gdir[3];
+      sh_basis_grad<DEG>(S.dir[0], S.dir[1], S.dir[2], wk, gdir[0], gdir[1], gdir[2]);
+      const float dd = S.dir[0] * gdir[0] + S.dir[1] * gdir[1] + S.dir[2] * gdir[2];
+      const float invn = 1.0f / S.dnorm;
+      float gcc[3];
+      for (int k = 0; k < 3; ++k) {
+        const float gv = (gdir[k] - S.dir[k] * dd) * invn;
+        gmu[k] += gv;
+        gcc[k] = -gv;
+      }
+      // camera centre c = -W^T t
+      for (int jj = 0; jj < 3; ++jj) {
+        for (int ii = 0; ii < 3; ++ii) {
+          GW[jj * 3 + ii] -= t[jj] * gcc[ii];
+          gt[jj] -= W[jj * 3 + ii] * gcc[ii];
+        }
+      }
+      // conic -> Sigma2 entries: dL/dSigma' = -Q Gq Q
+      const float h = 0.5f * g2[3];
+      const float X00 = S.q0 * (S.q0 * g2[2] + S.q1 * h) + S.q1 * (S.q0 * h + S.q1 * g2[4]);
+      const float X01 = S.q0 * (S.q1 * g2[2] + S.q2 * h) + S.q1 * (S.q1 * h + S.q2 * g2[4]);
+      const float X11 = S.q1 * (S.q1 * g2[2] + S.q2 * h) + S.q2 * (S.q1 * h + S.q2 * g2[4]);
+      const float ga = -X00, gb = -2.0f * X01, gc = -X11;
+      float gA0[3], gA1[3];
+      for (int c = 0; c < 3; ++c) {
+        gA0[c] = 2.0f * ga * S.A0[c] + gb * S.A1[c];
+        gA1[c] = gb * S.A0[c] + 2.0f * gc * S.A1[c];
+      }
+      float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f, gB[9];
+      for (int c = 0; c < 3; ++c) {
+        gJ00 += gA0[c] * S.B[0 * 3 + c];
+        gJ02 += gA0[c] * S.B[2 * 3 + c];
+        gJ11 += gA1[c] * S.B[1 * 3 + c];
+        gJ12 += gA1[c] * S.B[2 * 3 + c];
+        gB[0 * 3 + c] = S.J00 * gA0[c];
+        gB[1 * 3 + c] = S.J11 * gA1[c];
+        gB[2 * 3 + c] = S.J02 * gA0[c] + S.J12 * gA1[c];
+      }
+      // camera-frame position
+      const float iz = S.inv_z, iz2 = iz * iz;
+      const float fx = cam.fx, fy = cam.fy;
+      gp[0] = g2[0] * fx * iz;
+      gp[1] = g2[1] * fy * iz;
+      gp[2] = -(g2[0] * fx * S.p[0] + g2[1] * fy * S.p[1]) * iz2;
+      gp[2] += -gJ00 * fx * iz2 - gJ11 * fy * iz2;
+      if (!S.clx) {
+        gp[0] += -gJ02 * fx * iz2;
+        gp[2] += gJ02 * 2.0f * fx * S.p[0] * iz2 * iz;
+      } else {
+        gp[2] += gJ02 * fx * S.tx * iz2;
+      }
+      if (!S.cly) {
+        gp[1] += -gJ12 * fy * iz2;
+        gp[2] += gJ12 * 2.0f * fy * S.p[1] * iz2 * iz;
+      } else {
+        gp[2] += gJ12 * fy * S.ty * iz2;
+      }
+      // p = W mu + t
+      for (int r = 0; r < 3; ++r) {
+        gt[r] += gp[r];
+        for (int k = 0; k < 3; ++k) {
+          gmu[k] += W[r * 3 + k] * gp[r];
+          GW[r * 3 + k] += gp[r] * G.mu[k];
+        }
+      }
+      // B = W M
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) {
+          float gm = 0.f, gw = 0.f;
+          for (int q = 0; q < 3; ++q) {
+            gm += W[q * 3 + r] * gB[q * 3 + k];
+            gw += gB[r * 3 + q] * G.M[k * 3 + q];
+          }
+          // gm = dL/dM[r][k], gw = dL/dW[r][k]
+          gRq[r * 3 + k] += gm * G.s[k];
+          gsc[k] += gm * G.Rq[r * 3 + k];
+          GW[r * 3 + k] += gw;
+        }
+      if (want_pose) {
+        // dL/dphi = <dL/dW, [e]x W> + <dL/dt, [e]x t>, dL/drho = dL/dt
+        float Mm[9];
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c)
+            Mm[r * 3 + c] = GW[r * 3 + 0] * W[c * 3 + 0] + GW[r * 3 + 1] * W[c * 3 + 1] +
+                            GW[r * 3 + 2] * W[c * 3 + 2];
+        pose[0] = gt[0];
+        pose[1] = gt[1];
+        pose[2] = gt[2];
+        pose[3] = Mm[7] - Mm[5] + (t[1] * gt[2] - t[2] * gt[1]);
+        pose[4] = Mm[2] - Mm[6] + (t[2] * gt[0] - t[0] * gt[2]);
+        pose[5] = Mm[3] - Mm[1] + (t[0] * gt[1] - t[1] * gt[0]);
+      }
+    }
+    if (want_pose) {
+      for (int k = 0; k < 6; ++k) {
+        const float sum = wave_sum_all(pose[k]);
+        if (lane == 0) s_pose[w][k] = (double)sum;
+      }
+      __syncthreads();
+      if (threadIdx.x < 6) {
+        const double tot = s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] +
+                           s_pose[2][threadIdx.x] + s_pose[3][threadIdx.x];
+        pose_part[((int64_t)blockIdx.x * n_views + v) * 6 + threadIdx.x] = tot;
+      }
+      __syncthreads();
+    }
+  }
+  if (!valid || !want_map || !G.ok) return;
+  for (int k = 0; k < 3; ++k) {
+    g_means[k * n + i] += gmu[k];
+    g_log_scales[k * n + i] += G.s[k] * gsc[k];
+  }
+  g_ologit[i] += gol;
+  for (int k = 0; k < 3 * K; ++k) g_sh[k * n + i] += gf[k];
+  // R(q) -> normalised quaternion -> raw quaternion
+  const float qw = G.q[0], qx = G.q[1], qy = G.q[2], qz = G.q[3];
+  const float* g = gRq;
+  float dq[4];
+  dq[0] = 2.f * (-qz * g[1] + qy * g[2] + qz * g[3] - qx * g[5] - qy * g[6] + qx * g[7]);
+  dq[1] = 2.f * (qy * g[1] + qz * g[2] + qy * g[3] - 2.f * qx * g[4] - qw * g[5] + qz * g[6] +
+                 qw * g[7] - 2.f * qx * g[8]);
+  dq[2] = 2.f * (-2.f * qy * g[0] + qx * g[1] + qw * g[2] + qx * g[3] + qz * g[5] - qw * g[6] +
+                 qz * g[7] - 2.f * qy * g[8]);
+  dq[3] = 2.f * (-2.f * qz * g[0] - qw * g[1] + qx * g[2] + qw * g[3] - 2.f * qz * g[4] +
+                 qy * g[5] + qx * g[6] + qy * g[7]);
+  const float dot = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
+  const float inv = 1.0f / G.qnorm;
+  for (int k = 0; k < 4; ++k) g_quats[k * n + i] += (dq[k] - G.q[k] * dot) * inv;
+}
+
+__global__ void pose_reduce_kernel(const double* __restrict__ pose_part, int64_t nblocks,
+                                   int n_views, float* __restrict__ xi) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_views * 6) return;
+  double acc = 0.0;
+  for (int64_t b = 0; b < nblocks; ++b) acc += pose_part[b * n_views * 6 + t];
+  xi[t] += (float)acc;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+BwdPlan make_bwd_plan(int64_t n, const ViewTable& vt) {
+  BwdPlan P{};
+  const int64_t nblocks = (n + 255) / 256;
+  size_t off = 0;
+  P.off_grad2d = off;
+  off += align_up(sizeof(float) * 9 * (size_t)n * vt.n_views);
+  P.off_pose = off;
+  off += align_up(sizeof(double) * 6 * (size_t)std::max<int64_t>(nblocks, 1) * vt.n_views);
+  P.total = off;
+  return P;
+}
+
+hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const gs_bins& bins,
+                             const gs_camera* cams_dev, const ViewTable& vt, float3 bg,
+                             const float* dL_dimage, const float* final_T,
+                             const uint32_t* n_contrib, const gs_grads& grads, uint32_t flags,
+                             char* ws, const BwdPlan& plan, hipStream_t s) {
+  float* grad2d = reinterpret_cast<float*>(ws + plan.off_grad2d);
+  double* pose_part = reinterpret_cast<double*>(ws + plan.off_pose);
+  const int64_t n2d = 9 * g.n * (int64_t)vt.n_views;
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, n2d, s);
+  if (e != hipSuccess) return e;
+  if (vt.n_tiles > 0)
+    hipLaunchKernelGGL(render_bwd_kernel, dim3((unsigned)vt.n_tiles), dim3(kBlock), 0, s, vt,
+                       bins.ranges, bins.values, reinterpret_cast<const float2*>(p.xy),
+                       reinterpret_cast<const float4*>(p.conic_opacity),
+                       reinterpret_cast<const float4*>(p.rgb_depth), bg, dL_dimage, final_T,
+                       n_contrib, grad2d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (g.n == 0) return hipSuccess;
+  const int64_t nblocks = (g.n + 255) / 256;
+  const dim3 grid((unsigned)nblocks), block(256);
+#define GS_BWD_ARGS                                                                              \
+  g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, g.n, cams_dev, vt.n_views, p.radius,  \
+      grad2d, grads.means, grads.log_scales, grads.quats, grads.opacity_logits, grads.sh,        \
+      pose_part, flags
+  switch (g.sh_degree) {
+    case 0: hipLaunchKernelGGL(project_bwd_kernel<0>, grid, block, 0, s, GS_BWD_ARGS); break;
+    case 1: hipLaunchKernelGGL(project_bwd_kernel<1>, grid, block, 0, s, GS_BWD_ARGS); break;
+    case 2: hipLaunchKernelGGL(project_bwd_kernel<2>, grid, block, 0, s, GS_BWD_ARGS); break;
+    default: hipLaunchKernelGGL(project_bwd_kernel<3>, grid, block, 0, s, GS_BWD_ARGS); break;
+  }
+#undef GS_BWD_ARGS
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (!(flags & GS_BWD_NO_POSE)) {
+    const int nt = vt.n_views * 6;
+    hipLaunchKernelGGL(pose_reduce_kernel, dim3((nt + 63) / 64), dim3(64), 0, s, pose_part,
+                       nblocks, vt.n_views, grads.xi);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gsmi

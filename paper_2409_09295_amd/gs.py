@@ -1,0 +1,376 @@
+"""Thin ctypes binding of libgsmi (include/gs.h): argument marshalling only.
+
+Every function named ``gs_*`` here calls the C entry point of the same name;
+PyTorch tensors serve only as device memory and the current HIP stream.
+Tensors holding uint32/uint64 data use int32/int64 storage.  All work runs
+in the library's HIP kernels; there is no fallback path: importing this
+module fails if ``libgsmi.so`` is missing, and calls fail on a machine
+without a GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import scenes
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsmi.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2409_09295_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+GS_OK = 0
+GS_ERR_INVALID_ARGUMENT = 1
+GS_ERR_CAPACITY = 2
+GS_ERR_HIP = 3
+GS_ERR_UNSUPPORTED = 4
+GS_BWD_NO_POSE = 1
+GS_BWD_POSE_ONLY = 2
+GS_MAX_VIEWS = 64
+TILE = 16
+
+_p = ctypes.c_void_p
+
+
+class GsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.gs_last_error().decode(errors="replace")
+        name = _lib.gs_status_string(status).decode()
+        super().__init__(f"{where}: {name}: {msg}")
+
+
+class gs_camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("pad", ctypes.c_int32 * 2)]
+
+
+class gs_gaussians(ctypes.Structure):
+    _fields_ = [("means", _p), ("log_scales", _p), ("quats", _p), ("opacity_logits", _p),
+                ("sh", _p), ("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32)]
+
+
+class gs_views(ctypes.Structure):
+    _fields_ = [("cams_host", _p), ("cams_dev", _p), ("n_views", ctypes.c_int32),
+                ("tile_size", ctypes.c_int32)]
+
+
+class gs_projected(ctypes.Structure):
+    _fields_ = [("xy", _p), ("conic_opacity", _p), ("rgb_depth", _p), ("radius", _p)]
+
+
+class gs_bins(ctypes.Structure):
+    _fields_ = [("keys", _p), ("values", _p), ("ranges", _p), ("n_keys", _p),
+                ("capacity", ctypes.c_int64)]
+
+
+class gs_grads(ctypes.Structure):
+    _fields_ = [("means", _p), ("log_scales", _p), ("quats", _p), ("opacity_logits", _p),
+                ("sh", _p), ("xi", _p)]
+
+
+assert ctypes.sizeof(gs_camera) == 80
+
+_S = ctypes.c_void_p
+_lib.gs_status_string.restype = ctypes.c_char_p
+_lib.gs_status_string.argtypes = [ctypes.c_int]
+_lib.gs_last_error.restype = ctypes.c_char_p
+_lib.gs_version.restype = ctypes.c_char_p
+_lib.gs_num_tiles.restype = ctypes.c_int64
+_lib.gs_num_tiles.argtypes = [ctypes.POINTER(gs_views)]
+_lib.gs_num_pixels.restype = ctypes.c_int64
+_lib.gs_num_pixels.argtypes = [ctypes.POINTER(gs_views)]
+_lib.gs_preprocess.argtypes = [ctypes.POINTER(gs_gaussians), ctypes.POINTER(gs_views),
+                               ctypes.POINTER(gs_projected), _S]
+_lib.gs_bin_sort_workspace_size.restype = ctypes.c_size_t
+_lib.gs_bin_sort_workspace_size.argtypes = [ctypes.c_int64, ctypes.POINTER(gs_views), ctypes.c_int64]
+_lib.gs_bin_sort.argtypes = [ctypes.POINTER(gs_projected), ctypes.c_int64, ctypes.POINTER(gs_views),
+                             ctypes.POINTER(gs_bins), ctypes.POINTER(ctypes.c_uint32), _p,
+                             ctypes.c_size_t, _S]
+_lib.gs_render_fwd.argtypes = [ctypes.POINTER(gs_projected), ctypes.c_int64, ctypes.POINTER(gs_bins),
+                               ctypes.POINTER(gs_views), ctypes.POINTER(ctypes.c_float), _p, _p, _p,
+                               _p, _S]
+_lib.gs_render_bwd_workspace_size.restype = ctypes.c_size_t
+_lib.gs_render_bwd_workspace_size.argtypes = [ctypes.c_int64, ctypes.POINTER(gs_views)]
+_lib.gs_render_bwd.argtypes = [ctypes.POINTER(gs_gaussians), ctypes.POINTER(gs_projected),
+                               ctypes.POINTER(gs_bins), ctypes.POINTER(gs_views),
+                               ctypes.POINTER(ctypes.c_float), _p, _p, _p, ctypes.POINTER(gs_grads),
+                               ctypes.c_uint32, _p, ctypes.c_size_t, _S]
+_lib.gs_adam_step.argtypes = [_p, _p, _p, _p, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_float, ctypes.c_int32, _p, _S]
+_lib.gs_l1_loss_grad.argtypes = [_p, _p, ctypes.POINTER(gs_views), _p, _p, _S]
+
+EXPORTED = ("gs_status_string", "gs_last_error", "gs_version", "gs_num_tiles", "gs_num_pixels",
+            "gs_preprocess", "gs_bin_sort_workspace_size", "gs_bin_sort", "gs_render_fwd",
+            "gs_render_bwd_workspace_size", "gs_render_bwd", "gs_adam_step", "gs_l1_loss_grad")
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def version() -> str:
+    return _lib.gs_version().decode()
+
+
+def _check(status: int, where: str):
+    if status != GS_OK:
+        raise GsError(status, where)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+def _bg(bg) -> Optional[ctypes.Array]:
+    if bg is None:
+        return None
+    return (ctypes.c_float * 3)(*[float(x) for x in bg])
+
+
+# ---------------------------------------------------------------------------
+# containers (device memory owned by torch tensors)
+# ---------------------------------------------------------------------------
+
+class Views:
+    """A batch of cameras: host records (sizes, tile layout) plus a device copy
+    (poses and intrinsics read by the kernels)."""
+
+    def __init__(self, cams: Sequence[scenes.Camera], device="cuda", tile_size: int = TILE):
+        recs = scenes.camera_records(list(cams))
+        self._host = (gs_camera * len(recs))()
+        ctypes.memmove(self._host, recs.ctypes.data, recs.nbytes)
+        self.records = recs
+        self.n_views = len(recs)
+        self.tile_size = tile_size
+        self.dev = torch.from_numpy(recs.view(np.uint8).copy()).to(device)
+        self.sizes = [(int(r["width"]), int(r["height"])) for r in recs]
+        self.struct = gs_views(ctypes.cast(self._host, _p), self.dev.data_ptr(), self.n_views, tile_size)
+
+    def update_poses(self, cams: Sequence[scenes.Camera]):
+        """Overwrite poses/intrinsics on the device (sizes must not change)."""
+        recs = scenes.camera_records(list(cams))
+        if [(int(r["width"]), int(r["height"])) for r in recs] != self.sizes:
+            raise ValueError("image sizes changed")
+        self.records = recs
+        ctypes.memmove(self._host, recs.ctypes.data, recs.nbytes)
+        self.dev.copy_(torch.from_numpy(recs.view(np.uint8).copy()))
+
+    @property
+    def n_tiles(self) -> int:
+        v = _lib.gs_num_tiles(ctypes.byref(self.struct))
+        if v < 0:
+            raise GsError(GS_ERR_INVALID_ARGUMENT, "gs_num_tiles")
+        return int(v)
+
+    @property
+    def n_pixels(self) -> int:
+        v = _lib.gs_num_pixels(ctypes.byref(self.struct))
+        if v < 0:
+            raise GsError(GS_ERR_INVALID_ARGUMENT, "gs_num_pixels")
+        return int(v)
+
+    def pixel_offsets(self) -> List[int]:
+        out, acc = [], 0
+        for w, h in self.sizes:
+            out.append(acc)
+            acc += w * h
+        return out
+
+    def split_images(self, flat: torch.Tensor) -> List[torch.Tensor]:
+        """Packed [V][3][H][W] buffer -> list of (3, H, W) views."""
+        out = []
+        for off, (w, h) in zip(self.pixel_offsets(), self.sizes):
+            out.append(flat[3 * off:3 * (off + w * h)].view(3, h, w))
+        return out
+
+    def split_maps(self, flat: torch.Tensor) -> List[torch.Tensor]:
+        """Packed [V][H][W] buffer -> list of (H, W) views."""
+        return [flat[off:off + w * h].view(h, w) for off, (w, h) in zip(self.pixel_offsets(), self.sizes)]
+
+
+@dataclasses.dataclass
+class Gaussians:
+    means: torch.Tensor            # (3, N) float32
+    log_scales: torch.Tensor       # (3, N)
+    quats: torch.Tensor            # (4, N)
+    opacity_logits: torch.Tensor   # (N,)
+    sh: torch.Tensor               # (3, K, N)
+    sh_degree: int
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[1])
+
+    @classmethod
+    def from_map(cls, gmap: scenes.GaussianMap, device="cuda") -> "Gaussians":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return cls(t(gmap.means), t(gmap.log_scales), t(gmap.quats), t(gmap.opacity_logits),
+                   t(gmap.sh), gmap.sh_degree)
+
+    def tensors(self):
+        return [self.means, self.log_scales, self.quats, self.opacity_logits, self.sh]
+
+    def struct(self) -> gs_gaussians:
+        for x in self.tensors():
+            if x.dtype != torch.float32 or not x.is_contiguous():
+                raise ValueError("Gaussian parameters must be contiguous float32")
+        return gs_gaussians(*[_ptr(x) for x in self.tensors()], self.n, self.sh_degree)
+
+
+@dataclasses.dataclass
+class Projected:
+    xy: torch.Tensor               # (V, N, 2) float32
+    conic_opacity: torch.Tensor    # (V, N, 4)
+    rgb_depth: torch.Tensor        # (V, N, 4)
+    radius: torch.Tensor           # (V, N) int32
+
+    @classmethod
+    def empty(cls, n_views: int, n: int, device="cuda") -> "Projected":
+        f = lambda *s: torch.empty(*s, dtype=torch.float32, device=device)
+        return cls(f(n_views, n, 2), f(n_views, n, 4), f(n_views, n, 4),
+                   torch.empty(n_views, n, dtype=torch.int32, device=device))
+
+    @classmethod
+    def from_splats(cls, sp: scenes.SplatSet, device="cuda") -> "Projected":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        return cls(t(sp.xy), t(sp.conic_opacity), t(sp.rgb_depth), t(sp.radius.astype(np.int32)))
+
+    def struct(self) -> gs_projected:
+        return gs_projected(_ptr(self.xy), _ptr(self.conic_opacity), _ptr(self.rgb_depth),
+                            _ptr(self.radius))
+
+
+@dataclasses.dataclass
+class Bins:
+    keys: torch.Tensor     # (capacity,) int64 storage of uint64
+    values: torch.Tensor   # (capacity,) int32 storage of uint32
+    ranges: torch.Tensor   # (n_tiles, 2) int32 storage of uint32
+    n_keys: torch.Tensor   # (1,) int32 storage of uint32
+    capacity: int
+
+    @classmethod
+    def empty(cls, capacity: int, n_tiles: int, device="cuda") -> "Bins":
+        cap = max(int(capacity), 1)
+        return cls(torch.empty(cap, dtype=torch.int64, device=device),
+                   torch.empty(cap, dtype=torch.int32, device=device),
+                   torch.empty(n_tiles, 2, dtype=torch.int32, device=device),
+                   torch.zeros(1, dtype=torch.int32, device=device), int(capacity))
+
+    def struct(self) -> gs_bins:
+        return gs_bins(_ptr(self.keys), _ptr(self.values), _ptr(self.ranges), _ptr(self.n_keys),
+                       self.capacity)
+
+
+@dataclasses.dataclass
+class Grads:
+    means: Optional[torch.Tensor]
+    log_scales: Optional[torch.Tensor]
+    quats: Optional[torch.Tensor]
+    opacity_logits: Optional[torch.Tensor]
+    sh: Optional[torch.Tensor]
+    xi: Optional[torch.Tensor]     # (V, 6) float32
+
+    @classmethod
+    def zeros_like(cls, g: Gaussians, n_views: int) -> "Grads":
+        z = torch.zeros_like
+        return cls(z(g.means), z(g.log_scales), z(g.quats), z(g.opacity_logits), z(g.sh),
+                   torch.zeros(n_views, 6, dtype=torch.float32, device=g.means.device))
+
+    def struct(self) -> gs_grads:
+        return gs_grads(_ptr(self.means), _ptr(self.log_scales), _ptr(self.quats),
+                        _ptr(self.opacity_logits), _ptr(self.sh), _ptr(self.xi))
+
+
+def workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    """Caller-owned scratch (torch's allocator returns >= 256-byte aligned blocks)."""
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+
+def gs_preprocess(g: Gaussians, views: Views, out: Projected, stream=None) -> None:
+    gs_, ps = g.struct(), out.struct()
+    _check(_lib.gs_preprocess(ctypes.byref(gs_), ctypes.byref(views.struct), ctypes.byref(ps),
+                              _stream(stream)), "gs_preprocess")
+
+
+def gs_bin_sort_workspace_size(n: int, views: Views, capacity: int) -> int:
+    return int(_lib.gs_bin_sort_workspace_size(n, ctypes.byref(views.struct), capacity))
+
+
+def gs_bin_sort(p: Projected, n: int, views: Views, bins: Bins, ws: torch.Tensor,
+                sync: bool = True, stream=None) -> Optional[int]:
+    """Returns the key count when ``sync`` (raises GsError(GS_ERR_CAPACITY)
+    with ``.required`` set if it exceeds the capacity); None otherwise."""
+    ps, bs = p.struct(), bins.struct()
+    cnt = ctypes.c_uint32(0)
+    st = _lib.gs_bin_sort(ctypes.byref(ps), n, ctypes.byref(views.struct), ctypes.byref(bs),
+                          ctypes.byref(cnt) if sync else None, _ptr(ws), ws.numel(), _stream(stream))
+    if st != GS_OK:
+        err = GsError(st, "gs_bin_sort")
+        err.required = int(cnt.value)
+        raise err
+    return int(cnt.value) if sync else None
+
+
+def gs_render_fwd(p: Projected, n: int, bins: Bins, views: Views, bg, image: torch.Tensor,
+                  final_T: torch.Tensor, n_contrib: torch.Tensor, depth: Optional[torch.Tensor] = None,
+                  stream=None) -> None:
+    ps, bs = p.struct(), bins.struct()
+    _check(_lib.gs_render_fwd(ctypes.byref(ps), n, ctypes.byref(bs), ctypes.byref(views.struct),
+                              _bg(bg), _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(depth),
+                              _stream(stream)), "gs_render_fwd")
+
+
+def gs_render_bwd_workspace_size(n: int, views: Views) -> int:
+    return int(_lib.gs_render_bwd_workspace_size(n, ctypes.byref(views.struct)))
+
+
+def gs_render_bwd(g: Gaussians, p: Projected, bins: Bins, views: Views, bg, dL_dimage: torch.Tensor,
+                  final_T: torch.Tensor, n_contrib: torch.Tensor, grads: Grads, flags: int,
+                  ws: torch.Tensor, stream=None) -> None:
+    gs_, ps, bs, gr = g.struct(), p.struct(), bins.struct(), grads.struct()
+    _check(_lib.gs_render_bwd(ctypes.byref(gs_), ctypes.byref(ps), ctypes.byref(bs),
+                              ctypes.byref(views.struct), _bg(bg), _ptr(dL_dimage), _ptr(final_T),
+                              _ptr(n_contrib), ctypes.byref(gr), flags, _ptr(ws), ws.numel(),
+                              _stream(stream)), "gs_render_bwd")
+
+
+def gs_adam_step(p: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, lr: float,
+                 beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, step: int = 1,
+                 mask: Optional[torch.Tensor] = None, stream=None) -> None:
+    n = p.numel()
+    for x in (g, m, v):
+        if x.numel() != n:
+            raise ValueError("Adam tensors must have equal sizes")
+    if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != n):
+        raise ValueError("mask must be uint8 with one entry per parameter")
+    _check(_lib.gs_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), n, lr, beta1, beta2, eps, step,
+                             _ptr(mask), _stream(stream)), "gs_adam_step")
+
+
+def gs_l1_loss_grad(image: torch.Tensor, target: torch.Tensor, views: Views, dL_dimage: torch.Tensor,
+                    loss: Optional[torch.Tensor] = None, stream=None) -> None:
+    _check(_lib.gs_l1_loss_grad(_ptr(image), _ptr(target), ctypes.byref(views.struct),
+                                _ptr(dL_dimage), _ptr(loss), _stream(stream)), "gs_l1_loss_grad")

@@ -1,0 +1,169 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/gs.h, and rejects invalid arguments with the
+documented status before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gs.h")
+LIB = os.path.join(ROOT, "paper_2409_09295_amd", "libgsmi.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def gs():
+    if not os.path.exists(LIB):
+        pytest.fail("libgsmi.so is not built (run python -m paper_2409_09295_amd.build)")
+    from paper_2409_09295_amd import gs as _gs
+    return _gs
+
+
+def test_every_declared_symbol_is_exported(gs):
+    names = _declared()
+    assert len(names) >= 13
+    lib = ctypes.CDLL(LIB)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(gs.EXPORTED) | {n for n in names if hasattr(lib, n)}
+
+
+def test_status_strings(gs):
+    lib = gs.lib()
+    assert lib.gs_status_string(0) == b"GS_OK"
+    assert lib.gs_status_string(2) == b"GS_ERR_CAPACITY"
+    assert lib.gs_status_string(99) == b"GS_ERR_UNKNOWN"
+    assert b"gfx950" in lib.gs_version()
+
+
+def _views(gs, sizes, tile=16):
+    arr = (gs.gs_camera * len(sizes))()
+    for i, (w, h) in enumerate(sizes):
+        arr[i].fx = arr[i].fy = 100.0
+        arr[i].cx, arr[i].cy = w / 2, h / 2
+        arr[i].width, arr[i].height = w, h
+        arr[i].R[0] = arr[i].R[4] = arr[i].R[8] = 1.0
+    v = gs.gs_views(ctypes.cast(arr, ctypes.c_void_p), 0xDEAD0000, len(sizes), tile)
+    v._keep = arr
+    return v
+
+
+def test_tile_and_pixel_counts(gs):
+    lib = gs.lib()
+    v = _views(gs, [(160, 120), (100, 70), (1200, 680)])
+    assert lib.gs_num_tiles(ctypes.byref(v)) == 10 * 8 + 7 * 5 + 75 * 43
+    assert lib.gs_num_pixels(ctypes.byref(v)) == 160 * 120 + 100 * 70 + 1200 * 680
+    bad = _views(gs, [(0, 10)])
+    assert lib.gs_num_tiles(ctypes.byref(bad)) == -1
+
+
+def test_workspace_sizes_grow(gs):
+    lib = gs.lib()
+    v = _views(gs, [(640, 480)])
+    a = lib.gs_bin_sort_workspace_size(1000, ctypes.byref(v), 10000)
+    b = lib.gs_bin_sort_workspace_size(2000, ctypes.byref(v), 10000)
+    c = lib.gs_bin_sort_workspace_size(1000, ctypes.byref(v), 20000)
+    assert 0 < a < b and a < c
+    assert lib.gs_render_bwd_workspace_size(1000, ctypes.byref(v)) >= 36 * 1000
+    assert lib.gs_bin_sort_workspace_size(-1, ctypes.byref(v), 10) == 0
+
+
+FAKE = 0x7F0000000000   # never dereferenced: validation fails first
+
+
+def _gauss(gs, n=10, deg=0):
+    return gs.gs_gaussians(FAKE, FAKE, FAKE, FAKE, FAKE, n, deg)
+
+
+def test_preprocess_argument_errors(gs):
+    lib = gs.lib()
+    v = _views(gs, [(64, 48)])
+    proj = gs.gs_projected(FAKE, FAKE, FAKE, FAKE)
+    assert lib.gs_preprocess(None, ctypes.byref(v), ctypes.byref(proj), None) == gs.GS_ERR_INVALID_ARGUMENT
+    g = _gauss(gs, deg=4)
+    assert lib.gs_preprocess(ctypes.byref(g), ctypes.byref(v), ctypes.byref(proj), None) == 1
+    assert b"sh_degree" in lib.gs_last_error()
+    g = _gauss(gs, n=-1)
+    assert lib.gs_preprocess(ctypes.byref(g), ctypes.byref(v), ctypes.byref(proj), None) == 1
+    g = _gauss(gs)
+    g.means = None
+    assert lib.gs_preprocess(ctypes.byref(g), ctypes.byref(v), ctypes.byref(proj), None) == 1
+    v8 = _views(gs, [(64, 48)], tile=8)
+    assert lib.gs_preprocess(ctypes.byref(_gauss(gs)), ctypes.byref(v8), ctypes.byref(proj),
+                             None) == gs.GS_ERR_UNSUPPORTED
+    v0 = _views(gs, [(64, 48)])
+    v0.n_views = 0
+    assert lib.gs_preprocess(ctypes.byref(_gauss(gs)), ctypes.byref(v0), ctypes.byref(proj), None) == 1
+    vbig = _views(gs, [(64, 48)] * 65)
+    assert lib.gs_preprocess(ctypes.byref(_gauss(gs)), ctypes.byref(vbig), ctypes.byref(proj), None) == 1
+    # n * views must fit the 32-bit splat index
+    g = _gauss(gs, n=1 << 31)
+    v3 = _views(gs, [(64, 48)] * 3)
+    assert lib.gs_preprocess(ctypes.byref(g), ctypes.byref(v3), ctypes.byref(proj), None) == 1
+
+
+def test_bin_sort_argument_errors(gs):
+    lib = gs.lib()
+    v = _views(gs, [(64, 48)])
+    proj = gs.gs_projected(FAKE, FAKE, FAKE, FAKE)
+    bins = gs.gs_bins(FAKE, FAKE, FAKE, FAKE, 100)
+    need = lib.gs_bin_sort_workspace_size(10, ctypes.byref(v), 100)
+    # workspace too small -> capacity error naming the size
+    st = lib.gs_bin_sort(ctypes.byref(proj), 10, ctypes.byref(v), ctypes.byref(bins), None, FAKE,
+                         need - 1, None)
+    assert st == gs.GS_ERR_CAPACITY
+    assert str(need).encode() in lib.gs_last_error()
+    # misaligned workspace
+    st = lib.gs_bin_sort(ctypes.byref(proj), 10, ctypes.byref(v), ctypes.byref(bins), None, FAKE + 4,
+                         need, None)
+    assert st == 1
+    bins.capacity = -5
+    st = lib.gs_bin_sort(ctypes.byref(proj), 10, ctypes.byref(v), ctypes.byref(bins), None, FAKE,
+                         need, None)
+    assert st == 1
+    bins = gs.gs_bins(None, FAKE, FAKE, FAKE, 100)
+    st = lib.gs_bin_sort(ctypes.byref(proj), 10, ctypes.byref(v), ctypes.byref(bins), None, FAKE,
+                         need, None)
+    assert st == 1
+
+
+def test_render_argument_errors(gs):
+    lib = gs.lib()
+    v = _views(gs, [(64, 48)])
+    proj = gs.gs_projected(FAKE, FAKE, FAKE, FAKE)
+    bins = gs.gs_bins(FAKE, FAKE, FAKE, FAKE, 100)
+    assert lib.gs_render_fwd(ctypes.byref(proj), 10, ctypes.byref(bins), ctypes.byref(v), None,
+                             None, FAKE, FAKE, None, None) == 1
+    g = _gauss(gs)
+    grads = gs.gs_grads(FAKE, FAKE, FAKE, FAKE, FAKE, None)
+    need = lib.gs_render_bwd_workspace_size(10, ctypes.byref(v))
+    # pose gradient requested but xi is NULL
+    assert lib.gs_render_bwd(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(bins), ctypes.byref(v),
+                             None, FAKE, FAKE, FAKE, ctypes.byref(grads), 0, FAKE, need, None) == 1
+    # exclusive flags
+    grads.xi = FAKE
+    assert lib.gs_render_bwd(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(bins), ctypes.byref(v),
+                             None, FAKE, FAKE, FAKE, ctypes.byref(grads), 3, FAKE, need, None) == 1
+    assert lib.gs_render_bwd(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(bins), ctypes.byref(v),
+                             None, FAKE, FAKE, FAKE, ctypes.byref(grads), 8, FAKE, need, None) == 1
+    assert lib.gs_render_bwd(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(bins), ctypes.byref(v),
+                             None, FAKE, FAKE, FAKE, ctypes.byref(grads), 0, FAKE, need - 1,
+                             None) == gs.GS_ERR_CAPACITY
+
+
+def test_adam_argument_errors(gs):
+    lib = gs.lib()
+    assert lib.gs_adam_step(FAKE, FAKE, FAKE, FAKE, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None, None) == 1
+    assert lib.gs_adam_step(FAKE, FAKE, FAKE, FAKE, 10, 1e-3, 1.0, 0.999, 1e-8, 1, None, None) == 1
+    assert lib.gs_adam_step(None, FAKE, FAKE, FAKE, 10, 1e-3, 0.9, 0.999, 1e-8, 1, None, None) == 1
+    assert lib.gs_adam_step(FAKE, FAKE, FAKE, FAKE, -1, 1e-3, 0.9, 0.999, 1e-8, 1, None, None) == 1
+    # n == 0 is a no-op that needs no device
+    assert lib.gs_adam_step(None, None, None, None, 0, 1e-3, 0.9, 0.999, 1e-8, 1, None, None) == 0

@@ -1,0 +1,351 @@
+"""GPU vs FP64 oracle parity, stage by stage and end to end (needs an MI355X)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import gs_oracle as O
+from paper_2409_09295_amd import scenes
+from tests.gpu_helpers import assert_grad_close, np_, random_dl, u32, u64
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# binning: bit-exact keys, values, ranges given the same splats
+# ---------------------------------------------------------------------------
+
+BIN_CASES = {
+    "one_view_160x120": [scenes.pinhole(160, 120, 150.0)],
+    "ragged_multi_view": [scenes.pinhole(100, 70, 80.0), scenes.pinhole(320, 240, 300.0),
+                          scenes.pinhole(48, 40, 40.0), scenes.pinhole(1200, 680, 984.0)],
+}
+
+
+def _gpu_bins(gs, sp, cams, capacity=None, sync=True):
+    views = gs.Views(cams)
+    proj = gs.Projected.from_splats(sp)
+    V, N = sp.radius.shape
+    cap = capacity if capacity is not None else 64 * N * V + 1024
+    bins = gs.Bins.empty(cap, views.n_tiles)
+    ws = gs.workspace(gs.gs_bin_sort_workspace_size(N, views, cap))
+    n = gs.gs_bin_sort(proj, N, views, bins, ws, sync=sync)
+    torch.cuda.synchronize()
+    return views, proj, bins, n
+
+
+@pytest.mark.parametrize("case", list(BIN_CASES))
+@pytest.mark.parametrize("sync", [True, False])
+def test_bin_sort_bit_exact(gs, case, sync):
+    cams = BIN_CASES[case]
+    n = 2500 if case != "ragged_multi_view" else 6000
+    sp = scenes.random_splats(n, cams, seed=21, depth_ties=0.2, cull_frac=0.05)
+    _log(f"bin_sort case={case} sync={sync} n={n}")
+    keys, vals, ranges, _, _ = O.bin_splats([sp.xy[v] for v in range(len(cams))],
+                                            [sp.rgb_depth[v, :, 3] for v in range(len(cams))],
+                                            [sp.radius[v] for v in range(len(cams))], cams, 16)
+    views, proj, bins, nk = _gpu_bins(gs, sp, cams, sync=sync)
+    got_n = int(u32(bins.n_keys)[0])
+    assert got_n == len(keys)
+    if sync:
+        assert nk == len(keys)
+    np.testing.assert_array_equal(u64(bins.keys)[:got_n], keys)
+    np.testing.assert_array_equal(u32(bins.values)[:got_n], vals)
+    np.testing.assert_array_equal(u32(bins.ranges), ranges)
+    # repeat: integer outputs are deterministic
+    views2, proj2, bins2, _ = _gpu_bins(gs, sp, cams, sync=sync)
+    np.testing.assert_array_equal(u64(bins2.keys)[:got_n], u64(bins.keys)[:got_n])
+    np.testing.assert_array_equal(u32(bins2.values)[:got_n], u32(bins.values)[:got_n])
+
+
+def test_bin_sort_all_culled(gs):
+    cams = [scenes.pinhole(64, 48, 60.0)]
+    sp = scenes.random_splats(500, cams, seed=2)
+    sp.radius[:] = 0
+    views, proj, bins, nk = _gpu_bins(gs, sp, cams)
+    assert nk == 0
+    assert int(u32(bins.n_keys)[0]) == 0
+    assert (u32(bins.ranges) == 0).all()
+
+
+def test_bin_sort_capacity(gs):
+    cams = [scenes.pinhole(160, 120, 150.0)]
+    sp = scenes.random_splats(800, cams, seed=5)
+    keys, *_ = O.bin_splats([sp.xy[0]], [sp.rgb_depth[0, :, 3]], [sp.radius[0]], cams, 16)
+    # synchronous: reports the required capacity and enqueues nothing more
+    with pytest.raises(gs.GsError) as ei:
+        _gpu_bins(gs, sp, cams, capacity=len(keys) - 1, sync=True)
+    assert ei.value.status == gs.GS_ERR_CAPACITY
+    assert ei.value.required == len(keys)
+    # asynchronous: the device count reports the overflow, no key is emitted
+    views, proj, bins, _ = _gpu_bins(gs, sp, cams, capacity=len(keys) - 1, sync=False)
+    assert int(u32(bins.n_keys)[0]) == len(keys)
+    assert (u32(bins.ranges) == 0).all()
+    # exact capacity succeeds
+    views, proj, bins, nk = _gpu_bins(gs, sp, cams, capacity=len(keys), sync=True)
+    assert nk == len(keys)
+    np.testing.assert_array_equal(u64(bins.keys)[:nk], keys)
+
+
+# ---------------------------------------------------------------------------
+# compositing from given splats
+# ---------------------------------------------------------------------------
+
+def _render_gpu(gs, sp, cams, bg=(0.0, 0.0, 0.0)):
+    views, proj, bins, nk = _gpu_bins(gs, sp, cams)
+    P = views.n_pixels
+    img = torch.empty(3 * P, device=DEV)
+    Tf = torch.empty(P, device=DEV)
+    nc = torch.empty(P, dtype=torch.int32, device=DEV)
+    dep = torch.empty(P, device=DEV)
+    gs.gs_render_fwd(proj, sp.radius.shape[1], bins, views, bg, img, Tf, nc, dep)
+    torch.cuda.synchronize()
+    return views, img, Tf, nc, dep
+
+
+@pytest.mark.parametrize("case", list(BIN_CASES))
+def test_render_fwd_splats(gs, case):
+    cams = BIN_CASES[case]
+    n = 2500 if case != "ragged_multi_view" else 4000
+    sp = scenes.random_splats(n, cams, seed=31)
+    bg = (0.2, 0.1, 0.05)
+    _log(f"render_fwd splats case={case}")
+    res, *_ = O.render_splats(sp, 16, bg=bg)
+    views, img, Tf, nc, dep = _render_gpu(gs, sp, cams, bg)
+    imgs = views.split_images(img)
+    Tfs = views.split_maps(Tf)
+    ncs = views.split_maps(nc)
+    deps = views.split_maps(dep)
+    total_masked = 0
+    for v, r in enumerate(res):
+        m = ~r["mask"]
+        total_masked += int(r["mask"].sum())
+        d = np.abs(np_(imgs[v]) - r["image"])[:, m]
+        assert d.max() <= 1e-4, (v, d.max())
+        assert np.abs(np_(Tfs[v]) - r["T_final"])[m].max() <= 1e-4
+        np.testing.assert_array_equal(np_(ncs[v])[m], r["n_contrib"][m])
+        assert np.abs(np_(deps[v]) - r["depth"])[m].max() <= 1e-3
+    assert total_masked <= 0.01 * views.n_pixels, total_masked
+
+
+# ---------------------------------------------------------------------------
+# full pipeline from Gaussian parameters
+# ---------------------------------------------------------------------------
+
+def _run_gpu(gs, wl, dl=None, flags=0):
+    from paper_2409_09295_amd.rasterizer import Rasterizer
+    g = gs.Gaussians.from_map(wl.gmap)
+    views = gs.Views(wl.cams)
+    rast = Rasterizer(g.n, views)
+    img = rast.forward(g, wl.bg)
+    out = dict(views=views, rast=rast, g=g, image=img.clone(), T=rast.final_T.clone(),
+               nc=rast.n_contrib.clone())
+    if dl is not None:
+        grads = gs.Grads.zeros_like(g, views.n_views)
+        rast.backward(g, torch.from_numpy(dl).to(DEV), grads, flags, wl.bg)
+        out["grads"] = grads
+    torch.cuda.synchronize()
+    return out
+
+
+def _check_projection(gs, wl, out, res):
+    V = len(wl.cams)
+    proj = out["rast"].proj
+    for v in range(V):
+        P = res["proj"][v]
+        vis = P["visible"]
+        rad = np_(proj.radius[v])
+        xy = np_(proj.xy[v])
+        co = np_(proj.conic_opacity[v])
+        rd = np_(proj.rgb_depth[v])
+        ext = P["ext"]
+        amb = np.abs(ext - np.round(ext)) < O.BAND_EXTENT * np.maximum(ext, 1.0)
+        z_amb = np.abs(P["z"] - O.Z_NEAR) < 1e-5
+        ok = ~(amb | z_amb)
+        np.testing.assert_array_equal((rad > 0)[ok], vis[ok])
+        np.testing.assert_array_equal(rad[ok & vis], P["radius"][ok & vis])
+        sel = vis & (rad > 0)
+        np.testing.assert_allclose(xy[sel, 0], P["u"][sel], rtol=2e-6, atol=2e-4)
+        np.testing.assert_allclose(xy[sel, 1], P["v"][sel], rtol=2e-6, atol=2e-4)
+        np.testing.assert_allclose(rd[sel, 3], P["z"][sel], rtol=1e-6)
+        np.testing.assert_allclose(co[sel, 3], P["opacity"][sel], rtol=1e-6)
+        np.testing.assert_allclose(rd[sel, :3], P["rgb"][sel], atol=2e-5)
+        conic = P["conic"][sel]
+        scale = np.abs(conic).max(axis=1, keepdims=True)
+        assert (np.abs(co[sel, :3] - conic) <= 2e-5 * scale + 1e-9).all()
+
+
+def _compare_images(views, out, res, tol=1e-4):
+    imgs = views.split_images(out["image"])
+    masked = 0
+    worst = 0.0
+    for v, r in enumerate(res["views"]):
+        m = ~r["mask"] & np.isfinite(r["image"][0])
+        masked += int(r["mask"].sum())
+        d = np.abs(np_(imgs[v]) - r["image"])[:, m]
+        worst = max(worst, float(d.max()) if d.size else 0.0)
+    assert worst <= tol, worst
+    return masked, worst
+
+
+def _masked_dl(views, res, dl):
+    """Zero dL/dC at near-threshold pixels (both paths get the same)."""
+    dl = dl.copy()
+    off = 0
+    for (w, h), r in zip(views.sizes, res["views"]):
+        blk = dl[3 * off:3 * (off + w * h)].reshape(3, h, w)
+        blk[:, r["mask"]] = 0.0
+        off += w * h
+    return dl
+
+
+def _split_dl(views, dl):
+    out, off = [], 0
+    for (w, h) in views.sizes:
+        out.append(dl[3 * off:3 * (off + w * h)].reshape(3, h, w).astype(np.float64))
+        off += w * h
+    return out
+
+
+def _grad_parity(gs, wl, seed, check_pose=True):
+    views = gs.Views(wl.cams)
+    _log(f"grad parity {wl.name}: oracle forward")
+    res0 = O.render(wl.gmap, wl.cams, bg=wl.bg)
+    dl = _masked_dl(views, res0, random_dl(views.sizes, seed))
+    _log(f"grad parity {wl.name}: GPU")
+    out = _run_gpu(gs, wl, dl)
+    _compare_images(views, out, res0)
+    _log(f"grad parity {wl.name}: oracle backward")
+    res = O.render(wl.gmap, wl.cams, bg=wl.bg, dL_dimage=_split_dl(views, dl))
+    g = out["grads"]
+    stats = {}
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        stats[name] = assert_grad_close(name, np_(getattr(g, name)), res["grads"][name])
+    if check_pose:
+        stats["xi"] = assert_grad_close("xi", np_(g.xi), res["grads"]["xi"])
+    _log(f"grad parity {wl.name}: relative L2 {stats}")
+    return out, res
+
+
+def test_c1_projection_and_image(gs):
+    wl = scenes.config_c1(0)
+    res = O.render(wl.gmap, wl.cams, bg=wl.bg)
+    out = _run_gpu(gs, wl)
+    _check_projection(gs, wl, out, res)
+    masked, worst = _compare_images(out["views"], out, res)
+    _log(f"c1 image: masked {masked} px, worst {worst:.3e}")
+    assert masked == 0
+    nc = np_(out["nc"]).reshape(120, 160)
+    np.testing.assert_array_equal(nc, res["views"][0]["n_contrib"])
+
+
+def test_c1_gradients(gs):
+    _grad_parity(gs, scenes.config_c1(0), seed=5)
+
+
+def test_c2_gradients(gs):
+    _grad_parity(gs, scenes.config_c2(0), seed=6)
+
+
+def test_background_and_multi_view_gradients(gs):
+    # two views of one cloud, non-black background: gradients sum over views
+    wl = scenes.config_c1(3)
+    rng = np.random.default_rng(4)
+    cam2 = scenes.perturb_pose(scenes.Camera(np.eye(3), np.zeros(3), 120.0, 120.0, 50.0, 40.0, 100, 72),
+                               rng)
+    wl = scenes.Workload("c1_two_views", wl.gmap, [wl.cams[0], cam2], [], bg=(0.3, 0.6, 0.1))
+    _grad_parity(gs, wl, seed=7)
+
+
+def test_c3_sampled_tiles(gs):
+    """Full-size single-view mapping workload (640x480, 200k Gaussians, SH 3):
+    images on sampled tiles, and all gradients with dL/dC restricted to those
+    tiles (so the oracle composites only the sampled tiles)."""
+    wl = scenes.config_c3(0)
+    views = gs.Views(wl.cams)
+    rng = np.random.default_rng(0)
+    TX, TY = 40, 30
+    picks = [(int(ty), int(tx)) for ty, tx in zip(rng.integers(0, TY, 10), rng.integers(0, TX, 10))]
+    picks += [(0, 0), (TY - 1, TX - 1), (TY // 2, TX // 2)]
+    _log("c3: oracle forward on sampled tiles")
+    res0 = O.render(wl.gmap, wl.cams, tiles=[picks])
+    dl = random_dl(views.sizes, 11).reshape(3, 480, 640)
+    keep = np.zeros((480, 640), bool)
+    for ty, tx in picks:
+        keep[16 * ty:16 * ty + 16, 16 * tx:16 * tx + 16] = True
+    dl[:, ~keep] = 0.0
+    dl = _masked_dl(views, res0, dl.reshape(-1))
+    _log("c3: GPU")
+    out = _run_gpu(gs, wl, dl)
+    masked, worst = _compare_images(views, out, res0)
+    _log(f"c3 sampled image: masked {masked} px, worst {worst:.3e}")
+    _log("c3: oracle backward on sampled tiles")
+    res = O.render(wl.gmap, wl.cams, dL_dimage=_split_dl(views, dl), tiles=[picks])
+    g = out["grads"]
+    for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        assert_grad_close(name, np_(getattr(g, name)), res["grads"][name])
+    assert_grad_close("xi", np_(g.xi), res["grads"]["xi"])
+
+
+def test_pose_only_matches_full(gs):
+    wl = scenes.config_c1(1)
+    views = gs.Views(wl.cams)
+    dl = random_dl(views.sizes, 3)
+    full = _run_gpu(gs, wl, dl, flags=0)["grads"]
+    po = _run_gpu(gs, wl, dl, flags=gs.GS_BWD_POSE_ONLY)["grads"]
+    np.testing.assert_allclose(np_(po.xi), np_(full.xi), rtol=1e-5, atol=1e-9)
+    assert np.abs(np_(po.means)).max() == 0.0
+    nop = _run_gpu(gs, wl, dl, flags=gs.GS_BWD_NO_POSE)["grads"]
+    assert np.abs(np_(nop.xi)).max() == 0.0
+    assert_grad_close("means", np_(nop.means), np_(full.means), rel=1e-4)
+
+
+# ---------------------------------------------------------------------------
+# elementwise kernels
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,offset,masked", [(1, 0, False), (1003, 0, False), (4096, 1, False),
+                                             (5000, 0, True)])
+def test_adam_step(gs, n, offset, masked):
+    rng = np.random.default_rng(n)
+    base = [rng.normal(size=n + offset).astype(np.float32) for _ in range(4)]
+    base[3] = np.abs(base[3])
+    mask = (rng.random(n) < 0.5).astype(np.uint8) if masked else None
+    t = [torch.from_numpy(b).to(DEV)[offset:] for b in base]
+    p, g, m, v = t
+    for step in (1, 2, 7):
+        ref = O.adam_step(np_(p), np_(g), np_(m), np_(v), 1e-3, 0.9, 0.999, 1e-8, step, mask)
+        gs.gs_adam_step(p, g, m, v, 1e-3, 0.9, 0.999, 1e-8, step,
+                        torch.from_numpy(mask).to(DEV) if mask is not None else None)
+        torch.cuda.synchronize()
+        for got, r in zip((p, m, v), ref):
+            np.testing.assert_allclose(np_(got), r, rtol=2e-6, atol=1e-7)
+
+
+def test_l1_loss_grad(gs):
+    cams = [scenes.pinhole(50, 30, 40.0), scenes.pinhole(17, 9, 10.0)]
+    views = gs.Views(cams)
+    rng = np.random.default_rng(0)
+    imgs = [rng.random((3, h, w)).astype(np.float32) for (w, h) in views.sizes]
+    tgts = [rng.random((3, h, w)).astype(np.float32) for (w, h) in views.sizes]
+    tgts[0][0, 0, :5] = imgs[0][0, 0, :5]       # exact ties -> sign 0
+    img = torch.from_numpy(np.concatenate([x.reshape(-1) for x in imgs])).to(DEV)
+    tgt = torch.from_numpy(np.concatenate([x.reshape(-1) for x in tgts])).to(DEV)
+    dl = torch.empty_like(img)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    gs.gs_l1_loss_grad(img, tgt, views, dl, loss)
+    torch.cuda.synchronize()
+    L_ref, off = 0.0, 0
+    for (w, h), a, b in zip(views.sizes, imgs, tgts):
+        L, g = O.l1_loss_grad(a, b)
+        L_ref += L
+        np.testing.assert_allclose(np_(dl)[3 * off:3 * (off + w * h)], g.reshape(-1), rtol=1e-6)
+        off += w * h
+    np.testing.assert_allclose(float(np_(loss)[0]), L_ref, rtol=1e-6)
