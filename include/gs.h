@@ -155,7 +155,18 @@ typedef struct gs_grads {
 
 enum {
   GS_BWD_NO_POSE = 1u,   /* skip the pose gradient (xi may be NULL)            */
-  GS_BWD_POSE_ONLY = 2u  /* only the pose gradient (map grads may be NULL)      */
+  GS_BWD_POSE_ONLY = 2u, /* only the pose gradient (map grads may be NULL)      */
+  GS_BWD_OVERWRITE = 4u  /* store gradients instead of accumulating (+=) them   */
+};
+
+/* Kernels that gs_set_kernel_events() can bracket. */
+enum {
+  GS_KERNEL_PREPROCESS = 0,   /* gs_preprocess's projection kernel                  */
+  GS_KERNEL_BIN_SORT = 1,     /* gs_bin_sort from key emission to tile ranges       */
+  GS_KERNEL_RENDER_FWD = 2,   /* gs_render_fwd's compositing kernel                 */
+  GS_KERNEL_RENDER_BWD = 3,   /* gs_render_bwd's reverse tile walk                  */
+  GS_KERNEL_PROJECT_BWD = 4,  /* gs_render_bwd's per-Gaussian projection backward   */
+  GS_KERNEL_COUNT = 5
 };
 
 /* Short name of a status code (static string). */
@@ -164,6 +175,14 @@ const char* gs_status_string(int status);
 const char* gs_last_error(void);
 /* Library version string. */
 const char* gs_version(void);
+
+/* Timing hook (thread-local): while set, every launch of `kernel` on this
+ * thread is bracketed by hipEventRecord(start, stream) and
+ * hipEventRecord(stop, stream) on the launch stream.  start/stop are
+ * hipEvent_t handles owned by the caller; NULL clears the hook.  Meant for
+ * measuring one kernel's duration in place; adds two event records per
+ * launch while set. */
+int gs_set_kernel_events(int kernel, void* start_event, void* stop_event);
 
 /* Total tiles and pixels of a view batch (host-only, validates views; < 0 on
  * invalid input). */
@@ -211,7 +230,8 @@ size_t gs_render_bwd_workspace_size(int64_t n, const gs_views* views);
  * reverse recovering the transmittance, reduces per-splat gradients over each
  * wavefront and accumulates them with atomics, then chains them per Gaussian
  * to the map parameters (summed over views) and to each view's pose tangent.
- * flags: 0 or GS_BWD_NO_POSE or GS_BWD_POSE_ONLY. */
+ * flags: 0, GS_BWD_NO_POSE or GS_BWD_POSE_ONLY, optionally or-ed with
+ * GS_BWD_OVERWRITE (gradients of culled Gaussians are then written as 0). */
 int gs_render_bwd(const gs_gaussians* g, const gs_projected* p, const gs_bins* bins,
                   const gs_views* views, const float* bg, const float* dL_dimage,
                   const float* final_T, const uint32_t* n_contrib, gs_grads* grads,
@@ -225,6 +245,19 @@ int gs_render_bwd(const gs_gaussians* g, const gs_projected* p, const gs_bins* b
 int gs_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                  float beta1, float beta2, float eps, int32_t step, const uint8_t* mask,
                  gs_stream_t stream);
+
+/* Capture-safe Adam step (same update as gs_adam_step) whose step number
+ * lives in device memory, for use inside a captured HIP graph:
+ *   t = *step_dev + 1 sets the bias correction; if commit != 0 the call then
+ *   stores t into *step_dev (the last parameter group of an optimisation step
+ *   commits, so all groups of one step share t).
+ * guard_n_keys (optional, device): when *guard_n_keys > guard_capacity (the
+ * step's tile binning overflowed and its gradients are incomplete) the call
+ * leaves p, m, v and *step_dev untouched. */
+int gs_adam_step_dev(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                     float beta1, float beta2, float eps, int32_t* step_dev, int32_t commit,
+                     const uint8_t* mask, const uint32_t* guard_n_keys, int64_t guard_capacity,
+                     gs_stream_t stream);
 
 /* L1 photometric loss L = sum over views of mean |C - C*| over 3 H W, and
  * dL/dC = sign(C - C*) / (3 H W) (sign(0) = 0), for every view (layouts of

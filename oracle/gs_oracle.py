@@ -58,7 +58,9 @@ EXTENT_SIGMAS = 3.0   # r = ceil(3 sqrt(lambda_max))
 # Bands used to flag float32 decisions that can legitimately go either way
 # (see near_threshold handling in render()).
 BAND_REL = 2e-5       # relative band on alpha vs 1/255, o e^power vs 0.99, T' vs 1e-4
-BAND_DEPTH = 4e-6     # relative depth difference under which two splats may swap
+BAND_DEPTH = 1e-12    # relative depth difference under which two splats may swap
+                      # (the kernel rounds a float64 depth once, so only depths
+                      # tied at float64 precision can order differently)
 BAND_EXTENT = 2e-6    # relative band on 3 sqrt(lambda_max) near an integer
 BAND_PX = 4e-6        # relative band on u -/+ r - 1/2 near an integer
 
@@ -307,7 +309,7 @@ def bin_splats(xy: Sequence[np.ndarray], depth_f32: Sequence[np.ndarray],
 # compositing (differentiable per tile)
 # ---------------------------------------------------------------------------
 
-def _composite_tile(px, py, S, bg, with_mask, depth=None):
+def _composite_tile(px, py, S, bg, with_mask, depth=None, depth_band=BAND_DEPTH):
     """px, py (P,) pixel centres; S (L, 9) rows u, v, Q00, Q01, Q11, o, r, g, b
     in list order.  Returns colour (P,3), T_final (P,), n_contrib (P,), weights
     (P,L), near-threshold mask (P,) and optional depth sum (P,)."""
@@ -352,8 +354,8 @@ def _composite_tile(px, py, S, bg, with_mask, depth=None):
                 | ((pw > -1e-6 * terms.detach() - 1e-12) & (pw.abs() < 1e-3)) \
                 | (keep & ((T_incl.detach() - T_MIN).abs() < BAND_REL * T_MIN))
             mask = (near & evaluated).any(dim=1)
-            if depth is not None and L > 1:
-                dz = (depth[1:] - depth[:-1]).abs() <= BAND_DEPTH * depth[1:].abs()
+            if depth is not None and depth_band is not None and L > 1:
+                dz = (depth[1:] - depth[:-1]).abs() <= depth_band * depth[1:].abs()
                 both = keep[:, 1:] & keep[:, :-1] & evaluated[:, 1:]
                 mask |= (both & dz[None, :]).any(dim=1)
     return C, T_fin, last, w, mask, dsum
@@ -368,13 +370,16 @@ def _tile_pixels(cam, tile_size, tx, ty):
 
 def composite(rows: torch.Tensor, depth: torch.Tensor, vals: np.ndarray, ranges: np.ndarray,
               bases, cams, tile_size: int, bg, dL_dimage=None, with_mask=True,
-              tile_mask=None, tiles=None):
+              pixel_mask=None, tiles=None, depth_band=BAND_DEPTH):
     """Composite every tile of every view.
 
     rows: (V*N, 9) float64 (u, v, Q00, Q01, Q11, o, r, g, b), a leaf if
     gradients are wanted; depth (V*N,) float64.  dL_dimage: per-view (3,H,W)
     arrays or None.  Per-tile backward accumulates into rows.grad.
-    tile_mask: optional per-view (TY, TX) bool arrays of tiles to flag.
+    pixel_mask: optional per-view (H, W) bool arrays of pixels to flag.
+    depth_band: relative depth gap under which two consecutive splats may be
+    ordered differently by a float32 depth (None when depths are given
+    exactly, as for render_splats).
     tiles: optional per-view collections of (ty, tx) to composite; pixels of
     other tiles are left NaN (image, T_final, depth) / -1 (n_contrib).
     Returns per-view lists: image (3,H,W), T_final, n_contrib, depth, mask."""
@@ -402,7 +407,7 @@ def composite(rows: torch.Tensor, depth: torch.Tensor, vals: np.ndarray, ranges:
                 S = rows.index_select(0, idx) if s1 > s0 else rows[:0]
                 dep = depth.index_select(0, idx).detach() if s1 > s0 else depth[:0].detach()
                 C, T_fin, last, _, mask, dsum = _composite_tile(
-                    xx.to(DT) + 0.5, yy.to(DT) + 0.5, S, bg_t, with_mask, dep)
+                    xx.to(DT) + 0.5, yy.to(DT) + 0.5, S, bg_t, with_mask, dep, depth_band)
                 if g is not None and rows.requires_grad and s1 > s0:
                     gC = g[:, yy, xx].T
                     (C * gC).sum().backward()
@@ -411,8 +416,8 @@ def composite(rows: torch.Tensor, depth: torch.Tensor, vals: np.ndarray, ranges:
                 nc[yy.numpy(), xx.numpy()] = last.numpy()
                 dimg[yy.numpy(), xx.numpy()] = dsum.detach().numpy()
                 m = mask.numpy()
-                if tile_mask is not None and tile_mask[vi][ty, tx]:
-                    m = np.ones_like(m)
+                if pixel_mask is not None:
+                    m = m | pixel_mask[vi][yy.numpy(), xx.numpy()]
                 msk[yy.numpy(), xx.numpy()] = m
         out.append(dict(image=img, T_final=Tf, n_contrib=nc, depth=dimg, mask=msk))
     return out
@@ -433,21 +438,28 @@ def render_splats(splats, tile_size: int = 16, bg=(0.0, 0.0, 0.0), with_mask=Tru
                       _t(splats.conic_opacity.reshape(V * N, 4)),
                       _t(splats.rgb_depth.reshape(V * N, 4)[:, :3])], dim=1)
     depth = _t(splats.rgb_depth.reshape(V * N, 4)[:, 3])
-    res = composite(rows, depth, vals, ranges, bases, splats.cams, tile_size, bg, None, with_mask)
+    res = composite(rows, depth, vals, ranges, bases, splats.cams, tile_size, bg, None, with_mask,
+                    depth_band=None)
     return res, keys, vals, ranges
 
 
-def _ambiguous_tiles(P, cam, tile_size):
-    """Tiles whose membership could differ under float32 rounding of the
-    extent, the projected centre or the near-plane test: returns (TY, TX) bool."""
+def _ambiguous_pixels(P, cam, tile_size):
+    """Pixels whose splat list could differ under float32 rounding of a
+    splat's extent, projected centre or near-plane test: for every such
+    splat, the pixels of the tiles it may or may not cover at which it would
+    be blended (raw alpha within the band of 1/255 or above).  Returns an
+    (H, W) bool array."""
     TX, TY = tile_grid(cam, tile_size)
-    flag = np.zeros((TY, TX), bool)
+    W, H = int(cam.width), int(cam.height)
+    flag = np.zeros((H, W), bool)
     u = P["u"].detach().numpy()
     v = P["v"].detach().numpy()
     ext = P["ext"].numpy()
     rad = P["radius"].numpy()
     vis = P["visible"].numpy()
     z = P["z"].detach().numpy()
+    conic = P["conic"].detach().numpy()
+    opac = P["opacity"].detach().numpy()
     with np.errstate(invalid="ignore"):
         ext_amb = np.abs(ext - np.round(ext)) < BAND_EXTENT * np.maximum(ext, 1.0)
         z_amb = np.abs(z - Z_NEAR) < 1e-5 * max(Z_NEAR, 1.0)
@@ -461,30 +473,36 @@ def _ambiguous_tiles(P, cam, tile_size):
         for val in (v - rad - 0.5, v + rad - 0.5):
             edge_amb |= np.abs(val - np.round(val)) < bv
     cand = np.nonzero((vis | z_amb) & (ext_amb | z_amb | edge_amb) & np.isfinite(u) & np.isfinite(v))[0]
-    W, H = int(cam.width), int(cam.height)
     for i in cand:
         if z_amb[i]:
             r_big = int(max(rad[i], 1)) + 1
-            x0, x1, y0, y1, c = tile_rects(u[i:i + 1] , v[i:i + 1], np.array([r_big]), W, H, tile_size)
+            x0, x1, y0, y1, c = tile_rects(u[i:i + 1], v[i:i + 1], np.array([r_big]), W, H, tile_size)
             if c[0] > 0:
-                flag[y0[0]:y1[0], x0[0]:x1[0]] = True
+                flag[y0[0] * tile_size:y1[0] * tile_size, x0[0] * tile_size:x1[0] * tile_size] = True
             continue
         big = tile_rects(np.array([u[i] - bu[i], u[i] + bu[i]]), np.array([v[i] - bv[i], v[i] + bv[i]]),
                          np.array([r_hi[i], r_hi[i]]), W, H, tile_size)
         small = tile_rects(np.array([u[i] - bu[i], u[i] + bu[i]]), np.array([v[i] - bv[i], v[i] + bv[i]]),
                            np.array([max(r_lo[i], 0), max(r_lo[i], 0)]), W, H, tile_size)
-        ux0, ux1 = big[0].min(), big[1].max()
-        uy0, uy1 = big[2].min(), big[3].max()
         if big[4].max() == 0:
             continue
         region = np.zeros((TY, TX), bool)
-        region[uy0:uy1, ux0:ux1] = True
+        region[big[2].min():big[3].max(), big[0].min():big[1].max()] = True
         if small[4].min() > 0:
             ix0, ix1 = small[0].max(), small[1].min()
             iy0, iy1 = small[2].max(), small[3].min()
             if ix1 > ix0 and iy1 > iy0:
                 region[iy0:iy1, ix0:ix1] = False
-        flag |= region
+        q0, q1, q2 = conic[i]
+        for ty, tx in zip(*np.nonzero(region)):
+            ys = np.arange(ty * tile_size, min((ty + 1) * tile_size, H))
+            xs = np.arange(tx * tile_size, min((tx + 1) * tile_size, W))
+            dy = ys[:, None] + 0.5 - v[i]
+            dx = xs[None, :] + 0.5 - u[i]
+            power = -0.5 * (q0 * dx * dx + q2 * dy * dy) - q1 * dx * dy
+            raw = opac[i] * np.exp(np.minimum(power, 0.0))
+            hit = raw >= ALPHA_MIN * (1.0 - BAND_REL)
+            flag[ys[0]:ys[-1] + 1, xs[0]:xs[-1] + 1] |= hit
     return flag
 
 
@@ -525,7 +543,7 @@ def render(gmap, cams, tile_size: int = 16, bg=(0.0, 0.0, 0.0), dL_dimage=None,
     xy = [torch.stack([P["u"], P["v"]], 1).detach().numpy() for P in projs]
     dz = [P["z"].detach().numpy().astype(np.float32) for P in projs]
     keys, vals, ranges, bases, _ = bin_splats(xy, dz, radius, cams, tile_size)
-    tmask = [_ambiguous_tiles(P, cam, tile_size) for P, cam in zip(projs, cams)] if with_mask else None
+    tmask = [_ambiguous_pixels(P, cam, tile_size) for P, cam in zip(projs, cams)] if with_mask else None
     res = composite(rows, depth, vals, ranges, bases, cams, tile_size, bg, dL_dimage, with_mask, tmask,
                     tiles)
     result = dict(views=res, keys=keys, values=vals, ranges=ranges, bases=bases,

@@ -53,6 +53,52 @@ __global__ __launch_bounds__(256) void adam_scalar_kernel(float* __restrict__ p,
   v[i] = vv;
 }
 
+// Device-step variant: coefficients derived in-kernel from *step_dev.
+__device__ __forceinline__ bool dev_coef(const int32_t* step_dev, const uint32_t* guard,
+                                         int64_t guard_cap, float lr, float b1, float b2,
+                                         float eps, AdamCoef& c) {
+  if (guard && (int64_t)(*guard) > guard_cap) return false;
+  const float t = (float)(*step_dev + 1);
+  c.lr = lr;
+  c.b1 = b1;
+  c.b2 = b2;
+  c.eps = eps;
+  c.inv_bc1 = 1.0f / (1.0f - powf(b1, t));
+  c.inv_bc2 = 1.0f / (1.0f - powf(b2, t));
+  return true;
+}
+
+__global__ __launch_bounds__(256) void adam_dev_kernel(float* __restrict__ p,
+                                                       const float* __restrict__ g,
+                                                       float* __restrict__ m,
+                                                       float* __restrict__ v, int64_t n,
+                                                       const uint8_t* __restrict__ mask, float lr,
+                                                       float b1, float b2, float eps,
+                                                       const int32_t* __restrict__ step_dev,
+                                                       const uint32_t* __restrict__ guard,
+                                                       int64_t guard_cap) {
+  AdamCoef c;
+  if (!dev_coef(step_dev, guard, guard_cap, lr, b1, b2, eps, c)) return;
+  const int64_t i4 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = i4 + k;
+    if (i >= n) return;
+    if (mask && mask[i] == 0) continue;
+    float pp = p[i], mm = m[i], vv = v[i];
+    adam_one(pp, g[i], mm, vv, c);
+    p[i] = pp;
+    m[i] = mm;
+    v[i] = vv;
+  }
+}
+
+__global__ void adam_commit_kernel(int32_t* __restrict__ step_dev,
+                                   const uint32_t* __restrict__ guard, int64_t guard_cap) {
+  if (guard && (int64_t)(*guard) > guard_cap) return;
+  *step_dev = *step_dev + 1;
+}
+
 __global__ __launch_bounds__(256) void l1_grad_kernel(const float* __restrict__ image,
                                                       const float* __restrict__ target,
                                                       ViewTable vt, float* __restrict__ grad,
@@ -110,6 +156,22 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
   if (begin < n)
     hipLaunchKernelGGL(adam_scalar_kernel, dim3((unsigned)((n - begin + 255) / 256)), dim3(256), 0,
                        s, p, g, m, v, begin, n, mask, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_dev(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                           float beta1, float beta2, float eps, int32_t* step_dev, int32_t commit,
+                           const uint8_t* mask, const uint32_t* guard_n_keys,
+                           int64_t guard_capacity, hipStream_t s) {
+  if (n > 0) {
+    const int64_t threads = (n + 3) / 4;
+    hipLaunchKernelGGL(adam_dev_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+                       p, g, m, v, n, mask, lr, beta1, beta2, eps, step_dev, guard_n_keys,
+                       guard_capacity);
+  }
+  if (commit)
+    hipLaunchKernelGGL(adam_commit_kernel, dim3(1), dim3(1), 0, s, step_dev, guard_n_keys,
+                       guard_capacity);
   return hipGetLastError();
 }
 

@@ -432,6 +432,7 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   uint32_t* vA = (P.passes % 2 == 0) ? bins.values : vals_alt;
   uint64_t* kB = (P.passes % 2 == 0) ? keys_alt : bins.keys;
   uint32_t* vB = (P.passes % 2 == 0) ? vals_alt : bins.values;
+  kernel_event_start(GS_KERNEL_BIN_SORT, s);
   if (P.n_entries > 0)
     hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((P.n_entries + 255) / 256)), dim3(256), 0, s,
                        xy, p.radius, rd, offsets, P.n_entries, n, vt, flag, P.capacity, kA, vA);
@@ -448,6 +449,7 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   }
   hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((n_sort + 255) / 256)), dim3(256), 0, s,
                      bins.keys, bins.n_keys, P.capacity, bins.ranges);
+  kernel_event_stop(GS_KERNEL_BIN_SORT, s);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "bin sort launch");
   return GS_OK;
 }

@@ -11,6 +11,15 @@ namespace gsmi {
 
 namespace {
 thread_local char g_last_error[512] = "";
+thread_local hipEvent_t g_events[GS_KERNEL_COUNT][2] = {};
+}
+
+void kernel_event_start(int kernel, hipStream_t s) {
+  if (g_events[kernel][0]) (void)hipEventRecord(g_events[kernel][0], s);
+}
+
+void kernel_event_stop(int kernel, hipStream_t s) {
+  if (g_events[kernel][1]) (void)hipEventRecord(g_events[kernel][1], s);
 }
 
 void set_error(const char* fmt, ...) {
@@ -139,6 +148,15 @@ const char* gs_last_error(void) { return g_last_error; }
 
 const char* gs_version(void) { return "gsmi 0.1 (gfx950)"; }
 
+int gs_set_kernel_events(int kernel, void* start_event, void* stop_event) {
+  if (kernel < 0 || kernel >= GS_KERNEL_COUNT) return invalid("unknown kernel id %d", kernel);
+  if ((start_event == nullptr) != (stop_event == nullptr))
+    return invalid("start and stop events must both be set or both be NULL");
+  g_events[kernel][0] = static_cast<hipEvent_t>(start_event);
+  g_events[kernel][1] = static_cast<hipEvent_t>(stop_event);
+  return GS_OK;
+}
+
 int64_t gs_num_tiles(const gs_views* views) {
   ViewTable vt;
   if (build_view_table(views, vt) != GS_OK) return -1;
@@ -215,7 +233,8 @@ int gs_render_bwd(const gs_gaussians* g, const gs_projected* p, const gs_bins* b
   if ((st = check_gaussians(g, vt.n_views))) return st;
   if ((st = check_projected(p, g->n))) return st;
   if ((st = check_bins(bins, false))) return st;
-  if (flags & ~(uint32_t)(GS_BWD_NO_POSE | GS_BWD_POSE_ONLY)) return invalid("unknown flags");
+  if (flags & ~(uint32_t)(GS_BWD_NO_POSE | GS_BWD_POSE_ONLY | GS_BWD_OVERWRITE))
+    return invalid("unknown flags");
   if ((flags & GS_BWD_NO_POSE) && (flags & GS_BWD_POSE_ONLY))
     return invalid("GS_BWD_NO_POSE and GS_BWD_POSE_ONLY are exclusive");
   if (!dL_dimage || !final_T || !n_contrib || !grads) return invalid("an input pointer is NULL");
@@ -242,6 +261,22 @@ int gs_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float 
   if (!(eps >= 0.f) || !std::isfinite(lr)) return invalid("eps must be >= 0 and lr finite");
   const hipError_t e = launch_adam(p, g, m, v, n, lr, beta1, beta2, eps, step, mask, stream);
   return e == hipSuccess ? GS_OK : hip_fail(e, "gs_adam_step");
+}
+
+int gs_adam_step_dev(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                     float beta1, float beta2, float eps, int32_t* step_dev, int32_t commit,
+                     const uint8_t* mask, const uint32_t* guard_n_keys, int64_t guard_capacity,
+                     gs_stream_t stream) {
+  if (n < 0) return invalid("n = %lld < 0", (long long)n);
+  if (n > 0 && (!p || !g || !m || !v)) return invalid("a parameter pointer is NULL");
+  if (!step_dev) return invalid("step_dev is NULL");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f))
+    return invalid("betas must lie in [0, 1)");
+  if (!(eps >= 0.f) || !std::isfinite(lr)) return invalid("eps must be >= 0 and lr finite");
+  if (guard_n_keys && guard_capacity < 0) return invalid("guard_capacity < 0");
+  const hipError_t e = launch_adam_dev(p, g, m, v, n, lr, beta1, beta2, eps, step_dev, commit,
+                                       mask, guard_n_keys, guard_capacity, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_adam_step_dev");
 }
 
 int gs_l1_loss_grad(const float* image, const float* target, const gs_views* views,

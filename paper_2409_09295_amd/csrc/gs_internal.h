@@ -109,6 +109,10 @@ __device__ __forceinline__ bool eval_alpha(const float4& geo, const float4& app,
   return alpha >= kAlphaMin;
 }
 
+// Optional per-kernel timing events (see gs_set_kernel_events).
+void kernel_event_start(int kernel, hipStream_t s);
+void kernel_event_stop(int kernel, hipStream_t s);
+
 // Error reporting (thread-local buffer behind gs_last_error()).
 void set_error(const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
@@ -152,6 +156,11 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                        float beta1, float beta2, float eps, int32_t step, const uint8_t* mask,
                        hipStream_t s);
+
+hipError_t launch_adam_dev(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                           float beta1, float beta2, float eps, int32_t* step_dev, int32_t commit,
+                           const uint8_t* mask, const uint32_t* guard_n_keys,
+                           int64_t guard_capacity, hipStream_t s);
 
 hipError_t launch_l1_loss_grad(const float* image, const float* target, const ViewTable& vt,
                                float* dL_dimage, double* loss, hipStream_t s);

@@ -47,6 +47,7 @@ hipError_t launch_preprocess(const gs_gaussians& g, const gs_camera* cams_dev, i
   auto* xy = reinterpret_cast<float2*>(out.xy);
   auto* co = reinterpret_cast<float4*>(out.conic_opacity);
   auto* rd = reinterpret_cast<float4*>(out.rgb_depth);
+  kernel_event_start(GS_KERNEL_PREPROCESS, s);
   switch (g.sh_degree) {
     case 0:
       hipLaunchKernelGGL(preprocess_kernel<0>, grid, block, 0, s, g.means, g.log_scales, g.quats,
@@ -65,6 +66,7 @@ hipError_t launch_preprocess(const gs_gaussians& g, const gs_camera* cams_dev, i
                          g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius);
       break;
   }
+  kernel_event_stop(GS_KERNEL_PREPROCESS, s);
   return hipGetLastError();
 }
 

@@ -186,8 +186,15 @@ __device__ __forceinline__ void project_view(const GaussState& G, const gs_camer
   const float* W = cam.R;
   S.visible = false;
   S.radius = 0;
-  for (int r = 0; r < 3; ++r)
-    S.p[r] = W[r * 3 + 0] * G.mu[0] + W[r * 3 + 1] * G.mu[1] + W[r * 3 + 2] * G.mu[2] + cam.t[r];
+  // Camera-frame point in float64 from the float32 inputs (the products are
+  // exact), rounded once: the float32 depth that orders splats is then the
+  // correctly rounded depth, independent of summation order.
+  for (int r = 0; r < 3; ++r) {
+    const double pr = fma((double)W[r * 3 + 0], (double)G.mu[0],
+                          fma((double)W[r * 3 + 1], (double)G.mu[1],
+                              fma((double)W[r * 3 + 2], (double)G.mu[2], (double)cam.t[r])));
+    S.p[r] = (float)pr;
+  }
   const float z = S.p[2];
   if (!G.ok || !(z > kZNear)) return;
   S.inv_z = 1.0f / z;

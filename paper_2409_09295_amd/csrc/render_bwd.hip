@@ -324,13 +324,25 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
       __syncthreads();
     }
   }
-  if (!valid || !want_map || !G.ok) return;
-  for (int k = 0; k < 3; ++k) {
-    g_means[k * n + i] += gmu[k];
-    g_log_scales[k * n + i] += G.s[k] * gsc[k];
+  if (!valid || !want_map) return;
+  const bool overwrite = (flags & GS_BWD_OVERWRITE) != 0;
+  if (!G.ok) {
+    if (overwrite) {
+      for (int k = 0; k < 3; ++k) g_means[k * n + i] = g_log_scales[k * n + i] = 0.f;
+      for (int k = 0; k < 4; ++k) g_quats[k * n + i] = 0.f;
+      g_ologit[i] = 0.f;
+      for (int k = 0; k < 3 * K; ++k) g_sh[k * n + i] = 0.f;
+    }
+    return;
   }
-  g_ologit[i] += gol;
-  for (int k = 0; k < 3 * K; ++k) g_sh[k * n + i] += gf[k];
+  const float keep = overwrite ? 0.f : 1.f;   // 0 * old would keep a NaN; select instead
+  auto put = [&](float* ptr, float val) { *ptr = overwrite ? val : *ptr * keep + val; };
+  for (int k = 0; k < 3; ++k) {
+    put(&g_means[k * n + i], gmu[k]);
+    put(&g_log_scales[k * n + i], G.s[k] * gsc[k]);
+  }
+  put(&g_ologit[i], gol);
+  for (int k = 0; k < 3 * K; ++k) put(&g_sh[k * n + i], gf[k]);
   // R(q) -> normalised quaternion -> raw quaternion
   const float qw = G.q[0], qx = G.q[1], qy = G.q[2], qz = G.q[3];
   const float* g = gRq;
@@ -344,16 +356,16 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
                  qy * g[5] + qx * g[6] + qy * g[7]);
   const float dot = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
   const float inv = 1.0f / G.qnorm;
-  for (int k = 0; k < 4; ++k) g_quats[k * n + i] += (dq[k] - G.q[k] * dot) * inv;
+  for (int k = 0; k < 4; ++k) put(&g_quats[k * n + i], (dq[k] - G.q[k] * dot) * inv);
 }
 
 __global__ void pose_reduce_kernel(const double* __restrict__ pose_part, int64_t nblocks,
-                                   int n_views, float* __restrict__ xi) {
+                                   int n_views, float* __restrict__ xi, int overwrite) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_views * 6) return;
   double acc = 0.0;
   for (int64_t b = 0; b < nblocks; ++b) acc += pose_part[b * n_views * 6 + t];
-  xi[t] += (float)acc;
+  xi[t] = overwrite ? (float)acc : xi[t] + (float)acc;
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -382,12 +394,15 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
   const int64_t n2d = 9 * g.n * (int64_t)vt.n_views;
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, n2d, s);
   if (e != hipSuccess) return e;
-  if (vt.n_tiles > 0)
+  if (vt.n_tiles > 0) {
+    kernel_event_start(GS_KERNEL_RENDER_BWD, s);
     hipLaunchKernelGGL(render_bwd_kernel, dim3((unsigned)vt.n_tiles), dim3(kBlock), 0, s, vt,
                        bins.ranges, bins.values, reinterpret_cast<const float2*>(p.xy),
                        reinterpret_cast<const float4*>(p.conic_opacity),
                        reinterpret_cast<const float4*>(p.rgb_depth), bg, dL_dimage, final_T,
                        n_contrib, grad2d);
+    kernel_event_stop(GS_KERNEL_RENDER_BWD, s);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (g.n == 0) return hipSuccess;
   const int64_t nblocks = (g.n + 255) / 256;
@@ -396,6 +411,7 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
   g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, g.n, cams_dev, vt.n_views, p.radius,  \
       grad2d, grads.means, grads.log_scales, grads.quats, grads.opacity_logits, grads.sh,        \
       pose_part, flags
+  kernel_event_start(GS_KERNEL_PROJECT_BWD, s);
   switch (g.sh_degree) {
     case 0: hipLaunchKernelGGL(project_bwd_kernel<0>, grid, block, 0, s, GS_BWD_ARGS); break;
     case 1: hipLaunchKernelGGL(project_bwd_kernel<1>, grid, block, 0, s, GS_BWD_ARGS); break;
@@ -403,11 +419,12 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
     default: hipLaunchKernelGGL(project_bwd_kernel<3>, grid, block, 0, s, GS_BWD_ARGS); break;
   }
 #undef GS_BWD_ARGS
+  kernel_event_stop(GS_KERNEL_PROJECT_BWD, s);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (!(flags & GS_BWD_NO_POSE)) {
     const int nt = vt.n_views * 6;
     hipLaunchKernelGGL(pose_reduce_kernel, dim3((nt + 63) / 64), dim3(64), 0, s, pose_part,
-                       nblocks, vt.n_views, grads.xi);
+                       nblocks, vt.n_views, grads.xi, (flags & GS_BWD_OVERWRITE) ? 1 : 0);
   }
   return hipGetLastError();
 }

@@ -92,11 +92,13 @@ hipError_t launch_render_fwd(const gs_projected& p, const gs_bins& bins, const V
                              float3 bg, float* image, float* final_T, uint32_t* n_contrib,
                              float* depth, hipStream_t s) {
   if (vt.n_tiles == 0) return hipSuccess;
+  kernel_event_start(GS_KERNEL_RENDER_FWD, s);
   hipLaunchKernelGGL(render_fwd_kernel, dim3((unsigned)vt.n_tiles), dim3(kBlock), 0, s, vt,
                      bins.ranges, bins.values, reinterpret_cast<const float2*>(p.xy),
                      reinterpret_cast<const float4*>(p.conic_opacity),
                      reinterpret_cast<const float4*>(p.rgb_depth), bg, image, final_T, n_contrib,
                      depth);
+  kernel_event_stop(GS_KERNEL_RENDER_FWD, s);
   return hipGetLastError();
 }
 

@@ -33,6 +33,12 @@ GS_ERR_HIP = 3
 GS_ERR_UNSUPPORTED = 4
 GS_BWD_NO_POSE = 1
 GS_BWD_POSE_ONLY = 2
+GS_BWD_OVERWRITE = 4
+GS_KERNEL_PREPROCESS = 0
+GS_KERNEL_BIN_SORT = 1
+GS_KERNEL_RENDER_FWD = 2
+GS_KERNEL_RENDER_BWD = 3
+GS_KERNEL_PROJECT_BWD = 4
 GS_MAX_VIEWS = 64
 TILE = 16
 
@@ -107,10 +113,15 @@ _lib.gs_render_bwd.argtypes = [ctypes.POINTER(gs_gaussians), ctypes.POINTER(gs_p
 _lib.gs_adam_step.argtypes = [_p, _p, _p, _p, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, ctypes.c_float, ctypes.c_int32, _p, _S]
 _lib.gs_l1_loss_grad.argtypes = [_p, _p, ctypes.POINTER(gs_views), _p, _p, _S]
+_lib.gs_set_kernel_events.argtypes = [ctypes.c_int, _p, _p]
+_lib.gs_adam_step_dev.argtypes = [_p, _p, _p, _p, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_float, _p, ctypes.c_int32, _p, _p,
+                                  ctypes.c_int64, _S]
 
 EXPORTED = ("gs_status_string", "gs_last_error", "gs_version", "gs_num_tiles", "gs_num_pixels",
             "gs_preprocess", "gs_bin_sort_workspace_size", "gs_bin_sort", "gs_render_fwd",
-            "gs_render_bwd_workspace_size", "gs_render_bwd", "gs_adam_step", "gs_l1_loss_grad")
+            "gs_render_bwd_workspace_size", "gs_render_bwd", "gs_adam_step", "gs_l1_loss_grad",
+            "gs_set_kernel_events", "gs_adam_step_dev")
 
 
 def lib() -> ctypes.CDLL:
@@ -370,7 +381,30 @@ def gs_adam_step(p: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Ten
                              _ptr(mask), _stream(stream)), "gs_adam_step")
 
 
+def gs_adam_step_dev(p: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch.Tensor, lr: float,
+                     beta1: float, beta2: float, eps: float, step_dev: torch.Tensor, commit: bool,
+                     mask: Optional[torch.Tensor] = None, guard_n_keys: Optional[torch.Tensor] = None,
+                     guard_capacity: int = 0, stream=None) -> None:
+    n = p.numel()
+    for x in (g, m, v):
+        if x.numel() != n:
+            raise ValueError("Adam tensors must have equal sizes")
+    if step_dev.dtype != torch.int32 or step_dev.numel() != 1:
+        raise ValueError("step_dev must be one int32")
+    _check(_lib.gs_adam_step_dev(_ptr(p), _ptr(g), _ptr(m), _ptr(v), n, lr, beta1, beta2, eps,
+                                 _ptr(step_dev), int(bool(commit)), _ptr(mask), _ptr(guard_n_keys),
+                                 guard_capacity, _stream(stream)), "gs_adam_step_dev")
+
+
 def gs_l1_loss_grad(image: torch.Tensor, target: torch.Tensor, views: Views, dL_dimage: torch.Tensor,
                     loss: Optional[torch.Tensor] = None, stream=None) -> None:
     _check(_lib.gs_l1_loss_grad(_ptr(image), _ptr(target), ctypes.byref(views.struct),
                                 _ptr(dL_dimage), _ptr(loss), _stream(stream)), "gs_l1_loss_grad")
+
+
+def gs_set_kernel_events(kernel: int, start: Optional["torch.cuda.Event"], stop: Optional["torch.cuda.Event"]) -> None:
+    """Bracket every launch of ``kernel`` (GS_KERNEL_*) on this thread with the
+    two (timing-enabled) events; None clears."""
+    sp = None if start is None else start.cuda_event
+    ep = None if stop is None else stop.cuda_event
+    _check(_lib.gs_set_kernel_events(kernel, sp, ep), "gs_set_kernel_events")

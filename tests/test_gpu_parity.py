@@ -139,6 +139,11 @@ def test_render_fwd_splats(gs, case):
 # full pipeline from Gaussian parameters
 # ---------------------------------------------------------------------------
 
+def ocams(wl):
+    """The cameras exactly as the float32 records hand them to the kernels."""
+    return [c.as_float32() for c in wl.cams]
+
+
 def _run_gpu(gs, wl, dl=None, flags=0):
     from paper_2409_09295_amd.rasterizer import Rasterizer
     g = gs.Gaussians.from_map(wl.gmap)
@@ -217,13 +222,13 @@ def _split_dl(views, dl):
 def _grad_parity(gs, wl, seed, check_pose=True):
     views = gs.Views(wl.cams)
     _log(f"grad parity {wl.name}: oracle forward")
-    res0 = O.render(wl.gmap, wl.cams, bg=wl.bg)
+    res0 = O.render(wl.gmap, ocams(wl), bg=wl.bg)
     dl = _masked_dl(views, res0, random_dl(views.sizes, seed))
     _log(f"grad parity {wl.name}: GPU")
     out = _run_gpu(gs, wl, dl)
     _compare_images(views, out, res0)
     _log(f"grad parity {wl.name}: oracle backward")
-    res = O.render(wl.gmap, wl.cams, bg=wl.bg, dL_dimage=_split_dl(views, dl))
+    res = O.render(wl.gmap, ocams(wl), bg=wl.bg, dL_dimage=_split_dl(views, dl))
     g = out["grads"]
     stats = {}
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
@@ -236,12 +241,14 @@ def _grad_parity(gs, wl, seed, check_pose=True):
 
 def test_c1_projection_and_image(gs):
     wl = scenes.config_c1(0)
-    res = O.render(wl.gmap, wl.cams, bg=wl.bg)
+    res = O.render(wl.gmap, ocams(wl), bg=wl.bg)
     out = _run_gpu(gs, wl)
     _check_projection(gs, wl, out, res)
     masked, worst = _compare_images(out["views"], out, res)
-    _log(f"c1 image: masked {masked} px, worst {worst:.3e}")
-    assert masked == 0
+    _log(f"c1 image: {masked} near-threshold px, worst {worst:.3e} elsewhere")
+    # c1 passes with no exclusions: every pixel, flagged or not
+    full = np.abs(np_(out["image"]).reshape(3, 120, 160) - res["views"][0]["image"]).max()
+    assert full <= 1e-4, full
     nc = np_(out["nc"]).reshape(120, 160)
     np.testing.assert_array_equal(nc, res["views"][0]["n_contrib"])
 
@@ -275,7 +282,7 @@ def test_c3_sampled_tiles(gs):
     picks = [(int(ty), int(tx)) for ty, tx in zip(rng.integers(0, TY, 10), rng.integers(0, TX, 10))]
     picks += [(0, 0), (TY - 1, TX - 1), (TY // 2, TX // 2)]
     _log("c3: oracle forward on sampled tiles")
-    res0 = O.render(wl.gmap, wl.cams, tiles=[picks])
+    res0 = O.render(wl.gmap, ocams(wl), tiles=[picks])
     dl = random_dl(views.sizes, 11).reshape(3, 480, 640)
     keep = np.zeros((480, 640), bool)
     for ty, tx in picks:
@@ -287,7 +294,7 @@ def test_c3_sampled_tiles(gs):
     masked, worst = _compare_images(views, out, res0)
     _log(f"c3 sampled image: masked {masked} px, worst {worst:.3e}")
     _log("c3: oracle backward on sampled tiles")
-    res = O.render(wl.gmap, wl.cams, dL_dimage=_split_dl(views, dl), tiles=[picks])
+    res = O.render(wl.gmap, ocams(wl), dL_dimage=_split_dl(views, dl), tiles=[picks])
     g = out["grads"]
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
         assert_grad_close(name, np_(getattr(g, name)), res["grads"][name])
