@@ -52,6 +52,7 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--retune", action="store_true", help="ignore the tuning cache")
     return ap.parse_args()
 
 
@@ -62,7 +63,7 @@ def _build(spec, seed):
     return scenes.config_metric(seed, n=spec["n"], n_views=spec["views"])
 
 
-def _cpu_baseline(wl, sample_tiles=24, seed=0):
+def _cpu_baseline(wl, sample_tiles=400, seed=0):
     """The FP64 oracle on a bounded sample: projection (all Gaussians) and
     compositing forward + backward of ``sample_tiles`` random 16x16 tiles of
     view 0.  Returns (Mpix/s, pixels, seconds, threads)."""
@@ -94,6 +95,7 @@ def main():
     import numpy as np
     import torch
     from paper_2409_09295_amd import gs
+    from paper_2409_09295_amd import autotune
     from paper_2409_09295_amd.replay import BatchedStep, PlainStep
 
     dev = "cuda"
@@ -109,6 +111,8 @@ def main():
 
     # ---------------- batched (headline) ----------------
     step = BatchedStep(g, views, targets)
+    tuned = autotune.tune(step, force=args.retune)
+    print(f"[bench] tuned: {tuned}", file=sys.stderr, flush=True)
     step.capture()
     for _ in range(args.warmup):
         step.step()
@@ -136,6 +140,10 @@ def main():
              gs.GS_KERNEL_RENDER_FWD: "render_fwd", gs.GS_KERNEL_RENDER_BWD: "render_bwd",
              gs.GS_KERNEL_PROJECT_BWD: "project_bwd"}
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in names}
+    for k, (a, b) in ev.items():
+        a.record()          # torch creates the HIP event on first record
+        b.record()
+    torch.cuda.synchronize()
     for k, (a, b) in ev.items():
         gs.gs_set_kernel_events(k, a, b)
     kt = {k: [] for k in names}
@@ -203,7 +211,7 @@ def main():
     if not args.no_cpu_baseline:
         mp, px, dt, thr = _cpu_baseline(wl)
         cpu = {"value": mp, "unit": "Mpix/s", "cores": thr, "kind": "oracle",
-               "sample": f"fwd+bwd of {px} px (24 random 16x16 tiles of view 0) incl. projection "
+               "sample": f"fwd+bwd of {px} px (400 random 16x16 tiles of view 0) incl. projection "
                          f"and its backward for all {wl.gmap.n} Gaussians; {dt:.1f} s"}
         print(f"[bench] cpu oracle: {mp:.5f} Mpix/s over {dt:.1f}s", file=sys.stderr, flush=True)
 
@@ -219,6 +227,8 @@ def main():
         "plain": {"value": mpix_plain, "ms_per_step": ms_plain,
                   "speedup_batched_over_plain": (mpix / mpix_plain) if mpix_plain else None},
         "kernel_ms": kms,
+        "tuning": {"fwd_pixels_per_lane": tuned["fwd_ppl"], "bwd_pixels_per_lane": tuned["bwd_ppl"],
+                   "table_ms": tuned.get("table")},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

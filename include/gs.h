@@ -176,6 +176,22 @@ const char* gs_last_error(void);
 /* Library version string. */
 const char* gs_version(void);
 
+/* Kernel configuration keys for gs_set_tuning(). */
+enum {
+  GS_TUNE_FWD_PIXELS_PER_LANE = 0, /* gs_render_fwd: pixels per lane, 1 | 2 | 4 (default 1) */
+  GS_TUNE_BWD_PIXELS_PER_LANE = 1, /* gs_render_bwd: pixels per lane, 1 | 2 | 4 (default 1) */
+  GS_TUNE_COUNT = 2
+};
+
+/* Process-wide kernel configuration, set by an autotuner.  A 16x16 tile is
+ * covered by 256 / value threads.  value 0 restores the default.  Applies to
+ * launches enqueued after the call; a captured graph keeps the configuration
+ * it was captured with.  Results are identical for every setting up to
+ * float32 summation order of the gradient atomics. */
+int gs_set_tuning(int key, int value);
+/* Current value of a tuning key (< 0 for an unknown key). */
+int gs_get_tuning(int key);
+
 /* Timing hook (thread-local): while set, every launch of `kernel` on this
  * thread is bracketed by hipEventRecord(start, stream) and
  * hipEventRecord(stop, stream) on the launch stream.  start/stop are

@@ -26,7 +26,8 @@ ARCH = os.environ.get("GSMI_OFFLOAD_ARCH", "gfx950")
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+          "-munsafe-fp-atomics", "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
+          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
 def _compile(src: str, extra) -> str:

@@ -99,6 +99,10 @@ __global__ void adam_commit_kernel(int32_t* __restrict__ step_dev,
   *step_dev = *step_dev + 1;
 }
 
+// Grid-stride over one view per blockIdx.y with a bounded number of blocks,
+// so the loss needs at most kL1Blocks float64 atomics per view.
+constexpr int kL1Blocks = 128;
+
 __global__ __launch_bounds__(256) void l1_grad_kernel(const float* __restrict__ image,
                                                       const float* __restrict__ target,
                                                       ViewTable vt, float* __restrict__ grad,
@@ -107,17 +111,16 @@ __global__ __launch_bounds__(256) void l1_grad_kernel(const float* __restrict__ 
   const int v = blockIdx.y;
   const ViewInfo& vi = vt.v[v];
   const int64_t count = 3 * (int64_t)vi.width * vi.height;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const float inv = 1.0f / (float)count;
+  const int64_t base = 3 * vi.pix_base;
   float a = 0.0f;
-  if (i < count) {
-    const int64_t o = 3 * vi.pix_base + i;
-    const float d = image[o] - target[o];
-    const float inv = 1.0f / (float)count;
-    grad[o] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
-    a = fabsf(d);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float d = image[base + i] - target[base + i];
+    grad[base + i] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
+    a += fabsf(d);
   }
   if (loss == nullptr) return;
-  if ((int64_t)blockIdx.x * blockDim.x >= count) return;   // whole block idle (uniform)
   for (int d = 32; d > 0; d >>= 1) a += __shfl_xor(a, d, 64);
   if ((threadIdx.x & 63) == 0) s_wave[threadIdx.x >> 6] = a;
   __syncthreads();
@@ -181,8 +184,9 @@ hipError_t launch_l1_loss_grad(const float* image, const float* target, const Vi
   for (int v = 0; v < vt.n_views; ++v)
     max_count = std::max<int64_t>(max_count, 3 * (int64_t)vt.v[v].width * vt.v[v].height);
   if (loss) hipLaunchKernelGGL(zero_f64_kernel, dim3(1), dim3(1), 0, s, loss);
-  hipLaunchKernelGGL(l1_grad_kernel, dim3((unsigned)((max_count + 255) / 256), vt.n_views),
-                     dim3(256), 0, s, image, target, vt, dL_dimage, loss);
+  const int64_t blocks = std::min<int64_t>(kL1Blocks, (max_count + 255) / 256);
+  hipLaunchKernelGGL(l1_grad_kernel, dim3((unsigned)blocks, vt.n_views), dim3(256), 0, s, image,
+                     target, vt, dL_dimage, loss);
   return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 // C ABI of libgsmi: argument validation, workspace planning and launches.
 // Every entry point validates all arguments before enqueuing anything.
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -13,6 +14,12 @@ namespace {
 thread_local char g_last_error[512] = "";
 thread_local hipEvent_t g_events[GS_KERNEL_COUNT][2] = {};
 }
+
+namespace {
+std::atomic<int> g_tuning[GS_TUNE_COUNT] = {{1}, {1}};
+}
+
+int tuning(int key) { return g_tuning[key].load(std::memory_order_relaxed); }
 
 void kernel_event_start(int kernel, hipStream_t s) {
   if (g_events[kernel][0]) (void)hipEventRecord(g_events[kernel][0], s);
@@ -155,6 +162,20 @@ int gs_set_kernel_events(int kernel, void* start_event, void* stop_event) {
   g_events[kernel][0] = static_cast<hipEvent_t>(start_event);
   g_events[kernel][1] = static_cast<hipEvent_t>(stop_event);
   return GS_OK;
+}
+
+int gs_set_tuning(int key, int value) {
+  if (key < 0 || key >= GS_TUNE_COUNT) return invalid("unknown tuning key %d", key);
+  if (value == 0) value = 1;
+  if (value != 1 && value != 2 && value != 4)
+    return invalid("pixels per lane must be 1, 2 or 4 (got %d)", value);
+  g_tuning[key].store(value, std::memory_order_relaxed);
+  return GS_OK;
+}
+
+int gs_get_tuning(int key) {
+  if (key < 0 || key >= GS_TUNE_COUNT) return -1;
+  return tuning(key);
 }
 
 int64_t gs_num_tiles(const gs_views* views) {

@@ -109,6 +109,9 @@ __device__ __forceinline__ bool eval_alpha(const float4& geo, const float4& app,
   return alpha >= kAlphaMin;
 }
 
+// Process-wide tuning values (see gs_set_tuning); always a supported value.
+int tuning(int key);
+
 // Optional per-kernel timing events (see gs_set_kernel_events).
 void kernel_event_start(int kernel, hipStream_t s);
 void kernel_event_stop(int kernel, hipStream_t s);

@@ -39,6 +39,56 @@ __device__ __forceinline__ float lane63(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
+// Transposed wavefront reduction of nine values with the gfx950 cross-half
+// swaps.  v_permlane32_swap(a, b) exchanges a's lanes 32-63 with b's lanes
+// 0-31, so adding its two results leaves a's 32-lane partial sums in lanes
+// 0-31 and b's in lanes 32-63: one swap and one add halve two values.
+// v_permlane16_swap does the same on 16-lane rows.  After both levels each
+// 16-lane row of three registers holds a distinct value, and four row-local
+// DPP adds finish the sums:
+//   q0 rows = {v0, v2, v1, v3}, q1 rows = {v4, v6, v5, v7}, q2 row 0 = v8.
+__device__ __forceinline__ float swap32_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap16_add(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float x) {
+  return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf,
+                                                        false));
+}
+
+__device__ __forceinline__ float row16_sum(float x) {
+  x = dpp_add<0x128>(x);   // row_ror:8
+  x = dpp_add<0x124>(x);   // row_ror:4
+  x = dpp_add<0x4e>(x);    // quad_perm [2,3,0,1]
+  x = dpp_add<0xb1>(x);    // quad_perm [1,0,3,2]
+  return x;                // every lane of the row holds the row total
+}
+
+struct Reduced9 {
+  float q0, q1, q2;
+};
+
+__device__ __forceinline__ Reduced9 wave_reduce9(float v0, float v1, float v2, float v3, float v4,
+                                                 float v5, float v6, float v7, float v8) {
+  const float h0 = swap32_add(v0, v1), h1 = swap32_add(v2, v3);
+  const float h2 = swap32_add(v4, v5), h3 = swap32_add(v6, v7);
+  const float h4 = swap32_add(v8, 0.0f);
+  Reduced9 r;
+  r.q0 = row16_sum(swap16_add(h0, h1));
+  r.q1 = row16_sum(swap16_add(h2, h3));
+  r.q2 = row16_sum(swap16_add(h4, h4));
+  return r;
+}
+
 __device__ __forceinline__ void stage_splat(uint32_t g, const float2* __restrict__ xy,
                                             const float4* __restrict__ co,
                                             const float4* __restrict__ rd, StagedSplat& out) {
@@ -50,11 +100,13 @@ __device__ __forceinline__ void stage_splat(uint32_t g, const float2* __restrict
   out.col = make_float4(r.x, r.y, r.z, __uint_as_float(g));
 }
 
-__global__ __launch_bounds__(kBlock) void render_bwd_kernel(
+template <int PPL>
+__global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     ViewTable vt, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
     const float2* __restrict__ xy, const float4* __restrict__ co, const float4* __restrict__ rd,
     float3 bg, const float* __restrict__ dL_dimage, const float* __restrict__ final_T,
     const uint32_t* __restrict__ n_contrib, float* __restrict__ grad2d) {
+  constexpr int NT = kBlock / PPL;
   __shared__ StagedSplat s_splat[kBlock];
   __shared__ uint32_t s_maxlast;
   const int tile = blockIdx.x;
@@ -62,29 +114,49 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(
   const ViewInfo& vi = vt.v[v];
   const int lt = tile - vi.tile_base;
   const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int px = tx * kTile + (w & 1) * 8 + (lane & 7);
-  const int py = ty * kTile + (w >> 1) * 8 + (lane >> 3);
-  const bool inside = px < vi.width && py < vi.height;
-  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  const int lane = threadIdx.x & 63;
+  // where wave_reduce9 leaves each value: row r = lane / 16 of q0 holds value
+  // {0, 2, 1, 3}[r] and of q1 value 4 + {0, 2, 1, 3}[r]; the per-value factors
+  // turn the accumulated sums into dL/du, dL/dv (from the log2-scaled conic)
+  // and dL/dQ00, dL/dQ01, dL/dQ11.
+  const int row = lane >> 4;
+  const int red_off0 = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
+  // value factors: u, v: -1/log2(e); Q00, Q11: -1/2; Q01: -1; o, r, g, b: 1
+  const float red_scale0 = (row == 0 || row == 2) ? -1.0f / kLog2e : (row == 1) ? -0.5f : -1.0f;
+  const float red_scale1 = (row == 0) ? -0.5f : 1.0f;
 
-  float T = 1.0f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
-  float S0 = bg.x, S1 = bg.y, S2 = bg.z;
-  uint32_t last = 0;
-  if (inside) {
-    const int64_t pix = vi.pix_base + (int64_t)py * vi.width + px;
-    const int64_t plane = (int64_t)vi.width * vi.height;
-    const int64_t off = (int64_t)py * vi.width + px;
-    const float* g = dL_dimage + 3 * vi.pix_base;
-    dC0 = g[off];
-    dC1 = g[plane + off];
-    dC2 = g[2 * plane + off];
-    T = final_T[pix];
-    last = n_contrib[pix];
+  float fpx[PPL], fpy[PPL], T[PPL], dC0[PPL], dC1[PPL], dC2[PPL], S0[PPL], S1[PPL], S2[PPL];
+  uint32_t last[PPL];
+  uint32_t mylast = 0;
+  const int64_t plane = (int64_t)vi.width * vi.height;
+  const float* gimg = dL_dimage + 3 * vi.pix_base;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int i = k * NT + (int)threadIdx.x;
+    const int q = i >> 6, l = i & 63;
+    const int px = tx * kTile + (q & 1) * 8 + (l & 7);
+    const int py = ty * kTile + (q >> 1) * 8 + (l >> 3);
+    fpx[k] = (float)px + 0.5f;
+    fpy[k] = (float)py + 0.5f;
+    T[k] = 1.0f;
+    dC0[k] = dC1[k] = dC2[k] = 0.f;
+    S0[k] = bg.x;
+    S1[k] = bg.y;
+    S2[k] = bg.z;
+    last[k] = 0;
+    if (px < vi.width && py < vi.height) {
+      const int64_t off = (int64_t)py * vi.width + px;
+      dC0[k] = gimg[off];
+      dC1[k] = gimg[plane + off];
+      dC2[k] = gimg[2 * plane + off];
+      T[k] = final_T[vi.pix_base + off];
+      last[k] = n_contrib[vi.pix_base + off];
+      mylast = max(mylast, last[k]);
+    }
   }
   if (threadIdx.x == 0) s_maxlast = 0;
   __syncthreads();
-  if (last) atomicMax(&s_maxlast, last);
+  if (mylast) atomicMax(&s_maxlast, mylast);
   __syncthreads();
   const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
   // n_contrib never exceeds the tile's list length for a matching forward;
@@ -95,57 +167,56 @@ __global__ __launch_bounds__(kBlock) void render_bwd_kernel(
   for (int64_t bend = maxlast; bend > 0; bend -= kBlock) {
     const int64_t bstart = max((int64_t)0, bend - kBlock);
     __syncthreads();
-    const int64_t k = bstart + (int64_t)threadIdx.x;
-    if (k < bend) stage_splat(values[s + (uint32_t)k], xy, co, rd, s_splat[threadIdx.x]);
+#pragma unroll
+    for (int r = 0; r < PPL; ++r) {
+      const int slot = r * NT + (int)threadIdx.x;
+      const int64_t k = bstart + slot;
+      if (k < bend) stage_splat(values[s + (uint32_t)k], xy, co, rd, s_splat[slot]);
+    }
     __syncthreads();
     for (int j = (int)(bend - bstart) - 1; j >= 0; --j) {
-      const int64_t pos = bstart + j;
+      const uint32_t pos = (uint32_t)(bstart + j);
       float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, g4 = 0.f, g5 = 0.f, g6 = 0.f, g7 = 0.f,
             g8 = 0.f;
       bool contrib = false;
       const float4 geo = s_splat[j].geo;
       const float4 app = s_splat[j].app;
-      if (pos < (int64_t)last) {
+      const float4 col = s_splat[j].col;
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        if (pos >= last[k]) continue;
         float alpha, raw, G, dx, dy;
-        if (eval_alpha(geo, app, fpx, fpy, alpha, raw, G, dx, dy)) {
-          contrib = true;
-          const float4 col = s_splat[j].col;
-          const float Tk = T / (1.0f - alpha);
-          const float wgt = alpha * Tk;
-          g6 = wgt * dC0;
-          g7 = wgt * dC1;
-          g8 = wgt * dC2;
-          const float dalpha = Tk * ((col.x - S0) * dC0 + (col.y - S1) * dC1 + (col.z - S2) * dC2);
-          S0 = alpha * col.x + (1.0f - alpha) * S0;
-          S1 = alpha * col.y + (1.0f - alpha) * S1;
-          S2 = alpha * col.z + (1.0f - alpha) * S2;
-          T = Tk;
-          if (raw <= kAlphaMax) {
-            g5 = G * dalpha;
-            const float gP = alpha * dalpha;   // dL/dpower
-            g0 = gP * (2.0f * geo.z * dx + geo.w * dy);
-            g1 = gP * (geo.w * dx + 2.0f * app.x * dy);
-            g2 = gP * dx * dx;
-            g3 = gP * dx * dy;
-            g4 = gP * dy * dy;
-          }
-        }
+        if (!eval_alpha(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy)) continue;
+        contrib = true;
+        const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
+        const float wgt = alpha * Tk;
+        g6 += wgt * dC0[k];
+        g7 += wgt * dC1[k];
+        g8 += wgt * dC2[k];
+        const float dalpha =
+            Tk * ((col.x - S0[k]) * dC0[k] + (col.y - S1[k]) * dC1[k] + (col.z - S2[k]) * dC2[k]);
+        S0[k] = alpha * col.x + (1.0f - alpha) * S0[k];
+        S1[k] = alpha * col.y + (1.0f - alpha) * S1[k];
+        S2[k] = alpha * col.z + (1.0f - alpha) * S2[k];
+        T[k] = Tk;
+        // below the 0.99 clamp alpha = o G: d alpha/do = G, d alpha/dpower = alpha
+        const float live = raw <= kAlphaMax ? dalpha : 0.0f;
+        g5 += G * live;
+        const float gP = alpha * live;   // dL/dpower
+        const float gdx = gP * dx, gdy = gP * dy;
+        g0 += 2.0f * geo.z * gdx + geo.w * gdy;
+        g1 += geo.w * gdx + 2.0f * app.x * gdy;
+        g2 += gdx * dx;
+        g3 += gdx * dy;
+        g4 += gdy * dy;
       }
       if (__ballot(contrib)) {
-        const float r0 = lane63(wave_sum_to_lane63(g0)) * (-1.0f / kLog2e);
-        const float r1 = lane63(wave_sum_to_lane63(g1)) * (-1.0f / kLog2e);
-        const float r2 = lane63(wave_sum_to_lane63(g2)) * -0.5f;
-        const float r3 = lane63(wave_sum_to_lane63(g3)) * -1.0f;
-        const float r4 = lane63(wave_sum_to_lane63(g4)) * -0.5f;
-        const float r5 = lane63(wave_sum_to_lane63(g5));
-        const float r6 = lane63(wave_sum_to_lane63(g6));
-        const float r7 = lane63(wave_sum_to_lane63(g7));
-        const float r8 = lane63(wave_sum_to_lane63(g8));
-        if (lane < 9) {
-          const float val = lane == 0 ? r0 : lane == 1 ? r1 : lane == 2 ? r2 : lane == 3 ? r3
-                          : lane == 4 ? r4 : lane == 5 ? r5 : lane == 6 ? r6 : lane == 7 ? r7 : r8;
-          const uint32_t gidx = __float_as_uint(s_splat[j].col.w);
-          unsafeAtomicAdd(&grad2d[(int64_t)gidx * 9 + lane], val);
+        const Reduced9 r = wave_reduce9(g0, g1, g2, g3, g4, g5, g6, g7, g8);
+        if ((lane & 15) == 0) {
+          const int64_t base = (int64_t)__float_as_uint(col.w) * 9;
+          unsafeAtomicAdd(&grad2d[base + red_off0], r.q0 * red_scale0);
+          unsafeAtomicAdd(&grad2d[base + red_off0 + 4], r.q1 * red_scale1);
+          if (lane == 0) unsafeAtomicAdd(&grad2d[base + 8], r.q2);
         }
       }
     }
@@ -359,13 +430,22 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
   for (int k = 0; k < 4; ++k) put(&g_quats[k * n + i], (dq[k] - G.q[k] * dot) * inv);
 }
 
-__global__ void pose_reduce_kernel(const double* __restrict__ pose_part, int64_t nblocks,
-                                   int n_views, float* __restrict__ xi, int overwrite) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_views * 6) return;
+// One workgroup per (view, component): strided float64 sum over the
+// per-workgroup partials, then a tree reduction in LDS (fixed order).
+__global__ __launch_bounds__(256) void pose_reduce_kernel(const double* __restrict__ pose_part,
+                                                          int64_t nblocks, int n_views,
+                                                          float* __restrict__ xi, int overwrite) {
+  __shared__ double s_acc[256];
+  const int t = blockIdx.x;   // view * 6 + component
   double acc = 0.0;
-  for (int64_t b = 0; b < nblocks; ++b) acc += pose_part[b * n_views * 6 + t];
-  xi[t] = overwrite ? (float)acc : xi[t] + (float)acc;
+  for (int64_t b = threadIdx.x; b < nblocks; b += 256) acc += pose_part[b * n_views * 6 + t];
+  s_acc[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s_acc[threadIdx.x] += s_acc[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) xi[t] = overwrite ? (float)s_acc[0] : xi[t] + (float)s_acc[0];
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -395,12 +475,21 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, n2d, s);
   if (e != hipSuccess) return e;
   if (vt.n_tiles > 0) {
+    const auto* xy = reinterpret_cast<const float2*>(p.xy);
+    const auto* co = reinterpret_cast<const float4*>(p.conic_opacity);
+    const auto* rd = reinterpret_cast<const float4*>(p.rgb_depth);
+    const int ppl = tuning(GS_TUNE_BWD_PIXELS_PER_LANE);
+    const dim3 grid((unsigned)vt.n_tiles);
     kernel_event_start(GS_KERNEL_RENDER_BWD, s);
-    hipLaunchKernelGGL(render_bwd_kernel, dim3((unsigned)vt.n_tiles), dim3(kBlock), 0, s, vt,
-                       bins.ranges, bins.values, reinterpret_cast<const float2*>(p.xy),
-                       reinterpret_cast<const float4*>(p.conic_opacity),
-                       reinterpret_cast<const float4*>(p.rgb_depth), bg, dL_dimage, final_T,
-                       n_contrib, grad2d);
+    if (ppl == 4)
+      hipLaunchKernelGGL(render_bwd_kernel<4>, grid, dim3(kBlock / 4), 0, s, vt, bins.ranges,
+                         bins.values, xy, co, rd, bg, dL_dimage, final_T, n_contrib, grad2d);
+    else if (ppl == 2)
+      hipLaunchKernelGGL(render_bwd_kernel<2>, grid, dim3(kBlock / 2), 0, s, vt, bins.ranges,
+                         bins.values, xy, co, rd, bg, dL_dimage, final_T, n_contrib, grad2d);
+    else
+      hipLaunchKernelGGL(render_bwd_kernel<1>, grid, dim3(kBlock), 0, s, vt, bins.ranges,
+                         bins.values, xy, co, rd, bg, dL_dimage, final_T, n_contrib, grad2d);
     kernel_event_stop(GS_KERNEL_RENDER_BWD, s);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -423,7 +512,7 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (!(flags & GS_BWD_NO_POSE)) {
     const int nt = vt.n_views * 6;
-    hipLaunchKernelGGL(pose_reduce_kernel, dim3((nt + 63) / 64), dim3(64), 0, s, pose_part,
+    hipLaunchKernelGGL(pose_reduce_kernel, dim3(nt), dim3(256), 0, s, pose_part,
                        nblocks, vt.n_views, grads.xi, (flags & GS_BWD_OVERWRITE) ? 1 : 0);
   }
   return hipGetLastError();

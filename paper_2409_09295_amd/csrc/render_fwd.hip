@@ -1,11 +1,15 @@
-// gs_render_fwd: front-to-back compositing, one 256-thread workgroup per
-// 16x16 tile of any view in the batch (one grid over all views).
+// gs_render_fwd: front-to-back compositing, one workgroup per 16x16 tile of
+// any view in the batch (a single grid spans all views).
 //
-// Each wavefront owns an 8x8 quadrant of the tile (lane -> pixel).  The
-// workgroup stages the tile's sorted splats in LDS 256 at a time (one
-// gathered record per thread), then every lane walks the batch; records are
-// read as LDS broadcasts.  A workgroup stops fetching batches once every
-// pixel has terminated.
+// A workgroup of 256 / PPL threads covers the tile, each lane owning PPL
+// pixels (PPL = 1, 2 or 4, chosen by the tuner): tile-local pixel
+// i = k * (256 / PPL) + thread maps to quadrant i / 64 and position i % 64
+// inside it, so with PPL = 1 each wavefront owns one 8x8 quadrant and with
+// PPL = 4 one wavefront owns the tile, every lane holding the same position
+// in the four quadrants.  The tile's sorted splats are staged in LDS 256 at
+// a time (gathered once per workgroup) and read back as wave-uniform
+// broadcasts, so a staged record serves 64 * PPL pixels per LDS read.  A
+// workgroup stops once every pixel has terminated.
 #include "gs_internal.h"
 
 namespace gsmi {
@@ -23,66 +27,91 @@ __device__ __forceinline__ void stage_splat(uint32_t g, const float2* __restrict
   out.col = make_float4(r.x, r.y, r.z, __uint_as_float(g));
 }
 
-__global__ __launch_bounds__(kBlock) void render_fwd_kernel(
+template <int PPL>
+__global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
     ViewTable vt, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
     const float2* __restrict__ xy, const float4* __restrict__ co, const float4* __restrict__ rd,
     float3 bg, float* __restrict__ image, float* __restrict__ final_T,
     uint32_t* __restrict__ n_contrib, float* __restrict__ depth_out) {
+  constexpr int NT = kBlock / PPL;
   __shared__ StagedSplat s_splat[kBlock];
   const int tile = blockIdx.x;
   const int v = find_view(vt, tile);
   const ViewInfo& vi = vt.v[v];
   const int lt = tile - vi.tile_base;
   const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int px = tx * kTile + (w & 1) * 8 + (lane & 7);
-  const int py = ty * kTile + (w >> 1) * 8 + (lane >> 3);
-  const bool inside = px < vi.width && py < vi.height;
-  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+
+  int px[PPL], py[PPL];
+  float fpx[PPL], fpy[PPL], T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL];
+  uint32_t last[PPL];
+  bool inside[PPL], done[PPL];
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int i = k * NT + (int)threadIdx.x;
+    const int q = i >> 6, l = i & 63;
+    px[k] = tx * kTile + (q & 1) * 8 + (l & 7);
+    py[k] = ty * kTile + (q >> 1) * 8 + (l >> 3);
+    inside[k] = px[k] < vi.width && py[k] < vi.height;
+    done[k] = !inside[k];
+    fpx[k] = (float)px[k] + 0.5f;
+    fpy[k] = (float)py[k] + 0.5f;
+    T[k] = 1.0f;
+    C0[k] = C1[k] = C2[k] = D[k] = 0.0f;
+    last[k] = 0;
+  }
 
   const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
-  bool done = !inside;
-  float T = 1.0f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
-  uint32_t last = 0;
   for (int64_t b = s; b < (int64_t)e; b += kBlock) {
-    if (__syncthreads_count(done ? 0 : 1) == 0) break;
-    const int64_t idx = b + threadIdx.x;
-    if (idx < (int64_t)e) stage_splat(values[idx], xy, co, rd, s_splat[threadIdx.x]);
+    bool all_done = true;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) all_done = all_done && done[k];
+    if (__syncthreads_count(all_done ? 0 : 1) == 0) break;
+#pragma unroll
+    for (int r = 0; r < PPL; ++r) {
+      const int slot = r * NT + (int)threadIdx.x;
+      const int64_t idx = b + slot;
+      if (idx < (int64_t)e) stage_splat(values[idx], xy, co, rd, s_splat[slot]);
+    }
     __syncthreads();
     const int cnt = (int)min((int64_t)kBlock, (int64_t)e - b);
-    if (!done) {
+    if (!all_done) {
       for (int j = 0; j < cnt; ++j) {
         const float4 geo = s_splat[j].geo;
         const float4 app = s_splat[j].app;
-        float alpha, raw, G, dx, dy;
-        if (!eval_alpha(geo, app, fpx, fpy, alpha, raw, G, dx, dy)) continue;
-        const float Tn = T * (1.0f - alpha);
-        if (Tn < kTMin) {
-          done = true;
-          break;
-        }
         const float4 col = s_splat[j].col;
-        const float wgt = alpha * T;
-        C0 += col.x * wgt;
-        C1 += col.y * wgt;
-        C2 += col.z * wgt;
-        D += app.z * wgt;
-        T = Tn;
-        last = (uint32_t)(b - (int64_t)s) + (uint32_t)j + 1;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+          if (done[k]) continue;
+          float alpha, raw, G, dx, dy;
+          if (!eval_alpha(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy)) continue;
+          const float Tn = T[k] * (1.0f - alpha);
+          if (Tn < kTMin) {
+            done[k] = true;
+            continue;
+          }
+          const float wgt = alpha * T[k];
+          C0[k] += col.x * wgt;
+          C1[k] += col.y * wgt;
+          C2[k] += col.z * wgt;
+          D[k] += app.z * wgt;
+          T[k] = Tn;
+          last[k] = (uint32_t)(b - (int64_t)s) + (uint32_t)j + 1;
+        }
       }
     }
   }
-  if (inside) {
-    const int64_t pix = vi.pix_base + (int64_t)py * vi.width + px;
-    const int64_t plane = (int64_t)vi.width * vi.height;
-    float* img = image + 3 * vi.pix_base;
-    const int64_t off = (int64_t)py * vi.width + px;
-    img[off] = C0 + T * bg.x;
-    img[plane + off] = C1 + T * bg.y;
-    img[2 * plane + off] = C2 + T * bg.z;
-    final_T[pix] = T;
-    n_contrib[pix] = last;
-    if (depth_out) depth_out[pix] = D;
+  const int64_t plane = (int64_t)vi.width * vi.height;
+  float* img = image + 3 * vi.pix_base;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    if (!inside[k]) continue;
+    const int64_t off = (int64_t)py[k] * vi.width + px[k];
+    img[off] = C0[k] + T[k] * bg.x;
+    img[plane + off] = C1[k] + T[k] * bg.y;
+    img[2 * plane + off] = C2[k] + T[k] * bg.z;
+    final_T[vi.pix_base + off] = T[k];
+    n_contrib[vi.pix_base + off] = last[k];
+    if (depth_out) depth_out[vi.pix_base + off] = D[k];
   }
 }
 
@@ -92,12 +121,21 @@ hipError_t launch_render_fwd(const gs_projected& p, const gs_bins& bins, const V
                              float3 bg, float* image, float* final_T, uint32_t* n_contrib,
                              float* depth, hipStream_t s) {
   if (vt.n_tiles == 0) return hipSuccess;
+  const auto* xy = reinterpret_cast<const float2*>(p.xy);
+  const auto* co = reinterpret_cast<const float4*>(p.conic_opacity);
+  const auto* rd = reinterpret_cast<const float4*>(p.rgb_depth);
+  const int ppl = tuning(GS_TUNE_FWD_PIXELS_PER_LANE);
+  const dim3 grid((unsigned)vt.n_tiles);
   kernel_event_start(GS_KERNEL_RENDER_FWD, s);
-  hipLaunchKernelGGL(render_fwd_kernel, dim3((unsigned)vt.n_tiles), dim3(kBlock), 0, s, vt,
-                     bins.ranges, bins.values, reinterpret_cast<const float2*>(p.xy),
-                     reinterpret_cast<const float4*>(p.conic_opacity),
-                     reinterpret_cast<const float4*>(p.rgb_depth), bg, image, final_T, n_contrib,
-                     depth);
+  if (ppl == 4)
+    hipLaunchKernelGGL(render_fwd_kernel<4>, grid, dim3(kBlock / 4), 0, s, vt, bins.ranges,
+                       bins.values, xy, co, rd, bg, image, final_T, n_contrib, depth);
+  else if (ppl == 2)
+    hipLaunchKernelGGL(render_fwd_kernel<2>, grid, dim3(kBlock / 2), 0, s, vt, bins.ranges,
+                       bins.values, xy, co, rd, bg, image, final_T, n_contrib, depth);
+  else
+    hipLaunchKernelGGL(render_fwd_kernel<1>, grid, dim3(kBlock), 0, s, vt, bins.ranges,
+                       bins.values, xy, co, rd, bg, image, final_T, n_contrib, depth);
   kernel_event_stop(GS_KERNEL_RENDER_FWD, s);
   return hipGetLastError();
 }

@@ -39,6 +39,8 @@ GS_KERNEL_BIN_SORT = 1
 GS_KERNEL_RENDER_FWD = 2
 GS_KERNEL_RENDER_BWD = 3
 GS_KERNEL_PROJECT_BWD = 4
+GS_TUNE_FWD_PIXELS_PER_LANE = 0
+GS_TUNE_BWD_PIXELS_PER_LANE = 1
 GS_MAX_VIEWS = 64
 TILE = 16
 
@@ -114,6 +116,8 @@ _lib.gs_adam_step.argtypes = [_p, _p, _p, _p, ctypes.c_int64, ctypes.c_float, ct
                               ctypes.c_float, ctypes.c_float, ctypes.c_int32, _p, _S]
 _lib.gs_l1_loss_grad.argtypes = [_p, _p, ctypes.POINTER(gs_views), _p, _p, _S]
 _lib.gs_set_kernel_events.argtypes = [ctypes.c_int, _p, _p]
+_lib.gs_set_tuning.argtypes = [ctypes.c_int, ctypes.c_int]
+_lib.gs_get_tuning.argtypes = [ctypes.c_int]
 _lib.gs_adam_step_dev.argtypes = [_p, _p, _p, _p, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, ctypes.c_float, _p, ctypes.c_int32, _p, _p,
                                   ctypes.c_int64, _S]
@@ -121,7 +125,7 @@ _lib.gs_adam_step_dev.argtypes = [_p, _p, _p, _p, ctypes.c_int64, ctypes.c_float
 EXPORTED = ("gs_status_string", "gs_last_error", "gs_version", "gs_num_tiles", "gs_num_pixels",
             "gs_preprocess", "gs_bin_sort_workspace_size", "gs_bin_sort", "gs_render_fwd",
             "gs_render_bwd_workspace_size", "gs_render_bwd", "gs_adam_step", "gs_l1_loss_grad",
-            "gs_set_kernel_events", "gs_adam_step_dev")
+            "gs_set_kernel_events", "gs_adam_step_dev", "gs_set_tuning", "gs_get_tuning")
 
 
 def lib() -> ctypes.CDLL:
@@ -407,4 +411,14 @@ def gs_set_kernel_events(kernel: int, start: Optional["torch.cuda.Event"], stop:
     two (timing-enabled) events; None clears."""
     sp = None if start is None else start.cuda_event
     ep = None if stop is None else stop.cuda_event
+    if (start is not None and not sp) or (stop is not None and not ep):
+        raise ValueError("record each event once before registering it (torch creates it lazily)")
     _check(_lib.gs_set_kernel_events(kernel, sp, ep), "gs_set_kernel_events")
+
+
+def gs_set_tuning(key: int, value: int) -> None:
+    _check(_lib.gs_set_tuning(key, value), "gs_set_tuning")
+
+
+def gs_get_tuning(key: int) -> int:
+    return int(_lib.gs_get_tuning(key))

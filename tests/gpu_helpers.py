@@ -24,16 +24,18 @@ def random_dl(views_sizes, seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def assert_grad_close(name, g, ref, rel=1e-3):
-    """|g - ref| <= rel * max(|ref|, 1e-3 * max|ref|) elementwise and
-    ||g - ref|| <= rel * ||ref|| for the group."""
+def assert_grad_close(name, g, ref, rel=1e-3, atol_frac=1e-5):
+    """Elementwise |g - ref| <= rel |ref| + atol_frac max|ref|, and the group's
+    ||g - ref||_2 <= rel ||ref||_2.  The absolute floor covers float32
+    summation roundoff in elements whose per-pixel contributions cancel
+    (their exact value is orders of magnitude below the group's largest)."""
     g = np.asarray(g, np.float64).reshape(-1)
     ref = np.asarray(ref, np.float64).reshape(-1)
     scale = np.abs(ref).max() if ref.size else 0.0
     if scale == 0.0:
         assert np.abs(g).max() == 0.0 if g.size else True, name
         return
-    tol = rel * np.maximum(np.abs(ref), 1e-3 * scale)
+    tol = rel * np.abs(ref) + atol_frac * scale
     err = np.abs(g - ref)
     bad = err > tol
     l2 = np.linalg.norm(g - ref) / np.linalg.norm(ref)

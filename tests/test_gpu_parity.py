@@ -110,8 +110,23 @@ def _render_gpu(gs, sp, cams, bg=(0.0, 0.0, 0.0)):
     return views, img, Tf, nc, dep
 
 
+@pytest.fixture
+def ppl_setting(gs, request):
+    """Runs a test under a pixels-per-lane setting of both tile kernels."""
+    fwd, bwd = request.param
+    gs.gs_set_tuning(gs.GS_TUNE_FWD_PIXELS_PER_LANE, fwd)
+    gs.gs_set_tuning(gs.GS_TUNE_BWD_PIXELS_PER_LANE, bwd)
+    yield request.param
+    gs.gs_set_tuning(gs.GS_TUNE_FWD_PIXELS_PER_LANE, 0)
+    gs.gs_set_tuning(gs.GS_TUNE_BWD_PIXELS_PER_LANE, 0)
+
+
+PPL_SETTINGS = [(1, 1), (2, 2), (4, 4)]
+
+
+@pytest.mark.parametrize("ppl_setting", PPL_SETTINGS, indirect=True)
 @pytest.mark.parametrize("case", list(BIN_CASES))
-def test_render_fwd_splats(gs, case):
+def test_render_fwd_splats(gs, case, ppl_setting):
     cams = BIN_CASES[case]
     n = 2500 if case != "ragged_multi_view" else 4000
     sp = scenes.random_splats(n, cams, seed=31)
@@ -253,7 +268,8 @@ def test_c1_projection_and_image(gs):
     np.testing.assert_array_equal(nc, res["views"][0]["n_contrib"])
 
 
-def test_c1_gradients(gs):
+@pytest.mark.parametrize("ppl_setting", PPL_SETTINGS, indirect=True)
+def test_c1_gradients(gs, ppl_setting):
     _grad_parity(gs, scenes.config_c1(0), seed=5)
 
 
@@ -261,7 +277,8 @@ def test_c2_gradients(gs):
     _grad_parity(gs, scenes.config_c2(0), seed=6)
 
 
-def test_background_and_multi_view_gradients(gs):
+@pytest.mark.parametrize("ppl_setting", [(2, 4)], indirect=True)
+def test_background_and_multi_view_gradients(gs, ppl_setting):
     # two views of one cloud, non-black background: gradients sum over views
     wl = scenes.config_c1(3)
     rng = np.random.default_rng(4)
