@@ -1,13 +1,17 @@
 // gs_preprocess: project every Gaussian into every view of a batch.
 //
-// One lane per Gaussian.  The Gaussian's parameters are read once with
-// coalesced component-major loads (lane i reads element i of each component
-// array) and reused for all views, so a batch of V views costs one read of
-// the map plus V writes of 52 bytes per Gaussian.  Camera records are
-// wave-uniform.
+// One lane per (Gaussian, group of kViewsPerLane views).  The Gaussian's
+// parameters are read with coalesced component-major loads (lane i reads
+// element i of each component array) and reused for every view of the group,
+// so a batch of V views costs ceil(V / kViewsPerLane) reads of the map (the
+// repeats hit in L2/MALL) plus V writes of 52 bytes per Gaussian; splitting
+// the views over grid.y keeps enough wavefronts in flight to hide the long
+// per-view dependency chain.  Camera records are wave-uniform.
 #include "project.h"
 
 namespace gsmi {
+
+constexpr int kViewsPerLane = 4;
 
 template <int DEG>
 __global__ __launch_bounds__(256) void preprocess_kernel(
@@ -20,10 +24,14 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
   if (i >= n) return;
   GaussState G;
   load_gauss(means, log_scales, quats, ologit, n, i, G);
-  for (int v = 0; v < n_views; ++v) {
+  SHCoef<DEG> C;
+  load_sh<DEG>(sh, n, i, C);
+  const int v0 = blockIdx.y * kViewsPerLane;
+  const int v1 = min(n_views, v0 + kViewsPerLane);
+  for (int v = v0; v < v1; ++v) {
     const gs_camera cam = cams[v];
     ViewState S;
-    project_view<DEG>(G, cam, sh, n, i, S);
+    project_view<DEG>(G, cam, C, S);
     const int64_t o = (int64_t)v * n + i;
     if (S.visible) {
       xy[o] = make_float2(S.u, S.v);
@@ -43,7 +51,7 @@ hipError_t launch_preprocess(const gs_gaussians& g, const gs_camera* cams_dev, i
                              const gs_projected& out, hipStream_t s) {
   if (g.n == 0) return hipSuccess;
   const dim3 block(256);
-  const dim3 grid((unsigned)((g.n + 255) / 256));
+  const dim3 grid((unsigned)((g.n + 255) / 256), (unsigned)((n_views + kViewsPerLane - 1) / kViewsPerLane));
   auto* xy = reinterpret_cast<float2*>(out.xy);
   auto* co = reinterpret_cast<float4*>(out.conic_opacity);
   auto* rd = reinterpret_cast<float4*>(out.rgb_depth);

@@ -179,10 +179,23 @@ struct ViewState {
   bool visible;
 };
 
+// SH coefficients of one Gaussian, [3][K] in registers.
+template <int DEG>
+struct SHCoef {
+  float f[3 * SHDim<DEG>::K];
+};
+
+template <int DEG>
+__device__ __forceinline__ void load_sh(const float* __restrict__ sh, int64_t n, int64_t i,
+                                        SHCoef<DEG>& C) {
+  constexpr int K = SHDim<DEG>::K;
+#pragma unroll
+  for (int k = 0; k < 3 * K; ++k) C.f[k] = sh[k * n + i];
+}
+
 template <int DEG>
 __device__ __forceinline__ void project_view(const GaussState& G, const gs_camera& cam,
-                                             const float* __restrict__ sh, int64_t n, int64_t i,
-                                             ViewState& S) {
+                                             const SHCoef<DEG>& C, ViewState& S) {
   const float* W = cam.R;
   S.visible = false;
   S.radius = 0;
@@ -197,7 +210,7 @@ __device__ __forceinline__ void project_view(const GaussState& G, const gs_camer
   }
   const float z = S.p[2];
   if (!G.ok || !(z > kZNear)) return;
-  S.inv_z = 1.0f / z;
+  S.inv_z = __builtin_amdgcn_rcpf(z);
   const float fx = cam.fx, fy = cam.fy;
   const float rx = S.p[0] * S.inv_z, ry = S.p[1] * S.inv_z;
   S.u = fx * rx + cam.cx;
@@ -228,7 +241,7 @@ __device__ __forceinline__ void project_view(const GaussState& G, const gs_camer
   const float m12 = S.A0[1] * S.A1[2] - S.A0[2] * S.A1[1];
   S.det = (m01 * m01 + m02 * m02 + m12 * m12) + kDilation * (S.a + S.c) + kDilation * kDilation;
   if (!(S.det > 0.0f)) return;
-  const float inv_det = 1.0f / S.det;
+  const float inv_det = __builtin_amdgcn_rcpf(S.det);
   const float s0 = S.a + kDilation, s2 = S.c + kDilation;
   S.q0 = s2 * inv_det;
   S.q1 = -S.b * inv_det;
@@ -243,14 +256,14 @@ __device__ __forceinline__ void project_view(const GaussState& G, const gs_camer
     cc[k] = -(W[0 * 3 + k] * cam.t[0] + W[1 * 3 + k] * cam.t[1] + W[2 * 3 + k] * cam.t[2]);
   float d[3] = {G.mu[0] - cc[0], G.mu[1] - cc[1], G.mu[2] - cc[2]};
   S.dnorm = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-  const float invd = 1.0f / S.dnorm;
+  const float invd = __builtin_amdgcn_rsqf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   for (int k = 0; k < 3; ++k) S.dir[k] = d[k] * invd;
   constexpr int K = SHDim<DEG>::K;
   float Y[K];
   sh_basis<DEG>(S.dir[0], S.dir[1], S.dir[2], Y);
   for (int ch = 0; ch < 3; ++ch) {
     float acc = 0.5f;
-    for (int k = 0; k < K; ++k) acc += sh[(ch * K + k) * n + i] * Y[k];
+    for (int k = 0; k < K; ++k) acc += C.f[ch * K + k] * Y[k];
     S.rgb_pos[ch] = acc >= 0.0f;
     S.rgb[ch] = fmaxf(acc, 0.0f);
   }

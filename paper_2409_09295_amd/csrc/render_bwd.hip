@@ -8,10 +8,13 @@
 // are summed over the wavefront with DPP row operations and added to a
 // per-(view, splat) accumulator with one 9-lane atomic.
 //
-// Pass 2 (per Gaussian, all views): re-evaluates the projection and chains
-// the screen-space partials to the map parameters (summed over views in
-// registers) and to each view's pose tangent; pose partials are reduced per
-// workgroup in float64 and summed over workgroups by a final small kernel.
+// The screen-space partials live in a Gaussian-major [n][V][9] buffer.
+//
+// Pass 2 (one lane per (Gaussian, view)): re-evaluates the projection and
+// chains the screen-space partials to the map parameters, summed over the
+// Gaussian's view lanes with cross-lane adds, and to each view's pose
+// tangent; pose partials are reduced per workgroup in float64 and summed over
+// workgroups by a final small kernel (fixed order, deterministic).
 #include "project.h"
 
 namespace gsmi {
@@ -89,14 +92,20 @@ __device__ __forceinline__ Reduced9 wave_reduce9(float v0, float v1, float v2, f
   return r;
 }
 
-__device__ __forceinline__ void stage_splat(uint32_t g, const float2* __restrict__ xy,
+// Stages splat `g` (index view * n + Gaussian into the [V][n] splat arrays)
+// and the index Gaussian * V + view of its accumulator in the Gaussian-major
+// [n][V][9] screen-space gradient buffer.
+__device__ __forceinline__ void stage_splat(uint32_t g, uint32_t n, uint32_t n_views,
+                                            const float2* __restrict__ xy,
                                             const float4* __restrict__ co,
                                             const float4* __restrict__ rd, StagedSplat& out) {
   const float2 m = xy[g];
   const float4 c = co[g];
   const float4 r = rd[g];
+  const uint32_t view = g / n;
+  const uint32_t acc = (g - view * n) * n_views + view;
   out.geo = make_float4(m.x, m.y, -0.5f * kLog2e * c.x, -kLog2e * c.y);
-  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.w, 0.0f);
+  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.w, __uint_as_float(acc));
   out.col = make_float4(r.x, r.y, r.z, __uint_as_float(g));
 }
 
@@ -105,7 +114,7 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     ViewTable vt, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
     const float2* __restrict__ xy, const float4* __restrict__ co, const float4* __restrict__ rd,
     float3 bg, const float* __restrict__ dL_dimage, const float* __restrict__ final_T,
-    const uint32_t* __restrict__ n_contrib, float* __restrict__ grad2d) {
+    const uint32_t* __restrict__ n_contrib, uint32_t n_gauss, float* __restrict__ grad2d) {
   constexpr int NT = kBlock / PPL;
   __shared__ StagedSplat s_splat[kBlock];
   __shared__ uint32_t s_maxlast;
@@ -171,7 +180,9 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     for (int r = 0; r < PPL; ++r) {
       const int slot = r * NT + (int)threadIdx.x;
       const int64_t k = bstart + slot;
-      if (k < bend) stage_splat(values[s + (uint32_t)k], xy, co, rd, s_splat[slot]);
+      if (k < bend)
+        stage_splat(values[s + (uint32_t)k], n_gauss, (uint32_t)vt.n_views, xy, co, rd,
+                    s_splat[slot]);
     }
     __syncthreads();
     for (int j = (int)(bend - bstart) - 1; j >= 0; --j) {
@@ -213,7 +224,7 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
       if (__ballot(contrib)) {
         const Reduced9 r = wave_reduce9(g0, g1, g2, g3, g4, g5, g6, g7, g8);
         if ((lane & 15) == 0) {
-          const int64_t base = (int64_t)__float_as_uint(col.w) * 9;
+          const int64_t base = (int64_t)__float_as_uint(app.w) * 9;
           unsafeAtomicAdd(&grad2d[base + red_off0], r.q0 * red_scale0);
           unsafeAtomicAdd(&grad2d[base + red_off0 + 4], r.q1 * red_scale1);
           if (lane == 0) unsafeAtomicAdd(&grad2d[base + 8], r.q2);
@@ -227,207 +238,247 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
 // per-Gaussian backward through the projection
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ float wave_sum_all(float x) {
-  return lane63(wave_sum_to_lane63(x));
+// Sum over the LPG lanes of each lane group (lanes l with equal l / LPG),
+// result in every lane of the group.  Quad permutes for distances 1 and 2,
+// then mirrors (valid once the smaller groups are uniform), then the
+// cross-row swaps.
+template <int LPG>
+__device__ __forceinline__ float group_sum(float x) {
+  if (LPG >= 2) x = dpp_add<0xb1>(x);   // quad_perm [1,0,3,2]
+  if (LPG >= 4) x = dpp_add<0x4e>(x);   // quad_perm [2,3,0,1]
+  if (LPG >= 8) x = dpp_add<0x141>(x);  // row_half_mirror
+  if (LPG >= 16) x = dpp_add<0x140>(x); // row_mirror
+  if (LPG >= 32) x = swap16_add(x, x);
+  if (LPG >= 64) x = swap32_add(x, x);
+  return x;
 }
 
+// Sum over lane groups, keeping the position inside the group (lane l and
+// l + m * LPG are added): moves that preserve l mod LPG.
+template <int LPG>
+__device__ __forceinline__ float across_groups(float x) {
+  if (LPG <= 1) x = dpp_add<0xb1>(x);   // quad_perm [1,0,3,2]
+  if (LPG <= 2) x = dpp_add<0x4e>(x);   // quad_perm [2,3,0,1]
+  if (LPG <= 4) x = dpp_add<0x124>(x);  // row_ror:4
+  if (LPG <= 8) x = dpp_add<0x128>(x);  // row_ror:8
+  if (LPG <= 16) x = swap16_add(x, x);
+  if (LPG <= 32) x = swap32_add(x, x);
+  return x;
+}
+
+// Slots of the per-(Gaussian, view) contribution vector.
+constexpr int kCMu = 0, kCRq = 3, kCSc = 12, kCOl = 15, kCSh = 16;
+
+// Chain the nine screen-space partials of one (Gaussian, view) to the map
+// parameters (accumulated into c) and to the view's pose tangent.
 template <int DEG>
+__device__ __forceinline__ void chain_one(const GaussState& G, const gs_camera& cam,
+                                          const float* __restrict__ sh, int64_t n, int64_t i,
+                                          const float* g2, float* c, float* pose) {
+  constexpr int K = SHDim<DEG>::K;
+  SHCoef<DEG> C;
+  load_sh<DEG>(sh, n, i, C);
+  ViewState S;
+  project_view<DEG>(G, cam, C, S);
+  const float* W = cam.R;
+  const float* t = cam.t;
+  float GW[9] = {0.f}, gt[3] = {0.f, 0.f, 0.f}, gp[3];
+  // opacity
+  c[kCOl] += G.o * (1.0f - G.o) * g2[5];
+  // colour -> SH coefficients and view direction
+  float Y[K];
+  sh_basis<DEG>(S.dir[0], S.dir[1], S.dir[2], Y);
+  const float grgb[3] = {S.rgb_pos[0] ? g2[6] : 0.f, S.rgb_pos[1] ? g2[7] : 0.f,
+                         S.rgb_pos[2] ? g2[8] : 0.f};
+  float wk[K];
+  for (int k = 0; k < K; ++k) wk[k] = 0.f;
+  for (int ch = 0; ch < 3; ++ch)
+    for (int k = 0; k < K; ++k) {
+      c[kCSh + ch * K + k] += grgb[ch] * Y[k];
+      wk[k] += grgb[ch] * C.f[ch * K + k];
+    }
+  float gdir[3];
+  sh_basis_grad<DEG>(S.dir[0], S.dir[1], S.dir[2], wk, gdir[0], gdir[1], gdir[2]);
+  const float dd = S.dir[0] * gdir[0] + S.dir[1] * gdir[1] + S.dir[2] * gdir[2];
+  const float invn = 1.0f / S.dnorm;
+  float gcc[3];
+  for (int k = 0; k < 3; ++k) {
+    const float gv = (gdir[k] - S.dir[k] * dd) * invn;
+    c[kCMu + k] += gv;
+    gcc[k] = -gv;
+  }
+  // camera centre c = -W^T t
+  for (int jj = 0; jj < 3; ++jj)
+    for (int ii = 0; ii < 3; ++ii) {
+      GW[jj * 3 + ii] -= t[jj] * gcc[ii];
+      gt[jj] -= W[jj * 3 + ii] * gcc[ii];
+    }
+  // conic -> Sigma2 entries: dL/dSigma' = -Q Gq Q
+  const float h = 0.5f * g2[3];
+  const float X00 = S.q0 * (S.q0 * g2[2] + S.q1 * h) + S.q1 * (S.q0 * h + S.q1 * g2[4]);
+  const float X01 = S.q0 * (S.q1 * g2[2] + S.q2 * h) + S.q1 * (S.q1 * h + S.q2 * g2[4]);
+  const float X11 = S.q1 * (S.q1 * g2[2] + S.q2 * h) + S.q2 * (S.q1 * h + S.q2 * g2[4]);
+  const float ga = -X00, gb = -2.0f * X01, gc = -X11;
+  float gA0[3], gA1[3];
+  for (int k = 0; k < 3; ++k) {
+    gA0[k] = 2.0f * ga * S.A0[k] + gb * S.A1[k];
+    gA1[k] = gb * S.A0[k] + 2.0f * gc * S.A1[k];
+  }
+  float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f, gB[9];
+  for (int k = 0; k < 3; ++k) {
+    gJ00 += gA0[k] * S.B[0 * 3 + k];
+    gJ02 += gA0[k] * S.B[2 * 3 + k];
+    gJ11 += gA1[k] * S.B[1 * 3 + k];
+    gJ12 += gA1[k] * S.B[2 * 3 + k];
+    gB[0 * 3 + k] = S.J00 * gA0[k];
+    gB[1 * 3 + k] = S.J11 * gA1[k];
+    gB[2 * 3 + k] = S.J02 * gA0[k] + S.J12 * gA1[k];
+  }
+  // camera-frame position (projection and Jacobian)
+  const float iz = S.inv_z, iz2 = iz * iz;
+  const float fx = cam.fx, fy = cam.fy;
+  gp[0] = g2[0] * fx * iz;
+  gp[1] = g2[1] * fy * iz;
+  gp[2] = -(g2[0] * fx * S.p[0] + g2[1] * fy * S.p[1]) * iz2;
+  gp[2] += -gJ00 * fx * iz2 - gJ11 * fy * iz2;
+  if (!S.clx) {
+    gp[0] += -gJ02 * fx * iz2;
+    gp[2] += gJ02 * 2.0f * fx * S.p[0] * iz2 * iz;
+  } else {
+    gp[2] += gJ02 * fx * S.tx * iz2;
+  }
+  if (!S.cly) {
+    gp[1] += -gJ12 * fy * iz2;
+    gp[2] += gJ12 * 2.0f * fy * S.p[1] * iz2 * iz;
+  } else {
+    gp[2] += gJ12 * fy * S.ty * iz2;
+  }
+  // p = W mu + t
+  for (int r = 0; r < 3; ++r) {
+    gt[r] += gp[r];
+    for (int k = 0; k < 3; ++k) {
+      c[kCMu + k] += W[r * 3 + k] * gp[r];
+      GW[r * 3 + k] += gp[r] * G.mu[k];
+    }
+  }
+  // B = W M with M = R(q) diag(s)
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) {
+      float gm = 0.f, gw = 0.f;
+      for (int q = 0; q < 3; ++q) {
+        gm += W[q * 3 + r] * gB[q * 3 + k];
+        gw += gB[r * 3 + q] * G.M[k * 3 + q];
+      }
+      c[kCRq + r * 3 + k] += gm * G.s[k];
+      c[kCSc + k] += gm * G.Rq[r * 3 + k];
+      GW[r * 3 + k] += gw;
+    }
+  // dL/dphi = <dL/dW, [e]x W> + <dL/dt, [e]x t>, dL/drho = dL/dt
+  float Mm[9];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k)
+      Mm[r * 3 + k] = GW[r * 3 + 0] * W[k * 3 + 0] + GW[r * 3 + 1] * W[k * 3 + 1] +
+                      GW[r * 3 + 2] * W[k * 3 + 2];
+  pose[0] += gt[0];
+  pose[1] += gt[1];
+  pose[2] += gt[2];
+  pose[3] += Mm[7] - Mm[5] + (t[1] * gt[2] - t[2] * gt[1]);
+  pose[4] += Mm[2] - Mm[6] + (t[2] * gt[0] - t[0] * gt[2]);
+  pose[5] += Mm[3] - Mm[1] + (t[0] * gt[1] - t[1] * gt[0]);
+}
+
+constexpr int kProjBwdMaxBlocks = 2048;
+
+// One lane per (Gaussian, view): wavefronts hold 64 / LPG Gaussians with LPG
+// lanes each (LPG = next power of two >= views).  Map gradients are summed
+// over a Gaussian's lanes in registers (group_sum), pose partials over the
+// Gaussians of each view (across_groups), then per workgroup in float64.
+template <int DEG, int LPG>
 __global__ __launch_bounds__(256) void project_bwd_kernel(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ ologit,
     const float* __restrict__ sh, int64_t n, const gs_camera* __restrict__ cams, int n_views,
-    const int32_t* __restrict__ radius, const float* __restrict__ grad2d,
-    float* __restrict__ g_means, float* __restrict__ g_log_scales, float* __restrict__ g_quats,
-    float* __restrict__ g_ologit, float* __restrict__ g_sh, double* __restrict__ pose_part,
-    uint32_t flags) {
+    const float* __restrict__ grad2d, float* __restrict__ g_means,
+    float* __restrict__ g_log_scales, float* __restrict__ g_quats, float* __restrict__ g_ologit,
+    float* __restrict__ g_sh, double* __restrict__ pose_part, uint32_t flags) {
   constexpr int K = SHDim<DEG>::K;
-  __shared__ double s_pose[4][6];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = i < n;
+  constexpr int NC = kCSh + 3 * K;
+  constexpr int GPW = 64 / LPG;
+  __shared__ float s_pose[4][64][6];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int sub = lane / LPG, v = lane % LPG;
+  const bool view_ok = v < n_views;
   const bool want_pose = !(flags & GS_BWD_NO_POSE);
   const bool want_map = !(flags & GS_BWD_POSE_ONLY);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  GaussState G;
-  if (valid) load_gauss(means, log_scales, quats, ologit, n, i, G);
-  else G.ok = false;
-  float gmu[3] = {0.f, 0.f, 0.f}, gRq[9] = {0.f}, gsc[3] = {0.f, 0.f, 0.f}, gol = 0.f;
-  float gf[3 * K];
-  for (int k = 0; k < 3 * K; ++k) gf[k] = 0.f;
-
-  for (int v = 0; v < n_views; ++v) {
-    float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    const int64_t o = (int64_t)v * n + i;
+  const bool overwrite = (flags & GS_BWD_OVERWRITE) != 0;
+  float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const int64_t per_block = 4 * GPW;
+  for (int64_t base = (int64_t)blockIdx.x * per_block; base < n;
+       base += (int64_t)gridDim.x * per_block) {
+    const int64_t i = base + w * GPW + sub;
+    const bool valid = i < n;
+    GaussState G;
+    if (valid) load_gauss(means, log_scales, quats, ologit, n, i, G);
+    else G.ok = false;
+    float c[NC];
+    for (int k = 0; k < NC; ++k) c[k] = 0.f;
+    bool active = valid && view_ok && G.ok;
     float g2[9];
-    bool active = valid && G.ok && radius[o] > 0;
     if (active) {
+      const float* src = grad2d + ((int64_t)i * n_views + v) * 9;
       bool nz = false;
       for (int k = 0; k < 9; ++k) {
-        g2[k] = grad2d[o * 9 + k];
+        g2[k] = src[k];
         nz = nz || g2[k] != 0.0f;
       }
       active = nz;
     }
-    if (active) {
-      const gs_camera cam = cams[v];
-      ViewState S;
-      project_view<DEG>(G, cam, sh, n, i, S);
-      const float* W = cam.R;
-      const float* t = cam.t;
-      float GW[9] = {0.f}, gt[3] = {0.f, 0.f, 0.f}, gp[3];
-      // opacity
-      gol += G.o * (1.0f - G.o) * g2[5];
-      // colour -> SH coefficients and view direction
-      float Y[K];
-      sh_basis<DEG>(S.dir[0], S.dir[1], S.dir[2], Y);
-      const float grgb[3] = {S.rgb_pos[0] ? g2[6] : 0.f, S.rgb_pos[1] ? g2[7] : 0.f,
-                             S.rgb_pos[2] ? g2[8] : 0.f};
-      float wk[K];
-      for (int k = 0; k < K; ++k) wk[k] = 0.f;
-      for (int ch = 0; ch < 3; ++ch)
-        for (int k = 0; k < K; ++k) {
-          gf[ch * K + k] += grgb[ch] * Y[k];
-          wk[k] += grgb[ch] * sh[(ch * K + k) * n + i];
-        }
-      float gdir[3];
-      sh_basis_grad<DEG>(S.dir[0], S.dir[1], S.dir[2], wk, gdir[0], gdir[1], gdir[2]);
-      const float dd = S.dir[0] * gdir[0] + S.dir[1] * gdir[1] + S.dir[2] * gdir[2];
-      const float invn = 1.0f / S.dnorm;
-      float gcc[3];
-      for (int k = 0; k < 3; ++k) {
-        const float gv = (gdir[k] - S.dir[k] * dd) * invn;
-        gmu[k] += gv;
-        gcc[k] = -gv;
+    if (active) chain_one<DEG>(G, cams[v], sh, n, i, g2, c, pose);
+    if (!want_map) continue;
+    for (int k = 0; k < NC; ++k) c[k] = group_sum<LPG>(c[k]);
+    if (v != 0 || !valid) continue;
+    if (!G.ok) {
+      if (overwrite) {
+        for (int k = 0; k < 3; ++k) g_means[k * n + i] = g_log_scales[k * n + i] = 0.f;
+        for (int k = 0; k < 4; ++k) g_quats[k * n + i] = 0.f;
+        g_ologit[i] = 0.f;
+        for (int k = 0; k < 3 * K; ++k) g_sh[k * n + i] = 0.f;
       }
-      // camera centre c = -W^T t
-      for (int jj = 0; jj < 3; ++jj) {
-        for (int ii = 0; ii < 3; ++ii) {
-          GW[jj * 3 + ii] -= t[jj] * gcc[ii];
-          gt[jj] -= W[jj * 3 + ii] * gcc[ii];
-        }
-      }
-      // conic -> Sigma2 entries: dL/dSigma' = -Q Gq Q
-      const float h = 0.5f * g2[3];
-      const float X00 = S.q0 * (S.q0 * g2[2] + S.q1 * h) + S.q1 * (S.q0 * h + S.q1 * g2[4]);
-      const float X01 = S.q0 * (S.q1 * g2[2] + S.q2 * h) + S.q1 * (S.q1 * h + S.q2 * g2[4]);
-      const float X11 = S.q1 * (S.q1 * g2[2] + S.q2 * h) + S.q2 * (S.q1 * h + S.q2 * g2[4]);
-      const float ga = -X00, gb = -2.0f * X01, gc = -X11;
-      float gA0[3], gA1[3];
-      for (int c = 0; c < 3; ++c) {
-        gA0[c] = 2.0f * ga * S.A0[c] + gb * S.A1[c];
-        gA1[c] = gb * S.A0[c] + 2.0f * gc * S.A1[c];
-      }
-      float gJ00 = 0.f, gJ02 = 0.f, gJ11 = 0.f, gJ12 = 0.f, gB[9];
-      for (int c = 0; c < 3; ++c) {
-        gJ00 += gA0[c] * S.B[0 * 3 + c];
-        gJ02 += gA0[c] * S.B[2 * 3 + c];
-        gJ11 += gA1[c] * S.B[1 * 3 + c];
-        gJ12 += gA1[c] * S.B[2 * 3 + c];
-        gB[0 * 3 + c] = S.J00 * gA0[c];
-        gB[1 * 3 + c] = S.J11 * gA1[c];
-        gB[2 * 3 + c] = S.J02 * gA0[c] + S.J12 * gA1[c];
-      }
-      // camera-frame position
-      const float iz = S.inv_z, iz2 = iz * iz;
-      const float fx = cam.fx, fy = cam.fy;
-      gp[0] = g2[0] * fx * iz;
-      gp[1] = g2[1] * fy * iz;
-      gp[2] = -(g2[0] * fx * S.p[0] + g2[1] * fy * S.p[1]) * iz2;
-      gp[2] += -gJ00 * fx * iz2 - gJ11 * fy * iz2;
-      if (!S.clx) {
-        gp[0] += -gJ02 * fx * iz2;
-        gp[2] += gJ02 * 2.0f * fx * S.p[0] * iz2 * iz;
-      } else {
-        gp[2] += gJ02 * fx * S.tx * iz2;
-      }
-      if (!S.cly) {
-        gp[1] += -gJ12 * fy * iz2;
-        gp[2] += gJ12 * 2.0f * fy * S.p[1] * iz2 * iz;
-      } else {
-        gp[2] += gJ12 * fy * S.ty * iz2;
-      }
-      // p = W mu + t
-      for (int r = 0; r < 3; ++r) {
-        gt[r] += gp[r];
-        for (int k = 0; k < 3; ++k) {
-          gmu[k] += W[r * 3 + k] * gp[r];
-          GW[r * 3 + k] += gp[r] * G.mu[k];
-        }
-      }
-      // B = W M
-      for (int r = 0; r < 3; ++r)
-        for (int k = 0; k < 3; ++k) {
-          float gm = 0.f, gw = 0.f;
-          for (int q = 0; q < 3; ++q) {
-            gm += W[q * 3 + r] * gB[q * 3 + k];
-            gw += gB[r * 3 + q] * G.M[k * 3 + q];
-          }
-          // gm = dL/dM[r][k], gw = dL/dW[r][k]
-          gRq[r * 3 + k] += gm * G.s[k];
-          gsc[k] += gm * G.Rq[r * 3 + k];
-          GW[r * 3 + k] += gw;
-        }
-      if (want_pose) {
-        // dL/dphi = <dL/dW, [e]x W> + <dL/dt, [e]x t>, dL/drho = dL/dt
-        float Mm[9];
-        for (int r = 0; r < 3; ++r)
-          for (int c = 0; c < 3; ++c)
-            Mm[r * 3 + c] = GW[r * 3 + 0] * W[c * 3 + 0] + GW[r * 3 + 1] * W[c * 3 + 1] +
-                            GW[r * 3 + 2] * W[c * 3 + 2];
-        pose[0] = gt[0];
-        pose[1] = gt[1];
-        pose[2] = gt[2];
-        pose[3] = Mm[7] - Mm[5] + (t[1] * gt[2] - t[2] * gt[1]);
-        pose[4] = Mm[2] - Mm[6] + (t[2] * gt[0] - t[0] * gt[2]);
-        pose[5] = Mm[3] - Mm[1] + (t[0] * gt[1] - t[1] * gt[0]);
-      }
+      continue;
     }
-    if (want_pose) {
-      for (int k = 0; k < 6; ++k) {
-        const float sum = wave_sum_all(pose[k]);
-        if (lane == 0) s_pose[w][k] = (double)sum;
-      }
-      __syncthreads();
-      if (threadIdx.x < 6) {
-        const double tot = s_pose[0][threadIdx.x] + s_pose[1][threadIdx.x] +
-                           s_pose[2][threadIdx.x] + s_pose[3][threadIdx.x];
-        pose_part[((int64_t)blockIdx.x * n_views + v) * 6 + threadIdx.x] = tot;
-      }
-      __syncthreads();
+    auto put = [&](float* ptr, float val) { *ptr = overwrite ? val : *ptr + val; };
+    for (int k = 0; k < 3; ++k) {
+      put(&g_means[k * n + i], c[kCMu + k]);
+      put(&g_log_scales[k * n + i], G.s[k] * c[kCSc + k]);
     }
+    put(&g_ologit[i], c[kCOl]);
+    for (int k = 0; k < 3 * K; ++k) put(&g_sh[k * n + i], c[kCSh + k]);
+    // R(q) -> normalised quaternion -> raw quaternion
+    const float qw = G.q[0], qx = G.q[1], qy = G.q[2], qz = G.q[3];
+    const float* g = c + kCRq;
+    float dq[4];
+    dq[0] = 2.f * (-qz * g[1] + qy * g[2] + qz * g[3] - qx * g[5] - qy * g[6] + qx * g[7]);
+    dq[1] = 2.f * (qy * g[1] + qz * g[2] + qy * g[3] - 2.f * qx * g[4] - qw * g[5] + qz * g[6] +
+                   qw * g[7] - 2.f * qx * g[8]);
+    dq[2] = 2.f * (-2.f * qy * g[0] + qx * g[1] + qw * g[2] + qx * g[3] + qz * g[5] - qw * g[6] +
+                   qz * g[7] - 2.f * qy * g[8]);
+    dq[3] = 2.f * (-2.f * qz * g[0] - qw * g[1] + qx * g[2] + qw * g[3] - 2.f * qz * g[4] +
+                   qy * g[5] + qx * g[6] + qy * g[7]);
+    const float dot = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
+    const float inv = 1.0f / G.qnorm;
+    for (int k = 0; k < 4; ++k) put(&g_quats[k * n + i], (dq[k] - G.q[k] * dot) * inv);
   }
-  if (!valid || !want_map) return;
-  const bool overwrite = (flags & GS_BWD_OVERWRITE) != 0;
-  if (!G.ok) {
-    if (overwrite) {
-      for (int k = 0; k < 3; ++k) g_means[k * n + i] = g_log_scales[k * n + i] = 0.f;
-      for (int k = 0; k < 4; ++k) g_quats[k * n + i] = 0.f;
-      g_ologit[i] = 0.f;
-      for (int k = 0; k < 3 * K; ++k) g_sh[k * n + i] = 0.f;
-    }
-    return;
+  if (!want_pose) return;
+  for (int k = 0; k < 6; ++k) pose[k] = across_groups<LPG>(pose[k]);
+  if (lane < LPG && view_ok)
+    for (int k = 0; k < 6; ++k) s_pose[w][lane][k] = pose[k];
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_views * 6; t += 256) {
+    const int vv = t / 6, k = t % 6;
+    const double tot = (double)s_pose[0][vv][k] + (double)s_pose[1][vv][k] +
+                       (double)s_pose[2][vv][k] + (double)s_pose[3][vv][k];
+    pose_part[(int64_t)blockIdx.x * n_views * 6 + t] = tot;
   }
-  const float keep = overwrite ? 0.f : 1.f;   // 0 * old would keep a NaN; select instead
-  auto put = [&](float* ptr, float val) { *ptr = overwrite ? val : *ptr * keep + val; };
-  for (int k = 0; k < 3; ++k) {
-    put(&g_means[k * n + i], gmu[k]);
-    put(&g_log_scales[k * n + i], G.s[k] * gsc[k]);
-  }
-  put(&g_ologit[i], gol);
-  for (int k = 0; k < 3 * K; ++k) put(&g_sh[k * n + i], gf[k]);
-  // R(q) -> normalised quaternion -> raw quaternion
-  const float qw = G.q[0], qx = G.q[1], qy = G.q[2], qz = G.q[3];
-  const float* g = gRq;
-  float dq[4];
-  dq[0] = 2.f * (-qz * g[1] + qy * g[2] + qz * g[3] - qx * g[5] - qy * g[6] + qx * g[7]);
-  dq[1] = 2.f * (qy * g[1] + qz * g[2] + qy * g[3] - 2.f * qx * g[4] - qw * g[5] + qz * g[6] +
-                 qw * g[7] - 2.f * qx * g[8]);
-  dq[2] = 2.f * (-2.f * qy * g[0] + qx * g[1] + qw * g[2] + qx * g[3] + qz * g[5] - qw * g[6] +
-                 qz * g[7] - 2.f * qy * g[8]);
-  dq[3] = 2.f * (-2.f * qz * g[0] - qw * g[1] + qx * g[2] + qw * g[3] - 2.f * qz * g[4] +
-                 qy * g[5] + qx * g[6] + qy * g[7]);
-  const float dot = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
-  const float inv = 1.0f / G.qnorm;
-  for (int k = 0; k < 4; ++k) put(&g_quats[k * n + i], (dq[k] - G.q[k] * dot) * inv);
 }
 
 // One workgroup per (view, component): strided float64 sum over the
@@ -450,11 +501,22 @@ __global__ __launch_bounds__(256) void pose_reduce_kernel(const double* __restri
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+int lanes_per_gaussian(int n_views) {
+  int l = 1;
+  while (l < n_views) l <<= 1;
+  return l;
+}
+
+int64_t proj_bwd_blocks(int64_t n, int n_views) {
+  const int64_t per_block = 4 * (64 / lanes_per_gaussian(n_views));
+  return std::max<int64_t>(1, std::min<int64_t>(kProjBwdMaxBlocks, (n + per_block - 1) / per_block));
+}
+
 }  // namespace
 
 BwdPlan make_bwd_plan(int64_t n, const ViewTable& vt) {
   BwdPlan P{};
-  const int64_t nblocks = (n + 255) / 256;
+  const int64_t nblocks = proj_bwd_blocks(n, vt.n_views);
   size_t off = 0;
   P.off_grad2d = off;
   off += align_up(sizeof(float) * 9 * (size_t)n * vt.n_views);
@@ -463,6 +525,41 @@ BwdPlan make_bwd_plan(int64_t n, const ViewTable& vt) {
   P.total = off;
   return P;
 }
+
+namespace {
+
+template <int DEG>
+void launch_project_bwd_deg(const gs_gaussians& g, const gs_camera* cams, int V,
+                            const float* grad2d, const gs_grads& gr, double* pose_part,
+                            uint32_t flags, dim3 grid, dim3 block, hipStream_t s) {
+#define GS_PB(L)                                                                                 \
+  hipLaunchKernelGGL((project_bwd_kernel<DEG, L>), grid, block, 0, s, g.means, g.log_scales,    \
+                     g.quats, g.opacity_logits, g.sh, g.n, cams, V, grad2d, gr.means,           \
+                     gr.log_scales, gr.quats, gr.opacity_logits, gr.sh, pose_part, flags)
+  switch (lanes_per_gaussian(V)) {
+    case 1: GS_PB(1); break;
+    case 2: GS_PB(2); break;
+    case 4: GS_PB(4); break;
+    case 8: GS_PB(8); break;
+    case 16: GS_PB(16); break;
+    case 32: GS_PB(32); break;
+    default: GS_PB(64); break;
+  }
+#undef GS_PB
+}
+
+void launch_project_bwd(const gs_gaussians& g, const gs_camera* cams, int V, const float* grad2d,
+                        const gs_grads& gr, double* pose_part, uint32_t flags, dim3 grid,
+                        dim3 block, hipStream_t s) {
+  switch (g.sh_degree) {
+    case 0: launch_project_bwd_deg<0>(g, cams, V, grad2d, gr, pose_part, flags, grid, block, s); break;
+    case 1: launch_project_bwd_deg<1>(g, cams, V, grad2d, gr, pose_part, flags, grid, block, s); break;
+    case 2: launch_project_bwd_deg<2>(g, cams, V, grad2d, gr, pose_part, flags, grid, block, s); break;
+    default: launch_project_bwd_deg<3>(g, cams, V, grad2d, gr, pose_part, flags, grid, block, s); break;
+  }
+}
+
+}  // namespace
 
 hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const gs_bins& bins,
                              const gs_camera* cams_dev, const ViewTable& vt, float3 bg,
@@ -483,31 +580,24 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
     kernel_event_start(GS_KERNEL_RENDER_BWD, s);
     if (ppl == 4)
       hipLaunchKernelGGL(render_bwd_kernel<4>, grid, dim3(kBlock / 4), 0, s, vt, bins.ranges,
-                         bins.values, xy, co, rd, bg, dL_dimage, final_T, n_contrib, grad2d);
+                         bins.values, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
+                         (uint32_t)g.n, grad2d);
     else if (ppl == 2)
       hipLaunchKernelGGL(render_bwd_kernel<2>, grid, dim3(kBlock / 2), 0, s, vt, bins.ranges,
-                         bins.values, xy, co, rd, bg, dL_dimage, final_T, n_contrib, grad2d);
+                         bins.values, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
+                         (uint32_t)g.n, grad2d);
     else
       hipLaunchKernelGGL(render_bwd_kernel<1>, grid, dim3(kBlock), 0, s, vt, bins.ranges,
-                         bins.values, xy, co, rd, bg, dL_dimage, final_T, n_contrib, grad2d);
+                         bins.values, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
+                         (uint32_t)g.n, grad2d);
     kernel_event_stop(GS_KERNEL_RENDER_BWD, s);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (g.n == 0) return hipSuccess;
-  const int64_t nblocks = (g.n + 255) / 256;
+  const int64_t nblocks = proj_bwd_blocks(g.n, vt.n_views);
   const dim3 grid((unsigned)nblocks), block(256);
-#define GS_BWD_ARGS                                                                              \
-  g.means, g.log_scales, g.quats, g.opacity_logits, g.sh, g.n, cams_dev, vt.n_views, p.radius,  \
-      grad2d, grads.means, grads.log_scales, grads.quats, grads.opacity_logits, grads.sh,        \
-      pose_part, flags
   kernel_event_start(GS_KERNEL_PROJECT_BWD, s);
-  switch (g.sh_degree) {
-    case 0: hipLaunchKernelGGL(project_bwd_kernel<0>, grid, block, 0, s, GS_BWD_ARGS); break;
-    case 1: hipLaunchKernelGGL(project_bwd_kernel<1>, grid, block, 0, s, GS_BWD_ARGS); break;
-    case 2: hipLaunchKernelGGL(project_bwd_kernel<2>, grid, block, 0, s, GS_BWD_ARGS); break;
-    default: hipLaunchKernelGGL(project_bwd_kernel<3>, grid, block, 0, s, GS_BWD_ARGS); break;
-  }
-#undef GS_BWD_ARGS
+  launch_project_bwd(g, cams_dev, vt.n_views, grad2d, grads, pose_part, flags, grid, block, s);
   kernel_event_stop(GS_KERNEL_PROJECT_BWD, s);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (!(flags & GS_BWD_NO_POSE)) {

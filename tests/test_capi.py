@@ -167,3 +167,15 @@ def test_adam_argument_errors(gs):
     assert lib.gs_adam_step(FAKE, FAKE, FAKE, FAKE, -1, 1e-3, 0.9, 0.999, 1e-8, 1, None, None) == 1
     # n == 0 is a no-op that needs no device
     assert lib.gs_adam_step(None, None, None, None, 0, 1e-3, 0.9, 0.999, 1e-8, 1, None, None) == 0
+
+
+def test_se3_exp_closed_form_matches_matrix_exponential():
+    """Host-side pose update (closed form) vs the matrix exponential."""
+    import torch
+    from oracle import gs_oracle as O
+    from paper_2409_09295_amd.autograd import se3_exp
+    rng = np.random.default_rng(0)
+    for scale in (1e-12, 1e-3, 0.5, 2.0):
+        xi = rng.normal(size=6) * scale
+        ref = O.se3_exp(torch.as_tensor(xi)).numpy()
+        np.testing.assert_allclose(se3_exp(xi), ref, atol=1e-12)
