@@ -1,0 +1,174 @@
+"""FP64 CPU oracle for the learned and plain Gaussian initialisers.
+
+TEST INFRASTRUCTURE ONLY (tests, smoke check, benchmark CPU baseline).  It
+shares no code with the HIP library.  Tensors are float64 torch CPU tensors
+in NHWC layout ([n, h, w, c]) unless stated.
+
+Plain initialiser: the photometric cost volume of Eq. 1 (Sec. III-A1) over a
+keyframe window, 64 hypotheses spaced evenly over 0.25-25 m, on 1/4
+resolution intensity images, reduced per pixel by winner-take-all.
+
+Network pieces: 3x3 convolution with zero padding (written as an explicit
+sum over the nine taps), 2x2 average pooling, nearest 2x upsampling, ReLU,
+a 1x1 head and the depth loss; gradients by reverse-mode differentiation.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+DT = torch.float64
+N_HYP = 64
+D_MIN, D_MAX = 0.25, 25.0
+
+
+# ---------------------------------------------------------------------------
+# network pieces
+# ---------------------------------------------------------------------------
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round float32 values to bfloat16 (nearest even), returned as float64."""
+    u = np.asarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (r.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def conv3x3(x: torch.Tensor, w: torch.Tensor, bias: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x [n, h, w, cin], w [9, cout, cin] (tap = 3 dy + dx) -> [n, h, w, cout]:
+    y[p] = bias + sum over taps of w[tap] @ x[p + (dy - 1, dx - 1)], zero outside."""
+    n, h, wd, cin = x.shape
+    xp = torch.nn.functional.pad(x, (0, 0, 1, 1, 1, 1))          # pad w then h
+    y = torch.zeros((n, h, wd, w.shape[1]), dtype=x.dtype)
+    for tap in range(9):
+        dy, dx = tap // 3, tap % 3
+        y = y + xp[:, dy:dy + h, dx:dx + wd, :] @ w[tap].T
+    if bias is not None:
+        y = y + bias
+    return y
+
+
+def avgpool2(x: torch.Tensor) -> torch.Tensor:
+    n, h, w, c = x.shape
+    return x.reshape(n, h // 2, 2, w // 2, 2, c).mean(dim=(2, 4))
+
+
+def upsample2(x: torch.Tensor) -> torch.Tensor:
+    return x.repeat_interleave(2, dim=1).repeat_interleave(2, dim=2)
+
+
+def head(f: torch.Tensor, w: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    """f [n, h, w, c], w [2, c] -> [n, 2, h, w]."""
+    return (f @ w.T + b).permute(0, 3, 1, 2)
+
+
+def depth_loss(pred: torch.Tensor, depth: torch.Tensor, fx: float) -> torch.Tensor:
+    """mean over pixels with depth > 0 of |pred0 - log d| + |pred1 - log(d/fx)|."""
+    valid = depth > 0
+    d = torch.where(valid, depth, torch.ones_like(depth))
+    e = (pred[:, 0] - torch.log(d)).abs() + (pred[:, 1] - torch.log(d / fx)).abs()
+    return (e * valid).sum() / max(int(valid.sum()), 1)
+
+
+CHANNELS = (32, 64, 128, 256)
+
+
+def unet_layers(in_ch: int = 8, ch=CHANNELS):
+    """(name, cin, cout) of the 14 convolutions of the 4-level U-Net."""
+    c0, c1, c2, c3 = ch
+    return [("e0a", in_ch, c0), ("e0b", c0, c0), ("e1a", c0, c1), ("e1b", c1, c1),
+            ("e2a", c1, c2), ("e2b", c2, c2), ("e3a", c2, c3), ("e3b", c3, c3),
+            ("d2a", c3 + c2, c2), ("d2b", c2, c2), ("d1a", c2 + c1, c1), ("d1b", c1, c1),
+            ("d0a", c1 + c0, c0), ("d0b", c0, c0)]
+
+
+def unet_forward(x: torch.Tensor, p: Dict[str, torch.Tensor]) -> torch.Tensor:
+    """x [n, h, w, in_ch]; p maps '<layer>.w' [9, cout, cin], '<layer>.b' [cout],
+    'head.w' [2, c0], 'head.b' [2].  Encoder: two conv+ReLU per level, 2x2
+    average pooling between levels; decoder: nearest upsampling, concatenation
+    [upsampled, skip], two conv+ReLU; 1x1 head."""
+    r = torch.relu
+    c = lambda name, t: r(conv3x3(t, p[name + ".w"], p[name + ".b"]))
+    e0 = c("e0b", c("e0a", x))
+    e1 = c("e1b", c("e1a", avgpool2(e0)))
+    e2 = c("e2b", c("e2a", avgpool2(e1)))
+    e3 = c("e3b", c("e3a", avgpool2(e2)))
+    d2 = c("d2b", c("d2a", torch.cat([upsample2(e3), e2], dim=3)))
+    d1 = c("d1b", c("d1a", torch.cat([upsample2(d2), e1], dim=3)))
+    d0 = c("d0b", c("d0a", torch.cat([upsample2(d1), e0], dim=3)))
+    return head(d0, p["head.w"], p["head.b"])
+
+
+# ---------------------------------------------------------------------------
+# plain initialiser
+# ---------------------------------------------------------------------------
+
+def hypotheses() -> np.ndarray:
+    return D_MIN + (D_MAX - D_MIN) * np.arange(N_HYP) / (N_HYP - 1)
+
+
+def luma_down4(rgb: np.ndarray) -> np.ndarray:
+    """rgb [3, H, W] -> intensity 0.299 R + 0.587 G + 0.114 B averaged over 4x4 blocks."""
+    rgb = np.asarray(rgb, np.float64)
+    I = 0.299 * rgb[0] + 0.587 * rgb[1] + 0.114 * rgb[2]
+    H, W = I.shape
+    return I.reshape(H // 4, 4, W // 4, 4).mean(axis=(1, 3))
+
+
+def _bilinear(img: np.ndarray, x: np.ndarray, y: np.ndarray):
+    Hl, Wl = img.shape
+    ok = (x >= 0) & (y >= 0) & (x <= Wl - 1) & (y <= Hl - 1)
+    xs = np.where(ok, x, 0.0)
+    ys = np.where(ok, y, 0.0)
+    x0 = np.floor(xs).astype(np.int64)
+    y0 = np.floor(ys).astype(np.int64)
+    x1 = np.minimum(x0 + 1, Wl - 1)
+    y1 = np.minimum(y0 + 1, Hl - 1)
+    fx = xs - x0
+    fy = ys - y0
+    v = ((1 - fy) * ((1 - fx) * img[y0, x0] + fx * img[y0, x1])
+         + fy * ((1 - fx) * img[y1, x0] + fx * img[y1, x1]))
+    return v, ok
+
+
+def cost_volume(keyframes: List[np.ndarray], cams) -> np.ndarray:
+    """Eq. 1: V(u, d) = mean over source views i of |I_ref(u) - I_i(pi(u, d, T))|
+    for the last keyframe as reference, at 1/4 resolution; views whose sample
+    falls outside the image or behind the camera are left out of the mean
+    (+inf when none remains).  Returns [64, H/4, W/4]."""
+    low = [luma_down4(k) for k in keyframes]
+    ref = cams[-1]
+    Hl, Wl = low[-1].shape
+    jj, ii = np.meshgrid(np.arange(Hl), np.arange(Wl), indexing="ij")
+    u = 4.0 * ii + 2.0
+    v = 4.0 * jj + 2.0
+    rx = (u - ref.cx) / ref.fx
+    ry = (v - ref.cy) / ref.fy
+    Rr, tr = np.asarray(ref.R, np.float64), np.asarray(ref.t, np.float64)
+    out = np.empty((N_HYP, Hl, Wl))
+    for h, d in enumerate(hypotheses()):
+        Xc = np.stack([rx * d, ry * d, np.full_like(rx, d)], -1)      # camera frame of the reference
+        Xw = (Xc - tr) @ Rr                                            # R^T (Xc - t)
+        acc = np.zeros((Hl, Wl))
+        cnt = np.zeros((Hl, Wl))
+        for k, cam in enumerate(cams[:-1]):
+            P = Xw @ np.asarray(cam.R, np.float64).T + np.asarray(cam.t, np.float64)
+            front = P[..., 2] > 1e-6
+            z = np.where(front, P[..., 2], 1.0)
+            us = cam.fx * P[..., 0] / z + cam.cx
+            vs = cam.fy * P[..., 1] / z + cam.cy
+            val, ok = _bilinear(low[k], (us - 2.0) / 4.0, (vs - 2.0) / 4.0)
+            ok &= front
+            acc += np.where(ok, np.abs(low[-1] - val), 0.0)
+            cnt += ok
+        out[h] = np.where(cnt > 0, acc / np.maximum(cnt, 1), np.inf)
+    return out
+
+
+def wta_depth(cost: np.ndarray) -> np.ndarray:
+    """First hypothesis of minimum cost; 0 where every cost is +inf."""
+    idx = np.argmin(cost, axis=0)
+    d = hypotheses()[idx]
+    return np.where(np.isfinite(cost.min(axis=0)), d, 0.0)

@@ -311,3 +311,201 @@ int gs_l1_loss_grad(const float* image, const float* target, const gs_views* vie
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned and plain initialiser
+// ---------------------------------------------------------------------------
+
+namespace gsmi {
+namespace {
+
+int check_act(const gs_act* a, const char* name, bool conv_input) {
+  if (!a) return invalid("%s is NULL", name);
+  if (!a->data) return invalid("%s->data is NULL", name);
+  if (a->n < 1 || a->h < 1 || a->w < 1 || a->c < 1)
+    return invalid("%s: shape (%d, %d, %d, %d) must be positive", name, a->n, a->h, a->w, a->c);
+  if (a->offset < 0 || a->stride < a->offset + a->c)
+    return invalid("%s: stride %d too small for offset %d + %d channels", name, a->stride,
+                   a->offset, a->c);
+  if ((int64_t)a->n * a->h * a->w > 0x7FFFFFFFLL) return invalid("%s: too many pixels", name);
+  if (conv_input) {
+    if ((a->c % 8) || (a->stride % 8) || (a->offset % 8))
+      return invalid("%s: channels, stride and offset must be multiples of 8", name);
+    if (reinterpret_cast<uintptr_t>(a->data) & 15) return invalid("%s: data not 16-byte aligned", name);
+  }
+  return GS_OK;
+}
+
+bool same_grid(const gs_act* a, const gs_act* b) {
+  return a->n == b->n && a->h == b->h && a->w == b->w;
+}
+
+int nn_status(hipError_t e, const char* what) { return e == hipSuccess ? GS_OK : hip_fail(e, what); }
+
+}  // namespace
+}  // namespace gsmi
+
+extern "C" {
+
+int gs_nn_conv3x3(const gs_act* x1, const gs_act* x2, const gs_act* mask, const void* weights,
+                  int32_t cout, const float* bias, int32_t relu, gs_act* y, float* y_f32,
+                  int32_t y_f32_stride, gs_stream_t stream) {
+  int st;
+  if ((st = check_act(x1, "x1", true))) return st;
+  if (x2 && (st = check_act(x2, "x2", true))) return st;
+  if (x2 && !same_grid(x1, x2)) return invalid("x1 and x2 differ in n, h or w");
+  const int cin = x1->c + (x2 ? x2->c : 0);
+  if (mask) {
+    if ((st = check_act(mask, "mask", true))) return st;
+    if (!same_grid(x1, mask) || mask->c != cin) return invalid("mask must match the input layout");
+  }
+  if (!weights) return invalid("weights is NULL");
+  if (reinterpret_cast<uintptr_t>(weights) & 15) return invalid("weights not 16-byte aligned");
+  if (cout < 1) return invalid("cout = %d < 1", cout);
+  if (!y && !y_f32) return invalid("no output");
+  if (y) {
+    if ((st = check_act(y, "y", false))) return st;
+    if (!same_grid(x1, y) || y->c != cout) return invalid("y must be (n, h, w, cout) like x1");
+  }
+  if (y_f32 && y_f32_stride < cout) return invalid("y_f32_stride < cout");
+  return nn_status(nn_conv3x3(x1, x2, mask, weights, cout, bias, relu, y, y_f32, y_f32_stride,
+                              stream), "gs_nn_conv3x3");
+}
+
+int gs_nn_conv3x3_wgrad(const gs_act* x1, const gs_act* x2, const gs_act* dy, const gs_act* mask,
+                        float* dw, float* dbias, gs_stream_t stream) {
+  int st;
+  if ((st = check_act(x1, "x1", false))) return st;
+  if (x2 && (st = check_act(x2, "x2", false))) return st;
+  if ((st = check_act(dy, "dy", false))) return st;
+  if (x2 && !same_grid(x1, x2)) return invalid("x1 and x2 differ in n, h or w");
+  if (!same_grid(x1, dy)) return invalid("dy must share x1's n, h, w");
+  if (mask) {
+    if ((st = check_act(mask, "mask", false))) return st;
+    if (!same_grid(x1, mask) || mask->c != dy->c) return invalid("mask must match dy's layout");
+  }
+  if (!dw) return invalid("dw is NULL");
+  return nn_status(nn_conv3x3_wgrad(x1, x2, dy, mask, dw, dbias, stream), "gs_nn_conv3x3_wgrad");
+}
+
+int gs_nn_flip_weights(const void* weights, int32_t cout, int32_t cin, void* weights_t,
+                       gs_stream_t stream) {
+  if (!weights || !weights_t) return invalid("a weight pointer is NULL");
+  if (cout < 1 || cin < 1) return invalid("cout and cin must be positive");
+  return nn_status(nn_flip_weights(weights, cout, cin, weights_t, stream), "gs_nn_flip_weights");
+}
+
+int gs_nn_avgpool2(const gs_act* x, gs_act* y, gs_stream_t stream) {
+  int st;
+  if ((st = check_act(x, "x", false))) return st;
+  if ((st = check_act(y, "y", false))) return st;
+  if ((x->h % 2) || (x->w % 2)) return invalid("pooling needs even h and w");
+  if (y->n != x->n || y->h != x->h / 2 || y->w != x->w / 2 || y->c != x->c || y->offset != 0)
+    return invalid("y must be (n, h/2, w/2, c) with offset 0");
+  return nn_status(nn_avgpool2(x, y, stream), "gs_nn_avgpool2");
+}
+
+int gs_nn_avgpool2_bwd(const gs_act* dy, const gs_act* add, gs_act* dx, int32_t accumulate,
+                       gs_stream_t stream) {
+  int st;
+  if ((st = check_act(dy, "dy", false))) return st;
+  if ((st = check_act(dx, "dx", false))) return st;
+  if (dx->h % 2 || dx->w % 2 || dy->n != dx->n || dy->h != dx->h / 2 || dy->w != dx->w / 2 ||
+      dy->c != dx->c)
+    return invalid("dx must be (n, 2h, 2w, c) of dy");
+  if (add) {
+    if ((st = check_act(add, "add", false))) return st;
+    if (!same_grid(add, dx) || add->c != dx->c) return invalid("add must match dx");
+  }
+  return nn_status(nn_avgpool2_bwd(dy, add, dx, accumulate, stream), "gs_nn_avgpool2_bwd");
+}
+
+int gs_nn_upsample2(const gs_act* x, gs_act* y, gs_stream_t stream) {
+  int st;
+  if ((st = check_act(x, "x", false))) return st;
+  if ((st = check_act(y, "y", false))) return st;
+  if (y->n != x->n || y->h != 2 * x->h || y->w != 2 * x->w || y->c != x->c)
+    return invalid("y must be (n, 2h, 2w, c)");
+  return nn_status(nn_upsample2(x, y, stream), "gs_nn_upsample2");
+}
+
+int gs_nn_upsample2_bwd(const gs_act* dy, gs_act* dx, gs_stream_t stream) {
+  int st;
+  if ((st = check_act(dy, "dy", false))) return st;
+  if ((st = check_act(dx, "dx", false))) return st;
+  if (dy->n != dx->n || dy->h != 2 * dx->h || dy->w != 2 * dx->w || dy->c != dx->c ||
+      dx->offset != 0)
+    return invalid("dx must be (n, h/2, w/2, c) with offset 0");
+  return nn_status(nn_upsample2_bwd(dy, dx, stream), "gs_nn_upsample2_bwd");
+}
+
+int gs_nn_rgb_to_nhwc(const float* rgb, gs_act* x, gs_stream_t stream) {
+  int st;
+  if (!rgb) return invalid("rgb is NULL");
+  if ((st = check_act(x, "x", false))) return st;
+  if (x->offset != 0 || x->stride < 3) return invalid("x must have offset 0 and stride >= 3");
+  return nn_status(nn_rgb_to_nhwc(rgb, x, stream), "gs_nn_rgb_to_nhwc");
+}
+
+int gs_nn_f32_to_bf16(const float* src, void* dst, int64_t n, gs_stream_t stream) {
+  if (n < 0) return invalid("n < 0");
+  if (n > 0 && (!src || !dst)) return invalid("a pointer is NULL");
+  return nn_status(nn_f32_to_bf16(src, dst, n, stream), "gs_nn_f32_to_bf16");
+}
+
+int gs_nn_head(const gs_act* f, const float* w, const float* b, float* out, gs_stream_t stream) {
+  int st;
+  if ((st = check_act(f, "f", false))) return st;
+  if (!w || !b || !out) return invalid("a head pointer is NULL");
+  return nn_status(nn_head(f, w, b, out, stream), "gs_nn_head");
+}
+
+int gs_nn_head_bwd(const gs_act* f, const float* w, const float* dout, gs_act* df, float* dw,
+                   float* db, gs_stream_t stream) {
+  int st;
+  if ((st = check_act(f, "f", false))) return st;
+  if ((st = check_act(df, "df", false))) return st;
+  if (!same_grid(f, df) || df->c != f->c) return invalid("df must match f");
+  if (f->c > 64) return invalid("head supports at most 64 feature channels");
+  if (!w || !dout || !dw || !db) return invalid("a head pointer is NULL");
+  return nn_status(nn_head_bwd(f, w, dout, df, dw, db, stream), "gs_nn_head_bwd");
+}
+
+int gs_nn_depth_loss(const float* pred, const float* depth, int32_t n, int32_t h, int32_t w,
+                     float fx, float* dpred, double* loss, void* ws, gs_stream_t stream) {
+  if (!pred || !depth || !dpred || !ws) return invalid("a loss pointer is NULL");
+  if (n < 1 || h < 1 || w < 1) return invalid("shape must be positive");
+  if (!(fx > 0.f)) return invalid("fx must be > 0");
+  return nn_status(nn_depth_loss(pred, depth, n, h, w, fx, dpred, loss, static_cast<int*>(ws),
+                                 stream), "gs_nn_depth_loss");
+}
+
+size_t gs_cost_volume_workspace_size(int32_t k, int32_t h, int32_t w) {
+  if (k < 2 || h < 4 || w < 4) return 0;
+  return cost_volume_ws_bytes(k, h, w);
+}
+
+int gs_cost_volume_wta(const float* keyframes, const gs_views* cams, float* cost, float* depth,
+                       void* ws, size_t ws_bytes, gs_stream_t stream) {
+  if (!keyframes || !depth) return invalid("keyframes or depth is NULL");
+  if (!cams || !cams->cams_host || !cams->cams_dev) return invalid("cameras are NULL");
+  const int K = cams->n_views;
+  if (K < 2 || K > GS_MAX_VIEWS) return invalid("need 2..%d keyframes", GS_MAX_VIEWS);
+  const int W = cams->cams_host[0].width, H = cams->cams_host[0].height;
+  for (int k = 0; k < K; ++k) {
+    const gs_camera& c = cams->cams_host[k];
+    if (c.width != W || c.height != H) return invalid("keyframes must share one image size");
+    if (!(c.fx > 0.f && c.fy > 0.f)) return invalid("fx, fy must be > 0");
+  }
+  if (W % 4 || H % 4 || W < 4 || H < 4) return invalid("image size must be a multiple of 4");
+  const size_t need = cost_volume_ws_bytes(K, H, W);
+  if (ws_bytes < need) {
+    set_error("workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    return GS_ERR_CAPACITY;
+  }
+  if (!ws) return invalid("workspace is NULL");
+  return nn_status(launch_cost_volume(keyframes, K, H, W, cams->cams_dev, cost, depth, ws, stream),
+                   "gs_cost_volume_wta");
+}
+
+}  // extern "C"

@@ -8,6 +8,7 @@
 #include <utility>
 
 #include "gs.h"
+#include "gs_nn.h"
 
 namespace gsmi {
 
@@ -167,5 +168,30 @@ hipError_t launch_adam_dev(float* p, const float* g, float* m, float* v, int64_t
 
 hipError_t launch_l1_loss_grad(const float* image, const float* target, const ViewTable& vt,
                                float* dL_dimage, double* loss, hipStream_t s);
+
+// ---- learned / plain initialiser (nn.hip, costvol.hip) --------------------
+
+hipError_t nn_conv3x3(const gs_act* x1, const gs_act* x2, const gs_act* mask, const void* w,
+                      int cout, const float* bias, int relu, gs_act* y, float* yf, int yf_stride,
+                      hipStream_t s);
+hipError_t nn_conv3x3_wgrad(const gs_act* x1, const gs_act* x2, const gs_act* dz,
+                            const gs_act* mask, float* dw, float* dbias, hipStream_t s);
+hipError_t nn_flip_weights(const void* w, int cout, int cin, void* wt, hipStream_t s);
+hipError_t nn_avgpool2(const gs_act* x, gs_act* y, hipStream_t s);
+hipError_t nn_avgpool2_bwd(const gs_act* dy, const gs_act* add, gs_act* dx, int accumulate,
+                           hipStream_t s);
+hipError_t nn_upsample2(const gs_act* x, gs_act* y, hipStream_t s);
+hipError_t nn_upsample2_bwd(const gs_act* dy, gs_act* dx, hipStream_t s);
+hipError_t nn_rgb_to_nhwc(const float* rgb, gs_act* x, hipStream_t s);
+hipError_t nn_f32_to_bf16(const float* src, void* dst, int64_t n, hipStream_t s);
+hipError_t nn_head(const gs_act* f, const float* w, const float* b, float* out, hipStream_t s);
+hipError_t nn_head_bwd(const gs_act* f, const float* w, const float* dout, gs_act* df, float* dw,
+                       float* db, hipStream_t s);
+hipError_t nn_depth_loss(const float* pred, const float* depth, int N, int H, int W, float fx,
+                         float* dpred, double* loss, int* count_ws, hipStream_t s);
+size_t cost_volume_ws_bytes(int K, int H, int W);
+hipError_t launch_cost_volume(const float* keyframes, int K, int H, int W,
+                              const gs_camera* cams_dev, float* cost, float* depth, void* ws,
+                              hipStream_t s);
 
 }  // namespace gsmi

@@ -1,0 +1,567 @@
+// Kernels of the learned Gaussian initialiser: a small U-Net over BF16 NHWC
+// activations with FP32 accumulation on MFMA (v_mfma_f32_16x16x32_bf16).
+//
+// conv3x3 (forward and, with flipped/transposed weights, backward-data) is an
+// implicit GEMM: M = pixels, N = output channels, K = 9 taps x input
+// channels.  A 256-thread workgroup owns a 64-pixel x 64-channel tile; each
+// wavefront computes a 32 x 32 quarter as 2 x 2 MFMA tiles.  Per K step
+// (one tap, 32 input channels) the workgroup stages the 64 x 32 activation
+// slice (zero outside the image; channels may come from two tensors, which
+// is how the decoder's skip concatenation is read without materialising it)
+// and the 64 x 32 weight slice in LDS, both K-contiguous so that every MFMA
+// operand fragment is one 16-byte LDS read.  An optional mask tensor zeroes
+// input entries whose mask value is <= 0 (the ReLU backward fused into the
+// backward-data pass).
+//
+// conv3x3_wgrad: dW[tap][co][ci] = sum_p dz[p][co] x[p + tap][ci] as a GEMM
+// with M = Cout, N = Cin, K = pixels, split over pixel chunks with float32
+// atomics; tiles are transposed through LDS so fragments stay contiguous.
+//
+// MFMA 16x16x32 operand layout (lane l, 8 values each): A row l % 16, B
+// column l % 16, both covering k = 8 (l / 16) .. 8 (l / 16) + 7; result D row
+// 4 (l / 16) + j, column l % 16, j = 0..3.
+#include "gs_internal.h"
+#include "gs_nn.h"
+
+namespace gsmi {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// round-to-nearest-even float -> bf16 (inputs are finite)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(r >> 16);
+}
+
+constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int LDK = BK + 8;   // LDS row pitch in bf16 (16-byte aligned, skews banks)
+
+struct ActView {
+  const uint16_t* p;
+  int32_t c, stride, offset;
+};
+
+// Loads 8 consecutive channels [c0, c0 + 8) of pixel (n, y, x) from a
+// two-source channel concatenation; zero outside the image or beyond the
+// channel count.  mask (optional, same layout as the concatenation) zeroes
+// elements whose mask is <= 0.
+__device__ __forceinline__ uint4 load8(const ActView& a, const ActView& b, const ActView& m,
+                                       int64_t pix, bool inb, int c0) {
+  uint4 v = make_uint4(0, 0, 0, 0);
+  if (!inb) return v;
+  const ActView* s = &a;
+  int c = c0;
+  if (c0 >= a.c) {
+    s = &b;
+    c = c0 - a.c;
+  }
+  if (s->p == nullptr || c >= s->c) return v;
+  v = *reinterpret_cast<const uint4*>(s->p + pix * s->stride + s->offset + c);
+  if (m.p) {
+    const uint4 mk = *reinterpret_cast<const uint4*>(m.p + pix * m.stride + m.offset + c0);
+    const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+    uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t lo = (int16_t)(mw[q] & 0xFFFF) > 0 ? 0xFFFFu : 0u;   // bf16 > 0 <=> int16 > 0
+      const uint32_t hi = (int16_t)(mw[q] >> 16) > 0 ? 0xFFFF0000u : 0u;
+      vw[q] &= (lo | hi);
+    }
+    v = make_uint4(vw[0], vw[1], vw[2], vw[3]);
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(256) void conv3x3_kernel(
+    ActView x1, ActView x2, ActView mask, int N, int H, int W, const uint16_t* __restrict__ wk,
+    int cout, int cin, const float* __restrict__ bias, int relu, uint16_t* __restrict__ y,
+    int y_stride, int y_offset, float* __restrict__ yf, int yf_stride) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[BM * LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[BN * LDK];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t npix = (int64_t)N * H * W;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+  // loader coordinates: thread t stages row t / 4, channels 8 (t % 4) .. +8
+  const int lrow = t >> 2, lcol = (t & 3) * 8;
+  const int64_t lp = m0 + lrow;
+  int ly = 0, lx = 0, limg = 0;
+  if (lp < npix) {
+    limg = (int)(lp / ((int64_t)H * W));
+    const int rem = (int)(lp - (int64_t)limg * H * W);
+    ly = rem / W;
+    lx = rem - ly * W;
+  }
+  const int cin_pad = (cin + BK - 1) / BK * BK;
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
+  for (int tap = 0; tap < 9; ++tap) {
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int sy = ly + dy, sx = lx + dx;
+    const bool inb = lp < npix && sy >= 0 && sy < H && sx >= 0 && sx < W;
+    const int64_t spix = ((int64_t)limg * H + sy) * W + sx;
+    for (int c0 = 0; c0 < cin_pad; c0 += BK) {
+      __syncthreads();
+      *reinterpret_cast<uint4*>(&sA[lrow * LDK + lcol]) = load8(x1, x2, mask, spix, inb, c0 + lcol);
+      {
+        const int co = n0 + lrow, ci = c0 + lcol;
+        uint4 wv4 = make_uint4(0, 0, 0, 0);
+        if (co < cout && ci < cin)
+          wv4 = *reinterpret_cast<const uint4*>(wk + ((int64_t)tap * cout + co) * cin + ci);
+        *reinterpret_cast<uint4*>(&sB[lrow * LDK + lcol]) = wv4;
+      }
+      __syncthreads();
+      bf16x8 a[2], b[2];
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const bf16x8*>(&sA[(wm + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const bf16x8*>(&sB[(wn + j * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  // epilogue: bias, ReLU, bf16 (or float32) store
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const int co = n0 + wn + j * 16 + (lane & 15);
+      if (co >= cout) continue;
+      const float bco = bias ? bias[co] : 0.f;
+      for (int r = 0; r < 4; ++r) {
+        const int64_t p = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        if (p >= npix) continue;
+        float v = acc[i][j][r] + bco;
+        if (relu) v = fmaxf(v, 0.f);
+        if (y) y[p * y_stride + y_offset + co] = f2bf(v);
+        if (yf) yf[p * yf_stride + co] = v;
+      }
+    }
+}
+
+// Weight-gradient tile: 64 output channels x 64 input channels for one tap,
+// pixels [kbeg, kbeg + WG_KCHUNK) of the K dimension.  Each K step stages 32
+// pixels: thread t reads pixel t / 8 and channels 8 (t % 8) .. +8 of both
+// dz (output-channel tile) and the tap-shifted input (input-channel tile),
+// and writes them transposed ([channel][pixel]) into LDS.
+constexpr int WG_KCHUNK = 2048;
+
+__device__ __forceinline__ uint16_t act_at(const ActView& a, const ActView& b, int64_t pix, int c) {
+  const ActView& s = c < a.c ? a : b;
+  const int cc = c < a.c ? c : c - a.c;
+  return s.p[pix * s.stride + s.offset + cc];
+}
+
+__global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
+    ActView x1, ActView x2, ActView dz, ActView mask, int N, int H, int W, int cout, int cin,
+    float* __restrict__ dw, float* __restrict__ dbias) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[BM * LDK];   // [co][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t sB[BN * LDK];   // [ci][pixel]
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t npix = (int64_t)N * H * W;
+  const int co0 = blockIdx.x * BM;
+  const int tap = blockIdx.y % 9;
+  const int ci0 = (blockIdx.y / 9) * BN;
+  const int64_t kbeg = (int64_t)blockIdx.z * WG_KCHUNK;
+  const int64_t kend = min(npix, kbeg + WG_KCHUNK);
+  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  const bool do_bias = dbias != nullptr && tap == 4 && ci0 == 0;
+  float bacc = 0.f;
+  const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
+  const int kl = t >> 3, ch = (t & 7) * 8;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    uint16_t vz[8], vx[8];
+    for (int q = 0; q < 8; ++q) vz[q] = vx[q] = 0;
+    const int64_t p = k0 + kl;
+    if (p < kend) {
+      for (int q = 0; q < 8; ++q) {
+        const int co = co0 + ch + q;
+        if (co >= cout) break;
+        uint16_t z = dz.p[p * dz.stride + dz.offset + co];
+        if (mask.p && (int16_t)mask.p[p * mask.stride + mask.offset + co] <= 0) z = 0;
+        vz[q] = z;
+      }
+      const int img = (int)(p / ((int64_t)H * W));
+      const int rem = (int)(p - (int64_t)img * H * W);
+      const int yy = rem / W + dy, xx = rem % W + dx;
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+        const int64_t sp = ((int64_t)img * H + yy) * W + xx;
+        for (int q = 0; q < 8; ++q) {
+          const int ci = ci0 + ch + q;
+          if (ci >= cin) break;
+          vx[q] = act_at(x1, x2, sp, ci);
+        }
+      }
+    }
+    __syncthreads();
+    for (int q = 0; q < 8; ++q) {
+      sA[(ch + q) * LDK + kl] = vz[q];
+      sB[(ch + q) * LDK + kl] = vx[q];
+    }
+    __syncthreads();
+    if (do_bias && t < 64)
+      for (int k = 0; k < BK; ++k) bacc += bf2f(sA[t * LDK + k]);
+    bf16x8 a[2], b[2];
+    for (int i = 0; i < 2; ++i)
+      a[i] = *reinterpret_cast<const bf16x8*>(&sA[(wm + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+    for (int j = 0; j < 2; ++j)
+      b[j] = *reinterpret_cast<const bf16x8*>(&sB[(wn + j * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const int ci = ci0 + wn + j * 16 + (lane & 15);
+      if (ci >= cin) continue;
+      for (int r = 0; r < 4; ++r) {
+        const int co = co0 + wm + i * 16 + 4 * (lane >> 4) + r;
+        if (co >= cout) continue;
+        unsafeAtomicAdd(&dw[((int64_t)tap * cout + co) * cin + ci], acc[i][j][r]);
+      }
+    }
+  if (do_bias && t < 64 && co0 + t < cout) unsafeAtomicAdd(&dbias[co0 + t], bacc);
+}
+
+// w [9][cout][cin] -> wt [9][cin][cout] with taps mirrored (backward data)
+__global__ void flip_weights_kernel(const uint16_t* __restrict__ w, int cout, int cin,
+                                    uint16_t* __restrict__ wt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = 9LL * cout * cin;
+  if (i >= total) return;
+  const int tap = (int)(i / ((int64_t)cout * cin));
+  const int rem = (int)(i - (int64_t)tap * cout * cin);
+  const int co = rem / cin, ci = rem % cin;
+  wt[((int64_t)(8 - tap) * cin + ci) * cout + co] = w[i];
+}
+
+__global__ void avgpool2_kernel(ActView x, int N, int H, int W, uint16_t* __restrict__ y,
+                                int y_stride) {
+  const int Ho = H / 2, Wo = W / 2;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)N * Ho * Wo * x.c;
+  if (i >= total) return;
+  const int c = (int)(i % x.c);
+  const int64_t q = i / x.c;
+  const int n = (int)(q / ((int64_t)Ho * Wo));
+  const int r = (int)(q - (int64_t)n * Ho * Wo);
+  const int yo = r / Wo, xo = r % Wo;
+  float s = 0.f;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int64_t p = ((int64_t)n * H + 2 * yo + a) * W + 2 * xo + b;
+      s += bf2f(x.p[p * x.stride + x.offset + c]);
+    }
+  y[q * y_stride + c] = f2bf(0.25f * s);
+}
+
+// dx[p][c] (+)= dy[pool(p)][c] / 4 (dx may be a channel slice; accumulate adds)
+__global__ void avgpool2_bwd_kernel(ActView dy, int N, int H, int W, uint16_t* __restrict__ dx,
+                                    int dx_stride, int dx_offset, int accumulate,
+                                    const uint16_t* __restrict__ add_src, int add_stride,
+                                    int add_offset) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)N * H * W * dy.c;
+  if (i >= total) return;
+  const int c = (int)(i % dy.c);
+  const int64_t p = i / dy.c;
+  const int n = (int)(p / ((int64_t)H * W));
+  const int r = (int)(p - (int64_t)n * H * W);
+  const int yy = r / W, xx = r % W;
+  const int Ho = H / 2, Wo = W / 2;
+  float v = 0.f;
+  if (yy / 2 < Ho && xx / 2 < Wo) {
+    const int64_t q = ((int64_t)n * Ho + yy / 2) * Wo + xx / 2;
+    v = 0.25f * bf2f(dy.p[q * dy.stride + dy.offset + c]);
+  }
+  if (add_src) v += bf2f(add_src[p * add_stride + add_offset + c]);
+  uint16_t* o = dx + p * dx_stride + dx_offset + c;
+  *o = f2bf(accumulate ? bf2f(*o) + v : v);
+}
+
+__global__ void upsample2_kernel(ActView x, int N, int H, int W, uint16_t* __restrict__ y,
+                                 int y_stride, int y_offset) {
+  // x is (H/2) x (W/2); y is H x W
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)N * H * W * x.c;
+  if (i >= total) return;
+  const int c = (int)(i % x.c);
+  const int64_t p = i / x.c;
+  const int n = (int)(p / ((int64_t)H * W));
+  const int r = (int)(p - (int64_t)n * H * W);
+  const int yy = r / W, xx = r % W;
+  const int64_t q = ((int64_t)n * (H / 2) + yy / 2) * (W / 2) + xx / 2;
+  y[p * y_stride + y_offset + c] = x.p[q * x.stride + x.offset + c];
+}
+
+__global__ void upsample2_bwd_kernel(ActView dy, int N, int H, int W, uint16_t* __restrict__ dx,
+                                     int dx_stride) {
+  // dy is H x W, dx is (H/2) x (W/2): dx = sum of the 2x2 block
+  const int Ho = H / 2, Wo = W / 2;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)N * Ho * Wo * dy.c;
+  if (i >= total) return;
+  const int c = (int)(i % dy.c);
+  const int64_t q = i / dy.c;
+  const int n = (int)(q / ((int64_t)Ho * Wo));
+  const int r = (int)(q - (int64_t)n * Ho * Wo);
+  const int yo = r / Wo, xo = r % Wo;
+  float s = 0.f;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int64_t p = ((int64_t)n * H + 2 * yo + a) * W + 2 * xo + b;
+      s += bf2f(dy.p[p * dy.stride + dy.offset + c]);
+    }
+  dx[q * dx_stride + c] = f2bf(s);
+}
+
+// planar float32 RGB [N][3][H][W] -> NHWC bf16 with `stride` channels (zero padded)
+__global__ void rgb_to_nhwc_kernel(const float* __restrict__ rgb, int N, int H, int W,
+                                   uint16_t* __restrict__ x, int stride) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t npix = (int64_t)N * H * W;
+  if (p >= npix) return;
+  const int n = (int)(p / ((int64_t)H * W));
+  const int64_t r = p - (int64_t)n * H * W;
+  for (int c = 0; c < stride; ++c)
+    x[p * stride + c] = c < 3 ? f2bf(rgb[((int64_t)n * 3 + c) * H * W + r]) : (uint16_t)0;
+}
+
+__global__ void f32_to_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
+                                   int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = f2bf(src[i]);
+}
+
+// Per-pixel head on float32 features [p][2] (a 1x1 conv already applied by
+// conv3x3 with a 1x1 kernel would waste 8/9 of the work; the head is a 1x1
+// conv): out[n][k][y][x] = b[k] + sum_c w[k][c] f[p][c].
+__global__ void head_fwd_kernel(ActView f, int N, int H, int W, const float* __restrict__ w,
+                                const float* __restrict__ b, float* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t npix = (int64_t)N * H * W;
+  if (p >= npix) return;
+  float o0 = b[0], o1 = b[1];
+  for (int c = 0; c < f.c; ++c) {
+    const float v = bf2f(f.p[p * f.stride + f.offset + c]);
+    o0 += w[c] * v;
+    o1 += w[f.c + c] * v;
+  }
+  const int n = (int)(p / ((int64_t)H * W));
+  const int64_t r = p - (int64_t)n * H * W;
+  out[((int64_t)n * 2 + 0) * H * W + r] = o0;
+  out[((int64_t)n * 2 + 1) * H * W + r] = o1;
+}
+
+// Head backward: dF[p][c] = sum_k w[k][c] dout[k][p] masked by the feature's
+// ReLU (f > 0); dW, db accumulated with per-block reductions and atomics.
+__global__ __launch_bounds__(256) void head_bwd_kernel(ActView f, int N, int H, int W,
+                                                       const float* __restrict__ w,
+                                                       const float* __restrict__ dout,
+                                                       uint16_t* __restrict__ df, int df_stride,
+                                                       float* __restrict__ dw,
+                                                       float* __restrict__ db) {
+  __shared__ float s_dw[2 * 64 + 2];
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t npix = (int64_t)N * H * W;
+  for (int k = threadIdx.x; k < 2 * f.c + 2; k += blockDim.x) s_dw[k] = 0.f;
+  __syncthreads();
+  if (p < npix) {
+    const int n = (int)(p / ((int64_t)H * W));
+    const int64_t r = p - (int64_t)n * H * W;
+    const float g0 = dout[((int64_t)n * 2 + 0) * H * W + r];
+    const float g1 = dout[((int64_t)n * 2 + 1) * H * W + r];
+    atomicAdd(&s_dw[2 * f.c], g0);
+    atomicAdd(&s_dw[2 * f.c + 1], g1);
+    for (int c = 0; c < f.c; ++c) {
+      const float v = bf2f(f.p[p * f.stride + f.offset + c]);
+      atomicAdd(&s_dw[c], g0 * v);
+      atomicAdd(&s_dw[f.c + c], g1 * v);
+      const float d = v > 0.f ? (w[c] * g0 + w[f.c + c] * g1) : 0.f;
+      df[p * df_stride + c] = f2bf(d);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < 2 * f.c; k += blockDim.x) unsafeAtomicAdd(&dw[k], s_dw[k]);
+  if (threadIdx.x < 2) unsafeAtomicAdd(&db[threadIdx.x], s_dw[2 * f.c + threadIdx.x]);
+}
+
+// Depth supervision: pred [N][2][H][W] = (log depth, log scale); target depth
+// [N][H][W] (<= 0 marks invalid); log-scale target log(depth / fx).
+// loss = mean over valid of |pred0 - log d| + |pred1 - log(d / fx)|.
+__global__ __launch_bounds__(256) void depth_loss_kernel(const float* __restrict__ pred,
+                                                         const float* __restrict__ depth, int N,
+                                                         int H, int W, float fx,
+                                                         const int* __restrict__ count,
+                                                         float* __restrict__ dpred,
+                                                         double* __restrict__ loss) {
+  __shared__ float s_acc[4];
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t npix = (int64_t)N * H * W;
+  float l = 0.f;
+  if (p < npix) {
+    const int n = (int)(p / ((int64_t)H * W));
+    const int64_t r = p - (int64_t)n * H * W;
+    const float d = depth[p];
+    const float inv = 1.0f / (float)max(*count, 1);
+    float g0 = 0.f, g1 = 0.f;
+    if (d > 0.f) {
+      const float ld = logf(d), ls = logf(d / fx);
+      const float e0 = pred[((int64_t)n * 2 + 0) * H * W + r] - ld;
+      const float e1 = pred[((int64_t)n * 2 + 1) * H * W + r] - ls;
+      l = (fabsf(e0) + fabsf(e1)) * inv;
+      g0 = e0 > 0.f ? inv : (e0 < 0.f ? -inv : 0.f);
+      g1 = e1 > 0.f ? inv : (e1 < 0.f ? -inv : 0.f);
+    }
+    dpred[((int64_t)n * 2 + 0) * H * W + r] = g0;
+    dpred[((int64_t)n * 2 + 1) * H * W + r] = g1;
+  }
+  for (int d = 32; d > 0; d >>= 1) l += __shfl_xor(l, d, 64);
+  if ((threadIdx.x & 63) == 0) s_acc[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) atomicAdd(loss, (double)(s_acc[0] + s_acc[1] + s_acc[2] + s_acc[3]));
+}
+
+__global__ void count_valid_kernel(const float* __restrict__ depth, int64_t n,
+                                   int* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int c = (i < n && depth[i] > 0.f) ? 1 : 0;
+  for (int d = 32; d > 0; d >>= 1) c += __shfl_xor(c, d, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
+__global__ void zero_kernel(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+ActView view(const gs_act* a) {
+  ActView v{nullptr, 0, 0, 0};
+  if (a) {
+    v.p = static_cast<const uint16_t*>(a->data);
+    v.c = a->c;
+    v.stride = a->stride;
+    v.offset = a->offset;
+  }
+  return v;
+}
+
+unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t nn_conv3x3(const gs_act* x1, const gs_act* x2, const gs_act* mask, const void* w,
+                      int cout, const float* bias, int relu, gs_act* y, float* yf, int yf_stride,
+                      hipStream_t s) {
+  const int cin = x1->c + (x2 ? x2->c : 0);
+  const int64_t npix = (int64_t)x1->n * x1->h * x1->w;
+  const dim3 grid(blocks(npix, BM), (unsigned)((cout + BN - 1) / BN));
+  hipLaunchKernelGGL(conv3x3_kernel, grid, dim3(256), 0, s, view(x1), view(x2), view(mask),
+                     x1->n, x1->h, x1->w, static_cast<const uint16_t*>(w), cout, cin, bias, relu,
+                     y ? static_cast<uint16_t*>(y->data) : nullptr, y ? y->stride : 0,
+                     y ? y->offset : 0, yf, yf_stride);
+  return hipGetLastError();
+}
+
+hipError_t nn_conv3x3_wgrad(const gs_act* x1, const gs_act* x2, const gs_act* dz,
+                            const gs_act* mask, float* dw, float* dbias, hipStream_t s) {
+  const int cin = x1->c + (x2 ? x2->c : 0);
+  const int cout = dz->c;
+  const int64_t npix = (int64_t)x1->n * x1->h * x1->w;
+  const dim3 grid((unsigned)((cout + BM - 1) / BM), (unsigned)(9 * ((cin + BN - 1) / BN)),
+                  blocks(npix, WG_KCHUNK));
+  hipLaunchKernelGGL(conv3x3_wgrad_kernel, grid, dim3(256), 0, s, view(x1), view(x2), view(dz),
+                     view(mask), x1->n, x1->h, x1->w, cout, cin, dw, dbias);
+  return hipGetLastError();
+}
+
+hipError_t nn_flip_weights(const void* w, int cout, int cin, void* wt, hipStream_t s) {
+  hipLaunchKernelGGL(flip_weights_kernel, dim3(blocks(9LL * cout * cin)), dim3(256), 0, s,
+                     static_cast<const uint16_t*>(w), cout, cin, static_cast<uint16_t*>(wt));
+  return hipGetLastError();
+}
+
+hipError_t nn_avgpool2(const gs_act* x, gs_act* y, hipStream_t s) {
+  const int64_t total = (int64_t)x->n * (x->h / 2) * (x->w / 2) * x->c;
+  hipLaunchKernelGGL(avgpool2_kernel, dim3(blocks(total)), dim3(256), 0, s, view(x), x->n, x->h,
+                     x->w, static_cast<uint16_t*>(y->data) + y->offset, y->stride);
+  return hipGetLastError();
+}
+
+hipError_t nn_avgpool2_bwd(const gs_act* dy, const gs_act* add, gs_act* dx, int accumulate,
+                           hipStream_t s) {
+  const int64_t total = (int64_t)dx->n * dx->h * dx->w * dy->c;
+  hipLaunchKernelGGL(avgpool2_bwd_kernel, dim3(blocks(total)), dim3(256), 0, s, view(dy), dx->n,
+                     dx->h, dx->w, static_cast<uint16_t*>(dx->data), dx->stride, dx->offset,
+                     accumulate, add ? static_cast<const uint16_t*>(add->data) : nullptr,
+                     add ? add->stride : 0, add ? add->offset : 0);
+  return hipGetLastError();
+}
+
+hipError_t nn_upsample2(const gs_act* x, gs_act* y, hipStream_t s) {
+  const int64_t total = (int64_t)y->n * y->h * y->w * x->c;
+  hipLaunchKernelGGL(upsample2_kernel, dim3(blocks(total)), dim3(256), 0, s, view(x), y->n, y->h,
+                     y->w, static_cast<uint16_t*>(y->data), y->stride, y->offset);
+  return hipGetLastError();
+}
+
+hipError_t nn_upsample2_bwd(const gs_act* dy, gs_act* dx, hipStream_t s) {
+  const int64_t total = (int64_t)dx->n * dx->h * dx->w * dy->c;
+  hipLaunchKernelGGL(upsample2_bwd_kernel, dim3(blocks(total)), dim3(256), 0, s, view(dy), dy->n,
+                     dy->h, dy->w, static_cast<uint16_t*>(dx->data) + dx->offset, dx->stride);
+  return hipGetLastError();
+}
+
+hipError_t nn_rgb_to_nhwc(const float* rgb, gs_act* x, hipStream_t s) {
+  const int64_t npix = (int64_t)x->n * x->h * x->w;
+  hipLaunchKernelGGL(rgb_to_nhwc_kernel, dim3(blocks(npix)), dim3(256), 0, s, rgb, x->n, x->h,
+                     x->w, static_cast<uint16_t*>(x->data), x->stride);
+  return hipGetLastError();
+}
+
+hipError_t nn_f32_to_bf16(const float* src, void* dst, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(f32_to_bf16_kernel, dim3(blocks(n)), dim3(256), 0, s, src,
+                     static_cast<uint16_t*>(dst), n);
+  return hipGetLastError();
+}
+
+hipError_t nn_head(const gs_act* f, const float* w, const float* b, float* out, hipStream_t s) {
+  const int64_t npix = (int64_t)f->n * f->h * f->w;
+  hipLaunchKernelGGL(head_fwd_kernel, dim3(blocks(npix)), dim3(256), 0, s, view(f), f->n, f->h,
+                     f->w, w, b, out);
+  return hipGetLastError();
+}
+
+hipError_t nn_head_bwd(const gs_act* f, const float* w, const float* dout, gs_act* df, float* dw,
+                       float* db, hipStream_t s) {
+  const int64_t npix = (int64_t)f->n * f->h * f->w;
+  hipLaunchKernelGGL(head_bwd_kernel, dim3(blocks(npix)), dim3(256), 0, s, view(f), f->n, f->h,
+                     f->w, w, dout, static_cast<uint16_t*>(df->data) + df->offset, df->stride, dw,
+                     db);
+  return hipGetLastError();
+}
+
+hipError_t nn_depth_loss(const float* pred, const float* depth, int N, int H, int W, float fx,
+                         float* dpred, double* loss, int* count_ws, hipStream_t s) {
+  const int64_t npix = (int64_t)N * H * W;
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t*>(count_ws),
+                     (int64_t)1);
+  if (loss) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s,
+                               reinterpret_cast<uint32_t*>(loss), (int64_t)2);
+  hipLaunchKernelGGL(count_valid_kernel, dim3(blocks(npix)), dim3(256), 0, s, depth, npix, count_ws);
+  hipLaunchKernelGGL(depth_loss_kernel, dim3(blocks(npix)), dim3(256), 0, s, pred, depth, N, H, W,
+                     fx, count_ws, dpred, loss);
+  return hipGetLastError();
+}
+
+}  // namespace gsmi

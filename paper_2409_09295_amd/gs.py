@@ -422,3 +422,136 @@ def gs_set_tuning(key: int, value: int) -> None:
 
 def gs_get_tuning(key: int) -> int:
     return int(_lib.gs_get_tuning(key))
+
+
+# ---------------------------------------------------------------------------
+# learned / plain initialiser (include/gs_nn.h)
+# ---------------------------------------------------------------------------
+
+class gs_act(ctypes.Structure):
+    _fields_ = [("data", _p), ("n", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("c", ctypes.c_int32), ("stride", ctypes.c_int32), ("offset", ctypes.c_int32)]
+
+
+_PA = ctypes.POINTER(gs_act)
+_lib.gs_nn_conv3x3.argtypes = [_PA, _PA, _PA, _p, ctypes.c_int32, _p, ctypes.c_int32, _PA, _p,
+                               ctypes.c_int32, _S]
+_lib.gs_nn_conv3x3_wgrad.argtypes = [_PA, _PA, _PA, _PA, _p, _p, _S]
+_lib.gs_nn_flip_weights.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _S]
+_lib.gs_nn_avgpool2.argtypes = [_PA, _PA, _S]
+_lib.gs_nn_avgpool2_bwd.argtypes = [_PA, _PA, _PA, ctypes.c_int32, _S]
+_lib.gs_nn_upsample2.argtypes = [_PA, _PA, _S]
+_lib.gs_nn_upsample2_bwd.argtypes = [_PA, _PA, _S]
+_lib.gs_nn_rgb_to_nhwc.argtypes = [_p, _PA, _S]
+_lib.gs_nn_f32_to_bf16.argtypes = [_p, _p, ctypes.c_int64, _S]
+_lib.gs_nn_head.argtypes = [_PA, _p, _p, _p, _S]
+_lib.gs_nn_head_bwd.argtypes = [_PA, _p, _p, _PA, _p, _p, _S]
+_lib.gs_nn_depth_loss.argtypes = [_p, _p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_float, _p, _p, _p, _S]
+_lib.gs_cost_volume_workspace_size.restype = ctypes.c_size_t
+_lib.gs_cost_volume_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+_lib.gs_cost_volume_wta.argtypes = [_p, ctypes.POINTER(gs_views), _p, _p, _p, ctypes.c_size_t, _S]
+EXPORTED = EXPORTED + ("gs_nn_conv3x3", "gs_nn_conv3x3_wgrad", "gs_nn_flip_weights", "gs_nn_avgpool2",
+                       "gs_nn_avgpool2_bwd", "gs_nn_upsample2", "gs_nn_upsample2_bwd",
+                       "gs_nn_rgb_to_nhwc", "gs_nn_f32_to_bf16", "gs_nn_head", "gs_nn_head_bwd",
+                       "gs_nn_depth_loss", "gs_cost_volume_workspace_size", "gs_cost_volume_wta")
+
+
+class Act:
+    """BF16 NHWC activation view over a torch.bfloat16 tensor [n, h, w, stride]."""
+
+    def __init__(self, t: torch.Tensor, c: Optional[int] = None, offset: int = 0):
+        if t.dtype != torch.bfloat16 or t.dim() != 4 or not t.is_contiguous():
+            raise ValueError("activations are contiguous bfloat16 [n, h, w, stride]")
+        self.t = t
+        self.n, self.h, self.w, self.stride = (int(s) for s in t.shape)
+        self.c = self.stride - offset if c is None else int(c)
+        self.offset = int(offset)
+        self.struct = gs_act(t.data_ptr(), self.n, self.h, self.w, self.c, self.stride, self.offset)
+
+    @classmethod
+    def empty(cls, n, h, w, c, device="cuda", zero=False):
+        f = torch.zeros if zero else torch.empty
+        return cls(f(n, h, w, c, dtype=torch.bfloat16, device=device))
+
+    def slice(self, offset: int, c: int) -> "Act":
+        return Act(self.t, c, self.offset + offset)
+
+    def values(self) -> torch.Tensor:
+        """The view's channels as float32 [n, h, w, c] (a copy)."""
+        return self.t[..., self.offset:self.offset + self.c].float()
+
+
+def _ap(a: Optional[Act]):
+    return None if a is None else ctypes.byref(a.struct)
+
+
+def gs_nn_conv3x3(x1: Act, x2: Optional[Act], mask: Optional[Act], weights: torch.Tensor, cout: int,
+                  bias: Optional[torch.Tensor], relu: bool, y: Optional[Act],
+                  y_f32: Optional[torch.Tensor] = None, y_f32_stride: int = 0, stream=None) -> None:
+    _check(_lib.gs_nn_conv3x3(_ap(x1), _ap(x2), _ap(mask), _ptr(weights), cout, _ptr(bias), int(relu),
+                              _ap(y), _ptr(y_f32), y_f32_stride, _stream(stream)), "gs_nn_conv3x3")
+
+
+def gs_nn_conv3x3_wgrad(x1: Act, x2: Optional[Act], dy: Act, mask: Optional[Act], dw: torch.Tensor,
+                        dbias: Optional[torch.Tensor], stream=None) -> None:
+    _check(_lib.gs_nn_conv3x3_wgrad(_ap(x1), _ap(x2), _ap(dy), _ap(mask), _ptr(dw), _ptr(dbias),
+                                    _stream(stream)), "gs_nn_conv3x3_wgrad")
+
+
+def gs_nn_flip_weights(w: torch.Tensor, cout: int, cin: int, wt: torch.Tensor, stream=None) -> None:
+    _check(_lib.gs_nn_flip_weights(_ptr(w), cout, cin, _ptr(wt), _stream(stream)), "gs_nn_flip_weights")
+
+
+def gs_nn_avgpool2(x: Act, y: Act, stream=None) -> None:
+    _check(_lib.gs_nn_avgpool2(_ap(x), _ap(y), _stream(stream)), "gs_nn_avgpool2")
+
+
+def gs_nn_avgpool2_bwd(dy: Act, add: Optional[Act], dx: Act, accumulate: bool = False, stream=None) -> None:
+    _check(_lib.gs_nn_avgpool2_bwd(_ap(dy), _ap(add), _ap(dx), int(accumulate), _stream(stream)),
+           "gs_nn_avgpool2_bwd")
+
+
+def gs_nn_upsample2(x: Act, y: Act, stream=None) -> None:
+    _check(_lib.gs_nn_upsample2(_ap(x), _ap(y), _stream(stream)), "gs_nn_upsample2")
+
+
+def gs_nn_upsample2_bwd(dy: Act, dx: Act, stream=None) -> None:
+    _check(_lib.gs_nn_upsample2_bwd(_ap(dy), _ap(dx), _stream(stream)), "gs_nn_upsample2_bwd")
+
+
+def gs_nn_rgb_to_nhwc(rgb: torch.Tensor, x: Act, stream=None) -> None:
+    _check(_lib.gs_nn_rgb_to_nhwc(_ptr(rgb), _ap(x), _stream(stream)), "gs_nn_rgb_to_nhwc")
+
+
+def gs_nn_f32_to_bf16(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    if src.numel() != dst.numel():
+        raise ValueError("size mismatch")
+    _check(_lib.gs_nn_f32_to_bf16(_ptr(src), _ptr(dst), src.numel(), _stream(stream)), "gs_nn_f32_to_bf16")
+
+
+def gs_nn_head(f: Act, w: torch.Tensor, b: torch.Tensor, out: torch.Tensor, stream=None) -> None:
+    _check(_lib.gs_nn_head(_ap(f), _ptr(w), _ptr(b), _ptr(out), _stream(stream)), "gs_nn_head")
+
+
+def gs_nn_head_bwd(f: Act, w: torch.Tensor, dout: torch.Tensor, df: Act, dw: torch.Tensor,
+                   db: torch.Tensor, stream=None) -> None:
+    _check(_lib.gs_nn_head_bwd(_ap(f), _ptr(w), _ptr(dout), _ap(df), _ptr(dw), _ptr(db),
+                               _stream(stream)), "gs_nn_head_bwd")
+
+
+def gs_nn_depth_loss(pred: torch.Tensor, depth: torch.Tensor, fx: float, dpred: torch.Tensor,
+                     loss: Optional[torch.Tensor], ws: torch.Tensor, stream=None) -> None:
+    n, _, h, w = pred.shape
+    _check(_lib.gs_nn_depth_loss(_ptr(pred), _ptr(depth), n, h, w, fx, _ptr(dpred), _ptr(loss),
+                                 _ptr(ws), _stream(stream)), "gs_nn_depth_loss")
+
+
+def gs_cost_volume_wta(keyframes: torch.Tensor, views: Views, cost: Optional[torch.Tensor],
+                       depth: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
+    _check(_lib.gs_cost_volume_wta(_ptr(keyframes), ctypes.byref(views.struct), _ptr(cost), _ptr(depth),
+                                   _ptr(ws), ws.numel(), _stream(stream)), "gs_cost_volume_wta")
+
+
+def gs_cost_volume_workspace_size(k: int, h: int, w: int) -> int:
+    return int(_lib.gs_cost_volume_workspace_size(k, h, w))

@@ -1,5 +1,5 @@
 """C-ABI checks that need no GPU: the library loads, exports every entry
-point declared in include/gs.h, and rejects invalid arguments with the
+point declared in include/*.h, and rejects invalid arguments with the
 documented status before touching the device."""
 import ctypes
 import os
@@ -9,14 +9,16 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "gs.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("gs.h", "gs_nn.h")]
 LIB = os.path.join(ROOT, "paper_2409_09295_amd", "libgsmi.so")
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -29,11 +31,12 @@ def gs():
 
 def test_every_declared_symbol_is_exported(gs):
     names = _declared()
-    assert len(names) >= 13
+    assert len(names) >= 30
     lib = ctypes.CDLL(LIB)
     for n in names:
         assert hasattr(lib, n), n
-    assert set(names) <= set(gs.EXPORTED) | {n for n in names if hasattr(lib, n)}
+    # and the Python binding wraps every one of them
+    assert set(names) <= set(gs.EXPORTED), set(names) - set(gs.EXPORTED)
 
 
 def test_status_strings(gs):
@@ -179,3 +182,38 @@ def test_se3_exp_closed_form_matches_matrix_exponential():
         xi = rng.normal(size=6) * scale
         ref = O.se3_exp(torch.as_tensor(xi)).numpy()
         np.testing.assert_allclose(se3_exp(xi), ref, atol=1e-12)
+
+
+def _act(gs, c, stride=None, offset=0, n=1, h=8, w=8, data=0xDEAD0000):
+    return gs.gs_act(data, n, h, w, c, stride if stride is not None else c, offset)
+
+
+def test_nn_argument_errors(gs):
+    lib = gs.lib()
+    bad = gs.GS_ERR_INVALID_ARGUMENT
+    ok_x = _act(gs, 32)
+    y = _act(gs, 32)
+    w = ctypes.c_void_p(0xDEAD1000)
+    conv = lambda x1, x2, m, wt, cout, y_: lib.gs_nn_conv3x3(
+        ctypes.byref(x1), ctypes.byref(x2) if x2 else None, ctypes.byref(m) if m else None, wt, cout,
+        None, 1, ctypes.byref(y_) if y_ else None, None, 0, None)
+    assert conv(_act(gs, 12), None, None, w, 32, y) == bad            # channels not a multiple of 8
+    assert conv(_act(gs, 32, data=0xDEAD0004), None, None, w, 32, y) == bad   # misaligned
+    assert conv(ok_x, _act(gs, 32, h=4), None, w, 32, y) == bad       # concat of different grids
+    assert conv(ok_x, None, _act(gs, 16), w, 32, y) == bad            # mask layout
+    assert conv(ok_x, None, None, None, 32, y) == bad                 # no weights
+    assert conv(ok_x, None, None, ctypes.c_void_p(0xDEAD1002), 32, y) == bad  # misaligned weights
+    assert conv(ok_x, None, None, w, 32, None) == bad                 # no output
+    assert conv(ok_x, None, None, w, 64, y) == bad                    # y channels != cout
+    assert lib.gs_nn_avgpool2(ctypes.byref(_act(gs, 8, h=7)), ctypes.byref(_act(gs, 8, h=3, w=4)),
+                              None) == bad
+    assert lib.gs_nn_depth_loss(None, None, 1, 8, 8, ctypes.c_float(500.0), None, None, None, None) == bad
+    assert lib.gs_cost_volume_workspace_size(1, 64, 64) == 0
+    cams = _views(gs, [(64, 48), (64, 48)])
+    assert lib.gs_cost_volume_wta(ctypes.c_void_p(0xDEAD0000), ctypes.byref(cams), None,
+                                  ctypes.c_void_p(0xDEAD0000), ctypes.c_void_p(0xDEAD0000), 16,
+                                  None) == gs.GS_ERR_CAPACITY
+    odd = _views(gs, [(64, 48), (66, 48)])
+    assert lib.gs_cost_volume_wta(ctypes.c_void_p(0xDEAD0000), ctypes.byref(odd), None,
+                                  ctypes.c_void_p(0xDEAD0000), ctypes.c_void_p(0xDEAD0000), 1 << 20,
+                                  None) == bad

@@ -1,0 +1,224 @@
+"""Initialiser kernels vs the FP64 oracle (needs an MI355X), and the judge of
+the learned initialiser against the plain one."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nn_oracle as N
+from paper_2409_09295_amd import scenes
+from tests.gpu_helpers import np_
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _bf16(a):
+    return torch.as_tensor(np.asarray(a, np.float32)).to(torch.bfloat16)
+
+
+def _act(gs, t_bf16_nhwc, c=None):
+    return gs.Act(t_bf16_nhwc.contiguous().to(DEV), c)
+
+
+def _f64(t):
+    return t.float().double().cpu()
+
+
+CONV_CASES = [
+    # (n, h, w, cin1, cin2, cout)
+    (1, 8, 8, 8, 0, 32),        # first-layer shape (3 real channels padded to 8)
+    (2, 10, 13, 32, 0, 64),     # ragged pixel count, two images
+    (1, 16, 12, 64, 32, 96),    # skip concatenation, cout not a multiple of 64
+    (1, 6, 8, 256, 128, 128),   # deep
+]
+
+
+@pytest.mark.parametrize("case", CONV_CASES)
+def test_conv3x3_forward(gs, case):
+    n, h, w, c1, c2, cout = case
+    rng = np.random.default_rng(sum(case))
+    x1 = _bf16(rng.normal(size=(n, h, w, c1)))
+    x2 = _bf16(rng.normal(size=(n, h, w, c2))) if c2 else None
+    cin = c1 + c2
+    wt = _bf16(rng.normal(size=(9, cout, cin)) / np.sqrt(9 * cin))
+    b = torch.as_tensor(rng.normal(size=cout).astype(np.float32))
+    yf = torch.zeros(n * h * w, cout, device=DEV)
+    y = gs.Act.empty(n, h, w, cout, DEV)
+    gs.gs_nn_conv3x3(_act(gs, x1), _act(gs, x2) if x2 is not None else None, None, wt.to(DEV), cout,
+                     b.to(DEV), False, y, yf, cout)
+    ry = gs.Act.empty(n, h, w, cout, DEV)
+    gs.gs_nn_conv3x3(_act(gs, x1), _act(gs, x2) if x2 is not None else None, None, wt.to(DEV), cout,
+                     b.to(DEV), True, ry, None, 0)
+    torch.cuda.synchronize()
+    x = _f64(x1) if x2 is None else torch.cat([_f64(x1), _f64(x2)], 3)
+    ref = N.conv3x3(x, _f64(wt), b.double())
+    scale = N.conv3x3(x.abs(), _f64(wt).abs()) + b.double().abs()
+    got = np_(yf).reshape(n, h, w, cout)
+    # float32 accumulation of exact bf16 products
+    assert (np.abs(got - ref.numpy()) <= 1e-5 * scale.numpy() + 1e-7).all()
+    # bf16 output with ReLU: the rounded float32 result
+    expect = N.bf16_round(np.maximum(got, 0.0))
+    np.testing.assert_array_equal(np_(ry.values()), expect)
+
+
+def test_conv3x3_backward(gs):
+    n, h, w, cin, cout = 1, 12, 10, 64, 32
+    rng = np.random.default_rng(7)
+    x = _bf16(rng.normal(size=(n, h, w, cin)))
+    wt = _bf16(rng.normal(size=(9, cout, cin)) / np.sqrt(9 * cin))
+    y = _bf16(np.maximum(rng.normal(size=(n, h, w, cout)), 0.0))   # a ReLU output used as mask
+    gy = _bf16(rng.normal(size=(n, h, w, cout)))
+    # backward data: flip + conv with the ReLU mask fused
+    wflip = torch.empty(9, cin, cout, dtype=torch.bfloat16, device=DEV)
+    gs.gs_nn_flip_weights(wt.to(DEV), cout, cin, wflip)
+    gx = torch.zeros(n * h * w, cin, device=DEV)
+    gs.gs_nn_conv3x3(_act(gs, gy), None, _act(gs, y), wflip, cin, None, False, None, gx, cin)
+    # weight and bias gradients
+    dw = torch.zeros(9, cout, cin, device=DEV)
+    db = torch.zeros(cout, device=DEV)
+    gs.gs_nn_conv3x3_wgrad(_act(gs, x), None, _act(gs, gy), _act(gs, y), dw, db)
+    torch.cuda.synchronize()
+    xr = _f64(x).requires_grad_(True)
+    wr = _f64(wt).requires_grad_(True)
+    br = torch.zeros(cout, dtype=torch.float64, requires_grad=True)
+    z = N.conv3x3(xr, wr, br)
+    dz = _f64(gy) * (_f64(y) > 0)
+    (z * dz).sum().backward()
+    # error scales: the same sums over absolute values
+    gxs = N.conv3x3(dz.abs(), _f64(wt).abs().flip(0).transpose(1, 2))
+    wa = _f64(wt).abs().requires_grad_(True)
+    (N.conv3x3(_f64(x).abs(), wa) * dz.abs()).sum().backward()
+    dbs = dz.abs().sum(dim=(0, 1, 2))
+    assert (np.abs(np_(gx).reshape(n, h, w, cin) - xr.grad.numpy()) <= 1e-5 * gxs.numpy() + 1e-7).all()
+    assert (np.abs(np_(dw) - wr.grad.numpy()) <= 1e-5 * wa.grad.numpy() + 1e-7).all()
+    assert (np.abs(np_(db) - br.grad.numpy()) <= 1e-5 * dbs.numpy() + 1e-7).all()
+
+
+def test_pool_upsample_exact(gs):
+    rng = np.random.default_rng(3)
+    x = _bf16(rng.normal(size=(2, 8, 6, 16)))
+    y = gs.Act.empty(2, 4, 3, 16, DEV)
+    gs.gs_nn_avgpool2(_act(gs, x), y)
+    u = gs.Act.empty(2, 8, 6, 16, DEV)
+    gs.gs_nn_upsample2(y, u)
+    dx = gs.Act.empty(2, 8, 6, 16, DEV)
+    gs.gs_nn_avgpool2_bwd(y, None, dx)
+    du = gs.Act.empty(2, 4, 3, 16, DEV)
+    gs.gs_nn_upsample2_bwd(_act(gs, x), du)
+    torch.cuda.synchronize()
+    pooled = N.bf16_round(N.avgpool2(_f64(x)).numpy())
+    np.testing.assert_array_equal(np_(y.values()), pooled)
+    np.testing.assert_array_equal(np_(u.values()), N.upsample2(torch.as_tensor(pooled)).numpy())
+    np.testing.assert_array_equal(np_(dx.values()), N.bf16_round(N.upsample2(torch.as_tensor(pooled)).numpy() / 4))
+    sums = N.avgpool2(_f64(x)).numpy() * 4
+    np.testing.assert_array_equal(np_(du.values()), N.bf16_round(sums))
+
+
+def test_head_and_loss(gs):
+    rng = np.random.default_rng(5)
+    n, h, w, c = 2, 8, 8, 32
+    f = _bf16(np.maximum(rng.normal(size=(n, h, w, c)), 0))
+    hw = torch.as_tensor(rng.normal(size=(2, c)).astype(np.float32))
+    hb = torch.as_tensor(np.array([1.0, -5.0], np.float32))
+    out = torch.zeros(n, 2, h, w, device=DEV)
+    gs.gs_nn_head(_act(gs, f), hw.to(DEV), hb.to(DEV), out)
+    depth = torch.as_tensor(rng.uniform(0.5, 6, size=(n, h, w)).astype(np.float32))
+    depth[0, :2] = 0.0
+    dpred = torch.zeros_like(out)
+    loss = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ws = torch.zeros(4, dtype=torch.int32, device=DEV)
+    gs.gs_nn_depth_loss(out, depth.to(DEV), 300.0, dpred, loss, ws)
+    df = gs.Act.empty(n, h, w, c, DEV)
+    dw = torch.zeros(2, c, device=DEV)
+    db = torch.zeros(2, device=DEV)
+    gs.gs_nn_head_bwd(_act(gs, f), hw.to(DEV), dpred, df, dw, db)
+    torch.cuda.synchronize()
+    fr = _f64(f).requires_grad_(True)
+    wr = hw.double().requires_grad_(True)
+    br = hb.double().requires_grad_(True)
+    pr = N.head(fr, wr, br)
+    np.testing.assert_allclose(np_(out), pr.detach().numpy(), rtol=1e-5, atol=1e-5)
+    L = N.depth_loss(torch.as_tensor(np_(out)).double().requires_grad_(True), depth.double(), 300.0)
+    np.testing.assert_allclose(float(np_(loss)[0]), float(L.detach()), rtol=1e-5)
+    (pr * torch.as_tensor(np_(dpred)).double()).sum().backward()
+    np.testing.assert_allclose(np_(dw), wr.grad.numpy(), rtol=1e-4, atol=1e-7)
+    np.testing.assert_allclose(np_(db), br.grad.numpy(), rtol=1e-4, atol=1e-7)
+    expect_df = N.bf16_round((fr.grad * (fr > 0)).numpy())
+    assert np.abs(np_(df.values()) - expect_df).max() <= 2 ** -7 * np.abs(expect_df).max() + 1e-8
+
+
+def test_cost_volume_matches_oracle(gs):
+    from paper_2409_09295_amd import initnet
+    gmap, boxes = scenes.procedural_room(100000, seed=1)
+    cams = initnet.trajectory_cams(8, 3, boxes, 96, 64)
+    rgb, _ = initnet.render_dataset(gmap, cams)
+    views = gs.Views(cams)
+    ws = gs.workspace(gs.gs_cost_volume_workspace_size(8, 64, 96))
+    cost = torch.empty(64, 16, 24, device=DEV)
+    depth = torch.empty(16, 24, device=DEV)
+    gs.gs_cost_volume_wta(rgb.contiguous(), views, cost, depth, ws)
+    torch.cuda.synchronize()
+    imgs = [np_(rgb[k]).astype(np.float64) for k in range(8)]
+    ref = N.cost_volume(imgs, [c.as_float32() for c in cams])
+    got = np_(cost)
+    fin = np.isfinite(ref)
+    # A sample that lands within rounding of the image border is valid on one
+    # side only, which changes that entry's set of views: such entries are
+    # rare, every other entry agrees to float32 rounding.
+    both = fin & np.isfinite(got)
+    assert (fin == np.isfinite(got)).mean() > 0.999
+    close = np.abs(got[both] - ref[both]) < 2e-5
+    assert close.mean() > 0.999, close.mean()
+    # winner-take-all: compare where the minimum is unique by a clear margin
+    srt = np.sort(np.where(fin, ref, 1e9), axis=0)
+    clear = (srt[1] - srt[0]) > 1e-3
+    dref = N.wta_depth(ref)
+    agree = np.isclose(np_(depth)[clear], dref[clear], rtol=1e-6)
+    assert clear.sum() > 100 and agree.mean() > 0.995, (clear.sum(), agree.mean())
+
+
+def test_unet_forward_backward_matches_oracle(gs):
+    """Whole network at 32 x 24: GPU kernels vs the FP64 oracle network with
+    the same BF16 weights (activations rounded to BF16 on the GPU only, so
+    the comparison is relative)."""
+    from paper_2409_09295_amd import initnet
+    net = initnet.UNet(seed=3)
+    rng = np.random.default_rng(2)
+    rgb = torch.as_tensor(rng.random((1, 3, 24, 32)).astype(np.float32)).to(DEV)
+    depth = torch.as_tensor(rng.uniform(1, 4, size=(1, 24, 32)).astype(np.float32)).to(DEV)
+    pred = net.forward(rgb)
+    dpred = net.loss_and_grad(pred, depth, 40.0)
+    net.zero_grad()
+    net.backward(dpred)
+    torch.cuda.synchronize()
+    p = {}
+    for k, v in net.params.items():
+        t = v.detach().cpu()
+        if k.endswith(".w") and not k.startswith("head"):
+            t = t.to(torch.bfloat16).float()
+        p[k] = t.double().requires_grad_(True)
+    x = torch.zeros(1, 24, 32, 8, dtype=torch.float64)
+    x[..., :3] = torch.as_tensor(N.bf16_round(np_(rgb)[0].transpose(1, 2, 0)))
+    ref = N.unet_forward(x, p)
+    # the network's part of the output (the head bias is the depth prior)
+    hb = net.params["head.b"].double().cpu().numpy()[None, :, None, None]
+    r = ref.detach().numpy() - hb
+    rel = np.linalg.norm(np_(pred) - hb - r) / np.linalg.norm(r)
+    assert rel < 2e-2, rel
+    (ref * torch.as_tensor(np_(dpred)).double()).sum().backward()
+    for k in ("e0a.w", "e3b.w", "d2a.w", "d0b.w", "head.w", "d1a.b"):
+        g = np_(net.grads[k])
+        r = p[k].grad.numpy()
+        rel = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
+        assert rel < 1e-1, (k, rel)
+
+
+def test_learned_initialiser_beats_plain(gs):
+    """Trained on renders of the map, the network's depth error on held-out
+    views is no worse than the plain (cost volume + winner-take-all)
+    initialiser's."""
+    from paper_2409_09295_amd import initnet
+    net, rep = initnet.train_and_judge(log=lambda m: print(m, flush=True))
+    print(rep, flush=True)
+    assert np.isfinite(rep.final_loss)
+    assert rep.net_absrel <= rep.plain_absrel, rep
