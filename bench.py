@@ -36,9 +36,26 @@ WORKLOADS = {
 }
 
 HBM_PEAK_GBS = 8000.0
-# VALU issue rate: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (non-packed FP32
-# lane-operations per second).
+# VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-
+# instructions per second (a wave64 VALU instruction occupies a SIMD for four
+# cycles; packed FP32 and FMA counting are what take the FP32 figure to 157.3).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+# VALU instructions per (pixel, splat) pair in the per-pixel body of the
+# compositing loops, counted in the gfx950 assembly of this library: every
+# walked pair pays the evaluation (offset, quadratic form, exp2, opacity
+# product, clamp and the two tests); a pair that is blended pays the rest.
+# Wave-level overheads (LDS staging, the 9-value reduction and its atomics,
+# loop control) are not counted: they are what separates the achieved rate
+# from the peak.
+BWD_VALU_EVAL, BWD_VALU_BLEND = 11, 35
+FWD_VALU_EVAL, FWD_VALU_BLEND = 12, 11
+# Fraction of walked pairs that are blended, measured by the oracle on the
+# 200k-Gaussian room at 640x480 (used when the oracle leg is skipped).
+DEFAULT_BLEND_FRACTION = 0.44
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_bwd_room32_traffic.txt")
+TRAFFIC_SOURCES = ("paper_2409_09295_amd/csrc/render_bwd.hip", "paper_2409_09295_amd/csrc/gs_internal.h")
 
 
 def _args():
@@ -53,6 +70,13 @@ def _args():
     ap.add_argument("--kernel-steps", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--retune", action="store_true", help="ignore the tuning cache")
+    ap.add_argument("--no-v12", action="store_true", help="skip the 12-view (8 window + 4 past) line")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a float32 copy of this size first (scales HBM counters)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch the step eagerly instead of replaying a HIP graph (profiling)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="approximate length of the CPU oracle sample")
     return ap.parse_args()
 
 
@@ -63,27 +87,74 @@ def _build(spec, seed):
     return scenes.config_metric(seed, n=spec["n"], n_views=spec["views"])
 
 
-def _cpu_baseline(wl, sample_tiles=400, seed=0):
-    """The FP64 oracle on a bounded sample: projection (all Gaussians) and
-    compositing forward + backward of ``sample_tiles`` random 16x16 tiles of
-    view 0.  Returns (Mpix/s, pixels, seconds, threads)."""
+def _cpu_baseline(wl, budget_s=12.0, max_views=4, seed=0):
+    """The FP64 oracle, as it stands, on a bounded sample of the same step:
+    projection of all Gaussians, compositing of every pixel and the full
+    backward (pixels -> 2D -> 3D parameters and pose) of whole views, taken
+    in trajectory order until about ``budget_s`` seconds have passed.
+    Returns (Mpix/s, views, pixels, seconds, threads, blended fraction)."""
     import numpy as np
     import torch
     from oracle import gs_oracle as O
-    cam = wl.cams[0].as_float32()
-    TX, TY = O.tile_grid(cam, 16)
     rng = np.random.default_rng(seed)
-    flat = rng.choice(TX * TY, size=min(sample_tiles, TX * TY), replace=False)
-    picks = [(int(t // TX), int(t % TX)) for t in flat]
-    px = sum(min(16, cam.height - 16 * ty) * min(16, cam.width - 16 * tx) for ty, tx in picks)
-    dl = np.zeros((3, cam.height, cam.width))
-    for ty, tx in picks:
-        dl[:, 16 * ty:16 * ty + 16, 16 * tx:16 * tx + 16] = rng.normal(size=(3, 16, 16))[
-            :, :min(16, cam.height - 16 * ty), :min(16, cam.width - 16 * tx)]
-    t0 = time.perf_counter()
-    O.render(wl.gmap, [cam], dL_dimage=[dl], with_mask=False, tiles=[picks])
-    dt = time.perf_counter() - t0
-    return px / dt / 1e6, px, dt, torch.get_num_threads()
+    px, dt, walked, blended, nv = 0, 0.0, 0, 0, 0
+    while nv < min(max_views, len(wl.cams)) and dt < budget_s * 0.6:
+        cam = wl.cams[nv].as_float32()
+        dl = rng.normal(size=(3, cam.height, cam.width))
+        t0 = time.perf_counter()
+        r = O.render(wl.gmap, [cam], dL_dimage=[dl], with_mask=False)
+        dt += time.perf_counter() - t0
+        v = r["views"][0]
+        walked += int(v["n_contrib"].sum())
+        blended += int(v["n_blended"].sum())
+        px += cam.width * cam.height
+        nv += 1
+    return px / dt / 1e6, nv, px, dt, torch.get_num_threads(), blended / max(walked, 1)
+
+
+def _traffic():
+    """HBM bytes per launch of the reverse tile walk from the committed
+    counter summary, or None when the kernel's sources changed since."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != h.hexdigest():
+        return None
+    try:
+        return float(vals["fetch_bytes"]) + float(vals["write_bytes"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _time_batched(step, steps, warmup):
+    import torch
+    if step.use_graph:
+        step.capture()
+    for _ in range(warmup):
+        step.step()
+    torch.cuda.synchronize()
+    if step.overflowed():
+        raise RuntimeError("key capacity overflow during warm-up")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        step.step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    if step.overflowed():
+        raise RuntimeError("key capacity overflow during timing")
+    return e0.elapsed_time(e1) / steps, wall / steps * 1e3
 
 
 def main():
@@ -109,30 +180,23 @@ def main():
     targets = torch.from_numpy(np.concatenate([t.reshape(-1) for t in wl.targets])).to(dev)
     P = views.n_pixels
 
+    if args.copy_probe_mib:
+        # a plain elementwise copy of known size: reads and writes n bytes
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.rand(n, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+
     # ---------------- batched (headline) ----------------
-    step = BatchedStep(g, views, targets)
+    step = BatchedStep(g, views, targets, use_graph=not args.no_graph)
     tuned = autotune.tune(step, force=args.retune)
     print(f"[bench] tuned: {tuned}", file=sys.stderr, flush=True)
-    step.capture()
-    for _ in range(args.warmup):
-        step.step()
-    torch.cuda.synchronize()
-    if step.overflowed():
-        raise RuntimeError("key capacity overflow during warm-up")
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        step.step()
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_batched = e0.elapsed_time(e1) / args.steps
-    if step.overflowed():
-        raise RuntimeError("key capacity overflow during timing")
+    ms_batched, wall_ms = _time_batched(step, args.steps, args.warmup)
     n_keys = step.key_count()
-    print(f"[bench] batched: {ms_batched:.3f} ms/step ({wall / args.steps * 1e3:.3f} ms wall), "
+    print(f"[bench] batched: {ms_batched:.3f} ms/step ({wall_ms:.3f} ms wall), "
           f"{n_keys} keys", file=sys.stderr, flush=True)
 
     # ---------------- per-kernel durations (HIP events on the launch stream) ---------
@@ -161,6 +225,21 @@ def main():
 
     # algorithmic work of the reverse tile walk: list positions each pixel walks
     pairs_bwd = int(step.n_contrib.to(torch.int64).sum().item())
+    del step
+    torch.cuda.empty_cache()
+
+    # ---------------- paper-shaped batch: 8 window + 4 past views ----------------
+    v12 = None
+    if not args.no_v12 and len(wl.cams) > 12:
+        views12 = gs.Views(wl.cams[:12], dev)
+        t12 = targets[:3 * views12.n_pixels]
+        step12 = BatchedStep(g, views12, t12, use_graph=not args.no_graph)
+        ms12, _ = _time_batched(step12, args.steps, args.warmup)
+        v12 = {"views": 12, "ms_per_step": ms12,
+               "value": views12.n_pixels / (ms12 * 1e-3) / 1e6, "unit": "Mpix/s"}
+        print(f"[bench] 12 views: {ms12:.3f} ms/step", file=sys.stderr, flush=True)
+        del step12
+        torch.cuda.empty_cache()
 
     # ---------------- plain per-view reference ----------------
     ms_plain = None
@@ -183,37 +262,47 @@ def main():
     mpix = P / (ms_batched * 1e-3) / 1e6
     mpix_plain = P / (ms_plain * 1e-3) / 1e6 if ms_plain else None
 
+    # ---------------- CPU oracle baseline ----------------
+    cpu, blend_frac = None, DEFAULT_BLEND_FRACTION
+    if not args.no_cpu_baseline:
+        mp, nv, px, dt, thr, blend_frac = _cpu_baseline(wl, args.cpu_seconds)
+        cpu = {"value": mp, "unit": "Mpix/s", "cores": thr, "kind": "oracle",
+               "sample": f"fwd+bwd of {nv} whole {wl.cams[0].width}x{wl.cams[0].height} views "
+                         f"({px} px; projection, compositing and backward of all {wl.gmap.n} "
+                         f"Gaussians per view) in {dt:.1f} s"}
+        print(f"[bench] cpu oracle: {mp:.5f} Mpix/s over {dt:.1f}s; blended fraction "
+              f"{blend_frac:.3f}", file=sys.stderr, flush=True)
+
     # ---------------- roofline of the dominant kernel ----------------
     dom = max(kms, key=kms.get)
-    ops_per_pair_bwd = float(os.environ.get("GSMI_BWD_VALU_PER_PAIR", "48"))
-    if dom == "render_bwd":
-        achieved = pairs_bwd * ops_per_pair_bwd * 64 / 64 / (kms[dom] * 1e-3) / 1e12
-        roof = {"kernel": "render_bwd", "bound": "alu", "achieved": achieved,
-                "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                "traffic": None, "units": pairs_bwd, "per_unit": ops_per_pair_bwd,
-                "kernel_ms": kms[dom]}
-    elif dom == "render_fwd":
-        achieved = pairs_bwd * 20.0 / (kms[dom] * 1e-3) / 1e12
-        roof = {"kernel": "render_fwd", "bound": "alu", "achieved": achieved,
-                "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                "traffic": None, "units": pairs_bwd, "per_unit": 20.0, "kernel_ms": kms[dom]}
+    bwd_per_pair = BWD_VALU_EVAL + BWD_VALU_BLEND * blend_frac
+    fwd_per_pair = FWD_VALU_EVAL + FWD_VALU_BLEND * blend_frac
+    if dom in ("render_bwd", "render_fwd"):
+        per = bwd_per_pair if dom == "render_bwd" else fwd_per_pair
+        achieved = pairs_bwd * per / (kms[dom] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                "unit": "T VALU lane-ops/s", "frac": achieved / VALU_PEAK_TOPS,
+                "traffic": _traffic() if dom == "render_bwd" else None,
+                "units": pairs_bwd, "unit_name": "walked (pixel, splat) pairs",
+                "per_unit": per, "blend_fraction": blend_frac, "kernel_ms": kms[dom]}
     else:
         K = (wl.gmap.sh_degree + 1) ** 2
         per_gauss = 4 * (3 + 3 + 4 + 1 + 3 * K)
-        nbytes = g.n * (2 * per_gauss) + g.n * len(wl.cams) * (9 * 4 + 4 * 4)
+        nbytes = g.n * per_gauss + g.n * len(wl.cams) * (2 + 4 + 4 + 1) * 4
         achieved = nbytes / (kms[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "kernel_ms": kms[dom]}
 
-    # ---------------- CPU oracle baseline ----------------
-    cpu = None
-    if not args.no_cpu_baseline:
-        mp, px, dt, thr = _cpu_baseline(wl)
-        cpu = {"value": mp, "unit": "Mpix/s", "cores": thr, "kind": "oracle",
-               "sample": f"fwd+bwd of {px} px (400 random 16x16 tiles of view 0) incl. projection "
-                         f"and its backward for all {wl.gmap.n} Gaussians; {dt:.1f} s"}
-        print(f"[bench] cpu oracle: {mp:.5f} Mpix/s over {dt:.1f}s", file=sys.stderr, flush=True)
+    # HBM-bound stages: algorithmic bytes per launch / event-timed duration
+    K = (wl.gmap.sh_degree + 1) ** 2
+    pre_bytes = g.n * 4 * (3 + 3 + 4 + 1 + 3 * K) + g.n * len(wl.cams) * (8 + 16 + 16 + 4)
+    key_bits = max(1, math.ceil(math.log2(max(views.n_tiles, 2)))) + 32
+    passes = math.ceil(key_bits / 8)
+    sort_bytes = n_keys * 12 + n_keys * 24 * passes
+    hbm = {name: {"bytes": b, "ms": kms[name], "GB/s": b / (kms[name] * 1e-3) / 1e9,
+                  "frac": b / (kms[name] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+           for name, b in (("preprocess", pre_bytes), ("bin_sort", sort_bytes))}
 
     out = {
         "metric": "fwd+bwd Mpix/s at 640x480, 200k Gaussians; batched vs plain, same accuracy",
@@ -222,14 +311,17 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "gaussians": wl.gmap.n, "views": len(wl.cams),
                    "image_sizes": sorted(set(views.sizes)), "pixels_per_step": P,
-                   "sh_degree": wl.gmap.sh_degree, "step": "fwd+bwd+adam, one HIP graph",
+                   "sh_degree": wl.gmap.sh_degree,
+                   "step": "fwd+bwd+adam, " + ("eager launches" if args.no_graph else "one HIP graph"),
                    "keys": n_keys, "parallelism": "single GPU"},
         "plain": {"value": mpix_plain, "ms_per_step": ms_plain,
                   "speedup_batched_over_plain": (mpix / mpix_plain) if mpix_plain else None},
+        "paper_shaped_12_views": v12,
         "kernel_ms": kms,
         "tuning": {"fwd_pixels_per_lane": tuned["fwd_ppl"], "bwd_pixels_per_lane": tuned["bwd_ppl"],
                    "table_ms": tuned.get("table")},
         "roofline": roof,
+        "hbm_kernels": hbm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -382,7 +382,9 @@ def composite(rows: torch.Tensor, depth: torch.Tensor, vals: np.ndarray, ranges:
     exactly, as for render_splats).
     tiles: optional per-view collections of (ty, tx) to composite; pixels of
     other tiles are left NaN (image, T_final, depth) / -1 (n_contrib).
-    Returns per-view lists: image (3,H,W), T_final, n_contrib, depth, mask."""
+    Returns per-view lists: image (3,H,W), T_final, n_contrib (list position
+    of the last blended splat), n_blended (number of splats blended), depth,
+    mask."""
     bg_t = _t(bg)
     out = []
     for vi, cam in enumerate(cams):
@@ -392,6 +394,7 @@ def composite(rows: torch.Tensor, depth: torch.Tensor, vals: np.ndarray, ranges:
         img = np.full((3, H, W), fill)
         Tf = np.full((H, W), np.nan if tiles is not None else 1.0)
         nc = np.full((H, W), -1 if tiles is not None else 0, np.int64)
+        nu = np.full((H, W), -1 if tiles is not None else 0, np.int64)
         dimg = np.full((H, W), fill)
         msk = np.zeros((H, W), bool)
         g = None if dL_dimage is None else _t(dL_dimage[vi])
@@ -406,7 +409,7 @@ def composite(rows: torch.Tensor, depth: torch.Tensor, vals: np.ndarray, ranges:
                 idx = torch.as_tensor(vals[s0:s1].astype(np.int64))
                 S = rows.index_select(0, idx) if s1 > s0 else rows[:0]
                 dep = depth.index_select(0, idx).detach() if s1 > s0 else depth[:0].detach()
-                C, T_fin, last, _, mask, dsum = _composite_tile(
+                C, T_fin, last, w, mask, dsum = _composite_tile(
                     xx.to(DT) + 0.5, yy.to(DT) + 0.5, S, bg_t, with_mask, dep, depth_band)
                 if g is not None and rows.requires_grad and s1 > s0:
                     gC = g[:, yy, xx].T
@@ -414,12 +417,13 @@ def composite(rows: torch.Tensor, depth: torch.Tensor, vals: np.ndarray, ranges:
                 img[:, yy.numpy(), xx.numpy()] = C.detach().numpy().T
                 Tf[yy.numpy(), xx.numpy()] = T_fin.detach().numpy()
                 nc[yy.numpy(), xx.numpy()] = last.numpy()
+                nu[yy.numpy(), xx.numpy()] = (w.detach() > 0).sum(dim=1).numpy()
                 dimg[yy.numpy(), xx.numpy()] = dsum.detach().numpy()
                 m = mask.numpy()
                 if pixel_mask is not None:
                     m = m | pixel_mask[vi][yy.numpy(), xx.numpy()]
                 msk[yy.numpy(), xx.numpy()] = m
-        out.append(dict(image=img, T_final=Tf, n_contrib=nc, depth=dimg, mask=msk))
+        out.append(dict(image=img, T_final=Tf, n_contrib=nc, n_blended=nu, depth=dimg, mask=msk))
     return out
 
 
