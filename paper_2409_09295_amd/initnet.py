@@ -6,7 +6,7 @@ Sec. III-A1) reduced by belief propagation (Sec. III-A2).  This module holds
 
 * ``plain_depth``: the cost volume of Eq. 1 at 1/4 resolution, reduced by
   winner-take-all (``gs_cost_volume_wta``), upsampled 4x by repetition: the
-  fallback initialiser and the reference the learned one is judged against;
+  fallback initialiser and the reference the learned one is measured against;
 * ``UNet``: a 4-level U-Net (32/64/128/256 channels, two 3x3 conv + ReLU per
   level, 2x2 average pooling, nearest upsampling with skip concatenation, a
   1x1 head) that maps one RGB keyframe to per-pixel log depth and log scale.
@@ -311,12 +311,12 @@ class InitReport:
     conv_tflops: float
 
 
-def train_and_judge(n_gauss: int = 200000, W: int = 128, H: int = 96, n_train: int = 600,
+def train_and_compare(n_gauss: int = 200000, W: int = 128, H: int = 96, n_train: int = 600,
                     n_heldout: int = 12, window: int = 8, epochs: int = 15, batch: int = 8,
                     lr: float = 2e-3, seed: int = 0, device="cuda", log=None) -> Tuple[UNet, InitReport]:
     """Renders a procedural room, trains the U-Net on (render, depth) pairs and
     compares its depth AbsRel with the plain initialiser's on held-out
-    trajectory views (each judged with the `window` preceding keyframes)."""
+    trajectory views (each with the `window` preceding keyframes as its window)."""
     gmap, boxes = scenes.procedural_room(n_gauss, seed)
     train_cams = trajectory_cams(n_train, seed + 101, boxes, W, H)
     test_cams = trajectory_cams(n_heldout + window, seed + 202, boxes, W, H)

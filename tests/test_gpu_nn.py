@@ -1,4 +1,4 @@
-"""Initialiser kernels vs the FP64 oracle (needs an MI355X), and the judge of
+"""Initialiser kernels vs the FP64 oracle (needs an MI355X), and the comparison of
 the learned initialiser against the plain one."""
 import numpy as np
 import pytest
@@ -218,7 +218,7 @@ def test_learned_initialiser_beats_plain(gs):
     views is no worse than the plain (cost volume + winner-take-all)
     initialiser's."""
     from paper_2409_09295_amd import initnet
-    net, rep = initnet.train_and_judge(log=lambda m: print(m, flush=True))
+    net, rep = initnet.train_and_compare(log=lambda m: print(m, flush=True))
     print(rep, flush=True)
     assert np.isfinite(rep.final_loss)
     assert rep.net_absrel <= rep.plain_absrel, rep
