@@ -75,7 +75,7 @@ def _args():
                     help="run a float32 copy of this size first (scales HBM counters)")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch the step eagerly instead of replaying a HIP graph (profiling)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate length of the CPU oracle sample")
     return ap.parse_args()
 
@@ -87,7 +87,7 @@ def _build(spec, seed):
     return scenes.config_metric(seed, n=spec["n"], n_views=spec["views"])
 
 
-def _cpu_baseline(wl, budget_s=12.0, max_views=4, seed=0):
+def _cpu_baseline(wl, budget_s=15.0, max_views=32, seed=0):
     """The FP64 oracle, as it stands, on a bounded sample of the same step:
     projection of all Gaussians, compositing of every pixel and the full
     backward (pixels -> 2D -> 3D parameters and pose) of whole views, taken
@@ -98,7 +98,7 @@ def _cpu_baseline(wl, budget_s=12.0, max_views=4, seed=0):
     from oracle import gs_oracle as O
     rng = np.random.default_rng(seed)
     px, dt, walked, blended, nv = 0, 0.0, 0, 0, 0
-    while nv < min(max_views, len(wl.cams)) and dt < budget_s * 0.6:
+    while nv < min(max_views, len(wl.cams)) and dt < budget_s:
         cam = wl.cams[nv].as_float32()
         dl = rng.normal(size=(3, cam.height, cam.width))
         t0 = time.perf_counter()

@@ -173,7 +173,8 @@ enum {
 const char* gs_status_string(int status);
 /* Text of the last GS_ERR_* raised on this thread (static per-thread buffer). */
 const char* gs_last_error(void);
-/* Library version string. */
+/* Library version string, ending in a hash of the sources it was built from
+ * (static string). */
 const char* gs_version(void);
 
 /* Kernel configuration keys for gs_set_tuning(). */

@@ -153,7 +153,10 @@ const char* gs_status_string(int status) {
 
 const char* gs_last_error(void) { return g_last_error; }
 
-const char* gs_version(void) { return "gsmi 0.1 (gfx950)"; }
+#ifndef GSMI_SOURCE_ID
+#define GSMI_SOURCE_ID "unknown"
+#endif
+const char* gs_version(void) { return "gsmi 0.1 (gfx950) src " GSMI_SOURCE_ID; }
 
 int gs_set_kernel_events(int kernel, void* start_event, void* stop_event) {
   if (kernel < 0 || kernel >= GS_KERNEL_COUNT) return invalid("unknown kernel id %d", kernel);

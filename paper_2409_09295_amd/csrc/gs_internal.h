@@ -86,9 +86,68 @@ __device__ __forceinline__ bool tile_rect(float uf, float vf, int32_t r, int32_t
 // a = -log2(e)/2 Q00, b = -log2(e) Q01, c = -log2(e)/2 Q11, i.e. p2 = log2(e) * power.
 struct StagedSplat {
   float4 geo;   // u, v, a, b
-  float4 app;   // c, opacity, depth, (unused)
-  float4 col;   // r, g, b, (value index as bits)
+  float4 app;   // c, opacity, depth, (forward: quadrant mask bits; backward: accumulator index)
+  float4 col;   // r, g, b, (forward: value index; backward: quadrant mask bits)
 };
+
+// Minimum over the box [x0, x1] x [y0, y1] of f(x, y) = a x^2 + 2 b x y + c y^2
+// (a, c > 0, ac > b^2): 0 if the box holds the origin, otherwise attained on
+// an edge, where f is a convex parabola minimised at the clamped vertex.
+__device__ __forceinline__ float quad_box_min(float a, float b, float c, float x0, float x1,
+                                              float y0, float y1) {
+  if (x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f) return 0.f;
+  // approximate reciprocals only move the clamped vertex by a relative
+  // 1e-7, which raises f there by a negligible second-order amount
+  const float ia = __builtin_amdgcn_rcpf(a), ic = __builtin_amdgcn_rcpf(c);
+  float best = INFINITY;
+  const float ys[2] = {y0, y1}, xs[2] = {x0, x1};
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const float y = ys[k];
+    const float x = fminf(fmaxf(-b * y * ia, x0), x1);
+    best = fminf(best, a * x * x + 2.0f * b * x * y + c * y * y);
+    const float xe = xs[k];
+    const float ye = fminf(fmaxf(-b * xe * ic, y0), y1);
+    best = fminf(best, a * xe * xe + 2.0f * b * xe * ye + c * ye * ye);
+  }
+  return best;
+}
+
+// Which 8x8 quadrants of the tile whose top-left pixel is (tx0, ty0) a splat
+// can reach: bit q (quadrant x offset 8 (q & 1), y offset 8 (q >> 1)) is
+// clear only if at every pixel centre of the quadrant the splat's alpha is
+// below 1/255 with a margin that covers the float32 rounding of the
+// per-pixel evaluation, so a pixel of a clear quadrant would skip the splat
+// anyway and skipping it for the whole quadrant changes no result.
+// alpha >= 1/255 needs o e^(-m/2) >= 1/255 with m = d^T Q d, i.e.
+// m <= 2 ln(255 o); the box minimum of m decides.
+__device__ __forceinline__ uint32_t quadrant_mask(float u, float v, float q00, float q01,
+                                                  float q11, float o, int tx0, int ty0, int W,
+                                                  int H) {
+  if (!(o * 255.0f >= 1.0f - 1e-4f)) return 0u;
+  const float lvl = 2.0f * __logf(fmaxf(o * 255.0f, 1.0f));
+  uint32_t mask = 0u;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int px0 = tx0 + 8 * (q & 1), py0 = ty0 + 8 * (q >> 1);
+    if (px0 >= W || py0 >= H) continue;
+    const float x0 = (float)px0 + 0.5f - u, x1 = (float)min(px0 + 7, W - 1) + 0.5f - u;
+    const float y0 = (float)py0 + 0.5f - v, y1 = (float)min(py0 + 7, H - 1) + 0.5f - v;
+    const float m = quad_box_min(q00, q01, q11, x0, x1, y0, y1);
+    const float dx = fmaxf(fabsf(x0), fabsf(x1)), dy = fmaxf(fabsf(y0), fabsf(y1));
+    const float terms = q00 * dx * dx + 2.0f * fabsf(q01) * dx * dy + q11 * dy * dy;
+    const float margin = 1e-4f * lvl + 1e-5f * terms + 1e-5f;
+    if (!(m > lvl + margin)) mask |= 1u << q;
+  }
+  return mask;
+}
+
+// Wave-uniform 64-bit value (a mask read by every lane from the same LDS word).
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
 
 // Blending decision shared bit-for-bit by the forward and backward kernels:
 // returns false if the splat is skipped at this pixel (power > 0 or

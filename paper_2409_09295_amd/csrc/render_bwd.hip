@@ -95,18 +95,21 @@ __device__ __forceinline__ Reduced9 wave_reduce9(float v0, float v1, float v2, f
 // Stages splat `g` (index view * n + Gaussian into the [V][n] splat arrays)
 // and the index Gaussian * V + view of its accumulator in the Gaussian-major
 // [n][V][9] screen-space gradient buffer.
-__device__ __forceinline__ void stage_splat(uint32_t g, uint32_t n, uint32_t n_views,
-                                            const float2* __restrict__ xy,
-                                            const float4* __restrict__ co,
-                                            const float4* __restrict__ rd, StagedSplat& out) {
+__device__ __forceinline__ uint32_t stage_splat(uint32_t g, uint32_t n, uint32_t n_views,
+                                                const float2* __restrict__ xy,
+                                                const float4* __restrict__ co,
+                                                const float4* __restrict__ rd, int tx0, int ty0,
+                                                int W, int H, StagedSplat& out) {
   const float2 m = xy[g];
   const float4 c = co[g];
   const float4 r = rd[g];
   const uint32_t view = g / n;
   const uint32_t acc = (g - view * n) * n_views + view;
+  const uint32_t reach = quadrant_mask(m.x, m.y, c.x, c.y, c.z, c.w, tx0, ty0, W, H);
   out.geo = make_float4(m.x, m.y, -0.5f * kLog2e * c.x, -kLog2e * c.y);
   out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.w, __uint_as_float(acc));
-  out.col = make_float4(r.x, r.y, r.z, __uint_as_float(g));
+  out.col = make_float4(r.x, r.y, r.z, __uint_as_float(reach));
+  return reach;
 }
 
 template <int PPL>
@@ -116,7 +119,10 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     float3 bg, const float* __restrict__ dL_dimage, const float* __restrict__ final_T,
     const uint32_t* __restrict__ n_contrib, uint32_t n_gauss, float* __restrict__ grad2d) {
   constexpr int NT = kBlock / PPL;
+  constexpr int kWords = kBlock / 64;
   __shared__ StagedSplat s_splat[kBlock];
+  // s_reach[q][w] bit b: staged splat 64 w + b can reach quadrant q
+  __shared__ uint64_t s_reach[4][kWords];
   __shared__ uint32_t s_maxlast;
   const int tile = blockIdx.x;
   const int v = find_view(vt, tile);
@@ -135,7 +141,7 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
   const float red_scale1 = (row == 0) ? -0.5f : 1.0f;
 
   float fpx[PPL], fpy[PPL], T[PPL], dC0[PPL], dC1[PPL], dC2[PPL], S0[PPL], S1[PPL], S2[PPL];
-  uint32_t last[PPL];
+  uint32_t last[PPL], qbit[PPL];
   uint32_t mylast = 0;
   const int64_t plane = (int64_t)vi.width * vi.height;
   const float* gimg = dL_dimage + 3 * vi.pix_base;
@@ -145,6 +151,7 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     const int q = i >> 6, l = i & 63;
     const int px = tx * kTile + (q & 1) * 8 + (l & 7);
     const int py = ty * kTile + (q >> 1) * 8 + (l >> 3);
+    qbit[k] = __builtin_amdgcn_readfirstlane(1u << q);   // uniform over the wave
     fpx[k] = (float)px + 0.5f;
     fpy[k] = (float)py + 0.5f;
     T[k] = 1.0f;
@@ -163,9 +170,14 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
       mylast = max(mylast, last[k]);
     }
   }
+  // list positions this wave has to walk: below the largest n_contrib of its pixels
+  uint32_t wave_last = mylast;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, d, 64));
+  wave_last = __builtin_amdgcn_readfirstlane(wave_last);
   if (threadIdx.x == 0) s_maxlast = 0;
   __syncthreads();
-  if (mylast) atomicMax(&s_maxlast, mylast);
+  if (lane == 0 && wave_last) atomicMax(&s_maxlast, wave_last);
   __syncthreads();
   const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
   // n_contrib never exceeds the tile's list length for a matching forward;
@@ -180,54 +192,75 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     for (int r = 0; r < PPL; ++r) {
       const int slot = r * NT + (int)threadIdx.x;
       const int64_t k = bstart + slot;
+      uint32_t reach = 0;
       if (k < bend)
-        stage_splat(values[s + (uint32_t)k], n_gauss, (uint32_t)vt.n_views, xy, co, rd,
-                    s_splat[slot]);
+        reach = stage_splat(values[s + (uint32_t)k], n_gauss, (uint32_t)vt.n_views, xy, co, rd,
+                            tx * kTile, ty * kTile, vi.width, vi.height, s_splat[slot]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t bq = __ballot((reach >> q) & 1u);
+        if (lane == 0) s_reach[q][slot >> 6] = bq;
+      }
     }
     __syncthreads();
-    for (int j = (int)(bend - bstart) - 1; j >= 0; --j) {
-      const uint32_t pos = (uint32_t)(bstart + j);
-      float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, g4 = 0.f, g5 = 0.f, g6 = 0.f, g7 = 0.f,
-            g8 = 0.f;
-      bool contrib = false;
-      const float4 geo = s_splat[j].geo;
-      const float4 app = s_splat[j].app;
-      const float4 col = s_splat[j].col;
+    // Walk, in reverse list order, only the staged splats below this wave's
+    // last blended position that reach one of its quadrants.
+    for (int w = kWords - 1; w >= 0; --w) {
+      const int64_t lim = (int64_t)wave_last - bstart - 64 * w;   // allowed bits: b < lim
+      if (lim <= 0) continue;
+      uint64_t m = 0;
 #pragma unroll
-      for (int k = 0; k < PPL; ++k) {
-        if (pos >= last[k]) continue;
-        float alpha, raw, G, dx, dy;
-        if (!eval_alpha(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy)) continue;
-        contrib = true;
-        const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
-        const float wgt = alpha * Tk;
-        g6 += wgt * dC0[k];
-        g7 += wgt * dC1[k];
-        g8 += wgt * dC2[k];
-        const float dalpha =
-            Tk * ((col.x - S0[k]) * dC0[k] + (col.y - S1[k]) * dC1[k] + (col.z - S2[k]) * dC2[k]);
-        S0[k] = alpha * col.x + (1.0f - alpha) * S0[k];
-        S1[k] = alpha * col.y + (1.0f - alpha) * S1[k];
-        S2[k] = alpha * col.z + (1.0f - alpha) * S2[k];
-        T[k] = Tk;
-        // below the 0.99 clamp alpha = o G: d alpha/do = G, d alpha/dpower = alpha
-        const float live = raw <= kAlphaMax ? dalpha : 0.0f;
-        g5 += G * live;
-        const float gP = alpha * live;   // dL/dpower
-        const float gdx = gP * dx, gdy = gP * dy;
-        g0 += 2.0f * geo.z * gdx + geo.w * gdy;
-        g1 += geo.w * gdx + 2.0f * app.x * gdy;
-        g2 += gdx * dx;
-        g3 += gdx * dy;
-        g4 += gdy * dy;
-      }
-      if (__ballot(contrib)) {
-        const Reduced9 r = wave_reduce9(g0, g1, g2, g3, g4, g5, g6, g7, g8);
-        if ((lane & 15) == 0) {
-          const int64_t base = (int64_t)__float_as_uint(app.w) * 9;
-          unsafeAtomicAdd(&grad2d[base + red_off0], r.q0 * red_scale0);
-          unsafeAtomicAdd(&grad2d[base + red_off0 + 4], r.q1 * red_scale1);
-          if (lane == 0) unsafeAtomicAdd(&grad2d[base + 8], r.q2);
+      for (int k = 0; k < PPL; ++k) m |= s_reach[__builtin_ctz(qbit[k])][w];
+      m = uniform_u64(m);
+      if (lim < 64) m &= (uint64_t(1) << lim) - 1;
+      while (m) {
+        const int bit = 63 - __builtin_clzll(m);
+        m &= ~(uint64_t(1) << bit);
+        const int j = 64 * w + bit;
+        const uint32_t pos = (uint32_t)(bstart + j);
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, g4 = 0.f, g5 = 0.f, g6 = 0.f, g7 = 0.f,
+              g8 = 0.f;
+        bool contrib = false;
+        const float4 geo = s_splat[j].geo;
+        const float4 app = s_splat[j].app;
+        const float4 col = s_splat[j].col;
+        const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(col.w)) : ~0u;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+          if (pos >= last[k] || !(reach & qbit[k])) continue;
+          float alpha, raw, G, dx, dy;
+          if (!eval_alpha(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy)) continue;
+          contrib = true;
+          const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
+          const float wgt = alpha * Tk;
+          g6 += wgt * dC0[k];
+          g7 += wgt * dC1[k];
+          g8 += wgt * dC2[k];
+          const float dalpha = Tk * ((col.x - S0[k]) * dC0[k] + (col.y - S1[k]) * dC1[k] +
+                                     (col.z - S2[k]) * dC2[k]);
+          S0[k] = alpha * col.x + (1.0f - alpha) * S0[k];
+          S1[k] = alpha * col.y + (1.0f - alpha) * S1[k];
+          S2[k] = alpha * col.z + (1.0f - alpha) * S2[k];
+          T[k] = Tk;
+          // below the 0.99 clamp alpha = o G: d alpha/do = G, d alpha/dpower = alpha
+          const float live = raw <= kAlphaMax ? dalpha : 0.0f;
+          g5 += G * live;
+          const float gP = alpha * live;   // dL/dpower
+          const float gdx = gP * dx, gdy = gP * dy;
+          g0 += 2.0f * geo.z * gdx + geo.w * gdy;
+          g1 += geo.w * gdx + 2.0f * app.x * gdy;
+          g2 += gdx * dx;
+          g3 += gdx * dy;
+          g4 += gdy * dy;
+        }
+        if (__ballot(contrib)) {
+          const Reduced9 r = wave_reduce9(g0, g1, g2, g3, g4, g5, g6, g7, g8);
+          if ((lane & 15) == 0) {
+            const int64_t base = (int64_t)__float_as_uint(app.w) * 9;
+            unsafeAtomicAdd(&grad2d[base + red_off0], r.q0 * red_scale0);
+            unsafeAtomicAdd(&grad2d[base + red_off0 + 4], r.q1 * red_scale1);
+            if (lane == 0) unsafeAtomicAdd(&grad2d[base + 8], r.q2);
+          }
         }
       }
     }

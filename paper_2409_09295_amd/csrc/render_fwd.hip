@@ -16,15 +16,19 @@ namespace gsmi {
 
 namespace {
 
-__device__ __forceinline__ void stage_splat(uint32_t g, const float2* __restrict__ xy,
-                                            const float4* __restrict__ co,
-                                            const float4* __restrict__ rd, StagedSplat& out) {
+// Stages splat g and returns the quadrants of the tile it can reach.
+__device__ __forceinline__ uint32_t stage_splat(uint32_t g, const float2* __restrict__ xy,
+                                                const float4* __restrict__ co,
+                                                const float4* __restrict__ rd, int tx0, int ty0,
+                                                int W, int H, StagedSplat& out) {
   const float2 m = xy[g];
   const float4 c = co[g];
   const float4 r = rd[g];
+  const uint32_t reach = quadrant_mask(m.x, m.y, c.x, c.y, c.z, c.w, tx0, ty0, W, H);
   out.geo = make_float4(m.x, m.y, -0.5f * kLog2e * c.x, -kLog2e * c.y);
-  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.w, 0.0f);
+  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.w, __uint_as_float(reach));
   out.col = make_float4(r.x, r.y, r.z, __uint_as_float(g));
+  return reach;
 }
 
 template <int PPL>
@@ -34,14 +38,19 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
     float3 bg, float* __restrict__ image, float* __restrict__ final_T,
     uint32_t* __restrict__ n_contrib, float* __restrict__ depth_out) {
   constexpr int NT = kBlock / PPL;
+  constexpr int kWords = kBlock / 64;
   __shared__ StagedSplat s_splat[kBlock];
+  // s_reach[q][w] bit b: staged splat 64 w + b can reach quadrant q
+  __shared__ uint64_t s_reach[4][kWords];
   const int tile = blockIdx.x;
   const int v = find_view(vt, tile);
   const ViewInfo& vi = vt.v[v];
   const int lt = tile - vi.tile_base;
   const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
+  const int lane = threadIdx.x & 63;
 
   int px[PPL], py[PPL];
+  uint32_t qbit[PPL];   // quadrant bit of each of the lane's pixels (wave-uniform)
   float fpx[PPL], fpy[PPL], T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL];
   uint32_t last[PPL];
   bool inside[PPL], done[PPL];
@@ -51,6 +60,7 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
     const int q = i >> 6, l = i & 63;
     px[k] = tx * kTile + (q & 1) * 8 + (l & 7);
     py[k] = ty * kTile + (q >> 1) * 8 + (l >> 3);
+    qbit[k] = __builtin_amdgcn_readfirstlane(1u << q);
     inside[k] = px[k] < vi.width && py[k] < vi.height;
     done[k] = !inside[k];
     fpx[k] = (float)px[k] + 0.5f;
@@ -70,18 +80,35 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
     for (int r = 0; r < PPL; ++r) {
       const int slot = r * NT + (int)threadIdx.x;
       const int64_t idx = b + slot;
-      if (idx < (int64_t)e) stage_splat(values[idx], xy, co, rd, s_splat[slot]);
+      uint32_t reach = 0;
+      if (idx < (int64_t)e)
+        reach = stage_splat(values[idx], xy, co, rd, tx * kTile, ty * kTile, vi.width,
+                            vi.height, s_splat[slot]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint64_t bq = __ballot((reach >> q) & 1u);
+        if (lane == 0) s_reach[q][slot >> 6] = bq;
+      }
     }
     __syncthreads();
-    const int cnt = (int)min((int64_t)kBlock, (int64_t)e - b);
-    if (!all_done) {
-      for (int j = 0; j < cnt; ++j) {
+    // Walk, in list order, only the staged splats that reach one of this
+    // wave's quadrants; stop once every pixel of the wave has terminated.
+    if (__all(all_done)) continue;
+    for (int w = 0; w < kWords; ++w) {
+      uint64_t m = 0;
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) m |= s_reach[__builtin_ctz(qbit[k])][w];
+      m = uniform_u64(m);
+      while (m) {
+        const int j = 64 * w + __builtin_ctzll(m);
+        m &= m - 1;
         const float4 geo = s_splat[j].geo;
         const float4 app = s_splat[j].app;
         const float4 col = s_splat[j].col;
+        const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(app.w)) : ~0u;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-          if (done[k]) continue;
+          if (done[k] || !(reach & qbit[k])) continue;
           float alpha, raw, G, dx, dy;
           if (!eval_alpha(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy)) continue;
           const float Tn = T[k] * (1.0f - alpha);
@@ -97,6 +124,10 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
           T[k] = Tn;
           last[k] = (uint32_t)(b - (int64_t)s) + (uint32_t)j + 1;
         }
+        bool live = false;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) live = live || !done[k];
+        if (!__any(live)) m = 0;   // every pixel of the wave has terminated
       }
     }
   }
