@@ -65,6 +65,30 @@ def test_bin_sort_bit_exact(gs, case, sync):
     np.testing.assert_array_equal(u32(bins2.values)[:got_n], u32(bins.values)[:got_n])
 
 
+@pytest.mark.parametrize("n", [700, 3000])
+def test_bin_sort_crowded_tiles(gs, n):
+    """Every splat covers the same few tiles: per-tile lists of n keys (above
+    and below the in-LDS limit of the per-tile depth sort), a third of them
+    at repeated depths so that ties fall back to the Gaussian index."""
+    cams = [scenes.pinhole(48, 40, 40.0)]
+    sp = scenes.random_splats(n, cams, seed=33, depth_ties=0.35, cull_frac=0.02)
+    rng = np.random.default_rng(34)
+    sp.xy[0, :, 0] = rng.uniform(14.0, 18.0, n)
+    sp.xy[0, :, 1] = rng.uniform(14.0, 18.0, n)
+    sp.radius[0] = np.where(sp.radius[0] > 0, rng.integers(1, 6, n), 0).astype(np.int32)
+    keys, vals, ranges, _, _ = O.bin_splats([sp.xy[0]], [sp.rgb_depth[0, :, 3]], [sp.radius[0]],
+                                            cams, 16)
+    longest = int((ranges[:, 1] - ranges[:, 0]).max())
+    _log(f"crowded tiles n={n}: {len(keys)} keys, longest list {longest}")
+    for sync in (True, False):
+        views, proj, bins, nk = _gpu_bins(gs, sp, cams, sync=sync)
+        got_n = int(u32(bins.n_keys)[0])
+        assert got_n == len(keys)
+        np.testing.assert_array_equal(u64(bins.keys)[:got_n], keys)
+        np.testing.assert_array_equal(u32(bins.values)[:got_n], vals)
+        np.testing.assert_array_equal(u32(bins.ranges), ranges)
+
+
 def test_bin_sort_all_culled(gs):
     cams = [scenes.pinhole(64, 48, 60.0)]
     sp = scenes.random_splats(500, cams, seed=2)
