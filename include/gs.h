@@ -276,6 +276,28 @@ int gs_adam_step_dev(float* p, const float* g, float* m, float* v, int64_t n, fl
                      const uint8_t* mask, const uint32_t* guard_n_keys, int64_t guard_capacity,
                      gs_stream_t stream);
 
+/* One parameter group of gs_adam_step_groups_dev (device pointers). */
+typedef struct gs_adam_group {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t n;
+  float lr;
+} gs_adam_group;
+
+#define GS_ADAM_MAX_GROUPS 8
+
+/* gs_adam_step_dev over up to GS_ADAM_MAX_GROUPS parameter groups (each with
+ * its own learning rate and n >= 0, no mask) in a single launch, followed by
+ * the commit of *step_dev.  groups is a host array read during the call.
+ * Results are identical to one gs_adam_step_dev call per group with the
+ * last one committing. */
+int gs_adam_step_groups_dev(const gs_adam_group* groups, int32_t n_groups, float beta1,
+                            float beta2, float eps, int32_t* step_dev,
+                            const uint32_t* guard_n_keys, int64_t guard_capacity,
+                            gs_stream_t stream);
+
 /* L1 photometric loss L = sum over views of mean |C - C*| over 3 H W, and
  * dL/dC = sign(C - C*) / (3 H W) (sign(0) = 0), for every view (layouts of
  * image).  loss (optional, device float64 [1]) is overwritten with L. */

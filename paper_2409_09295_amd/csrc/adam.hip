@@ -12,12 +12,15 @@ struct AdamCoef {
   float lr, b1, b2, eps, inv_bc1, inv_bc2;
 };
 
+// Written with explicit fused multiply-adds so that every kernel that uses
+// it rounds identically, whatever contraction the compiler would choose.
 __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, const AdamCoef& c) {
-  m = c.b1 * m + (1.0f - c.b1) * g;
-  v = c.b2 * v + (1.0f - c.b2) * g * g;
+  m = __builtin_fmaf(c.b1, m, (1.0f - c.b1) * g);
+  v = __builtin_fmaf(c.b2, v, ((1.0f - c.b2) * g) * g);
   const float mhat = m * c.inv_bc1;
   const float vhat = v * c.inv_bc2;
-  p -= c.lr * mhat / (sqrtf(vhat) + c.eps);
+  const float step = mhat / (__builtin_sqrtf(vhat) + c.eps);
+  p = __builtin_fmaf(-c.lr, step, p);
 }
 
 __global__ __launch_bounds__(256) void adam_vec4_kernel(float4* __restrict__ p,
@@ -85,6 +88,61 @@ __global__ __launch_bounds__(256) void adam_dev_kernel(float* __restrict__ p,
     const int64_t i = i4 + k;
     if (i >= n) return;
     if (mask && mask[i] == 0) continue;
+    float pp = p[i], mm = m[i], vv = v[i];
+    adam_one(pp, g[i], mm, vv, c);
+    p[i] = pp;
+    m[i] = mm;
+    v[i] = vv;
+  }
+}
+
+// All groups in one grid: group k owns blocks [first[k], first[k + 1]), each
+// thread updates four consecutive parameters (one 16-byte access per array
+// when the group's arrays are 16-byte aligned).
+struct AdamGroups {
+  float* p[GS_ADAM_MAX_GROUPS];
+  const float* g[GS_ADAM_MAX_GROUPS];
+  float* m[GS_ADAM_MAX_GROUPS];
+  float* v[GS_ADAM_MAX_GROUPS];
+  int64_t n[GS_ADAM_MAX_GROUPS];
+  float lr[GS_ADAM_MAX_GROUPS];
+  int32_t vec[GS_ADAM_MAX_GROUPS];
+  int64_t first[GS_ADAM_MAX_GROUPS + 1];
+  int32_t count;
+};
+
+__global__ __launch_bounds__(256) void adam_groups_kernel(AdamGroups G, float b1, float b2,
+                                                          float eps,
+                                                          const int32_t* __restrict__ step_dev,
+                                                          const uint32_t* __restrict__ guard,
+                                                          int64_t guard_cap) {
+  const int64_t b = blockIdx.x;
+  int k = 0;
+  for (int q = 1; q < G.count; ++q) k = (b >= G.first[q]) ? q : k;
+  AdamCoef c;
+  if (!dev_coef(step_dev, guard, guard_cap, G.lr[k], b1, b2, eps, c)) return;
+  const int64_t i4 = ((b - G.first[k]) * blockDim.x + threadIdx.x) * 4;
+  const int64_t n = G.n[k];
+  if (i4 >= n) return;
+  float* __restrict__ p = G.p[k];
+  const float* __restrict__ g = G.g[k];
+  float* __restrict__ m = G.m[k];
+  float* __restrict__ v = G.v[k];
+  if (G.vec[k] && i4 + 4 <= n) {
+    float4 pp = *reinterpret_cast<float4*>(p + i4);
+    const float4 gg = *reinterpret_cast<const float4*>(g + i4);
+    float4 mm = *reinterpret_cast<float4*>(m + i4);
+    float4 vv = *reinterpret_cast<float4*>(v + i4);
+    adam_one(pp.x, gg.x, mm.x, vv.x, c);
+    adam_one(pp.y, gg.y, mm.y, vv.y, c);
+    adam_one(pp.z, gg.z, mm.z, vv.z, c);
+    adam_one(pp.w, gg.w, mm.w, vv.w, c);
+    *reinterpret_cast<float4*>(p + i4) = pp;
+    *reinterpret_cast<float4*>(m + i4) = mm;
+    *reinterpret_cast<float4*>(v + i4) = vv;
+    return;
+  }
+  for (int64_t i = i4; i < min(n, i4 + 4); ++i) {
     float pp = p[i], mm = m[i], vv = v[i];
     adam_one(pp, g[i], mm, vv, c);
     p[i] = pp;
@@ -175,6 +233,35 @@ hipError_t launch_adam_dev(float* p, const float* g, float* m, float* v, int64_t
   if (commit)
     hipLaunchKernelGGL(adam_commit_kernel, dim3(1), dim3(1), 0, s, step_dev, guard_n_keys,
                        guard_capacity);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_groups(const gs_adam_group* groups, int n_groups, float beta1,
+                              float beta2, float eps, int32_t* step_dev,
+                              const uint32_t* guard_n_keys, int64_t guard_capacity,
+                              hipStream_t s) {
+  AdamGroups G{};
+  G.count = n_groups;
+  int64_t blocks = 0;
+  for (int k = 0; k < n_groups; ++k) {
+    const gs_adam_group& q = groups[k];
+    G.p[k] = q.p;
+    G.g[k] = q.g;
+    G.m[k] = q.m;
+    G.v[k] = q.v;
+    G.n[k] = q.n;
+    G.lr[k] = q.lr;
+    G.vec[k] = ((reinterpret_cast<uintptr_t>(q.p) | reinterpret_cast<uintptr_t>(q.g) |
+                 reinterpret_cast<uintptr_t>(q.m) | reinterpret_cast<uintptr_t>(q.v)) & 15) == 0;
+    G.first[k] = blocks;
+    blocks += (q.n + 1023) / 1024;
+  }
+  G.first[n_groups] = blocks;
+  if (blocks > 0)
+    hipLaunchKernelGGL(adam_groups_kernel, dim3((unsigned)blocks), dim3(256), 0, s, G, beta1,
+                       beta2, eps, step_dev, guard_n_keys, guard_capacity);
+  hipLaunchKernelGGL(adam_commit_kernel, dim3(1), dim3(1), 0, s, step_dev, guard_n_keys,
+                     guard_capacity);
   return hipGetLastError();
 }
 

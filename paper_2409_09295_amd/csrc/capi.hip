@@ -303,6 +303,29 @@ int gs_adam_step_dev(float* p, const float* g, float* m, float* v, int64_t n, fl
   return e == hipSuccess ? GS_OK : hip_fail(e, "gs_adam_step_dev");
 }
 
+int gs_adam_step_groups_dev(const gs_adam_group* groups, int32_t n_groups, float beta1,
+                            float beta2, float eps, int32_t* step_dev,
+                            const uint32_t* guard_n_keys, int64_t guard_capacity,
+                            gs_stream_t stream) {
+  if (!groups) return invalid("groups is NULL");
+  if (n_groups < 1 || n_groups > GS_ADAM_MAX_GROUPS)
+    return invalid("n_groups = %d outside 1..%d", n_groups, GS_ADAM_MAX_GROUPS);
+  for (int k = 0; k < n_groups; ++k) {
+    const gs_adam_group& q = groups[k];
+    if (q.n < 0) return invalid("group %d: n = %lld < 0", k, (long long)q.n);
+    if (q.n > 0 && (!q.p || !q.g || !q.m || !q.v)) return invalid("group %d: a pointer is NULL", k);
+    if (!std::isfinite(q.lr)) return invalid("group %d: lr is not finite", k);
+  }
+  if (!step_dev) return invalid("step_dev is NULL");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f))
+    return invalid("betas must lie in [0, 1)");
+  if (!(eps >= 0.f)) return invalid("eps must be >= 0");
+  if (guard_n_keys && guard_capacity < 0) return invalid("guard_capacity < 0");
+  const hipError_t e = launch_adam_groups(groups, n_groups, beta1, beta2, eps, step_dev,
+                                          guard_n_keys, guard_capacity, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_adam_step_groups_dev");
+}
+
 int gs_l1_loss_grad(const float* image, const float* target, const gs_views* views,
                     float* dL_dimage, double* loss, gs_stream_t stream) {
   ViewTable vt;

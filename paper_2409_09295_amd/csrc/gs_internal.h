@@ -220,6 +220,10 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
                        float beta1, float beta2, float eps, int32_t step, const uint8_t* mask,
                        hipStream_t s);
 
+hipError_t launch_adam_groups(const gs_adam_group* groups, int n_groups, float beta1,
+                              float beta2, float eps, int32_t* step_dev,
+                              const uint32_t* guard_n_keys, int64_t guard_capacity,
+                              hipStream_t s);
 hipError_t launch_adam_dev(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                            float beta1, float beta2, float eps, int32_t* step_dev, int32_t commit,
                            const uint8_t* mask, const uint32_t* guard_n_keys,

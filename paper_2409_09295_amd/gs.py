@@ -12,7 +12,7 @@ from __future__ import annotations
 import ctypes
 import dataclasses
 import os
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -122,10 +122,22 @@ _lib.gs_adam_step_dev.argtypes = [_p, _p, _p, _p, ctypes.c_int64, ctypes.c_float
                                   ctypes.c_float, ctypes.c_float, _p, ctypes.c_int32, _p, _p,
                                   ctypes.c_int64, _S]
 
+
+class gs_adam_group(ctypes.Structure):
+    _fields_ = [("p", _p), ("g", _p), ("m", _p), ("v", _p), ("n", ctypes.c_int64),
+                ("lr", ctypes.c_float)]
+
+
+GS_ADAM_MAX_GROUPS = 8
+_lib.gs_adam_step_groups_dev.argtypes = [ctypes.POINTER(gs_adam_group), ctypes.c_int32,
+                                         ctypes.c_float, ctypes.c_float, ctypes.c_float, _p, _p,
+                                         ctypes.c_int64, _S]
+
 EXPORTED = ("gs_status_string", "gs_last_error", "gs_version", "gs_num_tiles", "gs_num_pixels",
             "gs_preprocess", "gs_bin_sort_workspace_size", "gs_bin_sort", "gs_render_fwd",
             "gs_render_bwd_workspace_size", "gs_render_bwd", "gs_adam_step", "gs_l1_loss_grad",
-            "gs_set_kernel_events", "gs_adam_step_dev", "gs_set_tuning", "gs_get_tuning")
+            "gs_set_kernel_events", "gs_adam_step_dev", "gs_adam_step_groups_dev",
+            "gs_set_tuning", "gs_get_tuning")
 
 
 def lib() -> ctypes.CDLL:
@@ -398,6 +410,29 @@ def gs_adam_step_dev(p: torch.Tensor, g: torch.Tensor, m: torch.Tensor, v: torch
     _check(_lib.gs_adam_step_dev(_ptr(p), _ptr(g), _ptr(m), _ptr(v), n, lr, beta1, beta2, eps,
                                  _ptr(step_dev), int(bool(commit)), _ptr(mask), _ptr(guard_n_keys),
                                  guard_capacity, _stream(stream)), "gs_adam_step_dev")
+
+
+def adam_groups(groups: Sequence[Tuple[torch.Tensor, torch.Tensor, torch.Tensor, torch.Tensor, float]]):
+    """Host array of gs_adam_group from (p, g, m, v, lr) tuples (kept by the caller)."""
+    arr = (gs_adam_group * len(groups))()
+    for k, (p, g, m, v, lr) in enumerate(groups):
+        n = p.numel()
+        for x in (g, m, v):
+            if x.numel() != n:
+                raise ValueError("Adam tensors must have equal sizes")
+        arr[k] = gs_adam_group(_ptr(p), _ptr(g), _ptr(m), _ptr(v), n, lr)
+    return arr
+
+
+def gs_adam_step_groups_dev(groups, beta1: float, beta2: float, eps: float, step_dev: torch.Tensor,
+                            guard_n_keys: Optional[torch.Tensor] = None, guard_capacity: int = 0,
+                            stream=None) -> None:
+    """groups: an array from adam_groups()."""
+    if step_dev.dtype != torch.int32 or step_dev.numel() != 1:
+        raise ValueError("step_dev must be one int32")
+    _check(_lib.gs_adam_step_groups_dev(groups, len(groups), beta1, beta2, eps, _ptr(step_dev),
+                                        _ptr(guard_n_keys), guard_capacity, _stream(stream)),
+           "gs_adam_step_groups_dev")
 
 
 def gs_l1_loss_grad(image: torch.Tensor, target: torch.Tensor, views: Views, dL_dimage: torch.Tensor,

@@ -57,11 +57,14 @@ class _AdamState:
             dst.copy_(src)
 
     def apply(self, grads: gs.Grads, guard_n_keys=None, guard_capacity: int = 0):
+        """One Adam step of every group in a single launch (graph-capture safe)."""
         gl = [grads.means, grads.log_scales, grads.quats, grads.opacity_logits, grads.sh]
-        last = len(self.params) - 1
-        for k, (p, g_, m, v, lr) in enumerate(zip(self.params, gl, self.m, self.v, self.lrs)):
-            gs.gs_adam_step_dev(p, g_, m, v, lr, BETA1, BETA2, EPS, self.step_dev, k == last,
-                                guard_n_keys=guard_n_keys, guard_capacity=guard_capacity)
+        key = tuple(t.data_ptr() for t in gl)
+        if getattr(self, "_groups_key", None) != key:
+            self._groups = gs.adam_groups(list(zip(self.params, gl, self.m, self.v, self.lrs)))
+            self._groups_key = key
+        gs.gs_adam_step_groups_dev(self._groups, BETA1, BETA2, EPS, self.step_dev,
+                                   guard_n_keys=guard_n_keys, guard_capacity=guard_capacity)
 
 
 class BatchedStep:

@@ -377,6 +377,46 @@ def test_adam_step(gs, n, offset, masked):
             np.testing.assert_allclose(np_(got), r, rtol=2e-6, atol=1e-7)
 
 
+def test_adam_groups_match_per_group_calls(gs):
+    """The single-launch grouped update equals one device-step call per
+    group bit for bit (ragged and unaligned groups included), and skips
+    everything, counter included, when the binning guard reports overflow."""
+    rng = np.random.default_rng(9)
+    sizes = [(1, 0), (1003, 0), (4096, 1), (37, 3), (250000, 0)]
+    lrs = [1e-3, 5e-2, 2.5e-3, 1e-2, 1.6e-4]
+
+    def make():
+        out = []
+        for (n, off) in sizes:
+            b = [rng.normal(size=n + off).astype(np.float32) for _ in range(4)]
+            b[3] = np.abs(b[3])
+            out.append([torch.from_numpy(x).to(DEV)[off:] for x in b])
+        return out
+
+    A = make()
+    B = [[t.clone() for t in grp] for grp in A]
+    sa = torch.zeros(1, dtype=torch.int32, device=DEV)
+    sb = torch.zeros(1, dtype=torch.int32, device=DEV)
+    guard = torch.tensor([10], dtype=torch.int32, device=DEV)
+    arr = gs.adam_groups([(p, g, m, v, lr) for (p, g, m, v), lr in zip(A, lrs)])
+    for step in range(3):
+        gs.gs_adam_step_groups_dev(arr, 0.9, 0.999, 1e-15, sa, guard_n_keys=guard, guard_capacity=20)
+        for k, ((p, g, m, v), lr) in enumerate(zip(B, lrs)):
+            gs.gs_adam_step_dev(p, g, m, v, lr, 0.9, 0.999, 1e-15, sb, k == len(B) - 1,
+                                guard_n_keys=guard, guard_capacity=20)
+    torch.cuda.synchronize()
+    assert int(sa.item()) == int(sb.item()) == 3
+    for ga, gb in zip(A, B):
+        for x, y in zip(ga, gb):
+            torch.testing.assert_close(x, y, rtol=0, atol=0)
+    before = [t.clone() for grp in A for t in grp]
+    gs.gs_adam_step_groups_dev(arr, 0.9, 0.999, 1e-15, sa, guard_n_keys=guard, guard_capacity=5)
+    torch.cuda.synchronize()
+    assert int(sa.item()) == 3
+    for x, y in zip([t for grp in A for t in grp], before):
+        torch.testing.assert_close(x, y, rtol=0, atol=0)
+
+
 def test_l1_loss_grad(gs):
     cams = [scenes.pinhole(50, 30, 40.0), scenes.pinhole(17, 9, 10.0)]
     views = gs.Views(cams)
