@@ -8,13 +8,15 @@
 // are summed over the wavefront with DPP row operations and added to a
 // per-(view, splat) accumulator with one 9-lane atomic.
 //
-// The screen-space partials live in a Gaussian-major [n][V][9] buffer.
+// The screen-space partials live in a view-major [V][n][9] buffer (the
+// layout of the projected splats), so both passes touch it coalesced.
 //
-// Pass 2 (one lane per (Gaussian, view)): re-evaluates the projection and
-// chains the screen-space partials to the map parameters, summed over the
-// Gaussian's view lanes with cross-lane adds, and to each view's pose
-// tangent; pose partials are reduced per workgroup in float64 and summed over
-// workgroups by a final small kernel (fixed order, deterministic).
+// Pass 2 (one lane per Gaussian, looping over the views): for every view
+// where some lane of the wavefront has a visible splat with nonzero partials,
+// re-evaluates the projection and chains the partials to the map parameters
+// (accumulated in the lane) and to the view's pose tangent (summed over the
+// wavefront, then per workgroup in float64, then over workgroups by a final
+// small kernel in a fixed order: deterministic).
 #include "project.h"
 
 namespace gsmi {
@@ -92,9 +94,8 @@ __device__ __forceinline__ Reduced9 wave_reduce9(float v0, float v1, float v2, f
   return r;
 }
 
-// Stages splat `g` (index view * n + Gaussian into the [V][n] splat arrays)
-// and the index Gaussian * V + view of its accumulator in the Gaussian-major
-// [n][V][9] screen-space gradient buffer.
+// Stages splat `g` (index view * n + Gaussian into the [V][n] splat arrays,
+// also the index of its accumulator in the [V][n][9] gradient buffer).
 __device__ __forceinline__ uint32_t stage_splat(uint32_t g, uint32_t n, uint32_t n_views,
                                                 const float2* __restrict__ xy,
                                                 const float4* __restrict__ co,
@@ -103,11 +104,9 @@ __device__ __forceinline__ uint32_t stage_splat(uint32_t g, uint32_t n, uint32_t
   const float2 m = xy[g];
   const float4 c = co[g];
   const float4 r = rd[g];
-  const uint32_t view = g / n;
-  const uint32_t acc = (g - view * n) * n_views + view;
   const uint32_t reach = quadrant_mask(m.x, m.y, c.x, c.y, c.z, c.w, tx0, ty0, W, H);
   out.geo = make_float4(m.x, m.y, -0.5f * kLog2e * c.x, -kLog2e * c.y);
-  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.w, __uint_as_float(acc));
+  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.w, __uint_as_float(g));
   out.col = make_float4(r.x, r.y, r.z, __uint_as_float(reach));
   return reach;
 }
@@ -271,34 +270,6 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
 // per-Gaussian backward through the projection
 // ---------------------------------------------------------------------------
 
-// Sum over the LPG lanes of each lane group (lanes l with equal l / LPG),
-// result in every lane of the group.  Quad permutes for distances 1 and 2,
-// then mirrors (valid once the smaller groups are uniform), then the
-// cross-row swaps.
-template <int LPG>
-__device__ __forceinline__ float group_sum(float x) {
-  if (LPG >= 2) x = dpp_add<0xb1>(x);   // quad_perm [1,0,3,2]
-  if (LPG >= 4) x = dpp_add<0x4e>(x);   // quad_perm [2,3,0,1]
-  if (LPG >= 8) x = dpp_add<0x141>(x);  // row_half_mirror
-  if (LPG >= 16) x = dpp_add<0x140>(x); // row_mirror
-  if (LPG >= 32) x = swap16_add(x, x);
-  if (LPG >= 64) x = swap32_add(x, x);
-  return x;
-}
-
-// Sum over lane groups, keeping the position inside the group (lane l and
-// l + m * LPG are added): moves that preserve l mod LPG.
-template <int LPG>
-__device__ __forceinline__ float across_groups(float x) {
-  if (LPG <= 1) x = dpp_add<0xb1>(x);   // quad_perm [1,0,3,2]
-  if (LPG <= 2) x = dpp_add<0x4e>(x);   // quad_perm [2,3,0,1]
-  if (LPG <= 4) x = dpp_add<0x124>(x);  // row_ror:4
-  if (LPG <= 8) x = dpp_add<0x128>(x);  // row_ror:8
-  if (LPG <= 16) x = swap16_add(x, x);
-  if (LPG <= 32) x = swap32_add(x, x);
-  return x;
-}
-
 // Slots of the per-(Gaussian, view) contribution vector.
 constexpr int kCMu = 0, kCRq = 3, kCSc = 12, kCOl = 15, kCSh = 16;
 
@@ -306,11 +277,9 @@ constexpr int kCMu = 0, kCRq = 3, kCSc = 12, kCOl = 15, kCSh = 16;
 // parameters (accumulated into c) and to the view's pose tangent.
 template <int DEG>
 __device__ __forceinline__ void chain_one(const GaussState& G, const gs_camera& cam,
-                                          const float* __restrict__ sh, int64_t n, int64_t i,
-                                          const float* g2, float* c, float* pose) {
+                                          const SHCoef<DEG>& C, const float* g2, float* c,
+                                          float* pose) {
   constexpr int K = SHDim<DEG>::K;
-  SHCoef<DEG> C;
-  load_sh<DEG>(sh, n, i, C);
   ViewState S;
   project_view<DEG>(G, cam, C, S);
   const float* W = cam.R;
@@ -422,54 +391,62 @@ __device__ __forceinline__ void chain_one(const GaussState& G, const gs_camera& 
 
 constexpr int kProjBwdMaxBlocks = 2048;
 
-// One lane per (Gaussian, view): wavefronts hold 64 / LPG Gaussians with LPG
-// lanes each (LPG = next power of two >= views).  Map gradients are summed
-// over a Gaussian's lanes in registers (group_sum), pose partials over the
-// Gaussians of each view (across_groups), then per workgroup in float64.
-template <int DEG, int LPG>
+// One lane per Gaussian (grid-stride), views in turn.  Map gradients
+// accumulate in the lane; each view's pose partials are summed over the
+// wavefront and added, in float64, to the wave's row of s_pose.
+template <int DEG>
 __global__ __launch_bounds__(256) void project_bwd_kernel(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ ologit,
     const float* __restrict__ sh, int64_t n, const gs_camera* __restrict__ cams, int n_views,
-    const float* __restrict__ grad2d, float* __restrict__ g_means,
-    float* __restrict__ g_log_scales, float* __restrict__ g_quats, float* __restrict__ g_ologit,
-    float* __restrict__ g_sh, double* __restrict__ pose_part, uint32_t flags) {
+    const int32_t* __restrict__ radius, const float* __restrict__ grad2d,
+    float* __restrict__ g_means, float* __restrict__ g_log_scales, float* __restrict__ g_quats,
+    float* __restrict__ g_ologit, float* __restrict__ g_sh, double* __restrict__ pose_part,
+    uint32_t flags) {
   constexpr int K = SHDim<DEG>::K;
   constexpr int NC = kCSh + 3 * K;
-  constexpr int GPW = 64 / LPG;
-  __shared__ float s_pose[4][64][6];
+  __shared__ double s_pose[4][GS_MAX_VIEWS][6];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int sub = lane / LPG, v = lane % LPG;
-  const bool view_ok = v < n_views;
   const bool want_pose = !(flags & GS_BWD_NO_POSE);
   const bool want_map = !(flags & GS_BWD_POSE_ONLY);
   const bool overwrite = (flags & GS_BWD_OVERWRITE) != 0;
-  float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  const int64_t per_block = 4 * GPW;
-  for (int64_t base = (int64_t)blockIdx.x * per_block; base < n;
-       base += (int64_t)gridDim.x * per_block) {
-    const int64_t i = base + w * GPW + sub;
+  for (int t = threadIdx.x; t < 4 * GS_MAX_VIEWS * 6; t += 256) (&s_pose[0][0][0])[t] = 0.0;
+  __syncthreads();
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+    const int64_t i = base + threadIdx.x;
     const bool valid = i < n;
     GaussState G;
     if (valid) load_gauss(means, log_scales, quats, ologit, n, i, G);
     else G.ok = false;
+    SHCoef<DEG> C;
+    if (G.ok) load_sh<DEG>(sh, n, i, C);
     float c[NC];
     for (int k = 0; k < NC; ++k) c[k] = 0.f;
-    bool active = valid && view_ok && G.ok;
-    float g2[9];
-    if (active) {
-      const float* src = grad2d + ((int64_t)i * n_views + v) * 9;
+    for (int v = 0; v < n_views; ++v) {
+      const int64_t e = (int64_t)v * n + i;
+      bool active = G.ok && radius[e] > 0;
+      if (!__any(active)) continue;
+      float g2[9];
       bool nz = false;
-      for (int k = 0; k < 9; ++k) {
-        g2[k] = src[k];
-        nz = nz || g2[k] != 0.0f;
+      if (active) {
+        const float* src = grad2d + e * 9;
+        for (int k = 0; k < 9; ++k) {
+          g2[k] = src[k];
+          nz = nz || g2[k] != 0.0f;
+        }
       }
-      active = nz;
+      active = active && nz;
+      if (!__any(active)) continue;
+      float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (active) chain_one<DEG>(G, cams[v], C, g2, c, pose);
+      if (want_pose) {
+        for (int k = 0; k < 6; ++k) {
+          const float tot = lane63(wave_sum_to_lane63(pose[k]));
+          if (lane == 0) s_pose[w][v][k] += (double)tot;
+        }
+      }
     }
-    if (active) chain_one<DEG>(G, cams[v], sh, n, i, g2, c, pose);
-    if (!want_map) continue;
-    for (int k = 0; k < NC; ++k) c[k] = group_sum<LPG>(c[k]);
-    if (v != 0 || !valid) continue;
+    if (!want_map || !valid) continue;
     if (!G.ok) {
       if (overwrite) {
         for (int k = 0; k < 3; ++k) g_means[k * n + i] = g_log_scales[k * n + i] = 0.f;
@@ -502,15 +479,11 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
     for (int k = 0; k < 4; ++k) put(&g_quats[k * n + i], (dq[k] - G.q[k] * dot) * inv);
   }
   if (!want_pose) return;
-  for (int k = 0; k < 6; ++k) pose[k] = across_groups<LPG>(pose[k]);
-  if (lane < LPG && view_ok)
-    for (int k = 0; k < 6; ++k) s_pose[w][lane][k] = pose[k];
   __syncthreads();
   for (int t = threadIdx.x; t < n_views * 6; t += 256) {
     const int vv = t / 6, k = t % 6;
-    const double tot = (double)s_pose[0][vv][k] + (double)s_pose[1][vv][k] +
-                       (double)s_pose[2][vv][k] + (double)s_pose[3][vv][k];
-    pose_part[(int64_t)blockIdx.x * n_views * 6 + t] = tot;
+    pose_part[(int64_t)blockIdx.x * n_views * 6 + t] =
+        s_pose[0][vv][k] + s_pose[1][vv][k] + s_pose[2][vv][k] + s_pose[3][vv][k];
   }
 }
 
@@ -534,15 +507,8 @@ __global__ __launch_bounds__(256) void pose_reduce_kernel(const double* __restri
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int lanes_per_gaussian(int n_views) {
-  int l = 1;
-  while (l < n_views) l <<= 1;
-  return l;
-}
-
-int64_t proj_bwd_blocks(int64_t n, int n_views) {
-  const int64_t per_block = 4 * (64 / lanes_per_gaussian(n_views));
-  return std::max<int64_t>(1, std::min<int64_t>(kProjBwdMaxBlocks, (n + per_block - 1) / per_block));
+int64_t proj_bwd_blocks(int64_t n, int /*n_views*/) {
+  return std::max<int64_t>(1, std::min<int64_t>(kProjBwdMaxBlocks, (n + 255) / 256));
 }
 
 }  // namespace
@@ -563,32 +529,22 @@ namespace {
 
 template <int DEG>
 void launch_project_bwd_deg(const gs_gaussians& g, const gs_camera* cams, int V,
-                            const float* grad2d, const gs_grads& gr, double* pose_part,
-                            uint32_t flags, dim3 grid, dim3 block, hipStream_t s) {
-#define GS_PB(L)                                                                                 \
-  hipLaunchKernelGGL((project_bwd_kernel<DEG, L>), grid, block, 0, s, g.means, g.log_scales,    \
-                     g.quats, g.opacity_logits, g.sh, g.n, cams, V, grad2d, gr.means,           \
-                     gr.log_scales, gr.quats, gr.opacity_logits, gr.sh, pose_part, flags)
-  switch (lanes_per_gaussian(V)) {
-    case 1: GS_PB(1); break;
-    case 2: GS_PB(2); break;
-    case 4: GS_PB(4); break;
-    case 8: GS_PB(8); break;
-    case 16: GS_PB(16); break;
-    case 32: GS_PB(32); break;
-    default: GS_PB(64); break;
-  }
-#undef GS_PB
+                            const int32_t* radius, const float* grad2d, const gs_grads& gr,
+                            double* pose_part, uint32_t flags, dim3 grid, dim3 block,
+                            hipStream_t s) {
+  hipLaunchKernelGGL((project_bwd_kernel<DEG>), grid, block, 0, s, g.means, g.log_scales, g.quats,
+                     g.opacity_logits, g.sh, g.n, cams, V, radius, grad2d, gr.means,
+                     gr.log_scales, gr.quats, gr.opacity_logits, gr.sh, pose_part, flags);
 }
 
-void launch_project_bwd(const gs_gaussians& g, const gs_camera* cams, int V, const float* grad2d,
-                        const gs_grads& gr, double* pose_part, uint32_t flags, dim3 grid,
-                        dim3 block, hipStream_t s) {
+void launch_project_bwd(const gs_gaussians& g, const gs_camera* cams, int V, const int32_t* radius,
+                        const float* grad2d, const gs_grads& gr, double* pose_part, uint32_t flags,
+                        dim3 grid, dim3 block, hipStream_t s) {
   switch (g.sh_degree) {
-    case 0: launch_project_bwd_deg<0>(g, cams, V, grad2d, gr, pose_part, flags, grid, block, s); break;
-    case 1: launch_project_bwd_deg<1>(g, cams, V, grad2d, gr, pose_part, flags, grid, block, s); break;
-    case 2: launch_project_bwd_deg<2>(g, cams, V, grad2d, gr, pose_part, flags, grid, block, s); break;
-    default: launch_project_bwd_deg<3>(g, cams, V, grad2d, gr, pose_part, flags, grid, block, s); break;
+    case 0: launch_project_bwd_deg<0>(g, cams, V, radius, grad2d, gr, pose_part, flags, grid, block, s); break;
+    case 1: launch_project_bwd_deg<1>(g, cams, V, radius, grad2d, gr, pose_part, flags, grid, block, s); break;
+    case 2: launch_project_bwd_deg<2>(g, cams, V, radius, grad2d, gr, pose_part, flags, grid, block, s); break;
+    default: launch_project_bwd_deg<3>(g, cams, V, radius, grad2d, gr, pose_part, flags, grid, block, s); break;
   }
 }
 
@@ -630,7 +586,8 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
   const int64_t nblocks = proj_bwd_blocks(g.n, vt.n_views);
   const dim3 grid((unsigned)nblocks), block(256);
   kernel_event_start(GS_KERNEL_PROJECT_BWD, s);
-  launch_project_bwd(g, cams_dev, vt.n_views, grad2d, grads, pose_part, flags, grid, block, s);
+  launch_project_bwd(g, cams_dev, vt.n_views, p.radius, grad2d, grads, pose_part, flags, grid,
+                     block, s);
   kernel_event_stop(GS_KERNEL_PROJECT_BWD, s);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (!(flags & GS_BWD_NO_POSE)) {
