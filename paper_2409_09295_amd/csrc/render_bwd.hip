@@ -131,12 +131,13 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
   const int lane = threadIdx.x & 63;
   // where wave_reduce9 leaves each value: row r = lane / 16 of q0 holds value
   // {0, 2, 1, 3}[r] and of q1 value 4 + {0, 2, 1, 3}[r]; the per-value factors
-  // turn the accumulated sums into dL/du, dL/dv (from the log2-scaled conic)
-  // and dL/dQ00, dL/dQ01, dL/dQ11.
+  // turn the accumulated sums into dL/dQ00, dL/dQ01, dL/dQ11 (slots 0 and 1
+  // keep sum(dL/dpower * (dx, dy)), which the projection backward multiplies
+  // by the conic to obtain dL/du, dL/dv).
   const int row = lane >> 4;
   const int red_off0 = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
-  // value factors: u, v: -1/log2(e); Q00, Q11: -1/2; Q01: -1; o, r, g, b: 1
-  const float red_scale0 = (row == 0 || row == 2) ? -1.0f / kLog2e : (row == 1) ? -0.5f : -1.0f;
+  // value factors: slots 0, 1: 1; Q00, Q11: -1/2; Q01: -1; o, r, g, b: 1
+  const float red_scale0 = (row == 0 || row == 2) ? 1.0f : (row == 1) ? -0.5f : -1.0f;
   const float red_scale1 = (row == 0) ? -0.5f : 1.0f;
 
   float fpx[PPL], fpy[PPL], T[PPL], dC0[PPL], dC1[PPL], dC2[PPL], S0[PPL], S1[PPL], S2[PPL];
@@ -235,19 +236,22 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
           g6 += wgt * dC0[k];
           g7 += wgt * dC1[k];
           g8 += wgt * dC2[k];
-          const float dalpha = Tk * ((col.x - S0[k]) * dC0[k] + (col.y - S1[k]) * dC1[k] +
-                                     (col.z - S2[k]) * dC2[k]);
-          S0[k] = alpha * col.x + (1.0f - alpha) * S0[k];
-          S1[k] = alpha * col.y + (1.0f - alpha) * S1[k];
-          S2[k] = alpha * col.z + (1.0f - alpha) * S2[k];
+          const float d0 = col.x - S0[k], d1 = col.y - S1[k], d2 = col.z - S2[k];
+          const float dalpha = Tk * (d0 * dC0[k] + d1 * dC1[k] + d2 * dC2[k]);
+          // colour behind the next splat in front: alpha c + (1 - alpha) S
+          S0[k] = __builtin_fmaf(alpha, d0, S0[k]);
+          S1[k] = __builtin_fmaf(alpha, d1, S1[k]);
+          S2[k] = __builtin_fmaf(alpha, d2, S2[k]);
           T[k] = Tk;
           // below the 0.99 clamp alpha = o G: d alpha/do = G, d alpha/dpower = alpha
           const float live = raw <= kAlphaMax ? dalpha : 0.0f;
           g5 += G * live;
           const float gP = alpha * live;   // dL/dpower
           const float gdx = gP * dx, gdy = gP * dy;
-          g0 += 2.0f * geo.z * gdx + geo.w * gdy;
-          g1 += geo.w * gdx + 2.0f * app.x * gdy;
+          // d power/du = Q00 dx + Q01 dy (and likewise v): the conic factor is
+          // the same for every pixel, so only sum(gP d) is accumulated here
+          g0 += gdx;
+          g1 += gdy;
           g2 += gdx * dx;
           g3 += gdx * dy;
           g4 += gdy * dy;
@@ -339,9 +343,13 @@ __device__ __forceinline__ void chain_one(const GaussState& G, const gs_camera& 
   // camera-frame position (projection and Jacobian)
   const float iz = S.inv_z, iz2 = iz * iz;
   const float fx = cam.fx, fy = cam.fy;
-  gp[0] = g2[0] * fx * iz;
-  gp[1] = g2[1] * fy * iz;
-  gp[2] = -(g2[0] * fx * S.p[0] + g2[1] * fy * S.p[1]) * iz2;
+  // screen-space centre: slots 0, 1 hold sum(dL/dpower * (dx, dy)) over the
+  // pixels; dL/du = Q00 s0 + Q01 s1, dL/dv = Q01 s0 + Q11 s1
+  const float gu = S.q0 * g2[0] + S.q1 * g2[1];
+  const float gv = S.q1 * g2[0] + S.q2 * g2[1];
+  gp[0] = gu * fx * iz;
+  gp[1] = gv * fy * iz;
+  gp[2] = -(gu * fx * S.p[0] + gv * fy * S.p[1]) * iz2;
   gp[2] += -gJ00 * fx * iz2 - gJ11 * fy * iz2;
   if (!S.clx) {
     gp[0] += -gJ02 * fx * iz2;
