@@ -169,6 +169,26 @@ __device__ __forceinline__ bool eval_alpha(const float4& geo, const float4& app,
   return alpha >= kAlphaMin;
 }
 
+// The same decision without a branch: every output is finite for every
+// pixel (the exponent is clamped at 0, which changes nothing where the splat
+// is kept), and the return value says whether the splat is kept.  Where it
+// is kept the outputs equal eval_alpha's bit for bit.
+__device__ __forceinline__ bool eval_alpha_all(const float4& geo, const float4& app, float px,
+                                               float py, float& alpha, float& raw, float& G,
+                                               float& dx, float& dy) {
+  dx = px - geo.x;
+  dy = py - geo.y;
+  const float t1 = geo.w * dy;
+  const float t2 = __builtin_fmaf(geo.z, dx, t1);
+  const float t3 = app.x * dy;
+  const float t4 = t3 * dy;
+  const float p2 = __builtin_fmaf(dx, t2, t4);
+  G = __builtin_amdgcn_exp2f(fminf(p2, 0.0f));
+  raw = app.y * G;
+  alpha = fminf(kAlphaMax, raw);
+  return p2 <= 0.0f && alpha >= kAlphaMin;
+}
+
 // Process-wide tuning values (see gs_set_tuning); always a supported value.
 int tuning(int key);
 

@@ -171,10 +171,16 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     }
   }
   // list positions this wave has to walk: below the largest n_contrib of its pixels
-  uint32_t wave_last = mylast;
+  uint32_t slot_last[PPL];   // per pixel slot: largest n_contrib over the wave
+  uint32_t wave_last = 0;
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, d, 64));
-  wave_last = __builtin_amdgcn_readfirstlane(wave_last);
+  for (int k = 0; k < PPL; ++k) {
+    uint32_t x = last[k];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, d, 64));
+    slot_last[k] = __builtin_amdgcn_readfirstlane(x);
+    wave_last = max(wave_last, slot_last[k]);
+  }
   if (threadIdx.x == 0) s_maxlast = 0;
   __syncthreads();
   if (lane == 0 && wave_last) atomicMax(&s_maxlast, wave_last);
@@ -227,9 +233,12 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
         const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(col.w)) : ~0u;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-          if (pos >= last[k] || !(reach & qbit[k])) continue;
+          // slot-uniform skips: quadrant not reached, or every pixel of the
+          // slot in this wave already past its last blended splat
+          if (!(reach & qbit[k]) || pos >= slot_last[k]) continue;
           float alpha, raw, G, dx, dy;
-          if (!eval_alpha(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy)) continue;
+          const bool ok = eval_alpha_all(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy);
+          if (!ok || pos >= last[k]) continue;
           contrib = true;
           const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
           const float wgt = alpha * Tk;
