@@ -108,14 +108,13 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
         const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(app.w)) : ~0u;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
-          if (done[k] || !(reach & qbit[k])) continue;
+          if (!(reach & qbit[k])) continue;   // slot-uniform
           float alpha, raw, G, dx, dy;
-          if (!eval_alpha(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy)) continue;
+          const bool ok = eval_alpha_all(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy) && !done[k];
           const float Tn = T[k] * (1.0f - alpha);
-          if (Tn < kTMin) {
-            done[k] = true;
-            continue;
-          }
+          const bool term = ok && Tn < kTMin;   // stops before this splat
+          done[k] = done[k] || term;
+          if (!ok || term) continue;
           const float wgt = alpha * T[k];
           C0[k] += col.x * wgt;
           C1[k] += col.y * wgt;
