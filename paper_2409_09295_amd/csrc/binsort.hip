@@ -260,11 +260,33 @@ __global__ __launch_bounds__(256) void radix_upsweep_kernel(const uint64_t* __re
   hist[(int64_t)t * nblocks + blockIdx.x] = h[0][t] + h[1][t] + h[2][t] + h[3][t];
 }
 
+// Exclusive scan of each digit's row of per-block counts in the digit-major
+// histogram [256][nblocks] (one workgroup per digit); row totals to tot[256].
+// The down-sweep adds the exclusive prefix of the totals.
+__global__ __launch_bounds__(256) void hist_row_scan_kernel(uint32_t* __restrict__ hist,
+                                                            uint32_t nblocks,
+                                                            uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s_wave[4];
+  uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
+  const uint32_t per = (nblocks + 255) / 256;
+  const uint32_t lo = min(nblocks, threadIdx.x * per), hi = min(lo + per, nblocks);
+  uint32_t sum = 0;
+  for (uint32_t k = lo; k < hi; ++k) sum += row[k];
+  uint32_t total;
+  uint32_t run = block_exclusive_scan<uint32_t>(sum, s_wave, total);
+  for (uint32_t k = lo; k < hi; ++k) {
+    const uint32_t x = row[k];
+    row[k] = run;
+    run += x;
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = total;
+}
+
 __global__ __launch_bounds__(256) void radix_downsweep_kernel(
     const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ n_keys, int64_t capacity, int shift,
-    const uint32_t* __restrict__ hist, uint32_t nblocks) {
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot, uint32_t nblocks) {
   __shared__ uint32_t s_wcnt[4][256];
   __shared__ uint32_t s_wpre[4][256];
   __shared__ uint32_t s_dstart[256];
@@ -315,7 +337,8 @@ __global__ __launch_bounds__(256) void radix_downsweep_kernel(
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan<uint32_t>(c0 + c1 + c2 + c3, s_wave, tot);
     s_dstart[t] = ex;
-    s_gbase[t] = hist[(int64_t)t * nblocks + blockIdx.x];
+    const uint32_t dbase = block_exclusive_scan<uint32_t>(digit_tot[t], s_wave, tot);
+    s_gbase[t] = hist[(int64_t)t * nblocks + blockIdx.x] + dbase;
   }
   __syncthreads();
 #pragma unroll
@@ -376,7 +399,6 @@ BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity)
   P.scan_blocks = (P.n_entries + kScanChunk - 1) / kScanChunk;
   P.sort_blocks = (capacity + kSortChunk - 1) / kSortChunk;
   const int64_t hist_n = 256 * std::max<int64_t>(P.sort_blocks, 1);
-  const int64_t hist_part = (hist_n + kScanChunk - 1) / kScanChunk;
   size_t off = 0;
   P.off_counts = off;    off += align_up(sizeof(uint32_t) * P.n_entries);
   P.off_offsets = off;   off += align_up(sizeof(uint32_t) * P.n_entries);
@@ -384,7 +406,7 @@ BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity)
   P.off_keys_alt = off;  off += align_up(sizeof(uint64_t) * capacity);
   P.off_vals_alt = off;  off += align_up(sizeof(uint32_t) * capacity);
   P.off_hist = off;      off += align_up(sizeof(uint32_t) * hist_n);
-  P.off_hist_part = off; off += align_up(sizeof(uint64_t) * (hist_part + 1));
+  P.off_hist_part = off; off += align_up(sizeof(uint32_t) * 256);   // digit totals
   P.off_flag = off;      off += align_up(sizeof(uint64_t) * 4);
   P.total = off;
   return P;
@@ -441,9 +463,11 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
     const int shift = 8 * pass;
     hipLaunchKernelGGL(radix_upsweep_kernel, dim3(nblocks), dim3(256), 0, s, kA, bins.n_keys,
                        P.capacity, shift, hist, nblocks);
-    scan_u32(hist, hist, 256 * (int64_t)nblocks, hist_part, flag + 1, nullptr, s);
+    hipLaunchKernelGGL(hist_row_scan_kernel, dim3(256), dim3(256), 0, s, hist, nblocks,
+                       reinterpret_cast<uint32_t*>(hist_part));
     hipLaunchKernelGGL(radix_downsweep_kernel, dim3(nblocks), dim3(256), 0, s, kA, vA, kB, vB,
-                       bins.n_keys, P.capacity, shift, hist, nblocks);
+                       bins.n_keys, P.capacity, shift, hist,
+                       reinterpret_cast<const uint32_t*>(hist_part), nblocks);
     std::swap(kA, kB);
     std::swap(vA, vB);
   }
