@@ -298,6 +298,19 @@ int gs_adam_step_groups_dev(const gs_adam_group* groups, int32_t n_groups, float
                             const uint32_t* guard_n_keys, int64_t guard_capacity,
                             gs_stream_t stream);
 
+/* gs_render_fwd fused with gs_l1_loss_grad: composites exactly as
+ * gs_render_fwd (same image, final_T, n_contrib; no depth) and, from the
+ * image values it writes, dL/dC = sign(C - C*) / (3 H W) into dL_dimage
+ * (identical to gs_l1_loss_grad's) and, if loss != NULL, the loss (the
+ * same sum, added in a fixed order: equal up to float rounding).
+ * target: [3][H][W] per view like image.  ws: gs_render_fwd_l1_workspace_size
+ * bytes (one float per tile). */
+size_t gs_render_fwd_l1_workspace_size(const gs_views* views);
+int gs_render_fwd_l1(const gs_projected* p, int64_t n, const gs_bins* bins,
+                     const gs_views* views, const float* bg, float* image, float* final_T,
+                     uint32_t* n_contrib, const float* target, float* dL_dimage, double* loss,
+                     void* workspace, size_t workspace_bytes, gs_stream_t stream);
+
 /* L1 photometric loss L = sum over views of mean |C - C*| over 3 H W, and
  * dL/dC = sign(C - C*) / (3 H W) (sign(0) = 0), for every view (layouts of
  * image).  loss (optional, device float64 [1]) is overwritten with L. */

@@ -236,9 +236,35 @@ int gs_render_fwd(const gs_projected* p, int64_t n, const gs_bins* bins, const g
   if ((st = check_projected(p, n))) return st;
   if ((st = check_bins(bins, false))) return st;
   if (!image || !final_T || !n_contrib) return invalid("an output pointer is NULL");
-  const hipError_t e =
-      launch_render_fwd(*p, *bins, vt, read_bg(bg), image, final_T, n_contrib, depth, stream);
+  const hipError_t e = launch_render_fwd(*p, *bins, vt, read_bg(bg), image, final_T, n_contrib,
+                                         depth, nullptr, nullptr, nullptr, nullptr, stream);
   return e == hipSuccess ? GS_OK : hip_fail(e, "gs_render_fwd");
+}
+
+size_t gs_render_fwd_l1_workspace_size(const gs_views* views) {
+  ViewTable vt;
+  if (build_view_table(views, vt) != GS_OK) return 0;
+  return std::max<size_t>(256, sizeof(float) * (size_t)vt.n_tiles);
+}
+
+int gs_render_fwd_l1(const gs_projected* p, int64_t n, const gs_bins* bins,
+                     const gs_views* views, const float* bg, float* image, float* final_T,
+                     uint32_t* n_contrib, const float* target, float* dL_dimage, double* loss,
+                     void* workspace, size_t workspace_bytes, gs_stream_t stream) {
+  ViewTable vt;
+  int st = build_view_table(views, vt);
+  if (st) return st;
+  if (n < 0) return invalid("n = %lld < 0", (long long)n);
+  if ((st = check_projected(p, n))) return st;
+  if ((st = check_bins(bins, false))) return st;
+  if (!image || !final_T || !n_contrib) return invalid("an output pointer is NULL");
+  if (!target || !dL_dimage) return invalid("target or dL_dimage is NULL");
+  const size_t need = std::max<size_t>(256, sizeof(float) * (size_t)vt.n_tiles);
+  if ((st = check_workspace(workspace, workspace_bytes, need))) return st;
+  const hipError_t e =
+      launch_render_fwd(*p, *bins, vt, read_bg(bg), image, final_T, n_contrib, nullptr, target,
+                        dL_dimage, loss, static_cast<float*>(workspace), stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_render_fwd_l1");
 }
 
 size_t gs_render_bwd_workspace_size(int64_t n, const gs_views* views) {

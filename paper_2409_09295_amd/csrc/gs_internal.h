@@ -222,9 +222,12 @@ BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity)
 int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs_bins& bins,
                  uint32_t* n_keys_host, char* ws, const BinSortPlan& plan, hipStream_t s);
 
+// target == nullptr: plain compositing; otherwise also the L1 gradient into
+// dL, per-tile loss shares into tile_loss and (loss != nullptr) their sum.
 hipError_t launch_render_fwd(const gs_projected& p, const gs_bins& bins, const ViewTable& vt,
                              float3 bg, float* image, float* final_T, uint32_t* n_contrib,
-                             float* depth, hipStream_t s);
+                             float* depth, const float* target, float* dL, double* loss,
+                             float* tile_loss, hipStream_t s);
 
 struct BwdPlan {
   size_t off_grad2d, off_pose, total;

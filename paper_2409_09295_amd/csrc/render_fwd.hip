@@ -31,12 +31,15 @@ __device__ __forceinline__ uint32_t stage_splat(uint32_t g, const float2* __rest
   return reach;
 }
 
-template <int PPL>
+// L1: also the photometric L1 gradient against `target` and the tile's
+// share of the loss (written to tile_loss[tile]).
+template <int PPL, bool L1>
 __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
     ViewTable vt, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
     const float2* __restrict__ xy, const float4* __restrict__ co, const float4* __restrict__ rd,
     float3 bg, float* __restrict__ image, float* __restrict__ final_T,
-    uint32_t* __restrict__ n_contrib, float* __restrict__ depth_out) {
+    uint32_t* __restrict__ n_contrib, float* __restrict__ depth_out,
+    const float* __restrict__ target, float* __restrict__ dL, float* __restrict__ tile_loss) {
   constexpr int NT = kBlock / PPL;
   constexpr int kWords = kBlock / 64;
   __shared__ StagedSplat s_splat[kBlock];
@@ -132,41 +135,89 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
   }
   const int64_t plane = (int64_t)vi.width * vi.height;
   float* img = image + 3 * vi.pix_base;
+  // L1 against the target, as gs_l1_loss_grad computes it from the image
+  const float inv = 1.0f / (float)(3 * plane);
+  float lsum = 0.0f;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     if (!inside[k]) continue;
     const int64_t off = (int64_t)py[k] * vi.width + px[k];
-    img[off] = C0[k] + T[k] * bg.x;
-    img[plane + off] = C1[k] + T[k] * bg.y;
-    img[2 * plane + off] = C2[k] + T[k] * bg.z;
+    const float c[3] = {C0[k] + T[k] * bg.x, C1[k] + T[k] * bg.y, C2[k] + T[k] * bg.z};
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) img[ch * plane + off] = c[ch];
     final_T[vi.pix_base + off] = T[k];
     n_contrib[vi.pix_base + off] = last[k];
-    if (depth_out) depth_out[vi.pix_base + off] = D[k];
+    if (!L1 && depth_out) depth_out[vi.pix_base + off] = D[k];
+    if (L1) {
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const int64_t o = 3 * vi.pix_base + ch * plane + off;
+        const float d = c[ch] - target[o];
+        dL[o] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
+        lsum += fabsf(d);
+      }
+    }
   }
+  if (L1) {
+    __shared__ float s_l[kBlock / 64];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) lsum += __shfl_xor(lsum, d, 64);
+    if ((threadIdx.x & 63) == 0) s_l[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float t = 0.0f;
+      for (int w = 0; w < NT / 64; ++w) t += s_l[w];
+      tile_loss[tile] = t * inv;
+    }
+  }
+}
+
+// Loss = sum of the per-tile shares, in float64 and a fixed order.
+__global__ __launch_bounds__(1024) void tile_loss_sum_kernel(const float* __restrict__ tile_loss,
+                                                             int n_tiles,
+                                                             double* __restrict__ loss) {
+  __shared__ double s_acc[1024];
+  double a = 0.0;
+  for (int t = threadIdx.x; t < n_tiles; t += 1024) a += (double)tile_loss[t];
+  s_acc[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s_acc[threadIdx.x] += s_acc[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = s_acc[0];
 }
 
 }  // namespace
 
 hipError_t launch_render_fwd(const gs_projected& p, const gs_bins& bins, const ViewTable& vt,
                              float3 bg, float* image, float* final_T, uint32_t* n_contrib,
-                             float* depth, hipStream_t s) {
+                             float* depth, const float* target, float* dL, double* loss,
+                             float* tile_loss, hipStream_t s) {
   if (vt.n_tiles == 0) return hipSuccess;
   const auto* xy = reinterpret_cast<const float2*>(p.xy);
   const auto* co = reinterpret_cast<const float4*>(p.conic_opacity);
   const auto* rd = reinterpret_cast<const float4*>(p.rgb_depth);
   const int ppl = tuning(GS_TUNE_FWD_PIXELS_PER_LANE);
   const dim3 grid((unsigned)vt.n_tiles);
+  const bool l1 = target != nullptr;
+#define GS_FWD(P, L)                                                                       \
+  hipLaunchKernelGGL((render_fwd_kernel<P, L>), grid, dim3(kBlock / P), 0, s, vt, bins.ranges, \
+                     bins.values, xy, co, rd, bg, image, final_T, n_contrib, depth, target,  \
+                     dL, tile_loss)
   kernel_event_start(GS_KERNEL_RENDER_FWD, s);
-  if (ppl == 4)
-    hipLaunchKernelGGL(render_fwd_kernel<4>, grid, dim3(kBlock / 4), 0, s, vt, bins.ranges,
-                       bins.values, xy, co, rd, bg, image, final_T, n_contrib, depth);
-  else if (ppl == 2)
-    hipLaunchKernelGGL(render_fwd_kernel<2>, grid, dim3(kBlock / 2), 0, s, vt, bins.ranges,
-                       bins.values, xy, co, rd, bg, image, final_T, n_contrib, depth);
-  else
-    hipLaunchKernelGGL(render_fwd_kernel<1>, grid, dim3(kBlock), 0, s, vt, bins.ranges,
-                       bins.values, xy, co, rd, bg, image, final_T, n_contrib, depth);
+  if (ppl == 4) {
+    if (l1) GS_FWD(4, true); else GS_FWD(4, false);
+  } else if (ppl == 2) {
+    if (l1) GS_FWD(2, true); else GS_FWD(2, false);
+  } else {
+    if (l1) GS_FWD(1, true); else GS_FWD(1, false);
+  }
+#undef GS_FWD
   kernel_event_stop(GS_KERNEL_RENDER_FWD, s);
+  if (l1 && loss)
+    hipLaunchKernelGGL(tile_loss_sum_kernel, dim3(1), dim3(1024), 0, s, tile_loss, vt.n_tiles,
+                       loss);
   return hipGetLastError();
 }
 

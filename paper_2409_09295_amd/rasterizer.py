@@ -45,8 +45,7 @@ class Rasterizer:
         self.bins = gs.Bins.empty(capacity, self.n_tiles, self.device)
         self.sort_ws = gs.workspace(gs.gs_bin_sort_workspace_size(self.n, self.views, capacity), self.device)
 
-    def forward(self, g: gs.Gaussians, bg: Sequence[float] = (0.0, 0.0, 0.0)) -> torch.Tensor:
-        """Renders every view; returns the packed image buffer [V][3][H][W]."""
+    def _project_and_bin(self, g: gs.Gaussians):
         if g.n != self.n:
             raise ValueError("Gaussian count changed")
         gs.gs_preprocess(g, self.views, self.proj)
@@ -58,8 +57,24 @@ class Rasterizer:
                 if e.status != gs.GS_ERR_CAPACITY or e.required <= self.bins.capacity:
                     raise
                 self._alloc_bins(int(e.required * 1.25) + 1024)
+
+    def forward(self, g: gs.Gaussians, bg: Sequence[float] = (0.0, 0.0, 0.0)) -> torch.Tensor:
+        """Renders every view; returns the packed image buffer [V][3][H][W]."""
+        self._project_and_bin(g)
         gs.gs_render_fwd(self.proj, self.n, self.bins, self.views, bg, self.image, self.final_T,
                          self.n_contrib, self.depth)
+        return self.image
+
+    def forward_l1(self, g: gs.Gaussians, target: torch.Tensor, dL_dimage: torch.Tensor,
+                   loss: Optional[torch.Tensor] = None,
+                   bg: Sequence[float] = (0.0, 0.0, 0.0)) -> torch.Tensor:
+        """forward() plus the L1 photometric gradient against ``target`` (and
+        the loss) in the same compositing pass."""
+        self._project_and_bin(g)
+        if getattr(self, "_l1_ws", None) is None:
+            self._l1_ws = gs.workspace(gs.gs_render_fwd_l1_workspace_size(self.views), self.device)
+        gs.gs_render_fwd_l1(self.proj, self.n, self.bins, self.views, bg, self.image, self.final_T,
+                            self.n_contrib, target, dL_dimage, loss, self._l1_ws)
         return self.image
 
     def backward(self, g: gs.Gaussians, dL_dimage: torch.Tensor, grads: gs.Grads, flags: int = 0,

@@ -88,6 +88,7 @@ class BatchedStep:
         self.dL = torch.zeros(3 * P, dtype=torch.float32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
         self.bwd_ws = gs.workspace(gs.gs_render_bwd_workspace_size(self.n, views), dev)
+        self.l1_ws = gs.workspace(gs.gs_render_fwd_l1_workspace_size(views), dev)
         self.adam = _AdamState(g, lrs or DEFAULT_LR)
         self.n_tiles = views.n_tiles
         if capacity is None:
@@ -120,9 +121,9 @@ class BatchedStep:
     def _body(self):
         gs.gs_preprocess(self.g, self.views, self.proj)
         gs.gs_bin_sort(self.proj, self.n, self.views, self.bins, self.sort_ws, sync=False)
-        gs.gs_render_fwd(self.proj, self.n, self.bins, self.views, self.bg, self.image, self.final_T,
-                         self.n_contrib)
-        gs.gs_l1_loss_grad(self.image, self.targets, self.views, self.dL, self.loss)
+        gs.gs_render_fwd_l1(self.proj, self.n, self.bins, self.views, self.bg, self.image,
+                            self.final_T, self.n_contrib, self.targets, self.dL, self.loss,
+                            self.l1_ws)
         flags = gs.GS_BWD_OVERWRITE | (0 if self.pose else gs.GS_BWD_NO_POSE)
         gs.gs_render_bwd(self.g, self.proj, self.bins, self.views, self.bg, self.dL, self.final_T,
                          self.n_contrib, self.grads, flags, self.bwd_ws)
@@ -196,8 +197,7 @@ class PlainStep:
     def step(self):
         self.xi.zero_()
         for k, (v, r, t, dl) in enumerate(zip(self.views, self.rasts, self.targets, self.dL)):
-            img = r.forward(self.g, self.bg)
-            gs.gs_l1_loss_grad(img, t, v, dl)
+            r.forward_l1(self.g, t, dl, bg=self.bg)
             grads = gs.Grads(self.grads.means, self.grads.log_scales, self.grads.quats,
                              self.grads.opacity_logits, self.grads.sh, self.xi[k:k + 1])
             flags = (gs.GS_BWD_OVERWRITE if k == 0 else 0) | (0 if self.pose else gs.GS_BWD_NO_POSE)

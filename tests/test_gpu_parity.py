@@ -417,6 +417,33 @@ def test_adam_groups_match_per_group_calls(gs):
         torch.testing.assert_close(x, y, rtol=0, atol=0)
 
 
+@pytest.mark.parametrize("ppl_setting", PPL_SETTINGS, indirect=True)
+def test_render_fwd_l1_matches_separate_calls(gs, ppl_setting):
+    """The fused compositing + L1 pass gives the same image, final T,
+    n_contrib and dL/dC bit for bit as gs_render_fwd then gs_l1_loss_grad,
+    and the same loss up to summation order (ragged views, background)."""
+    cams = BIN_CASES["ragged_multi_view"]
+    sp = scenes.random_splats(3000, cams, seed=41)
+    views, proj, bins, nk = _gpu_bins(gs, sp, cams)
+    P = views.n_pixels
+    bg = (0.1, 0.3, 0.2)
+    rng = np.random.default_rng(42)
+    target = torch.from_numpy(rng.random(3 * P).astype(np.float32)).to(DEV)
+    a = [torch.empty(3 * P, device=DEV), torch.empty(P, device=DEV),
+         torch.empty(P, dtype=torch.int32, device=DEV), torch.empty(3 * P, device=DEV),
+         torch.zeros(1, dtype=torch.float64, device=DEV)]
+    b = [t.clone() for t in a]
+    N = sp.radius.shape[1]
+    gs.gs_render_fwd(proj, N, bins, views, bg, a[0], a[1], a[2])
+    gs.gs_l1_loss_grad(a[0], target, views, a[3], a[4])
+    ws = gs.workspace(gs.gs_render_fwd_l1_workspace_size(views))
+    gs.gs_render_fwd_l1(proj, N, bins, views, bg, b[0], b[1], b[2], target, b[3], b[4], ws)
+    torch.cuda.synchronize()
+    for x, y in zip(a[:4], b[:4]):
+        torch.testing.assert_close(x, y, rtol=0, atol=0)
+    np.testing.assert_allclose(float(b[4].item()), float(a[4].item()), rtol=1e-6)
+
+
 def test_l1_loss_grad(gs):
     cams = [scenes.pinhole(50, 30, 40.0), scenes.pinhole(17, 9, 10.0)]
     views = gs.Views(cams)
