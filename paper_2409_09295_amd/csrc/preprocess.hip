@@ -11,7 +11,7 @@
 
 namespace gsmi {
 
-constexpr int kViewsPerLane = 4;
+constexpr int kViewsPerLane = 32;
 
 template <int DEG>
 __global__ __launch_bounds__(256) void preprocess_kernel(
