@@ -504,6 +504,18 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
   }
 }
 
+// Clears the partials of visible splats (radius > 0): the only slots the
+// reverse walk adds to and the projection backward reads.
+__global__ __launch_bounds__(256) void zero_visible_kernel(const int32_t* __restrict__ radius,
+                                                           int64_t n_entries,
+                                                           float* __restrict__ grad2d) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_entries || radius[e] <= 0) return;
+  float* d = grad2d + e * 9;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) d[k] = 0.0f;
+}
+
 // One workgroup per (view, component): strided float64 sum over the
 // per-workgroup partials, then a tree reduction in LDS (fixed order).
 __global__ __launch_bounds__(256) void pose_reduce_kernel(const double* __restrict__ pose_part,
@@ -574,8 +586,11 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
                              char* ws, const BwdPlan& plan, hipStream_t s) {
   float* grad2d = reinterpret_cast<float*>(ws + plan.off_grad2d);
   double* pose_part = reinterpret_cast<double*>(ws + plan.off_pose);
-  const int64_t n2d = 9 * g.n * (int64_t)vt.n_views;
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(grad2d), 0u, n2d, s);
+  const int64_t n_entries = g.n * (int64_t)vt.n_views;
+  if (n_entries > 0)
+    hipLaunchKernelGGL(zero_visible_kernel, dim3((unsigned)((n_entries + 255) / 256)), dim3(256), 0,
+                       s, p.radius, n_entries, grad2d);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (vt.n_tiles > 0) {
     const auto* xy = reinterpret_cast<const float2*>(p.xy);
