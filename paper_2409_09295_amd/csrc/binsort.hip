@@ -1,20 +1,25 @@
 // gs_bin_sort: tile binning and (tile, depth) ordering of the splats.
 //
 //   count     one lane per (view, splat): tile rectangle (float64 from the
-//             float32 centre) -> number of tiles
-//   scan      device-wide exclusive scan of the counts (reduce / scan
-//             partials / down-sweep), total in 64 bits
-//   emit      wave-cooperative emission: the 64 splats of a wave own a
-//             contiguous key range; the wave walks that range 64 keys at a
-//             time and each lane locates its owner by binary search over the
-//             wave's 64 start offsets, so stores are contiguous and big
-//             rectangles do not serialise one lane
-//   sort      LSD radix sort, 8-bit digits over the used key bits
-//             (32 depth bits + ceil(log2 tiles) tile bits).  Per pass: block
-//             histograms, a scan of the digit-major histogram, then a
-//             down-sweep that ranks keys within the block with wave ballots
-//             (stable), stages them in LDS in digit order and writes each
-//             digit run contiguously
+//             float32 centre) -> number of tiles, and whether it has any
+//   depth     the splats with tiles are compacted in entry order (a scan of
+//             the flags) and sorted by their float32 depth bits with a
+//             stable LSD radix sort, so equal depths keep entry order; this
+//             sorts one item per visible splat instead of one per key
+//   scan      device-wide exclusive scan of the tile counts in that order,
+//             total in 64 bits (the key count)
+//   emit      wave-cooperative emission in depth order: the 64 splats of a
+//             wave own a contiguous key range; the wave walks that range 64
+//             keys at a time and each lane locates its owner by binary search
+//             over the wave's 64 start offsets, so stores are contiguous and
+//             big rectangles do not serialise one lane
+//   tile sort stable LSD radix sort of the keys on their tile bits only
+//             (ceil(log2 tiles) bits): keys of a tile keep the depth order of
+//             their emission, giving the (tile, depth, entry) order.  Per
+//             pass: block histograms, a row scan of the digit-major
+//             histogram, then a down-sweep that ranks keys within the block
+//             with wave ballots (stable), stages them in LDS in digit order
+//             and writes each digit run contiguously
 //   ranges    [start, end) per global tile from tile boundaries in the
 //             sorted keys
 #include "gs_internal.h"
@@ -157,7 +162,8 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* __restrict__ p,
 __global__ __launch_bounds__(256) void count_kernel(const float2* __restrict__ xy,
                                                     const int32_t* __restrict__ radius,
                                                     int64_t n_entries, int64_t n, ViewTable vt,
-                                                    uint32_t* __restrict__ counts) {
+                                                    uint32_t* __restrict__ counts,
+                                                    uint32_t* __restrict__ binned) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_entries) return;
   const int v = (int)(e / n);
@@ -165,14 +171,45 @@ __global__ __launch_bounds__(256) void count_kernel(const float2* __restrict__ x
   Rect rc;
   const float2 c = xy[e];
   const bool ok = tile_rect(c.x, c.y, radius[e], vi.width, vi.height, rc);
-  counts[e] = ok ? (uint32_t)((rc.x1 - rc.x0) * (rc.y1 - rc.y0)) : 0u;
+  const uint32_t cnt = ok ? (uint32_t)((rc.x1 - rc.x0) * (rc.y1 - rc.y0)) : 0u;
+  counts[e] = cnt;
+  binned[e] = cnt > 0 ? 1u : 0u;
 }
 
+// Splats with at least one tile, in entry order: depth bits and entry index.
+__global__ __launch_bounds__(256) void compact_kernel(const uint32_t* __restrict__ counts,
+                                                      const uint32_t* __restrict__ pos,
+                                                      const float4* __restrict__ rd,
+                                                      int64_t n_entries,
+                                                      uint32_t* __restrict__ dkey,
+                                                      uint32_t* __restrict__ dval) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_entries || counts[e] == 0) return;
+  const uint32_t j = pos[e];
+  dkey[j] = __float_as_uint(rd[e].w);
+  dval[j] = (uint32_t)e;
+}
+
+// Tile counts in depth order (zero past the binned splats).
+__global__ __launch_bounds__(256) void gather_counts_kernel(const uint32_t* __restrict__ order,
+                                                            const uint32_t* __restrict__ n_order,
+                                                            const uint32_t* __restrict__ counts,
+                                                            int64_t n_entries,
+                                                            uint32_t* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_entries) return;
+  out[j] = j < (int64_t)*n_order ? counts[order[j]] : 0u;
+}
+
+// Items j < *n_items are splats order[j] (depth order); item j's keys start at
+// offsets[j].
 __global__ __launch_bounds__(256) void emit_kernel(const float2* __restrict__ xy,
                                                    const int32_t* __restrict__ radius,
                                                    const float4* __restrict__ rd,
+                                                   const uint32_t* __restrict__ order,
+                                                   const uint32_t* __restrict__ n_items,
                                                    const uint32_t* __restrict__ offsets,
-                                                   int64_t n_entries, int64_t n, ViewTable vt,
+                                                   int64_t n, ViewTable vt,
                                                    const uint64_t* __restrict__ total,
                                                    int64_t capacity, uint64_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals) {
@@ -182,22 +219,25 @@ __global__ __launch_bounds__(256) void emit_kernel(const float2* __restrict__ xy
   __shared__ uint32_t s_w[4][64];
   __shared__ uint32_t s_tx[4][64];
   __shared__ uint32_t s_db[4][64];
+  __shared__ uint32_t s_e[4][64];
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t start = 0xFFFFFFFFu, cnt = 0, t0 = 0, rw = 1, tx = 1, db = 0;
-  if (e < n_entries) {
-    const int v = (int)(e / n);
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = j < (int64_t)*n_items;
+  uint32_t start = 0xFFFFFFFFu, cnt = 0, t0 = 0, rw = 1, tx = 1, db = 0, ent = 0;
+  if (valid) {
+    ent = order[j];
+    const int v = (int)(ent / n);
     const ViewInfo& vi = vt.v[v];
     Rect rc;
-    const float2 c = xy[e];
-    const bool ok = tile_rect(c.x, c.y, radius[e], vi.width, vi.height, rc);
-    start = offsets[e];
+    const float2 c = xy[ent];
+    const bool ok = tile_rect(c.x, c.y, radius[ent], vi.width, vi.height, rc);
+    start = offsets[j];
     if (ok) {
       cnt = (uint32_t)((rc.x1 - rc.x0) * (rc.y1 - rc.y0));
       t0 = (uint32_t)(vi.tile_base + rc.y0 * vi.tiles_x + rc.x0);
       rw = (uint32_t)(rc.x1 - rc.x0);
       tx = (uint32_t)vi.tiles_x;
-      db = __float_as_uint(rd[e].w);
+      db = __float_as_uint(rd[ent].w);
     }
   }
   s_start[w][lane] = start;
@@ -205,8 +245,8 @@ __global__ __launch_bounds__(256) void emit_kernel(const float2* __restrict__ xy
   s_w[w][lane] = rw;
   s_tx[w][lane] = tx;
   s_db[w][lane] = db;
+  s_e[w][lane] = ent;
   // wave range [first start, last end)
-  const bool valid = e < n_entries;
   const uint64_t vmask = __ballot(valid);
   if (vmask == 0) return;
   const uint32_t wbase = __shfl(start, 0, 64);
@@ -214,19 +254,18 @@ __global__ __launch_bounds__(256) void emit_kernel(const float2* __restrict__ xy
   const uint32_t wend = __shfl(start + cnt, last, 64);
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const int64_t ebase = (int64_t)blockIdx.x * blockDim.x + w * 64;
   for (uint32_t pos = wbase + lane; pos < wend; pos += 64) {
     int lo = 0, hi = (int)last;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (s_start[w][mid] <= pos) lo = mid; else hi = mid - 1;
     }
-    const uint32_t j = pos - s_start[w][lo];
+    const uint32_t jj = pos - s_start[w][lo];
     const uint32_t width = s_w[w][lo];
-    const uint32_t row = j / width;
-    const uint32_t tile = s_t0[w][lo] + row * s_tx[w][lo] + (j - row * width);
+    const uint32_t row = jj / width;
+    const uint32_t tile = s_t0[w][lo] + row * s_tx[w][lo] + (jj - row * width);
     keys[pos] = ((uint64_t)tile << 32) | (uint64_t)s_db[w][lo];
-    vals[pos] = (uint32_t)(ebase + lo);
+    vals[pos] = s_e[w][lo];
   }
 }
 
@@ -239,7 +278,8 @@ __device__ __forceinline__ uint32_t valid_keys(const uint32_t* n_keys, int64_t c
   return ((int64_t)n <= capacity) ? n : 0u;
 }
 
-__global__ __launch_bounds__(256) void radix_upsweep_kernel(const uint64_t* __restrict__ keys,
+template <typename K>
+__global__ __launch_bounds__(256) void radix_upsweep_kernel(const K* __restrict__ keys,
                                                             const uint32_t* __restrict__ n_keys,
                                                             int64_t capacity, int shift,
                                                             uint32_t* __restrict__ hist,
@@ -282,9 +322,10 @@ __global__ __launch_bounds__(256) void hist_row_scan_kernel(uint32_t* __restrict
   if (threadIdx.x == 0) tot[blockIdx.x] = total;
 }
 
+template <typename K>
 __global__ __launch_bounds__(256) void radix_downsweep_kernel(
-    const uint64_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
-    uint64_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
+    const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ n_keys, int64_t capacity, int shift,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot, uint32_t nblocks) {
   __shared__ uint32_t s_wcnt[4][256];
@@ -292,7 +333,7 @@ __global__ __launch_bounds__(256) void radix_downsweep_kernel(
   __shared__ uint32_t s_dstart[256];
   __shared__ uint32_t s_gbase[256];
   __shared__ uint32_t s_wave[4];
-  __shared__ uint64_t s_keys[kSortChunk];
+  __shared__ K s_keys[kSortChunk];
   __shared__ uint32_t s_vals[kSortChunk];
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
   for (int k = threadIdx.x; k < 4 * 256; k += 256) (&s_wcnt[0][0])[k] = 0;
@@ -300,14 +341,14 @@ __global__ __launch_bounds__(256) void radix_downsweep_kernel(
   const uint32_t n = valid_keys(n_keys, capacity);
   const int64_t bstart = (int64_t)blockIdx.x * kSortChunk;
   const int64_t base = bstart + w * (kSortChunk / 4);
-  uint64_t key[kSortItems];
+  K key[kSortItems];
   uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
     const int64_t idx = base + j * 64 + lane;
     const bool valid = idx < n;
-    key[j] = valid ? keys_in[idx] : 0ull;
+    key[j] = valid ? keys_in[idx] : (K)0;
     val[j] = valid ? vals_in[idx] : 0u;
     const uint32_t d = (uint32_t)(key[j] >> shift) & 255u;
     dig[j] = d;
@@ -356,7 +397,7 @@ __global__ __launch_bounds__(256) void radix_downsweep_kernel(
   for (int q = 0; q < kSortItems; ++q) {
     const int pos = q * 256 + threadIdx.x;
     if (pos < nb_valid) {
-      const uint64_t k = s_keys[pos];
+      const K k = s_keys[pos];
       const uint32_t d = (uint32_t)(k >> shift) & 255u;
       const uint32_t o = s_gbase[d] + (uint32_t)pos - s_dstart[d];
       keys_out[o] = k;
@@ -395,44 +436,86 @@ BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity)
   P.n_tiles = vt.n_tiles;
   int tile_bits = 0;
   while ((int64_t(1) << tile_bits) < (int64_t)vt.n_tiles) ++tile_bits;
-  P.passes = (32 + tile_bits + 7) / 8;
+  P.passes = (tile_bits + 7) / 8;   // tile digits of the keys (depth is ordered beforehand)
   P.scan_blocks = (P.n_entries + kScanChunk - 1) / kScanChunk;
   P.sort_blocks = (capacity + kSortChunk - 1) / kSortChunk;
-  const int64_t hist_n = 256 * std::max<int64_t>(P.sort_blocks, 1);
+  const int64_t depth_blocks = (P.n_entries + kSortChunk - 1) / kSortChunk;
+  const int64_t hist_n = 256 * std::max<int64_t>(std::max(P.sort_blocks, depth_blocks), 1);
+  const size_t ne = sizeof(uint32_t) * (size_t)P.n_entries;
   size_t off = 0;
-  P.off_counts = off;    off += align_up(sizeof(uint32_t) * P.n_entries);
-  P.off_offsets = off;   off += align_up(sizeof(uint32_t) * P.n_entries);
+  P.off_counts = off;    off += align_up(ne);
+  P.off_offsets = off;   off += align_up(ne);   // binned flags -> positions; sorted offsets
+  P.off_dkey = off;      off += align_up(2 * ne);
+  P.off_dval = off;      off += align_up(2 * ne);
   P.off_scan_part = off; off += align_up(sizeof(uint64_t) * (P.scan_blocks + 1));
   P.off_keys_alt = off;  off += align_up(sizeof(uint64_t) * capacity);
   P.off_vals_alt = off;  off += align_up(sizeof(uint32_t) * capacity);
   P.off_hist = off;      off += align_up(sizeof(uint32_t) * hist_n);
   P.off_hist_part = off; off += align_up(sizeof(uint32_t) * 256);   // digit totals
-  P.off_flag = off;      off += align_up(sizeof(uint64_t) * 4);
+  P.off_flag = off;      off += align_up(sizeof(uint64_t) * 8);
   P.total = off;
   return P;
+}
+
+// One LSD radix pass over n (device count, at most cap) keys of type K.
+template <typename K>
+void radix_pass(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, const uint32_t* n,
+                int64_t cap, int shift, uint32_t* hist, uint32_t* digit_tot, hipStream_t s) {
+  const uint32_t nblocks = (uint32_t)((cap + kSortChunk - 1) / kSortChunk);
+  hipLaunchKernelGGL((radix_upsweep_kernel<K>), dim3(nblocks), dim3(256), 0, s, kin, n, cap, shift,
+                     hist, nblocks);
+  hipLaunchKernelGGL(hist_row_scan_kernel, dim3(256), dim3(256), 0, s, hist, nblocks, digit_tot);
+  hipLaunchKernelGGL((radix_downsweep_kernel<K>), dim3(nblocks), dim3(256), 0, s, kin, vin, kout,
+                     vout, n, cap, shift, hist, digit_tot, nblocks);
 }
 
 int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs_bins& bins,
                  uint32_t* n_keys_host, char* ws, const BinSortPlan& P, hipStream_t s) {
   auto* counts = reinterpret_cast<uint32_t*>(ws + P.off_counts);
   auto* offsets = reinterpret_cast<uint32_t*>(ws + P.off_offsets);
+  auto* dkey = reinterpret_cast<uint32_t*>(ws + P.off_dkey);
+  auto* dval = reinterpret_cast<uint32_t*>(ws + P.off_dval);
   auto* part = reinterpret_cast<uint64_t*>(ws + P.off_scan_part);
   auto* keys_alt = reinterpret_cast<uint64_t*>(ws + P.off_keys_alt);
   auto* vals_alt = reinterpret_cast<uint32_t*>(ws + P.off_vals_alt);
   auto* hist = reinterpret_cast<uint32_t*>(ws + P.off_hist);
-  auto* hist_part = reinterpret_cast<uint64_t*>(ws + P.off_hist_part);
-  auto* flag = reinterpret_cast<uint64_t*>(ws + P.off_flag);   // [0] total keys, [1] scratch
+  auto* digit_tot = reinterpret_cast<uint32_t*>(ws + P.off_hist_part);
+  auto* flag = reinterpret_cast<uint64_t*>(ws + P.off_flag);   // [0] keys, [1] binned splats
+  auto* n_binned = reinterpret_cast<uint32_t*>(flag + 2);
   const auto* xy = reinterpret_cast<const float2*>(p.xy);
   const auto* rd = reinterpret_cast<const float4*>(p.rgb_depth);
+  const int64_t ne = P.n_entries;
+  const unsigned eblocks = (unsigned)((ne + 255) / 256);
   hipError_t e;
 
+  kernel_event_start(GS_KERNEL_BIN_SORT, s);
   if ((e = launch_fill_u32(bins.ranges, 0u, 2 * (int64_t)vt.n_tiles, s)) != hipSuccess)
     return hip_fail(e, "fill ranges");
-  if (P.n_entries > 0)
-    hipLaunchKernelGGL(count_kernel, dim3((unsigned)((P.n_entries + 255) / 256)), dim3(256), 0, s,
-                       xy, p.radius, P.n_entries, n, vt, counts);
-  scan_u32(counts, offsets, P.n_entries, part, flag, bins.n_keys, s);
-  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "count/scan launch");
+  // 1. tiles per splat; binned splats compacted in entry order with their depth
+  if (ne > 0) {
+    hipLaunchKernelGGL(count_kernel, dim3(eblocks), dim3(256), 0, s, xy, p.radius, ne, n, vt,
+                       counts, offsets);
+    scan_u32(offsets, offsets, ne, part, flag + 1, n_binned, s);
+    hipLaunchKernelGGL(compact_kernel, dim3(eblocks), dim3(256), 0, s, counts, offsets, rd, ne,
+                       dkey, dval);
+    // 2. stable sort of the binned splats by depth (ties keep entry order)
+    uint32_t *ka = dkey, *va = dval, *kb = dkey + ne, *vb = dval + ne;
+    for (int pass = 0; pass < 4; ++pass) {
+      radix_pass<uint32_t>(ka, va, kb, vb, n_binned, ne, 8 * pass, hist, digit_tot, s);
+      std::swap(ka, kb);
+      std::swap(va, vb);
+    }
+    // ka/va (= dkey/dval after an even number of passes) hold the depth order
+    // 3. key offsets in depth order; their total is the key count
+    hipLaunchKernelGGL(gather_counts_kernel, dim3(eblocks), dim3(256), 0, s, va, n_binned, counts,
+                       ne, offsets);
+    scan_u32(offsets, offsets, ne, part, flag, bins.n_keys, s);
+  } else {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, s,
+                       reinterpret_cast<uint32_t*>(flag), 0u, (int64_t)16);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, s, bins.n_keys, 0u, (int64_t)1);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "count/depth-order launch");
 
   int64_t n_sort = P.capacity;   // keys the sort grid covers
   if (n_keys_host) {
@@ -448,26 +531,21 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
     }
     n_sort = (int64_t)total;
   }
-  if (n_sort == 0) return GS_OK;
+  if (n_sort == 0 || ne == 0) {
+    kernel_event_stop(GS_KERNEL_BIN_SORT, s);
+    return GS_OK;
+  }
 
+  // 4. keys emitted in depth order, then a stable sort on the tile bits only
   uint64_t* kA = (P.passes % 2 == 0) ? bins.keys : keys_alt;
   uint32_t* vA = (P.passes % 2 == 0) ? bins.values : vals_alt;
   uint64_t* kB = (P.passes % 2 == 0) ? keys_alt : bins.keys;
   uint32_t* vB = (P.passes % 2 == 0) ? vals_alt : bins.values;
-  kernel_event_start(GS_KERNEL_BIN_SORT, s);
-  if (P.n_entries > 0)
-    hipLaunchKernelGGL(emit_kernel, dim3((unsigned)((P.n_entries + 255) / 256)), dim3(256), 0, s,
-                       xy, p.radius, rd, offsets, P.n_entries, n, vt, flag, P.capacity, kA, vA);
-  const uint32_t nblocks = (uint32_t)((n_sort + kSortChunk - 1) / kSortChunk);
+  hipLaunchKernelGGL(emit_kernel, dim3(eblocks), dim3(256), 0, s, xy, p.radius, rd, dval,
+                     n_binned, offsets, n, vt, flag, P.capacity, kA, vA);
   for (int pass = 0; pass < P.passes; ++pass) {
-    const int shift = 8 * pass;
-    hipLaunchKernelGGL(radix_upsweep_kernel, dim3(nblocks), dim3(256), 0, s, kA, bins.n_keys,
-                       P.capacity, shift, hist, nblocks);
-    hipLaunchKernelGGL(hist_row_scan_kernel, dim3(256), dim3(256), 0, s, hist, nblocks,
-                       reinterpret_cast<uint32_t*>(hist_part));
-    hipLaunchKernelGGL(radix_downsweep_kernel, dim3(nblocks), dim3(256), 0, s, kA, vA, kB, vB,
-                       bins.n_keys, P.capacity, shift, hist,
-                       reinterpret_cast<const uint32_t*>(hist_part), nblocks);
+    radix_pass<uint64_t>(kA, vA, kB, vB, bins.n_keys, std::min<int64_t>(n_sort, P.capacity),
+                         32 + 8 * pass, hist, digit_tot, s);
     std::swap(kA, kB);
     std::swap(vA, vB);
   }

@@ -211,12 +211,12 @@ struct BinSortPlan {
   int64_t n_entries;     // V * n
   int64_t capacity;
   int32_t n_tiles;
-  int32_t passes;        // radix passes of 8 bits
+  int32_t passes;        // radix passes of 8 bits over the keys' tile bits
   int64_t scan_blocks;   // blocks of the entry scan
   int64_t sort_blocks;   // blocks of the radix sort at capacity
   // workspace layout (byte offsets)
-  size_t off_counts, off_offsets, off_scan_part, off_keys_alt, off_vals_alt, off_hist,
-      off_hist_part, off_flag, total;
+  size_t off_counts, off_offsets, off_dkey, off_dval, off_scan_part, off_keys_alt, off_vals_alt,
+      off_hist, off_hist_part, off_flag, total;
 };
 BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity);
 int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs_bins& bins,
