@@ -43,13 +43,14 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 # VALU instructions per (pixel, splat) pair in the per-pixel body of the
 # compositing loops, counted in the gfx950 assembly of this library: every
-# walked pair pays the evaluation (offset, quadratic form, exp2, opacity
-# product, clamp and the two tests); a pair that is blended pays the rest.
+# walked pair pays the evaluation (offset, quadratic form, clamp, exp2,
+# opacity product, alpha clamp and the two tests; the forward adds the
+# transmittance product and its test); a pair that is blended pays the rest.
 # Wave-level overheads (LDS staging, the 9-value reduction and its atomics,
 # loop control) are not counted: they are what separates the achieved rate
 # from the peak.
-BWD_VALU_EVAL, BWD_VALU_BLEND = 11, 35
-FWD_VALU_EVAL, FWD_VALU_BLEND = 12, 11
+BWD_VALU_EVAL, BWD_VALU_BLEND = 13, 28
+FWD_VALU_EVAL, FWD_VALU_BLEND = 16, 4
 # Fraction of walked pairs that are blended, measured by the oracle on the
 # 200k-Gaussian room at 640x480 (used when the oracle leg is skipped).
 DEFAULT_BLEND_FRACTION = 0.44
