@@ -208,8 +208,8 @@ int64_t gs_num_pixels(const gs_views* views);
 
 /* Projection of every Gaussian into every view (the activations, covariance,
  * view transform, projection, EWA, extent and colour steps above).
- * out arrays hold [n_views][n] entries.  Culled entries get radius 0 and
- * zeroed splat fields. */
+ * out arrays hold [n_views][n] entries.  Culled entries get radius 0; their
+ * other fields are left as they were (no consumer reads them). */
 int gs_preprocess(const gs_gaussians* g, const gs_views* views, gs_projected* out,
                   gs_stream_t stream);
 

@@ -39,10 +39,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
       rd[o] = make_float4(S.rgb[0], S.rgb[1], S.rgb[2], S.p[2]);
       radius[o] = S.radius;
     } else {
-      xy[o] = make_float2(0.f, 0.f);
-      co[o] = make_float4(0.f, 0.f, 0.f, 0.f);
-      rd[o] = make_float4(0.f, 0.f, 0.f, 0.f);
-      radius[o] = 0;
+      radius[o] = 0;   // the other fields of a culled entry are never read
     }
   }
 }
