@@ -224,48 +224,52 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
         m &= ~(uint64_t(1) << bit);
         const int j = 64 * w + bit;
         const uint32_t pos = (uint32_t)(bstart + j);
-        float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, g4 = 0.f, g5 = 0.f, g6 = 0.f, g7 = 0.f,
-              g8 = 0.f;
-        bool contrib = false;
         const float4 geo = s_splat[j].geo;
         const float4 app = s_splat[j].app;
         const float4 col = s_splat[j].col;
         const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(col.w)) : ~0u;
+        // Per pixel slot, branch-free over the wave: a lane whose pixel does
+        // not blend this splat takes alpha = 0, which leaves T and S exactly
+        // as they were and contributes exact zeros.  The first slot with a
+        // blending lane writes the partial sums, later ones add.
+        float g0, g1, g2, g3, g4, g5, g6, g7, g8;
+        bool started = false;
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
           // slot-uniform skips: quadrant not reached, or every pixel of the
           // slot in this wave already past its last blended splat
           if (!(reach & qbit[k]) || pos >= slot_last[k]) continue;
           float alpha, raw, G, dx, dy;
-          const bool ok = eval_alpha_all(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy);
-          if (!ok || pos >= last[k]) continue;
-          contrib = true;
-          const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - alpha);
-          const float wgt = alpha * Tk;
-          g6 += wgt * dC0[k];
-          g7 += wgt * dC1[k];
-          g8 += wgt * dC2[k];
+          const bool ok =
+              eval_alpha_all(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy) && pos < last[k];
+          if (!__ballot(ok)) continue;
+          const float a = ok ? alpha : 0.0f;
+          const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - a);
+          const float wgt = a * Tk;
           const float d0 = col.x - S0[k], d1 = col.y - S1[k], d2 = col.z - S2[k];
           const float dalpha = Tk * (d0 * dC0[k] + d1 * dC1[k] + d2 * dC2[k]);
           // colour behind the next splat in front: alpha c + (1 - alpha) S
-          S0[k] = __builtin_fmaf(alpha, d0, S0[k]);
-          S1[k] = __builtin_fmaf(alpha, d1, S1[k]);
-          S2[k] = __builtin_fmaf(alpha, d2, S2[k]);
+          S0[k] = __builtin_fmaf(a, d0, S0[k]);
+          S1[k] = __builtin_fmaf(a, d1, S1[k]);
+          S2[k] = __builtin_fmaf(a, d2, S2[k]);
           T[k] = Tk;
           // below the 0.99 clamp alpha = o G: d alpha/do = G, d alpha/dpower = alpha
-          const float live = raw <= kAlphaMax ? dalpha : 0.0f;
-          g5 += G * live;
-          const float gP = alpha * live;   // dL/dpower
+          const float live = (ok && raw <= kAlphaMax) ? dalpha : 0.0f;
+          const float gP = a * live;   // dL/dpower
           const float gdx = gP * dx, gdy = gP * dy;
           // d power/du = Q00 dx + Q01 dy (and likewise v): the conic factor is
           // the same for every pixel, so only sum(gP d) is accumulated here
-          g0 += gdx;
-          g1 += gdy;
-          g2 += gdx * dx;
-          g3 += gdx * dy;
-          g4 += gdy * dy;
+          const float v2 = gdx * dx, v3 = gdx * dy, v4 = gdy * dy, v5 = G * live;
+          const float v6 = wgt * dC0[k], v7 = wgt * dC1[k], v8 = wgt * dC2[k];
+          if (k == 0 || !started) {
+            g0 = gdx; g1 = gdy; g2 = v2; g3 = v3; g4 = v4; g5 = v5; g6 = v6; g7 = v7; g8 = v8;
+          } else {
+            g0 += gdx; g1 += gdy; g2 += v2; g3 += v3; g4 += v4; g5 += v5; g6 += v6; g7 += v7;
+            g8 += v8;
+          }
+          started = true;
         }
-        if (__ballot(contrib)) {
+        if (started) {
           const Reduced9 r = wave_reduce9(g0, g1, g2, g3, g4, g5, g6, g7, g8);
           if ((lane & 15) == 0) {
             const int64_t base = (int64_t)__float_as_uint(app.w) * 9;
