@@ -226,6 +226,7 @@ def main():
 
     # algorithmic work of the reverse tile walk: list positions each pixel walks
     pairs_bwd = int(step.n_contrib.to(torch.int64).sum().item())
+    n_visible = int((step.proj.radius > 0).sum().item())
     del step
     torch.cuda.empty_cache()
 
@@ -297,10 +298,16 @@ def main():
 
     # HBM-bound stages: algorithmic bytes per launch / event-timed duration
     K = (wl.gmap.sh_degree + 1) ** 2
-    pre_bytes = g.n * 4 * (3 + 3 + 4 + 1 + 3 * K) + g.n * len(wl.cams) * (8 + 16 + 16 + 4)
-    key_bits = max(1, math.ceil(math.log2(max(views.n_tiles, 2)))) + 32
-    passes = math.ceil(key_bits / 8)
-    sort_bytes = n_keys * 12 + n_keys * 24 * passes
+    # preprocess: the map once, a 44-byte splat per visible (Gaussian, view),
+    # a radius per culled one
+    pre_bytes = (g.n * 4 * (3 + 3 + 4 + 1 + 3 * K) + n_visible * (8 + 16 + 16 + 4)
+                 + (g.n * len(wl.cams) - n_visible) * 4)
+    # binning: radii and centres of every entry (12 B), the depth sort of the
+    # visible splats (4 passes, 8 B read + 8 B written), 12 B per key emitted
+    # and 24 B per key per tile-digit pass
+    tile_passes = math.ceil(max(1, math.ceil(math.log2(max(views.n_tiles, 2)))) / 8)
+    sort_bytes = (g.n * len(wl.cams) * 12 + n_visible * 4 * 16 + n_keys * 12
+                  + n_keys * 24 * tile_passes)
     hbm = {name: {"bytes": b, "ms": kms[name], "GB/s": b / (kms[name] * 1e-3) / 1e9,
                   "frac": b / (kms[name] * 1e-3) / 1e9 / HBM_PEAK_GBS}
            for name, b in (("preprocess", pre_bytes), ("bin_sort", sort_bytes))}
