@@ -43,13 +43,15 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 # VALU instructions per (pixel, splat) pair in the per-pixel body of the
 # compositing loops, counted in the gfx950 assembly of this library: every
-# walked pair pays the evaluation (offset, quadratic form, clamp, exp2,
-# opacity product, alpha clamp and the two tests; the forward adds the
-# transmittance product and its test); a pair that is blended pays the rest.
+# walked pair pays the evaluation (offsets, quadratic form -- its x terms
+# shared by a lane's two pixels in one column --, clamp, exp2, opacity
+# product, alpha clamp and the tests; the forward adds the transmittance
+# product, its test and the termination mark); a pair that is blended pays
+# the rest.
 # Wave-level overheads (LDS staging, the 9-value reduction and its atomics,
 # loop control) are not counted: they are what separates the achieved rate
 # from the peak.
-BWD_VALU_EVAL, BWD_VALU_BLEND = 13, 28
+BWD_VALU_EVAL, BWD_VALU_BLEND = 12, 27
 FWD_VALU_EVAL, FWD_VALU_BLEND = 16, 4
 # Fraction of walked pairs that are blended, measured by the oracle on the
 # 200k-Gaussian room at 640x480 (used when the oracle leg is skipped).

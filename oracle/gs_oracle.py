@@ -58,6 +58,10 @@ EXTENT_SIGMAS = 3.0   # r = ceil(3 sqrt(lambda_max))
 # Bands used to flag float32 decisions that can legitimately go either way
 # (see near_threshold handling in render()).
 BAND_REL = 2e-5       # relative band on alpha vs 1/255, o e^power vs 0.99, T' vs 1e-4
+BAND_TERMS = 2.4e-7   # plus this times |Q00| dx^2 + 2 |Q01 dx dy| + |Q11| dy^2 on the two
+                      # alpha decisions: float32 evaluation of the exponent rounds each
+                      # of its terms, so its absolute error scales with their magnitudes
+                      # (not with the exponent itself) for an elongated splat
 BAND_DEPTH = 1e-12    # relative depth difference under which two splats may swap
                       # (the kernel rounds a float64 depth once, so only depths
                       # tied at float64 precision can order differently)
@@ -349,8 +353,9 @@ def _composite_tile(px, py, S, bg, with_mask, depth=None, depth_band=BAND_DEPTH)
             rr = raw.detach()
             pw = power.detach()
             terms = (q0 * dx * dx).abs() + (q2 * dy * dy).abs() + 2 * (q1 * dx * dy).abs()
-            near = ((rr - ALPHA_MIN).abs() < BAND_REL * ALPHA_MIN) \
-                | ((rr - ALPHA_MAX).abs() < BAND_REL * ALPHA_MAX) \
+            band = BAND_REL + BAND_TERMS * terms
+            near = ((rr - ALPHA_MIN).abs() < band * ALPHA_MIN) \
+                | ((rr - ALPHA_MAX).abs() < band * ALPHA_MAX) \
                 | ((pw > -1e-6 * terms.detach() - 1e-12) & (pw.abs() < 1e-3)) \
                 | (keep & ((T_incl.detach() - T_MIN).abs() < BAND_REL * T_MIN))
             mask = (near & evaluated).any(dim=1)

@@ -286,9 +286,10 @@ __global__ __launch_bounds__(256) void radix_upsweep_kernel(const K* __restrict_
                                                             uint32_t nblocks) {
   __shared__ uint32_t h[4][256];
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  const uint32_t n = valid_keys(n_keys, capacity);
+  if ((int64_t)blockIdx.x * kSortChunk >= (int64_t)n) return;   // past the keys: column unused
   for (int k = threadIdx.x; k < 4 * 256; k += 256) (&h[0][0])[k] = 0;
   __syncthreads();
-  const uint32_t n = valid_keys(n_keys, capacity);
   const int64_t base = (int64_t)blockIdx.x * kSortChunk + w * (kSortChunk / 4);
 #pragma unroll
   for (int j = 0; j < kSortItems; ++j) {
@@ -305,11 +306,15 @@ __global__ __launch_bounds__(256) void radix_upsweep_kernel(const K* __restrict_
 // The down-sweep adds the exclusive prefix of the totals.
 __global__ __launch_bounds__(256) void hist_row_scan_kernel(uint32_t* __restrict__ hist,
                                                             uint32_t nblocks,
+                                                            const uint32_t* __restrict__ n_keys,
+                                                            int64_t capacity,
                                                             uint32_t* __restrict__ tot) {
   __shared__ uint32_t s_wave[4];
   uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
-  const uint32_t per = (nblocks + 255) / 256;
-  const uint32_t lo = min(nblocks, threadIdx.x * per), hi = min(lo + per, nblocks);
+  // columns of blocks past the keys are neither written nor read
+  const uint32_t used = min(nblocks, (valid_keys(n_keys, capacity) + kSortChunk - 1) / kSortChunk);
+  const uint32_t per = (used + 255) / 256;
+  const uint32_t lo = min(used, threadIdx.x * per), hi = min(lo + per, used);
   uint32_t sum = 0;
   for (uint32_t k = lo; k < hi; ++k) sum += row[k];
   uint32_t total;
@@ -336,10 +341,11 @@ __global__ __launch_bounds__(256) void radix_downsweep_kernel(
   __shared__ K s_keys[kSortChunk];
   __shared__ uint32_t s_vals[kSortChunk];
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
-  for (int k = threadIdx.x; k < 4 * 256; k += 256) (&s_wcnt[0][0])[k] = 0;
-  __syncthreads();
   const uint32_t n = valid_keys(n_keys, capacity);
   const int64_t bstart = (int64_t)blockIdx.x * kSortChunk;
+  if (bstart >= (int64_t)n) return;   // no keys in this block
+  for (int k = threadIdx.x; k < 4 * 256; k += 256) (&s_wcnt[0][0])[k] = 0;
+  __syncthreads();
   const int64_t base = bstart + w * (kSortChunk / 4);
   K key[kSortItems];
   uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
@@ -464,7 +470,8 @@ void radix_pass(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, cons
   const uint32_t nblocks = (uint32_t)((cap + kSortChunk - 1) / kSortChunk);
   hipLaunchKernelGGL((radix_upsweep_kernel<K>), dim3(nblocks), dim3(256), 0, s, kin, n, cap, shift,
                      hist, nblocks);
-  hipLaunchKernelGGL(hist_row_scan_kernel, dim3(256), dim3(256), 0, s, hist, nblocks, digit_tot);
+  hipLaunchKernelGGL(hist_row_scan_kernel, dim3(256), dim3(256), 0, s, hist, nblocks, n, cap,
+                     digit_tot);
   hipLaunchKernelGGL((radix_downsweep_kernel<K>), dim3(nblocks), dim3(256), 0, s, kin, vin, kout,
                      vout, n, cap, shift, hist, digit_tot, nblocks);
 }

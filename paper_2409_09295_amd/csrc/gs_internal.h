@@ -84,10 +84,12 @@ __device__ __forceinline__ bool tile_rect(float uf, float vf, int32_t r, int32_t
 // pre-scaled so that log2 of the Gaussian falloff is
 //   p2 = a dx^2 + b dx dy + c dy^2,
 // a = -log2(e)/2 Q00, b = -log2(e) Q01, c = -log2(e)/2 Q11, i.e. p2 = log2(e) * power.
+// The fields every walk step reads come first, so one LDS base address
+// serves all reads of a record.
 struct StagedSplat {
   float4 geo;   // u, v, a, b
-  float4 app;   // c, opacity, depth, (forward: quadrant mask bits; backward: accumulator index)
-  float4 col;   // r, g, b, (forward: value index; backward: quadrant mask bits)
+  float4 app;   // c, opacity, red, green
+  float4 ext;   // blue, quadrant mask bits, depth, accumulator index bits
 };
 
 // Minimum over the box [x0, x1] x [y0, y1] of f(x, y) = a x^2 + 2 b x y + c y^2
@@ -149,40 +151,33 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-// Blending decision shared bit-for-bit by the forward and backward kernels:
-// returns false if the splat is skipped at this pixel (power > 0 or
-// alpha < 1/255); otherwise alpha, the unclamped o*G and G = e^power.
-__device__ __forceinline__ bool eval_alpha(const float4& geo, const float4& app, float px,
-                                           float py, float& alpha, float& raw, float& G,
-                                           float& dx, float& dy) {
-  dx = px - geo.x;
-  dy = py - geo.y;
-  const float t1 = geo.w * dy;                 // b dy
-  const float t2 = __builtin_fmaf(geo.z, dx, t1);  // a dx + b dy
-  const float t3 = app.x * dy;                 // c dy
-  const float t4 = t3 * dy;                    // c dy^2
-  const float p2 = __builtin_fmaf(dx, t2, t4); // a dx^2 + b dx dy + c dy^2
-  if (p2 > 0.0f) return false;
-  G = __builtin_amdgcn_exp2f(p2);
-  raw = app.y * G;
-  alpha = fminf(kAlphaMax, raw);
-  return alpha >= kAlphaMin;
+// Blending decision shared bit-for-bit by the forward and backward kernels.
+// The exponent (log2 units) at pixel (px, py) is
+//   power = a dx^2 + dy (c dy + b dx),   dx = px - u, dy = py - v,
+// with (u, v, a, b) = geo and c = app.x.  The terms that depend only on dx
+// are shared by every pixel of one column (a lane's pixels often share their
+// x), so they are computed once per splat and column.
+struct ColumnTerms {
+  float dx, adx2, bdx;
+};
+
+__device__ __forceinline__ ColumnTerms column_terms(const float4& geo, float px) {
+  ColumnTerms t;
+  t.dx = px - geo.x;
+  t.bdx = geo.w * t.dx;
+  t.adx2 = (geo.z * t.dx) * t.dx;
+  return t;
 }
 
-// The same decision without a branch: every output is finite for every
-// pixel (the exponent is clamped at 0, which changes nothing where the splat
-// is kept), and the return value says whether the splat is kept.  Where it
-// is kept the outputs equal eval_alpha's bit for bit.
-__device__ __forceinline__ bool eval_alpha_all(const float4& geo, const float4& app, float px,
-                                               float py, float& alpha, float& raw, float& G,
-                                               float& dx, float& dy) {
-  dx = px - geo.x;
+// Without a branch: every output is finite for every pixel (the exponent is
+// clamped at 0, which changes nothing where the splat is kept), and the
+// return value says whether the splat is kept (power <= 0 and
+// alpha >= 1/255).  alpha = min(0.99, o G), raw = o G, G = 2^power.
+__device__ __forceinline__ bool eval_alpha_at(const ColumnTerms& ct, const float4& geo,
+                                              const float4& app, float py, float& alpha,
+                                              float& raw, float& G, float& dy) {
   dy = py - geo.y;
-  const float t1 = geo.w * dy;
-  const float t2 = __builtin_fmaf(geo.z, dx, t1);
-  const float t3 = app.x * dy;
-  const float t4 = t3 * dy;
-  const float p2 = __builtin_fmaf(dx, t2, t4);
+  const float p2 = __builtin_fmaf(dy, __builtin_fmaf(app.x, dy, ct.bdx), ct.adx2);
   G = __builtin_amdgcn_exp2f(fminf(p2, 0.0f));
   raw = app.y * G;
   alpha = fminf(kAlphaMax, raw);

@@ -49,9 +49,10 @@ __device__ __forceinline__ float lane63(float x) {
 // 0-31, so adding its two results leaves a's 32-lane partial sums in lanes
 // 0-31 and b's in lanes 32-63: one swap and one add halve two values.
 // v_permlane16_swap does the same on 16-lane rows.  After both levels each
-// 16-lane row of three registers holds a distinct value, and four row-local
+// 16-lane row of two registers holds a distinct value, and four row-local
 // DPP adds finish the sums:
-//   q0 rows = {v0, v2, v1, v3}, q1 rows = {v4, v6, v5, v7}, q2 row 0 = v8.
+//   q0 rows = {v0, v2, v1, v3}, q1 rows = {v4, v6, v5, v7};
+// the ninth value takes the plain DPP reduction to lane 63.
 __device__ __forceinline__ float swap32_add(float a, float b) {
   const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
                                                   false);
@@ -64,10 +65,11 @@ __device__ __forceinline__ float swap16_add(float a, float b) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
+// x + x of another lane of the same 16-lane row (every lane is a valid source)
 template <int CTRL>
 __device__ __forceinline__ float dpp_add(float x) {
   return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf,
-                                                        false));
+                                                        true));
 }
 
 __device__ __forceinline__ float row16_sum(float x) {
@@ -82,15 +84,15 @@ struct Reduced9 {
   float q0, q1, q2;
 };
 
+// q0 and q1 as described above; the ninth value's total lands in lane 63 of q2.
 __device__ __forceinline__ Reduced9 wave_reduce9(float v0, float v1, float v2, float v3, float v4,
                                                  float v5, float v6, float v7, float v8) {
   const float h0 = swap32_add(v0, v1), h1 = swap32_add(v2, v3);
   const float h2 = swap32_add(v4, v5), h3 = swap32_add(v6, v7);
-  const float h4 = swap32_add(v8, 0.0f);
   Reduced9 r;
   r.q0 = row16_sum(swap16_add(h0, h1));
   r.q1 = row16_sum(swap16_add(h2, h3));
-  r.q2 = row16_sum(swap16_add(h4, h4));
+  r.q2 = wave_sum_to_lane63(v8);
   return r;
 }
 
@@ -106,8 +108,8 @@ __device__ __forceinline__ uint32_t stage_splat(uint32_t g, uint32_t n, uint32_t
   const float4 r = rd[g];
   const uint32_t reach = quadrant_mask(m.x, m.y, c.x, c.y, c.z, c.w, tx0, ty0, W, H);
   out.geo = make_float4(m.x, m.y, -0.5f * kLog2e * c.x, -kLog2e * c.y);
-  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.w, __uint_as_float(g));
-  out.col = make_float4(r.x, r.y, r.z, __uint_as_float(reach));
+  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.x, r.y);
+  out.ext = make_float4(r.z, __uint_as_float(reach), r.w, __uint_as_float(g));
   return reach;
 }
 
@@ -130,16 +132,13 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
   const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
   const int lane = threadIdx.x & 63;
   // where wave_reduce9 leaves each value: row r = lane / 16 of q0 holds value
-  // {0, 2, 1, 3}[r] and of q1 value 4 + {0, 2, 1, 3}[r]; the per-value factors
-  // turn the accumulated sums into dL/dQ00, dL/dQ01, dL/dQ11 (slots 0 and 1
-  // keep sum(dL/dpower * (dx, dy)), which the projection backward multiplies
-  // by the conic to obtain dL/du, dL/dv).
+  // {0, 2, 1, 3}[r] and of q1 value 4 + {0, 2, 1, 3}[r]; lane 63 of q2 holds
+  // value 8
   const int row = lane >> 4;
   const int red_off0 = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
-  // value factors: slots 0, 1: 1; Q00, Q11: -1/2; Q01: -1; o, r, g, b: 1
-  const float red_scale0 = (row == 0 || row == 2) ? 1.0f : (row == 1) ? -0.5f : -1.0f;
-  const float red_scale1 = (row == 0) ? -0.5f : 1.0f;
 
+  // pixel k of a lane lies in column k % NC (see the forward kernel)
+  constexpr int NC = PPL == 4 ? 2 : 1;
   float fpx[PPL], fpy[PPL], T[PPL], dC0[PPL], dC1[PPL], dC2[PPL], S0[PPL], S1[PPL], S2[PPL];
   uint32_t last[PPL], qbit[PPL];
   uint32_t mylast = 0;
@@ -226,27 +225,31 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
         const uint32_t pos = (uint32_t)(bstart + j);
         const float4 geo = s_splat[j].geo;
         const float4 app = s_splat[j].app;
-        const float4 col = s_splat[j].col;
-        const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(col.w)) : ~0u;
+        const float4 ext = s_splat[j].ext;
+        const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(ext.y)) : ~0u;
         // Per pixel slot, branch-free over the wave: a lane whose pixel does
         // not blend this splat takes alpha = 0, which leaves T and S exactly
-        // as they were and contributes exact zeros.  The first slot with a
-        // blending lane writes the partial sums, later ones add.
-        float g0, g1, g2, g3, g4, g5, g6, g7, g8;
+        // as they were and contributes exact zeros.
+        float g0 = -0.0f, g1 = -0.0f, g2 = -0.0f, g3 = -0.0f, g4 = -0.0f, g5 = -0.0f,
+              g6 = -0.0f, g7 = -0.0f, g8 = -0.0f;   // -0 + x == x exactly
         bool started = false;
+        ColumnTerms ct[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ct[c] = column_terms(geo, fpx[c]);
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
           // slot-uniform skips: quadrant not reached, or every pixel of the
           // slot in this wave already past its last blended splat
           if (!(reach & qbit[k]) || pos >= slot_last[k]) continue;
-          float alpha, raw, G, dx, dy;
+          float alpha, raw, G, dy;
+          const float dx = ct[k % NC].dx;
           const bool ok =
-              eval_alpha_all(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy) && pos < last[k];
+              eval_alpha_at(ct[k % NC], geo, app, fpy[k], alpha, raw, G, dy) && pos < last[k];
           if (!__ballot(ok)) continue;
           const float a = ok ? alpha : 0.0f;
           const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - a);
           const float wgt = a * Tk;
-          const float d0 = col.x - S0[k], d1 = col.y - S1[k], d2 = col.z - S2[k];
+          const float d0 = app.z - S0[k], d1 = app.w - S1[k], d2 = ext.x - S2[k];
           const float dalpha = Tk * (d0 * dC0[k] + d1 * dC1[k] + d2 * dC2[k]);
           // colour behind the next splat in front: alpha c + (1 - alpha) S
           S0[k] = __builtin_fmaf(a, d0, S0[k]);
@@ -261,22 +264,19 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
           // the same for every pixel, so only sum(gP d) is accumulated here
           const float v2 = gdx * dx, v3 = gdx * dy, v4 = gdy * dy, v5 = G * live;
           const float v6 = wgt * dC0[k], v7 = wgt * dC1[k], v8 = wgt * dC2[k];
-          if (k == 0 || !started) {
-            g0 = gdx; g1 = gdy; g2 = v2; g3 = v3; g4 = v4; g5 = v5; g6 = v6; g7 = v7; g8 = v8;
-          } else {
-            g0 += gdx; g1 += gdy; g2 += v2; g3 += v3; g4 += v4; g5 += v5; g6 += v6; g7 += v7;
-            g8 += v8;
-          }
+          g0 += gdx; g1 += gdy; g2 += v2; g3 += v3; g4 += v4; g5 += v5; g6 += v6; g7 += v7;
+          g8 += v8;
           started = true;
         }
         if (started) {
           const Reduced9 r = wave_reduce9(g0, g1, g2, g3, g4, g5, g6, g7, g8);
+          const uint32_t acc = __builtin_amdgcn_readfirstlane(__float_as_uint(ext.w));
+          float* dst = grad2d + (int64_t)acc * 9;   // wave-uniform
           if ((lane & 15) == 0) {
-            const int64_t base = (int64_t)__float_as_uint(app.w) * 9;
-            unsafeAtomicAdd(&grad2d[base + red_off0], r.q0 * red_scale0);
-            unsafeAtomicAdd(&grad2d[base + red_off0 + 4], r.q1 * red_scale1);
-            if (lane == 0) unsafeAtomicAdd(&grad2d[base + 8], r.q2);
+            unsafeAtomicAdd(dst + red_off0, r.q0);
+            unsafeAtomicAdd(dst + red_off0 + 4, r.q1);
           }
+          if (lane == 63) unsafeAtomicAdd(dst + 8, r.q2);
         }
       }
     }
@@ -455,6 +455,11 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
           g2[k] = src[k];
           nz = nz || g2[k] != 0.0f;
         }
+        // slots 2-4 hold sum(dL/dpower * (dx^2, dx dy, dy^2)); dL/dQ00,
+        // dL/dQ01, dL/dQ11 are those times -1/2, -1, -1/2 (exact scalings)
+        g2[2] *= -0.5f;
+        g2[3] = -g2[3];
+        g2[4] *= -0.5f;
       }
       active = active && nz;
       if (!__any(active)) continue;

@@ -26,8 +26,8 @@ __device__ __forceinline__ uint32_t stage_splat(uint32_t g, const float2* __rest
   const float4 r = rd[g];
   const uint32_t reach = quadrant_mask(m.x, m.y, c.x, c.y, c.z, c.w, tx0, ty0, W, H);
   out.geo = make_float4(m.x, m.y, -0.5f * kLog2e * c.x, -kLog2e * c.y);
-  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.w, __uint_as_float(reach));
-  out.col = make_float4(r.x, r.y, r.z, __uint_as_float(g));
+  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.x, r.y);
+  out.ext = make_float4(r.z, __uint_as_float(reach), r.w, __uint_as_float(g));
   return reach;
 }
 
@@ -52,11 +52,16 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
   const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
   const int lane = threadIdx.x & 63;
 
+  // pixel k of a lane lies in column k % NC: with 2 pixels per lane both
+  // share their x, with 4 the even and the odd ones do
+  constexpr int NC = PPL == 4 ? 2 : 1;
   int px[PPL], py[PPL];
   uint32_t qbit[PPL];   // quadrant bit of each of the lane's pixels (wave-uniform)
+  // T > 0: transmittance of a live pixel; T < 0: the pixel has terminated
+  // (or lies outside the image) and -T is its final transmittance
   float fpx[PPL], fpy[PPL], T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL];
   uint32_t last[PPL];
-  bool inside[PPL], done[PPL];
+  bool inside[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int i = k * NT + (int)threadIdx.x;
@@ -65,10 +70,9 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
     py[k] = ty * kTile + (q >> 1) * 8 + (l >> 3);
     qbit[k] = __builtin_amdgcn_readfirstlane(1u << q);
     inside[k] = px[k] < vi.width && py[k] < vi.height;
-    done[k] = !inside[k];
     fpx[k] = (float)px[k] + 0.5f;
     fpy[k] = (float)py[k] + 0.5f;
-    T[k] = 1.0f;
+    T[k] = inside[k] ? 1.0f : -1.0f;
     C0[k] = C1[k] = C2[k] = D[k] = 0.0f;
     last[k] = 0;
   }
@@ -77,7 +81,7 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
   for (int64_t b = s; b < (int64_t)e; b += kBlock) {
     bool all_done = true;
 #pragma unroll
-    for (int k = 0; k < PPL; ++k) all_done = all_done && done[k];
+    for (int k = 0; k < PPL; ++k) all_done = all_done && !(T[k] > 0.0f);
     if (__syncthreads_count(all_done ? 0 : 1) == 0) break;
 #pragma unroll
     for (int r = 0; r < PPL; ++r) {
@@ -107,28 +111,32 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
         m &= m - 1;
         const float4 geo = s_splat[j].geo;
         const float4 app = s_splat[j].app;
-        const float4 col = s_splat[j].col;
-        const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(app.w)) : ~0u;
+        const float4 ext = s_splat[j].ext;
+        const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(ext.y)) : ~0u;
+        ColumnTerms ct[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) ct[c] = column_terms(geo, fpx[c]);
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
           if (!(reach & qbit[k])) continue;   // slot-uniform
-          float alpha, raw, G, dx, dy;
-          const bool ok = eval_alpha_all(geo, app, fpx[k], fpy[k], alpha, raw, G, dx, dy) && !done[k];
+          float alpha, raw, G, dy;
+          const bool ok = eval_alpha_at(ct[k % NC], geo, app, fpy[k], alpha, raw, G, dy);
+          // a terminated pixel (T < 0) gets Tn <= 0 < kTMin: it never blends again
           const float Tn = T[k] * (1.0f - alpha);
           const bool term = ok && Tn < kTMin;   // stops before this splat
-          done[k] = done[k] || term;
+          if (term) T[k] = -fabsf(T[k]);
           if (!ok || term) continue;
           const float wgt = alpha * T[k];
-          C0[k] += col.x * wgt;
-          C1[k] += col.y * wgt;
-          C2[k] += col.z * wgt;
-          D[k] += app.z * wgt;
+          C0[k] += app.z * wgt;
+          C1[k] += app.w * wgt;
+          C2[k] += ext.x * wgt;
+          D[k] += ext.z * wgt;
           T[k] = Tn;
           last[k] = (uint32_t)(b - (int64_t)s) + (uint32_t)j + 1;
         }
         bool live = false;
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) live = live || !done[k];
+        for (int k = 0; k < PPL; ++k) live = live || __float_as_int(T[k]) > 0;
         if (!__any(live)) m = 0;   // every pixel of the wave has terminated
       }
     }
@@ -142,10 +150,11 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
   for (int k = 0; k < PPL; ++k) {
     if (!inside[k]) continue;
     const int64_t off = (int64_t)py[k] * vi.width + px[k];
-    const float c[3] = {C0[k] + T[k] * bg.x, C1[k] + T[k] * bg.y, C2[k] + T[k] * bg.z};
+    const float Tf = fabsf(T[k]);
+    const float c[3] = {C0[k] + Tf * bg.x, C1[k] + Tf * bg.y, C2[k] + Tf * bg.z};
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) img[ch * plane + off] = c[ch];
-    final_T[vi.pix_base + off] = T[k];
+    final_T[vi.pix_base + off] = Tf;
     n_contrib[vi.pix_base + off] = last[k];
     if (!L1 && depth_out) depth_out[vi.pix_base + off] = D[k];
     if (L1) {
