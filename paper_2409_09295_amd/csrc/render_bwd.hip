@@ -4,6 +4,8 @@
 // pixel starts at its last blended splat (n_contrib) with T = final_T and the
 // normalised colour behind it S = bg, and walks the tile list in reverse,
 // recovering the transmittance before splat i as T_i = T_{i+1} / (1 - a_i).
+// Only the projection of S on the pixel's dL/dC is needed (dL/dalpha_i =
+// T_i (c_i - S_i) . dL/dC), so that scalar is what the walk carries.
 // For each splat the 9 screen-space partials (u, v, Q00, Q01, Q11, o, r, g, b)
 // are summed over the wavefront with DPP row operations and added to a
 // per-(view, splat) accumulator with one 9-lane atomic.
@@ -134,12 +136,17 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
   // where wave_reduce9 leaves each value: row r = lane / 16 of q0 holds value
   // {0, 2, 1, 3}[r] and of q1 value 4 + {0, 2, 1, 3}[r]; lane 63 of q2 holds
   // value 8
-  const int row = lane >> 4;
+  // One atomic instruction adds all nine: lane 16 r takes q0's row total,
+  // lane 16 r + 1 q1's, lane 63 the ninth value.
+  const int row = lane >> 4, col16 = lane & 15;
   const int red_off0 = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
+  const bool red_q0 = col16 == 0, red_q1 = col16 == 1, red_q2 = lane == 63;
+  const int red_off = red_q0 ? red_off0 : red_q1 ? red_off0 + 4 : 8;
 
   // pixel k of a lane lies in column k % NC (see the forward kernel)
   constexpr int NC = PPL == 4 ? 2 : 1;
-  float fpx[PPL], fpy[PPL], T[PPL], dC0[PPL], dC1[PPL], dC2[PPL], S0[PPL], S1[PPL], S2[PPL];
+  // sdc: (colour behind the current splat) . dL/dC of the pixel
+  float fpx[PPL], fpy[PPL], T[PPL], dC0[PPL], dC1[PPL], dC2[PPL], sdc[PPL];
   uint32_t last[PPL], qbit[PPL];
   uint32_t mylast = 0;
   const int64_t plane = (int64_t)vi.width * vi.height;
@@ -154,10 +161,7 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     fpx[k] = (float)px + 0.5f;
     fpy[k] = (float)py + 0.5f;
     T[k] = 1.0f;
-    dC0[k] = dC1[k] = dC2[k] = 0.f;
-    S0[k] = bg.x;
-    S1[k] = bg.y;
-    S2[k] = bg.z;
+    dC0[k] = dC1[k] = dC2[k] = sdc[k] = 0.f;
     last[k] = 0;
     if (px < vi.width && py < vi.height) {
       const int64_t off = (int64_t)py * vi.width + px;
@@ -165,6 +169,7 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
       dC1[k] = gimg[plane + off];
       dC2[k] = gimg[2 * plane + off];
       T[k] = final_T[vi.pix_base + off];
+      sdc[k] = bg.x * dC0[k] + bg.y * dC1[k] + bg.z * dC2[k];
       last[k] = n_contrib[vi.pix_base + off];
       mylast = max(mylast, last[k]);
     }
@@ -244,17 +249,16 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
           float alpha, raw, G, dy;
           const float dx = ct[k % NC].dx;
           const bool ok =
-              eval_alpha_at(ct[k % NC], geo, app, fpy[k], alpha, raw, G, dy) && pos < last[k];
+              eval_alpha_at<true>(ct[k % NC], geo, app, fpy[k], alpha, raw, G, dy) &&
+              pos < last[k];
           if (!__ballot(ok)) continue;
           const float a = ok ? alpha : 0.0f;
           const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - a);
           const float wgt = a * Tk;
-          const float d0 = app.z - S0[k], d1 = app.w - S1[k], d2 = ext.x - S2[k];
-          const float dalpha = Tk * (d0 * dC0[k] + d1 * dC1[k] + d2 * dC2[k]);
-          // colour behind the next splat in front: alpha c + (1 - alpha) S
-          S0[k] = __builtin_fmaf(a, d0, S0[k]);
-          S1[k] = __builtin_fmaf(a, d1, S1[k]);
-          S2[k] = __builtin_fmaf(a, d2, S2[k]);
+          const float dot = (app.z * dC0[k] + app.w * dC1[k] + ext.x * dC2[k]) - sdc[k];
+          const float dalpha = Tk * dot;   // (c - S) . dL/dC
+          // colour behind the next splat in front: S + alpha (c - S)
+          sdc[k] = __builtin_fmaf(a, dot, sdc[k]);
           T[k] = Tk;
           // below the 0.99 clamp alpha = o G: d alpha/do = G, d alpha/dpower = alpha
           const float live = (ok && raw <= kAlphaMax) ? dalpha : 0.0f;
@@ -272,11 +276,8 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
           const Reduced9 r = wave_reduce9(g0, g1, g2, g3, g4, g5, g6, g7, g8);
           const uint32_t acc = __builtin_amdgcn_readfirstlane(__float_as_uint(ext.w));
           float* dst = grad2d + (int64_t)acc * 9;   // wave-uniform
-          if ((lane & 15) == 0) {
-            unsafeAtomicAdd(dst + red_off0, r.q0);
-            unsafeAtomicAdd(dst + red_off0 + 4, r.q1);
-          }
-          if (lane == 63) unsafeAtomicAdd(dst + 8, r.q2);
+          const float val = red_q0 ? r.q0 : red_q1 ? r.q1 : r.q2;
+          if (red_q0 || red_q1 || red_q2) unsafeAtomicAdd(dst + red_off, val);
         }
       }
     }
@@ -513,16 +514,19 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
   }
 }
 
-// Clears the partials of visible splats (radius > 0): the only slots the
-// reverse walk adds to and the projection backward reads.
+// Clears the partials of visible splats (radius > 0): the only records the
+// reverse walk adds to and the projection backward reads.  One 16-byte store
+// per lane over the flat [V n 9] float array: a store that touches a visible
+// record is made whole, which may also clear the neighbouring record (never
+// read when that splat is not visible).  The last store may reach up to 12
+// bytes past the array, inside the region's 256-byte alignment padding.
 __global__ __launch_bounds__(256) void zero_visible_kernel(const int32_t* __restrict__ radius,
                                                            int64_t n_entries,
-                                                           float* __restrict__ grad2d) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_entries || radius[e] <= 0) return;
-  float* d = grad2d + e * 9;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) d[k] = 0.0f;
+                                                           float4* __restrict__ grad2d) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // float4 index
+  if (i >= (9 * n_entries + 3) / 4) return;
+  const int64_t e0 = (4 * i) / 9, e1 = min((4 * i + 3) / 9, n_entries - 1);
+  if (radius[e0] > 0 || radius[e1] > 0) grad2d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // One workgroup per (view, component): strided float64 sum over the
@@ -597,8 +601,8 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
   double* pose_part = reinterpret_cast<double*>(ws + plan.off_pose);
   const int64_t n_entries = g.n * (int64_t)vt.n_views;
   if (n_entries > 0)
-    hipLaunchKernelGGL(zero_visible_kernel, dim3((unsigned)((n_entries + 255) / 256)), dim3(256), 0,
-                       s, p.radius, n_entries, grad2d);
+    hipLaunchKernelGGL(zero_visible_kernel, dim3((unsigned)(((9 * n_entries + 3) / 4 + 255) / 256)),
+                       dim3(256), 0, s, p.radius, n_entries, reinterpret_cast<float4*>(grad2d));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (vt.n_tiles > 0) {

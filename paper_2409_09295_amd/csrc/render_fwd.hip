@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
         for (int k = 0; k < PPL; ++k) {
           if (!(reach & qbit[k])) continue;   // slot-uniform
           float alpha, raw, G, dy;
-          const bool ok = eval_alpha_at(ct[k % NC], geo, app, fpy[k], alpha, raw, G, dy);
+          const bool ok = eval_alpha_at<false>(ct[k % NC], geo, app, fpy[k], alpha, raw, G, dy);
           // a terminated pixel (T < 0) gets Tn <= 0 < kTMin: it never blends again
           const float Tn = T[k] * (1.0f - alpha);
           const bool term = ok && Tn < kTMin;   // stops before this splat
@@ -187,7 +187,18 @@ __global__ __launch_bounds__(1024) void tile_loss_sum_kernel(const float* __rest
                                                              double* __restrict__ loss) {
   __shared__ double s_acc[1024];
   double a = 0.0;
-  for (int t = threadIdx.x; t < n_tiles; t += 1024) a += (double)tile_loss[t];
+  // lane t sums tiles t, t + 1024, t + 2048, ... in that order; eight loads
+  // in flight per round trip
+  for (int t0 = threadIdx.x; t0 < n_tiles; t0 += 8 * 1024) {
+    float x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + u * 1024;
+      x[u] = t < n_tiles ? tile_loss[t] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a += (double)x[u];
+  }
   s_acc[threadIdx.x] = a;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
