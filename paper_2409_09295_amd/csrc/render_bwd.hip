@@ -122,8 +122,12 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     float3 bg, const float* __restrict__ dL_dimage, const float* __restrict__ final_T,
     const uint32_t* __restrict__ n_contrib, uint32_t n_gauss, float* __restrict__ grad2d) {
   constexpr int NT = kBlock / PPL;
-  constexpr int kWords = kBlock / 64;
-  __shared__ StagedSplat s_splat[kBlock];
+  // splats staged per batch: with one wavefront per tile (PPL 4) a smaller
+  // batch halves the LDS per workgroup, so twice as many fit on a CU
+  constexpr int kStage = PPL == 4 ? 128 : 256;
+  constexpr int kPerThread = kStage / NT;
+  constexpr int kWords = kStage / 64;
+  __shared__ StagedSplat s_splat[kStage];
   // s_reach[q][w] bit b: staged splat 64 w + b can reach quadrant q
   __shared__ uint64_t s_reach[4][kWords];
   __shared__ uint32_t s_maxlast;
@@ -195,11 +199,11 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
   const int64_t list_len = (int64_t)e - (int64_t)s;
   const int64_t maxlast = min((int64_t)s_maxlast, max(list_len, (int64_t)0));
 
-  for (int64_t bend = maxlast; bend > 0; bend -= kBlock) {
-    const int64_t bstart = max((int64_t)0, bend - kBlock);
+  for (int64_t bend = maxlast; bend > 0; bend -= kStage) {
+    const int64_t bstart = max((int64_t)0, bend - kStage);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < PPL; ++r) {
+    for (int r = 0; r < kPerThread; ++r) {
       const int slot = r * NT + (int)threadIdx.x;
       const int64_t k = bstart + slot;
       uint32_t reach = 0;

@@ -7,9 +7,9 @@
 // inside it, so with PPL = 1 each wavefront owns one 8x8 quadrant and with
 // PPL = 4 one wavefront owns the tile, every lane holding the same position
 // in the four quadrants.  The tile's sorted splats are staged in LDS 256 at
-// a time (gathered once per workgroup) and read back as wave-uniform
-// broadcasts, so a staged record serves 64 * PPL pixels per LDS read.  A
-// workgroup stops once every pixel has terminated.
+// a time (128 with PPL = 4; gathered once per workgroup) and read back as
+// wave-uniform broadcasts, so a staged record serves 64 * PPL pixels per LDS
+// read.  A workgroup stops once every pixel has terminated.
 #include "gs_internal.h"
 
 namespace gsmi {
@@ -41,8 +41,12 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
     uint32_t* __restrict__ n_contrib, float* __restrict__ depth_out,
     const float* __restrict__ target, float* __restrict__ dL, float* __restrict__ tile_loss) {
   constexpr int NT = kBlock / PPL;
-  constexpr int kWords = kBlock / 64;
-  __shared__ StagedSplat s_splat[kBlock];
+  // splats staged per batch: with one wavefront per tile (PPL 4) a smaller
+  // batch halves the LDS per workgroup, so twice as many fit on a CU
+  constexpr int kStage = PPL == 4 ? 128 : 256;
+  constexpr int kPerThread = kStage / NT;
+  constexpr int kWords = kStage / 64;
+  __shared__ StagedSplat s_splat[kStage];
   // s_reach[q][w] bit b: staged splat 64 w + b can reach quadrant q
   __shared__ uint64_t s_reach[4][kWords];
   const int tile = blockIdx.x;
@@ -78,13 +82,13 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
   }
 
   const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
-  for (int64_t b = s; b < (int64_t)e; b += kBlock) {
+  for (int64_t b = s; b < (int64_t)e; b += kStage) {
     bool all_done = true;
 #pragma unroll
     for (int k = 0; k < PPL; ++k) all_done = all_done && !(T[k] > 0.0f);
     if (__syncthreads_count(all_done ? 0 : 1) == 0) break;
 #pragma unroll
-    for (int r = 0; r < PPL; ++r) {
+    for (int r = 0; r < kPerThread; ++r) {
       const int slot = r * NT + (int)threadIdx.x;
       const int64_t idx = b + slot;
       uint32_t reach = 0;
