@@ -519,18 +519,15 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
 }
 
 // Clears the partials of visible splats (radius > 0): the only records the
-// reverse walk adds to and the projection backward reads.  One 16-byte store
-// per lane over the flat [V n 9] float array: a store that touches a visible
-// record is made whole, which may also clear the neighbouring record (never
-// read when that splat is not visible).  The last store may reach up to 12
-// bytes past the array, inside the region's 256-byte alignment padding.
+// reverse walk adds to and the projection backward reads.
 __global__ __launch_bounds__(256) void zero_visible_kernel(const int32_t* __restrict__ radius,
                                                            int64_t n_entries,
-                                                           float4* __restrict__ grad2d) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // float4 index
-  if (i >= (9 * n_entries + 3) / 4) return;
-  const int64_t e0 = (4 * i) / 9, e1 = min((4 * i + 3) / 9, n_entries - 1);
-  if (radius[e0] > 0 || radius[e1] > 0) grad2d[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                                                           float* __restrict__ grad2d) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_entries || radius[e] <= 0) return;
+  float* d = grad2d + e * 9;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) d[k] = 0.0f;
 }
 
 // One workgroup per (view, component): strided float64 sum over the
@@ -605,8 +602,8 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
   double* pose_part = reinterpret_cast<double*>(ws + plan.off_pose);
   const int64_t n_entries = g.n * (int64_t)vt.n_views;
   if (n_entries > 0)
-    hipLaunchKernelGGL(zero_visible_kernel, dim3((unsigned)(((9 * n_entries + 3) / 4 + 255) / 256)),
-                       dim3(256), 0, s, p.radius, n_entries, reinterpret_cast<float4*>(grad2d));
+    hipLaunchKernelGGL(zero_visible_kernel, dim3((unsigned)((n_entries + 255) / 256)), dim3(256), 0,
+                       s, p.radius, n_entries, grad2d);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (vt.n_tiles > 0) {

@@ -196,10 +196,12 @@ __global__ __launch_bounds__(1024) void tile_loss_sum_kernel(const float* __rest
   for (int t0 = threadIdx.x; t0 < n_tiles; t0 += 8 * 1024) {
     float x[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 8; ++u) {   // in-bounds loads without a branch, masked after
       const int t = t0 + u * 1024;
-      x[u] = t < n_tiles ? tile_loss[t] : 0.0f;
+      x[u] = tile_loss[min(t, n_tiles - 1)];
     }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = t0 + u * 1024 < n_tiles ? x[u] : 0.0f;
 #pragma unroll
     for (int u = 0; u < 8; ++u) a += (double)x[u];
   }
