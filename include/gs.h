@@ -156,7 +156,8 @@ typedef struct gs_grads {
 enum {
   GS_BWD_NO_POSE = 1u,   /* skip the pose gradient (xi may be NULL)            */
   GS_BWD_POSE_ONLY = 2u, /* only the pose gradient (map grads may be NULL)      */
-  GS_BWD_OVERWRITE = 4u  /* store gradients instead of accumulating (+=) them   */
+  GS_BWD_OVERWRITE = 4u, /* store gradients instead of accumulating (+=) them   */
+  GS_BWD_KEEP_CLEAR = 8u /* workspace handed over clear, returned clear (below)  */
 };
 
 /* Kernels that gs_set_kernel_events() can bracket. */
@@ -248,7 +249,14 @@ size_t gs_render_bwd_workspace_size(int64_t n, const gs_views* views);
  * wavefront and accumulates them with atomics, then chains them per Gaussian
  * to the map parameters (summed over views) and to each view's pose tangent.
  * flags: 0, GS_BWD_NO_POSE or GS_BWD_POSE_ONLY, optionally or-ed with
- * GS_BWD_OVERWRITE (gradients of culled Gaussians are then written as 0). */
+ * GS_BWD_OVERWRITE (gradients of culled Gaussians are then written as 0) and
+ * GS_BWD_KEEP_CLEAR.  Without GS_BWD_KEEP_CLEAR the call first clears the
+ * per-splat partials it accumulates into (one pass over the [V][n] entries).
+ * With it the caller guarantees that the workspace is clear on entry: all
+ * zero bytes (e.g. a fresh workspace the caller zeroed), or last used by a
+ * completed call with this flag for the same n and views and not modified
+ * since; the call then skips that pass and leaves the workspace clear again
+ * (the projection backward zeroes each partial after reading it). */
 int gs_render_bwd(const gs_gaussians* g, const gs_projected* p, const gs_bins* bins,
                   const gs_views* views, const float* bg, const float* dL_dimage,
                   const float* final_T, const uint32_t* n_contrib, gs_grads* grads,

@@ -283,7 +283,8 @@ int gs_render_bwd(const gs_gaussians* g, const gs_projected* p, const gs_bins* b
   if ((st = check_gaussians(g, vt.n_views))) return st;
   if ((st = check_projected(p, g->n))) return st;
   if ((st = check_bins(bins, false))) return st;
-  if (flags & ~(uint32_t)(GS_BWD_NO_POSE | GS_BWD_POSE_ONLY | GS_BWD_OVERWRITE))
+  if (flags & ~(uint32_t)(GS_BWD_NO_POSE | GS_BWD_POSE_ONLY | GS_BWD_OVERWRITE |
+                          GS_BWD_KEEP_CLEAR))
     return invalid("unknown flags");
   if ((flags & GS_BWD_NO_POSE) && (flags & GS_BWD_POSE_ONLY))
     return invalid("GS_BWD_NO_POSE and GS_BWD_POSE_ONLY are exclusive");

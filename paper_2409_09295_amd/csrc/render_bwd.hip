@@ -425,7 +425,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ ologit,
     const float* __restrict__ sh, int64_t n, const gs_camera* __restrict__ cams, int n_views,
-    const int32_t* __restrict__ radius, const float* __restrict__ grad2d,
+    const int32_t* __restrict__ radius, float* __restrict__ grad2d,
     float* __restrict__ g_means, float* __restrict__ g_log_scales, float* __restrict__ g_quats,
     float* __restrict__ g_ologit, float* __restrict__ g_sh, double* __restrict__ pose_part,
     uint32_t flags) {
@@ -436,6 +436,7 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
   const bool want_pose = !(flags & GS_BWD_NO_POSE);
   const bool want_map = !(flags & GS_BWD_POSE_ONLY);
   const bool overwrite = (flags & GS_BWD_OVERWRITE) != 0;
+  const bool keep_clear = (flags & GS_BWD_KEEP_CLEAR) != 0;
   for (int t = threadIdx.x; t < 4 * GS_MAX_VIEWS * 6; t += 256) (&s_pose[0][0][0])[t] = 0.0;
   __syncthreads();
   for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
@@ -455,11 +456,13 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
       float g2[9];
       bool nz = false;
       if (active) {
-        const float* src = grad2d + e * 9;
+        float* src = grad2d + e * 9;
         for (int k = 0; k < 9; ++k) {
           g2[k] = src[k];
           nz = nz || g2[k] != 0.0f;
         }
+        if (keep_clear && nz)   // leave the record clear for the next call
+          for (int k = 0; k < 9; ++k) src[k] = 0.0f;
         // slots 2-4 hold sum(dL/dpower * (dx^2, dx dy, dy^2)); dL/dQ00,
         // dL/dQ01, dL/dQ11 are those times -1/2, -1, -1/2 (exact scalings)
         g2[2] *= -0.5f;
@@ -572,7 +575,7 @@ namespace {
 
 template <int DEG>
 void launch_project_bwd_deg(const gs_gaussians& g, const gs_camera* cams, int V,
-                            const int32_t* radius, const float* grad2d, const gs_grads& gr,
+                            const int32_t* radius, float* grad2d, const gs_grads& gr,
                             double* pose_part, uint32_t flags, dim3 grid, dim3 block,
                             hipStream_t s) {
   hipLaunchKernelGGL((project_bwd_kernel<DEG>), grid, block, 0, s, g.means, g.log_scales, g.quats,
@@ -581,7 +584,7 @@ void launch_project_bwd_deg(const gs_gaussians& g, const gs_camera* cams, int V,
 }
 
 void launch_project_bwd(const gs_gaussians& g, const gs_camera* cams, int V, const int32_t* radius,
-                        const float* grad2d, const gs_grads& gr, double* pose_part, uint32_t flags,
+                        float* grad2d, const gs_grads& gr, double* pose_part, uint32_t flags,
                         dim3 grid, dim3 block, hipStream_t s) {
   switch (g.sh_degree) {
     case 0: launch_project_bwd_deg<0>(g, cams, V, radius, grad2d, gr, pose_part, flags, grid, block, s); break;
@@ -601,7 +604,7 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
   float* grad2d = reinterpret_cast<float*>(ws + plan.off_grad2d);
   double* pose_part = reinterpret_cast<double*>(ws + plan.off_pose);
   const int64_t n_entries = g.n * (int64_t)vt.n_views;
-  if (n_entries > 0)
+  if (n_entries > 0 && !(flags & GS_BWD_KEEP_CLEAR))
     hipLaunchKernelGGL(zero_visible_kernel, dim3((unsigned)((n_entries + 255) / 256)), dim3(256), 0,
                        s, p.radius, n_entries, grad2d);
   hipError_t e = hipGetLastError();

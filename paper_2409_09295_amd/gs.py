@@ -34,6 +34,7 @@ GS_ERR_UNSUPPORTED = 4
 GS_BWD_NO_POSE = 1
 GS_BWD_POSE_ONLY = 2
 GS_BWD_OVERWRITE = 4
+GS_BWD_KEEP_CLEAR = 8
 GS_KERNEL_PREPROCESS = 0
 GS_KERNEL_BIN_SORT = 1
 GS_KERNEL_RENDER_FWD = 2

@@ -87,7 +87,8 @@ class BatchedStep:
         self.n_contrib = torch.zeros(P, dtype=torch.int32, device=dev)
         self.dL = torch.zeros(3 * P, dtype=torch.float32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
-        self.bwd_ws = gs.workspace(gs.gs_render_bwd_workspace_size(self.n, views), dev)
+        # handed to every backward as clear (GS_BWD_KEEP_CLEAR): zeroed once here
+        self.bwd_ws = gs.workspace(gs.gs_render_bwd_workspace_size(self.n, views), dev).zero_()
         self.l1_ws = gs.workspace(gs.gs_render_fwd_l1_workspace_size(views), dev)
         self.adam = _AdamState(g, lrs or DEFAULT_LR)
         self.n_tiles = views.n_tiles
@@ -124,7 +125,8 @@ class BatchedStep:
         gs.gs_render_fwd_l1(self.proj, self.n, self.bins, self.views, self.bg, self.image,
                             self.final_T, self.n_contrib, self.targets, self.dL, self.loss,
                             self.l1_ws)
-        flags = gs.GS_BWD_OVERWRITE | (0 if self.pose else gs.GS_BWD_NO_POSE)
+        flags = (gs.GS_BWD_OVERWRITE | gs.GS_BWD_KEEP_CLEAR
+                 | (0 if self.pose else gs.GS_BWD_NO_POSE))
         gs.gs_render_bwd(self.g, self.proj, self.bins, self.views, self.bg, self.dL, self.final_T,
                          self.n_contrib, self.grads, flags, self.bwd_ws)
         if self.optimize:

@@ -151,12 +151,12 @@ def test_render_argument_errors(gs):
     # pose gradient requested but xi is NULL
     assert lib.gs_render_bwd(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(bins), ctypes.byref(v),
                              None, FAKE, FAKE, FAKE, ctypes.byref(grads), 0, FAKE, need, None) == 1
-    # exclusive flags
+    # exclusive flags, then an unknown flag bit
     grads.xi = FAKE
     assert lib.gs_render_bwd(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(bins), ctypes.byref(v),
                              None, FAKE, FAKE, FAKE, ctypes.byref(grads), 3, FAKE, need, None) == 1
     assert lib.gs_render_bwd(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(bins), ctypes.byref(v),
-                             None, FAKE, FAKE, FAKE, ctypes.byref(grads), 8, FAKE, need, None) == 1
+                             None, FAKE, FAKE, FAKE, ctypes.byref(grads), 16, FAKE, need, None) == 1
     assert lib.gs_render_bwd(ctypes.byref(g), ctypes.byref(proj), ctypes.byref(bins), ctypes.byref(v),
                              None, FAKE, FAKE, FAKE, ctypes.byref(grads), 0, FAKE, need - 1,
                              None) == gs.GS_ERR_CAPACITY

@@ -355,6 +355,30 @@ def test_pose_only_matches_full(gs):
     assert_grad_close("means", np_(nop.means), np_(full.means), rel=1e-4)
 
 
+def test_keep_clear_matches_clearing_backward(gs):
+    """GS_BWD_KEEP_CLEAR on a zeroed workspace, twice in a row with different
+    dL/dC, gives each time the gradients of a backward that clears its
+    partials first: the first call leaves the workspace clear."""
+    from paper_2409_09295_amd.rasterizer import Rasterizer
+    wl = scenes.config_c1(2)
+    g = gs.Gaussians.from_map(wl.gmap)
+    views = gs.Views(wl.cams)
+    rast = Rasterizer(g.n, views)
+    rast.forward(g, wl.bg)
+    ws = gs.workspace(gs.gs_render_bwd_workspace_size(g.n, views), DEV).zero_()
+    for seed in (4, 5):
+        dl = torch.from_numpy(random_dl(views.sizes, seed)).to(DEV)
+        ref = gs.Grads.zeros_like(g, views.n_views)
+        rast.backward(g, dl, ref, gs.GS_BWD_OVERWRITE, wl.bg)
+        got = gs.Grads.zeros_like(g, views.n_views)
+        gs.gs_render_bwd(g, rast.proj, rast.bins, views, wl.bg, dl, rast.final_T, rast.n_contrib,
+                         got, gs.GS_BWD_OVERWRITE | gs.GS_BWD_KEEP_CLEAR, ws)
+        torch.cuda.synchronize()
+        _log(f"keep-clear call with dL seed {seed}")
+        for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "xi"):
+            assert_grad_close(k, np_(getattr(got, k)), np_(getattr(ref, k)), rel=1e-5)
+
+
 # ---------------------------------------------------------------------------
 # elementwise kernels
 # ---------------------------------------------------------------------------
