@@ -461,3 +461,42 @@ def test_adam_first_step_closed_form():
     p2, m2, v2 = O.adam_step(p, g, np.zeros(100), np.zeros(100), lr, 0.9, 0.999, eps, 1, mask)
     np.testing.assert_array_equal(p2[mask == 0], p[mask == 0])
     np.testing.assert_allclose(p2[mask == 1], p1[mask == 1])
+
+
+def test_alpha_band_covers_float32_exponent_rounding():
+    """The near-threshold band on the alpha decisions (relative BAND_REL plus
+    BAND_TERMS times |Q00| dx^2 + 2 |Q01 dx dy| + |Q11| dy^2) bounds the
+    relative error of o e^power when the exponent is evaluated in float32 by
+    either association of its terms, for splats elongated up to 40:1 sampled
+    far along their major axis where the terms cancel most."""
+    rng = np.random.default_rng(7)
+    f32 = np.float32
+    l2e = f32(1.4426950408889634)
+    worst = 0.0
+    for _ in range(2000):
+        s1, s2 = np.exp(rng.uniform(np.log(0.6), np.log(24.0), 2))
+        th = rng.uniform(0, np.pi)
+        cs, sn = np.cos(th), np.sin(th)
+        i1, i2 = 1 / s1 ** 2, 1 / s2 ** 2
+        q = np.array([cs * cs * i1 + sn * sn * i2, cs * sn * (i1 - i2), sn * sn * i1 + cs * cs * i2],
+                     np.float32)
+        mx, my = rng.uniform(0, 1200, 2).astype(np.float32)
+        major = (cs, sn) if s1 > s2 else (-sn, cs)
+        t = rng.uniform(-3, 3) * max(s1, s2)
+        px = f32(np.floor(mx + t * major[0]) + 0.5)
+        py = f32(np.floor(my + t * major[1]) + 0.5)
+        dx, dy = f32(px - mx), f32(py - my)
+        a, b, c = f32(-0.5) * l2e * q[0], -l2e * q[1], f32(-0.5) * l2e * q[2]
+        fma = lambda x, y, z: f32(np.float64(x) * np.float64(y) + np.float64(z))
+        p_a = fma(dx, fma(a, dx, b * dy), (c * dy) * dy)
+        p_b = fma(dy, fma(c, dy, b * dx), (a * dx) * dx)
+        dx64, dy64 = np.float64(px) - np.float64(mx), np.float64(py) - np.float64(my)
+        q64 = q.astype(np.float64)
+        exact = -0.5 * (q64[0] * dx64 ** 2 + 2 * q64[1] * dx64 * dy64 + q64[2] * dy64 ** 2)
+        terms = abs(q64[0]) * dx64 ** 2 + 2 * abs(q64[1] * dx64 * dy64) + abs(q64[2]) * dy64 ** 2
+        band = O.BAND_REL + O.BAND_TERMS * terms
+        for p in (p_a, p_b):
+            rel = abs(np.expm1(np.float64(p) / 1.4426950408889634 - exact))
+            worst = max(worst, rel / band)
+            assert rel <= band, (rel, band, terms)
+    assert worst > 0.01, worst   # the bound is exercised, not vacuous
