@@ -117,12 +117,17 @@ typedef struct gs_views {
  *   xy            float2: u, v
  *   conic_opacity float4: Q00, Q01, Q11, o
  *   rgb_depth     float4: r, g, b, camera-frame z
- *   radius        int32:  r in pixels, 0 = culled */
+ *   radius        int32:  r in pixels, 0 = culled
+ *   tiles         uint32: number of tiles the splat's rectangle covers, 0 if
+ *                 it covers none (optional: NULL = not stored; gs_preprocess
+ *                 writes it when non-NULL, gs_bin_sort reads it when non-NULL
+ *                 and otherwise computes it from xy and radius) */
 typedef struct gs_projected {
   float* xy;
   float* conic_opacity;
   float* rgb_depth;
   int32_t* radius;
+  uint32_t* tiles;
 } gs_projected;
 
 /* Tile binning result (device):

@@ -2,6 +2,7 @@
 //
 //   count     one lane per (view, splat): tile rectangle (float64 from the
 //             float32 centre) -> number of tiles, and whether it has any
+//             (skipped when the projection stored the counts)
 //   depth     the splats with tiles are compacted in entry order (a scan of
 //             the flags) and sorted by their float32 depth bits with a
 //             stable LSD radix sort, so equal depths keep entry order; this
@@ -72,6 +73,15 @@ __device__ __forceinline__ T block_exclusive_scan(T x, T* s_wave, T& total) {
 // generic exclusive scan of uint32 values (out may alias in)
 // ---------------------------------------------------------------------------
 
+// PRED: the scanned value is (in[i] != 0) instead of in[i].
+template <bool PRED>
+__device__ __forceinline__ uint32_t scan_in(const uint32_t* in, int64_t idx, int64_t n) {
+  if (idx >= n) return 0u;
+  const uint32_t x = in[idx];
+  return PRED ? (x != 0u ? 1u : 0u) : x;
+}
+
+template <bool PRED>
 __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in,
                                                                    int64_t n,
                                                                    uint64_t* __restrict__ partial) {
@@ -79,10 +89,8 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   uint64_t acc = 0;
 #pragma unroll
-  for (int r = 0; r < kScanItems; ++r) {
-    const int64_t idx = base + r * kScanThreads + threadIdx.x;
-    acc += (idx < n) ? in[idx] : 0u;
-  }
+  for (int r = 0; r < kScanItems; ++r)
+    acc += scan_in<PRED>(in, base + r * kScanThreads + threadIdx.x, n);
   uint64_t tot;
   block_exclusive_scan<uint64_t>(acc, s_wave, tot);
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
@@ -120,6 +128,8 @@ __global__ __launch_bounds__(kPartThreads) void scan_partials_kernel(uint64_t* _
   }
 }
 
+// out may alias in: every value is read before its position is written.
+template <bool PRED>
 __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t* in, int64_t n,
                                                                  const uint64_t* __restrict__ partial,
                                                                  uint32_t* out) {
@@ -128,7 +138,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t*
   uint32_t carry = (uint32_t)partial[blockIdx.x];
   for (int r = 0; r < kScanItems; ++r) {
     const int64_t idx = base + r * kScanThreads + threadIdx.x;
-    const uint32_t x = (idx < n) ? in[idx] : 0u;
+    const uint32_t x = scan_in<PRED>(in, idx, n);
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan<uint32_t>(x, s_wave, tot);
     if (idx < n) out[idx] = carry + ex;
@@ -136,16 +146,18 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t*
   }
 }
 
+// Exclusive scan of in[0, n) (of in[i] != 0 with PRED) into out.
+template <bool PRED = false>
 void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint64_t* partial, uint64_t* total,
               uint32_t* n_keys, hipStream_t s) {
   const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
   if (nb > 0)
-    hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n,
-                       partial);
+    hipLaunchKernelGGL(scan_reduce_kernel<PRED>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in,
+                       n, partial);
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kPartThreads), 0, s, partial, nb, total,
                      n_keys);
   if (nb > 0)
-    hipLaunchKernelGGL(scan_down_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n,
+    hipLaunchKernelGGL(scan_down_kernel<PRED>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n,
                        partial, out);
 }
 
@@ -498,12 +510,19 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   kernel_event_start(GS_KERNEL_BIN_SORT, s);
   if ((e = launch_fill_u32(bins.ranges, 0u, 2 * (int64_t)vt.n_tiles, s)) != hipSuccess)
     return hip_fail(e, "fill ranges");
-  // 1. tiles per splat; binned splats compacted in entry order with their depth
+  // 1. tiles per splat (from the projection when it stored them); binned
+  // splats compacted in entry order with their depth
   if (ne > 0) {
-    hipLaunchKernelGGL(count_kernel, dim3(eblocks), dim3(256), 0, s, xy, p.radius, ne, n, vt,
-                       counts, offsets);
-    scan_u32(offsets, offsets, ne, part, flag + 1, n_binned, s);
-    hipLaunchKernelGGL(compact_kernel, dim3(eblocks), dim3(256), 0, s, counts, offsets, rd, ne,
+    const uint32_t* tiles = p.tiles;
+    if (tiles) {
+      scan_u32<true>(tiles, offsets, ne, part, flag + 1, n_binned, s);
+    } else {
+      hipLaunchKernelGGL(count_kernel, dim3(eblocks), dim3(256), 0, s, xy, p.radius, ne, n, vt,
+                         counts, offsets);
+      scan_u32(offsets, offsets, ne, part, flag + 1, n_binned, s);
+      tiles = counts;
+    }
+    hipLaunchKernelGGL(compact_kernel, dim3(eblocks), dim3(256), 0, s, tiles, offsets, rd, ne,
                        dkey, dval);
     // 2. stable sort of the binned splats by depth (ties keep entry order)
     uint32_t *ka = dkey, *va = dval, *kb = dkey + ne, *vb = dval + ne;
@@ -514,7 +533,7 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
     }
     // ka/va (= dkey/dval after an even number of passes) hold the depth order
     // 3. key offsets in depth order; their total is the key count
-    hipLaunchKernelGGL(gather_counts_kernel, dim3(eblocks), dim3(256), 0, s, va, n_binned, counts,
+    hipLaunchKernelGGL(gather_counts_kernel, dim3(eblocks), dim3(256), 0, s, va, n_binned, tiles,
                        ne, offsets);
     scan_u32(offsets, offsets, ne, part, flag, bins.n_keys, s);
   } else {

@@ -4,7 +4,8 @@
 // parameters are read with coalesced component-major loads (lane i reads
 // element i of each component array) and reused for every view of the group,
 // so a batch of V views costs ceil(V / kViewsPerLane) reads of the map (the
-// repeats hit in L2/MALL) plus V writes of 52 bytes per Gaussian; splitting
+// repeats hit in L2/MALL) plus, per view, 48 bytes written for a visible splat
+// (44 without tile counts) and 8 for a culled one (4); splitting
 // the views over grid.y keeps enough wavefronts in flight to hide the long
 // per-view dependency chain.  Camera records are wave-uniform.
 #include "project.h"
@@ -19,7 +20,7 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
     const float* __restrict__ quats, const float* __restrict__ ologit,
     const float* __restrict__ sh, int64_t n, const gs_camera* __restrict__ cams, int n_views,
     float2* __restrict__ xy, float4* __restrict__ co, float4* __restrict__ rd,
-    int32_t* __restrict__ radius) {
+    int32_t* __restrict__ radius, uint32_t* __restrict__ tiles) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   GaussState G;
@@ -38,8 +39,14 @@ __global__ __launch_bounds__(256) void preprocess_kernel(
       co[o] = make_float4(S.q0, S.q1, S.q2, G.o);
       rd[o] = make_float4(S.rgb[0], S.rgb[1], S.rgb[2], S.p[2]);
       radius[o] = S.radius;
+      if (tiles) {   // tiles of the rectangle, as the binning counts them
+        Rect rc;
+        const bool ok = tile_rect(S.u, S.v, S.radius, cam.width, cam.height, rc);
+        tiles[o] = ok ? (uint32_t)((rc.x1 - rc.x0) * (rc.y1 - rc.y0)) : 0u;
+      }
     } else {
       radius[o] = 0;   // the other fields of a culled entry are never read
+      if (tiles) tiles[o] = 0u;
     }
   }
 }
@@ -56,19 +63,23 @@ hipError_t launch_preprocess(const gs_gaussians& g, const gs_camera* cams_dev, i
   switch (g.sh_degree) {
     case 0:
       hipLaunchKernelGGL(preprocess_kernel<0>, grid, block, 0, s, g.means, g.log_scales, g.quats,
-                         g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius);
+                         g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius,
+                         out.tiles);
       break;
     case 1:
       hipLaunchKernelGGL(preprocess_kernel<1>, grid, block, 0, s, g.means, g.log_scales, g.quats,
-                         g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius);
+                         g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius,
+                         out.tiles);
       break;
     case 2:
       hipLaunchKernelGGL(preprocess_kernel<2>, grid, block, 0, s, g.means, g.log_scales, g.quats,
-                         g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius);
+                         g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius,
+                         out.tiles);
       break;
     default:
       hipLaunchKernelGGL(preprocess_kernel<3>, grid, block, 0, s, g.means, g.log_scales, g.quats,
-                         g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius);
+                         g.opacity_logits, g.sh, g.n, cams_dev, n_views, xy, co, rd, out.radius,
+                         out.tiles);
       break;
   }
   kernel_event_stop(GS_KERNEL_PREPROCESS, s);

@@ -73,7 +73,8 @@ class gs_views(ctypes.Structure):
 
 
 class gs_projected(ctypes.Structure):
-    _fields_ = [("xy", _p), ("conic_opacity", _p), ("rgb_depth", _p), ("radius", _p)]
+    _fields_ = [("xy", _p), ("conic_opacity", _p), ("rgb_depth", _p), ("radius", _p),
+                ("tiles", _p)]
 
 
 class gs_bins(ctypes.Structure):
@@ -276,12 +277,13 @@ class Projected:
     conic_opacity: torch.Tensor    # (V, N, 4)
     rgb_depth: torch.Tensor        # (V, N, 4)
     radius: torch.Tensor           # (V, N) int32
+    tiles: Optional[torch.Tensor] = None   # (V, N) int32 storage of uint32, or not stored
 
     @classmethod
     def empty(cls, n_views: int, n: int, device="cuda") -> "Projected":
         f = lambda *s: torch.empty(*s, dtype=torch.float32, device=device)
-        return cls(f(n_views, n, 2), f(n_views, n, 4), f(n_views, n, 4),
-                   torch.empty(n_views, n, dtype=torch.int32, device=device))
+        i = lambda: torch.empty(n_views, n, dtype=torch.int32, device=device)
+        return cls(f(n_views, n, 2), f(n_views, n, 4), f(n_views, n, 4), i(), i())
 
     @classmethod
     def from_splats(cls, sp: scenes.SplatSet, device="cuda") -> "Projected":
@@ -290,7 +292,7 @@ class Projected:
 
     def struct(self) -> gs_projected:
         return gs_projected(_ptr(self.xy), _ptr(self.conic_opacity), _ptr(self.rgb_depth),
-                            _ptr(self.radius))
+                            _ptr(self.radius), _ptr(self.tiles) if self.tiles is not None else None)
 
 
 @dataclasses.dataclass

@@ -224,6 +224,11 @@ def _check_projection(gs, wl, out, res):
         conic = P["conic"][sel]
         scale = np.abs(conic).max(axis=1, keepdims=True)
         assert (np.abs(co[sel, :3] - conic) <= 2e-5 * scale + 1e-9).all()
+        # stored tile counts: the oracle's rectangles of the stored centres and radii
+        cam = wl.cams[v]
+        *_, cnt = O.tile_rects(xy[:, 0].astype(np.float64), xy[:, 1].astype(np.float64),
+                               np.where(rad > 0, rad, 0), int(cam.width), int(cam.height), 16)
+        np.testing.assert_array_equal(np_(proj.tiles[v]).astype(np.int64), cnt)
 
 
 def _compare_images(views, out, res, tol=1e-4):
