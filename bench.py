@@ -229,6 +229,7 @@ def main():
     # algorithmic work of the reverse tile walk: list positions each pixel walks
     pairs_bwd = int(step.n_contrib.to(torch.int64).sum().item())
     n_visible = int((step.proj.radius > 0).sum().item())
+    n_binned = int((step.proj.tiles != 0).sum().item())   # visible splats that touch a tile
     del step
     torch.cuda.empty_cache()
 
@@ -300,16 +301,17 @@ def main():
 
     # HBM-bound stages: algorithmic bytes per launch / event-timed duration
     K = (wl.gmap.sh_degree + 1) ** 2
-    # preprocess: the map once, a 44-byte splat per visible (Gaussian, view),
-    # a radius per culled one
-    pre_bytes = (g.n * 4 * (3 + 3 + 4 + 1 + 3 * K) + n_visible * (8 + 16 + 16 + 4)
-                 + (g.n * len(wl.cams) - n_visible) * 4)
-    # binning: radii and centres of every entry (12 B), the depth sort of the
-    # visible splats (4 passes, 8 B read + 8 B written), 12 B per key emitted
-    # and 24 B per key per tile-digit pass
+    # preprocess: the map once, a 48-byte splat (with its tile count) per
+    # visible (Gaussian, view), a radius and a zero count per culled one
+    pre_bytes = (g.n * 4 * (3 + 3 + 4 + 1 + 3 * K) + n_visible * (8 + 16 + 16 + 4 + 4)
+                 + (g.n * len(wl.cams) - n_visible) * 8)
+    # binning: the tile count of every entry (4 B) and the radius, centre and
+    # depth of every binned splat (one that touches a tile), the depth sort of
+    # the binned splats (4 passes, 8 B read + 8 B written), 12 B per key
+    # emitted and 24 B per key per tile-digit pass
     tile_passes = math.ceil(max(1, math.ceil(math.log2(max(views.n_tiles, 2)))) / 8)
-    sort_bytes = (g.n * len(wl.cams) * 12 + n_visible * 4 * 16 + n_keys * 12
-                  + n_keys * 24 * tile_passes)
+    sort_bytes = (g.n * len(wl.cams) * 4 + n_binned * (4 + 8 + 4) + n_binned * 4 * 16
+                  + n_keys * 12 + n_keys * 24 * tile_passes)
     hbm = {name: {"bytes": b, "ms": kms[name], "GB/s": b / (kms[name] * 1e-3) / 1e9,
                   "frac": b / (kms[name] * 1e-3) / 1e9 / HBM_PEAK_GBS}
            for name, b in (("preprocess", pre_bytes), ("bin_sort", sort_bytes))}
