@@ -128,22 +128,36 @@ __global__ __launch_bounds__(kPartThreads) void scan_partials_kernel(uint64_t* _
   }
 }
 
-// out may alias in: every value is read before its position is written.
+// Each wave scans 1024 consecutive values of the block's chunk as 16 rows of
+// 64 (coalesced), carrying the running total from row to row, so only the
+// four wave totals need a block-level step.  out may alias in: every value is
+// read before its position is written.
 template <bool PRED>
 __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t* in, int64_t n,
                                                                  const uint64_t* __restrict__ partial,
                                                                  uint32_t* out) {
   __shared__ uint32_t s_wave[4];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk;
-  uint32_t carry = (uint32_t)partial[blockIdx.x];
-  for (int r = 0; r < kScanItems; ++r) {
-    const int64_t idx = base + r * kScanThreads + threadIdx.x;
-    const uint32_t x = scan_in<PRED>(in, idx, n);
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<uint32_t>(x, s_wave, tot);
-    if (idx < n) out[idx] = carry + ex;
-    carry += tot;
+  constexpr int kRows = kScanChunk / kScanThreads;   // 16 rows of 64 per wave
+  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)w * (64 * kRows) + lane;
+  uint32_t x[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) x[r] = scan_in<PRED>(in, base + 64 * r, n);
+  uint32_t run = 0;
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const uint32_t inc = wave_inclusive_scan(x[r]);
+    const uint32_t row_tot = __builtin_amdgcn_readlane(inc, 63);
+    x[r] = run + inc - x[r];   // exclusive prefix within the wave's 1024 values
+    run += row_tot;
   }
+  if (lane == 0) s_wave[w] = run;
+  __syncthreads();
+  uint32_t carry = (uint32_t)partial[blockIdx.x];
+  for (uint32_t k = 0; k < w; ++k) carry += s_wave[k];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r)
+    if (base + 64 * r < n) out[base + 64 * r] = carry + x[r];
 }
 
 // Exclusive scan of in[0, n) (of in[i] != 0 with PRED) into out.
