@@ -15,6 +15,7 @@ resident in device memory before timing starts.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -231,6 +232,7 @@ def main():
     n_visible = int((step.proj.radius > 0).sum().item())
     n_binned = int((step.proj.tiles != 0).sum().item())   # visible splats that touch a tile
     del step
+    gc.collect()
     torch.cuda.empty_cache()
 
     # ---------------- paper-shaped batch: 8 window + 4 past views ----------------
@@ -244,6 +246,7 @@ def main():
                "value": views12.n_pixels / (ms12 * 1e-3) / 1e6, "unit": "Mpix/s"}
         print(f"[bench] 12 views: {ms12:.3f} ms/step", file=sys.stderr, flush=True)
         del step12
+        gc.collect()
         torch.cuda.empty_cache()
 
     # ---------------- plain per-view reference ----------------

@@ -136,13 +136,20 @@ typedef struct gs_projected {
  *   values [capacity] uint32 view * n + Gaussian index
  *   ranges [n_tiles][2] uint32 [start, end) into keys/values per global tile
  *   n_keys [1] uint32 number of keys emitted (may exceed capacity, in which
- *          case the call reported or flagged overflow and keys are partial) */
+ *          case the call reported or flagged overflow and keys are partial)
+ *   order  [n_tiles] uint32 (optional, NULL = not computed): every global
+ *          tile id once, longest lists first (grouped by list length in
+ *          half-octave steps; the order within a group is not specified).
+ *          gs_bin_sort writes it when non-NULL; the compositing calls then
+ *          start the most expensive tiles first, which shortens the tail of
+ *          the launch, and their results do not depend on it. */
 typedef struct gs_bins {
   uint64_t* keys;
   uint32_t* values;
   uint32_t* ranges;
   uint32_t* n_keys;
   int64_t capacity;
+  uint32_t* order;
 } gs_bins;
 
 /* Gradients, same layouts as gs_gaussians, accumulated (+=).  xi [V][6]

@@ -450,6 +450,45 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint64_t* __restrict_
     ranges[2 * (int64_t)tile + 1] = (uint32_t)(i + 1);
 }
 
+// Tile order, longest lists first: 32 groups by list length (0, then half
+// octaves), filled longest group first; one workgroup.  Positions within a
+// group come from LDS atomics (unspecified order, every tile exactly once).
+constexpr int kOrderGroups = 32;
+
+__device__ __forceinline__ int length_group(uint32_t len) {   // ascending in len
+  if (len == 0) return 0;
+  const int lg = 31 - __clz(len);
+  const int half = lg > 0 ? (int)((len >> (lg - 1)) & 1u) : 0;
+  return min(kOrderGroups - 1, 1 + 2 * lg + half);
+}
+
+__global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t* __restrict__ ranges,
+                                                          int n_tiles, uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_cnt[kOrderGroups];
+  __shared__ uint32_t s_cur[kOrderGroups];
+  if (threadIdx.x < kOrderGroups) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x)
+    atomicAdd(&s_cnt[length_group(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = kOrderGroups - 1; b >= 0; --b) {
+      s_cur[b] = run;
+      run += s_cnt[b];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x)
+    order[atomicAdd(&s_cur[length_group(ranges[2 * t + 1] - ranges[2 * t])], 1u)] = (uint32_t)t;
+}
+
+// Identity order (so that bins.order is a permutation on every return path).
+__global__ __launch_bounds__(256) void identity_order_kernel(uint32_t* __restrict__ order, int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) order[t] = (uint32_t)t;
+}
+
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
@@ -524,6 +563,9 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   kernel_event_start(GS_KERNEL_BIN_SORT, s);
   if ((e = launch_fill_u32(bins.ranges, 0u, 2 * (int64_t)vt.n_tiles, s)) != hipSuccess)
     return hip_fail(e, "fill ranges");
+  if (bins.order && vt.n_tiles > 0)
+    hipLaunchKernelGGL(identity_order_kernel, dim3((unsigned)((vt.n_tiles + 255) / 256)),
+                       dim3(256), 0, s, bins.order, vt.n_tiles);
   // 1. tiles per splat (from the projection when it stored them); binned
   // splats compacted in entry order with their depth
   if (ne > 0) {
@@ -591,6 +633,9 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   }
   hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((n_sort + 255) / 256)), dim3(256), 0, s,
                      bins.keys, bins.n_keys, P.capacity, bins.ranges);
+  if (bins.order && vt.n_tiles > 0)
+    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, bins.ranges, vt.n_tiles,
+                       bins.order);
   kernel_event_stop(GS_KERNEL_BIN_SORT, s);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "bin sort launch");
   return GS_OK;

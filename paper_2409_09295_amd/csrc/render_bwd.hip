@@ -118,6 +118,7 @@ __device__ __forceinline__ uint32_t stage_splat(uint32_t g, uint32_t n, uint32_t
 template <int PPL>
 __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     ViewTable vt, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
+    const uint32_t* __restrict__ order,
     const float2* __restrict__ xy, const float4* __restrict__ co, const float4* __restrict__ rd,
     float3 bg, const float* __restrict__ dL_dimage, const float* __restrict__ final_T,
     const uint32_t* __restrict__ n_contrib, uint32_t n_gauss, float* __restrict__ grad2d) {
@@ -131,7 +132,9 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
   // s_reach[q][w] bit b: staged splat 64 w + b can reach quadrant q
   __shared__ uint64_t s_reach[4][kWords];
   __shared__ uint32_t s_maxlast;
-  const int tile = blockIdx.x;
+  // the tile order (longest lists first) when the binning produced one
+  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+  if (tile >= vt.n_tiles) return;
   const int v = find_view(vt, tile);
   const ViewInfo& vi = vt.v[v];
   const int lt = tile - vi.tile_base;
@@ -618,15 +621,15 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
     kernel_event_start(GS_KERNEL_RENDER_BWD, s);
     if (ppl == 4)
       hipLaunchKernelGGL(render_bwd_kernel<4>, grid, dim3(kBlock / 4), 0, s, vt, bins.ranges,
-                         bins.values, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
+                         bins.values, bins.order, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
                          (uint32_t)g.n, grad2d);
     else if (ppl == 2)
       hipLaunchKernelGGL(render_bwd_kernel<2>, grid, dim3(kBlock / 2), 0, s, vt, bins.ranges,
-                         bins.values, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
+                         bins.values, bins.order, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
                          (uint32_t)g.n, grad2d);
     else
       hipLaunchKernelGGL(render_bwd_kernel<1>, grid, dim3(kBlock), 0, s, vt, bins.ranges,
-                         bins.values, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
+                         bins.values, bins.order, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
                          (uint32_t)g.n, grad2d);
     kernel_event_stop(GS_KERNEL_RENDER_BWD, s);
   }

@@ -36,6 +36,7 @@ __device__ __forceinline__ uint32_t stage_splat(uint32_t g, const float2* __rest
 template <int PPL, bool L1>
 __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
     ViewTable vt, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
+    const uint32_t* __restrict__ order,
     const float2* __restrict__ xy, const float4* __restrict__ co, const float4* __restrict__ rd,
     float3 bg, float* __restrict__ image, float* __restrict__ final_T,
     uint32_t* __restrict__ n_contrib, float* __restrict__ depth_out,
@@ -49,7 +50,9 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
   __shared__ StagedSplat s_splat[kStage];
   // s_reach[q][w] bit b: staged splat 64 w + b can reach quadrant q
   __shared__ uint64_t s_reach[4][kWords];
-  const int tile = blockIdx.x;
+  // the tile order (longest lists first) when the binning produced one
+  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+  if (tile >= vt.n_tiles) return;
   const int v = find_view(vt, tile);
   const ViewInfo& vi = vt.v[v];
   const int lt = tile - vi.tile_base;
@@ -229,8 +232,8 @@ hipError_t launch_render_fwd(const gs_projected& p, const gs_bins& bins, const V
   const bool l1 = target != nullptr;
 #define GS_FWD(P, L)                                                                       \
   hipLaunchKernelGGL((render_fwd_kernel<P, L>), grid, dim3(kBlock / P), 0, s, vt, bins.ranges, \
-                     bins.values, xy, co, rd, bg, image, final_T, n_contrib, depth, target,  \
-                     dL, tile_loss)
+                     bins.values, bins.order, xy, co, rd, bg, image, final_T, n_contrib, depth, \
+                     target, dL, tile_loss)
   kernel_event_start(GS_KERNEL_RENDER_FWD, s);
   if (ppl == 4) {
     if (l1) GS_FWD(4, true); else GS_FWD(4, false);

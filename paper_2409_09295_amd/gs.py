@@ -79,7 +79,7 @@ class gs_projected(ctypes.Structure):
 
 class gs_bins(ctypes.Structure):
     _fields_ = [("keys", _p), ("values", _p), ("ranges", _p), ("n_keys", _p),
-                ("capacity", ctypes.c_int64)]
+                ("capacity", ctypes.c_int64), ("order", _p)]
 
 
 class gs_grads(ctypes.Structure):
@@ -302,18 +302,20 @@ class Bins:
     ranges: torch.Tensor   # (n_tiles, 2) int32 storage of uint32
     n_keys: torch.Tensor   # (1,) int32 storage of uint32
     capacity: int
+    order: Optional[torch.Tensor] = None   # (n_tiles,) int32 storage of uint32, or not computed
 
     @classmethod
-    def empty(cls, capacity: int, n_tiles: int, device="cuda") -> "Bins":
+    def empty(cls, capacity: int, n_tiles: int, device="cuda", order: bool = True) -> "Bins":
         cap = max(int(capacity), 1)
         return cls(torch.empty(cap, dtype=torch.int64, device=device),
                    torch.empty(cap, dtype=torch.int32, device=device),
                    torch.empty(n_tiles, 2, dtype=torch.int32, device=device),
-                   torch.zeros(1, dtype=torch.int32, device=device), int(capacity))
+                   torch.zeros(1, dtype=torch.int32, device=device), int(capacity),
+                   torch.empty(max(n_tiles, 1), dtype=torch.int32, device=device) if order else None)
 
     def struct(self) -> gs_bins:
         return gs_bins(_ptr(self.keys), _ptr(self.values), _ptr(self.ranges), _ptr(self.n_keys),
-                       self.capacity)
+                       self.capacity, _ptr(self.order) if self.order is not None else None)
 
 
 @dataclasses.dataclass
@@ -351,6 +353,12 @@ def gs_preprocess(g: Gaussians, views: Views, out: Projected, stream=None) -> No
                               _stream(stream)), "gs_preprocess")
 
 
+def _capacity_error(status: int, required: int) -> GsError:
+    err = GsError(status, "gs_bin_sort")
+    err.required = required
+    return err
+
+
 def gs_bin_sort_workspace_size(n: int, views: Views, capacity: int) -> int:
     return int(_lib.gs_bin_sort_workspace_size(n, ctypes.byref(views.struct), capacity))
 
@@ -364,9 +372,10 @@ def gs_bin_sort(p: Projected, n: int, views: Views, bins: Bins, ws: torch.Tensor
     st = _lib.gs_bin_sort(ctypes.byref(ps), n, ctypes.byref(views.struct), ctypes.byref(bs),
                           ctypes.byref(cnt) if sync else None, _ptr(ws), ws.numel(), _stream(stream))
     if st != GS_OK:
-        err = GsError(st, "gs_bin_sort")
-        err.required = int(cnt.value)
-        raise err
+        # built and raised in one expression: an exception held in a local of
+        # this frame would reference itself through its traceback, keeping the
+        # caller's frame (and everything it holds) alive until a cyclic GC pass
+        raise _capacity_error(st, int(cnt.value))
     return int(cnt.value) if sync else None
 
 

@@ -28,6 +28,7 @@ views, then the same Adam updates.
 """
 from __future__ import annotations
 
+import gc
 from typing import Dict, Optional, Sequence
 
 import torch
@@ -143,6 +144,10 @@ class BatchedStep:
         torch.cuda.synchronize()
         self.adam.restore(snap)
         torch.cuda.synchronize()
+        # Collect unreachable cycles now: a dead step found by the collector
+        # during the capture would free its graph's memory pool, and freeing
+        # device memory is not allowed while a stream is capturing.
+        gc.collect()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             self._body()

@@ -217,3 +217,35 @@ def test_nn_argument_errors(gs):
     assert lib.gs_cost_volume_wta(ctypes.c_void_p(0xDEAD0000), ctypes.byref(odd), None,
                                   ctypes.c_void_p(0xDEAD0000), ctypes.c_void_p(0xDEAD0000), 1 << 20,
                                   None) == bad
+
+
+def test_capacity_error_holds_no_reference_cycle(gs):
+    """A caught capacity error must not keep the catching frame's locals
+    alive: a step object kept by such a cycle is freed only by a later
+    cyclic GC pass, which may run while a graph is being captured."""
+    import gc
+    import weakref
+
+    class Owner:
+        pass
+
+    def raiser():
+        raise gs._capacity_error(gs.GS_ERR_CAPACITY, 123)
+
+    def catcher(owner):
+        try:
+            raiser()
+        except gs.GsError as e:
+            return e.required
+
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        owner = Owner()
+        ref = weakref.ref(owner)
+        assert catcher(owner) == 123
+        del owner
+        assert ref() is None
+    finally:
+        if was:
+            gc.enable()

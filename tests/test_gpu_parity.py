@@ -89,6 +89,43 @@ def test_bin_sort_crowded_tiles(gs, n):
         np.testing.assert_array_equal(u32(bins.ranges), ranges)
 
 
+def test_tile_order_longest_first(gs):
+    """bins.order is a permutation of the tiles with non-increasing list-length
+    groups (half octaves), and compositing gives the same image with it as
+    in plain tile order."""
+    cams = BIN_CASES["ragged_multi_view"]
+    sp = scenes.random_splats(4000, cams, seed=33)
+    views, proj, bins, nk = _gpu_bins(gs, sp, cams)
+    order = np_(bins.order).astype(np.int64)
+    assert sorted(order.tolist()) == list(range(views.n_tiles))
+    rg = np_(bins.ranges).astype(np.int64)
+    ln = rg[:, 1] - rg[:, 0]
+
+    def group(x):
+        if x == 0:
+            return 0
+        lg = int(x).bit_length() - 1
+        half = (int(x) >> (lg - 1)) & 1 if lg > 0 else 0
+        return min(31, 1 + 2 * lg + half)
+
+    groups = np.array([group(x) for x in ln[order]])
+    assert (np.diff(groups) <= 0).all()
+    assert ln[order[0]] == ln.max()
+    outs = []
+    for use_order in (True, False):
+        b = bins if use_order else gs.Bins(bins.keys, bins.values, bins.ranges, bins.n_keys,
+                                           bins.capacity, None)
+        P = views.n_pixels
+        img = torch.empty(3 * P, device=DEV)
+        Tf = torch.empty(P, device=DEV)
+        nc = torch.empty(P, dtype=torch.int32, device=DEV)
+        gs.gs_render_fwd(proj, sp.radius.shape[1], b, views, (0.2, 0.1, 0.05), img, Tf, nc, None)
+        torch.cuda.synchronize()
+        outs.append((img, Tf, nc))
+    for a, c in zip(*outs):
+        torch.testing.assert_close(a, c, rtol=0, atol=0)
+
+
 def test_bin_sort_all_culled(gs):
     cams = [scenes.pinhole(64, 48, 60.0)]
     sp = scenes.random_splats(500, cams, seed=2)
