@@ -37,10 +37,14 @@ WORKLOADS = {
 }
 
 HBM_PEAK_GBS = 8000.0
-# VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-
-# instructions per second (a wave64 VALU instruction occupies a SIMD for four
-# cycles; packed FP32 and FMA counting are what take the FP32 figure to 157.3).
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# VALU peak: the published FP32 vector rate, 157.3 TFLOP/s, counts an FMA as
+# two operations: 256 CUs x 128 lanes x 2.4 GHz = 78.6 T lane-operations per
+# second, i.e. two wave64 instructions per CU per cycle.  Measured on the
+# MI355X, independent chains of v_mul/v_add/v_sub/v_fmac with VGPR (or inline
+# constant) operands issue at 1.8-1.9 per CU-cycle; compares, min/max/med3,
+# DPP, shifts, conversions and any instruction with an SGPR source issue at
+# half that, v_exp/v_rcp at a quarter.
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 
 # VALU instructions per (pixel, splat) pair in the per-pixel body of the
 # compositing loops, counted in the gfx950 assembly of this library: every

@@ -451,8 +451,9 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint64_t* __restrict_
 }
 
 // Tile order, longest lists first: 32 groups by list length (0, then half
-// octaves), filled longest group first; one workgroup.  Positions within a
-// group come from LDS atomics (unspecified order, every tile exactly once).
+// octaves), filled longest group first.  Positions within a group are
+// unspecified (every tile appears exactly once).  grp[0..31] counts each
+// group, grp[32..63] hands out positions; both start at zero.
 constexpr int kOrderGroups = 32;
 
 __device__ __forceinline__ int length_group(uint32_t len) {   // ascending in len
@@ -462,31 +463,54 @@ __device__ __forceinline__ int length_group(uint32_t len) {   // ascending in le
   return min(kOrderGroups - 1, 1 + 2 * lg + half);
 }
 
-__global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t* __restrict__ ranges,
-                                                          int n_tiles, uint32_t* __restrict__ order) {
-  __shared__ uint32_t s_cnt[kOrderGroups];
-  __shared__ uint32_t s_cur[kOrderGroups];
-  if (threadIdx.x < kOrderGroups) s_cnt[threadIdx.x] = 0;
-  __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x)
-    atomicAdd(&s_cnt[length_group(ranges[2 * t + 1] - ranges[2 * t])], 1u);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int b = kOrderGroups - 1; b >= 0; --b) {
-      s_cur[b] = run;
-      run += s_cnt[b];
-    }
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x)
-    order[atomicAdd(&s_cur[length_group(ranges[2 * t + 1] - ranges[2 * t])], 1u)] = (uint32_t)t;
+__device__ __forceinline__ int tile_group(const uint32_t* ranges, int t) {
+  return length_group(ranges[2 * (int64_t)t + 1] - ranges[2 * (int64_t)t]);
 }
 
-// Identity order (so that bins.order is a permutation on every return path).
-__global__ __launch_bounds__(256) void identity_order_kernel(uint32_t* __restrict__ order, int n) {
+__global__ __launch_bounds__(256) void order_count_kernel(const uint32_t* __restrict__ ranges,
+                                                          int n_tiles, uint32_t* __restrict__ grp) {
+  __shared__ uint32_t s_cnt[kOrderGroups];
+  if (threadIdx.x < kOrderGroups) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_tiles) atomicAdd(&s_cnt[tile_group(ranges, t)], 1u);
+  __syncthreads();
+  if (threadIdx.x < kOrderGroups && s_cnt[threadIdx.x] != 0)
+    atomicAdd(&grp[threadIdx.x], s_cnt[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(256) void order_scatter_kernel(const uint32_t* __restrict__ ranges,
+                                                            int n_tiles, uint32_t* __restrict__ grp,
+                                                            uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_cnt[kOrderGroups];
+  __shared__ uint32_t s_base[kOrderGroups];
+  if (threadIdx.x < kOrderGroups) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int g = 0;
+  uint32_t rank = 0;
+  if (t < n_tiles) {
+    g = tile_group(ranges, t);
+    rank = atomicAdd(&s_cnt[g], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kOrderGroups) {
+    const int b = (int)threadIdx.x;
+    uint32_t start = 0;   // tiles in the longer groups
+    for (int h = kOrderGroups - 1; h > b; --h) start += grp[h];
+    s_base[b] = s_cnt[b] ? start + atomicAdd(&grp[kOrderGroups + b], s_cnt[b]) : 0u;
+  }
+  __syncthreads();
+  if (t < n_tiles) order[s_base[g] + rank] = (uint32_t)t;
+}
+
+// Identity order (so that bins.order is a permutation on every return path);
+// also clears the group counters of the tile order.
+__global__ __launch_bounds__(256) void identity_order_kernel(uint32_t* __restrict__ order, int n,
+                                                             uint32_t* __restrict__ grp) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) order[t] = (uint32_t)t;
+  if (blockIdx.x == 0 && threadIdx.x < 2 * kOrderGroups) grp[threadIdx.x] = 0;
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -524,6 +548,7 @@ BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity)
   P.off_hist = off;      off += align_up(sizeof(uint32_t) * hist_n);
   P.off_hist_part = off; off += align_up(sizeof(uint32_t) * 256);   // digit totals
   P.off_flag = off;      off += align_up(sizeof(uint64_t) * 8);
+  P.off_order = off;     off += align_up(sizeof(uint32_t) * 2 * kOrderGroups);   // tile order
   P.total = off;
   return P;
 }
@@ -554,6 +579,7 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   auto* digit_tot = reinterpret_cast<uint32_t*>(ws + P.off_hist_part);
   auto* flag = reinterpret_cast<uint64_t*>(ws + P.off_flag);   // [0] keys, [1] binned splats
   auto* n_binned = reinterpret_cast<uint32_t*>(flag + 2);
+  auto* order_grp = reinterpret_cast<uint32_t*>(ws + P.off_order);
   const auto* xy = reinterpret_cast<const float2*>(p.xy);
   const auto* rd = reinterpret_cast<const float4*>(p.rgb_depth);
   const int64_t ne = P.n_entries;
@@ -565,7 +591,7 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
     return hip_fail(e, "fill ranges");
   if (bins.order && vt.n_tiles > 0)
     hipLaunchKernelGGL(identity_order_kernel, dim3((unsigned)((vt.n_tiles + 255) / 256)),
-                       dim3(256), 0, s, bins.order, vt.n_tiles);
+                       dim3(256), 0, s, bins.order, vt.n_tiles, order_grp);
   // 1. tiles per splat (from the projection when it stored them); binned
   // splats compacted in entry order with their depth
   if (ne > 0) {
@@ -633,9 +659,13 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   }
   hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((n_sort + 255) / 256)), dim3(256), 0, s,
                      bins.keys, bins.n_keys, P.capacity, bins.ranges);
-  if (bins.order && vt.n_tiles > 0)
-    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, bins.ranges, vt.n_tiles,
-                       bins.order);
+  if (bins.order && vt.n_tiles > 0) {
+    const dim3 tgrid((unsigned)((vt.n_tiles + 255) / 256));
+    hipLaunchKernelGGL(order_count_kernel, tgrid, dim3(256), 0, s, bins.ranges, vt.n_tiles,
+                       order_grp);
+    hipLaunchKernelGGL(order_scatter_kernel, tgrid, dim3(256), 0, s, bins.ranges, vt.n_tiles,
+                       order_grp, bins.order);
+  }
   kernel_event_stop(GS_KERNEL_BIN_SORT, s);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "bin sort launch");
   return GS_OK;

@@ -214,7 +214,7 @@ struct BinSortPlan {
   int64_t sort_blocks;   // blocks of the radix sort at capacity
   // workspace layout (byte offsets)
   size_t off_counts, off_offsets, off_dkey, off_dval, off_scan_part, off_keys_alt, off_vals_alt,
-      off_hist, off_hist_part, off_flag, total;
+      off_hist, off_hist_part, off_flag, off_order, total;
 };
 BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity);
 int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs_bins& bins,

@@ -96,6 +96,7 @@ def test_tile_order_longest_first(gs):
     cams = BIN_CASES["ragged_multi_view"]
     sp = scenes.random_splats(4000, cams, seed=33)
     views, proj, bins, nk = _gpu_bins(gs, sp, cams)
+    assert views.n_tiles > 4 * 256   # several workgroups of the order kernels
     order = np_(bins.order).astype(np.int64)
     assert sorted(order.tolist()) == list(range(views.n_tiles))
     rg = np_(bins.ranges).astype(np.int64)
