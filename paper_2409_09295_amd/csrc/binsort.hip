@@ -450,11 +450,13 @@ __global__ __launch_bounds__(256) void ranges_kernel(const uint64_t* __restrict_
     ranges[2 * (int64_t)tile + 1] = (uint32_t)(i + 1);
 }
 
-// Tile order, longest lists first: 32 groups by list length (0, then half
-// octaves), filled longest group first.  Positions within a group are
-// unspecified (every tile appears exactly once).  grp[0..31] counts each
-// group, grp[32..63] hands out positions; both start at zero.
+// Tile order, longest lists first: a stable sort of the tiles by 32 list
+// length groups (0, then half octaves), longest group first and ascending
+// tile index within a group, so that tiles running side by side stay close
+// in the image.  Three passes over blocks of kOrderBlock tiles: group counts
+// per block, per-(block, group) output offsets, stable scatter.
 constexpr int kOrderGroups = 32;
+constexpr int kOrderBlock = 256;
 
 __device__ __forceinline__ int length_group(uint32_t len) {   // ascending in len
   if (len == 0) return 0;
@@ -467,50 +469,97 @@ __device__ __forceinline__ int tile_group(const uint32_t* ranges, int t) {
   return length_group(ranges[2 * (int64_t)t + 1] - ranges[2 * (int64_t)t]);
 }
 
-__global__ __launch_bounds__(256) void order_count_kernel(const uint32_t* __restrict__ ranges,
-                                                          int n_tiles, uint32_t* __restrict__ grp) {
-  __shared__ uint32_t s_cnt[kOrderGroups];
-  if (threadIdx.x < kOrderGroups) s_cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n_tiles) atomicAdd(&s_cnt[tile_group(ranges, t)], 1u);
-  __syncthreads();
-  if (threadIdx.x < kOrderGroups && s_cnt[threadIdx.x] != 0)
-    atomicAdd(&grp[threadIdx.x], s_cnt[threadIdx.x]);
-}
-
-__global__ __launch_bounds__(256) void order_scatter_kernel(const uint32_t* __restrict__ ranges,
-                                                            int n_tiles, uint32_t* __restrict__ grp,
-                                                            uint32_t* __restrict__ order) {
-  __shared__ uint32_t s_cnt[kOrderGroups];
-  __shared__ uint32_t s_base[kOrderGroups];
-  if (threadIdx.x < kOrderGroups) s_cnt[threadIdx.x] = 0;
-  __syncthreads();
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int g = 0;
-  uint32_t rank = 0;
-  if (t < n_tiles) {
-    g = tile_group(ranges, t);
-    rank = atomicAdd(&s_cnt[g], 1u);
+// Group of this thread's tile (-1 past the end), its rank among the block's
+// earlier tiles of the same group, and the block's count of every group.
+__device__ __forceinline__ int block_group_ranks(const uint32_t* ranges, int n_tiles,
+                                                 uint32_t* s_wcnt /* [4][32] */,
+                                                 uint32_t* s_cnt /* [32] */, uint32_t& rank) {
+  const int t = blockIdx.x * kOrderBlock + (int)threadIdx.x;
+  const int g = t < n_tiles ? tile_group(ranges, t) : -1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint64_t peers = 0;
+  for (int h = 0; h < kOrderGroups; ++h) {
+    const uint64_t m = __ballot(g == h);
+    if (g == h) peers = m;
+    if (lane == 0) s_wcnt[wave * kOrderGroups + h] = (uint32_t)__popcll(m);
   }
   __syncthreads();
   if (threadIdx.x < kOrderGroups) {
-    const int b = (int)threadIdx.x;
-    uint32_t start = 0;   // tiles in the longer groups
-    for (int h = kOrderGroups - 1; h > b; --h) start += grp[h];
-    s_base[b] = s_cnt[b] ? start + atomicAdd(&grp[kOrderGroups + b], s_cnt[b]) : 0u;
+    uint32_t c = 0;
+    for (int w = 0; w < kOrderBlock / 64; ++w) c += s_wcnt[w * kOrderGroups + threadIdx.x];
+    s_cnt[threadIdx.x] = c;
+  }
+  rank = 0;
+  if (g >= 0) {
+    for (int w = 0; w < wave; ++w) rank += s_wcnt[w * kOrderGroups + g];
+    rank += (uint32_t)__popcll(peers & ((uint64_t(1) << lane) - 1));
   }
   __syncthreads();
-  if (t < n_tiles) order[s_base[g] + rank] = (uint32_t)t;
+  return g;
 }
 
-// Identity order (so that bins.order is a permutation on every return path);
-// also clears the group counters of the tile order.
-__global__ __launch_bounds__(256) void identity_order_kernel(uint32_t* __restrict__ order, int n,
-                                                             uint32_t* __restrict__ grp) {
+__global__ __launch_bounds__(kOrderBlock) void order_count_kernel(
+    const uint32_t* __restrict__ ranges, int n_tiles, uint32_t* __restrict__ blk) {
+  __shared__ uint32_t s_wcnt[4 * kOrderGroups];
+  __shared__ uint32_t s_cnt[kOrderGroups];
+  uint32_t rank;
+  block_group_ranks(ranges, n_tiles, s_wcnt, s_cnt, rank);
+  if (threadIdx.x < kOrderGroups) blk[blockIdx.x * kOrderGroups + threadIdx.x] = s_cnt[threadIdx.x];
+}
+
+// One workgroup: blk[b][g] (counts) -> output offset of block b's group-g
+// tiles.  Thread (g, j) owns the blocks of chunk j for group g.
+__global__ __launch_bounds__(1024) void order_offsets_kernel(uint32_t* __restrict__ blk, int nblk) {
+  __shared__ uint32_t s_part[kOrderGroups][33];
+  __shared__ uint32_t s_start[kOrderGroups];
+  const int g = threadIdx.x & 31, j = threadIdx.x >> 5;
+  const int chunk = (nblk + 31) / 32;
+  const int b0 = min(nblk, j * chunk), b1 = min(nblk, b0 + chunk);
+  uint32_t sum = 0;
+  for (int b = b0; b < b1; ++b) sum += blk[b * kOrderGroups + g];
+  s_part[g][j] = sum;
+  __syncthreads();
+  if (threadIdx.x < kOrderGroups) {   // chunk prefix per group, then group totals
+    uint32_t run = 0;
+    for (int k = 0; k < 32; ++k) {
+      const uint32_t v = s_part[threadIdx.x][k];
+      s_part[threadIdx.x][k] = run;
+      run += v;
+    }
+    s_part[threadIdx.x][32] = run;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {   // longest group first
+    uint32_t run = 0;
+    for (int h = kOrderGroups - 1; h >= 0; --h) {
+      s_start[h] = run;
+      run += s_part[h][32];
+    }
+  }
+  __syncthreads();
+  uint32_t off = s_start[g] + s_part[g][j];
+  for (int b = b0; b < b1; ++b) {
+    const uint32_t c = blk[b * kOrderGroups + g];
+    blk[b * kOrderGroups + g] = off;
+    off += c;
+  }
+}
+
+__global__ __launch_bounds__(kOrderBlock) void order_scatter_kernel(
+    const uint32_t* __restrict__ ranges, int n_tiles, const uint32_t* __restrict__ blk,
+    uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_wcnt[4 * kOrderGroups];
+  __shared__ uint32_t s_cnt[kOrderGroups];
+  uint32_t rank;
+  const int g = block_group_ranks(ranges, n_tiles, s_wcnt, s_cnt, rank);
+  if (g >= 0)
+    order[blk[blockIdx.x * kOrderGroups + g] + rank] = (uint32_t)(blockIdx.x * kOrderBlock + threadIdx.x);
+}
+
+// Identity order, so that bins.order is a permutation on every return path.
+__global__ __launch_bounds__(256) void identity_order_kernel(uint32_t* __restrict__ order, int n) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) order[t] = (uint32_t)t;
-  if (blockIdx.x == 0 && threadIdx.x < 2 * kOrderGroups) grp[threadIdx.x] = 0;
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -548,7 +597,8 @@ BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity)
   P.off_hist = off;      off += align_up(sizeof(uint32_t) * hist_n);
   P.off_hist_part = off; off += align_up(sizeof(uint32_t) * 256);   // digit totals
   P.off_flag = off;      off += align_up(sizeof(uint64_t) * 8);
-  P.off_order = off;     off += align_up(sizeof(uint32_t) * 2 * kOrderGroups);   // tile order
+  P.off_order = off;     // tile order: per-(block, group) counts, then offsets
+  off += align_up(sizeof(uint32_t) * kOrderGroups * ((vt.n_tiles + kOrderBlock - 1) / kOrderBlock));
   P.total = off;
   return P;
 }
@@ -579,7 +629,7 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   auto* digit_tot = reinterpret_cast<uint32_t*>(ws + P.off_hist_part);
   auto* flag = reinterpret_cast<uint64_t*>(ws + P.off_flag);   // [0] keys, [1] binned splats
   auto* n_binned = reinterpret_cast<uint32_t*>(flag + 2);
-  auto* order_grp = reinterpret_cast<uint32_t*>(ws + P.off_order);
+  auto* order_blk = reinterpret_cast<uint32_t*>(ws + P.off_order);
   const auto* xy = reinterpret_cast<const float2*>(p.xy);
   const auto* rd = reinterpret_cast<const float4*>(p.rgb_depth);
   const int64_t ne = P.n_entries;
@@ -591,7 +641,7 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
     return hip_fail(e, "fill ranges");
   if (bins.order && vt.n_tiles > 0)
     hipLaunchKernelGGL(identity_order_kernel, dim3((unsigned)((vt.n_tiles + 255) / 256)),
-                       dim3(256), 0, s, bins.order, vt.n_tiles, order_grp);
+                       dim3(256), 0, s, bins.order, vt.n_tiles);
   // 1. tiles per splat (from the projection when it stored them); binned
   // splats compacted in entry order with their depth
   if (ne > 0) {
@@ -660,11 +710,12 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((n_sort + 255) / 256)), dim3(256), 0, s,
                      bins.keys, bins.n_keys, P.capacity, bins.ranges);
   if (bins.order && vt.n_tiles > 0) {
-    const dim3 tgrid((unsigned)((vt.n_tiles + 255) / 256));
-    hipLaunchKernelGGL(order_count_kernel, tgrid, dim3(256), 0, s, bins.ranges, vt.n_tiles,
-                       order_grp);
-    hipLaunchKernelGGL(order_scatter_kernel, tgrid, dim3(256), 0, s, bins.ranges, vt.n_tiles,
-                       order_grp, bins.order);
+    const int nblk = (vt.n_tiles + kOrderBlock - 1) / kOrderBlock;
+    hipLaunchKernelGGL(order_count_kernel, dim3((unsigned)nblk), dim3(kOrderBlock), 0, s,
+                       bins.ranges, vt.n_tiles, order_blk);
+    hipLaunchKernelGGL(order_offsets_kernel, dim3(1), dim3(1024), 0, s, order_blk, nblk);
+    hipLaunchKernelGGL(order_scatter_kernel, dim3((unsigned)nblk), dim3(kOrderBlock), 0, s,
+                       bins.ranges, vt.n_tiles, order_blk, bins.order);
   }
   kernel_event_stop(GS_KERNEL_BIN_SORT, s);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "bin sort launch");

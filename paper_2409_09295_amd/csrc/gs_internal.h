@@ -171,17 +171,19 @@ __device__ __forceinline__ ColumnTerms column_terms(const float4& geo, float px)
 
 // Without a branch: the return value says whether the splat is kept
 // (power <= 0 and alpha >= 1/255); alpha = min(0.99, o G), raw = o G,
-// G = 2^power.  With CLAMP the exponent is clamped at 0 first, which changes
-// nothing where the splat is kept and keeps every output finite for every
-// pixel (for a caller that multiplies G into zeros); without it a pixel
-// that skips the splat may see G > 1.
+// G = 2^power.  With CLAMP, G is clamped to [0, 1] (equal to 2^min(power, 0)),
+// which changes nothing where the splat is kept and keeps every output finite
+// for every pixel (for a caller that multiplies G into zeros); without it a
+// pixel that skips the splat may see G > 1.
 template <bool CLAMP>
 __device__ __forceinline__ bool eval_alpha_at(const ColumnTerms& ct, const float4& geo,
                                               const float4& app, float py, float& alpha,
                                               float& raw, float& G, float& dy) {
   dy = py - geo.y;
   const float p2 = __builtin_fmaf(dy, __builtin_fmaf(app.x, dy, ct.bdx), ct.adx2);
-  G = __builtin_amdgcn_exp2f(CLAMP ? fminf(p2, 0.0f) : p2);
+  // the clamp is an output modifier of the exp (no extra instruction)
+  G = CLAMP ? __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(p2), 0.0f, 1.0f)
+            : __builtin_amdgcn_exp2f(p2);
   raw = app.y * G;
   alpha = fminf(kAlphaMax, raw);
   return p2 <= 0.0f && alpha >= kAlphaMin;
