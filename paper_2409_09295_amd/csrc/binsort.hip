@@ -81,12 +81,24 @@ __device__ __forceinline__ uint32_t scan_in(const uint32_t* in, int64_t idx, int
   return PRED ? (x != 0u ? 1u : 0u) : x;
 }
 
+// n_dev (optional): a device-side count that bounds n further; blocks past it
+// write a zero partial (reduce) or nothing (down-sweep).
+__device__ __forceinline__ int64_t scan_bound(int64_t n, const uint32_t* n_dev) {
+  return n_dev ? min(n, (int64_t)*n_dev) : n;
+}
+
 template <bool PRED>
 __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in,
                                                                    int64_t n,
+                                                                   const uint32_t* __restrict__ n_dev,
                                                                    uint64_t* __restrict__ partial) {
   __shared__ uint64_t s_wave[4];
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
+  n = scan_bound(n, n_dev);
+  if (base >= n) {   // uniform over the block
+    if (threadIdx.x == 0) partial[blockIdx.x] = 0;
+    return;
+  }
   uint64_t acc = 0;
 #pragma unroll
   for (int r = 0; r < kScanItems; ++r)
@@ -134,10 +146,13 @@ __global__ __launch_bounds__(kPartThreads) void scan_partials_kernel(uint64_t* _
 // read before its position is written.
 template <bool PRED>
 __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t* in, int64_t n,
+                                                                 const uint32_t* __restrict__ n_dev,
                                                                  const uint64_t* __restrict__ partial,
                                                                  uint32_t* out) {
   __shared__ uint32_t s_wave[4];
   constexpr int kRows = kScanChunk / kScanThreads;   // 16 rows of 64 per wave
+  n = scan_bound(n, n_dev);
+  if ((int64_t)blockIdx.x * kScanChunk >= n) return;   // uniform over the block
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)w * (64 * kRows) + lane;
   uint32_t x[kRows];
@@ -160,19 +175,20 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t*
     if (base + 64 * r < n) out[base + 64 * r] = carry + x[r];
 }
 
-// Exclusive scan of in[0, n) (of in[i] != 0 with PRED) into out.
+// Exclusive scan of in[0, m) (of in[i] != 0 with PRED) into out, where
+// m = min(n, *n_dev) when n_dev is given (out[m, n) is left untouched), else n.
 template <bool PRED = false>
-void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint64_t* partial, uint64_t* total,
-              uint32_t* n_keys, hipStream_t s) {
+void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* n_dev,
+              uint64_t* partial, uint64_t* total, uint32_t* n_keys, hipStream_t s) {
   const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
   if (nb > 0)
     hipLaunchKernelGGL(scan_reduce_kernel<PRED>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in,
-                       n, partial);
+                       n, n_dev, partial);
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kPartThreads), 0, s, partial, nb, total,
                      n_keys);
   if (nb > 0)
     hipLaunchKernelGGL(scan_down_kernel<PRED>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n,
-                       partial, out);
+                       n_dev, partial, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -216,15 +232,15 @@ __global__ __launch_bounds__(256) void compact_kernel(const uint32_t* __restrict
   dval[j] = (uint32_t)e;
 }
 
-// Tile counts in depth order (zero past the binned splats).
+// Tile counts in depth order, for the first *n_order positions.
 __global__ __launch_bounds__(256) void gather_counts_kernel(const uint32_t* __restrict__ order,
                                                             const uint32_t* __restrict__ n_order,
                                                             const uint32_t* __restrict__ counts,
                                                             int64_t n_entries,
                                                             uint32_t* __restrict__ out) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_entries) return;
-  out[j] = j < (int64_t)*n_order ? counts[order[j]] : 0u;
+  if (j >= min(n_entries, (int64_t)*n_order)) return;
+  out[j] = counts[order[j]];
 }
 
 // Items j < *n_items are splats order[j] (depth order); item j's keys start at
@@ -647,11 +663,11 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   if (ne > 0) {
     const uint32_t* tiles = p.tiles;
     if (tiles) {
-      scan_u32<true>(tiles, offsets, ne, part, flag + 1, n_binned, s);
+      scan_u32<true>(tiles, offsets, ne, nullptr, part, flag + 1, n_binned, s);
     } else {
       hipLaunchKernelGGL(count_kernel, dim3(eblocks), dim3(256), 0, s, xy, p.radius, ne, n, vt,
                          counts, offsets);
-      scan_u32(offsets, offsets, ne, part, flag + 1, n_binned, s);
+      scan_u32(offsets, offsets, ne, nullptr, part, flag + 1, n_binned, s);
       tiles = counts;
     }
     hipLaunchKernelGGL(compact_kernel, dim3(eblocks), dim3(256), 0, s, tiles, offsets, rd, ne,
@@ -667,7 +683,8 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
     // 3. key offsets in depth order; their total is the key count
     hipLaunchKernelGGL(gather_counts_kernel, dim3(eblocks), dim3(256), 0, s, va, n_binned, tiles,
                        ne, offsets);
-    scan_u32(offsets, offsets, ne, part, flag, bins.n_keys, s);
+    // (positions past the binned splats are neither written nor read)
+    scan_u32(offsets, offsets, ne, n_binned, part, flag, bins.n_keys, s);
   } else {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, s,
                        reinterpret_cast<uint32_t*>(flag), 0u, (int64_t)16);
