@@ -144,11 +144,21 @@ __global__ __launch_bounds__(kPartThreads) void scan_partials_kernel(uint64_t* _
 // 64 (coalesced), carrying the running total from row to row, so only the
 // four wave totals need a block-level step.  out may alias in: every value is
 // read before its position is written.
-template <bool PRED>
+// Compacting form (Compact::on, with PRED): instead of the positions, the
+// entries with in[i] != 0 are written in entry order as dkey[pos] = depth
+// bits of rd[i], dval[pos] = i.
+struct Compact {
+  const float4* rd = nullptr;
+  uint32_t* dkey = nullptr;
+  uint32_t* dval = nullptr;
+};
+
+template <bool PRED, bool COMPACT = false>
 __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t* in, int64_t n,
                                                                  const uint32_t* __restrict__ n_dev,
                                                                  const uint64_t* __restrict__ partial,
-                                                                 uint32_t* out) {
+                                                                 uint32_t* out, Compact cp) {
+  static_assert(!COMPACT || PRED, "compaction scans the binned flags");
   __shared__ uint32_t s_wave[4];
   constexpr int kRows = kScanChunk / kScanThreads;   // 16 rows of 64 per wave
   n = scan_bound(n, n_dev);
@@ -156,8 +166,12 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t*
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)w * (64 * kRows) + lane;
   uint32_t x[kRows];
+  uint32_t flags = 0;   // COMPACT: bit r set when row r's value is 1
 #pragma unroll
-  for (int r = 0; r < kRows; ++r) x[r] = scan_in<PRED>(in, base + 64 * r, n);
+  for (int r = 0; r < kRows; ++r) {
+    x[r] = scan_in<PRED>(in, base + 64 * r, n);
+    if (COMPACT) flags |= x[r] << r;
+  }
   uint32_t run = 0;
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
@@ -171,15 +185,27 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t*
   uint32_t carry = (uint32_t)partial[blockIdx.x];
   for (uint32_t k = 0; k < w; ++k) carry += s_wave[k];
 #pragma unroll
-  for (int r = 0; r < kRows; ++r)
-    if (base + 64 * r < n) out[base + 64 * r] = carry + x[r];
+  for (int r = 0; r < kRows; ++r) {
+    const int64_t idx = base + 64 * r;
+    if (COMPACT) {
+      if ((flags >> r) & 1u) {
+        const uint32_t j = carry + x[r];
+        cp.dkey[j] = __float_as_uint(cp.rd[idx].w);
+        cp.dval[j] = (uint32_t)idx;
+      }
+    } else if (idx < n) {
+      out[idx] = carry + x[r];
+    }
+  }
 }
 
 // Exclusive scan of in[0, m) (of in[i] != 0 with PRED) into out, where
-// m = min(n, *n_dev) when n_dev is given (out[m, n) is left untouched), else n.
-template <bool PRED = false>
+// m = min(n, *n_dev) when n_dev is given (out[m, n) is left untouched), else n;
+// with COMPACT the scan compacts instead (see scan_down_kernel) and out is unused.
+template <bool PRED = false, bool COMPACT = false>
 void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* n_dev,
-              uint64_t* partial, uint64_t* total, uint32_t* n_keys, hipStream_t s) {
+              uint64_t* partial, uint64_t* total, uint32_t* n_keys, hipStream_t s,
+              Compact cp = Compact{}) {
   const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
   if (nb > 0)
     hipLaunchKernelGGL(scan_reduce_kernel<PRED>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in,
@@ -187,8 +213,8 @@ void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* n_de
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kPartThreads), 0, s, partial, nb, total,
                      n_keys);
   if (nb > 0)
-    hipLaunchKernelGGL(scan_down_kernel<PRED>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n,
-                       n_dev, partial, out);
+    hipLaunchKernelGGL((scan_down_kernel<PRED, COMPACT>), dim3((unsigned)nb), dim3(kScanThreads), 0,
+                       s, in, n, n_dev, partial, out, cp);
 }
 
 // ---------------------------------------------------------------------------
@@ -204,8 +230,7 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t* __restrict__ p,
 __global__ __launch_bounds__(256) void count_kernel(const float2* __restrict__ xy,
                                                     const int32_t* __restrict__ radius,
                                                     int64_t n_entries, int64_t n, ViewTable vt,
-                                                    uint32_t* __restrict__ counts,
-                                                    uint32_t* __restrict__ binned) {
+                                                    uint32_t* __restrict__ counts) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_entries) return;
   const int v = (int)(e / n);
@@ -215,21 +240,6 @@ __global__ __launch_bounds__(256) void count_kernel(const float2* __restrict__ x
   const bool ok = tile_rect(c.x, c.y, radius[e], vi.width, vi.height, rc);
   const uint32_t cnt = ok ? (uint32_t)((rc.x1 - rc.x0) * (rc.y1 - rc.y0)) : 0u;
   counts[e] = cnt;
-  binned[e] = cnt > 0 ? 1u : 0u;
-}
-
-// Splats with at least one tile, in entry order: depth bits and entry index.
-__global__ __launch_bounds__(256) void compact_kernel(const uint32_t* __restrict__ counts,
-                                                      const uint32_t* __restrict__ pos,
-                                                      const float4* __restrict__ rd,
-                                                      int64_t n_entries,
-                                                      uint32_t* __restrict__ dkey,
-                                                      uint32_t* __restrict__ dval) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_entries || counts[e] == 0) return;
-  const uint32_t j = pos[e];
-  dkey[j] = __float_as_uint(rd[e].w);
-  dval[j] = (uint32_t)e;
 }
 
 // Tile counts in depth order, for the first *n_order positions.
@@ -604,7 +614,7 @@ BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity)
   const size_t ne = sizeof(uint32_t) * (size_t)P.n_entries;
   size_t off = 0;
   P.off_counts = off;    off += align_up(ne);
-  P.off_offsets = off;   off += align_up(ne);   // binned flags -> positions; sorted offsets
+  P.off_offsets = off;   off += align_up(ne);   // key offsets in depth order
   P.off_dkey = off;      off += align_up(2 * ne);
   P.off_dval = off;      off += align_up(2 * ne);
   P.off_scan_part = off; off += align_up(sizeof(uint64_t) * (P.scan_blocks + 1));
@@ -661,17 +671,18 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   // 1. tiles per splat (from the projection when it stored them); binned
   // splats compacted in entry order with their depth
   if (ne > 0) {
+    // (the scan's down-sweep writes the compacted depth keys and entries)
     const uint32_t* tiles = p.tiles;
-    if (tiles) {
-      scan_u32<true>(tiles, offsets, ne, nullptr, part, flag + 1, n_binned, s);
-    } else {
+    if (!tiles) {
       hipLaunchKernelGGL(count_kernel, dim3(eblocks), dim3(256), 0, s, xy, p.radius, ne, n, vt,
-                         counts, offsets);
-      scan_u32(offsets, offsets, ne, nullptr, part, flag + 1, n_binned, s);
+                         counts);
       tiles = counts;
     }
-    hipLaunchKernelGGL(compact_kernel, dim3(eblocks), dim3(256), 0, s, tiles, offsets, rd, ne,
-                       dkey, dval);
+    Compact cp;
+    cp.rd = rd;
+    cp.dkey = dkey;
+    cp.dval = dval;
+    scan_u32<true, true>(tiles, nullptr, ne, nullptr, part, flag + 1, n_binned, s, cp);
     // 2. stable sort of the binned splats by depth (ties keep entry order)
     uint32_t *ka = dkey, *va = dval, *kb = dkey + ne, *vb = dval + ne;
     for (int pass = 0; pass < 4; ++pass) {

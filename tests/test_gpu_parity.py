@@ -29,9 +29,19 @@ BIN_CASES = {
 }
 
 
-def _gpu_bins(gs, sp, cams, capacity=None, sync=True):
+def _oracle_tile_counts(sp, cams):
+    """Per-(view, splat) tile counts from the oracle's rectangles, as the
+    projection stores them."""
+    return np.stack([O.tile_rects(sp.xy[v, :, 0].astype(np.float64), sp.xy[v, :, 1].astype(np.float64),
+                                  sp.radius[v], c.width, c.height, 16)[4]
+                     for v, c in enumerate(cams)]).astype(np.int32)
+
+
+def _gpu_bins(gs, sp, cams, capacity=None, sync=True, stored_counts=False):
     views = gs.Views(cams)
     proj = gs.Projected.from_splats(sp)
+    if stored_counts:   # the path that takes the projection's tile counts
+        proj.tiles = torch.from_numpy(_oracle_tile_counts(sp, cams)).to(DEV)
     V, N = sp.radius.shape
     cap = capacity if capacity is not None else 64 * N * V + 1024
     bins = gs.Bins.empty(cap, views.n_tiles)
@@ -43,15 +53,16 @@ def _gpu_bins(gs, sp, cams, capacity=None, sync=True):
 
 @pytest.mark.parametrize("case", list(BIN_CASES))
 @pytest.mark.parametrize("sync", [True, False])
-def test_bin_sort_bit_exact(gs, case, sync):
+@pytest.mark.parametrize("stored", [False, True], ids=["counted", "stored_counts"])
+def test_bin_sort_bit_exact(gs, case, sync, stored):
     cams = BIN_CASES[case]
     n = 2500 if case != "ragged_multi_view" else 6000
     sp = scenes.random_splats(n, cams, seed=21, depth_ties=0.2, cull_frac=0.05)
-    _log(f"bin_sort case={case} sync={sync} n={n}")
+    _log(f"bin_sort case={case} sync={sync} stored_counts={stored} n={n}")
     keys, vals, ranges, _, _ = O.bin_splats([sp.xy[v] for v in range(len(cams))],
                                             [sp.rgb_depth[v, :, 3] for v in range(len(cams))],
                                             [sp.radius[v] for v in range(len(cams))], cams, 16)
-    views, proj, bins, nk = _gpu_bins(gs, sp, cams, sync=sync)
+    views, proj, bins, nk = _gpu_bins(gs, sp, cams, sync=sync, stored_counts=stored)
     got_n = int(u32(bins.n_keys)[0])
     assert got_n == len(keys)
     if sync:
@@ -60,7 +71,7 @@ def test_bin_sort_bit_exact(gs, case, sync):
     np.testing.assert_array_equal(u32(bins.values)[:got_n], vals)
     np.testing.assert_array_equal(u32(bins.ranges), ranges)
     # repeat: integer outputs are deterministic
-    views2, proj2, bins2, _ = _gpu_bins(gs, sp, cams, sync=sync)
+    views2, proj2, bins2, _ = _gpu_bins(gs, sp, cams, sync=sync, stored_counts=stored)
     np.testing.assert_array_equal(u64(bins2.keys)[:got_n], u64(bins.keys)[:got_n])
     np.testing.assert_array_equal(u32(bins2.values)[:got_n], u32(bins.values)[:got_n])
 
