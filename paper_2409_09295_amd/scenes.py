@@ -295,13 +295,31 @@ def _room_rects(rng, n_boxes=20):
     return rects, boxes
 
 
+def _morton2(s: np.ndarray) -> np.ndarray:
+    """Z-order code of points in [0, 1)^2 (16 bits per axis)."""
+    q = np.clip((s * 65536.0).astype(np.int64), 0, 65535)
+
+    def spread(x):
+        x = (x | (x << 8)) & 0x00FF00FF
+        x = (x | (x << 4)) & 0x0F0F0F0F
+        x = (x | (x << 2)) & 0x33333333
+        return (x | (x << 1)) & 0x55555555
+
+    return spread(q[:, 0]) | (spread(q[:, 1]) << 1)
+
+
 def procedural_room(n: int, seed: int, sh_degree: int = 3, n_boxes: int = 20):
     """A 5 x 5 x 3 m room (6 planes) plus ``n_boxes`` boxes (edges U[0.2, 1] m,
     resting on the floor, random yaw).  Gaussians are placed area-uniformly on
     the surfaces with N(0, 0.01 m) jitter along the normal, oriented with the
     third axis on the normal, scales (a, a, 0.1 a) with a = sqrt(area / n),
     opacity logits N(2, 0.5), degree-0 colour from seeded value noise and
-    higher SH bands N(0, 0.05).  Returns (GaussianMap, boxes)."""
+    higher SH bands N(0, 0.05).  Index order is surface by surface and, on a
+    surface, a Z-order curve over its two coordinates: a map built from
+    keyframes inserts the Gaussians of one image region together, so nearby
+    indices are nearby in space (drawing them in random order instead would
+    make every run of indices span the whole surface).
+    Returns (GaussianMap, boxes)."""
     rng = np.random.default_rng(seed)
     rects, boxes = _room_rects(rng, n_boxes)
     areas = np.array([r.area for r in rects])
@@ -314,6 +332,7 @@ def procedural_room(n: int, seed: int, sh_degree: int = 3, n_boxes: int = 20):
         if c == 0:
             continue
         s = rng.random((c, 2))
+        s = s[np.argsort(_morton2(s), kind="stable")]   # insertion order: see above
         pts = r.origin + s[:, :1] * r.u + s[:, 1:] * r.v
         nrm = r.normal
         pts = pts + rng.normal(0.0, 0.01, size=(c, 1)) * nrm
