@@ -3,8 +3,8 @@
 // One lane per (Gaussian, group of kViewsPerLane views).  The Gaussian's
 // parameters are read with coalesced component-major loads (lane i reads
 // element i of each component array) and reused for every view of the group,
-// so a batch of V views costs ceil(V / kViewsPerLane) reads of the map (the
-// repeats hit in L2/MALL) plus, per view, 48 bytes written for a visible splat
+// so a batch of V views costs ceil(V / kViewsPerLane) reads of the map
+// plus, per view, 48 bytes written for a visible splat
 // (44 without tile counts) and 8 for a culled one (4); splitting
 // the views over grid.y keeps enough wavefronts in flight to hide the long
 // per-view dependency chain.  Camera records are wave-uniform.
@@ -12,7 +12,10 @@
 
 namespace gsmi {
 
-constexpr int kViewsPerLane = 32;
+// 16 rather than 32: the grid then holds twice as many, half as long
+// wavefronts, so the last ones do not run alone in a second round
+// (3,125 wavefronts of 32 views against 3,072 resident at 200k Gaussians).
+constexpr int kViewsPerLane = 16;
 
 template <int DEG>
 __global__ __launch_bounds__(256) void preprocess_kernel(
