@@ -138,11 +138,13 @@ typedef struct gs_projected {
  *   n_keys [1] uint32 number of keys emitted (may exceed capacity, in which
  *          case the call reported or flagged overflow and keys are partial)
  *   order  [n_tiles] uint32 (optional, NULL = not computed): every global
- *          tile id once, longest lists first (grouped by list length in
- *          half-octave steps; the order within a group is not specified).
- *          gs_bin_sort writes it when non-NULL; the compositing calls then
- *          start the most expensive tiles first, which shortens the tail of
- *          the launch, and their results do not depend on it. */
+ *          tile id once, longest lists first: tiles are grouped by list
+ *          length (0, then half-octave steps), groups in descending length,
+ *          ascending tile id within a group.  gs_bin_sort writes it when
+ *          non-NULL (the identity when it returns before the ranges exist);
+ *          the compositing calls then start the most expensive tiles first,
+ *          which shortens the tail of the launch, and their results do not
+ *          depend on it. */
 typedef struct gs_bins {
   uint64_t* keys;
   uint32_t* values;

@@ -582,10 +582,15 @@ __global__ __launch_bounds__(kOrderBlock) void order_scatter_kernel(
     order[blk[blockIdx.x * kOrderGroups + g] + rank] = (uint32_t)(blockIdx.x * kOrderBlock + threadIdx.x);
 }
 
-// Identity order, so that bins.order is a permutation on every return path.
-__global__ __launch_bounds__(256) void identity_order_kernel(uint32_t* __restrict__ order, int n) {
+// Start of every call: all ranges empty and, when an order is requested, the
+// identity order (so that bins.order is a permutation on every return path).
+__global__ __launch_bounds__(256) void clear_bins_kernel(uint32_t* __restrict__ ranges, int n_tiles,
+                                                         uint32_t* __restrict__ order) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) order[t] = (uint32_t)t;
+  if (t >= n_tiles) return;
+  ranges[2 * (int64_t)t] = 0u;
+  ranges[2 * (int64_t)t + 1] = 0u;
+  if (order) order[t] = (uint32_t)t;
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -663,11 +668,9 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   hipError_t e;
 
   kernel_event_start(GS_KERNEL_BIN_SORT, s);
-  if ((e = launch_fill_u32(bins.ranges, 0u, 2 * (int64_t)vt.n_tiles, s)) != hipSuccess)
-    return hip_fail(e, "fill ranges");
-  if (bins.order && vt.n_tiles > 0)
-    hipLaunchKernelGGL(identity_order_kernel, dim3((unsigned)((vt.n_tiles + 255) / 256)),
-                       dim3(256), 0, s, bins.order, vt.n_tiles);
+  if (vt.n_tiles > 0)
+    hipLaunchKernelGGL(clear_bins_kernel, dim3((unsigned)((vt.n_tiles + 255) / 256)), dim3(256), 0,
+                       s, bins.ranges, vt.n_tiles, bins.order);
   // 1. tiles per splat (from the projection when it stored them); binned
   // splats compacted in entry order with their depth
   if (ne > 0) {
