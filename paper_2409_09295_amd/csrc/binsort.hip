@@ -253,8 +253,28 @@ __global__ __launch_bounds__(256) void gather_counts_kernel(const uint32_t* __re
   out[j] = counts[order[j]];
 }
 
+// Inclusive prefix maximum over the 64 lanes of a wavefront (DPP row shifts,
+// then the row broadcasts; lanes without a source see 0, the identity here).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, true);
+}
+
+__device__ __forceinline__ uint32_t wave_prefix_max(uint32_t x) {
+  x = max(x, dpp_u32<0x111, 0xf>(x));   // row_shr:1
+  x = max(x, dpp_u32<0x112, 0xf>(x));   // row_shr:2
+  x = max(x, dpp_u32<0x114, 0xf>(x));   // row_shr:4
+  x = max(x, dpp_u32<0x118, 0xf>(x));   // row_shr:8
+  x = max(x, dpp_u32<0x142, 0xa>(x));   // row_bcast:15 into rows 1 and 3
+  x = max(x, dpp_u32<0x143, 0xc>(x));   // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 // Items j < *n_items are splats order[j] (depth order); item j's keys start at
-// offsets[j].
+// offsets[j].  A wavefront owns the contiguous key range of its 64 items and
+// writes it 64 keys at a time: in each window of 64 positions, every item
+// with keys marks where it starts, and a prefix maximum over the lanes gives
+// each position its item (the item marked last at or before it).
 __global__ __launch_bounds__(256) void emit_kernel(const float2* __restrict__ xy,
                                                    const int32_t* __restrict__ radius,
                                                    const float4* __restrict__ rd,
@@ -266,16 +286,13 @@ __global__ __launch_bounds__(256) void emit_kernel(const float2* __restrict__ xy
                                                    int64_t capacity, uint64_t* __restrict__ keys,
                                                    uint32_t* __restrict__ vals) {
   if (*total > (uint64_t)capacity) return;  // overflow: nothing is emitted
-  __shared__ uint32_t s_start[4][64];
-  __shared__ uint32_t s_t0[4][64];
-  __shared__ uint32_t s_w[4][64];
-  __shared__ uint32_t s_tx[4][64];
-  __shared__ uint32_t s_db[4][64];
-  __shared__ uint32_t s_e[4][64];
+  __shared__ uint4 s_rect[4][64];    // start, first tile, rectangle width, tiles per row
+  __shared__ uint2 s_val[4][64];     // depth bits, entry
+  __shared__ uint32_t s_mark[4][64];
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = j < (int64_t)*n_items;
-  uint32_t start = 0xFFFFFFFFu, cnt = 0, t0 = 0, rw = 1, tx = 1, db = 0, ent = 0;
+  uint32_t start = 0, cnt = 0, t0 = 0, rw = 1, tx = 1, db = 0, ent = 0;
   if (valid) {
     ent = order[j];
     const int v = (int)(ent / n);
@@ -292,32 +309,36 @@ __global__ __launch_bounds__(256) void emit_kernel(const float2* __restrict__ xy
       db = __float_as_uint(rd[ent].w);
     }
   }
-  s_start[w][lane] = start;
-  s_t0[w][lane] = t0;
-  s_w[w][lane] = rw;
-  s_tx[w][lane] = tx;
-  s_db[w][lane] = db;
-  s_e[w][lane] = ent;
-  // wave range [first start, last end)
+  s_rect[w][lane] = make_uint4(start, t0, rw, tx);
+  s_val[w][lane] = make_uint2(db, ent);
+  // wave range [first start, last end); the items are contiguous from lane 0
   const uint64_t vmask = __ballot(valid);
   if (vmask == 0) return;
   const uint32_t wbase = __shfl(start, 0, 64);
   const uint32_t last = 63 - __clzll(vmask);
   const uint32_t wend = __shfl(start + cnt, last, 64);
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (uint32_t pos = wbase + lane; pos < wend; pos += 64) {
-    int lo = 0, hi = (int)last;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_start[w][mid] <= pos) lo = mid; else hi = mid - 1;
+  uint32_t carry = 0;   // 1 + item of the position before the window
+  for (uint32_t w0 = wbase; w0 < wend; w0 += 64) {
+    s_mark[w][lane] = 0;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    if (cnt > 0 && start >= w0 && start - w0 < 64) s_mark[w][start - w0] = lane + 1;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t m = wave_prefix_max(max(s_mark[w][lane], carry));
+    carry = (uint32_t)__builtin_amdgcn_readlane((int)m, 63);
+    const uint32_t pos = w0 + lane;
+    if (pos < wend) {
+      const uint4 r = s_rect[w][m - 1];
+      const uint2 d = s_val[w][m - 1];
+      const uint32_t jj = pos - r.x;
+      const uint32_t row = jj / r.z;
+      const uint32_t tile = r.y + row * r.w + (jj - row * r.z);
+      keys[pos] = ((uint64_t)tile << 32) | (uint64_t)d.x;
+      vals[pos] = d.y;
     }
-    const uint32_t jj = pos - s_start[w][lo];
-    const uint32_t width = s_w[w][lo];
-    const uint32_t row = jj / width;
-    const uint32_t tile = s_t0[w][lo] + row * s_tx[w][lo] + (jj - row * width);
-    keys[pos] = ((uint64_t)tile << 32) | (uint64_t)s_db[w][lo];
-    vals[pos] = s_e[w][lo];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
 }
 
