@@ -33,7 +33,11 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanChunk = kScanThreads * kScanItems;   // 4096
 constexpr int kSortItems = 8;
-constexpr int kSortChunk = 256 * kSortItems;            // 2048
+constexpr int kSortChunk = 256 * kSortItems;            // 2048 keys per workgroup (tile passes)
+// The depth passes sort only the binned splats (about a ninth of the
+// entries): chunks of 1,024 keys put more workgroups in flight (measured
+// against 2,048 and 512).
+constexpr int kDepthItems = 4;
 constexpr int kPartThreads = 1024;
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
@@ -351,21 +355,23 @@ __device__ __forceinline__ uint32_t valid_keys(const uint32_t* n_keys, int64_t c
   return ((int64_t)n <= capacity) ? n : 0u;
 }
 
-template <typename K>
+// ITEMS keys per thread: a workgroup sorts a chunk of 256 * ITEMS keys.
+template <typename K, int ITEMS>
 __global__ __launch_bounds__(256) void radix_upsweep_kernel(const K* __restrict__ keys,
                                                             const uint32_t* __restrict__ n_keys,
                                                             int64_t capacity, int shift,
                                                             uint32_t* __restrict__ hist,
                                                             uint32_t nblocks) {
+  constexpr int kChunk = 256 * ITEMS;
   __shared__ uint32_t h[4][256];
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
   const uint32_t n = valid_keys(n_keys, capacity);
-  if ((int64_t)blockIdx.x * kSortChunk >= (int64_t)n) return;   // past the keys: column unused
+  if ((int64_t)blockIdx.x * kChunk >= (int64_t)n) return;   // past the keys: column unused
   for (int k = threadIdx.x; k < 4 * 256; k += 256) (&h[0][0])[k] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortChunk + w * (kSortChunk / 4);
+  const int64_t base = (int64_t)blockIdx.x * kChunk + w * (kChunk / 4);
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
+  for (int j = 0; j < ITEMS; ++j) {
     const int64_t idx = base + j * 64 + lane;
     if (idx < n) atomicAdd(&h[w][(uint32_t)(keys[idx] >> shift) & 255u], 1u);
   }
@@ -378,14 +384,14 @@ __global__ __launch_bounds__(256) void radix_upsweep_kernel(const K* __restrict_
 // histogram [256][nblocks] (one workgroup per digit); row totals to tot[256].
 // The down-sweep adds the exclusive prefix of the totals.
 __global__ __launch_bounds__(256) void hist_row_scan_kernel(uint32_t* __restrict__ hist,
-                                                            uint32_t nblocks,
+                                                            uint32_t nblocks, uint32_t chunk,
                                                             const uint32_t* __restrict__ n_keys,
                                                             int64_t capacity,
                                                             uint32_t* __restrict__ tot) {
   __shared__ uint32_t s_wave[4];
   uint32_t* row = hist + (int64_t)blockIdx.x * nblocks;
   // columns of blocks past the keys are neither written nor read
-  const uint32_t used = min(nblocks, (valid_keys(n_keys, capacity) + kSortChunk - 1) / kSortChunk);
+  const uint32_t used = min(nblocks, (valid_keys(n_keys, capacity) + chunk - 1) / chunk);
   const uint32_t per = (used + 255) / 256;
   const uint32_t lo = min(used, threadIdx.x * per), hi = min(lo + per, used);
   uint32_t sum = 0;
@@ -400,31 +406,32 @@ __global__ __launch_bounds__(256) void hist_row_scan_kernel(uint32_t* __restrict
   if (threadIdx.x == 0) tot[blockIdx.x] = total;
 }
 
-template <typename K>
+template <typename K, int ITEMS>
 __global__ __launch_bounds__(256) void radix_downsweep_kernel(
     const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ n_keys, int64_t capacity, int shift,
     const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot, uint32_t nblocks) {
+  constexpr int kChunk = 256 * ITEMS;
   __shared__ uint32_t s_wcnt[4][256];
   __shared__ uint32_t s_wpre[4][256];
   __shared__ uint32_t s_dstart[256];
   __shared__ uint32_t s_gbase[256];
   __shared__ uint32_t s_wave[4];
-  __shared__ K s_keys[kSortChunk];
-  __shared__ uint32_t s_vals[kSortChunk];
+  __shared__ K s_keys[kChunk];
+  __shared__ uint32_t s_vals[kChunk];
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
   const uint32_t n = valid_keys(n_keys, capacity);
-  const int64_t bstart = (int64_t)blockIdx.x * kSortChunk;
+  const int64_t bstart = (int64_t)blockIdx.x * kChunk;
   if (bstart >= (int64_t)n) return;   // no keys in this block
   for (int k = threadIdx.x; k < 4 * 256; k += 256) (&s_wcnt[0][0])[k] = 0;
   __syncthreads();
-  const int64_t base = bstart + w * (kSortChunk / 4);
-  K key[kSortItems];
-  uint32_t val[kSortItems], rank[kSortItems], dig[kSortItems];
+  const int64_t base = bstart + w * (kChunk / 4);
+  K key[ITEMS];
+  uint32_t val[ITEMS], rank[ITEMS], dig[ITEMS];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
+  for (int j = 0; j < ITEMS; ++j) {
     const int64_t idx = base + j * 64 + lane;
     const bool valid = idx < n;
     key[j] = valid ? keys_in[idx] : (K)0;
@@ -462,7 +469,7 @@ __global__ __launch_bounds__(256) void radix_downsweep_kernel(
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
+  for (int j = 0; j < ITEMS; ++j) {
     const int64_t idx = base + j * 64 + lane;
     if (idx < n) {
       const uint32_t lp = s_dstart[dig[j]] + s_wpre[w][dig[j]] + rank[j];
@@ -471,9 +478,9 @@ __global__ __launch_bounds__(256) void radix_downsweep_kernel(
     }
   }
   __syncthreads();
-  const int64_t nb_valid = min((int64_t)kSortChunk, (int64_t)n - bstart);
+  const int64_t nb_valid = min((int64_t)kChunk, (int64_t)n - bstart);
 #pragma unroll
-  for (int q = 0; q < kSortItems; ++q) {
+  for (int q = 0; q < ITEMS; ++q) {
     const int pos = q * 256 + threadIdx.x;
     if (pos < nb_valid) {
       const K k = s_keys[pos];
@@ -635,7 +642,8 @@ BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity)
   P.passes = (tile_bits + 7) / 8;   // tile digits of the keys (depth is ordered beforehand)
   P.scan_blocks = (P.n_entries + kScanChunk - 1) / kScanChunk;
   P.sort_blocks = (capacity + kSortChunk - 1) / kSortChunk;
-  const int64_t depth_blocks = (P.n_entries + kSortChunk - 1) / kSortChunk;
+  const int64_t depth_chunk = 256 * kDepthItems;
+  const int64_t depth_blocks = (P.n_entries + depth_chunk - 1) / depth_chunk;
   const int64_t hist_n = 256 * std::max<int64_t>(std::max(P.sort_blocks, depth_blocks), 1);
   const size_t ne = sizeof(uint32_t) * (size_t)P.n_entries;
   size_t off = 0;
@@ -655,17 +663,19 @@ BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity)
   return P;
 }
 
-// One LSD radix pass over n (device count, at most cap) keys of type K.
-template <typename K>
+// One LSD radix pass over n (device count, at most cap) keys of type K, in
+// chunks of 256 * ITEMS keys.
+template <typename K, int ITEMS>
 void radix_pass(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, const uint32_t* n,
                 int64_t cap, int shift, uint32_t* hist, uint32_t* digit_tot, hipStream_t s) {
-  const uint32_t nblocks = (uint32_t)((cap + kSortChunk - 1) / kSortChunk);
-  hipLaunchKernelGGL((radix_upsweep_kernel<K>), dim3(nblocks), dim3(256), 0, s, kin, n, cap, shift,
-                     hist, nblocks);
-  hipLaunchKernelGGL(hist_row_scan_kernel, dim3(256), dim3(256), 0, s, hist, nblocks, n, cap,
-                     digit_tot);
-  hipLaunchKernelGGL((radix_downsweep_kernel<K>), dim3(nblocks), dim3(256), 0, s, kin, vin, kout,
-                     vout, n, cap, shift, hist, digit_tot, nblocks);
+  constexpr int64_t chunk = 256 * ITEMS;
+  const uint32_t nblocks = (uint32_t)((cap + chunk - 1) / chunk);
+  hipLaunchKernelGGL((radix_upsweep_kernel<K, ITEMS>), dim3(nblocks), dim3(256), 0, s, kin, n, cap,
+                     shift, hist, nblocks);
+  hipLaunchKernelGGL(hist_row_scan_kernel, dim3(256), dim3(256), 0, s, hist, nblocks,
+                     (uint32_t)chunk, n, cap, digit_tot);
+  hipLaunchKernelGGL((radix_downsweep_kernel<K, ITEMS>), dim3(nblocks), dim3(256), 0, s, kin, vin,
+                     kout, vout, n, cap, shift, hist, digit_tot, nblocks);
 }
 
 int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs_bins& bins,
@@ -710,7 +720,7 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
     // 2. stable sort of the binned splats by depth (ties keep entry order)
     uint32_t *ka = dkey, *va = dval, *kb = dkey + ne, *vb = dval + ne;
     for (int pass = 0; pass < 4; ++pass) {
-      radix_pass<uint32_t>(ka, va, kb, vb, n_binned, ne, 8 * pass, hist, digit_tot, s);
+      radix_pass<uint32_t, kDepthItems>(ka, va, kb, vb, n_binned, ne, 8 * pass, hist, digit_tot, s);
       std::swap(ka, kb);
       std::swap(va, vb);
     }
@@ -754,7 +764,7 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   hipLaunchKernelGGL(emit_kernel, dim3(eblocks), dim3(256), 0, s, xy, p.radius, rd, dval,
                      n_binned, offsets, n, vt, flag, P.capacity, kA, vA);
   for (int pass = 0; pass < P.passes; ++pass) {
-    radix_pass<uint64_t>(kA, vA, kB, vB, bins.n_keys, std::min<int64_t>(n_sort, P.capacity),
+    radix_pass<uint64_t, kSortItems>(kA, vA, kB, vB, bins.n_keys, std::min<int64_t>(n_sort, P.capacity),
                          32 + 8 * pass, hist, digit_tot, s);
     std::swap(kA, kB);
     std::swap(vA, vB);
