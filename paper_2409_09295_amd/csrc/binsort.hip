@@ -30,8 +30,8 @@ namespace gsmi {
 namespace {
 
 constexpr int kScanThreads = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanChunk = kScanThreads * kScanItems;   // 4096
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kScanThreads * kScanItems;   // 2048 (measured against 4096)
 constexpr int kSortItems = 8;
 constexpr int kSortChunk = 256 * kSortItems;            // 2048 keys per workgroup (tile passes)
 // The depth passes sort only the binned splats (about a ninth of the
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kPartThreads) void scan_partials_kernel(uint64_t* _
   }
 }
 
-// Each wave scans 1024 consecutive values of the block's chunk as 16 rows of
+// Each wave scans kScanChunk / 4 consecutive values of the block's chunk as rows of
 // 64 (coalesced), carrying the running total from row to row, so only the
 // four wave totals need a block-level step.  out may alias in: every value is
 // read before its position is written.
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t*
                                                                  uint32_t* out, Compact cp) {
   static_assert(!COMPACT || PRED, "compaction scans the binned flags");
   __shared__ uint32_t s_wave[4];
-  constexpr int kRows = kScanChunk / kScanThreads;   // 16 rows of 64 per wave
+  constexpr int kRows = kScanChunk / kScanThreads;   // rows of 64 per wave
   n = scan_bound(n, n_dev);
   if ((int64_t)blockIdx.x * kScanChunk >= n) return;   // uniform over the block
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
