@@ -100,6 +100,16 @@ def test_bin_sort_crowded_tiles(gs, n):
         np.testing.assert_array_equal(u32(bins.ranges), ranges)
 
 
+def _length_group(x):
+    """Group of a tile list of x keys in the tile order: 0 when empty, then
+    half octaves (1 + 2 floor(log2 x) + the bit below the leading one)."""
+    if x == 0:
+        return 0
+    lg = int(x).bit_length() - 1
+    half = (int(x) >> (lg - 1)) & 1 if lg > 0 else 0
+    return min(31, 1 + 2 * lg + half)
+
+
 def test_tile_order_longest_first(gs):
     """bins.order is the stable sort of the tiles by list-length group (half
     octaves), longest group first, and compositing gives the same image with
@@ -113,14 +123,7 @@ def test_tile_order_longest_first(gs):
     rg = np_(bins.ranges).astype(np.int64)
     ln = rg[:, 1] - rg[:, 0]
 
-    def group(x):
-        if x == 0:
-            return 0
-        lg = int(x).bit_length() - 1
-        half = (int(x) >> (lg - 1)) & 1 if lg > 0 else 0
-        return min(31, 1 + 2 * lg + half)
-
-    groups = np.array([group(x) for x in ln])
+    groups = np.array([_length_group(x) for x in ln])
     np.testing.assert_array_equal(order, np.argsort(-groups, kind="stable"))
     assert ln[order[0]] == ln.max()
     outs = []
@@ -146,6 +149,21 @@ def test_bin_sort_all_culled(gs):
     assert nk == 0
     assert int(u32(bins.n_keys)[0]) == 0
     assert (u32(bins.ranges) == 0).all()
+    # returned before any range existed: the order is the identity
+    np.testing.assert_array_equal(u32(bins.order), np.arange(views.n_tiles))
+
+
+@pytest.mark.parametrize("size", [(16, 16), (40, 23)], ids=["one_tile", "six_tiles"])
+def test_tile_order_small_grids(gs, size):
+    """Grids smaller than one workgroup of the order kernels, with empty
+    tiles: the order is still the stable sort by list-length group."""
+    cams = [scenes.pinhole(size[0], size[1], 20.0)]
+    sp = scenes.random_splats(40, cams, seed=9)
+    views, proj, bins, nk = _gpu_bins(gs, sp, cams)
+    rg = u32(bins.ranges).astype(np.int64).reshape(-1, 2)
+    ln = rg[:, 1] - rg[:, 0]
+    grp = np.array([_length_group(x) for x in ln])
+    np.testing.assert_array_equal(u32(bins.order), np.argsort(-grp, kind="stable"))
 
 
 def test_bin_sort_capacity(gs):
