@@ -132,7 +132,10 @@ typedef struct gs_projected {
 
 /* Tile binning result (device):
  *   keys   [capacity] uint64 (global tile << 32) | float32 bits of depth,
- *          ascending; ties ordered by value
+ *          ascending; ties ordered by value.  Optional for gs_bin_sort
+ *          (NULL = not written; values, ranges and order are the same, and
+ *          the sort then carries 32-bit tile ids in the workspace, which
+ *          moves a third less data); the compositing calls never read it.
  *   values [capacity] uint32 view * n + Gaussian index
  *   ranges [n_tiles][2] uint32 [start, end) into keys/values per global tile
  *   n_keys [1] uint32 number of keys emitted (may exceed capacity, in which

@@ -47,7 +47,7 @@ class _State:
 
     def _alloc_bins(self, capacity: int):
         capacity = int(min(capacity, 0xFFFFFFFF))
-        self.bins = gs.Bins.empty(capacity, self.n_tiles, self.device)
+        self.bins = gs.Bins.empty(capacity, self.n_tiles, self.device, keys=False)   # never read here
         self.sort_ws = gs.workspace(gs.gs_bin_sort_workspace_size(self.n, self.views, capacity),
                                     self.device)
 

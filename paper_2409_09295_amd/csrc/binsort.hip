@@ -279,6 +279,10 @@ __device__ __forceinline__ uint32_t wave_prefix_max(uint32_t x) {
 // writes it 64 keys at a time: in each window of 64 positions, every item
 // with keys marks where it starts, and a prefix maximum over the lanes gives
 // each position its item (the item marked last at or before it).
+// K = uint64_t: keys (tile << 32) | depth bits; K = uint32_t: the tile id
+// alone (the keys are emitted in depth order, and the tile passes are
+// stable, so the tile id is all the sort needs).
+template <typename K>
 __global__ __launch_bounds__(256) void emit_kernel(const float2* __restrict__ xy,
                                                    const int32_t* __restrict__ radius,
                                                    const float4* __restrict__ rd,
@@ -287,7 +291,7 @@ __global__ __launch_bounds__(256) void emit_kernel(const float2* __restrict__ xy
                                                    const uint32_t* __restrict__ offsets,
                                                    int64_t n, ViewTable vt,
                                                    const uint64_t* __restrict__ total,
-                                                   int64_t capacity, uint64_t* __restrict__ keys,
+                                                   int64_t capacity, K* __restrict__ keys,
                                                    uint32_t* __restrict__ vals) {
   if (*total > (uint64_t)capacity) return;  // overflow: nothing is emitted
   __shared__ uint4 s_rect[4][64];    // start, first tile, rectangle width, tiles per row
@@ -338,7 +342,10 @@ __global__ __launch_bounds__(256) void emit_kernel(const float2* __restrict__ xy
       const uint32_t jj = pos - r.x;
       const uint32_t row = jj / r.z;
       const uint32_t tile = r.y + row * r.w + (jj - row * r.z);
-      keys[pos] = ((uint64_t)tile << 32) | (uint64_t)d.x;
+      if constexpr (sizeof(K) == 8)
+        keys[pos] = ((uint64_t)tile << 32) | (uint64_t)d.x;
+      else
+        keys[pos] = tile;
       vals[pos] = d.y;
     }
     __builtin_amdgcn_wave_barrier();
@@ -492,15 +499,19 @@ __global__ __launch_bounds__(256) void radix_downsweep_kernel(
   }
 }
 
-__global__ __launch_bounds__(256) void ranges_kernel(const uint64_t* __restrict__ keys,
+__device__ __forceinline__ uint32_t key_tile(uint64_t k) { return (uint32_t)(k >> 32); }
+__device__ __forceinline__ uint32_t key_tile(uint32_t k) { return k; }
+
+template <typename K>
+__global__ __launch_bounds__(256) void ranges_kernel(const K* __restrict__ keys,
                                                      const uint32_t* __restrict__ n_keys,
                                                      int64_t capacity, uint32_t* __restrict__ ranges) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t n = valid_keys(n_keys, capacity);
   if (i >= n) return;
-  const uint32_t tile = (uint32_t)(keys[i] >> 32);
-  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != tile) ranges[2 * (int64_t)tile] = (uint32_t)i;
-  if (i == (int64_t)n - 1 || (uint32_t)(keys[i + 1] >> 32) != tile)
+  const uint32_t tile = key_tile(keys[i]);
+  if (i == 0 || key_tile(keys[i - 1]) != tile) ranges[2 * (int64_t)tile] = (uint32_t)i;
+  if (i == (int64_t)n - 1 || key_tile(keys[i + 1]) != tile)
     ranges[2 * (int64_t)tile + 1] = (uint32_t)(i + 1);
 }
 
@@ -678,6 +689,35 @@ void radix_pass(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, cons
                      kout, vout, n, cap, shift, hist, digit_tot, nblocks);
 }
 
+// Key emission in depth order, the stable passes over the tile bits (the
+// first at bit tile_shift of K) and the ranges.  out/alt: the key buffers;
+// after an even number of passes the sorted keys and values are in out and
+// bins.values.
+template <typename K>
+void tile_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs_bins& bins, K* out,
+               K* alt, uint32_t* vals_alt, int tile_shift, const uint32_t* dval,
+               const uint32_t* n_binned, const uint32_t* offsets, const uint64_t* flag,
+               int64_t n_sort, uint32_t* hist, uint32_t* digit_tot, const BinSortPlan& P,
+               hipStream_t s) {
+  const auto* xy = reinterpret_cast<const float2*>(p.xy);
+  const auto* rd = reinterpret_cast<const float4*>(p.rgb_depth);
+  const unsigned eblocks = (unsigned)((P.n_entries + 255) / 256);
+  K* kA = (P.passes % 2 == 0) ? out : alt;
+  uint32_t* vA = (P.passes % 2 == 0) ? bins.values : vals_alt;
+  K* kB = (P.passes % 2 == 0) ? alt : out;
+  uint32_t* vB = (P.passes % 2 == 0) ? vals_alt : bins.values;
+  hipLaunchKernelGGL((emit_kernel<K>), dim3(eblocks), dim3(256), 0, s, xy, p.radius, rd, dval,
+                     n_binned, offsets, n, vt, flag, P.capacity, kA, vA);
+  for (int pass = 0; pass < P.passes; ++pass) {
+    radix_pass<K, kSortItems>(kA, vA, kB, vB, bins.n_keys, std::min<int64_t>(n_sort, P.capacity),
+                              tile_shift + 8 * pass, hist, digit_tot, s);
+    std::swap(kA, kB);
+    std::swap(vA, vB);
+  }
+  hipLaunchKernelGGL((ranges_kernel<K>), dim3((unsigned)((n_sort + 255) / 256)), dim3(256), 0, s,
+                     kA, bins.n_keys, P.capacity, bins.ranges);
+}
+
 int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs_bins& bins,
                  uint32_t* n_keys_host, char* ws, const BinSortPlan& P, hipStream_t s) {
   auto* counts = reinterpret_cast<uint32_t*>(ws + P.off_counts);
@@ -757,20 +797,14 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   }
 
   // 4. keys emitted in depth order, then a stable sort on the tile bits only
-  uint64_t* kA = (P.passes % 2 == 0) ? bins.keys : keys_alt;
-  uint32_t* vA = (P.passes % 2 == 0) ? bins.values : vals_alt;
-  uint64_t* kB = (P.passes % 2 == 0) ? keys_alt : bins.keys;
-  uint32_t* vB = (P.passes % 2 == 0) ? vals_alt : bins.values;
-  hipLaunchKernelGGL(emit_kernel, dim3(eblocks), dim3(256), 0, s, xy, p.radius, rd, dval,
-                     n_binned, offsets, n, vt, flag, P.capacity, kA, vA);
-  for (int pass = 0; pass < P.passes; ++pass) {
-    radix_pass<uint64_t, kSortItems>(kA, vA, kB, vB, bins.n_keys, std::min<int64_t>(n_sort, P.capacity),
-                         32 + 8 * pass, hist, digit_tot, s);
-    std::swap(kA, kB);
-    std::swap(vA, vB);
-  }
-  hipLaunchKernelGGL(ranges_kernel, dim3((unsigned)((n_sort + 255) / 256)), dim3(256), 0, s,
-                     bins.keys, bins.n_keys, P.capacity, bins.ranges);
+  // (with bins.keys == NULL on 32-bit tile ids held in the workspace)
+  if (bins.keys)
+    tile_sort<uint64_t>(p, n, vt, bins, bins.keys, reinterpret_cast<uint64_t*>(keys_alt), vals_alt,
+                        32, dval, n_binned, offsets, flag, n_sort, hist, digit_tot, P, s);
+  else
+    tile_sort<uint32_t>(p, n, vt, bins, reinterpret_cast<uint32_t*>(keys_alt),
+                        reinterpret_cast<uint32_t*>(keys_alt) + P.capacity, vals_alt, 0, dval,
+                        n_binned, offsets, flag, n_sort, hist, digit_tot, P, s);
   if (bins.order && vt.n_tiles > 0) {
     const int nblk = (vt.n_tiles + kOrderBlock - 1) / kOrderBlock;
     hipLaunchKernelGGL(order_count_kernel, dim3((unsigned)nblk), dim3(kOrderBlock), 0, s,

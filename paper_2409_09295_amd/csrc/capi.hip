@@ -220,7 +220,7 @@ int gs_bin_sort(const gs_projected* p, int64_t n, const gs_views* views, gs_bins
   if ((uint64_t)n * (uint64_t)vt.n_views > 0xFFFFFFFFull)
     return invalid("n * n_views exceeds 2^32 - 1");
   if ((st = check_projected(p, n))) return st;
-  if ((st = check_bins(bins, true))) return st;
+  if ((st = check_bins(bins, false))) return st;   // keys are optional
   const BinSortPlan plan = make_bin_sort_plan(n, vt, bins->capacity);
   if ((st = check_workspace(workspace, workspace_bytes, plan.total))) return st;
   return run_bin_sort(*p, n, vt, *bins, n_keys_host, static_cast<char*>(workspace), plan, stream);

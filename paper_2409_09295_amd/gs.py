@@ -297,7 +297,7 @@ class Projected:
 
 @dataclasses.dataclass
 class Bins:
-    keys: torch.Tensor     # (capacity,) int64 storage of uint64
+    keys: Optional[torch.Tensor]   # (capacity,) int64 storage of uint64, or not written
     values: torch.Tensor   # (capacity,) int32 storage of uint32
     ranges: torch.Tensor   # (n_tiles, 2) int32 storage of uint32
     n_keys: torch.Tensor   # (1,) int32 storage of uint32
@@ -305,9 +305,12 @@ class Bins:
     order: Optional[torch.Tensor] = None   # (n_tiles,) int32 storage of uint32, or not computed
 
     @classmethod
-    def empty(cls, capacity: int, n_tiles: int, device="cuda", order: bool = True) -> "Bins":
+    def empty(cls, capacity: int, n_tiles: int, device="cuda", order: bool = True,
+              keys: bool = True) -> "Bins":
+        """keys=False: no key array (gs_bin_sort then sorts 32-bit tile ids
+        in its workspace; values, ranges and order are the same)."""
         cap = max(int(capacity), 1)
-        return cls(torch.empty(cap, dtype=torch.int64, device=device),
+        return cls(torch.empty(cap, dtype=torch.int64, device=device) if keys else None,
                    torch.empty(cap, dtype=torch.int32, device=device),
                    torch.empty(n_tiles, 2, dtype=torch.int32, device=device),
                    torch.zeros(1, dtype=torch.int32, device=device), int(capacity),

@@ -42,7 +42,7 @@ class Rasterizer:
 
     def _alloc_bins(self, capacity: int):
         capacity = int(min(capacity, 0xFFFFFFFF))
-        self.bins = gs.Bins.empty(capacity, self.n_tiles, self.device)
+        self.bins = gs.Bins.empty(capacity, self.n_tiles, self.device, keys=False)   # never read here
         self.sort_ws = gs.workspace(gs.gs_bin_sort_workspace_size(self.n, self.views, capacity), self.device)
 
     def _project_and_bin(self, g: gs.Gaussians):

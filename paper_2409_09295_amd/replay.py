@@ -104,13 +104,13 @@ class BatchedStep:
     def _alloc_bins(self, capacity: int):
         capacity = int(min(capacity, 0xFFFFFFFF))
         dev = self.g.means.device
-        self.bins = gs.Bins.empty(capacity, self.n_tiles, dev)
+        self.bins = gs.Bins.empty(capacity, self.n_tiles, dev, keys=False)   # never read here
         self.sort_ws = gs.workspace(gs.gs_bin_sort_workspace_size(self.n, self.views, capacity), dev)
 
     def measure_keys(self) -> int:
         """Key count of the current map (one synchronous binning pass)."""
         gs.gs_preprocess(self.g, self.views, self.proj)
-        probe = gs.Bins.empty(1, self.n_tiles, self.g.means.device)
+        probe = gs.Bins.empty(1, self.n_tiles, self.g.means.device, keys=False)
         ws = gs.workspace(gs.gs_bin_sort_workspace_size(self.n, self.views, 1), self.g.means.device)
         try:
             return int(gs.gs_bin_sort(self.proj, self.n, self.views, probe, ws, sync=True))

@@ -132,7 +132,8 @@ def test_bin_sort_argument_errors(gs):
     st = lib.gs_bin_sort(ctypes.byref(proj), 10, ctypes.byref(v), ctypes.byref(bins), None, FAKE,
                          need, None)
     assert st == 1
-    bins = gs.gs_bins(None, FAKE, FAKE, FAKE, 100)
+    # keys are optional; values, ranges and the device count are not
+    bins = gs.gs_bins(FAKE, None, FAKE, FAKE, 100)
     st = lib.gs_bin_sort(ctypes.byref(proj), 10, ctypes.byref(v), ctypes.byref(bins), None, FAKE,
                          need, None)
     assert st == 1

@@ -37,14 +37,14 @@ def _oracle_tile_counts(sp, cams):
                      for v, c in enumerate(cams)]).astype(np.int32)
 
 
-def _gpu_bins(gs, sp, cams, capacity=None, sync=True, stored_counts=False):
+def _gpu_bins(gs, sp, cams, capacity=None, sync=True, stored_counts=False, keys=True):
     views = gs.Views(cams)
     proj = gs.Projected.from_splats(sp)
     if stored_counts:   # the path that takes the projection's tile counts
         proj.tiles = torch.from_numpy(_oracle_tile_counts(sp, cams)).to(DEV)
     V, N = sp.radius.shape
     cap = capacity if capacity is not None else 64 * N * V + 1024
-    bins = gs.Bins.empty(cap, views.n_tiles)
+    bins = gs.Bins.empty(cap, views.n_tiles, keys=keys)
     ws = gs.workspace(gs.gs_bin_sort_workspace_size(N, views, cap))
     n = gs.gs_bin_sort(proj, N, views, bins, ws, sync=sync)
     torch.cuda.synchronize()
@@ -54,26 +54,34 @@ def _gpu_bins(gs, sp, cams, capacity=None, sync=True, stored_counts=False):
 @pytest.mark.parametrize("case", list(BIN_CASES))
 @pytest.mark.parametrize("sync", [True, False])
 @pytest.mark.parametrize("stored", [False, True], ids=["counted", "stored_counts"])
-def test_bin_sort_bit_exact(gs, case, sync, stored):
+@pytest.mark.parametrize("with_keys", [True, False], ids=["keys", "tile_ids"])
+def test_bin_sort_bit_exact(gs, case, sync, stored, with_keys):
     cams = BIN_CASES[case]
     n = 2500 if case != "ragged_multi_view" else 6000
     sp = scenes.random_splats(n, cams, seed=21, depth_ties=0.2, cull_frac=0.05)
-    _log(f"bin_sort case={case} sync={sync} stored_counts={stored} n={n}")
+    _log(f"bin_sort case={case} sync={sync} stored_counts={stored} keys={with_keys} n={n}")
     keys, vals, ranges, _, _ = O.bin_splats([sp.xy[v] for v in range(len(cams))],
                                             [sp.rgb_depth[v, :, 3] for v in range(len(cams))],
                                             [sp.radius[v] for v in range(len(cams))], cams, 16)
-    views, proj, bins, nk = _gpu_bins(gs, sp, cams, sync=sync, stored_counts=stored)
+    views, proj, bins, nk = _gpu_bins(gs, sp, cams, sync=sync, stored_counts=stored,
+                                      keys=with_keys)
     got_n = int(u32(bins.n_keys)[0])
     assert got_n == len(keys)
     if sync:
         assert nk == len(keys)
-    np.testing.assert_array_equal(u64(bins.keys)[:got_n], keys)
+    if with_keys:
+        np.testing.assert_array_equal(u64(bins.keys)[:got_n], keys)
+    else:
+        assert bins.keys is None
     np.testing.assert_array_equal(u32(bins.values)[:got_n], vals)
     np.testing.assert_array_equal(u32(bins.ranges), ranges)
     # repeat: integer outputs are deterministic
-    views2, proj2, bins2, _ = _gpu_bins(gs, sp, cams, sync=sync, stored_counts=stored)
-    np.testing.assert_array_equal(u64(bins2.keys)[:got_n], u64(bins.keys)[:got_n])
+    views2, proj2, bins2, _ = _gpu_bins(gs, sp, cams, sync=sync, stored_counts=stored,
+                                        keys=with_keys)
+    if with_keys:
+        np.testing.assert_array_equal(u64(bins2.keys)[:got_n], u64(bins.keys)[:got_n])
     np.testing.assert_array_equal(u32(bins2.values)[:got_n], u32(bins.values)[:got_n])
+    np.testing.assert_array_equal(u32(bins2.order), u32(bins.order))
 
 
 @pytest.mark.parametrize("n", [700, 3000])
@@ -91,11 +99,12 @@ def test_bin_sort_crowded_tiles(gs, n):
                                             cams, 16)
     longest = int((ranges[:, 1] - ranges[:, 0]).max())
     _log(f"crowded tiles n={n}: {len(keys)} keys, longest list {longest}")
-    for sync in (True, False):
-        views, proj, bins, nk = _gpu_bins(gs, sp, cams, sync=sync)
+    for sync, with_keys in ((True, True), (False, True), (False, False)):
+        views, proj, bins, nk = _gpu_bins(gs, sp, cams, sync=sync, keys=with_keys)
         got_n = int(u32(bins.n_keys)[0])
         assert got_n == len(keys)
-        np.testing.assert_array_equal(u64(bins.keys)[:got_n], keys)
+        if with_keys:
+            np.testing.assert_array_equal(u64(bins.keys)[:got_n], keys)
         np.testing.assert_array_equal(u32(bins.values)[:got_n], vals)
         np.testing.assert_array_equal(u32(bins.ranges), ranges)
 
