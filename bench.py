@@ -312,13 +312,14 @@ def main():
     # visible (Gaussian, view), a radius and a zero count per culled one
     pre_bytes = (g.n * 4 * (3 + 3 + 4 + 1 + 3 * K) + n_visible * (8 + 16 + 16 + 4 + 4)
                  + (g.n * len(wl.cams) - n_visible) * 8)
-    # binning: the tile count of every entry (4 B) and the radius, centre and
-    # depth of every binned splat (one that touches a tile), the depth sort of
-    # the binned splats (4 passes, 8 B read + 8 B written), 12 B per key
-    # emitted and 24 B per key per tile-digit pass
+    # binning (the step bins without keys): the tile count of every entry
+    # (4 B) and the radius, centre and depth of every binned splat (one that
+    # touches a tile), the depth sort of the binned splats (4 passes, 8 B read
+    # + 8 B written), 8 B per (tile id, value) emitted and 16 B per key per
+    # tile-digit pass
     tile_passes = math.ceil(max(1, math.ceil(math.log2(max(views.n_tiles, 2)))) / 8)
     sort_bytes = (g.n * len(wl.cams) * 4 + n_binned * (4 + 8 + 4) + n_binned * 4 * 16
-                  + n_keys * 12 + n_keys * 24 * tile_passes)
+                  + n_keys * 8 + n_keys * 16 * tile_passes)
     hbm = {name: {"bytes": b, "ms": kms[name], "GB/s": b / (kms[name] * 1e-3) / 1e9,
                   "frac": b / (kms[name] * 1e-3) / 1e9 / HBM_PEAK_GBS}
            for name, b in (("preprocess", pre_bytes), ("bin_sort", sort_bytes))}
