@@ -3,26 +3,30 @@
 //   count     one lane per (view, splat): tile rectangle (float64 from the
 //             float32 centre) -> number of tiles, and whether it has any
 //             (skipped when the projection stored the counts)
-//   depth     the splats with tiles are compacted in entry order (a scan of
-//             the flags) and sorted by their float32 depth bits with a
+//   depth     the splats with tiles are compacted in entry order (by the
+//             down-sweep of a scan of the flags) and sorted by their float32
+//             depth bits with a
 //             stable LSD radix sort, so equal depths keep entry order; this
 //             sorts one item per visible splat instead of one per key
 //   scan      device-wide exclusive scan of the tile counts in that order,
 //             total in 64 bits (the key count)
 //   emit      wave-cooperative emission in depth order: the 64 splats of a
 //             wave own a contiguous key range; the wave walks that range 64
-//             keys at a time and each lane locates its owner by binary search
-//             over the wave's 64 start offsets, so stores are contiguous and
-//             big rectangles do not serialise one lane
+//             keys at a time and each lane finds its owner with a prefix
+//             maximum over the splats' start marks, so stores are contiguous
+//             and big rectangles do not serialise one lane
 //   tile sort stable LSD radix sort of the keys on their tile bits only
 //             (ceil(log2 tiles) bits): keys of a tile keep the depth order of
 //             their emission, giving the (tile, depth, entry) order.  Per
 //             pass: block histograms, a row scan of the digit-major
 //             histogram, then a down-sweep that ranks keys within the block
 //             with wave ballots (stable), stages them in LDS in digit order
-//             and writes each digit run contiguously
+//             and writes each digit run contiguously.  Without output keys
+//             the passes carry 32-bit tile ids instead of 64-bit keys
 //   ranges    [start, end) per global tile from tile boundaries in the
 //             sorted keys
+//   order     optional: the tiles stably sorted by list length group,
+//             longest first (the launch order of the compositing grids)
 #include "gs_internal.h"
 
 namespace gsmi {
