@@ -95,12 +95,27 @@ __device__ __forceinline__ int64_t scan_bound(int64_t n, const uint32_t* n_dev) 
   return n_dev ? min(n, (int64_t)*n_dev) : n;
 }
 
+// Optional work folded into a scan's reduce kernel (saves a launch): clear
+// ranges[n_tiles][2] and write the identity order (when order != nullptr).
+struct ClearBins {
+  uint32_t* ranges = nullptr;
+  int n_tiles = 0;
+  uint32_t* order = nullptr;
+};
+
 template <bool PRED>
 __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t* __restrict__ in,
                                                                    int64_t n,
                                                                    const uint32_t* __restrict__ n_dev,
-                                                                   uint64_t* __restrict__ partial) {
+                                                                   uint64_t* __restrict__ partial,
+                                                                   ClearBins clr) {
   __shared__ uint64_t s_wave[4];
+  for (int64_t t = (int64_t)blockIdx.x * kScanThreads + threadIdx.x; t < clr.n_tiles;
+       t += (int64_t)gridDim.x * kScanThreads) {
+    clr.ranges[2 * t] = 0u;
+    clr.ranges[2 * t + 1] = 0u;
+    if (clr.order) clr.order[t] = (uint32_t)t;
+  }
   const int64_t base = (int64_t)blockIdx.x * kScanChunk;
   n = scan_bound(n, n_dev);
   if (base >= n) {   // uniform over the block
@@ -213,11 +228,11 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t*
 template <bool PRED = false, bool COMPACT = false>
 void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* n_dev,
               uint64_t* partial, uint64_t* total, uint32_t* n_keys, hipStream_t s,
-              Compact cp = Compact{}) {
+              Compact cp = Compact{}, ClearBins clr = ClearBins{}) {
   const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
   if (nb > 0)
     hipLaunchKernelGGL(scan_reduce_kernel<PRED>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in,
-                       n, n_dev, partial);
+                       n, n_dev, partial, clr);
   hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kPartThreads), 0, s, partial, nb, total,
                      n_keys);
   if (nb > 0)
@@ -250,16 +265,6 @@ __global__ __launch_bounds__(256) void count_kernel(const float2* __restrict__ x
   counts[e] = cnt;
 }
 
-// Tile counts in depth order, for the first *n_order positions.
-__global__ __launch_bounds__(256) void gather_counts_kernel(const uint32_t* __restrict__ order,
-                                                            const uint32_t* __restrict__ n_order,
-                                                            const uint32_t* __restrict__ counts,
-                                                            int64_t n_entries,
-                                                            uint32_t* __restrict__ out) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= min(n_entries, (int64_t)*n_order)) return;
-  out[j] = counts[order[j]];
-}
 
 // Inclusive prefix maximum over the 64 lanes of a wavefront (DPP row shifts,
 // then the row broadcasts; lanes without a source see 0, the identity here).
@@ -417,12 +422,15 @@ __global__ __launch_bounds__(256) void hist_row_scan_kernel(uint32_t* __restrict
   if (threadIdx.x == 0) tot[blockIdx.x] = total;
 }
 
+// gather_in (optional): also writes gather_out[o] = gather_in[value] for the
+// value placed at o (the tile counts of the splats, in the sorted order).
 template <typename K, int ITEMS>
 __global__ __launch_bounds__(256) void radix_downsweep_kernel(
     const K* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     K* __restrict__ keys_out, uint32_t* __restrict__ vals_out,
     const uint32_t* __restrict__ n_keys, int64_t capacity, int shift,
-    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot, uint32_t nblocks) {
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ digit_tot, uint32_t nblocks,
+    const uint32_t* __restrict__ gather_in, uint32_t* __restrict__ gather_out) {
   constexpr int kChunk = 256 * ITEMS;
   __shared__ uint32_t s_wcnt[4][256];
   __shared__ uint32_t s_wpre[4][256];
@@ -497,8 +505,10 @@ __global__ __launch_bounds__(256) void radix_downsweep_kernel(
       const K k = s_keys[pos];
       const uint32_t d = (uint32_t)(k >> shift) & 255u;
       const uint32_t o = s_gbase[d] + (uint32_t)pos - s_dstart[d];
+      const uint32_t v = s_vals[pos];
       keys_out[o] = k;
-      vals_out[o] = s_vals[pos];
+      vals_out[o] = v;
+      if (gather_in) gather_out[o] = gather_in[v];
     }
   }
 }
@@ -682,7 +692,8 @@ BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity)
 // chunks of 256 * ITEMS keys.
 template <typename K, int ITEMS>
 void radix_pass(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, const uint32_t* n,
-                int64_t cap, int shift, uint32_t* hist, uint32_t* digit_tot, hipStream_t s) {
+                int64_t cap, int shift, uint32_t* hist, uint32_t* digit_tot, hipStream_t s,
+                const uint32_t* gather_in = nullptr, uint32_t* gather_out = nullptr) {
   constexpr int64_t chunk = 256 * ITEMS;
   const uint32_t nblocks = (uint32_t)((cap + chunk - 1) / chunk);
   hipLaunchKernelGGL((radix_upsweep_kernel<K, ITEMS>), dim3(nblocks), dim3(256), 0, s, kin, n, cap,
@@ -690,7 +701,7 @@ void radix_pass(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, cons
   hipLaunchKernelGGL(hist_row_scan_kernel, dim3(256), dim3(256), 0, s, hist, nblocks,
                      (uint32_t)chunk, n, cap, digit_tot);
   hipLaunchKernelGGL((radix_downsweep_kernel<K, ITEMS>), dim3(nblocks), dim3(256), 0, s, kin, vin,
-                     kout, vout, n, cap, shift, hist, digit_tot, nblocks);
+                     kout, vout, n, cap, shift, hist, digit_tot, nblocks, gather_in, gather_out);
 }
 
 // Key emission in depth order, the stable passes over the tile bits (the
@@ -743,7 +754,13 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   hipError_t e;
 
   kernel_event_start(GS_KERNEL_BIN_SORT, s);
-  if (vt.n_tiles > 0)
+  // all ranges empty and the identity order first (so that both are valid on
+  // every return path): folded into the first scan, or a kernel of its own
+  ClearBins clr;
+  clr.ranges = bins.ranges;
+  clr.n_tiles = vt.n_tiles;
+  clr.order = bins.order;
+  if (ne == 0 && vt.n_tiles > 0)
     hipLaunchKernelGGL(clear_bins_kernel, dim3((unsigned)((vt.n_tiles + 255) / 256)), dim3(256), 0,
                        s, bins.ranges, vt.n_tiles, bins.order);
   // 1. tiles per splat (from the projection when it stored them); binned
@@ -760,19 +777,21 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
     cp.rd = rd;
     cp.dkey = dkey;
     cp.dval = dval;
-    scan_u32<true, true>(tiles, nullptr, ne, nullptr, part, flag + 1, n_binned, s, cp);
+    scan_u32<true, true>(tiles, nullptr, ne, nullptr, part, flag + 1, n_binned, s, cp, clr);
     // 2. stable sort of the binned splats by depth (ties keep entry order)
     uint32_t *ka = dkey, *va = dval, *kb = dkey + ne, *vb = dval + ne;
+    // (the last pass also writes each splat's tile count in the sorted order)
     for (int pass = 0; pass < 4; ++pass) {
-      radix_pass<uint32_t, kDepthItems>(ka, va, kb, vb, n_binned, ne, 8 * pass, hist, digit_tot, s);
+      radix_pass<uint32_t, kDepthItems>(ka, va, kb, vb, n_binned, ne, 8 * pass, hist, digit_tot, s,
+                                        pass == 3 ? tiles : nullptr,
+                                        pass == 3 ? offsets : nullptr);
       std::swap(ka, kb);
       std::swap(va, vb);
     }
     // ka/va (= dkey/dval after an even number of passes) hold the depth order
-    // 3. key offsets in depth order; their total is the key count
-    hipLaunchKernelGGL(gather_counts_kernel, dim3(eblocks), dim3(256), 0, s, va, n_binned, tiles,
-                       ne, offsets);
-    // (positions past the binned splats are neither written nor read)
+    // 3. key offsets in depth order (an in-place scan of those counts); their
+    // total is the key count.  Positions past the binned splats are neither
+    // written nor read.
     scan_u32(offsets, offsets, ne, n_binned, part, flag, bins.n_keys, s);
   } else {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, s,
