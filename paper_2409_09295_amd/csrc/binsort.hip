@@ -42,7 +42,6 @@ constexpr int kSortChunk = 256 * kSortItems;            // 2048 keys per workgro
 // entries): chunks of 1,024 keys put more workgroups in flight (measured
 // against 2,048 and 512).
 constexpr int kDepthItems = 4;
-constexpr int kPartThreads = 1024;
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
 
@@ -131,37 +130,6 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// One block: exclusive scan of nb partials in place; total to *total and,
-// if n_keys != nullptr, min(total, 2^32 - 1) to *n_keys.
-__global__ __launch_bounds__(kPartThreads) void scan_partials_kernel(uint64_t* __restrict__ partial,
-                                                                     int64_t nb,
-                                                                     uint64_t* __restrict__ total,
-                                                                     uint32_t* __restrict__ n_keys) {
-  __shared__ uint64_t s_wave[kPartThreads / 64];
-  const int64_t per = (nb + kPartThreads - 1) / kPartThreads;
-  const int64_t lo = threadIdx.x * per, hi = min(lo + per, nb);
-  uint64_t sum = 0;
-  for (int64_t k = lo; k < hi; ++k) sum += partial[k];
-  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
-  const uint64_t inc = wave_inclusive_scan(sum);
-  if (lane == 63) s_wave[w] = inc;
-  __syncthreads();
-  uint64_t pre = 0, tot = 0;
-  for (uint32_t k = 0; k < kPartThreads / 64; ++k) {
-    pre += (k < w) ? s_wave[k] : 0;
-    tot += s_wave[k];
-  }
-  uint64_t run = pre + inc - sum;
-  for (int64_t k = lo; k < hi; ++k) {
-    const uint64_t x = partial[k];
-    partial[k] = run;
-    run += x;
-  }
-  if (threadIdx.x == 0) {
-    *total = tot;
-    if (n_keys) *n_keys = tot > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tot;
-  }
-}
 
 // Each wave scans kScanChunk / 4 consecutive values of the block's chunk as rows of
 // 64 (coalesced), carrying the running total from row to row, so only the
@@ -176,16 +144,33 @@ struct Compact {
   uint32_t* dval = nullptr;
 };
 
+// partial: the reduce kernel's block sums; each block adds up those of the
+// blocks before it (a few loads per thread), and the block holding the last
+// value writes the total to *total and min(total, 2^32 - 1) to *n_keys.
 template <bool PRED, bool COMPACT = false>
 __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t* in, int64_t n,
                                                                  const uint32_t* __restrict__ n_dev,
                                                                  const uint64_t* __restrict__ partial,
-                                                                 uint32_t* out, Compact cp) {
+                                                                 uint32_t* out, Compact cp,
+                                                                 uint64_t* __restrict__ total,
+                                                                 uint32_t* __restrict__ n_keys) {
   static_assert(!COMPACT || PRED, "compaction scans the binned flags");
   __shared__ uint32_t s_wave[4];
+  __shared__ uint64_t s_pre[4];
   constexpr int kRows = kScanChunk / kScanThreads;   // rows of 64 per wave
   n = scan_bound(n, n_dev);
-  if ((int64_t)blockIdx.x * kScanChunk >= n) return;   // uniform over the block
+  const int64_t bbase = (int64_t)blockIdx.x * kScanChunk;
+  if (bbase >= n) {   // uniform over the block
+    if (n == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+      *total = 0;
+      if (n_keys) *n_keys = 0;
+    }
+    return;
+  }
+  uint64_t pre = 0;
+  for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kScanThreads) pre += partial[i];
+  uint64_t block_pre;
+  block_exclusive_scan<uint64_t>(pre, s_pre, block_pre);   // block_pre = sum over all threads
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
   const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)w * (64 * kRows) + lane;
   uint32_t x[kRows];
@@ -205,8 +190,14 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t*
   }
   if (lane == 0) s_wave[w] = run;
   __syncthreads();
-  uint32_t carry = (uint32_t)partial[blockIdx.x];
+  uint32_t carry = (uint32_t)block_pre;
   for (uint32_t k = 0; k < w; ++k) carry += s_wave[k];
+  if (threadIdx.x == 0 && bbase + kScanChunk >= n) {   // the last block with values
+    const uint64_t tot =
+        block_pre + (uint64_t)s_wave[0] + s_wave[1] + (uint64_t)s_wave[2] + s_wave[3];
+    *total = tot;
+    if (n_keys) *n_keys = tot > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tot;
+  }
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
     const int64_t idx = base + 64 * r;
@@ -225,6 +216,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t*
 // Exclusive scan of in[0, m) (of in[i] != 0 with PRED) into out, where
 // m = min(n, *n_dev) when n_dev is given (out[m, n) is left untouched), else n;
 // with COMPACT the scan compacts instead (see scan_down_kernel) and out is unused.
+// The total goes to *total and, clamped to 32 bits, to *n_keys.  n > 0.
 template <bool PRED = false, bool COMPACT = false>
 void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* n_dev,
               uint64_t* partial, uint64_t* total, uint32_t* n_keys, hipStream_t s,
@@ -233,11 +225,9 @@ void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* n_de
   if (nb > 0)
     hipLaunchKernelGGL(scan_reduce_kernel<PRED>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in,
                        n, n_dev, partial, clr);
-  hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kPartThreads), 0, s, partial, nb, total,
-                     n_keys);
   if (nb > 0)
     hipLaunchKernelGGL((scan_down_kernel<PRED, COMPACT>), dim3((unsigned)nb), dim3(kScanThreads), 0,
-                       s, in, n, n_dev, partial, out, cp);
+                       s, in, n, n_dev, partial, out, cp, total, n_keys);
 }
 
 // ---------------------------------------------------------------------------
