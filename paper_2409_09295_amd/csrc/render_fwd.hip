@@ -42,9 +42,11 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
     uint32_t* __restrict__ n_contrib, float* __restrict__ depth_out,
     const float* __restrict__ target, float* __restrict__ dL, float* __restrict__ tile_loss) {
   constexpr int NT = kBlock / PPL;
-  // splats staged per batch: with one wavefront per tile (PPL 4) a smaller
-  // batch halves the LDS per workgroup, so twice as many fit on a CU
-  constexpr int kStage = PPL == 4 ? 128 : 256;
+  // splats staged per batch: with one wavefront per tile (PPL 4), one splat
+  // per lane (a smaller batch takes less LDS per workgroup, and a tile whose
+  // pixels all terminate early stages fewer splats it never walks; 64 was
+  // measured 4.5% faster than 128)
+  constexpr int kStage = PPL == 4 ? 64 : 256;
   constexpr int kPerThread = kStage / NT;
   constexpr int kWords = kStage / 64;
   __shared__ StagedSplat s_splat[kStage];
