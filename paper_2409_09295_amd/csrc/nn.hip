@@ -146,78 +146,104 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(
 }
 
 // Weight-gradient tile: 64 output channels x 64 input channels for one tap,
-// pixels [kbeg, kbeg + WG_KCHUNK) of the K dimension.  Each K step stages 32
-// pixels: thread t reads pixel t / 8 and channels 8 (t % 8) .. +8 of both
-// dz (output-channel tile) and the tap-shifted input (input-channel tile),
-// and writes them transposed ([channel][pixel]) into LDS.
-constexpr int WG_KCHUNK = 2048;
+// pixels [kbeg, kbeg + kchunk) of the K dimension.  Each stage covers 64
+// pixels: thread t loads pixels 2 (t % 32) and 2 (t % 32) + 1, channels
+// 8 (t / 32) .. +8, of both dz (output-channel tile) and the tap-shifted
+// input (input-channel tile) with 16-byte loads, and writes them transposed
+// ([channel][pixel], two pixels per 32-bit write) into LDS; each wavefront
+// then issues two K steps of four MFMAs.
+constexpr int WBK = 64;              // pixels per stage
+constexpr int WLDK = WBK + 8;        // LDS row pitch in bf16 (16-byte aligned rows)
+constexpr int kWgradBlocks = 1024;   // pixel chunks are sized for about this many workgroups
 
-__device__ __forceinline__ uint16_t act_at(const ActView& a, const ActView& b, int64_t pix, int c) {
-  const ActView& s = c < a.c ? a : b;
-  const int cc = c < a.c ? c : c - a.c;
-  return s.p[pix * s.stride + s.offset + cc];
-}
 
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
     ActView x1, ActView x2, ActView dz, ActView mask, int N, int H, int W, int cout, int cin,
-    float* __restrict__ dw, float* __restrict__ dbias) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[BM * LDK];   // [co][pixel]
-  __shared__ __attribute__((aligned(16))) uint16_t sB[BN * LDK];   // [ci][pixel]
+    int64_t kchunk, float* __restrict__ dw, float* __restrict__ dbias) {
+  __shared__ __attribute__((aligned(16))) uint16_t sA[BM * WLDK];   // [co][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t sB[BN * WLDK];   // [ci][pixel]
+  __shared__ float s_bias[BM][33];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t npix = (int64_t)N * H * W;
   const int co0 = blockIdx.x * BM;
   const int tap = blockIdx.y % 9;
   const int ci0 = (blockIdx.y / 9) * BN;
-  const int64_t kbeg = (int64_t)blockIdx.z * WG_KCHUNK;
-  const int64_t kend = min(npix, kbeg + WG_KCHUNK);
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = min(npix, kbeg + kchunk);
   const int dy = tap / 3 - 1, dx = tap % 3 - 1;
   f32x4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
   const bool do_bias = dbias != nullptr && tap == 4 && ci0 == 0;
-  float bacc = 0.f;
+  float bacc[8];
+  for (int q = 0; q < 8; ++q) bacc[q] = 0.f;
   const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
-  const int kl = t >> 3, ch = (t & 7) * 8;
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-    uint16_t vz[8], vx[8];
-    for (int q = 0; q < 8; ++q) vz[q] = vx[q] = 0;
-    const int64_t p = k0 + kl;
-    if (p < kend) {
-      for (int q = 0; q < 8; ++q) {
-        const int co = co0 + ch + q;
-        if (co >= cout) break;
-        uint16_t z = dz.p[p * dz.stride + dz.offset + co];
-        if (mask.p && (int16_t)mask.p[p * mask.stride + mask.offset + co] <= 0) z = 0;
-        vz[q] = z;
-      }
-      const int img = (int)(p / ((int64_t)H * W));
-      const int rem = (int)(p - (int64_t)img * H * W);
-      const int yy = rem / W + dy, xx = rem % W + dx;
-      if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
-        const int64_t sp = ((int64_t)img * H + yy) * W + xx;
-        for (int q = 0; q < 8; ++q) {
-          const int ci = ci0 + ch + q;
-          if (ci >= cin) break;
-          vx[q] = act_at(x1, x2, sp, ci);
-        }
+  // this thread stages pixels k0 + 2 pp and k0 + 2 pp + 1, channels 8 cg .. +8
+  const int pp = t & 31, cg = t >> 5;
+  const ActView none = {nullptr, 0, 0, 0};
+  // image coordinates of the first pixel, advanced by WBK pixels per stage
+  int64_t p0 = kbeg + 2 * pp;
+  int img = 0, py = 0, px = 0;
+  if (p0 < npix) {
+    img = (int)(p0 / ((int64_t)H * W));
+    const int rem = (int)(p0 - (int64_t)img * H * W);
+    py = rem / W;
+    px = rem - py * W;
+  }
+  for (int64_t k0 = kbeg; k0 < kend; k0 += WBK, p0 += WBK) {
+    // the thread's two pixels: (img, py, px) and the next one
+    int img1 = img, py1 = py, px1 = px + 1;
+    if (px1 == W) {
+      px1 = 0;
+      if (++py1 == H) {
+        py1 = 0;
+        ++img1;
       }
     }
+    const bool v0 = p0 < kend, v1 = p0 + 1 < kend;
+    const uint4 z0 = load8(dz, none, mask, p0, v0, co0 + 8 * cg);
+    const uint4 z1 = load8(dz, none, mask, p0 + 1, v1, co0 + 8 * cg);
+    const int sy0 = py + dy, sx0 = px + dx, sy1 = py1 + dy, sx1 = px1 + dx;
+    const bool i0 = v0 && sy0 >= 0 && sy0 < H && sx0 >= 0 && sx0 < W;
+    const bool i1 = v1 && sy1 >= 0 && sy1 < H && sx1 >= 0 && sx1 < W;
+    const uint4 xa = load8(x1, x2, none, ((int64_t)img * H + sy0) * W + sx0, i0, ci0 + 8 * cg);
+    const uint4 xb = load8(x1, x2, none, ((int64_t)img1 * H + sy1) * W + sx1, i1, ci0 + 8 * cg);
+    const uint32_t za[4] = {z0.x, z0.y, z0.z, z0.w}, zb[4] = {z1.x, z1.y, z1.z, z1.w};
+    const uint32_t xw0[4] = {xa.x, xa.y, xa.z, xa.w}, xw1[4] = {xb.x, xb.y, xb.z, xb.w};
     __syncthreads();
+    // transposed into [channel][pixel], two pixels per 32-bit write
+#pragma unroll
     for (int q = 0; q < 8; ++q) {
-      sA[(ch + q) * LDK + kl] = vz[q];
-      sB[(ch + q) * LDK + kl] = vx[q];
+      const int sh = 16 * (q & 1);
+      const uint32_t lo_z = (za[q >> 1] >> sh) & 0xFFFFu, hi_z = (zb[q >> 1] >> sh) & 0xFFFFu;
+      const uint32_t lo_x = (xw0[q >> 1] >> sh) & 0xFFFFu, hi_x = (xw1[q >> 1] >> sh) & 0xFFFFu;
+      *reinterpret_cast<uint32_t*>(&sA[(8 * cg + q) * WLDK + 2 * pp]) = lo_z | (hi_z << 16);
+      *reinterpret_cast<uint32_t*>(&sB[(8 * cg + q) * WLDK + 2 * pp]) = lo_x | (hi_x << 16);
+      if (do_bias) bacc[q] += bf2f((uint16_t)lo_z) + bf2f((uint16_t)hi_z);
     }
     __syncthreads();
-    if (do_bias && t < 64)
-      for (int k = 0; k < BK; ++k) bacc += bf2f(sA[t * LDK + k]);
-    bf16x8 a[2], b[2];
-    for (int i = 0; i < 2; ++i)
-      a[i] = *reinterpret_cast<const bf16x8*>(&sA[(wm + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
-    for (int j = 0; j < 2; ++j)
-      b[j] = *reinterpret_cast<const bf16x8*>(&sB[(wn + j * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
-    for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int ks = 0; ks < WBK / 32; ++ks) {
+      bf16x8 a[2], b[2];
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const bf16x8*>(
+            &sA[(wm + i * 16 + (lane & 15)) * WLDK + 32 * ks + 8 * (lane >> 4)]);
       for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        b[j] = *reinterpret_cast<const bf16x8*>(
+            &sB[(wn + j * 16 + (lane & 15)) * WLDK + 32 * ks + 8 * (lane >> 4)]);
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    // advance both coordinates by WBK pixels (WBK < W: at most one row wrap)
+    px += WBK;
+    while (px >= W) {
+      px -= W;
+      if (++py == H) {
+        py = 0;
+        ++img;
+      }
+    }
   }
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) {
@@ -229,7 +255,15 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
         unsafeAtomicAdd(&dw[((int64_t)tap * cout + co) * cin + ci], acc[i][j][r]);
       }
     }
-  if (do_bias && t < 64 && co0 + t < cout) unsafeAtomicAdd(&dbias[co0 + t], bacc);
+  if (do_bias) {   // block-uniform
+    for (int q = 0; q < 8; ++q) s_bias[8 * cg + q][pp] = bacc[q];
+    __syncthreads();
+    if (t < BM && co0 + t < cout) {
+      float sum = 0.f;
+      for (int k = 0; k < 32; ++k) sum += s_bias[t][k];
+      unsafeAtomicAdd(&dbias[co0 + t], sum);
+    }
+  }
 }
 
 // w [9][cout][cin] -> wt [9][cin][cout] with taps mirrored (backward data)
@@ -477,10 +511,16 @@ hipError_t nn_conv3x3_wgrad(const gs_act* x1, const gs_act* x2, const gs_act* dz
   const int cin = x1->c + (x2 ? x2->c : 0);
   const int cout = dz->c;
   const int64_t npix = (int64_t)x1->n * x1->h * x1->w;
+  // pixel chunks: enough workgroups to fill the chip, each long enough that
+  // its 4096 atomic adds into dw are few next to its MFMA work
+  const int64_t tiles = (int64_t)((cout + BM - 1) / BM) * 9 * ((cin + BN - 1) / BN);
+  const int64_t nk = std::max<int64_t>(1, kWgradBlocks / tiles);
+  int64_t kchunk = (npix + nk - 1) / nk;
+  kchunk = std::max<int64_t>(WBK, (kchunk + WBK - 1) / WBK * WBK);
   const dim3 grid((unsigned)((cout + BM - 1) / BM), (unsigned)(9 * ((cin + BN - 1) / BN)),
-                  blocks(npix, WG_KCHUNK));
+                  (unsigned)((npix + kchunk - 1) / kchunk));
   hipLaunchKernelGGL(conv3x3_wgrad_kernel, grid, dim3(256), 0, s, view(x1), view(x2), view(dz),
-                     view(mask), x1->n, x1->h, x1->w, cout, cin, dw, dbias);
+                     view(mask), x1->n, x1->h, x1->w, cout, cin, kchunk, dw, dbias);
   return hipGetLastError();
 }
 

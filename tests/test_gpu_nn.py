@@ -61,9 +61,19 @@ def test_conv3x3_forward(gs, case):
     np.testing.assert_array_equal(np_(ry.values()), expect)
 
 
-def test_conv3x3_backward(gs):
-    n, h, w, cin, cout = 1, 12, 10, 64, 32
-    rng = np.random.default_rng(7)
+BWD_CASES = [
+    # (n, h, w, cin1, cin2, cout)
+    (1, 12, 10, 64, 0, 32),     # rows narrower than one 64-pixel stage
+    (2, 9, 70, 32, 32, 96),     # two images, one row wrap per stage, skip concatenation
+    (1, 40, 96, 8, 0, 32),      # first-layer shape over many pixel chunks
+]
+
+
+@pytest.mark.parametrize("case", BWD_CASES)
+def test_conv3x3_backward(gs, case):
+    n, h, w, c1, c2, cout = case
+    cin = c1 + c2
+    rng = np.random.default_rng(7 + sum(case))
     x = _bf16(rng.normal(size=(n, h, w, cin)))
     wt = _bf16(rng.normal(size=(9, cout, cin)) / np.sqrt(9 * cin))
     y = _bf16(np.maximum(rng.normal(size=(n, h, w, cout)), 0.0))   # a ReLU output used as mask
@@ -76,7 +86,10 @@ def test_conv3x3_backward(gs):
     # weight and bias gradients
     dw = torch.zeros(9, cout, cin, device=DEV)
     db = torch.zeros(cout, device=DEV)
-    gs.gs_nn_conv3x3_wgrad(_act(gs, x), None, _act(gs, gy), _act(gs, y), dw, db)
+    # the input as one tensor, or as a skip concatenation of two
+    xa = _act(gs, x[..., :c1].contiguous()) if c2 else _act(gs, x)
+    xb = _act(gs, x[..., c1:].contiguous()) if c2 else None
+    gs.gs_nn_conv3x3_wgrad(xa, xb, _act(gs, gy), _act(gs, y), dw, db)
     torch.cuda.synchronize()
     xr = _f64(x).requires_grad_(True)
     wr = _f64(wt).requires_grad_(True)
