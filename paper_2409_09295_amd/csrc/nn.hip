@@ -77,59 +77,93 @@ __device__ __forceinline__ uint4 load8(const ActView& a, const ActView& b, const
   return v;
 }
 
+// Output tile of BMT pixels x BNT output channels; each of the four
+// wavefronts computes a (16 IM) x 32 block (IM x 2 MFMA tiles of 16 x 16).
+// K runs over 9 taps x cin in steps of BK = 32 channels; the next step's
+// global loads are issued before this step's MFMAs, so their latency hides
+// behind them.
+template <int BMT, int BNT, int IM>
 __global__ __launch_bounds__(256) void conv3x3_kernel(
     ActView x1, ActView x2, ActView mask, int N, int H, int W, const uint16_t* __restrict__ wk,
     int cout, int cin, const float* __restrict__ bias, int relu, uint16_t* __restrict__ y,
     int y_stride, int y_offset, float* __restrict__ yf, int yf_stride) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[BM * LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t sB[BN * LDK];
+  static_assert(BMT * BNT == 4 * 16 * IM * 32 && BNT % 32 == 0 && BMT % 64 == 0,
+                "four (16 IM) x 32 wavefront tiles");
+  constexpr int AR = BMT / 64;   // A rows (pixels) staged per thread
+  __shared__ __attribute__((aligned(16))) uint16_t sA[BMT * LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t sB[BNT * LDK];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t npix = (int64_t)N * H * W;
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
-  // loader coordinates: thread t stages row t / 4, channels 8 (t % 4) .. +8
-  const int lrow = t >> 2, lcol = (t & 3) * 8;
-  const int64_t lp = m0 + lrow;
-  int ly = 0, lx = 0, limg = 0;
-  if (lp < npix) {
-    limg = (int)(lp / ((int64_t)H * W));
-    const int rem = (int)(lp - (int64_t)limg * H * W);
-    ly = rem / W;
-    lx = rem - ly * W;
-  }
-  const int cin_pad = (cin + BK - 1) / BK * BK;
-  f32x4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
-  for (int tap = 0; tap < 9; ++tap) {
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    const int sy = ly + dy, sx = lx + dx;
-    const bool inb = lp < npix && sy >= 0 && sy < H && sx >= 0 && sx < W;
-    const int64_t spix = ((int64_t)limg * H + sy) * W + sx;
-    for (int c0 = 0; c0 < cin_pad; c0 += BK) {
-      __syncthreads();
-      *reinterpret_cast<uint4*>(&sA[lrow * LDK + lcol]) = load8(x1, x2, mask, spix, inb, c0 + lcol);
-      {
-        const int co = n0 + lrow, ci = c0 + lcol;
-        uint4 wv4 = make_uint4(0, 0, 0, 0);
-        if (co < cout && ci < cin)
-          wv4 = *reinterpret_cast<const uint4*>(wk + ((int64_t)tap * cout + co) * cin + ci);
-        *reinterpret_cast<uint4*>(&sB[lrow * LDK + lcol]) = wv4;
-      }
-      __syncthreads();
-      bf16x8 a[2], b[2];
-      for (int i = 0; i < 2; ++i)
-        a[i] = *reinterpret_cast<const bf16x8*>(&sA[(wm + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
-      for (int j = 0; j < 2; ++j)
-        b[j] = *reinterpret_cast<const bf16x8*>(&sB[(wn + j * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  const int64_t m0 = (int64_t)blockIdx.x * BMT;
+  const int n0 = blockIdx.y * BNT;
+  // loaders: thread t stages A rows (t / 4) + 64 u and B row t / 4 (when
+  // below BNT), channels 8 (t % 4) .. +8 of the step
+  const int lcol = (t & 3) * 8, lrow = t >> 2;
+  int ly[AR], lx[AR], limg[AR];
+  bool lok[AR];
+#pragma unroll
+  for (int u = 0; u < AR; ++u) {
+    const int64_t lp = m0 + lrow + 64 * u;
+    lok[u] = lp < npix;
+    limg[u] = ly[u] = lx[u] = 0;
+    if (lok[u]) {
+      limg[u] = (int)(lp / ((int64_t)H * W));
+      const int rem = (int)(lp - (int64_t)limg[u] * H * W);
+      ly[u] = rem / W;
+      lx[u] = rem - ly[u] * W;
     }
   }
+  const bool bload = lrow < BNT;
+  const int csteps = (cin + BK - 1) / BK;
+  const int nsteps = 9 * csteps;
+  uint4 ra[AR], rb;
+  auto fetch = [&](int step) {
+    const int tap = step / csteps, c0 = (step - tap * csteps) * BK;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+    for (int u = 0; u < AR; ++u) {
+      const int sy = ly[u] + dy, sx = lx[u] + dx;
+      const bool inb = lok[u] && sy >= 0 && sy < H && sx >= 0 && sx < W;
+      ra[u] = load8(x1, x2, mask, ((int64_t)limg[u] * H + sy) * W + sx, inb, c0 + lcol);
+    }
+    rb = make_uint4(0, 0, 0, 0);
+    const int co = n0 + lrow, ci = c0 + lcol;
+    if (bload && co < cout && ci < cin)
+      rb = *reinterpret_cast<const uint4*>(wk + ((int64_t)tap * cout + co) * cin + ci);
+  };
+  f32x4 acc[IM][2];
+#pragma unroll
+  for (int i = 0; i < IM; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  constexpr int WN = BNT / 32;   // wavefronts across the channels
+  const int wm = (wv % (4 / WN)) * 16 * IM, wn = (wv / (4 / WN)) * 32;
+  fetch(0);
+  for (int step = 0; step < nsteps; ++step) {
+    __syncthreads();   // the previous step's fragments have been read
+#pragma unroll
+    for (int u = 0; u < AR; ++u)
+      *reinterpret_cast<uint4*>(&sA[(lrow + 64 * u) * LDK + lcol]) = ra[u];
+    if (bload) *reinterpret_cast<uint4*>(&sB[lrow * LDK + lcol]) = rb;
+    __syncthreads();
+    if (step + 1 < nsteps) fetch(step + 1);
+    bf16x8 a[IM], b[2];
+#pragma unroll
+    for (int i = 0; i < IM; ++i)
+      a[i] = *reinterpret_cast<const bf16x8*>(&sA[(wm + i * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      b[j] = *reinterpret_cast<const bf16x8*>(&sB[(wn + j * 16 + (lane & 15)) * LDK + 8 * (lane >> 4)]);
+#pragma unroll
+    for (int i = 0; i < IM; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
   // epilogue: bias, ReLU, bf16 (or float32) store
-  for (int i = 0; i < 2; ++i)
+#pragma unroll
+  for (int i = 0; i < IM; ++i)
+#pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int co = n0 + wn + j * 16 + (lane & 15);
       if (co >= cout) continue;
@@ -190,8 +224,10 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
     py = rem / W;
     px = rem - py * W;
   }
-  for (int64_t k0 = kbeg; k0 < kend; k0 += WBK, p0 += WBK) {
-    // the thread's two pixels: (img, py, px) and the next one
+  // loads of the stage at p0 (the thread's two pixels: (img, py, px) and the
+  // next one); issued one stage ahead, before the MFMAs of the current one
+  uint4 z0, z1, xa, xb;
+  auto fetch = [&]() {
     int img1 = img, py1 = py, px1 = px + 1;
     if (px1 == W) {
       px1 = 0;
@@ -201,13 +237,26 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
       }
     }
     const bool v0 = p0 < kend, v1 = p0 + 1 < kend;
-    const uint4 z0 = load8(dz, none, mask, p0, v0, co0 + 8 * cg);
-    const uint4 z1 = load8(dz, none, mask, p0 + 1, v1, co0 + 8 * cg);
+    z0 = load8(dz, none, mask, p0, v0, co0 + 8 * cg);
+    z1 = load8(dz, none, mask, p0 + 1, v1, co0 + 8 * cg);
     const int sy0 = py + dy, sx0 = px + dx, sy1 = py1 + dy, sx1 = px1 + dx;
     const bool i0 = v0 && sy0 >= 0 && sy0 < H && sx0 >= 0 && sx0 < W;
     const bool i1 = v1 && sy1 >= 0 && sy1 < H && sx1 >= 0 && sx1 < W;
-    const uint4 xa = load8(x1, x2, none, ((int64_t)img * H + sy0) * W + sx0, i0, ci0 + 8 * cg);
-    const uint4 xb = load8(x1, x2, none, ((int64_t)img1 * H + sy1) * W + sx1, i1, ci0 + 8 * cg);
+    xa = load8(x1, x2, none, ((int64_t)img * H + sy0) * W + sx0, i0, ci0 + 8 * cg);
+    xb = load8(x1, x2, none, ((int64_t)img1 * H + sy1) * W + sx1, i1, ci0 + 8 * cg);
+    // advance to the next stage (WBK pixels on; rows may be narrower)
+    p0 += WBK;
+    px += WBK;
+    while (px >= W) {
+      px -= W;
+      if (++py == H) {
+        py = 0;
+        ++img;
+      }
+    }
+  };
+  fetch();
+  for (int64_t k0 = kbeg; k0 < kend; k0 += WBK) {
     const uint32_t za[4] = {z0.x, z0.y, z0.z, z0.w}, zb[4] = {z1.x, z1.y, z1.z, z1.w};
     const uint32_t xw0[4] = {xa.x, xa.y, xa.z, xa.w}, xw1[4] = {xb.x, xb.y, xb.z, xb.w};
     __syncthreads();
@@ -222,6 +271,7 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
       if (do_bias) bacc[q] += bf2f((uint16_t)lo_z) + bf2f((uint16_t)hi_z);
     }
     __syncthreads();
+    if (k0 + WBK < kend) fetch();
 #pragma unroll
     for (int ks = 0; ks < WBK / 32; ++ks) {
       bf16x8 a[2], b[2];
@@ -234,15 +284,6 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
       for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    // advance both coordinates by WBK pixels (WBK < W: at most one row wrap)
-    px += WBK;
-    while (px >= W) {
-      px -= W;
-      if (++py == H) {
-        py = 0;
-        ++img;
-      }
     }
   }
   for (int i = 0; i < 2; ++i)
@@ -498,11 +539,34 @@ hipError_t nn_conv3x3(const gs_act* x1, const gs_act* x2, const gs_act* mask, co
                       hipStream_t s) {
   const int cin = x1->c + (x2 ? x2->c : 0);
   const int64_t npix = (int64_t)x1->n * x1->h * x1->w;
-  const dim3 grid(blocks(npix, BM), (unsigned)((cout + BN - 1) / BN));
-  hipLaunchKernelGGL(conv3x3_kernel, grid, dim3(256), 0, s, view(x1), view(x2), view(mask),
-                     x1->n, x1->h, x1->w, static_cast<const uint16_t*>(w), cout, cin, bias, relu,
-                     y ? static_cast<uint16_t*>(y->data) : nullptr, y ? y->stride : 0,
-                     y ? y->offset : 0, yf, yf_stride);
+  // Tiles: up to 32 output channels, 32-channel tiles (a 64-channel tile
+  // would spend half its MFMAs on channels that do not exist); 64 x 32
+  // wavefront blocks while that still gives about 1,024 workgroups, else
+  // 32 x 32 ones (twice the workgroups for the small deep layers).
+  auto* yp = y ? static_cast<uint16_t*>(y->data) : nullptr;
+  const int ys = y ? y->stride : 0, yo = y ? y->offset : 0;
+  const auto* wp = static_cast<const uint16_t*>(w);
+  const unsigned ntile = (unsigned)((cout + 63) / 64);
+  // (the masked backward-data calls measured faster with the small tiles)
+  const bool narrow = cout <= 32 && mask == nullptr;
+  const bool big = mask == nullptr &&
+                   (int64_t)blocks(npix, narrow ? 256 : 128) * (narrow ? 1 : ntile) >= 1024;
+  if (narrow && big)
+    hipLaunchKernelGGL((conv3x3_kernel<256, 32, 4>), dim3(blocks(npix, 256), 1), dim3(256), 0, s,
+                       view(x1), view(x2), view(mask), x1->n, x1->h, x1->w, wp, cout, cin, bias,
+                       relu, yp, ys, yo, yf, yf_stride);
+  else if (narrow)
+    hipLaunchKernelGGL((conv3x3_kernel<128, 32, 2>), dim3(blocks(npix, 128), 1), dim3(256), 0, s,
+                       view(x1), view(x2), view(mask), x1->n, x1->h, x1->w, wp, cout, cin, bias,
+                       relu, yp, ys, yo, yf, yf_stride);
+  else if (big)
+    hipLaunchKernelGGL((conv3x3_kernel<128, 64, 4>), dim3(blocks(npix, 128), ntile), dim3(256), 0,
+                       s, view(x1), view(x2), view(mask), x1->n, x1->h, x1->w, wp, cout, cin, bias,
+                       relu, yp, ys, yo, yf, yf_stride);
+  else
+    hipLaunchKernelGGL((conv3x3_kernel<64, 64, 2>), dim3(blocks(npix, 64), ntile), dim3(256), 0,
+                       s, view(x1), view(x2), view(mask), x1->n, x1->h, x1->w, wp, cout, cin, bias,
+                       relu, yp, ys, yo, yf, yf_stride);
   return hipGetLastError();
 }
 
