@@ -340,42 +340,72 @@ __global__ void avgpool2_kernel(ActView x, int N, int H, int W, uint16_t* __rest
 }
 
 // dx[p][c] (+)= dy[pool(p)][c] / 4 (dx may be a channel slice; accumulate adds)
+__device__ __forceinline__ void unpack8(uint4 u, float* v) {
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+  for (int k = 0; k < 4; ++k) {
+    v[2 * k] = bf2f((uint16_t)(w[k] & 0xFFFFu));
+    v[2 * k + 1] = bf2f((uint16_t)(w[k] >> 16));
+  }
+}
+
+__device__ __forceinline__ uint4 pack8(const float* v) {
+  uint32_t w[4];
+  for (int k = 0; k < 4; ++k) w[k] = (uint32_t)f2bf(v[2 * k]) | ((uint32_t)f2bf(v[2 * k + 1]) << 16);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// 8 channels per thread (see upsample2_kernel)
 __global__ void avgpool2_bwd_kernel(ActView dy, int N, int H, int W, uint16_t* __restrict__ dx,
                                     int dx_stride, int dx_offset, int accumulate,
                                     const uint16_t* __restrict__ add_src, int add_stride,
                                     int add_offset) {
+  const int c8n = dy.c / 8;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)N * H * W * dy.c;
+  const int64_t total = (int64_t)N * H * W * c8n;
   if (i >= total) return;
-  const int c = (int)(i % dy.c);
-  const int64_t p = i / dy.c;
+  const int c = (int)(i % c8n) * 8;
+  const int64_t p = i / c8n;
   const int n = (int)(p / ((int64_t)H * W));
   const int r = (int)(p - (int64_t)n * H * W);
   const int yy = r / W, xx = r % W;
   const int Ho = H / 2, Wo = W / 2;
-  float v = 0.f;
+  float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (yy / 2 < Ho && xx / 2 < Wo) {
     const int64_t q = ((int64_t)n * Ho + yy / 2) * Wo + xx / 2;
-    v = 0.25f * bf2f(dy.p[q * dy.stride + dy.offset + c]);
+    unpack8(*reinterpret_cast<const uint4*>(dy.p + q * dy.stride + dy.offset + c), v);
+    for (int k = 0; k < 8; ++k) v[k] *= 0.25f;
   }
-  if (add_src) v += bf2f(add_src[p * add_stride + add_offset + c]);
-  uint16_t* o = dx + p * dx_stride + dx_offset + c;
-  *o = f2bf(accumulate ? bf2f(*o) + v : v);
+  if (add_src) {
+    float a[8];
+    unpack8(*reinterpret_cast<const uint4*>(add_src + p * add_stride + add_offset + c), a);
+    for (int k = 0; k < 8; ++k) v[k] += a[k];
+  }
+  uint4* o = reinterpret_cast<uint4*>(dx + p * dx_stride + dx_offset + c);
+  if (accumulate) {
+    float cur[8];
+    unpack8(*o, cur);
+    for (int k = 0; k < 8; ++k) v[k] = cur[k] + v[k];
+  }
+  *o = pack8(v);
 }
 
+// 8 channels (16 bytes) per thread; channel counts, strides and offsets are
+// multiples of 8.
 __global__ void upsample2_kernel(ActView x, int N, int H, int W, uint16_t* __restrict__ y,
                                  int y_stride, int y_offset) {
   // x is (H/2) x (W/2); y is H x W
+  const int c8n = x.c / 8;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)N * H * W * x.c;
+  const int64_t total = (int64_t)N * H * W * c8n;
   if (i >= total) return;
-  const int c = (int)(i % x.c);
-  const int64_t p = i / x.c;
+  const int c = (int)(i % c8n) * 8;
+  const int64_t p = i / c8n;
   const int n = (int)(p / ((int64_t)H * W));
   const int r = (int)(p - (int64_t)n * H * W);
   const int yy = r / W, xx = r % W;
   const int64_t q = ((int64_t)n * (H / 2) + yy / 2) * (W / 2) + xx / 2;
-  y[p * y_stride + y_offset + c] = x.p[q * x.stride + x.offset + c];
+  *reinterpret_cast<uint4*>(y + p * y_stride + y_offset + c) =
+      *reinterpret_cast<const uint4*>(x.p + q * x.stride + x.offset + c);
 }
 
 __global__ void upsample2_bwd_kernel(ActView dy, int N, int H, int W, uint16_t* __restrict__ dx,
@@ -439,35 +469,73 @@ __global__ void head_fwd_kernel(ActView f, int N, int H, int W, const float* __r
 
 // Head backward: dF[p][c] = sum_k w[k][c] dout[k][p] masked by the feature's
 // ReLU (f > 0); dW, db accumulated with per-block reductions and atomics.
+// Threads (channel lane t % 32, pixel group t / 32): each thread walks every
+// eighth pixel of the workgroup's 256-pixel chunks (grid-stride), handling
+// channels t % 32 + 32 k; the weight and bias partials stay in registers and
+// are reduced over the eight groups once per workgroup.
+constexpr int kHeadMaxSlots = 2;   // channels per thread: up to 64 feature channels (the C ABI limit)
+
 __global__ __launch_bounds__(256) void head_bwd_kernel(ActView f, int N, int H, int W,
                                                        const float* __restrict__ w,
                                                        const float* __restrict__ dout,
                                                        uint16_t* __restrict__ df, int df_stride,
                                                        float* __restrict__ dw,
                                                        float* __restrict__ db) {
-  __shared__ float s_dw[2 * 64 + 2];
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float s_red[8][2 * 32 * kHeadMaxSlots + 2];
+  const int t = threadIdx.x, cl = t & 31, pg = t >> 5;
   const int64_t npix = (int64_t)N * H * W;
-  for (int k = threadIdx.x; k < 2 * f.c + 2; k += blockDim.x) s_dw[k] = 0.f;
-  __syncthreads();
-  if (p < npix) {
-    const int n = (int)(p / ((int64_t)H * W));
-    const int64_t r = p - (int64_t)n * H * W;
-    const float g0 = dout[((int64_t)n * 2 + 0) * H * W + r];
-    const float g1 = dout[((int64_t)n * 2 + 1) * H * W + r];
-    atomicAdd(&s_dw[2 * f.c], g0);
-    atomicAdd(&s_dw[2 * f.c + 1], g1);
-    for (int c = 0; c < f.c; ++c) {
-      const float v = bf2f(f.p[p * f.stride + f.offset + c]);
-      atomicAdd(&s_dw[c], g0 * v);
-      atomicAdd(&s_dw[f.c + c], g1 * v);
-      const float d = v > 0.f ? (w[c] * g0 + w[f.c + c] * g1) : 0.f;
-      df[p * df_stride + c] = f2bf(d);
+  const int64_t hw = (int64_t)H * W;
+  const int slots = (f.c + 31) / 32;
+  float a0[kHeadMaxSlots], a1[kHeadMaxSlots], w0[kHeadMaxSlots], w1[kHeadMaxSlots];
+  for (int k = 0; k < kHeadMaxSlots; ++k) {
+    a0[k] = a1[k] = 0.f;
+    const int c = cl + 32 * k;
+    w0[k] = (k < slots && c < f.c) ? w[c] : 0.f;
+    w1[k] = (k < slots && c < f.c) ? w[f.c + c] : 0.f;
+  }
+  float b0 = 0.f, b1 = 0.f;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < npix; base += (int64_t)gridDim.x * 256) {
+    for (int j = pg; j < 256; j += 8) {
+      const int64_t p = base + j;
+      if (p >= npix) break;
+      const int n = (int)(p / hw);
+      const int64_t r = p - (int64_t)n * hw;
+      const float g0 = dout[((int64_t)n * 2 + 0) * hw + r];
+      const float g1 = dout[((int64_t)n * 2 + 1) * hw + r];
+      if (cl == 0) {
+        b0 += g0;
+        b1 += g1;
+      }
+      for (int k = 0; k < kHeadMaxSlots; ++k) {
+        const int c = cl + 32 * k;
+        if (k >= slots || c >= f.c) break;
+        const float v = bf2f(f.p[p * f.stride + f.offset + c]);
+        a0[k] += g0 * v;
+        a1[k] += g1 * v;
+        df[p * df_stride + c] = f2bf(v > 0.f ? (w0[k] * g0 + w1[k] * g1) : 0.f);
+      }
     }
   }
+  for (int k = 0; k < kHeadMaxSlots; ++k) {
+    s_red[pg][32 * k + cl] = a0[k];
+    s_red[pg][32 * kHeadMaxSlots + 32 * k + cl] = a1[k];
+  }
+  if (cl == 0) {
+    s_red[pg][64 * kHeadMaxSlots] = b0;
+    s_red[pg][64 * kHeadMaxSlots + 1] = b1;
+  }
   __syncthreads();
-  for (int k = threadIdx.x; k < 2 * f.c; k += blockDim.x) unsafeAtomicAdd(&dw[k], s_dw[k]);
-  if (threadIdx.x < 2) unsafeAtomicAdd(&db[threadIdx.x], s_dw[2 * f.c + threadIdx.x]);
+  for (int k = t; k < 2 * f.c + 2; k += 256) {
+    // k < f.c: dw row 0; f.c <= k < 2 f.c: dw row 1; then the two biases
+    const int col = k < f.c ? k : k < 2 * f.c ? 32 * kHeadMaxSlots + (k - f.c)
+                                              : 64 * kHeadMaxSlots + (k - 2 * f.c);
+    float sum = 0.f;
+    for (int g = 0; g < 8; ++g) sum += s_red[g][col];
+    if (k < 2 * f.c)
+      unsafeAtomicAdd(&dw[k], sum);
+    else
+      unsafeAtomicAdd(&db[k - 2 * f.c], sum);
+  }
 }
 
 // Depth supervision: pred [N][2][H][W] = (log depth, log scale); target depth
@@ -603,7 +671,7 @@ hipError_t nn_avgpool2(const gs_act* x, gs_act* y, hipStream_t s) {
 
 hipError_t nn_avgpool2_bwd(const gs_act* dy, const gs_act* add, gs_act* dx, int accumulate,
                            hipStream_t s) {
-  const int64_t total = (int64_t)dx->n * dx->h * dx->w * dy->c;
+  const int64_t total = (int64_t)dx->n * dx->h * dx->w * (dy->c / 8);
   hipLaunchKernelGGL(avgpool2_bwd_kernel, dim3(blocks(total)), dim3(256), 0, s, view(dy), dx->n,
                      dx->h, dx->w, static_cast<uint16_t*>(dx->data), dx->stride, dx->offset,
                      accumulate, add ? static_cast<const uint16_t*>(add->data) : nullptr,
@@ -612,7 +680,7 @@ hipError_t nn_avgpool2_bwd(const gs_act* dy, const gs_act* add, gs_act* dx, int 
 }
 
 hipError_t nn_upsample2(const gs_act* x, gs_act* y, hipStream_t s) {
-  const int64_t total = (int64_t)y->n * y->h * y->w * x->c;
+  const int64_t total = (int64_t)y->n * y->h * y->w * (x->c / 8);
   hipLaunchKernelGGL(upsample2_kernel, dim3(blocks(total)), dim3(256), 0, s, view(x), y->n, y->h,
                      y->w, static_cast<uint16_t*>(y->data), y->stride, y->offset);
   return hipGetLastError();
@@ -649,7 +717,9 @@ hipError_t nn_head(const gs_act* f, const float* w, const float* b, float* out, 
 hipError_t nn_head_bwd(const gs_act* f, const float* w, const float* dout, gs_act* df, float* dw,
                        float* db, hipStream_t s) {
   const int64_t npix = (int64_t)f->n * f->h * f->w;
-  hipLaunchKernelGGL(head_bwd_kernel, dim3(blocks(npix)), dim3(256), 0, s, view(f), f->n, f->h,
+  if (f->c > 32 * kHeadMaxSlots) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(head_bwd_kernel, dim3(std::min<unsigned>(blocks(npix), 1024u)), dim3(256), 0,
+                     s, view(f), f->n, f->h,
                      f->w, w, dout, static_cast<uint16_t*>(df->data) + df->offset, df->stride, dw,
                      db);
   return hipGetLastError();

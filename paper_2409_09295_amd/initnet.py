@@ -225,6 +225,35 @@ class UNet:
 # data: renders of the map with their depth
 # ---------------------------------------------------------------------------
 
+def conv_throughput(n: int = 4, h: int = 480, w: int = 640, reps: int = 5, seed: int = 0) -> dict:
+    """Forward and forward + backward time of the U-Net on n random h x w
+    images (HIP events around each pass), with the convolutions' rate:
+    forward flops as counted by unet_flops, backward twice that (data and
+    weight gradients)."""
+    net = UNet(seed=seed)
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    rgb = torch.rand(n, 3, h, w, device="cuda", generator=g)
+    dpred = torch.randn(n, 2, h, w, device="cuda", generator=g) * 1e-3
+    net.forward(rgb)
+    net.backward(dpred)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd = bwd = 0.0
+    for _ in range(reps):
+        ev[0].record()
+        net.forward(rgb)
+        ev[1].record()
+        net.backward(dpred)
+        ev[2].record()
+        torch.cuda.synchronize()
+        fwd += ev[0].elapsed_time(ev[1]) / reps
+        bwd += ev[1].elapsed_time(ev[2]) / reps
+    fl = unet_flops(h, w) * n
+    return {"images": n, "height": h, "width": w, "fwd_ms": fwd, "bwd_ms": bwd,
+            "fwd_tflops": fl / (fwd * 1e-3) / 1e12,
+            "fwd_bwd_tflops": 3 * fl / ((fwd + bwd) * 1e-3) / 1e12}
+
+
 def render_dataset(gmap: scenes.GaussianMap, cams: Sequence[scenes.Camera], batch: int = 16,
                    device="cuda") -> Tuple[torch.Tensor, torch.Tensor]:
     """(rgb [n, 3, h, w], depth [n, h, w]) rendered by the rasterizer; depth
