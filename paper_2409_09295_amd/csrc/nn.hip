@@ -319,27 +319,6 @@ __global__ void flip_weights_kernel(const uint16_t* __restrict__ w, int cout, in
   wt[((int64_t)(8 - tap) * cin + ci) * cout + co] = w[i];
 }
 
-__global__ void avgpool2_kernel(ActView x, int N, int H, int W, uint16_t* __restrict__ y,
-                                int y_stride) {
-  const int Ho = H / 2, Wo = W / 2;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)N * Ho * Wo * x.c;
-  if (i >= total) return;
-  const int c = (int)(i % x.c);
-  const int64_t q = i / x.c;
-  const int n = (int)(q / ((int64_t)Ho * Wo));
-  const int r = (int)(q - (int64_t)n * Ho * Wo);
-  const int yo = r / Wo, xo = r % Wo;
-  float s = 0.f;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      const int64_t p = ((int64_t)n * H + 2 * yo + a) * W + 2 * xo + b;
-      s += bf2f(x.p[p * x.stride + x.offset + c]);
-    }
-  y[q * y_stride + c] = f2bf(0.25f * s);
-}
-
-// dx[p][c] (+)= dy[pool(p)][c] / 4 (dx may be a channel slice; accumulate adds)
 __device__ __forceinline__ void unpack8(uint4 u, float* v) {
   const uint32_t w[4] = {u.x, u.y, u.z, u.w};
   for (int k = 0; k < 4; ++k) {
@@ -354,6 +333,32 @@ __device__ __forceinline__ uint4 pack8(const float* v) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// 8 channels per thread (channel counts, strides and offsets are multiples of 8)
+__global__ void avgpool2_kernel(ActView x, int N, int H, int W, uint16_t* __restrict__ y,
+                                int y_stride) {
+  const int Ho = H / 2, Wo = W / 2;
+  const int c8n = x.c / 8;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)N * Ho * Wo * c8n;
+  if (i >= total) return;
+  const int c = (int)(i % c8n) * 8;
+  const int64_t q = i / c8n;
+  const int n = (int)(q / ((int64_t)Ho * Wo));
+  const int r = (int)(q - (int64_t)n * Ho * Wo);
+  const int yo = r / Wo, xo = r % Wo;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int64_t p = ((int64_t)n * H + 2 * yo + a) * W + 2 * xo + b;
+      float v[8];
+      unpack8(*reinterpret_cast<const uint4*>(x.p + p * x.stride + x.offset + c), v);
+      for (int k = 0; k < 8; ++k) s[k] += v[k];
+    }
+  for (int k = 0; k < 8; ++k) s[k] *= 0.25f;
+  *reinterpret_cast<uint4*>(y + q * y_stride + c) = pack8(s);
+}
+
+// dx[p][c] (+)= dy[pool(p)][c] / 4 (dx may be a channel slice; accumulate adds)
 // 8 channels per thread (see upsample2_kernel)
 __global__ void avgpool2_bwd_kernel(ActView dy, int N, int H, int W, uint16_t* __restrict__ dx,
                                     int dx_stride, int dx_offset, int accumulate,
@@ -408,25 +413,29 @@ __global__ void upsample2_kernel(ActView x, int N, int H, int W, uint16_t* __res
       *reinterpret_cast<const uint4*>(x.p + q * x.stride + x.offset + c);
 }
 
+// 8 channels per thread (see avgpool2_kernel)
 __global__ void upsample2_bwd_kernel(ActView dy, int N, int H, int W, uint16_t* __restrict__ dx,
                                      int dx_stride) {
   // dy is H x W, dx is (H/2) x (W/2): dx = sum of the 2x2 block
   const int Ho = H / 2, Wo = W / 2;
+  const int c8n = dy.c / 8;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)N * Ho * Wo * dy.c;
+  const int64_t total = (int64_t)N * Ho * Wo * c8n;
   if (i >= total) return;
-  const int c = (int)(i % dy.c);
-  const int64_t q = i / dy.c;
+  const int c = (int)(i % c8n) * 8;
+  const int64_t q = i / c8n;
   const int n = (int)(q / ((int64_t)Ho * Wo));
   const int r = (int)(q - (int64_t)n * Ho * Wo);
   const int yo = r / Wo, xo = r % Wo;
-  float s = 0.f;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) {
       const int64_t p = ((int64_t)n * H + 2 * yo + a) * W + 2 * xo + b;
-      s += bf2f(dy.p[p * dy.stride + dy.offset + c]);
+      float v[8];
+      unpack8(*reinterpret_cast<const uint4*>(dy.p + p * dy.stride + dy.offset + c), v);
+      for (int k = 0; k < 8; ++k) s[k] += v[k];
     }
-  dx[q * dx_stride + c] = f2bf(s);
+  *reinterpret_cast<uint4*>(dx + q * dx_stride + c) = pack8(s);
 }
 
 // planar float32 RGB [N][3][H][W] -> NHWC bf16 with `stride` channels (zero padded)
@@ -663,7 +672,7 @@ hipError_t nn_flip_weights(const void* w, int cout, int cin, void* wt, hipStream
 }
 
 hipError_t nn_avgpool2(const gs_act* x, gs_act* y, hipStream_t s) {
-  const int64_t total = (int64_t)x->n * (x->h / 2) * (x->w / 2) * x->c;
+  const int64_t total = (int64_t)x->n * (x->h / 2) * (x->w / 2) * (x->c / 8);
   hipLaunchKernelGGL(avgpool2_kernel, dim3(blocks(total)), dim3(256), 0, s, view(x), x->n, x->h,
                      x->w, static_cast<uint16_t*>(y->data) + y->offset, y->stride);
   return hipGetLastError();
@@ -687,7 +696,7 @@ hipError_t nn_upsample2(const gs_act* x, gs_act* y, hipStream_t s) {
 }
 
 hipError_t nn_upsample2_bwd(const gs_act* dy, gs_act* dx, hipStream_t s) {
-  const int64_t total = (int64_t)dx->n * dx->h * dx->w * dy->c;
+  const int64_t total = (int64_t)dx->n * dx->h * dx->w * (dy->c / 8);
   hipLaunchKernelGGL(upsample2_bwd_kernel, dim3(blocks(total)), dim3(256), 0, s, view(dy), dy->n,
                      dy->h, dy->w, static_cast<uint16_t*>(dx->data) + dx->offset, dx->stride);
   return hipGetLastError();
