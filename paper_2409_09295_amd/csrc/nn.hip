@@ -47,6 +47,18 @@ struct ActView {
   int32_t c, stride, offset;
 };
 
+// Zeroes the bf16 elements of v whose mask element is <= 0.
+__device__ __forceinline__ uint4 apply_mask8(uint4 v, uint4 mk) {
+  const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
+  uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t lo = (int16_t)(mw[q] & 0xFFFF) > 0 ? 0xFFFFu : 0u;   // bf16 > 0 <=> int16 > 0
+    const uint32_t hi = (int16_t)(mw[q] >> 16) > 0 ? 0xFFFF0000u : 0u;
+    vw[q] &= (lo | hi);
+  }
+  return make_uint4(vw[0], vw[1], vw[2], vw[3]);
+}
+
 // Loads 8 consecutive channels [c0, c0 + 8) of pixel (n, y, x) from a
 // two-source channel concatenation; zero outside the image or beyond the
 // channel count.  mask (optional, same layout as the concatenation) zeroes
@@ -65,14 +77,7 @@ __device__ __forceinline__ uint4 load8(const ActView& a, const ActView& b, const
   v = *reinterpret_cast<const uint4*>(s->p + pix * s->stride + s->offset + c);
   if (m.p) {
     const uint4 mk = *reinterpret_cast<const uint4*>(m.p + pix * m.stride + m.offset + c0);
-    const uint32_t mw[4] = {mk.x, mk.y, mk.z, mk.w};
-    uint32_t vw[4] = {v.x, v.y, v.z, v.w};
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t lo = (int16_t)(mw[q] & 0xFFFF) > 0 ? 0xFFFFu : 0u;   // bf16 > 0 <=> int16 > 0
-      const uint32_t hi = (int16_t)(mw[q] >> 16) > 0 ? 0xFFFF0000u : 0u;
-      vw[q] &= (lo | hi);
-    }
-    v = make_uint4(vw[0], vw[1], vw[2], vw[3]);
+    v = apply_mask8(v, mk);
   }
   return v;
 }
@@ -189,6 +194,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(
 constexpr int WBK = 64;              // pixels per stage
 constexpr int WLDK = WBK + 8;        // LDS row pitch in bf16 (16-byte aligned rows)
 constexpr int kWgradBlocks = 1024;   // pixel chunks are sized for about this many workgroups
+constexpr int kWgrad32Blocks = 512;  // the narrow kernel: two resident workgroups per CU
 
 
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
@@ -304,6 +310,179 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
       for (int k = 0; k < 32; ++k) sum += s_bias[t][k];
       unsafeAtomicAdd(&dbias[co0 + t], sum);
     }
+  }
+}
+
+// Narrow weight gradient (cout <= 32): a 32 x 32 channel tile for one row
+// of three taps (dy fixed, dx = -1, 0, 1), so each stage's dz and mask loads
+// serve three taps.  The four wavefronts split the workgroup's pixels (wave
+// w takes every fourth 64-pixel stage), each staging through its own LDS
+// region, so only wave-level ordering is needed; the four partial tiles are
+// summed once at the end.  Lane l stages pixels 2 (l % 32), 2 (l % 32) + 1
+// and channel groups (l / 32) + 2 g, g = 0, 1, of dz and of the three
+// shifted inputs.
+__global__ __launch_bounds__(256) void conv3x3_wgrad32_kernel(
+    ActView x1, ActView x2, ActView dz, ActView mask, int N, int H, int W, int cout, int cin,
+    int64_t kchunk, float* __restrict__ dw, float* __restrict__ dbias) {
+  __shared__ __attribute__((aligned(16))) union {
+    struct {
+      uint16_t a[4][32 * WLDK];      // per wave [co][pixel]
+      uint16_t b[4][3][32 * WLDK];   // per wave and tap [ci][pixel]
+    } st;
+    float red[4][3][32][33];         // after the pixel loop: the four waves' tiles
+  } sm;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int64_t npix = (int64_t)N * H * W;
+  const int row = blockIdx.y % 3;
+  const int ci0 = (blockIdx.y / 3) * 32;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = min(npix, kbeg + kchunk);
+  const int dy = row - 1;
+  const bool do_bias = dbias != nullptr && row == 1 && ci0 == 0;
+  const int pp = lane & 31, gh = lane >> 5;
+  const ActView none = {nullptr, 0, 0, 0};
+  f32x4 acc[3][2][2];
+  for (int u = 0; u < 3; ++u)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) acc[u][i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  float bacc[16];
+  for (int q = 0; q < 16; ++q) bacc[q] = 0.f;
+  uint16_t* a_s = sm.st.a[wv];
+  const bool masked = mask.p != nullptr;
+  // image coordinates of the lane's first pixel, advanced by 4 WBK pixels
+  // per stage (the stride of one wavefront)
+  int64_t p0 = kbeg + (int64_t)wv * WBK + 2 * pp;
+  int img = 0, py = 0, px = 0;
+  if (p0 < npix) {
+    img = (int)(p0 / ((int64_t)H * W));
+    const int rem = (int)(p0 - (int64_t)img * H * W);
+    py = rem / W;
+    px = rem - py * W;
+  }
+  // [pixel][group] ([tap][pixel][group] for the input), loaded one stage
+  // ahead; the mask is applied when the stage is written to LDS, so no load
+  // waits on another
+  uint4 z[2][2], zm[2][2], xv[3][2][2];
+  auto fetch = [&]() {
+    int img1 = img, py1 = py, px1 = px + 1;
+    if (px1 == W) {
+      px1 = 0;
+      if (++py1 == H) {
+        py1 = 0;
+        ++img1;
+      }
+    }
+    const bool v0 = p0 < kend, v1 = p0 + 1 < kend;
+    const int sy0 = py + dy, sy1 = py1 + dy;
+    const bool r0 = v0 && sy0 >= 0 && sy0 < H, r1 = v1 && sy1 >= 0 && sy1 < H;
+    const int64_t row0 = ((int64_t)img * H + sy0) * W, row1 = ((int64_t)img1 * H + sy1) * W;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int cg = gh + 2 * g;   // channel group 0..3
+      z[0][g] = load8(dz, none, none, p0, v0, 8 * cg);
+      z[1][g] = load8(dz, none, none, p0 + 1, v1, 8 * cg);
+      if (masked) {
+        zm[0][g] = load8(mask, none, none, p0, v0, 8 * cg);
+        zm[1][g] = load8(mask, none, none, p0 + 1, v1, 8 * cg);
+      }
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int sx0 = px + u - 1, sx1 = px1 + u - 1;
+        xv[u][0][g] = load8(x1, x2, none, row0 + sx0, r0 && sx0 >= 0 && sx0 < W, ci0 + 8 * cg);
+        xv[u][1][g] = load8(x1, x2, none, row1 + sx1, r1 && sx1 >= 0 && sx1 < W, ci0 + 8 * cg);
+      }
+    }
+    p0 += 4 * WBK;
+    px += 4 * WBK;
+    while (px >= W) {
+      px -= W;
+      if (++py == H) {
+        py = 0;
+        ++img;
+      }
+    }
+  };
+  fetch();
+  for (int64_t k0 = kbeg + (int64_t)wv * WBK; k0 < kend; k0 += 4 * WBK) {
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int cg = gh + 2 * g;
+      const uint4 z0 = masked ? apply_mask8(z[0][g], zm[0][g]) : z[0][g];
+      const uint4 z1 = masked ? apply_mask8(z[1][g], zm[1][g]) : z[1][g];
+      const uint32_t za[4] = {z0.x, z0.y, z0.z, z0.w};
+      const uint32_t zb[4] = {z1.x, z1.y, z1.z, z1.w};
+      // transposed into [channel][pixel], two pixels per 32-bit write
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int sh = 16 * (q & 1);
+        const uint32_t lo_z = (za[q >> 1] >> sh) & 0xFFFFu, hi_z = (zb[q >> 1] >> sh) & 0xFFFFu;
+        *reinterpret_cast<uint32_t*>(&a_s[(8 * cg + q) * WLDK + 2 * pp]) = lo_z | (hi_z << 16);
+        if (do_bias) bacc[8 * g + q] += bf2f((uint16_t)lo_z) + bf2f((uint16_t)hi_z);
+      }
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const uint32_t xa[4] = {xv[u][0][g].x, xv[u][0][g].y, xv[u][0][g].z, xv[u][0][g].w};
+        const uint32_t xb[4] = {xv[u][1][g].x, xv[u][1][g].y, xv[u][1][g].z, xv[u][1][g].w};
+        uint16_t* b_s = sm.st.b[wv][u];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int sh = 16 * (q & 1);
+          const uint32_t lo_x = (xa[q >> 1] >> sh) & 0xFFFFu, hi_x = (xb[q >> 1] >> sh) & 0xFFFFu;
+          *reinterpret_cast<uint32_t*>(&b_s[(8 * cg + q) * WLDK + 2 * pp]) = lo_x | (hi_x << 16);
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    if (k0 + 4 * WBK < kend) fetch();
+#pragma unroll
+    for (int ks = 0; ks < WBK / 32; ++ks) {
+      bf16x8 a[2];
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const bf16x8*>(&a_s[(i * 16 + (lane & 15)) * WLDK + 32 * ks + 8 * (lane >> 4)]);
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const uint16_t* b_s = sm.st.b[wv][u];
+        bf16x8 b[2];
+        for (int j = 0; j < 2; ++j)
+          b[j] = *reinterpret_cast<const bf16x8*>(&b_s[(j * 16 + (lane & 15)) * WLDK + 32 * ks + 8 * (lane >> 4)]);
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j)
+            acc[u][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[u][i][j], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();   // fragments read before the next stage's writes
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+  // sum the four wavefronts' tiles: red[w][u][co][ci] (over the staging buffers)
+  __syncthreads();
+  float(*s_red)[3][32][33] = sm.red;
+  for (int u = 0; u < 3; ++u)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int r = 0; r < 4; ++r)
+          s_red[wv][u][i * 16 + 4 * (lane >> 4) + r][j * 16 + (lane & 15)] = acc[u][i][j][r];
+  __syncthreads();
+  for (int e = t; e < 3 * 32 * 32; e += 256) {
+    const int u = e >> 10, co = (e >> 5) & 31, ci = e & 31;
+    if (co >= cout || ci0 + ci >= cin) continue;
+    const float v = s_red[0][u][co][ci] + s_red[1][u][co][ci] + s_red[2][u][co][ci] + s_red[3][u][co][ci];
+    unsafeAtomicAdd(&dw[((int64_t)(3 * row + u) * cout + co) * cin + ci0 + ci], v);
+  }
+  if (do_bias) {   // block-uniform
+    __syncthreads();   // s_red is reused for the per-wave channel sums
+    float* sb = &s_red[0][0][0][0];
+    for (int q = 0; q < 16; ++q) {
+      float v = bacc[q];
+      for (int d = 1; d < 32; d <<= 1) v += __shfl_xor(v, d, 64);   // over the 32 pixel pairs
+      bacc[q] = v;
+    }
+    if (pp == 0)
+      for (int g = 0; g < 2; ++g)
+        for (int q = 0; q < 8; ++q) sb[wv * 32 + 8 * (gh + 2 * g) + q] = bacc[8 * g + q];
+    __syncthreads();
+    if (t < 32 && t < cout)
+      unsafeAtomicAdd(&dbias[t], sb[t] + sb[32 + t] + sb[64 + t] + sb[96 + t]);
   }
 }
 
@@ -654,6 +833,16 @@ hipError_t nn_conv3x3_wgrad(const gs_act* x1, const gs_act* x2, const gs_act* dz
   const int64_t npix = (int64_t)x1->n * x1->h * x1->w;
   // pixel chunks: enough workgroups to fill the chip, each long enough that
   // its 4096 atomic adds into dw are few next to its MFMA work
+  if (cout <= 32) {   // 32 x 32 channel tiles, a row of taps each (see conv3x3_wgrad32_kernel)
+    const int64_t tiles = 3 * (int64_t)((cin + 31) / 32);
+    const int64_t nk = std::max<int64_t>(1, kWgrad32Blocks / tiles);
+    int64_t kchunk = (npix + nk - 1) / nk;
+    kchunk = std::max<int64_t>(4 * WBK, (kchunk + 4 * WBK - 1) / (4 * WBK) * (4 * WBK));
+    const dim3 grid(1, (unsigned)(3 * ((cin + 31) / 32)), (unsigned)((npix + kchunk - 1) / kchunk));
+    hipLaunchKernelGGL(conv3x3_wgrad32_kernel, grid, dim3(256), 0, s, view(x1), view(x2),
+                       view(dz), view(mask), x1->n, x1->h, x1->w, cout, cin, kchunk, dw, dbias);
+    return hipGetLastError();
+  }
   const int64_t tiles = (int64_t)((cout + BM - 1) / BM) * 9 * ((cin + BN - 1) / BN);
   const int64_t nk = std::max<int64_t>(1, kWgradBlocks / tiles);
   int64_t kchunk = (npix + nk - 1) / nk;

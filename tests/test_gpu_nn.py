@@ -66,6 +66,8 @@ BWD_CASES = [
     (1, 12, 10, 64, 0, 32),     # rows narrower than one 64-pixel stage
     (2, 9, 70, 32, 32, 96),     # two images, one row wrap per stage, skip concatenation
     (1, 40, 96, 8, 0, 32),      # first-layer shape over many pixel chunks
+    (2, 9, 70, 32, 32, 32),     # the last decoder layer's shape: 32 x 32 tiles over a concatenation
+    (1, 12, 10, 16, 8, 16),     # fewer than 32 channels on both sides
 ]
 
 
