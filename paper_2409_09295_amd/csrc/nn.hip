@@ -232,7 +232,9 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
   }
   // loads of the stage at p0 (the thread's two pixels: (img, py, px) and the
   // next one); issued one stage ahead, before the MFMAs of the current one
-  uint4 z0, z1, xa, xb;
+  // the mask is applied when the stage is written to LDS, so no load waits on another
+  const bool masked = mask.p != nullptr;
+  uint4 z0, z1, m0, m1, xa, xb;
   auto fetch = [&]() {
     int img1 = img, py1 = py, px1 = px + 1;
     if (px1 == W) {
@@ -243,8 +245,12 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
       }
     }
     const bool v0 = p0 < kend, v1 = p0 + 1 < kend;
-    z0 = load8(dz, none, mask, p0, v0, co0 + 8 * cg);
-    z1 = load8(dz, none, mask, p0 + 1, v1, co0 + 8 * cg);
+    z0 = load8(dz, none, none, p0, v0, co0 + 8 * cg);
+    z1 = load8(dz, none, none, p0 + 1, v1, co0 + 8 * cg);
+    if (masked) {
+      m0 = load8(mask, none, none, p0, v0, co0 + 8 * cg);
+      m1 = load8(mask, none, none, p0 + 1, v1, co0 + 8 * cg);
+    }
     const int sy0 = py + dy, sx0 = px + dx, sy1 = py1 + dy, sx1 = px1 + dx;
     const bool i0 = v0 && sy0 >= 0 && sy0 < H && sx0 >= 0 && sx0 < W;
     const bool i1 = v1 && sy1 >= 0 && sy1 < H && sx1 >= 0 && sx1 < W;
@@ -263,7 +269,8 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
   };
   fetch();
   for (int64_t k0 = kbeg; k0 < kend; k0 += WBK) {
-    const uint32_t za[4] = {z0.x, z0.y, z0.z, z0.w}, zb[4] = {z1.x, z1.y, z1.z, z1.w};
+    const uint4 zz0 = masked ? apply_mask8(z0, m0) : z0, zz1 = masked ? apply_mask8(z1, m1) : z1;
+    const uint32_t za[4] = {zz0.x, zz0.y, zz0.z, zz0.w}, zb[4] = {zz1.x, zz1.y, zz1.z, zz1.w};
     const uint32_t xw0[4] = {xa.x, xa.y, xa.z, xa.w}, xw1[4] = {xb.x, xb.y, xb.z, xb.w};
     __syncthreads();
     // transposed into [channel][pixel], two pixels per 32-bit write
