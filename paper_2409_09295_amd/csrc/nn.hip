@@ -184,13 +184,14 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(
     }
 }
 
-// Weight-gradient tile: 64 output channels x 64 input channels for one tap,
+// Weight-gradient tile: 64 output channels x 64 input channels for one row
+// of three taps (dy fixed, dx = -1, 0, 1: one load of dz serves three taps),
 // pixels [kbeg, kbeg + kchunk) of the K dimension.  Each stage covers 64
 // pixels: thread t loads pixels 2 (t % 32) and 2 (t % 32) + 1, channels
 // 8 (t / 32) .. +8, of both dz (output-channel tile) and the tap-shifted
-// input (input-channel tile) with 16-byte loads, and writes them transposed
+// inputs (input-channel tile) with 16-byte loads, and writes them transposed
 // ([channel][pixel], two pixels per 32-bit write) into LDS; each wavefront
-// then issues two K steps of four MFMAs.
+// then issues two K steps of four MFMAs per tap.
 constexpr int WBK = 64;              // pixels per stage
 constexpr int WLDK = WBK + 8;        // LDS row pitch in bf16 (16-byte aligned rows)
 constexpr int kWgradBlocks = 1024;   // pixel chunks are sized for about this many workgroups
@@ -201,20 +202,21 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
     ActView x1, ActView x2, ActView dz, ActView mask, int N, int H, int W, int cout, int cin,
     int64_t kchunk, float* __restrict__ dw, float* __restrict__ dbias) {
   __shared__ __attribute__((aligned(16))) uint16_t sA[BM * WLDK];   // [co][pixel]
-  __shared__ __attribute__((aligned(16))) uint16_t sB[BN * WLDK];   // [ci][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t sB[3][BN * WLDK];   // per tap [ci][pixel]
   __shared__ float s_bias[BM][33];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int64_t npix = (int64_t)N * H * W;
   const int co0 = blockIdx.x * BM;
-  const int tap = blockIdx.y % 9;
-  const int ci0 = (blockIdx.y / 9) * BN;
+  const int row = blockIdx.y % 3;
+  const int ci0 = (blockIdx.y / 3) * BN;
   const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
   const int64_t kend = min(npix, kbeg + kchunk);
-  const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-  f32x4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  const bool do_bias = dbias != nullptr && tap == 4 && ci0 == 0;
+  const int dy = row - 1;
+  f32x4 acc[3][2][2];
+  for (int u = 0; u < 3; ++u)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) acc[u][i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  const bool do_bias = dbias != nullptr && row == 1 && ci0 == 0;
   float bacc[8];
   for (int q = 0; q < 8; ++q) bacc[q] = 0.f;
   const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
   // next one); issued one stage ahead, before the MFMAs of the current one
   // the mask is applied when the stage is written to LDS, so no load waits on another
   const bool masked = mask.p != nullptr;
-  uint4 z0, z1, m0, m1, xa, xb;
+  uint4 z0, z1, m0, m1, xa[3], xb[3];
   auto fetch = [&]() {
     int img1 = img, py1 = py, px1 = px + 1;
     if (px1 == W) {
@@ -251,11 +253,15 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
       m0 = load8(mask, none, none, p0, v0, co0 + 8 * cg);
       m1 = load8(mask, none, none, p0 + 1, v1, co0 + 8 * cg);
     }
-    const int sy0 = py + dy, sx0 = px + dx, sy1 = py1 + dy, sx1 = px1 + dx;
-    const bool i0 = v0 && sy0 >= 0 && sy0 < H && sx0 >= 0 && sx0 < W;
-    const bool i1 = v1 && sy1 >= 0 && sy1 < H && sx1 >= 0 && sx1 < W;
-    xa = load8(x1, x2, none, ((int64_t)img * H + sy0) * W + sx0, i0, ci0 + 8 * cg);
-    xb = load8(x1, x2, none, ((int64_t)img1 * H + sy1) * W + sx1, i1, ci0 + 8 * cg);
+    const int sy0 = py + dy, sy1 = py1 + dy;
+    const bool r0 = v0 && sy0 >= 0 && sy0 < H, r1 = v1 && sy1 >= 0 && sy1 < H;
+    const int64_t row0 = ((int64_t)img * H + sy0) * W, row1 = ((int64_t)img1 * H + sy1) * W;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int sx0 = px + u - 1, sx1 = px1 + u - 1;
+      xa[u] = load8(x1, x2, none, row0 + sx0, r0 && sx0 >= 0 && sx0 < W, ci0 + 8 * cg);
+      xb[u] = load8(x1, x2, none, row1 + sx1, r1 && sx1 >= 0 && sx1 < W, ci0 + 8 * cg);
+    }
     // advance to the next stage (WBK pixels on; rows may be narrower)
     p0 += WBK;
     px += WBK;
@@ -271,44 +277,57 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
   for (int64_t k0 = kbeg; k0 < kend; k0 += WBK) {
     const uint4 zz0 = masked ? apply_mask8(z0, m0) : z0, zz1 = masked ? apply_mask8(z1, m1) : z1;
     const uint32_t za[4] = {zz0.x, zz0.y, zz0.z, zz0.w}, zb[4] = {zz1.x, zz1.y, zz1.z, zz1.w};
-    const uint32_t xw0[4] = {xa.x, xa.y, xa.z, xa.w}, xw1[4] = {xb.x, xb.y, xb.z, xb.w};
     __syncthreads();
     // transposed into [channel][pixel], two pixels per 32-bit write
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int sh = 16 * (q & 1);
       const uint32_t lo_z = (za[q >> 1] >> sh) & 0xFFFFu, hi_z = (zb[q >> 1] >> sh) & 0xFFFFu;
-      const uint32_t lo_x = (xw0[q >> 1] >> sh) & 0xFFFFu, hi_x = (xw1[q >> 1] >> sh) & 0xFFFFu;
       *reinterpret_cast<uint32_t*>(&sA[(8 * cg + q) * WLDK + 2 * pp]) = lo_z | (hi_z << 16);
-      *reinterpret_cast<uint32_t*>(&sB[(8 * cg + q) * WLDK + 2 * pp]) = lo_x | (hi_x << 16);
       if (do_bias) bacc[q] += bf2f((uint16_t)lo_z) + bf2f((uint16_t)hi_z);
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const uint32_t xw0[4] = {xa[u].x, xa[u].y, xa[u].z, xa[u].w};
+      const uint32_t xw1[4] = {xb[u].x, xb[u].y, xb[u].z, xb[u].w};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int sh = 16 * (q & 1);
+        const uint32_t lo_x = (xw0[q >> 1] >> sh) & 0xFFFFu, hi_x = (xw1[q >> 1] >> sh) & 0xFFFFu;
+        *reinterpret_cast<uint32_t*>(&sB[u][(8 * cg + q) * WLDK + 2 * pp]) = lo_x | (hi_x << 16);
+      }
     }
     __syncthreads();
     if (k0 + WBK < kend) fetch();
 #pragma unroll
     for (int ks = 0; ks < WBK / 32; ++ks) {
-      bf16x8 a[2], b[2];
+      bf16x8 a[2];
       for (int i = 0; i < 2; ++i)
         a[i] = *reinterpret_cast<const bf16x8*>(
             &sA[(wm + i * 16 + (lane & 15)) * WLDK + 32 * ks + 8 * (lane >> 4)]);
-      for (int j = 0; j < 2; ++j)
-        b[j] = *reinterpret_cast<const bf16x8*>(
-            &sB[(wn + j * 16 + (lane & 15)) * WLDK + 32 * ks + 8 * (lane >> 4)]);
-      for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        bf16x8 b[2];
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-  }
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
-      const int ci = ci0 + wn + j * 16 + (lane & 15);
-      if (ci >= cin) continue;
-      for (int r = 0; r < 4; ++r) {
-        const int co = co0 + wm + i * 16 + 4 * (lane >> 4) + r;
-        if (co >= cout) continue;
-        unsafeAtomicAdd(&dw[((int64_t)tap * cout + co) * cin + ci], acc[i][j][r]);
+          b[j] = *reinterpret_cast<const bf16x8*>(
+              &sB[u][(wn + j * 16 + (lane & 15)) * WLDK + 32 * ks + 8 * (lane >> 4)]);
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j)
+            acc[u][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[u][i][j], 0, 0, 0);
       }
     }
+  }
+  for (int u = 0; u < 3; ++u)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        const int ci = ci0 + wn + j * 16 + (lane & 15);
+        if (ci >= cin) continue;
+        for (int r = 0; r < 4; ++r) {
+          const int co = co0 + wm + i * 16 + 4 * (lane >> 4) + r;
+          if (co >= cout) continue;
+          unsafeAtomicAdd(&dw[((int64_t)(3 * row + u) * cout + co) * cin + ci], acc[u][i][j][r]);
+        }
+      }
   if (do_bias) {   // block-uniform
     for (int q = 0; q < 8; ++q) s_bias[8 * cg + q][pp] = bacc[q];
     __syncthreads();
@@ -850,11 +869,11 @@ hipError_t nn_conv3x3_wgrad(const gs_act* x1, const gs_act* x2, const gs_act* dz
                        view(dz), view(mask), x1->n, x1->h, x1->w, cout, cin, kchunk, dw, dbias);
     return hipGetLastError();
   }
-  const int64_t tiles = (int64_t)((cout + BM - 1) / BM) * 9 * ((cin + BN - 1) / BN);
+  const int64_t tiles = (int64_t)((cout + BM - 1) / BM) * 3 * ((cin + BN - 1) / BN);
   const int64_t nk = std::max<int64_t>(1, kWgradBlocks / tiles);
   int64_t kchunk = (npix + nk - 1) / nk;
   kchunk = std::max<int64_t>(WBK, (kchunk + WBK - 1) / WBK * WBK);
-  const dim3 grid((unsigned)((cout + BM - 1) / BM), (unsigned)(9 * ((cin + BN - 1) / BN)),
+  const dim3 grid((unsigned)((cout + BM - 1) / BM), (unsigned)(3 * ((cin + BN - 1) / BN)),
                   (unsigned)((npix + kchunk - 1) / kchunk));
   hipLaunchKernelGGL(conv3x3_wgrad_kernel, grid, dim3(256), 0, s, view(x1), view(x2), view(dz),
                      view(mask), x1->n, x1->h, x1->w, cout, cin, kchunk, dw, dbias);
