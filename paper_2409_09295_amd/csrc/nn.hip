@@ -194,7 +194,7 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(
 // then issues two K steps of four MFMAs per tap.
 constexpr int WBK = 64;              // pixels per stage
 constexpr int WLDK = WBK + 8;        // LDS row pitch in bf16 (16-byte aligned rows)
-constexpr int kWgradBlocks = 1024;   // pixel chunks are sized for about this many workgroups
+constexpr int kWgradBlocks = 512;    // pixel chunks are sized for about this many workgroups
 constexpr int kWgrad32Blocks = 512;  // the narrow kernel: two resident workgroups per CU
 
 
