@@ -121,7 +121,12 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(
   const bool bload = lrow < BNT;
   const int csteps = (cin + BK - 1) / BK;
   const int nsteps = 9 * csteps;
-  uint4 ra[AR], rb;
+  // the mask (backward data: the ReLU of this layer's output) is loaded
+  // beside the values and applied when the step is written to LDS, so the
+  // prefetch does not wait for it
+  const bool masked = mask.p != nullptr;
+  const ActView none = {nullptr, 0, 0, 0};
+  uint4 ra[AR], rm[AR], rb;
   auto fetch = [&](int step) {
     const int tap = step / csteps, c0 = (step - tap * csteps) * BK;
     const int dy = tap / 3 - 1, dx = tap % 3 - 1;
@@ -129,7 +134,9 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(
     for (int u = 0; u < AR; ++u) {
       const int sy = ly[u] + dy, sx = lx[u] + dx;
       const bool inb = lok[u] && sy >= 0 && sy < H && sx >= 0 && sx < W;
-      ra[u] = load8(x1, x2, mask, ((int64_t)limg[u] * H + sy) * W + sx, inb, c0 + lcol);
+      const int64_t pix = ((int64_t)limg[u] * H + sy) * W + sx;
+      ra[u] = load8(x1, x2, none, pix, inb, c0 + lcol);
+      if (masked) rm[u] = load8(mask, none, none, pix, inb, c0 + lcol);
     }
     rb = make_uint4(0, 0, 0, 0);
     const int co = n0 + lrow, ci = c0 + lcol;
@@ -148,7 +155,8 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(
     __syncthreads();   // the previous step's fragments have been read
 #pragma unroll
     for (int u = 0; u < AR; ++u)
-      *reinterpret_cast<uint4*>(&sA[(lrow + 64 * u) * LDK + lcol]) = ra[u];
+      *reinterpret_cast<uint4*>(&sA[(lrow + 64 * u) * LDK + lcol]) =
+          masked ? apply_mask8(ra[u], rm[u]) : ra[u];
     if (bload) *reinterpret_cast<uint4*>(&sB[lrow * LDK + lcol]) = rb;
     __syncthreads();
     if (step + 1 < nsteps) fetch(step + 1);
@@ -829,8 +837,8 @@ hipError_t nn_conv3x3(const gs_act* x1, const gs_act* x2, const gs_act* mask, co
   const int ys = y ? y->stride : 0, yo = y ? y->offset : 0;
   const auto* wp = static_cast<const uint16_t*>(w);
   const unsigned ntile = (unsigned)((cout + 63) / 64);
-  // (the masked backward-data calls measured faster with the small tiles)
-  const bool narrow = cout <= 32 && mask == nullptr;
+  // (the masked backward-data calls measured faster without the large tiles)
+  const bool narrow = cout <= 32;
   const bool big = mask == nullptr &&
                    (int64_t)blocks(npix, narrow ? 256 : 128) * (narrow ? 1 : ntile) >= 1024;
   if (narrow && big)
