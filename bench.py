@@ -120,6 +120,35 @@ def _cpu_baseline(wl, budget_s=15.0, max_views=32, seed=0):
     return px / dt / 1e6, nv, px, dt, torch.get_num_threads(), blended / max(walked, 1)
 
 
+def _cpu_one_thread(wl, seed=0):
+    """The same oracle work on one thread: fwd+bwd of the first view."""
+    import numpy as np
+    import torch
+    from oracle import gs_oracle as O
+    rng = np.random.default_rng(seed)
+    cam = wl.cams[0].as_float32()
+    dl = rng.normal(size=(3, cam.height, cam.width))
+    prev = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        O.render(wl.gmap, [cam], dL_dimage=[dl], with_mask=False)
+        dt = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(prev)
+    return cam.width * cam.height / dt / 1e6, dt
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def _traffic():
     """HBM bytes per launch of the reverse tile walk from the committed
     counter summary, or None when the kernel's sources changed since."""
@@ -278,10 +307,14 @@ def main():
     cpu, blend_frac = None, DEFAULT_BLEND_FRACTION
     if not args.no_cpu_baseline:
         mp, nv, px, dt, thr, blend_frac = _cpu_baseline(wl, args.cpu_seconds)
+        mp1, dt1 = _cpu_one_thread(wl)
         cpu = {"value": mp, "unit": "Mpix/s", "cores": thr, "kind": "oracle",
                "sample": f"fwd+bwd of {nv} whole {wl.cams[0].width}x{wl.cams[0].height} views "
                          f"({px} px; projection, compositing and backward of all {wl.gmap.n} "
-                         f"Gaussians per view) in {dt:.1f} s"}
+                         f"Gaussians per view) in {dt:.1f} s",
+               "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+               "one_thread": {"value": mp1, "unit": "Mpix/s", "cores": 1,
+                              "sample": f"fwd+bwd of the first view in {dt1:.1f} s"}}
         print(f"[bench] cpu oracle: {mp:.5f} Mpix/s over {dt:.1f}s; blended fraction "
               f"{blend_frac:.3f}", file=sys.stderr, flush=True)
 

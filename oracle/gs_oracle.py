@@ -33,6 +33,9 @@ the steps below follow the published EWA-splatting/3DGS mathematics):
                    local and global objectives, Eq. 2 and Eq. 3)
   Adam             standard bias-corrected Adam (the paper does not name its
                    optimiser)
+  rendering error  E_k(g) = sum_u w(g, u) |R(M, T_k)(u) - C_k(u)| per Gaussian and
+                   view, and the active set {g : max_k E_k(g) > eps} united with
+                   the newly inserted Gaussians (selective optimisation, Sec. III-B2)
 
 Readings where the paper is silent are the constants below; every one of
 them is listed with its reason in the design notes.
@@ -568,6 +571,71 @@ def render(gmap, cams, tile_size: int = 16, bg=(0.0, 0.0, 0.0), dL_dimage=None,
                                xi=np.stack([zero(x) for x in xis]) if want_pose_grad else np.zeros((V, 6)))
         result["grad2d"] = rows.grad.numpy().reshape(V, N, 9)
     return result
+
+
+# ---------------------------------------------------------------------------
+# per-Gaussian rendering error and the active set (selective optimisation)
+# ---------------------------------------------------------------------------
+
+def render_error(gmap, cams, targets, tile_size: int = 16, bg=(0.0, 0.0, 0.0), pixel_mask=None):
+    """Per-Gaussian rendering error of the global stage's active-set selection
+    (Sec. III-B2), for every view k of ``cams``:
+
+        E_k(g) = sum over pixels u of w(g, u) |R(M, T_k)(u) - C_k(u)|
+
+    w(g, u) = alpha_g(u) T_g(u) is g's blending weight at u, R(M, T_k) the
+    render of the map from view k (this oracle's own) and C_k = targets[k]
+    (3, H, W).  The paper leaves the reduction over colour channels open; the
+    RGB residual's |.| is read as its L1 norm (sum over the channels).
+    pixel_mask: optional per-view (H, W) bool arrays of pixels to leave out
+    (their residual counts as 0).
+
+    Returns dict(err (V, N), weight (V, N): sum over u of w(g, u),
+    images: per-view (3, H, W) renders, T_final: per-view (H, W))."""
+    V, N = len(cams), gmap.n
+    res = render(gmap, cams, tile_size, bg, with_mask=False, want_pose_grad=False)
+    rows = []
+    for P in res["proj"]:
+        o = np.where(P["visible"], P["opacity"], 0.0)
+        rows.append(np.concatenate([P["u"][:, None], P["v"][:, None], P["conic"], o[:, None],
+                                    P["rgb"]], 1))
+    rows = _t(np.concatenate(rows, 0))
+    bg_t = _t(bg)
+    err = np.zeros(V * N)
+    wsum = np.zeros(V * N)
+    vals, ranges, bases = res["values"], res["ranges"], res["bases"]
+    for vi, cam in enumerate(cams):
+        TX, TY = tile_grid(cam, tile_size)
+        tgt = _t(targets[vi])
+        for ty in range(TY):
+            for tx in range(TX):
+                gt = bases[vi] + ty * TX + tx
+                s0, s1 = int(ranges[gt, 0]), int(ranges[gt, 1])
+                if s1 <= s0:
+                    continue
+                xx, yy = _tile_pixels(cam, tile_size, tx, ty)
+                idx = vals[s0:s1].astype(np.int64)
+                S = rows.index_select(0, torch.as_tensor(idx))
+                C, _, _, w, _, _ = _composite_tile(xx.to(DT) + 0.5, yy.to(DT) + 0.5, S, bg_t, False)
+                e = (C - tgt[:, yy, xx].T).abs().sum(dim=1)          # (P,) L1 over channels
+                if pixel_mask is not None:
+                    e = torch.where(torch.as_tensor(pixel_mask[vi][yy.numpy(), xx.numpy()]),
+                                    torch.zeros_like(e), e)
+                err[idx] += (w.T @ e).numpy()                          # a Gaussian appears once per tile
+                wsum[idx] += w.sum(dim=0).numpy()
+    return dict(err=err.reshape(V, N), weight=wsum.reshape(V, N),
+                images=[v["image"] for v in res["views"]], T_final=[v["T_final"] for v in res["views"]])
+
+
+def active_set(err: np.ndarray, eps: float, always: Optional[np.ndarray] = None) -> np.ndarray:
+    """E_t = {g : max over the window's views k of E_k(g) > eps}, united with
+    the Gaussians flagged in ``always`` (the newly inserted local map), as a
+    bool array over the Gaussians (Sec. III-B2)."""
+    err = np.asarray(err, np.float64)
+    mask = err.max(axis=0) > eps if err.shape[0] else np.zeros(err.shape[1], bool)
+    if always is not None:
+        mask = mask | (np.asarray(always) != 0)
+    return mask
 
 
 # ---------------------------------------------------------------------------

@@ -10,8 +10,11 @@ optimises the pose alone.  ``GSRender`` exposes the C-ABI renderer as a
     loss(images).backward()   # grads for the five parameter groups and xi
 
 ``xi`` is a (V, 6) tangent (rho, phi) of a left perturbation
-T_cw <- Exp(xi) T_cw; pass zeros: its gradient is the pose gradient at the
-current cameras (``apply_pose_step`` moves the cameras along it).
+T_cw <- Exp(xi) T_cw, evaluated at xi = 0: its gradient is the pose gradient
+at the current cameras (``apply_pose_step`` moves the cameras along it).  A
+nonzero ``xi`` is rejected (the image would otherwise belong to other
+poses than the gradient), and so is a backward after ``set_cameras`` has
+changed the poses its forward rendered.
 
 Between forward and backward only the per-pixel blend state is kept: the
 final transmittance and the index of the last blended splat (8 bytes per
@@ -44,6 +47,7 @@ class _State:
         self._alloc_bins(max(1 << 16, 4 * n * V))
         self.bwd_ws = gs.workspace(gs.gs_render_bwd_workspace_size(n, self.views), device)
         self.generation = 0          # bumps whenever proj/bins are rebuilt
+        self.cam_generation = 0      # bumps whenever the poses change
 
     def _alloc_bins(self, capacity: int):
         capacity = int(min(capacity, 0xFFFFFFFF))
@@ -73,6 +77,11 @@ def _gaussians(state: _State, means, log_scales, quats, opacity_logits, sh) -> g
 class _GSRenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, sh, xi, state: _State, recompute: bool):
+        if xi.shape != (state.views.n_views, 6):
+            raise ValueError(f"xi must have shape ({state.views.n_views}, 6)")
+        if bool(torch.count_nonzero(xi).item()):
+            raise ValueError("xi is the tangent at the current poses and must be zero; move the "
+                             "cameras with apply_pose_step or set_cameras instead")
         g = _gaussians(state, means, log_scales, quats, opacity_logits, sh)
         state.project_and_bin(g)
         P = state.views.n_pixels
@@ -83,6 +92,7 @@ class _GSRenderFn(torch.autograd.Function):
         ctx.state = state
         ctx.recompute = recompute
         ctx.generation = state.generation
+        ctx.cam_generation = state.cam_generation
         ctx.save_for_backward(means, log_scales, quats, opacity_logits, sh, final_T, n_contrib)
         return image
 
@@ -90,6 +100,9 @@ class _GSRenderFn(torch.autograd.Function):
     def backward(ctx, dL_dimage):
         means, log_scales, quats, opacity_logits, sh, final_T, n_contrib = ctx.saved_tensors
         state: _State = ctx.state
+        if state.cam_generation != ctx.cam_generation:
+            raise RuntimeError("the cameras changed between this forward and its backward; the "
+                               "saved blend state belongs to the old poses")
         g = _gaussians(state, means, log_scales, quats, opacity_logits, sh)
         if ctx.recompute or state.generation != ctx.generation:
             state.project_and_bin(g)
@@ -130,6 +143,7 @@ class GSRender:
     def set_cameras(self, cams: Sequence[scenes.Camera]):
         self.cams = list(cams)
         self.state.views.update_poses(self.cams)
+        self.state.cam_generation += 1
 
     def apply_pose_step(self, delta: np.ndarray):
         """T_cw <- Exp(delta_v) T_cw for every view (delta: (V, 6), rho then phi)."""

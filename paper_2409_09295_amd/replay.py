@@ -147,10 +147,18 @@ class BatchedStep:
         # Collect unreachable cycles now: a dead step found by the collector
         # during the capture would free its graph's memory pool, and freeing
         # device memory is not allowed while a stream is capturing.
+        # The collector stays off during the capture, so that no cycle found
+        # mid-capture can free memory either.
         gc.collect()
-        self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph):
-            self._body()
+        enabled = gc.isenabled()
+        gc.disable()
+        try:
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph):
+                self._body()
+        finally:
+            if enabled:
+                gc.enable()
         torch.cuda.synchronize()
 
     def step(self):

@@ -7,7 +7,7 @@ import torch
 
 from oracle import gs_oracle as O
 from paper_2409_09295_amd import scenes
-from tests.gpu_helpers import assert_grad_close, np_, random_dl, u32, u64
+from tests.gpu_helpers import assert_grad_close, assert_same_up_to_order, np_, random_dl, u32, u64
 
 pytestmark = pytest.mark.gpu
 
@@ -307,16 +307,32 @@ def _check_projection(gs, wl, out, res):
         np.testing.assert_array_equal(np_(proj.tiles[v]).astype(np.int64), cnt)
 
 
-def _compare_images(views, out, res, tol=1e-4):
+# Near-threshold pixels (a splat within float32 rounding of the 1/255 or 0.99
+# alpha bounds, of the 1e-4 transmittance stop, of a tile edge or of another
+# splat's depth) are left out of the comparison.  They must stay rare, or the
+# comparison would silently cover less: at most this fraction of the pixels
+# compared (the oracle flags 3 of 19,200 pixels at 160x120, 96 of 76,800 at
+# 320x240 and 1 of 3,072 on the sampled tiles of the 640x480 room).
+MAX_MASKED_FRAC = 2e-3
+
+
+def _compare_images(views, out, res, tol=1e-4, max_masked=None):
     imgs = views.split_images(out["image"])
     masked = 0
+    compared = 0
     worst = 0.0
     for v, r in enumerate(res["views"]):
-        m = ~r["mask"] & np.isfinite(r["image"][0])
+        finite = np.isfinite(r["image"][0])
+        m = ~r["mask"] & finite
         masked += int(r["mask"].sum())
+        compared += int(finite.sum())
         d = np.abs(np_(imgs[v]) - r["image"])[:, m]
         worst = max(worst, float(d.max()) if d.size else 0.0)
+    bound = max_masked if max_masked is not None else int(MAX_MASKED_FRAC * compared)
+    _log(f"  images: worst {worst:.3e} over {compared - masked} px, {masked} near-threshold px "
+         f"(bound {bound})")
     assert worst <= tol, worst
+    assert masked <= bound, (masked, bound)
     return masked, worst
 
 
@@ -413,7 +429,7 @@ def test_c3_sampled_tiles(gs):
     dl = _masked_dl(views, res0, dl.reshape(-1))
     _log("c3: GPU")
     out = _run_gpu(gs, wl, dl)
-    masked, worst = _compare_images(views, out, res0)
+    masked, worst = _compare_images(views, out, res0, max_masked=10)
     _log(f"c3 sampled image: masked {masked} px, worst {worst:.3e}")
     _log("c3: oracle backward on sampled tiles")
     res = O.render(wl.gmap, ocams(wl), dL_dimage=_split_dl(views, dl), tiles=[picks])
@@ -433,7 +449,7 @@ def test_pose_only_matches_full(gs):
     assert np.abs(np_(po.means)).max() == 0.0
     nop = _run_gpu(gs, wl, dl, flags=gs.GS_BWD_NO_POSE)["grads"]
     assert np.abs(np_(nop.xi)).max() == 0.0
-    assert_grad_close("means", np_(nop.means), np_(full.means), rel=1e-4)
+    assert_same_up_to_order("means", np_(nop.means), np_(full.means), rel=1e-4)
 
 
 def test_keep_clear_matches_clearing_backward(gs):
@@ -457,7 +473,7 @@ def test_keep_clear_matches_clearing_backward(gs):
         torch.cuda.synchronize()
         _log(f"keep-clear call with dL seed {seed}")
         for k in ("means", "log_scales", "quats", "opacity_logits", "sh", "xi"):
-            assert_grad_close(k, np_(getattr(got, k)), np_(getattr(ref, k)), rel=1e-5)
+            assert_same_up_to_order(k, np_(getattr(got, k)), np_(getattr(ref, k)))
 
 
 # ---------------------------------------------------------------------------

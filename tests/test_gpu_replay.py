@@ -9,7 +9,7 @@ import torch
 
 from oracle import gs_oracle as O
 from paper_2409_09295_amd import scenes
-from tests.gpu_helpers import assert_grad_close, np_, random_dl
+from tests.gpu_helpers import assert_grad_close, assert_same_up_to_order, np_, random_dl
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -47,7 +47,7 @@ def test_graph_replay_matches_eager_and_plain(gs):
         _log(f"replay {rep}: checking against the eager step")
         torch.testing.assert_close(img, img0, rtol=0, atol=0)       # same kernels, same order
         for k in GROUPS + ("xi",):
-            assert_grad_close(k, np_(gr[k]), np_(gr0[k]), rel=1e-5)
+            assert_same_up_to_order(k, np_(gr[k]), np_(gr0[k]))
         # eager work of the program between replays
         _ = (targets * 2).sum().item()
     # per-view reference path: same images bit for bit, same summed gradients
@@ -57,8 +57,8 @@ def test_graph_replay_matches_eager_and_plain(gs):
     for v, im in enumerate(views.split_images(img0)):
         torch.testing.assert_close(plain.rasts[v].image.view_as(im), im, rtol=0, atol=0)
     for k in GROUPS:
-        assert_grad_close(k, np_(getattr(plain.grads, k)), np_(gr0[k]), rel=1e-5)
-    assert_grad_close("xi", np_(plain.xi), np_(gr0["xi"]), rel=1e-5)
+        assert_same_up_to_order(k, np_(getattr(plain.grads, k)), np_(gr0[k]))
+    assert_same_up_to_order("xi", np_(plain.xi), np_(gr0["xi"]))
 
 
 def test_graph_replay_with_adam_tracks_eager(gs):
@@ -90,81 +90,179 @@ def test_graph_replay_with_adam_tracks_eager(gs):
         assert off.mean() < 5e-3, (k, off.mean())
 
 
-def _sampled_parity(gs, wl, view_ids, tiles_per_view, seed):
-    """Every view rendered in one batched launch; images compared with the
-    oracle on sampled tiles of ``view_ids``; gradients with dL/dC nonzero only
-    on those tiles."""
-    from tests.test_gpu_parity import _run_gpu
-    views = gs.Views(wl.cams)
+def _pick_tiles(cams, tiles_per_view, seed):
     rng = np.random.default_rng(seed)
-    sub = [wl.cams[v].as_float32() for v in view_ids]
     picks = []
-    for c in sub:
+    for c in cams:
         TX, TY = O.tile_grid(c, 16)
         p = {(int(rng.integers(0, TY)), int(rng.integers(0, TX))) for _ in range(tiles_per_view)}
         p |= {(0, 0), (TY - 1, TX - 1), (TY // 2, TX // 2)}
         picks.append(sorted(p))
-    _log(f"{wl.name}: oracle forward on {sum(map(len, picks))} sampled tiles of views {view_ids}")
-    res0 = O.render(wl.gmap, sub, bg=wl.bg, tiles=picks)
-    # dL/dC: random on the sampled tiles of the chosen views, zero elsewhere
-    dl = np.zeros(3 * views.n_pixels, np.float32)
-    offs = views.pixel_offsets()
+    return picks
+
+
+def _timed_step_parity(gs, wl, view_ids, tiles_per_view, seed, max_masked):
+    """The benchmark's step itself, one replay of its HIP graph (projection
+    of every view, binning with the device key count, compositing fused with
+    the L1 gradient, reverse tile walk on a workspace kept clear, projection
+    backward with pose tangents, grouped Adam), against the oracle on sampled
+    tiles of ``view_ids``.
+
+    The targets equal the step's own render everywhere except on the sampled
+    tiles (minus their near-threshold pixels), where they are random: the L1
+    gradient is then exactly zero elsewhere, and every gradient of the step
+    comes from pixels the oracle composites.  Checked: images and n_contrib
+    on the sampled tiles, dL/dC (zero elsewhere; the sign of the oracle's
+    residual on the sampled pixels), the loss, every parameter group's and
+    every pose's gradient, and the parameters after Adam (the oracle's Adam
+    applied to the step's own gradients)."""
+    from paper_2409_09295_amd import autotune
+    from paper_2409_09295_amd.replay import BETA1, BETA2, DEFAULT_LR, EPS, BatchedStep
+    g = gs.Gaussians.from_map(wl.gmap)
+    views = gs.Views(wl.cams)
+    P = views.n_pixels
+    targets = torch.zeros(3 * P, dtype=torch.float32, device=DEV)
+    step = BatchedStep(g, views, targets, bg=wl.bg)
+    tuned = autotune.tune(step)
+    _log(f"{wl.name}: tuned {tuned['fwd_ppl']}/{tuned['bwd_ppl']}")
+    try:
+        snap = step.adam.snapshot()
+        step._body()
+        torch.cuda.synchronize()
+        step.adam.restore(snap)
+        render = np_(step.image).copy()
+        sub = [wl.cams[v].as_float32() for v in view_ids]
+        picks = _pick_tiles(sub, tiles_per_view, seed)
+        _log(f"{wl.name}: oracle forward on {sum(map(len, picks))} sampled tiles of views {view_ids}")
+        res0 = O.render(wl.gmap, sub, bg=wl.bg, tiles=picks)
+        tgt = render.copy()
+        offs = views.pixel_offsets()
+        rng = np.random.default_rng(seed + 1)
+        keeps = []
+        masked = 0
+        for j, v in enumerate(view_ids):
+            w, h = views.sizes[v]
+            keep = np.zeros((h, w), bool)
+            for ty, tx in picks[j]:
+                keep[16 * ty:16 * ty + 16, 16 * tx:16 * tx + 16] = True
+            masked += int((keep & res0["views"][j]["mask"]).sum())
+            keep &= ~res0["views"][j]["mask"]
+            blk = tgt[3 * offs[v]:3 * (offs[v] + w * h)].reshape(3, h, w)
+            blk[:, keep] = rng.random((3, int(keep.sum())))
+            keeps.append(keep)
+        _log(f"{wl.name}: {masked} near-threshold px on the sampled tiles (bound {max_masked})")
+        assert masked <= max_masked, masked
+        targets.copy_(torch.from_numpy(tgt))
+        params0 = [np_(t).copy() for t in g.tensors()]
+        _log(f"{wl.name}: capture and one replay of the step, {len(wl.cams)} views")
+        step.capture()
+        step.step()
+        torch.cuda.synchronize()
+        assert not step.overflowed()
+        assert int(step.adam.step_dev.item()) == 1
+    finally:
+        autotune.apply(0, 0)
+    img = np_(step.image)
+    dl = np_(step.dL)
+    imgs = views.split_images(step.image)
+    worst = 0.0
     sub_dl = []
+    dl_zero = np.ones(3 * P, bool)
+    loss_ref = 0.0
     for j, v in enumerate(view_ids):
         w, h = views.sizes[v]
-        blk = random_dl([(w, h)], seed + j).reshape(3, h, w)
-        keep = np.zeros((h, w), bool)
-        for ty, tx in picks[j]:
-            keep[16 * ty:16 * ty + 16, 16 * tx:16 * tx + 16] = True
-        blk[:, ~keep] = 0.0
-        blk[:, res0["views"][j]["mask"]] = 0.0
-        dl[3 * offs[v]:3 * (offs[v] + w * h)] = blk.reshape(-1)
-        sub_dl.append(blk.astype(np.float64))
-    _log(f"{wl.name}: GPU, {len(wl.cams)} views in one launch")
-    out = _run_gpu(gs, wl, dl)
-    imgs = views.split_images(out["image"])
-    worst, masked = 0.0, 0
-    for j, v in enumerate(view_ids):
         r = res0["views"][j]
         m = ~r["mask"] & np.isfinite(r["image"][0])
-        masked += int(r["mask"].sum())
         d = np.abs(np_(imgs[v]) - r["image"])[:, m]
         worst = max(worst, float(d.max()))
-        ncg = np_(views.split_maps(out["nc"])[v])
-        np.testing.assert_array_equal(ncg[m], r["n_contrib"][m])
-    _log(f"{wl.name}: image worst {worst:.3e}, {masked} near-threshold px")
+        np.testing.assert_array_equal(np_(views.split_maps(step.n_contrib)[v])[m], r["n_contrib"][m])
+        blk = dl[3 * offs[v]:3 * (offs[v] + w * h)].reshape(3, h, w)
+        t = tgt[3 * offs[v]:3 * (offs[v] + w * h)].reshape(3, h, w)
+        resid = r["image"][:, keeps[j]] - t[:, keeps[j]]
+        expect = np.sign(resid) / (3.0 * w * h)
+        clear = np.abs(resid) > 1e-4          # sign not decided by the 1e-4 image tolerance
+        np.testing.assert_array_equal(blk[:, keeps[j]][clear], expect[clear].astype(np.float32))
+        loss_ref += float(np.abs(resid).sum()) / (3.0 * w * h)
+        sub_dl.append(blk.astype(np.float64))
+        zb = dl_zero[3 * offs[v]:3 * (offs[v] + w * h)].reshape(3, h, w)
+        zb[:, keeps[j]] = False
+    _log(f"{wl.name}: image worst {worst:.3e}")
     assert worst <= 1e-4
+    assert (dl[dl_zero] == 0.0).all(), "dL/dC nonzero where the target equals the render"
+    n_changed = sum(int(k.sum()) for k in keeps)
+    loss_tol = 1e-4 * 3 * n_changed / (3.0 * min(w * h for w, h in views.sizes))
+    assert abs(float(step.loss.item()) - loss_ref) <= loss_tol, (float(step.loss.item()), loss_ref)
     _log(f"{wl.name}: oracle backward")
     res = O.render(wl.gmap, sub, bg=wl.bg, dL_dimage=sub_dl, tiles=picks)
-    gr = out["grads"]
+    gr = step.grads
     for k in GROUPS:
         assert_grad_close(k, np_(getattr(gr, k)), res["grads"][k])
     xi = np_(gr.xi)
     assert_grad_close("xi", xi[view_ids], res["grads"]["xi"])
     others = np.setdiff1d(np.arange(len(wl.cams)), view_ids)
     assert np.abs(xi[others]).max() == 0.0
+    # Adam, as the step applied it: the oracle's update of the initial
+    # parameters with the step's own gradients
+    for k, p0, p1 in zip(GROUPS, params0, g.tensors()):
+        ref_p, _, _ = O.adam_step(p0, np_(getattr(gr, k)), np.zeros_like(p0), np.zeros_like(p0),
+                                  DEFAULT_LR[k], BETA1, BETA2, EPS, 1)
+        np.testing.assert_allclose(np_(p1), ref_p, rtol=2e-6, atol=1e-7, err_msg=k)
 
 
-def test_metric_workload_sampled_parity(gs):
+def test_timed_step_metric_workload(gs):
     """200k Gaussians, 32 views at 640x480: the benchmark's batch."""
-    from paper_2409_09295_amd import autotune
-    from paper_2409_09295_amd.replay import BatchedStep
-    wl = scenes.config_metric(0)
-    # the launch shape the benchmark times
-    g = gs.Gaussians.from_map(wl.gmap)
-    targets = torch.from_numpy(np.concatenate([t.reshape(-1) for t in wl.targets])).to(DEV)
-    tuned = autotune.tune(BatchedStep(g, gs.Views(wl.cams), targets))
-    _log(f"tuned {tuned['fwd_ppl']}/{tuned['bwd_ppl']}")
-    try:
-        _sampled_parity(gs, wl, [0, 17, 31], 6, seed=40)
-    finally:
-        autotune.apply(0, 0)
+    _timed_step_parity(gs, scenes.config_metric(0), [0, 17, 31], 6, seed=40, max_masked=10)
 
 
-def test_uneven_views_sampled_parity(gs):
+def test_timed_step_uneven_views(gs):
     """500k Gaussians, 32 keyframes of four sizes up to 1200x680."""
-    wl = scenes.config_c4(0)
-    _sampled_parity(gs, wl, [0, 1, 2, 3], 4, seed=50)
+    _timed_step_parity(gs, scenes.config_c4(0), [0, 1, 2, 3], 4, seed=50, max_masked=10)
+
+
+FULL_BIN_CASES = {
+    # the benchmark's batch: 38,400 tiles (two 8-bit tile passes)
+    "metric_32x640x480": lambda: scenes.config_metric(0),
+    # 77,400 tiles: above 2^16, so the tile bits take three passes
+    "wide_24x1200x680": lambda: scenes.room_views(200000, [(1200, 680)] * 24, 3, "room_24_1200x680"),
+}
+
+
+@pytest.mark.parametrize("case", list(FULL_BIN_CASES))
+def test_bin_sort_full_size_bit_exact(gs, case):
+    """Binning of the GPU's own projected splats at full size: keys, values,
+    ranges and the tile order bit for bit against the oracle's integer
+    binning of the same splats, with keys (synchronous) and without
+    (capacity mode, as the step runs it)."""
+    wl = FULL_BIN_CASES[case]()
+    g = gs.Gaussians.from_map(wl.gmap)
+    views = gs.Views(wl.cams)
+    V, N = views.n_views, g.n
+    proj = gs.Projected.empty(V, N)
+    gs.gs_preprocess(g, views, proj)
+    torch.cuda.synchronize()
+    xy, rd, rad = np_(proj.xy), np_(proj.rgb_depth), np_(proj.radius)
+    rad = np.where(rad > 0, rad, 0)
+    _log(f"{case}: {views.n_tiles} tiles; oracle binning")
+    keys, vals, ranges, _, _ = O.bin_splats([xy[v] for v in range(V)], [rd[v, :, 3] for v in range(V)],
+                                            [rad[v] for v in range(V)], wl.cams, 16)
+    _log(f"{case}: {len(keys)} keys")
+    for with_keys, sync in ((True, True), (False, False)):
+        bins = gs.Bins.empty(len(keys) + 1024, views.n_tiles, keys=with_keys)
+        ws = gs.workspace(gs.gs_bin_sort_workspace_size(N, views, bins.capacity))
+        gs.gs_bin_sort(proj, N, views, bins, ws, sync=sync)
+        torch.cuda.synchronize()
+        n = int(np_(bins.n_keys).view(np.uint32)[0])
+        assert n == len(keys)
+        if with_keys:
+            np.testing.assert_array_equal(np_(bins.keys)[:n].view(np.uint64), keys)
+        np.testing.assert_array_equal(np_(bins.values)[:n].view(np.uint32), vals)
+        np.testing.assert_array_equal(np_(bins.ranges).view(np.uint32), ranges)
+        ln = ranges[:, 1].astype(np.int64) - ranges[:, 0]
+        lg = np.floor(np.log2(np.maximum(ln, 1))).astype(np.int64)
+        half = np.where(lg > 0, (ln >> np.maximum(lg - 1, 0)) & 1, 0)
+        grp = np.where(ln == 0, 0, np.minimum(31, 1 + 2 * lg + half))
+        np.testing.assert_array_equal(np_(bins.order).view(np.uint32), np.argsort(-grp, kind="stable"))
+        del bins, ws
 
 
 def test_batched_at_least_3x_plain(gs):

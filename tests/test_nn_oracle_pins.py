@@ -80,3 +80,64 @@ def test_cost_volume_fronto_parallel_plane_recovers_depth():
     d = N.wta_depth(cost)
     inner = d[4:-4, 4:-4]
     assert np.mean(np.abs(inner - D) < 1e-9) > 0.9
+
+
+def test_head_hand_computed():
+    """1x1 head on two pixels with three features: out[n, k, y, x] =
+    sum_c f[n, y, x, c] w[k, c] + b[k], worked by hand; the output layout is
+    [n, 2, h, w]."""
+    f = torch.tensor([[[[1.0, 2.0, 3.0], [-1.0, 0.0, 0.5]]]], dtype=torch.float64)   # [1, 1, 2, 3]
+    w = torch.tensor([[0.5, -1.0, 2.0], [1.0, 1.0, 1.0]], dtype=torch.float64)
+    b = torch.tensor([0.25, -3.0], dtype=torch.float64)
+    out = N.head(f, w, b)
+    assert out.shape == (1, 2, 1, 2)
+    np.testing.assert_allclose(out[0, :, 0, :].numpy(), [[4.75, 0.75], [3.0, -3.5]], atol=1e-15)
+
+
+def test_depth_loss_hand_computed():
+    """Three pixels, one without depth; fx = e^2 so log(d / fx) = log d - 2:
+    residuals (0.5, 0.25) and (0.25, -0.5) give a mean of 0.75 over the two
+    valid pixels, and gradients +-1/2 there, 0 at the invalid one."""
+    e = math.e
+    depth = torch.tensor([[[e, 0.0, 1.0]]], dtype=torch.float64)               # [1, 1, 3]
+    pred = torch.tensor([[[[1.5, 7.0, 0.25]], [[-1.25, 9.0, -2.5]]]], dtype=torch.float64,
+                        requires_grad=True)                                      # [1, 2, 1, 3]
+    L = N.depth_loss(pred, depth, e * e)
+    assert abs(float(L.detach()) - 0.75) < 1e-14
+    L.backward()
+    np.testing.assert_allclose(pred.grad[0, :, 0].numpy(), [[0.5, 0.0, 0.5], [-0.5, 0.0, -0.5]],
+                               atol=1e-15)
+
+
+def test_unet_forward_matches_library_layers():
+    """The whole network against the same architecture assembled from
+    torch.nn.functional library layers in NCHW (conv2d with padding 1,
+    avg_pool2d, nearest interpolate, cat, relu, a 1x1 conv2d head)."""
+    F = torch.nn.functional
+    rng = np.random.default_rng(7)
+    ch = (4, 8, 8, 16)
+    p = {}
+    for name, cin, cout in N.unet_layers(8, ch):
+        p[name + ".w"] = torch.as_tensor(rng.normal(size=(9, cout, cin)) / math.sqrt(9 * cin))
+        p[name + ".b"] = torch.as_tensor(rng.normal(size=cout) * 0.1)
+    p["head.w"] = torch.as_tensor(rng.normal(size=(2, ch[0])))
+    p["head.b"] = torch.as_tensor(rng.normal(size=2))
+    x = torch.as_tensor(rng.normal(size=(2, 16, 24, 8)))
+    ours = N.unet_forward(x, p)
+
+    def conv(name, t):
+        w = p[name + ".w"]
+        k = w.reshape(3, 3, w.shape[1], w.shape[2]).permute(2, 3, 0, 1)
+        return F.relu(F.conv2d(t, k, p[name + ".b"], padding=1))
+
+    up = lambda t: F.interpolate(t, scale_factor=2, mode="nearest")
+    xc = x.permute(0, 3, 1, 2)
+    e0 = conv("e0b", conv("e0a", xc))
+    e1 = conv("e1b", conv("e1a", F.avg_pool2d(e0, 2)))
+    e2 = conv("e2b", conv("e2a", F.avg_pool2d(e1, 2)))
+    e3 = conv("e3b", conv("e3a", F.avg_pool2d(e2, 2)))
+    d2 = conv("d2b", conv("d2a", torch.cat([up(e3), e2], 1)))
+    d1 = conv("d1b", conv("d1a", torch.cat([up(d2), e1], 1)))
+    d0 = conv("d0b", conv("d0a", torch.cat([up(d1), e0], 1)))
+    ref = F.conv2d(d0, p["head.w"][:, :, None, None], p["head.b"])
+    torch.testing.assert_close(ours, ref, rtol=1e-10, atol=1e-10)

@@ -500,3 +500,195 @@ def test_alpha_band_covers_float32_exponent_rounding():
             worst = max(worst, rel / band)
             assert rel <= band, (rel, band, terms)
     assert worst > 0.01, worst   # the bound is exercised, not vacuous
+
+
+# ---------------------------------------------------------------------------
+# off-axis EWA Jacobian and the camera rotation of Sigma
+# ---------------------------------------------------------------------------
+
+def _rot_from_quat_scipy(q_wxyz):
+    from scipy.spatial.transform import Rotation
+    w, x, y, z = q_wxyz
+    return Rotation.from_quat([x, y, z, w]).as_matrix()      # scipy orders (x, y, z, w)
+
+
+def test_ewa_covariance_matches_finite_difference_jacobian():
+    """Sigma' of project_view equals J Wc Sigma Wc^T J^T + 0.3 I with J taken
+    from central differences of the pinhole map p -> (fx x/z + cx, fy y/z + cy),
+    at off-axis points under a rotated camera.  Inside the 1.3 guard the
+    Jacobian is the map's own; outside it, the map's Jacobian at the camera
+    point moved onto the guard (x/z, y/z clamped, z kept).  Sigma comes from
+    scipy's rotation of the quaternion.  A sign flip in the x/z (y/z) column,
+    a missing clamp or Wc^T Sigma Wc in place of Wc Sigma Wc^T fails here."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(12)
+    W, H, fx, fy, cx, cy = 320, 240, 260.0, 250.0, 150.0, 130.0
+    Wc = Rotation.from_rotvec([0.3, -0.5, 0.2]).as_matrix()
+    tc = np.array([0.2, -0.1, 0.4])
+    n = 60
+    # camera-frame points: x/z, y/z spread to 2.2x the guard limits
+    lx, ly = 1.3 * W / (2 * fx), 1.3 * H / (2 * fy)
+    z = rng.uniform(1.0, 5.0, n)
+    p = np.stack([rng.uniform(-2.2, 2.2, n) * lx * z, rng.uniform(-2.2, 2.2, n) * ly * z, z])
+    mu = Wc.T @ (p - tc[:, None])
+    q = rng.normal(size=(4, n))
+    q /= np.linalg.norm(q, axis=0)
+    ls = rng.normal(-2.0, 0.6, size=(3, n))
+    P = O.project_view(torch.as_tensor(mu), torch.as_tensor(ls), torch.as_tensor(q),
+                       torch.zeros(n, dtype=torch.float64), torch.zeros((3, 1, n), dtype=torch.float64),
+                       0, torch.as_tensor(Wc), torch.as_tensor(tc),
+                       scenes.Camera(Wc, tc, fx, fy, cx, cy, W, H))
+    conic = P["conic"].numpy()
+
+    def proj(pt):
+        return np.array([fx * pt[0] / pt[2] + cx, fy * pt[1] / pt[2] + cy])
+
+    inside = 0
+    for i in range(n):
+        tx = np.clip(p[0, i] / p[2, i], -lx, lx)
+        ty = np.clip(p[1, i] / p[2, i], -ly, ly)
+        inside += (abs(p[0, i] / p[2, i]) < lx) and (abs(p[1, i] / p[2, i]) < ly)
+        base = np.array([tx * p[2, i], ty * p[2, i], p[2, i]])
+        J = np.zeros((2, 3))
+        for k in range(3):
+            h = 1e-5 * p[2, i]
+            e = np.zeros(3)
+            e[k] = h
+            J[:, k] = (proj(base + e) - proj(base - e)) / (2 * h)
+        Rq = _rot_from_quat_scipy(q[:, i])
+        S = Rq @ np.diag(np.exp(2 * ls[:, i])) @ Rq.T
+        Sp = J @ Wc @ S @ Wc.T @ J.T + 0.3 * np.eye(2)
+        a, b, c = conic[i]
+        got = np.linalg.inv(np.array([[a, b], [b, c]]))
+        np.testing.assert_allclose(got, Sp, rtol=1e-7, atol=1e-9 * np.abs(Sp).max(), err_msg=str(i))
+    assert 5 < inside < n - 5          # both branches of the guard are exercised
+
+
+def test_render_is_equivariant_under_camera_rotation():
+    """At SH degree 0 (view-independent colour) the map seen from (R, t)
+    renders exactly like the rotated map (mu -> R mu, q -> q_R (x) q) seen from
+    (I, t): both put every Gaussian at the same camera-frame point with the
+    same camera-frame covariance R Sigma R^T.  A camera rotation applied as
+    R^T Sigma R breaks this."""
+    from scipy.spatial.transform import Rotation
+    gmap = scenes.random_cloud(400, 0, seed=13, box=((-1.5, 1.5), (-1.0, 1.0), (2.0, 5.0)))
+    Rc = Rotation.from_rotvec([0.25, -0.35, 0.15]).as_matrix()
+    t = np.array([0.1, -0.05, 0.3])
+    # a map whose camera-frame points under (Rc, t) equal gmap's under (I, t)
+    mu_a = Rc.T @ gmap.means.astype(np.float64)
+    qa = np.stack([_hamilton(_quat_of(Rc.T), gmap.quats[:, i].astype(np.float64))
+                   for i in range(gmap.n)], 1)
+    rot = scenes.GaussianMap(mu_a, gmap.log_scales.astype(np.float64), qa,
+                             gmap.opacity_logits.astype(np.float64), gmap.sh.astype(np.float64), 0)
+    W, H, f = 96, 72, 80.0
+    cam_r = scenes.Camera(Rc, t, f, f, W / 2, H / 2, W, H)
+    cam_i = scenes.Camera(np.eye(3), t, f, f, W / 2, H / 2, W, H)
+    a = O.render(rot, [cam_r], bg=(0.1, 0.2, 0.3))
+    b = O.render(gmap, [cam_i], bg=(0.1, 0.2, 0.3))
+    m = ~(a["views"][0]["mask"] | b["views"][0]["mask"])
+    assert m.mean() > 0.95
+    np.testing.assert_allclose(a["views"][0]["image"][:, m], b["views"][0]["image"][:, m], atol=1e-10)
+    np.testing.assert_allclose(a["proj"][0]["conic"], b["proj"][0]["conic"], rtol=1e-9, atol=1e-12)
+
+
+def _quat_of(R):
+    from scipy.spatial.transform import Rotation
+    x, y, z, w = Rotation.from_matrix(R).as_quat()
+    return np.array([w, x, y, z])
+
+
+# ---------------------------------------------------------------------------
+# per-Gaussian rendering error (selective optimisation)
+# ---------------------------------------------------------------------------
+
+def _covered_pixels(u, v, r, W, H, ts=16):
+    """Pixels of the tiles that hold a pixel centre inside [u +- r] x [v +- r],
+    by enumeration."""
+    tiles = set()
+    for j in range(H):
+        for i in range(W):
+            if abs(i + 0.5 - u) <= r and abs(j + 0.5 - v) <= r:
+                tiles.add((j // ts, i // ts))
+    cov = np.zeros((H, W), bool)
+    for (ty, tx) in tiles:
+        cov[ty * ts:(ty + 1) * ts, tx * ts:(tx + 1) * ts] = True
+    return cov
+
+
+@pytest.mark.parametrize("s,z,o_logit,W,H", [(0.2, 3.0, 1.0, 32, 24), (0.03, 2.0, 2.5, 80, 64)])
+def test_render_error_single_gaussian_closed_form(s, z, o_logit, W, H):
+    """One on-axis isotropic Gaussian, black background, black target: the
+    render is c alpha(u), so E = sum_c c_c * sum over covered pixels of
+    alpha(u)^2, with alpha(u) = min(0.99, o exp(-|d|^2 / (2 var))) where at
+    least 1/255, var = (f s / z)^2 + 0.3."""
+    f = 100.0
+    f0 = [0.7, -0.3, 1.2]
+    g, cam = _single(np.float32(s), np.float32(z), f, W, H, o_logit, f0)
+    s, z = math.exp(float(g.log_scales[0, 0])), float(np.float32(z))
+    o = 1 / (1 + math.exp(-float(np.float32(o_logit))))
+    var = (f * s / z) ** 2 + 0.3
+    r = math.ceil(3 * math.sqrt(var))
+    c = np.maximum(np.asarray(g.sh[:, 0, 0], np.float64) * 0.5 / math.sqrt(math.pi) + 0.5, 0.0)
+    cov = _covered_pixels(W / 2, H / 2, r, W, H)
+    jj, ii = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    a = np.minimum(0.99, o * np.exp(-((ii - W / 2) ** 2 + (jj - H / 2) ** 2) / (2 * var)))
+    a = np.where((a >= 1 / 255) & cov, a, 0.0)
+    expect = c.sum() * (a * a).sum()
+    res = O.render_error(g, [cam], [np.zeros((3, H, W))])
+    np.testing.assert_allclose(res["err"][0, 0], expect, rtol=1e-12)
+    np.testing.assert_allclose(res["weight"][0, 0], a.sum(), rtol=1e-12)
+
+
+def test_render_error_occlusion_two_gaussians():
+    """A splat behind another on the axis: its weight is alpha_b (1 - alpha_f)
+    per pixel, and with target t the residual is |c_f a_f + c_b a_b (1 - a_f) - t|
+    summed over channels (black background, every pixel covered)."""
+    W, H, f = 32, 24, 100.0
+    g = scenes.GaussianMap(
+        means=np.array([[0.0, 0.0], [0.0, 0.0], [3.0, 4.0]], np.float32),
+        log_scales=np.log(np.array([[0.25, 0.35]] * 3, np.float32)),
+        quats=np.array([[1.0, 1.0], [0.0, 0.0], [0.0, 0.0], [0.0, 0.0]], np.float32),
+        opacity_logits=np.array([0.3, 1.5], np.float32),
+        sh=np.array([[0.4, -0.6], [0.1, 0.9], [-1.0, 0.5]], np.float32).reshape(3, 1, 2), sh_degree=0)
+    cam = scenes.Camera(np.eye(3), np.zeros(3), f, f, W / 2, H / 2, W, H)
+    rng = np.random.default_rng(3)
+    tgt = rng.random((3, H, W))
+    jj, ii = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    alph, col = [], []
+    for k in range(2):
+        s = math.exp(float(g.log_scales[0, k]))
+        z = float(g.means[2, k])
+        var = (f * s / z) ** 2 + 0.3
+        assert math.ceil(3 * math.sqrt(var)) >= W / 2   # the rectangle covers the image
+        o = 1 / (1 + math.exp(-float(g.opacity_logits[k])))
+        a = np.minimum(0.99, o * np.exp(-((ii - W / 2) ** 2 + (jj - H / 2) ** 2) / (2 * var)))
+        alph.append(np.where(a >= 1 / 255, a, 0.0))
+        col.append(np.maximum(g.sh[:, 0, k].astype(np.float64) * 0.5 / math.sqrt(math.pi) + 0.5, 0))
+    wf, wb = alph[0], alph[1] * (1 - alph[0])
+    img = col[0][:, None, None] * wf + col[1][:, None, None] * wb
+    e = np.abs(img - tgt).sum(axis=0)
+    res = O.render_error(g, [cam], [tgt])
+    np.testing.assert_allclose(res["err"][0], [(wf * e).sum(), (wb * e).sum()], rtol=1e-11)
+    np.testing.assert_allclose(res["images"][0], img, atol=1e-12)
+
+
+def test_render_error_weights_sum_to_coverage():
+    """Summed over the Gaussians, E_k equals sum_u (1 - T_final(u)) e(u): the
+    blending weights of a pixel add up to one minus its final transmittance
+    (random cloud, two views, background and a random target)."""
+    gmap = scenes.random_cloud(300, 0, seed=5)
+    cams = [scenes.pinhole(64, 48, 60.0),
+            scenes.perturb_pose(scenes.pinhole(48, 40, 50.0), np.random.default_rng(6))]
+    rng = np.random.default_rng(7)
+    tg = [rng.random((3, c.height, c.width)) for c in cams]
+    res = O.render_error(gmap, cams, tg, bg=(0.2, 0.1, 0.3))
+    for k in range(2):
+        e = np.abs(res["images"][k] - tg[k]).sum(axis=0)
+        np.testing.assert_allclose(res["err"][k].sum(), ((1 - res["T_final"][k]) * e).sum(), rtol=1e-10)
+        np.testing.assert_allclose(res["weight"][k].sum(), (1 - res["T_final"][k]).sum(), rtol=1e-10)
+    m = O.active_set(res["err"], float(np.median(res["err"].max(axis=0))))
+    assert 0 < m.sum() < gmap.n
+    always = np.zeros(gmap.n, np.uint8)
+    always[:7] = 1
+    m2 = O.active_set(res["err"], 1e30, always)
+    np.testing.assert_array_equal(m2, always.astype(bool))
