@@ -336,11 +336,162 @@ int gs_render_fwd_l1(const gs_projected* p, int64_t n, const gs_bins* bins,
                      uint32_t* n_contrib, const float* target, float* dL_dimage, double* loss,
                      void* workspace, size_t workspace_bytes, gs_stream_t stream);
 
+/* Per-Gaussian rendering error of the global stage (Sec. III-B2, the
+ * selection of the set E_t of Gaussians with high rendering error in the
+ * current window): for every view k and splat g ([n_views][n] entries, the
+ * layout of the projected splats)
+ *   err[k][g] = sum over pixels u of w(g, u) * sum_c |image_c(u) - target_c(u)|
+ * where w(g, u) = alpha T is g's blending weight at u.  p, bins, image and
+ * n_contrib are those of a gs_render_fwd (or gs_render_fwd_l1) call on the
+ * same views, unchanged since; target holds the views' reference images C_k
+ * (layout of image).  The weights are recomputed with the forward's own
+ * float32 arithmetic, so they equal the forward's bit for bit.  The RGB
+ * residual's |.| is its L1 norm over the three channels (the paper leaves the
+ * channel reduction open).  err (device float32 [n_views][n]) is
+ * overwritten: 0 for splats that blend into no pixel.  Accumulated with
+ * float32 atomics (the summation order varies between calls). */
+int gs_render_error(const gs_projected* p, int64_t n, const gs_bins* bins, const gs_views* views,
+                    const float* image, const float* target, const uint32_t* n_contrib,
+                    float* err, gs_stream_t stream);
+
+/* Active set of the global stage's selective optimisation (Sec. III-B2):
+ *   mask[g] = 1 if max over the n_views views of err[k][g] > eps, or if
+ *             always[g] != 0 (the newly inserted Gaussians, which are always
+ *             optimised); 0 otherwise
+ * for g < n.  err: device float32 [n_views][n] (e.g. from gs_render_error);
+ * always (optional, device uint8 [n]); mask (device uint8 [n]) overwritten;
+ * err_max (optional, device float32 [n]) receives the per-Gaussian maximum;
+ * n_active (optional, device uint32 [1]) receives the number of set mask
+ * bytes.  n_views in 1 .. GS_MAX_VIEWS, eps finite.  The comparison is done
+ * in float32. */
+int gs_active_set(const float* err, int64_t n, int32_t n_views, float eps, const uint8_t* always,
+                  uint8_t* mask, float* err_max, uint32_t* n_active, gs_stream_t stream);
+
+/* gs_adam_step_groups_dev restricted to an active set of Gaussians: every
+ * group is laid out [C][n_gauss] (its n a multiple of n_gauss, like the
+ * parameter groups of gs_gaussians), and element e of a group is updated
+ * only if gauss_mask[e % n_gauss] != 0; other elements (parameter and both
+ * moments) are left untouched.  The updated elements equal those of the
+ * unmasked call bit for bit.  gauss_mask: device uint8 [n_gauss]. */
+int gs_adam_step_groups_masked_dev(const gs_adam_group* groups, int32_t n_groups, float beta1,
+                                   float beta2, float eps, int32_t* step_dev,
+                                   const uint8_t* gauss_mask, int64_t n_gauss,
+                                   const uint32_t* guard_n_keys, int64_t guard_capacity,
+                                   gs_stream_t stream);
+
+/* ---- map maintenance of the global stage (Sec. III-B2) -------------------
+ * Structure-of-arrays data ([C][n] float32 arrays, component-major like the
+ * parameter groups of gs_gaussians and their Adam moments) is moved by the
+ * calls below; up to GS_SOA_MAX_ARRAYS arrays per call. */
+#define GS_SOA_MAX_ARRAYS 16
+
+/* One array of gs_concat: dst [C][n_a + n_b] = a [C][n_a] followed, per
+ * component, by b [C][n_b]; when b is NULL the second part is filled with
+ * `fill`.  Device pointers; dst must not overlap a or b. */
+typedef struct gs_concat_array {
+  const float* a;
+  const float* b;
+  float* dst;
+  int32_t components;
+  float fill;
+} gs_concat_array;
+
+/* Insertion of the local map into the global map, M'_t = M_{t-1} united with
+ * the local map (Sec. III-B2), as a concatenation of every parameter array
+ * (global Gaussians first); the insertion's lowered opacity is a constant
+ * fill of the local part of the opacity-logit array (b = NULL, fill =
+ * logit(0.2)), and new Adam moments are fills of 0.  arrays is a host array
+ * read during the call; n_a, n_b >= 0. */
+int gs_concat(const gs_concat_array* arrays, int32_t n_arrays, int64_t n_a, int64_t n_b,
+              gs_stream_t stream);
+
+/* Opacity rule of the pruning step (Sec. III-B2): keep[i] = 1 if the opacity
+ * sigmoid(opacity_logits[i]) is at least min_opacity, else 0, decided in
+ * float32 as opacity_logits[i] >= logit(min_opacity) (the threshold computed
+ * in float64 and rounded to float32).  min_opacity in (0, 1); keep: device
+ * uint8 [n]. */
+int gs_prune_mask(const float* opacity_logits, int64_t n, float min_opacity, uint8_t* keep,
+                  gs_stream_t stream);
+
+/* One array of gs_compact: src [C][n]; dst has room for C * n floats and
+ * receives the compacted [C][n_kept] array in its first C * n_kept floats. */
+typedef struct gs_compact_array {
+  const float* src;
+  float* dst;
+  int32_t components;
+} gs_compact_array;
+
+/* Scratch for gs_compact (bytes). */
+size_t gs_compact_workspace_size(int64_t n);
+
+/* Stable compaction of every array by keep (device uint8 [n]): kept entries
+ * keep their order.  n_kept (device uint32 [1]) receives their count; the
+ * destination component stride is that count, read on the device, so no
+ * host synchronisation is needed (capture-safe).  dst must not overlap src. */
+int gs_compact(const gs_compact_array* arrays, int32_t n_arrays, int64_t n, const uint8_t* keep,
+               uint32_t* n_kept, void* workspace, size_t workspace_bytes, gs_stream_t stream);
+
+/* Isotropic regulariser of the mapping objectives (Eq. 2, Eq. 3; the paper
+ * only says that it keeps Gaussians from growing elongated or thin):
+ *   E_iso = weight / (3 n) * sum_i sum_j |s_ij - (s_i0 + s_i1 + s_i2) / 3|
+ * with s = exp(log_scales) ([3][n] device float32).  Its gradient with respect
+ * to the log-scales is added (+=) to grad_log_scales ([3][n]); loss
+ * (optional, device float64 [1]) is overwritten with E_iso. */
+int gs_iso_loss_grad(const float* log_scales, int64_t n, float weight, float* grad_log_scales,
+                     double* loss, gs_stream_t stream);
+
+/* Pose step of the mapping objectives, which minimise over the keyframe poses
+ * T_k as well as the map (Eq. 2, Eq. 3): one Adam step on each view's pose
+ * tangent xi = (rho, phi) from its gradient grad_xi [n_views][6] (as written
+ * by gs_render_bwd), then T_cw <- Exp(delta) T_cw with delta = -lr m_hat /
+ * (sqrt(v_hat) + eps) (lr_trans for rho, lr_rot for phi), evaluated in float64
+ * (closed-form SE(3) exponential) and stored back into cams_dev's R and t.
+ * m, v: device float32 [n_views][6] moments; step_dev: device int32 step
+ * counter (t = *step_dev + 1, then incremented); view_mask (optional, device
+ * uint8 [n_views]): only views with a nonzero byte move (the past views of
+ * the photometric-consistency loss keep their poses).  cams_dev: the device
+ * camera records of a gs_views (sizes and intrinsics are not touched).
+ * Capture-safe: no host synchronisation. */
+int gs_pose_adam_step(gs_camera* cams_dev, const float* grad_xi, float* m, float* v,
+                      int32_t n_views, const uint8_t* view_mask, float lr_trans, float lr_rot,
+                      float beta1, float beta2, float eps, int32_t* step_dev, gs_stream_t stream);
+
 /* L1 photometric loss L = sum over views of mean |C - C*| over 3 H W, and
  * dL/dC = sign(C - C*) / (3 H W) (sign(0) = 0), for every view (layouts of
  * image).  loss (optional, device float64 [1]) is overwritten with L. */
 int gs_l1_loss_grad(const float* image, const float* target, const gs_views* views,
                     float* dL_dimage, double* loss, gs_stream_t stream);
+
+/* ---- overhead-memory ledger of the mapping loop (Sec. IV-B) ---------------
+ * The paper reports a system's memory as the map plus the overhead, the
+ * inputs and temporaries needed to produce the map, counting only variables
+ * essential to the algorithm (caches kept solely for speed are left out) and
+ * tracking them where they are created and freed.  The calls below are that
+ * ledger: a driver registers each essential buffer's bytes under a category
+ * when it allocates it and releases them (negative bytes) when it frees it.
+ * Host-only (no device work), process-wide, thread-safe. */
+enum {
+  GS_MEM_MAP = 0,            /* the Gaussian map (parameters)                    */
+  GS_MEM_KEYFRAMES = 1,      /* keyframe images held in the sliding window       */
+  GS_MEM_POSES = 2,          /* keyframe camera records (window and past poses)  */
+  GS_MEM_INIT = 3,           /* initialisation temporaries (cost volume, depth)  */
+  GS_MEM_RENDER_TARGETS = 4, /* re-rendered past views of the consistency loss   */
+  GS_MEM_BLEND_STATE = 5,    /* per-pixel state kept from forward to backward    */
+  GS_MEM_OPTIMISER = 6,      /* optimiser state of the map and poses             */
+  GS_MEM_CATEGORIES = 7
+};
+
+/* Adds bytes (negative: releases) to a category.  GS_ERR_INVALID_ARGUMENT for
+ * an unknown category or a release below zero (then nothing changes). */
+int gs_mem_track(int32_t category, int64_t bytes);
+/* Current and peak bytes per category (arrays of GS_MEM_CATEGORIES, host,
+ * each optional), and the current and peak overhead total (every category
+ * but GS_MEM_MAP and GS_MEM_OPTIMISER, whose size follows the map's;
+ * optional). */
+int gs_mem_report(int64_t* current, int64_t* peak, int64_t* overhead_current,
+                  int64_t* overhead_peak);
+/* Restarts the peaks from the current values. */
+int gs_mem_reset_peaks(void);
 
 #ifdef __cplusplus
 }

@@ -36,6 +36,8 @@ the steps below follow the published EWA-splatting/3DGS mathematics):
   rendering error  E_k(g) = sum_u w(g, u) |R(M, T_k)(u) - C_k(u)| per Gaussian and
                    view, and the active set {g : max_k E_k(g) > eps} united with
                    the newly inserted Gaussians (selective optimisation, Sec. III-B2)
+  global stage     insertion of the local map at opacity 0.2, the isotropic
+                   regulariser, pruning below opacity 0.7 (Sec. III-B2)
 
 Readings where the paper is silent are the constants below; every one of
 them is listed with its reason in the design notes.
@@ -573,11 +575,96 @@ def render(gmap, cams, tile_size: int = 16, bg=(0.0, 0.0, 0.0), dL_dimage=None,
     return result
 
 
+def gradient_term_mass(gmap, cams, dL_dimage, gauss_ids, tile_size: int = 16, bg=(0.0, 0.0, 0.0),
+                       tiles=None):
+    """Absolute first-order mass of the per-pixel terms whose sum is each map
+    gradient of the Gaussians ``gauss_ids``: for a parameter theta of
+    Gaussian g,
+
+        mass(theta) = sum over views and pixels u of
+                      sum_k |d row_k / d theta| |d (C(u) . dL/dC(u)) / d row_k|
+
+    with row = g's screen-space splat (u, v, conic, opacity, colour).  The
+    gradient itself is the same sum without the absolute values; when its
+    terms cancel, mass / |gradient| is the factor by which rounding of the
+    terms is amplified.  Also returns the longest list position walked by any
+    pixel where one of the Gaussians contributes.  Test infrastructure: it
+    bounds float32 rounding of ill-conditioned gradient elements and is not a
+    reference value.  Returns (dict group -> array (len(ids), components),
+    walk)."""
+    ids = [int(i) for i in gauss_ids]
+    K = (gmap.sh_degree + 1) ** 2
+    comps = dict(means=3, log_scales=3, quats=4, opacity_logits=1, sh=3 * K)
+    mass = {k: np.zeros((len(ids), c)) for k, c in comps.items()}
+    walk = 0
+    leaves = [_t(a) for a in gmap.arrays()]
+    bg_t = _t(bg)
+    for vi, cam in enumerate(cams):
+        R = _t(np.asarray(cam.R, np.float64).reshape(3, 3))
+        t = _t(np.asarray(cam.t, np.float64).reshape(3))
+        P = project_view(*leaves, gmap.sh_degree, R, t, cam)
+        o = torch.where(P["visible"], P["opacity"], torch.zeros_like(P["opacity"]))
+        rows = torch.cat([P["u"][:, None], P["v"][:, None], P["conic"], o[:, None], P["rgb"]], 1)
+        rows = rows.detach()
+        radius = torch.where(P["visible"], P["radius"], torch.zeros_like(P["radius"])).numpy()
+        xy = torch.stack([P["u"], P["v"]], 1).detach().numpy()
+        _, vals, ranges, _, _ = bin_splats([xy], [P["z"].detach().numpy().astype(np.float32)],
+                                           [radius], [cam], tile_size)
+        # d row / d theta of each listed Gaussian (a single-Gaussian projection)
+        jac = {}
+        for j, gi in enumerate(ids):
+            if not bool(P["visible"][gi]):
+                continue
+            sl = [a[..., gi:gi + 1].clone().requires_grad_(True) for a in leaves]
+            Pg = project_view(*sl, gmap.sh_degree, R, t, cam)
+            row = torch.cat([Pg["u"], Pg["v"], Pg["conic"][0], Pg["opacity"], Pg["rgb"][0]])
+            J = []
+            for k in range(9):
+                gk = torch.autograd.grad(row[k], sl, retain_graph=True, allow_unused=True)
+                J.append(torch.cat([(x if x is not None else torch.zeros_like(a)).reshape(-1)
+                                    for x, a in zip(gk, sl)]))
+            jac[gi] = torch.stack(J).abs().numpy()                  # (9, n_params)
+        if not jac:
+            continue
+        TX, TY = tile_grid(cam, tile_size)
+        g = _t(dL_dimage[vi])
+        want = None if tiles is None else set(tiles[vi])
+        for ty in range(TY):
+            for tx in range(TX):
+                if want is not None and (ty, tx) not in want:
+                    continue
+                gt = ty * TX + tx
+                s0, s1 = int(ranges[gt, 0]), int(ranges[gt, 1])
+                lst = vals[s0:s1].astype(np.int64)
+                here = [(j, gi, int(np.nonzero(lst == gi)[0][0])) for j, gi in enumerate(ids)
+                        if gi in jac and (lst == gi).any()]
+                if not here:
+                    continue
+                xx, yy = _tile_pixels(cam, tile_size, tx, ty)
+                S = rows[torch.as_tensor(lst)].clone().requires_grad_(True)
+                C, _, last, _, _, _ = _composite_tile(xx.to(DT) + 0.5, yy.to(DT) + 0.5, S, bg_t, False)
+                f = (C * g[:, yy, xx].T).sum(dim=1)
+                gr = torch.autograd.grad(f, S, grad_outputs=torch.eye(f.shape[0], dtype=DT),
+                                         is_grads_batched=True)[0]          # (P, L, 9)
+                for j, gi, pos in here:
+                    sp = gr[:, pos, :].abs()
+                    if float(sp.sum()) == 0.0:
+                        continue
+                    walk = max(walk, int(last.max()))
+                    m = sp.sum(dim=0).numpy() @ jac[gi]                   # (n_params,)
+                    off = 0
+                    for k, c in comps.items():
+                        mass[k][j] += m[off:off + c]
+                        off += c
+    return mass, walk
+
+
 # ---------------------------------------------------------------------------
 # per-Gaussian rendering error and the active set (selective optimisation)
 # ---------------------------------------------------------------------------
 
-def render_error(gmap, cams, targets, tile_size: int = 16, bg=(0.0, 0.0, 0.0), pixel_mask=None):
+def render_error(gmap, cams, targets, tile_size: int = 16, bg=(0.0, 0.0, 0.0), pixel_mask=None,
+                 tiles=None):
     """Per-Gaussian rendering error of the global stage's active-set selection
     (Sec. III-B2), for every view k of ``cams``:
 
@@ -588,7 +675,8 @@ def render_error(gmap, cams, targets, tile_size: int = 16, bg=(0.0, 0.0, 0.0), p
     (3, H, W).  The paper leaves the reduction over colour channels open; the
     RGB residual's |.| is read as its L1 norm (sum over the channels).
     pixel_mask: optional per-view (H, W) bool arrays of pixels to leave out
-    (their residual counts as 0).
+    (their residual counts as 0).  tiles: optional per-view collections of
+    (ty, tx): only those tiles' pixels are summed (the others count as 0).
 
     Returns dict(err (V, N), weight (V, N): sum over u of w(g, u),
     images: per-view (3, H, W) renders, T_final: per-view (H, W))."""
@@ -607,8 +695,11 @@ def render_error(gmap, cams, targets, tile_size: int = 16, bg=(0.0, 0.0, 0.0), p
     for vi, cam in enumerate(cams):
         TX, TY = tile_grid(cam, tile_size)
         tgt = _t(targets[vi])
+        want = None if tiles is None else set(tiles[vi])
         for ty in range(TY):
             for tx in range(TX):
+                if want is not None and (ty, tx) not in want:
+                    continue
                 gt = bases[vi] + ty * TX + tx
                 s0, s1 = int(ranges[gt, 0]), int(ranges[gt, 1])
                 if s1 <= s0:
@@ -636,6 +727,79 @@ def active_set(err: np.ndarray, eps: float, always: Optional[np.ndarray] = None)
     if always is not None:
         mask = mask | (np.asarray(always) != 0)
     return mask
+
+
+# ---------------------------------------------------------------------------
+# global stage: insertion, isotropic regulariser, pruning
+# ---------------------------------------------------------------------------
+
+INSERT_OPACITY = 0.2     # opacity of the local map when it enters the global map
+PRUNE_OPACITY = 0.7      # Gaussians below this opacity are pruned after optimisation
+ISO_WEIGHT = 10.0        # weight of the isotropic regulariser (the paper gives none)
+
+
+def logit(p: float) -> float:
+    return math.log(p / (1.0 - p))
+
+
+def insert(global_map, local_map, opacity: float = INSERT_OPACITY):
+    """Pre-optimised global map M'_t = M_{t-1} united with the local map M~_t
+    (Sec. III-B2): the previous global map's Gaussians first, then the local
+    map's, whose opacity is lowered to ``opacity`` (its logit) before the
+    insertion.  Returns the five parameter arrays (float64) and the flags of
+    the inserted Gaussians."""
+    out = []
+    for k, (a, b) in enumerate(zip(global_map.arrays(), local_map.arrays())):
+        b = np.asarray(b, np.float64)
+        if k == 3:
+            b = np.full(b.shape, logit(opacity))
+        out.append(np.concatenate([np.asarray(a, np.float64), b], axis=-1))
+    new = np.r_[np.zeros(global_map.n, np.uint8), np.ones(local_map.n, np.uint8)]
+    return out, new
+
+
+def iso_loss_grad(log_scales, weight: float = ISO_WEIGHT):
+    """Isotropic regulariser E_iso (Eq. 2 and Eq. 3; the paper states only that
+    it keeps Gaussians from becoming elongated or thin): the mean over all
+    Gaussians and their three axes of |s_j - mean_k s_k|, s = exp(log_scale),
+    times ``weight``.  Returns (E_iso, dE_iso/dlog_scales (3, N))."""
+    ls = _t(log_scales).requires_grad_(True)
+    s = torch.exp(ls)
+    # s_j - (s_0 + s_1 + s_2) / 3 written as a third of s_j's differences to the
+    # other two: the same value, exactly 0 when the three scales are equal
+    d = torch.stack([(s[0] - s[1]) + (s[0] - s[2]), (s[1] - s[0]) + (s[1] - s[2]),
+                     (s[2] - s[0]) + (s[2] - s[1])]) / 3.0
+    E = weight * d.abs().mean()
+    E.backward()
+    return float(E.detach()), ls.grad.numpy()
+
+
+def prune_keep(opacity_logits, min_opacity: float = PRUNE_OPACITY):
+    """Gaussians kept by the opacity rule of the pruning step (Sec. III-B2):
+    opacity sigmoid(logit) not below ``min_opacity``.  The occupancy rule
+    (Gaussian mixture regression on free-space Gaussians) is not part of this
+    reading."""
+    o = 1.0 / (1.0 + np.exp(-np.asarray(opacity_logits, np.float64)))
+    return o >= min_opacity
+
+
+def pose_adam_step(R, t, g, m, v, lr_trans, lr_rot, beta1, beta2, eps, step):
+    """The pose step of the mapping objectives (which minimise over the
+    keyframe poses T_k, Eq. 2 and Eq. 3): one bias-corrected Adam step on the
+    left-perturbation tangent xi = (rho, phi) from its gradient g (6,), with
+    rate lr_trans on rho and lr_rot on phi, then T <- Exp(delta) T.  Returns
+    the new (R, t, m, v) in float64."""
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1 - beta2) * g * g
+    lr = np.r_[[lr_trans] * 3, [lr_rot] * 3]
+    delta = -lr * (m / (1 - beta1 ** step)) / (np.sqrt(v / (1 - beta2 ** step)) + eps)
+    E = se3_exp(torch.as_tensor(delta)).numpy()
+    T = np.eye(4)
+    T[:3, :3] = np.asarray(R, np.float64).reshape(3, 3)
+    T[:3, 3] = np.asarray(t, np.float64).reshape(3)
+    Tn = E @ T
+    return Tn[:3, :3], Tn[:3, 3], m, v
 
 
 # ---------------------------------------------------------------------------

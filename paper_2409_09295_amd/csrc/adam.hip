@@ -66,8 +66,11 @@ __device__ __forceinline__ bool dev_coef(const int32_t* step_dev, const uint32_t
   c.b1 = b1;
   c.b2 = b2;
   c.eps = eps;
-  c.inv_bc1 = 1.0f / (1.0f - powf(b1, t));
-  c.inv_bc2 = 1.0f / (1.0f - powf(b2, t));
+  // 1 - b^t = -expm1(t log1p(b - 1)): b - 1 is exact in float32, and this form
+  // avoids the cancellation of 1 - powf(b, t), which for b2 = 0.999 and small
+  // t loses about five of float32's digits
+  c.inv_bc1 = -1.0f / expm1f(t * log1pf(b1 - 1.0f));
+  c.inv_bc2 = -1.0f / expm1f(t * log1pf(b2 - 1.0f));
   return true;
 }
 
@@ -109,6 +112,10 @@ struct AdamGroups {
   int32_t vec[GS_ADAM_MAX_GROUPS];
   int64_t first[GS_ADAM_MAX_GROUPS + 1];
   int32_t count;
+  // optional per-Gaussian mask: element e of a group ([C][n_gauss] layout)
+  // belongs to Gaussian e % n_gauss and is updated only if its byte is nonzero
+  const uint8_t* gmask;
+  int64_t n_gauss;
 };
 
 __global__ __launch_bounds__(256) void adam_groups_kernel(AdamGroups G, float b1, float b2,
@@ -128,7 +135,18 @@ __global__ __launch_bounds__(256) void adam_groups_kernel(AdamGroups G, float b1
   const float* __restrict__ g = G.g[k];
   float* __restrict__ m = G.m[k];
   float* __restrict__ v = G.v[k];
-  if (G.vec[k] && i4 + 4 <= n) {
+  const uint8_t* __restrict__ gm = G.gmask;
+  uint32_t on = 0xFu;   // bit j: element i4 + j is updated
+  if (gm) {
+    int64_t r = i4 % G.n_gauss;
+    on = 0u;
+    for (int j = 0; j < 4; ++j) {
+      on |= (uint32_t)(gm[r] != 0) << j;
+      if (++r == G.n_gauss) r = 0;
+    }
+    if (on == 0u) return;
+  }
+  if (G.vec[k] && i4 + 4 <= n && on == 0xFu) {
     float4 pp = *reinterpret_cast<float4*>(p + i4);
     const float4 gg = *reinterpret_cast<const float4*>(g + i4);
     float4 mm = *reinterpret_cast<float4*>(m + i4);
@@ -143,6 +161,7 @@ __global__ __launch_bounds__(256) void adam_groups_kernel(AdamGroups G, float b1
     return;
   }
   for (int64_t i = i4; i < min(n, i4 + 4); ++i) {
+    if (!((on >> (i - i4)) & 1u)) continue;
     float pp = p[i], mm = m[i], vv = v[i];
     adam_one(pp, g[i], mm, vv, c);
     p[i] = pp;
@@ -239,9 +258,11 @@ hipError_t launch_adam_dev(float* p, const float* g, float* m, float* v, int64_t
 hipError_t launch_adam_groups(const gs_adam_group* groups, int n_groups, float beta1,
                               float beta2, float eps, int32_t* step_dev,
                               const uint32_t* guard_n_keys, int64_t guard_capacity,
-                              hipStream_t s) {
+                              hipStream_t s, const uint8_t* gauss_mask, int64_t n_gauss) {
   AdamGroups G{};
   G.count = n_groups;
+  G.gmask = gauss_mask;
+  G.n_gauss = gauss_mask ? n_gauss : 1;
   int64_t blocks = 0;
   for (int k = 0; k < n_groups; ++k) {
     const gs_adam_group& q = groups[k];

@@ -353,6 +353,135 @@ int gs_adam_step_groups_dev(const gs_adam_group* groups, int32_t n_groups, float
   return e == hipSuccess ? GS_OK : hip_fail(e, "gs_adam_step_groups_dev");
 }
 
+int gs_render_error(const gs_projected* p, int64_t n, const gs_bins* bins, const gs_views* views,
+                    const float* image, const float* target, const uint32_t* n_contrib,
+                    float* err, gs_stream_t stream) {
+  ViewTable vt;
+  int st = build_view_table(views, vt);
+  if (st) return st;
+  if (n < 0) return invalid("n = %lld < 0", (long long)n);
+  if ((uint64_t)n * (uint64_t)vt.n_views > 0xFFFFFFFFull)
+    return invalid("n * n_views exceeds 2^32 - 1");
+  if ((st = check_projected(p, n))) return st;
+  if ((st = check_bins(bins, false))) return st;
+  if (!image || !target || !n_contrib) return invalid("an input image pointer is NULL");
+  if (n > 0 && !err) return invalid("err is NULL");
+  const hipError_t e = launch_render_error(*p, n, *bins, vt, image, target, n_contrib, err, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_render_error");
+}
+
+int gs_active_set(const float* err, int64_t n, int32_t n_views, float eps, const uint8_t* always,
+                  uint8_t* mask, float* err_max, uint32_t* n_active, gs_stream_t stream) {
+  if (n < 0) return invalid("n = %lld < 0", (long long)n);
+  if (n_views < 1 || n_views > GS_MAX_VIEWS)
+    return invalid("n_views = %d outside [1, %d]", n_views, GS_MAX_VIEWS);
+  if (!std::isfinite(eps)) return invalid("eps must be finite");
+  if (n > 0 && (!err || !mask)) return invalid("err or mask is NULL");
+  const hipError_t e =
+      launch_active_set(err, n, n_views, eps, always, mask, err_max, n_active, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_active_set");
+}
+
+int gs_adam_step_groups_masked_dev(const gs_adam_group* groups, int32_t n_groups, float beta1,
+                                   float beta2, float eps, int32_t* step_dev,
+                                   const uint8_t* gauss_mask, int64_t n_gauss,
+                                   const uint32_t* guard_n_keys, int64_t guard_capacity,
+                                   gs_stream_t stream) {
+  if (!groups) return invalid("groups is NULL");
+  if (n_groups < 1 || n_groups > GS_ADAM_MAX_GROUPS)
+    return invalid("n_groups = %d outside 1..%d", n_groups, GS_ADAM_MAX_GROUPS);
+  if (n_gauss < 1) return invalid("n_gauss = %lld < 1", (long long)n_gauss);
+  if (!gauss_mask) return invalid("gauss_mask is NULL");
+  for (int k = 0; k < n_groups; ++k) {
+    const gs_adam_group& q = groups[k];
+    if (q.n < 0 || q.n % n_gauss)
+      return invalid("group %d: n = %lld is not a multiple of n_gauss", k, (long long)q.n);
+    if (q.n > 0 && (!q.p || !q.g || !q.m || !q.v)) return invalid("group %d: a pointer is NULL", k);
+    if (!std::isfinite(q.lr)) return invalid("group %d: lr is not finite", k);
+  }
+  if (!step_dev) return invalid("step_dev is NULL");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f))
+    return invalid("betas must lie in [0, 1)");
+  if (!(eps >= 0.f)) return invalid("eps must be >= 0");
+  if (guard_n_keys && guard_capacity < 0) return invalid("guard_capacity < 0");
+  const hipError_t e = launch_adam_groups(groups, n_groups, beta1, beta2, eps, step_dev,
+                                          guard_n_keys, guard_capacity, stream, gauss_mask,
+                                          n_gauss);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_adam_step_groups_masked_dev");
+}
+
+int gs_concat(const gs_concat_array* arrays, int32_t n_arrays, int64_t n_a, int64_t n_b,
+              gs_stream_t stream) {
+  if (!arrays) return invalid("arrays is NULL");
+  if (n_arrays < 1 || n_arrays > GS_SOA_MAX_ARRAYS)
+    return invalid("n_arrays = %d outside 1..%d", n_arrays, GS_SOA_MAX_ARRAYS);
+  if (n_a < 0 || n_b < 0) return invalid("n_a and n_b must be >= 0");
+  for (int k = 0; k < n_arrays; ++k) {
+    const gs_concat_array& q = arrays[k];
+    if (q.components < 1) return invalid("array %d: components < 1", k);
+    if (n_a + n_b > 0 && !q.dst) return invalid("array %d: dst is NULL", k);
+    if (n_a > 0 && !q.a) return invalid("array %d: a is NULL", k);
+  }
+  const hipError_t e = launch_concat(arrays, n_arrays, n_a, n_b, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_concat");
+}
+
+int gs_prune_mask(const float* opacity_logits, int64_t n, float min_opacity, uint8_t* keep,
+                  gs_stream_t stream) {
+  if (n < 0) return invalid("n = %lld < 0", (long long)n);
+  if (!(min_opacity > 0.f && min_opacity < 1.f)) return invalid("min_opacity must lie in (0, 1)");
+  if (n > 0 && (!opacity_logits || !keep)) return invalid("a pointer is NULL");
+  const double p = (double)min_opacity;
+  const float thr = (float)std::log(p / (1.0 - p));
+  const hipError_t e = launch_prune_mask(opacity_logits, n, thr, keep, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_prune_mask");
+}
+
+size_t gs_compact_workspace_size(int64_t n) { return n < 0 ? 0 : compact_ws_bytes(n); }
+
+int gs_compact(const gs_compact_array* arrays, int32_t n_arrays, int64_t n, const uint8_t* keep,
+               uint32_t* n_kept, void* workspace, size_t workspace_bytes, gs_stream_t stream) {
+  if (!arrays) return invalid("arrays is NULL");
+  if (n_arrays < 1 || n_arrays > GS_SOA_MAX_ARRAYS)
+    return invalid("n_arrays = %d outside 1..%d", n_arrays, GS_SOA_MAX_ARRAYS);
+  if (n < 0 || n > 0xFFFFFFFFll) return invalid("n = %lld outside [0, 2^32 - 1]", (long long)n);
+  if (!n_kept) return invalid("n_kept is NULL");
+  if (n > 0 && !keep) return invalid("keep is NULL");
+  for (int k = 0; k < n_arrays; ++k) {
+    const gs_compact_array& q = arrays[k];
+    if (q.components < 1) return invalid("array %d: components < 1", k);
+    if (n > 0 && (!q.src || !q.dst)) return invalid("array %d: a pointer is NULL", k);
+  }
+  int st;
+  if ((st = check_workspace(workspace, workspace_bytes, compact_ws_bytes(n)))) return st;
+  const hipError_t e = launch_compact(arrays, n_arrays, n, keep, n_kept, workspace, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_compact");
+}
+
+int gs_pose_adam_step(gs_camera* cams_dev, const float* grad_xi, float* m, float* v,
+                      int32_t n_views, const uint8_t* view_mask, float lr_trans, float lr_rot,
+                      float beta1, float beta2, float eps, int32_t* step_dev, gs_stream_t stream) {
+  if (n_views < 1 || n_views > GS_MAX_VIEWS)
+    return invalid("n_views = %d outside [1, %d]", n_views, GS_MAX_VIEWS);
+  if (!cams_dev || !grad_xi || !m || !v || !step_dev) return invalid("a pointer is NULL");
+  if (!(std::isfinite(lr_trans) && std::isfinite(lr_rot))) return invalid("learning rates must be finite");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f))
+    return invalid("betas must lie in [0, 1)");
+  if (!(eps >= 0.f)) return invalid("eps must be >= 0");
+  const hipError_t e = launch_pose_adam(cams_dev, grad_xi, m, v, n_views, view_mask, lr_trans,
+                                        lr_rot, beta1, beta2, eps, step_dev, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_pose_adam_step");
+}
+
+int gs_iso_loss_grad(const float* log_scales, int64_t n, float weight, float* grad_log_scales,
+                     double* loss, gs_stream_t stream) {
+  if (n < 0) return invalid("n = %lld < 0", (long long)n);
+  if (!std::isfinite(weight)) return invalid("weight must be finite");
+  if (n > 0 && (!log_scales || !grad_log_scales)) return invalid("a pointer is NULL");
+  const hipError_t e = launch_iso_loss_grad(log_scales, n, weight, grad_log_scales, loss, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_iso_loss_grad");
+}
+
 int gs_l1_loss_grad(const float* image, const float* target, const gs_views* views,
                     float* dL_dimage, double* loss, gs_stream_t stream) {
   ViewTable vt;

@@ -243,14 +243,38 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
                        float beta1, float beta2, float eps, int32_t step, const uint8_t* mask,
                        hipStream_t s);
 
+// gauss_mask (optional): per-Gaussian update mask over groups laid out
+// [C][n_gauss] (element e belongs to Gaussian e % n_gauss).
 hipError_t launch_adam_groups(const gs_adam_group* groups, int n_groups, float beta1,
                               float beta2, float eps, int32_t* step_dev,
                               const uint32_t* guard_n_keys, int64_t guard_capacity,
-                              hipStream_t s);
+                              hipStream_t s, const uint8_t* gauss_mask = nullptr,
+                              int64_t n_gauss = 0);
 hipError_t launch_adam_dev(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                            float beta1, float beta2, float eps, int32_t* step_dev, int32_t commit,
                            const uint8_t* mask, const uint32_t* guard_n_keys,
                            int64_t guard_capacity, hipStream_t s);
+
+hipError_t launch_render_error(const gs_projected& p, int64_t n, const gs_bins& bins,
+                               const ViewTable& vt, const float* image, const float* target,
+                               const uint32_t* n_contrib, float* err, hipStream_t s);
+hipError_t launch_active_set(const float* err, int64_t n, int n_views, float eps,
+                             const uint8_t* always, uint8_t* mask, float* err_max,
+                             uint32_t* n_active, hipStream_t s);
+
+hipError_t launch_concat(const gs_concat_array* arrays, int n_arrays, int64_t na, int64_t nb,
+                         hipStream_t s);
+hipError_t launch_prune_mask(const float* ologit, int64_t n, float min_logit, uint8_t* keep,
+                             hipStream_t s);
+size_t compact_ws_bytes(int64_t n);
+hipError_t launch_compact(const gs_compact_array* arrays, int n_arrays, int64_t n,
+                          const uint8_t* keep, uint32_t* n_kept, void* ws, hipStream_t s);
+hipError_t launch_pose_adam(gs_camera* cams_dev, const float* grad_xi, float* m, float* v,
+                            int n_views, const uint8_t* view_mask, float lr_trans, float lr_rot,
+                            float beta1, float beta2, float eps, int32_t* step_dev,
+                            hipStream_t s);
+hipError_t launch_iso_loss_grad(const float* log_scales, int64_t n, float weight,
+                                float* grad_log_scales, double* loss, hipStream_t s);
 
 hipError_t launch_l1_loss_grad(const float* image, const float* target, const ViewTable& vt,
                                float* dL_dimage, double* loss, hipStream_t s);

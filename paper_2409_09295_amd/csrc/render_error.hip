@@ -1,0 +1,196 @@
+// gs_render_error and gs_active_set: the per-Gaussian rendering error of the
+// global stage's active-set selection (Sec. III-B2) and its thresholding.
+//
+// The error of splat g in view k sums, over the pixels g blends into, its
+// blending weight w = alpha T times the pixel's L1 colour residual between
+// the render and the view's reference image.  The walk is the forward's:
+// one workgroup per 16x16 tile (4 wavefronts, one 8x8 quadrant each), the
+// tile's sorted splats staged 256 at a time in LDS with their quadrant
+// reach masks, every pixel walking its list front to back.  A pixel blends
+// exactly the splats at list positions below its n_contrib that pass the
+// alpha test (the forward stopped after its last blended splat), and its
+// transmittance is updated with the forward's own float32 operations, so
+// every weight equals the forward's bit for bit.  Per splat, the wave's
+// w * residual products are summed with DPP and added to the splat's error
+// by one lane.
+#include "gs_internal.h"
+
+namespace gsmi {
+
+namespace {
+
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ float dpp_or_zero(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, BANK_MASK, false));
+}
+
+// Sum over the 64 lanes of a wavefront; the total lands in lane 63.
+__device__ __forceinline__ float wave_sum_to_lane63(float x) {
+  x += dpp_or_zero<0xb1, 0xf, 0xf>(x);   // quad_perm [1,0,3,2]
+  x += dpp_or_zero<0x4e, 0xf, 0xf>(x);   // quad_perm [2,3,0,1]
+  x += dpp_or_zero<0x124, 0xf, 0xf>(x);  // row_ror:4
+  x += dpp_or_zero<0x128, 0xf, 0xf>(x);  // row_ror:8 -> every lane holds its row sum
+  x += dpp_or_zero<0x142, 0xa, 0xf>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_or_zero<0x143, 0xc, 0xf>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ uint32_t stage_splat(uint32_t g, const float2* __restrict__ xy,
+                                                const float4* __restrict__ co,
+                                                const float4* __restrict__ rd, int tx0, int ty0,
+                                                int W, int H, StagedSplat& out) {
+  const float2 m = xy[g];
+  const float4 c = co[g];
+  const float4 r = rd[g];
+  const uint32_t reach = quadrant_mask(m.x, m.y, c.x, c.y, c.z, c.w, tx0, ty0, W, H);
+  out.geo = make_float4(m.x, m.y, -0.5f * kLog2e * c.x, -kLog2e * c.y);
+  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.x, r.y);
+  out.ext = make_float4(r.z, __uint_as_float(reach), r.w, __uint_as_float(g));
+  return reach;
+}
+
+constexpr int kStage = 256;
+constexpr int kWords = kStage / 64;
+
+__global__ __launch_bounds__(kBlock) void render_error_kernel(
+    ViewTable vt, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
+    const uint32_t* __restrict__ order, const float2* __restrict__ xy,
+    const float4* __restrict__ co, const float4* __restrict__ rd, const float* __restrict__ image,
+    const float* __restrict__ target, const uint32_t* __restrict__ n_contrib,
+    float* __restrict__ err) {
+  __shared__ StagedSplat s_splat[kStage];
+  __shared__ uint64_t s_reach[4][kWords];   // bit b of [q][w]: staged splat 64 w + b reaches q
+  __shared__ uint32_t s_maxlast;
+  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+  if (tile >= vt.n_tiles) return;
+  const int v = find_view(vt, tile);
+  const ViewInfo& vi = vt.v[v];
+  const int lt = tile - vi.tile_base;
+  const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int px = tx * kTile + (q & 1) * 8 + (lane & 7);
+  const int py = ty * kTile + (q >> 1) * 8 + (lane >> 3);
+  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  float resid = 0.0f;   // L1 colour residual of the pixel
+  uint32_t last = 0;
+  if (px < vi.width && py < vi.height) {
+    const int64_t plane = (int64_t)vi.width * vi.height;
+    const int64_t off = (int64_t)py * vi.width + px;
+    const int64_t o = 3 * vi.pix_base + off;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) resid += fabsf(image[o + ch * plane] - target[o + ch * plane]);
+    last = n_contrib[vi.pix_base + off];
+  }
+  // positions this wave walks: below the largest n_contrib of its pixels
+  uint32_t wl = last;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) wl = max(wl, (uint32_t)__shfl_xor((int)wl, d, 64));
+  const uint32_t wave_last = __builtin_amdgcn_readfirstlane(wl);
+  if (threadIdx.x == 0) s_maxlast = 0;
+  __syncthreads();
+  if (lane == 0 && wave_last) atomicMax(&s_maxlast, wave_last);
+  __syncthreads();
+  const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
+  // n_contrib never exceeds the list length for a matching forward; the
+  // clamp keeps every list read inside [s, e) regardless
+  const int64_t list_len = (int64_t)e - (int64_t)s;
+  const int64_t maxlast = min((int64_t)s_maxlast, max(list_len, (int64_t)0));
+  float T = 1.0f;
+  for (int64_t b = 0; b < maxlast; b += kStage) {
+    __syncthreads();
+    const int64_t k = b + threadIdx.x;
+    uint32_t reach = 0;
+    if (k < maxlast)
+      reach = stage_splat(values[s + (uint32_t)k], xy, co, rd, tx * kTile, ty * kTile, vi.width,
+                          vi.height, s_splat[threadIdx.x]);
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const uint64_t bq = __ballot((reach >> qq) & 1u);
+      if (lane == 0) s_reach[qq][threadIdx.x >> 6] = bq;
+    }
+    __syncthreads();
+    for (int w = 0; w < kWords; ++w) {
+      const int64_t lim = (int64_t)wave_last - b - 64 * w;   // allowed bits: j < lim
+      if (lim <= 0) break;
+      uint64_t m = uniform_u64(s_reach[q][w]);
+      if (lim < 64) m &= (uint64_t(1) << lim) - 1;
+      while (m) {
+        const int j = 64 * w + __builtin_ctzll(m);
+        m &= m - 1;
+        const uint32_t pos = (uint32_t)(b + j);
+        const float4 geo = s_splat[j].geo;
+        const float4 app = s_splat[j].app;
+        const ColumnTerms ct = column_terms(geo, fpx);
+        float alpha, raw, G, dy;
+        const bool ok = eval_alpha_at<false>(ct, geo, app, fpy, alpha, raw, G, dy) && pos < last;
+        if (!__ballot(ok)) continue;
+        const float wgt = ok ? alpha * T : 0.0f;
+        if (ok) T = T * (1.0f - alpha);
+        const float tot = wave_sum_to_lane63(wgt * resid);
+        if (lane == 63) {
+          const uint32_t acc = __float_as_uint(s_splat[j].ext.w);
+          unsafeAtomicAdd(err + acc, tot);
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_f32_kernel(float* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0f;
+}
+
+// One lane per Gaussian: the largest error over the views, compared with eps.
+__global__ __launch_bounds__(256) void active_set_kernel(
+    const float* __restrict__ err, int64_t n, int n_views, float eps,
+    const uint8_t* __restrict__ always, uint8_t* __restrict__ mask, float* __restrict__ err_max,
+    uint32_t* __restrict__ n_active) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool on = false;
+  if (i < n) {
+    float mx = err[i];
+    for (int v = 1; v < n_views; ++v) mx = fmaxf(mx, err[(int64_t)v * n + i]);
+    on = mx > eps || (always && always[i] != 0);
+    mask[i] = on ? 1 : 0;
+    if (err_max) err_max[i] = mx;
+  }
+  if (n_active) {
+    const uint64_t b = __ballot(on);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(n_active, (uint32_t)__popcll(b));
+  }
+}
+
+__global__ void zero_u32_kernel(uint32_t* p) { *p = 0u; }
+
+}  // namespace
+
+hipError_t launch_render_error(const gs_projected& p, int64_t n, const gs_bins& bins,
+                               const ViewTable& vt, const float* image, const float* target,
+                               const uint32_t* n_contrib, float* err, hipStream_t s) {
+  const int64_t entries = n * (int64_t)vt.n_views;
+  if (entries > 0)
+    hipLaunchKernelGGL(fill_f32_kernel, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0, s,
+                       err, entries);
+  if (vt.n_tiles > 0 && n > 0)
+    hipLaunchKernelGGL(render_error_kernel, dim3((unsigned)vt.n_tiles), dim3(kBlock), 0, s, vt,
+                       bins.ranges, bins.values, bins.order,
+                       reinterpret_cast<const float2*>(p.xy),
+                       reinterpret_cast<const float4*>(p.conic_opacity),
+                       reinterpret_cast<const float4*>(p.rgb_depth), image, target, n_contrib,
+                       err);
+  return hipGetLastError();
+}
+
+hipError_t launch_active_set(const float* err, int64_t n, int n_views, float eps,
+                             const uint8_t* always, uint8_t* mask, float* err_max,
+                             uint32_t* n_active, hipStream_t s) {
+  if (n_active) hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, n_active);
+  if (n > 0)
+    hipLaunchKernelGGL(active_set_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, err,
+                       n, n_views, eps, always, mask, err_max, n_active);
+  return hipGetLastError();
+}
+
+}  // namespace gsmi

@@ -140,12 +140,51 @@ _lib.gs_adam_step_groups_dev.argtypes = [ctypes.POINTER(gs_adam_group), ctypes.c
                                          ctypes.c_float, ctypes.c_float, ctypes.c_float, _p, _p,
                                          ctypes.c_int64, _S]
 
+_lib.gs_render_error.argtypes = [ctypes.POINTER(gs_projected), ctypes.c_int64, ctypes.POINTER(gs_bins),
+                                 ctypes.POINTER(gs_views), _p, _p, _p, _p, _S]
+_lib.gs_active_set.argtypes = [_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, _p, _p, _p, _p, _S]
+_lib.gs_adam_step_groups_masked_dev.argtypes = [ctypes.POINTER(gs_adam_group), ctypes.c_int32,
+                                                ctypes.c_float, ctypes.c_float, ctypes.c_float, _p, _p,
+                                                ctypes.c_int64, _p, ctypes.c_int64, _S]
+
+
+class gs_concat_array(ctypes.Structure):
+    _fields_ = [("a", _p), ("b", _p), ("dst", _p), ("components", ctypes.c_int32),
+                ("fill", ctypes.c_float)]
+
+
+class gs_compact_array(ctypes.Structure):
+    _fields_ = [("src", _p), ("dst", _p), ("components", ctypes.c_int32)]
+
+
+GS_SOA_MAX_ARRAYS = 16
+_lib.gs_concat.argtypes = [ctypes.POINTER(gs_concat_array), ctypes.c_int32, ctypes.c_int64,
+                           ctypes.c_int64, _S]
+_lib.gs_prune_mask.argtypes = [_p, ctypes.c_int64, ctypes.c_float, _p, _S]
+_lib.gs_compact_workspace_size.restype = ctypes.c_size_t
+_lib.gs_compact_workspace_size.argtypes = [ctypes.c_int64]
+_lib.gs_compact.argtypes = [ctypes.POINTER(gs_compact_array), ctypes.c_int32, ctypes.c_int64, _p, _p,
+                            _p, ctypes.c_size_t, _S]
+_lib.gs_iso_loss_grad.argtypes = [_p, ctypes.c_int64, ctypes.c_float, _p, _p, _S]
+_lib.gs_pose_adam_step.argtypes = [_p, _p, _p, _p, ctypes.c_int32, _p, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_float, ctypes.c_float, _p, _S]
+
+GS_MEM_MAP, GS_MEM_KEYFRAMES, GS_MEM_POSES, GS_MEM_INIT = 0, 1, 2, 3
+GS_MEM_RENDER_TARGETS, GS_MEM_BLEND_STATE, GS_MEM_OPTIMISER, GS_MEM_CATEGORIES = 4, 5, 6, 7
+MEM_CATEGORY_NAMES = ("map", "keyframes", "poses", "init", "render_targets", "blend_state", "optimiser")
+_lib.gs_mem_track.argtypes = [ctypes.c_int32, ctypes.c_int64]
+_lib.gs_mem_report.argtypes = [_p, _p, _p, _p]
+_lib.gs_mem_reset_peaks.argtypes = []
+
 EXPORTED = ("gs_status_string", "gs_last_error", "gs_version", "gs_num_tiles", "gs_num_pixels",
             "gs_preprocess", "gs_bin_sort_workspace_size", "gs_bin_sort", "gs_render_fwd",
             "gs_render_bwd_workspace_size", "gs_render_bwd", "gs_adam_step", "gs_l1_loss_grad",
             "gs_set_kernel_events", "gs_adam_step_dev", "gs_adam_step_groups_dev",
             "gs_render_fwd_l1_workspace_size", "gs_render_fwd_l1",
-            "gs_set_tuning", "gs_get_tuning")
+            "gs_set_tuning", "gs_get_tuning", "gs_render_error", "gs_active_set",
+            "gs_adam_step_groups_masked_dev", "gs_concat", "gs_prune_mask",
+            "gs_compact_workspace_size", "gs_compact", "gs_iso_loss_grad", "gs_pose_adam_step",
+            "gs_mem_track", "gs_mem_report", "gs_mem_reset_peaks")
 
 
 def lib() -> ctypes.CDLL:
@@ -208,6 +247,13 @@ class Views:
         self.records = recs
         ctypes.memmove(self._host, recs.ctypes.data, recs.nbytes)
         self.dev.copy_(torch.from_numpy(recs.view(np.uint8).copy()))
+
+    def download_poses(self):
+        """Host records <- device records (after poses were moved on the device)."""
+        recs = self.dev.cpu().numpy().view(self.records.dtype).copy()
+        self.records = recs
+        ctypes.memmove(self._host, recs.ctypes.data, recs.nbytes)
+        return recs
 
     @property
     def n_tiles(self) -> int:
@@ -469,6 +515,151 @@ def gs_adam_step_groups_dev(groups, beta1: float, beta2: float, eps: float, step
     _check(_lib.gs_adam_step_groups_dev(groups, len(groups), beta1, beta2, eps, _ptr(step_dev),
                                         _ptr(guard_n_keys), guard_capacity, _stream(stream)),
            "gs_adam_step_groups_dev")
+
+
+def gs_render_error(p: Projected, n: int, bins: Bins, views: Views, image: torch.Tensor,
+                    target: torch.Tensor, n_contrib: torch.Tensor, err: torch.Tensor,
+                    stream=None) -> None:
+    """err: float32 (V, n), overwritten with E_k(g)."""
+    if err.dtype != torch.float32 or err.numel() != views.n_views * n:
+        raise ValueError("err must be float32 with n_views * n entries")
+    ps, bs = p.struct(), bins.struct()
+    _check(_lib.gs_render_error(ctypes.byref(ps), n, ctypes.byref(bs), ctypes.byref(views.struct),
+                                _ptr(image), _ptr(target), _ptr(n_contrib), _ptr(err), _stream(stream)),
+           "gs_render_error")
+
+
+def gs_active_set(err: torch.Tensor, n: int, n_views: int, eps: float, mask: torch.Tensor,
+                  always: Optional[torch.Tensor] = None, err_max: Optional[torch.Tensor] = None,
+                  n_active: Optional[torch.Tensor] = None, stream=None) -> None:
+    if err.dtype != torch.float32 or err.numel() < n_views * n:
+        raise ValueError("err must be float32 with n_views * n entries")
+    if mask.dtype != torch.uint8 or mask.numel() < n:
+        raise ValueError("mask must be uint8 with n entries")
+    if always is not None and (always.dtype != torch.uint8 or always.numel() < n):
+        raise ValueError("always must be uint8 with n entries")
+    _check(_lib.gs_active_set(_ptr(err), n, n_views, eps, _ptr(always), _ptr(mask), _ptr(err_max),
+                              _ptr(n_active), _stream(stream)), "gs_active_set")
+
+
+def gs_adam_step_groups_masked_dev(groups, beta1: float, beta2: float, eps: float,
+                                   step_dev: torch.Tensor, gauss_mask: torch.Tensor, n_gauss: int,
+                                   guard_n_keys: Optional[torch.Tensor] = None,
+                                   guard_capacity: int = 0, stream=None) -> None:
+    """groups: an array from adam_groups(); gauss_mask: uint8 [n_gauss]."""
+    if step_dev.dtype != torch.int32 or step_dev.numel() != 1:
+        raise ValueError("step_dev must be one int32")
+    if gauss_mask.dtype != torch.uint8 or gauss_mask.numel() != n_gauss:
+        raise ValueError("gauss_mask must be uint8 with n_gauss entries")
+    _check(_lib.gs_adam_step_groups_masked_dev(groups, len(groups), beta1, beta2, eps, _ptr(step_dev),
+                                               _ptr(gauss_mask), n_gauss, _ptr(guard_n_keys),
+                                               guard_capacity, _stream(stream)),
+           "gs_adam_step_groups_masked_dev")
+
+
+def gs_concat(arrays: Sequence[Tuple[torch.Tensor, Optional[torch.Tensor], torch.Tensor, int, float]],
+              n_a: int, n_b: int, stream=None) -> None:
+    """arrays: (a [C*n_a], b [C*n_b] or None, dst [C*(n_a+n_b)], C, fill) tuples."""
+    arr = (gs_concat_array * len(arrays))()
+    for k, (a, b, dst, c, fill) in enumerate(arrays):
+        if a.numel() != c * n_a or dst.numel() != c * (n_a + n_b) or (b is not None and b.numel() != c * n_b):
+            raise ValueError(f"array {k}: sizes do not match the component count")
+        for t in (a, b, dst):
+            if t is not None and t.dtype != torch.float32:
+                raise ValueError("arrays are float32")
+        arr[k] = gs_concat_array(_ptr(a), _ptr(b), _ptr(dst), c, fill)
+    _check(_lib.gs_concat(arr, len(arrays), n_a, n_b, _stream(stream)), "gs_concat")
+
+
+def gs_prune_mask(opacity_logits: torch.Tensor, min_opacity: float, keep: torch.Tensor,
+                  stream=None) -> None:
+    n = opacity_logits.numel()
+    if keep.dtype != torch.uint8 or keep.numel() < n:
+        raise ValueError("keep must be uint8 with n entries")
+    _check(_lib.gs_prune_mask(_ptr(opacity_logits), n, min_opacity, _ptr(keep), _stream(stream)),
+           "gs_prune_mask")
+
+
+def gs_compact_workspace_size(n: int) -> int:
+    return int(_lib.gs_compact_workspace_size(n))
+
+
+def gs_compact(arrays: Sequence[Tuple[torch.Tensor, torch.Tensor, int]], n: int, keep: torch.Tensor,
+               n_kept: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
+    """arrays: (src [C*n], dst [>= C*n], C) tuples; n_kept: int32 [1] (device)."""
+    arr = (gs_compact_array * len(arrays))()
+    for k, (src, dst, c) in enumerate(arrays):
+        if src.numel() != c * n or dst.numel() < c * n:
+            raise ValueError(f"array {k}: sizes do not match the component count")
+        arr[k] = gs_compact_array(_ptr(src), _ptr(dst), c)
+    _check(_lib.gs_compact(arr, len(arrays), n, _ptr(keep), _ptr(n_kept), _ptr(ws), ws.numel(),
+                           _stream(stream)), "gs_compact")
+
+
+def gs_iso_loss_grad(log_scales: torch.Tensor, weight: float, grad_log_scales: torch.Tensor,
+                     loss: Optional[torch.Tensor] = None, stream=None) -> None:
+    n = log_scales.shape[-1]
+    if log_scales.numel() != 3 * n or grad_log_scales.numel() != 3 * n:
+        raise ValueError("log-scales and their gradient are [3][n]")
+    _check(_lib.gs_iso_loss_grad(_ptr(log_scales), n, weight, _ptr(grad_log_scales), _ptr(loss),
+                                 _stream(stream)), "gs_iso_loss_grad")
+
+
+def gs_pose_adam_step(views: Views, grad_xi: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                      step_dev: torch.Tensor, lr_trans: float, lr_rot: float, beta1: float = 0.9,
+                      beta2: float = 0.999, eps: float = 1e-15,
+                      view_mask: Optional[torch.Tensor] = None, stream=None) -> None:
+    """Moves the device poses of ``views`` (their host records keep the old
+    poses; ``Views.download_poses`` refreshes them)."""
+    V = views.n_views
+    for t in (grad_xi, m, v):
+        if t.dtype != torch.float32 or t.numel() != 6 * V:
+            raise ValueError("grad_xi, m, v must be float32 [n_views][6]")
+    _check(_lib.gs_pose_adam_step(views.dev.data_ptr(), _ptr(grad_xi), _ptr(m), _ptr(v), V,
+                                  _ptr(view_mask), lr_trans, lr_rot, beta1, beta2, eps, _ptr(step_dev),
+                                  _stream(stream)), "gs_pose_adam_step")
+
+
+def gs_mem_track(category: int, nbytes: int) -> None:
+    _check(_lib.gs_mem_track(category, int(nbytes)), "gs_mem_track")
+
+
+def gs_mem_report() -> dict:
+    cur = (ctypes.c_int64 * GS_MEM_CATEGORIES)()
+    peak = (ctypes.c_int64 * GS_MEM_CATEGORIES)()
+    oc, op = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(_lib.gs_mem_report(cur, peak, ctypes.byref(oc), ctypes.byref(op)), "gs_mem_report")
+    return {"current": dict(zip(MEM_CATEGORY_NAMES, list(cur))),
+            "peak": dict(zip(MEM_CATEGORY_NAMES, list(peak))),
+            "overhead_current": oc.value, "overhead_peak": op.value}
+
+
+def gs_mem_reset_peaks() -> None:
+    _check(_lib.gs_mem_reset_peaks(), "gs_mem_reset_peaks")
+
+
+class Tracked:
+    """Registers a buffer's bytes in the overhead-memory ledger for as long
+    as this object lives (the constructor/destructor accounting the paper's
+    memory profiler uses).  ``release()`` ends the registration early."""
+
+    def __init__(self, category: int, t_or_bytes):
+        self.category = category
+        self.nbytes = int(t_or_bytes.numel() * t_or_bytes.element_size()
+                          if isinstance(t_or_bytes, torch.Tensor) else t_or_bytes)
+        gs_mem_track(category, self.nbytes)
+        self._live = True
+
+    def release(self):
+        if self._live:
+            self._live = False
+            _lib.gs_mem_track(self.category, -self.nbytes)
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
 
 
 def gs_l1_loss_grad(image: torch.Tensor, target: torch.Tensor, views: Views, dL_dimage: torch.Tensor,

@@ -57,23 +57,37 @@ class _AdamState:
         for dst, src in zip(self.params + self.m + self.v + [self.step_dev], snap):
             dst.copy_(src)
 
-    def apply(self, grads: gs.Grads, guard_n_keys=None, guard_capacity: int = 0):
-        """One Adam step of every group in a single launch (graph-capture safe)."""
+    def apply(self, grads: gs.Grads, guard_n_keys=None, guard_capacity: int = 0,
+              active: Optional[torch.Tensor] = None):
+        """One Adam step of every group in a single launch (graph-capture safe);
+        with ``active`` (uint8 per Gaussian) only the active Gaussians move."""
         gl = [grads.means, grads.log_scales, grads.quats, grads.opacity_logits, grads.sh]
         key = tuple(t.data_ptr() for t in gl)
         if getattr(self, "_groups_key", None) != key:
             self._groups = gs.adam_groups(list(zip(self.params, gl, self.m, self.v, self.lrs)))
             self._groups_key = key
-        gs.gs_adam_step_groups_dev(self._groups, BETA1, BETA2, EPS, self.step_dev,
-                                   guard_n_keys=guard_n_keys, guard_capacity=guard_capacity)
+        if active is None:
+            gs.gs_adam_step_groups_dev(self._groups, BETA1, BETA2, EPS, self.step_dev,
+                                       guard_n_keys=guard_n_keys, guard_capacity=guard_capacity)
+        else:
+            gs.gs_adam_step_groups_masked_dev(self._groups, BETA1, BETA2, EPS, self.step_dev, active,
+                                              active.numel(), guard_n_keys=guard_n_keys,
+                                              guard_capacity=guard_capacity)
 
 
 class BatchedStep:
     def __init__(self, g: gs.Gaussians, views: gs.Views, targets: torch.Tensor, *,
                  lrs: Optional[Dict[str, float]] = None, capacity: Optional[int] = None,
                  headroom: float = 1.25, bg: Sequence[float] = (0.0, 0.0, 0.0),
-                 optimize: bool = True, pose: bool = True, use_graph: bool = True):
+                 optimize: bool = True, pose: bool = True, use_graph: bool = True,
+                 active: Optional[torch.Tensor] = None, iso_weight: float = 0.0):
+        """active: optional uint8 per-Gaussian mask; only active Gaussians are
+        updated (the selective optimisation of the global stage).  iso_weight:
+        weight of the isotropic regulariser added to the photometric loss (0:
+        none)."""
         self.g, self.views, self.bg = g, views, tuple(bg)
+        self.active = active
+        self.iso_weight = float(iso_weight)
         self.n = g.n
         self.targets = targets
         self.optimize, self.pose, self.use_graph = optimize, pose, use_graph
@@ -88,6 +102,7 @@ class BatchedStep:
         self.n_contrib = torch.zeros(P, dtype=torch.int32, device=dev)
         self.dL = torch.zeros(3 * P, dtype=torch.float32, device=dev)
         self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.iso_loss = torch.zeros(1, dtype=torch.float64, device=dev)
         # handed to every backward as clear (GS_BWD_KEEP_CLEAR): zeroed once here
         self.bwd_ws = gs.workspace(gs.gs_render_bwd_workspace_size(self.n, views), dev).zero_()
         self.l1_ws = gs.workspace(gs.gs_render_fwd_l1_workspace_size(views), dev)
@@ -99,6 +114,10 @@ class BatchedStep:
         self._alloc_bins(capacity)
         self.graph: Optional[torch.cuda.CUDAGraph] = None
         self.recaptures = 0
+        # optional work appended to every iteration (inside the graph), and
+        # device state it modifies, restored after the warm-up of a capture
+        self.post_body = None
+        self.extra_state = []
 
     # -- buffers ------------------------------------------------------------
     def _alloc_bins(self, capacity: int):
@@ -130,12 +149,18 @@ class BatchedStep:
                  | (0 if self.pose else gs.GS_BWD_NO_POSE))
         gs.gs_render_bwd(self.g, self.proj, self.bins, self.views, self.bg, self.dL, self.final_T,
                          self.n_contrib, self.grads, flags, self.bwd_ws)
+        if self.iso_weight:
+            gs.gs_iso_loss_grad(self.g.log_scales, self.iso_weight, self.grads.log_scales,
+                                self.iso_loss)
         if self.optimize:
-            self.adam.apply(self.grads, self.bins.n_keys, self.bins.capacity)
+            self.adam.apply(self.grads, self.bins.n_keys, self.bins.capacity, self.active)
+        if self.post_body is not None:
+            self.post_body()
 
     def capture(self):
         """Warm up eagerly (state restored afterwards), then capture one step."""
         snap = self.adam.snapshot()
+        extra = [t.clone() for t in self.extra_state]
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
@@ -143,6 +168,8 @@ class BatchedStep:
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         self.adam.restore(snap)
+        for dst, src in zip(self.extra_state, extra):
+            dst.copy_(src)
         torch.cuda.synchronize()
         # Collect unreachable cycles now: a dead step found by the collector
         # during the capture would free its graph's memory pool, and freeing

@@ -24,14 +24,41 @@ def random_dl(views_sizes, seed: int) -> np.ndarray:
     return np.concatenate(parts).astype(np.float32)
 
 
-def assert_grad_close(name, g, ref, rel=1e-3, floor=1e-3):
+U32 = 2.0 ** -24   # float32 unit roundoff
+
+
+def term_mass(gmap, cams, dls, tiles=None, bg=(0.0, 0.0, 0.0)):
+    """mass_fn for assert_grad_close: the oracle's absolute first-order mass
+    of the per-pixel terms of given gradient elements, and the longest list
+    walk among their pixels."""
+    from oracle import gs_oracle as O
+    N = gmap.n
+
+    def fn(group, flat):
+        comp, gi = np.divmod(np.asarray(flat, np.int64), N)
+        ids = sorted(set(gi.tolist()))
+        mass, walk = O.gradient_term_mass(gmap, cams, dls, ids, bg=bg, tiles=tiles)
+        row = {g: j for j, g in enumerate(ids)}
+        return np.array([mass[group][row[int(g)], int(c)] for c, g in zip(comp, gi)]), walk
+
+    return fn
+
+
+def assert_grad_close(name, g, ref, rel=1e-3, floor=1e-3, mass_fn=None):
     """GPU gradient vs the FP64 oracle, the parity contract for gradients:
     per element |g - ref| <= rel * max(|ref|, floor * max|ref|) and, over the
     group, ||g - ref||_2 <= rel ||ref||_2.  The floor (1e-3 of the group's
     largest magnitude) covers elements that are sums of cancelling per-pixel
-    terms, whose float32 value carries the summation's rounding of the terms
-    rather than 1e-3 of its own (tiny) size.  Prints the worst element's
-    ratio to its tolerance and the smallest floor that would have passed."""
+    terms.
+
+    mass_fn (optional): an element outside that bound is still accepted when
+    its terms cancel so strongly that float32 rounding alone explains the
+    error: |g - ref| <= u (walk + 64) mass, where mass is the oracle's exact
+    sum of the absolute values of the element's per-pixel terms (through the
+    splat's screen-space parameters), u = 2^-24, and walk + 64 counts the
+    roundings a term can collect (the transmittance recovered through up to
+    `walk` splats of the reverse walk, then a 64-lane reduction).  Prints how
+    many elements needed it.  The L2 bound has no exception."""
     g = np.asarray(g, np.float64).reshape(-1)
     ref = np.asarray(ref, np.float64).reshape(-1)
     scale = np.abs(ref).max() if ref.size else 0.0
@@ -43,9 +70,17 @@ def assert_grad_close(name, g, ref, rel=1e-3, floor=1e-3):
     bad = err > tol
     l2 = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     worst = int(np.argmax(err / tol))
-    need = float(np.max(err / (rel * scale)))   # floor under which every element passes
-    print(f"  {name}: rel L2 {l2:.2e}, worst err/tol {err[worst] / tol[worst]:.3f}, "
-          f"floor needed {need:.1e} (contract {floor:.0e})", flush=True)
+    extra = ""
+    if bad.any() and mass_fn is not None:
+        idx = np.nonzero(bad)[0]
+        mass, walk = mass_fn(name, idx)
+        bound = U32 * (walk + 64) * mass
+        ok = err[idx] <= bound
+        extra = (f", {len(idx)} outside the contract: {int(ok.sum())} within the float32 bound of "
+                 f"their cancelling terms (terms/value up to "
+                 f"{np.max(mass / np.maximum(np.abs(ref[idx]), 1e-300)):.0f}, walk {walk})")
+        bad[idx[ok]] = False
+    print(f"  {name}: rel L2 {l2:.2e}, worst err/tol {err[worst] / tol[worst]:.3f}{extra}", flush=True)
     msg = (f"{name}: {bad.sum()} of {g.size} elements outside tolerance; relative L2 {l2:.3e}; "
            f"worst index {worst}: gpu {g[worst]:.6e} ref {ref[worst]:.6e} tol {tol[worst]:.3e}")
     assert not bad.any(), msg
@@ -67,3 +102,8 @@ def assert_same_up_to_order(name, a, b, rel=1e-5, atol_frac=1e-5):
     worst = int(np.argmax(err / tol))
     assert (err <= tol).all(), (f"{name}: {(err > tol).sum()} of {a.size} elements differ; worst "
                                 f"index {worst}: {a[worst]:.6e} vs {b[worst]:.6e}")
+
+
+def f32(x: float) -> float:
+    """A hyperparameter as the C ABI receives it (a float32), in float64."""
+    return float(np.float32(x))

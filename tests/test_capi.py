@@ -250,3 +250,57 @@ def test_capacity_error_holds_no_reference_cycle(gs):
     finally:
         if was:
             gc.enable()
+
+
+def test_selective_entry_points_reject_bad_arguments(gs):
+    lib = gs.lib()
+    bad = gs.GS_ERR_INVALID_ARGUMENT
+    v = _views(gs, [(64, 48)])
+    proj = gs.gs_projected(FAKE, FAKE, FAKE, FAKE)
+    bins = gs.gs_bins(FAKE, FAKE, FAKE, FAKE, 100)
+    assert lib.gs_render_error(ctypes.byref(proj), 10, ctypes.byref(bins), ctypes.byref(v), FAKE,
+                               None, FAKE, FAKE, None) == bad              # no target
+    assert lib.gs_render_error(ctypes.byref(proj), 10, ctypes.byref(bins), ctypes.byref(v), FAKE,
+                               FAKE, FAKE, None, None) == bad              # no output
+    act = lambda n, views, eps: lib.gs_active_set(FAKE, n, views, ctypes.c_float(eps), None, FAKE,
+                                                   None, None, None)
+    assert act(10, 0, 1.0) == bad
+    assert act(10, 65, 1.0) == bad
+    assert act(-1, 1, 1.0) == bad
+    assert act(10, 1, float("nan")) == bad
+    assert lib.gs_active_set(FAKE, 10, 1, ctypes.c_float(1.0), None, None, None, None, None) == bad
+    grp = (gs.gs_adam_group * 2)()
+    grp[0] = gs.gs_adam_group(FAKE, FAKE, FAKE, FAKE, 30, 1e-3)
+    grp[1] = gs.gs_adam_group(FAKE, FAKE, FAKE, FAKE, 31, 1e-3)   # not a multiple of n_gauss
+    masked = lambda n_groups, mask, n_gauss: lib.gs_adam_step_groups_masked_dev(
+        grp, n_groups, ctypes.c_float(0.9), ctypes.c_float(0.999), ctypes.c_float(1e-15), FAKE, mask,
+        n_gauss, None, 0, None)
+    assert masked(2, FAKE, 10) == bad
+    assert masked(1, None, 10) == bad
+    assert masked(1, FAKE, 0) == bad
+
+
+def test_memory_ledger_tracks_current_and_peak(gs):
+    """Host-only ledger: per-category current and peak bytes, the overhead
+    total without the map, refused over-release, peak reset."""
+    lib = gs.lib()
+    gs.gs_mem_reset_peaks()
+    base = gs.gs_mem_report()
+    a = gs.Tracked(gs.GS_MEM_KEYFRAMES, 3 * 640 * 480 * 4)
+    b = gs.Tracked(gs.GS_MEM_INIT, 160 * 120 * 64 * 4)
+    m = gs.Tracked(gs.GS_MEM_MAP, 1000)
+    r = gs.gs_mem_report()
+    assert r["current"]["keyframes"] - base["current"]["keyframes"] == 3 * 640 * 480 * 4
+    assert r["overhead_current"] - base["overhead_current"] == 3 * 640 * 480 * 4 + 160 * 120 * 64 * 4
+    b.release()
+    del b
+    r2 = gs.gs_mem_report()
+    assert r2["overhead_peak"] - base["overhead_current"] == 3 * 640 * 480 * 4 + 160 * 120 * 64 * 4
+    assert r2["overhead_current"] - base["overhead_current"] == 3 * 640 * 480 * 4
+    assert r2["peak"]["init"] - base["current"]["init"] == 160 * 120 * 64 * 4
+    assert lib.gs_mem_track(gs.GS_MEM_POSES, -(r2["current"]["poses"] + 1)) == gs.GS_ERR_INVALID_ARGUMENT
+    assert lib.gs_mem_track(99, 1) == gs.GS_ERR_INVALID_ARGUMENT
+    del a, m
+    gs.gs_mem_reset_peaks()
+    r3 = gs.gs_mem_report()
+    assert r3["overhead_peak"] == r3["overhead_current"] == base["overhead_current"]

@@ -7,7 +7,8 @@ import torch
 
 from oracle import gs_oracle as O
 from paper_2409_09295_amd import scenes
-from tests.gpu_helpers import assert_grad_close, assert_same_up_to_order, np_, random_dl, u32, u64
+from tests.gpu_helpers import (assert_grad_close, assert_same_up_to_order, f32, np_, term_mass,
+                               random_dl, u32, u64)
 
 pytestmark = pytest.mark.gpu
 
@@ -365,10 +366,11 @@ def _grad_parity(gs, wl, seed, check_pose=True):
     _compare_images(views, out, res0)
     _log(f"grad parity {wl.name}: oracle backward")
     res = O.render(wl.gmap, ocams(wl), bg=wl.bg, dL_dimage=_split_dl(views, dl))
+    mass = term_mass(wl.gmap, ocams(wl), _split_dl(views, dl), bg=wl.bg)
     g = out["grads"]
     stats = {}
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
-        stats[name] = assert_grad_close(name, np_(getattr(g, name)), res["grads"][name])
+        stats[name] = assert_grad_close(name, np_(getattr(g, name)), res["grads"][name], mass_fn=mass)
     if check_pose:
         stats["xi"] = assert_grad_close("xi", np_(g.xi), res["grads"]["xi"])
     _log(f"grad parity {wl.name}: relative L2 {stats}")
@@ -433,9 +435,10 @@ def test_c3_sampled_tiles(gs):
     _log(f"c3 sampled image: masked {masked} px, worst {worst:.3e}")
     _log("c3: oracle backward on sampled tiles")
     res = O.render(wl.gmap, ocams(wl), dL_dimage=_split_dl(views, dl), tiles=[picks])
+    mass = term_mass(wl.gmap, ocams(wl), _split_dl(views, dl), tiles=[picks])
     g = out["grads"]
     for name in ("means", "log_scales", "quats", "opacity_logits", "sh"):
-        assert_grad_close(name, np_(getattr(g, name)), res["grads"][name])
+        assert_grad_close(name, np_(getattr(g, name)), res["grads"][name], mass_fn=mass)
     assert_grad_close("xi", np_(g.xi), res["grads"]["xi"])
 
 
@@ -490,7 +493,8 @@ def test_adam_step(gs, n, offset, masked):
     t = [torch.from_numpy(b).to(DEV)[offset:] for b in base]
     p, g, m, v = t
     for step in (1, 2, 7):
-        ref = O.adam_step(np_(p), np_(g), np_(m), np_(v), 1e-3, 0.9, 0.999, 1e-8, step, mask)
+        ref = O.adam_step(np_(p), np_(g), np_(m), np_(v), f32(1e-3), f32(0.9), f32(0.999), f32(1e-8),
+                          step, mask)
         gs.gs_adam_step(p, g, m, v, 1e-3, 0.9, 0.999, 1e-8, step,
                         torch.from_numpy(mask).to(DEV) if mask is not None else None)
         torch.cuda.synchronize()

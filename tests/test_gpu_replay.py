@@ -9,7 +9,8 @@ import torch
 
 from oracle import gs_oracle as O
 from paper_2409_09295_amd import scenes
-from tests.gpu_helpers import assert_grad_close, assert_same_up_to_order, np_, random_dl
+from tests.gpu_helpers import (assert_grad_close, assert_same_up_to_order, f32, np_, term_mass,
+                               random_dl)
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -194,9 +195,10 @@ def _timed_step_parity(gs, wl, view_ids, tiles_per_view, seed, max_masked):
     assert abs(float(step.loss.item()) - loss_ref) <= loss_tol, (float(step.loss.item()), loss_ref)
     _log(f"{wl.name}: oracle backward")
     res = O.render(wl.gmap, sub, bg=wl.bg, dL_dimage=sub_dl, tiles=picks)
+    mass = term_mass(wl.gmap, sub, sub_dl, tiles=picks, bg=wl.bg)
     gr = step.grads
     for k in GROUPS:
-        assert_grad_close(k, np_(getattr(gr, k)), res["grads"][k])
+        assert_grad_close(k, np_(getattr(gr, k)), res["grads"][k], mass_fn=mass)
     xi = np_(gr.xi)
     assert_grad_close("xi", xi[view_ids], res["grads"]["xi"])
     others = np.setdiff1d(np.arange(len(wl.cams)), view_ids)
@@ -205,7 +207,7 @@ def _timed_step_parity(gs, wl, view_ids, tiles_per_view, seed, max_masked):
     # parameters with the step's own gradients
     for k, p0, p1 in zip(GROUPS, params0, g.tensors()):
         ref_p, _, _ = O.adam_step(p0, np_(getattr(gr, k)), np.zeros_like(p0), np.zeros_like(p0),
-                                  DEFAULT_LR[k], BETA1, BETA2, EPS, 1)
+                                  f32(DEFAULT_LR[k]), f32(BETA1), f32(BETA2), f32(EPS), 1)
         np.testing.assert_allclose(np_(p1), ref_p, rtol=2e-6, atol=1e-7, err_msg=k)
 
 

@@ -692,3 +692,88 @@ def test_render_error_weights_sum_to_coverage():
     always[:7] = 1
     m2 = O.active_set(res["err"], 1e30, always)
     np.testing.assert_array_equal(m2, always.astype(bool))
+
+
+# ---------------------------------------------------------------------------
+# global stage: insertion, isotropic regulariser, pruning
+# ---------------------------------------------------------------------------
+
+def test_iso_loss_closed_form():
+    """Scales (a, a, b) with a > b: the three deviations from the mean are
+    (a-b)/3, (a-b)/3, -2(a-b)/3, so E = weight/(3n) * 4(a-b)/3 for that
+    Gaussian, and dE/dlog s = s * weight/(3n) * (sgn - mean sgn): 2/3 on the
+    two large axes, -4/3 on the small one.  An isotropic Gaussian adds 0."""
+    a, b, w = 0.3, 0.1, 10.0
+    ls = np.log(np.array([[a, 0.2], [a, 0.2], [b, 0.2]]))
+    E, g = O.iso_loss_grad(ls, w)
+    c = w / (3 * 2)
+    assert abs(E - c * 4 * (a - b) / 3) < 1e-15
+    np.testing.assert_allclose(g[:, 0], [a * c * 2 / 3, a * c * 2 / 3, -b * c * 4 / 3], rtol=1e-12)
+    np.testing.assert_allclose(g[:, 1], 0.0, atol=1e-17)
+
+
+def test_insert_appends_the_local_map_at_opacity_0_2():
+    gm = scenes.random_cloud(7, 1, seed=1)
+    lm = scenes.random_cloud(4, 1, seed=2)
+    arrs, new = O.insert(gm, lm)
+    for k, (out, a, b) in enumerate(zip(arrs, gm.arrays(), lm.arrays())):
+        assert out.shape[-1] == 11
+        np.testing.assert_array_equal(out[..., :7], a)
+        if k != 3:
+            np.testing.assert_array_equal(out[..., 7:], b)
+    np.testing.assert_allclose(1 / (1 + np.exp(-arrs[3][7:])), 0.2, rtol=1e-15)
+    np.testing.assert_array_equal(new, [0] * 7 + [1] * 4)
+
+
+def test_prune_keeps_opacity_at_least_0_7():
+    lg = np.log(0.7 / 0.3)
+    x = np.array([lg - 1e-9, lg + 1e-9, -3.0, 3.0, 0.0])
+    np.testing.assert_array_equal(O.prune_keep(x), [False, True, False, True, False])
+
+
+def test_pose_step_first_adam_step_closed_form():
+    """First Adam step: m_hat / sqrt(v_hat) = sign(g), so the tangent step is
+    -lr sign(g) per component.  A pure rho gradient then translates the camera
+    by exactly that; a pure phi gradient about z rotates it by lr about z
+    (rotating t with it)."""
+    R = np.eye(3)
+    t = np.array([0.3, -0.2, 1.0])
+    z6 = np.zeros(6)
+    Rn, tn, _, _ = O.pose_adam_step(R, t, [2.0, -1e-3, 0, 0, 0, 0], z6, z6, 0.01, 0.02, 0.9, 0.999,
+                                    1e-15, 1)
+    np.testing.assert_allclose(Rn, R, atol=1e-15)
+    np.testing.assert_allclose(tn, t + [-0.01, 0.01, 0.0], atol=1e-13)
+    Rn, tn, _, _ = O.pose_adam_step(R, t, [0, 0, 0, 0, 0, -5.0], z6, z6, 0.01, 0.02, 0.9, 0.999, 1e-15,
+                                    1)
+    c, s_ = math.cos(0.02), math.sin(0.02)
+    Rz = np.array([[c, -s_, 0], [s_, c, 0], [0, 0, 1]])
+    np.testing.assert_allclose(Rn, Rz, atol=1e-14)
+    np.testing.assert_allclose(tn, Rz @ t, atol=1e-14)
+
+
+def test_gradient_term_mass_bounds_the_gradient():
+    """The term mass of a gradient element is at least its magnitude
+    (triangle inequality), with equality when no term cancels: a lone
+    Gaussian's opacity logit under a positive dL/dC on a black background
+    (every pixel adds dC/do > 0)."""
+    W, H, f = 48, 40, 60.0
+    g, cam = _single(np.float32(0.1), np.float32(3.0), f, W, H, 0.4, [0.5, 0.2, 0.9])
+    dl = [np.full((3, H, W), 1e-3)]
+    res = O.render(g, [cam], dL_dimage=dl)
+    mass, walk = O.gradient_term_mass(g, [cam], dl, [0])
+    go = res["grads"]["opacity_logits"][0]
+    assert go > 0
+    np.testing.assert_allclose(mass["opacity_logits"][0, 0], go, rtol=1e-12)
+    assert walk == 1
+    # a random cloud: mass >= |grad| for every parameter of the listed Gaussians
+    gm = scenes.random_cloud(200, 1, seed=3)
+    cams = [scenes.pinhole(64, 48, 60.0)]
+    rng = np.random.default_rng(4)
+    dl = [rng.normal(size=(3, 48, 64)) * 1e-3]
+    res = O.render(gm, cams, dL_dimage=dl)
+    ids = [int(i) for i in np.nonzero(res["proj"][0]["visible"])[0][:12]]
+    mass, walk = O.gradient_term_mass(gm, cams, dl, ids)
+    for k in ("means", "log_scales", "quats", "opacity_logits", "sh"):
+        gk = res["grads"][k].reshape(-1, gm.n)[:, ids].T
+        assert (mass[k] >= np.abs(gk) * (1 - 1e-9) - 1e-18).all(), k
+    assert walk >= 1
