@@ -456,6 +456,25 @@ int gs_pose_adam_step(gs_camera* cams_dev, const float* grad_xi, float* m, float
                       int32_t n_views, const uint8_t* view_mask, float lr_trans, float lr_rot,
                       float beta1, float beta2, float eps, int32_t* step_dev, gs_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * gs_render_fwd_l1 without a workspace.  Same arguments, results and
+ * asynchrony as gs_render_fwd_l1 (bit for bit); the per-tile loss shares go
+ * to a static device array of GS_NOALLOC_MAX_TILES floats (1 MiB) that the
+ * library holds on every GPU it runs on until the process ends.  The call
+ * allocates nothing and synchronises nothing; a batch of more than
+ * GS_NOALLOC_MAX_TILES tiles is rejected with GS_ERR_CAPACITY before any
+ * work is enqueued.  The array's address is taken on the current device at
+ * the first call there (the stream must belong to the current device).
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (different streams or threads) race, so serialise them.  Nothing needs
+ * clearing between calls: each call writes every tile share it reads. */
+#define GS_NOALLOC_MAX_TILES 262144
+int gs_render_fwd_l1_noalloc(const gs_projected* p, int64_t n, const gs_bins* bins,
+                             const gs_views* views, const float* bg, float* image,
+                             float* final_T, uint32_t* n_contrib, const float* target,
+                             float* dL_dimage, double* loss, gs_stream_t stream);
+
 /* L1 photometric loss L = sum over views of mean |C - C*| over 3 H W, and
  * dL/dC = sign(C - C*) / (3 H W) (sign(0) = 0), for every view (layouts of
  * image).  loss (optional, device float64 [1]) is overwritten with L. */

@@ -267,6 +267,31 @@ int gs_render_fwd_l1(const gs_projected* p, int64_t n, const gs_bins* bins,
   return e == hipSuccess ? GS_OK : hip_fail(e, "gs_render_fwd_l1");
 }
 
+int gs_render_fwd_l1_noalloc(const gs_projected* p, int64_t n, const gs_bins* bins,
+                             const gs_views* views, const float* bg, float* image,
+                             float* final_T, uint32_t* n_contrib, const float* target,
+                             float* dL_dimage, double* loss, gs_stream_t stream) {
+  ViewTable vt;
+  int st = build_view_table(views, vt);
+  if (st) return st;
+  if (n < 0) return invalid("n = %lld < 0", (long long)n);
+  if ((st = check_projected(p, n))) return st;
+  if ((st = check_bins(bins, false))) return st;
+  if (!image || !final_T || !n_contrib) return invalid("an output pointer is NULL");
+  if (!target || !dL_dimage) return invalid("target or dL_dimage is NULL");
+  if (vt.n_tiles > GS_NOALLOC_MAX_TILES) {
+    set_error("%d tiles exceed the %d tile shares of the static scratch", vt.n_tiles,
+              GS_NOALLOC_MAX_TILES);
+    return GS_ERR_CAPACITY;
+  }
+  float* scratch = nullptr;
+  hipError_t e = noalloc_scratch(&scratch);
+  if (e != hipSuccess) return hip_fail(e, "gs_render_fwd_l1_noalloc: scratch address");
+  e = launch_render_fwd(*p, *bins, vt, read_bg(bg), image, final_T, n_contrib, nullptr, target,
+                        dL_dimage, loss, scratch, stream);
+  return e == hipSuccess ? GS_OK : hip_fail(e, "gs_render_fwd_l1_noalloc");
+}
+
 size_t gs_render_bwd_workspace_size(int64_t n, const gs_views* views) {
   ViewTable vt;
   if (n < 0 || build_view_table(views, vt) != GS_OK) return 0;

@@ -229,6 +229,10 @@ hipError_t launch_render_fwd(const gs_projected& p, const gs_bins& bins, const V
                              float* depth, const float* target, float* dL, double* loss,
                              float* tile_loss, hipStream_t s);
 
+// Device address of gs_render_fwd_l1_noalloc's static per-tile scratch on the
+// current device (taken with hipGetSymbolAddress on first use per device).
+hipError_t noalloc_scratch(float** out);
+
 struct BwdPlan {
   size_t off_grad2d, off_pose, total;
 };

@@ -10,9 +10,17 @@
 // a time (128 with PPL = 4; gathered once per workgroup) and read back as
 // wave-uniform broadcasts, so a staged record serves 64 * PPL pixels per LDS
 // read.  A workgroup stops once every pixel has terminated.
+#include <mutex>
+
 #include "gs_internal.h"
 
 namespace gsmi {
+
+// Per-tile loss shares of gs_render_fwd_l1_noalloc: a library-owned device
+// array instead of a caller workspace.  Every GPU holds its own copy until
+// the process ends; host code reaches it only through the per-device address
+// taken by noalloc_scratch().
+static __device__ __align__(256) float scratch[GS_NOALLOC_MAX_TILES];
 
 namespace {
 
@@ -225,6 +233,28 @@ __global__ __launch_bounds__(1024) void tile_loss_sum_kernel(const float* __rest
 }
 
 }  // namespace
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {   // once per device, with that device current
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<float*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 hipError_t launch_render_fwd(const gs_projected& p, const gs_bins& bins, const ViewTable& vt,
                              float3 bg, float* image, float* final_T, uint32_t* n_contrib,

@@ -113,6 +113,10 @@ _lib.gs_render_fwd_l1_workspace_size.argtypes = [ctypes.POINTER(gs_views)]
 _lib.gs_render_fwd_l1.argtypes = [ctypes.POINTER(gs_projected), ctypes.c_int64, ctypes.POINTER(gs_bins),
                                   ctypes.POINTER(gs_views), ctypes.POINTER(ctypes.c_float), _p, _p, _p,
                                   _p, _p, _p, _p, ctypes.c_size_t, _S]
+_lib.gs_render_fwd_l1_noalloc.argtypes = [ctypes.POINTER(gs_projected), ctypes.c_int64,
+                                          ctypes.POINTER(gs_bins), ctypes.POINTER(gs_views),
+                                          ctypes.POINTER(ctypes.c_float), _p, _p, _p, _p, _p, _p, _S]
+GS_NOALLOC_MAX_TILES = 262144
 _lib.gs_render_bwd_workspace_size.restype = ctypes.c_size_t
 _lib.gs_render_bwd_workspace_size.argtypes = [ctypes.c_int64, ctypes.POINTER(gs_views)]
 _lib.gs_render_bwd.argtypes = [ctypes.POINTER(gs_gaussians), ctypes.POINTER(gs_projected),
@@ -180,7 +184,7 @@ EXPORTED = ("gs_status_string", "gs_last_error", "gs_version", "gs_num_tiles", "
             "gs_preprocess", "gs_bin_sort_workspace_size", "gs_bin_sort", "gs_render_fwd",
             "gs_render_bwd_workspace_size", "gs_render_bwd", "gs_adam_step", "gs_l1_loss_grad",
             "gs_set_kernel_events", "gs_adam_step_dev", "gs_adam_step_groups_dev",
-            "gs_render_fwd_l1_workspace_size", "gs_render_fwd_l1",
+            "gs_render_fwd_l1_workspace_size", "gs_render_fwd_l1", "gs_render_fwd_l1_noalloc",
             "gs_set_tuning", "gs_get_tuning", "gs_render_error", "gs_active_set",
             "gs_adam_step_groups_masked_dev", "gs_concat", "gs_prune_mask",
             "gs_compact_workspace_size", "gs_compact", "gs_iso_loss_grad", "gs_pose_adam_step",
@@ -450,6 +454,17 @@ def gs_render_fwd_l1(p: Projected, n: int, bins: Bins, views: Views, bg, image: 
                                  _bg(bg), _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(target),
                                  _ptr(dL_dimage), _ptr(loss), _ptr(ws), ws.numel(), _stream(stream)),
            "gs_render_fwd_l1")
+
+
+def gs_render_fwd_l1_noalloc(p: Projected, n: int, bins: Bins, views: Views, bg, image: torch.Tensor,
+                             final_T: torch.Tensor, n_contrib: torch.Tensor, target: torch.Tensor,
+                             dL_dimage: torch.Tensor, loss: Optional[torch.Tensor], stream=None) -> None:
+    """gs_render_fwd_l1 with the library's static scratch (no workspace)."""
+    ps, bs = p.struct(), bins.struct()
+    _check(_lib.gs_render_fwd_l1_noalloc(ctypes.byref(ps), n, ctypes.byref(bs), ctypes.byref(views.struct),
+                                         _bg(bg), _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(target),
+                                         _ptr(dL_dimage), _ptr(loss), _stream(stream)),
+           "gs_render_fwd_l1_noalloc")
 
 
 def gs_render_bwd_workspace_size(n: int, views: Views) -> int:
