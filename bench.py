@@ -17,7 +17,6 @@ from __future__ import annotations
 import argparse
 import gc
 import json
-import math
 import os
 import platform
 import subprocess
@@ -346,13 +345,12 @@ def main():
     pre_bytes = (g.n * 4 * (3 + 3 + 4 + 1 + 3 * K) + n_visible * (8 + 16 + 16 + 4 + 4)
                  + (g.n * len(wl.cams) - n_visible) * 8)
     # binning (the step bins without keys): the tile count of every entry
-    # (4 B) and the radius, centre and depth of every binned splat (one that
-    # touches a tile), the depth sort of the binned splats (4 passes, 8 B read
-    # + 8 B written), 8 B per (tile id, value) emitted and 16 B per key per
-    # tile-digit pass
-    tile_passes = math.ceil(max(1, math.ceil(math.log2(max(views.n_tiles, 2)))) / 8)
-    sort_bytes = (g.n * len(wl.cams) * 4 + n_binned * (4 + 8 + 4) + n_binned * 4 * 16
-                  + n_keys * 8 + n_keys * 16 * tile_passes)
+    # (4 B), the centre, radius and depth of every binned splat (one that
+    # touches a tile: 16 B), per key its (depth, entry) pair staged in its
+    # tile's segment and read back by the segment sort (16 B) and its value
+    # (4 B), per tile its range (8 B) and launch-order slot (4 B)
+    sort_bytes = (g.n * len(wl.cams) * 4 + n_binned * 16 + n_keys * (16 + 4)
+                  + views.n_tiles * 12)
     hbm = {name: {"bytes": b, "ms": kms[name], "GB/s": b / (kms[name] * 1e-3) / 1e9,
                   "frac": b / (kms[name] * 1e-3) / 1e9 / HBM_PEAK_GBS}
            for name, b in (("preprocess", pre_bytes), ("bin_sort", sort_bytes))}

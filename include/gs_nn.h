@@ -111,6 +111,26 @@ size_t gs_cost_volume_workspace_size(int32_t k, int32_t h, int32_t w);
 int gs_cost_volume_wta(const float* keyframes, const gs_views* cams, float* cost, float* depth,
                        void* ws, size_t ws_bytes, gs_stream_t stream);
 
+/* Depth from the cost volume by belief propagation (Sec. III-A2: a depth
+ * image from the volume under a smoothness prior, Felzenszwalb and
+ * Huttenlocher's loopy min-sum formulation).  cost: device float32
+ * [64][h][w] as gs_cost_volume_wta writes it (+inf entries, hypotheses no
+ * source view sees, cost `invalid_cost`).  On the 4-connected grid a pixel sends
+ * each neighbour, for every label l' of the receiver,
+ *   min over l of D(l) + (messages from its other three neighbours)(l)
+ *                 + min(lam |l - l'|, trunc),
+ * shifted to a zero minimum; messages start at 0 and are updated
+ * synchronously `iters` times; a pixel's label is the first minimum of its
+ * data cost plus its four incoming messages.  Outputs (device, optional
+ * each): labels int32 [h][w], depth float32 [h][w] (the label's
+ * hypothesis, 0.25 + 24.75 l / 63 m).  lam, trunc >= 0 and finite, iters
+ * >= 0.  ws: gs_bp_workspace_size bytes (data costs and two message sets,
+ * 9 x 64 floats per pixel). */
+size_t gs_bp_workspace_size(int32_t h, int32_t w);
+int gs_bp_labels(const float* cost, int32_t h, int32_t w, float lam, float trunc, int32_t iters,
+                 float invalid_cost, int32_t* labels, float* depth, void* ws, size_t ws_bytes,
+                 gs_stream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

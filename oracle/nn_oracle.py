@@ -6,7 +6,9 @@ in NHWC layout ([n, h, w, c]) unless stated.
 
 Plain initialiser: the photometric cost volume of Eq. 1 (Sec. III-A1) over a
 keyframe window, 64 hypotheses spaced evenly over 0.25-25 m, on 1/4
-resolution intensity images, reduced per pixel by winner-take-all.
+resolution intensity images, reduced per pixel by winner-take-all or by
+loopy min-sum belief propagation under a truncated linear smoothness prior
+(Sec. III-A2).
 
 Network pieces: 3x3 convolution with zero padding (written as an explicit
 sum over the nine taps), 2x2 average pooling, nearest 2x upsampling, ReLU,
@@ -172,3 +174,63 @@ def wta_depth(cost: np.ndarray) -> np.ndarray:
     idx = np.argmin(cost, axis=0)
     d = hypotheses()[idx]
     return np.where(np.isfinite(cost.min(axis=0)), d, 0.0)
+
+
+# ---------------------------------------------------------------------------
+# belief propagation over the cost volume (Sec. III-A2)
+# ---------------------------------------------------------------------------
+
+BP_LAMBDA = 0.01        # smoothness cost per hypothesis step (the paper gives none)
+BP_TRUNC = 0.08         # truncation of the smoothness cost
+BP_ITERS = 30           # synchronous message-passing iterations
+BP_INVALID = 1.0        # data cost of a hypothesis no source view sees
+
+
+def bp_messages_step(D, m, lam, trunc):
+    """One synchronous min-sum iteration on the 4-connected grid.
+
+    D [L, H, W] data costs; m [4, L, H, W] the messages each pixel received
+    in the last iteration, from its left (0), right (1), upper (2) and lower
+    (3) neighbour.  A pixel sends to a neighbour the minimum over its own
+    labels l of D(l) plus the messages it received from its other three
+    neighbours plus the smoothness cost min(lam |l - l'|, trunc), for every
+    label l' of the receiver, shifted so that its minimum is 0.  Written out
+    as the definition (an explicit minimum over l for each l')."""
+    L, H, W = D.shape
+    lab = np.arange(L)
+    S = np.minimum(lam * np.abs(lab[:, None] - lab[None, :]), trunc)       # [l, l']
+    total = D + m.sum(axis=0)
+    new = np.zeros_like(m)
+
+    def send(h):
+        out = np.empty_like(h)
+        for lp in range(L):
+            out[lp] = (h + S[:, lp][:, None, None]).min(axis=0)
+        return out - out.min(axis=0, keepdims=True)
+
+    # to the right neighbour: excludes what came from the right
+    new[0][:, :, 1:] = send(total - m[1])[:, :, :-1]
+    new[1][:, :, :-1] = send(total - m[0])[:, :, 1:]          # to the left
+    new[2][:, 1:, :] = send(total - m[3])[:, :-1, :]          # downwards
+    new[3][:, :-1, :] = send(total - m[2])[:, 1:, :]          # upwards
+    return new
+
+
+def belief_propagation(cost, lam=BP_LAMBDA, trunc=BP_TRUNC, iters=BP_ITERS, invalid=BP_INVALID):
+    """Loopy min-sum belief propagation (Felzenszwalb and Huttenlocher's
+    formulation, Sec. III-A2) over a cost volume [L, H, W]: +inf entries (no
+    valid source view) cost ``invalid``; messages start at 0 and are updated
+    synchronously ``iters`` times; the label of a pixel is the first minimum of
+    its belief, the data cost plus the four incoming messages.  Returns
+    (labels [H, W], beliefs [L, H, W])."""
+    D = np.where(np.isfinite(cost), np.asarray(cost, np.float64), invalid)
+    m = np.zeros((4,) + D.shape)
+    for _ in range(iters):
+        m = bp_messages_step(D, m, lam, trunc)
+    belief = D + m.sum(axis=0)
+    return np.argmin(belief, axis=0), belief
+
+
+def bp_depth(cost, **kw) -> np.ndarray:
+    labels, _ = belief_propagation(cost, **kw)
+    return hypotheses()[labels]

@@ -687,6 +687,31 @@ int gs_nn_depth_loss(const float* pred, const float* depth, int32_t n, int32_t h
                                  stream), "gs_nn_depth_loss");
 }
 
+size_t gs_bp_workspace_size(int32_t h, int32_t w) {
+  if (h < 1 || w < 1) return 0;
+  return bp_ws_bytes(h, w);
+}
+
+int gs_bp_labels(const float* cost, int32_t h, int32_t w, float lam, float trunc, int32_t iters,
+                 float invalid_cost, int32_t* labels, float* depth, void* ws, size_t ws_bytes,
+                 gs_stream_t stream) {
+  if (!cost) return invalid("cost is NULL");
+  if (h < 1 || w < 1) return invalid("h and w must be positive");
+  if ((int64_t)h * w > (1ll << 26)) return invalid("too many pixels");
+  if (!(std::isfinite(lam) && lam >= 0.f && std::isfinite(trunc) && trunc >= 0.f))
+    return invalid("lam and trunc must be finite and >= 0");
+  if (!std::isfinite(invalid_cost)) return invalid("invalid_cost must be finite");
+  if (iters < 0) return invalid("iters < 0");
+  const size_t need = bp_ws_bytes(h, w);
+  if (ws_bytes < need) {
+    set_error("workspace of %zu bytes is smaller than the %zu required", ws_bytes, need);
+    return GS_ERR_CAPACITY;
+  }
+  if (!ws) return invalid("workspace is NULL");
+  return nn_status(launch_bp(cost, h, w, lam, trunc, iters, invalid_cost, labels, depth, ws, stream),
+                   "gs_bp_labels");
+}
+
 size_t gs_cost_volume_workspace_size(int32_t k, int32_t h, int32_t w) {
   if (k < 2 || h < 4 || w < 4) return 0;
   return cost_volume_ws_bytes(k, h, w);

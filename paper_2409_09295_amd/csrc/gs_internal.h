@@ -210,13 +210,12 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, int64_t n, hipStream_t s
 struct BinSortPlan {
   int64_t n_entries;     // V * n
   int64_t capacity;
+  int64_t chunks;        // binning workgroups per view
   int32_t n_tiles;
-  int32_t passes;        // radix passes of 8 bits over the keys' tile bits
-  int64_t scan_blocks;   // blocks of the entry scan
-  int64_t sort_blocks;   // blocks of the radix sort at capacity
+  int32_t lds_tiles;     // LDS histogram bins (largest view, at most the LDS limit)
   // workspace layout (byte offsets)
-  size_t off_counts, off_offsets, off_dkey, off_dval, off_scan_part, off_keys_alt, off_vals_alt,
-      off_hist, off_hist_part, off_flag, off_order, total;
+  size_t off_matrix, off_counts, off_starts, off_long, off_flag, off_partial, off_order,
+      off_staged, off_spare, total;
 };
 BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity);
 int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs_bins& bins,
@@ -304,6 +303,9 @@ hipError_t nn_head_bwd(const gs_act* f, const float* w, const float* dout, gs_ac
 hipError_t nn_depth_loss(const float* pred, const float* depth, int N, int H, int W, float fx,
                          float* dpred, double* loss, int* count_ws, hipStream_t s);
 size_t cost_volume_ws_bytes(int K, int H, int W);
+size_t bp_ws_bytes(int h, int w);
+hipError_t launch_bp(const float* cost, int h, int w, float lam, float trunc, int iters,
+                     float invalid, int32_t* labels, float* depth, void* ws, hipStream_t s);
 hipError_t launch_cost_volume(const float* keyframes, int K, int H, int W,
                               const gs_camera* cams_dev, float* cost, float* depth, void* ws,
                               hipStream_t s);

@@ -728,6 +728,11 @@ _lib.gs_nn_depth_loss.argtypes = [_p, _p, ctypes.c_int32, ctypes.c_int32, ctypes
 _lib.gs_cost_volume_workspace_size.restype = ctypes.c_size_t
 _lib.gs_cost_volume_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
 _lib.gs_cost_volume_wta.argtypes = [_p, ctypes.POINTER(gs_views), _p, _p, _p, ctypes.c_size_t, _S]
+_lib.gs_bp_workspace_size.restype = ctypes.c_size_t
+_lib.gs_bp_workspace_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
+_lib.gs_bp_labels.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_int32, ctypes.c_float, _p, _p, _p, ctypes.c_size_t, _S]
+EXPORTED = EXPORTED + ("gs_bp_workspace_size", "gs_bp_labels")
 EXPORTED = EXPORTED + ("gs_nn_conv3x3", "gs_nn_conv3x3_wgrad", "gs_nn_flip_weights", "gs_nn_avgpool2",
                        "gs_nn_avgpool2_bwd", "gs_nn_upsample2", "gs_nn_upsample2_bwd",
                        "gs_nn_rgb_to_nhwc", "gs_nn_f32_to_bf16", "gs_nn_head", "gs_nn_head_bwd",
@@ -832,3 +837,16 @@ def gs_cost_volume_wta(keyframes: torch.Tensor, views: Views, cost: Optional[tor
 
 def gs_cost_volume_workspace_size(k: int, h: int, w: int) -> int:
     return int(_lib.gs_cost_volume_workspace_size(k, h, w))
+
+
+def gs_bp_workspace_size(h: int, w: int) -> int:
+    return int(_lib.gs_bp_workspace_size(h, w))
+
+
+def gs_bp_labels(cost: torch.Tensor, h: int, w: int, lam: float, trunc: float, iters: int,
+                 invalid: float, labels: Optional[torch.Tensor], depth: Optional[torch.Tensor],
+                 ws: torch.Tensor, stream=None) -> None:
+    if cost.dtype != torch.float32 or cost.numel() != 64 * h * w:
+        raise ValueError("cost must be float32 [64][h][w]")
+    _check(_lib.gs_bp_labels(_ptr(cost), h, w, lam, trunc, iters, invalid, _ptr(labels), _ptr(depth),
+                             _ptr(ws), ws.numel(), _stream(stream)), "gs_bp_labels")

@@ -291,14 +291,28 @@ def trajectory_cams(n: int, seed: int, boxes, W: int, H: int, per_path: int = 50
 # plain initialiser and evaluation
 # ---------------------------------------------------------------------------
 
-def plain_depth(keyframes: torch.Tensor, cams: Sequence[scenes.Camera], device="cuda") -> torch.Tensor:
-    """Eq. 1 cost volume + winner-take-all for the last keyframe, upsampled
-    4x by repetition: [h, w] (0 where no hypothesis had a valid view)."""
+BP_LAMBDA, BP_TRUNC, BP_ITERS, BP_INVALID = 0.01, 0.08, 30, 1.0
+
+
+def plain_depth(keyframes: torch.Tensor, cams: Sequence[scenes.Camera], device="cuda",
+                method: str = "wta") -> torch.Tensor:
+    """Eq. 1 cost volume for the last keyframe, reduced per pixel by
+    winner-take-all (``method="wta"``; 0 where no hypothesis had a valid
+    view) or by belief propagation under the truncated linear smoothness
+    prior (``"bp"``, Sec. III-A2), upsampled 4x by repetition: [h, w]."""
     k, _, H, W = keyframes.shape
     views = gs.Views(list(cams), device)
     ws = gs.workspace(gs.gs_cost_volume_workspace_size(k, H, W), device)
     low = torch.empty(H // 4, W // 4, device=device)
-    gs.gs_cost_volume_wta(keyframes.contiguous(), views, None, low, ws)
+    if method == "wta":
+        gs.gs_cost_volume_wta(keyframes.contiguous(), views, None, low, ws)
+    elif method == "bp":
+        cost = torch.empty(64, H // 4, W // 4, device=device)
+        gs.gs_cost_volume_wta(keyframes.contiguous(), views, cost, low, ws)
+        bws = gs.workspace(gs.gs_bp_workspace_size(H // 4, W // 4), device)
+        gs.gs_bp_labels(cost, H // 4, W // 4, BP_LAMBDA, BP_TRUNC, BP_ITERS, BP_INVALID, None, low, bws)
+    else:
+        raise ValueError(f"unknown method {method}")
     return low.repeat_interleave(4, 0).repeat_interleave(4, 1)
 
 

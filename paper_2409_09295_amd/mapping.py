@@ -39,9 +39,13 @@ import torch
 from . import gs, scenes
 from .global_stage import ISO_WEIGHT, GlobalStage, prune
 from .initnet import plain_depth, propose
-from .replay import BatchedStep
+from .replay import DEFAULT_LR, BatchedStep
 
 Y00 = 0.28209479177387814   # degree-0 real spherical harmonic
+
+# Step sizes of the mapping stages: a map grown from a few hundred inserted
+# Gaussians needs faster opacity and scale changes than refining a dense one.
+MAPPING_LR = dict(DEFAULT_LR, opacity_logits=0.1, means=1e-3, log_scales=1e-2)
 
 
 def _map_bytes(g: gs.Gaussians) -> int:
@@ -50,13 +54,14 @@ def _map_bytes(g: gs.Gaussians) -> int:
 
 class MappingLoop:
     def __init__(self, width: int, height: int, fx: float, *, window: int = 8, n_past: int = 4,
-                 stride: int = 8, local_iters: int = 30, global_iters: int = 50,
+                 stride: int = 8, local_iters: int = 60, global_iters: int = 100,
                  active_quantile: float = 0.85, sh_degree: int = 0, seed: int = 0,
-                 device="cuda"):
+                 lrs: Optional[Dict[str, float]] = None, device="cuda"):
         self.W, self.H, self.fx = width, height, fx
         self.N, self.n_past, self.stride = window, n_past, stride
         self.local_iters, self.global_iters = local_iters, global_iters
         self.q = active_quantile
+        self.lrs = dict(MAPPING_LR) if lrs is None else lrs
         self.sh_degree = sh_degree
         self.device = device
         self.rng = np.random.default_rng(seed)
@@ -113,7 +118,7 @@ class MappingLoop:
         targets = self._window_tensor().reshape(-1)
         blend = gs.Tracked(gs.GS_MEM_BLEND_STATE, 8 * views.n_pixels)
         opt = gs.Tracked(gs.GS_MEM_OPTIMISER, 2 * _map_bytes(local))
-        step = BatchedStep(local, views, targets, iso_weight=ISO_WEIGHT, pose=False)
+        step = BatchedStep(local, views, targets, lrs=self.lrs, iso_weight=ISO_WEIGHT, pose=False)
         for _ in range(self.local_iters):
             step.step_checked()
         del step
@@ -136,7 +141,7 @@ class MappingLoop:
         # the threshold: the active_quantile of the Gaussians' largest errors
         # (the paper does not state its value)
         stage = GlobalStage(self.map, local, wcams, kfs, past, None, eps_quantile=self.q,
-                            pose_lr=None)
+                            lrs=self.lrs, pose_lr=None)
         eps = stage.eps
         opt = gs.Tracked(gs.GS_MEM_OPTIMISER, 2 * _map_bytes(stage.map))
         stage.iterate(self.global_iters)

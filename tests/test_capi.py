@@ -72,7 +72,7 @@ def test_workspace_sizes_grow(gs):
     lib = gs.lib()
     v = _views(gs, [(640, 480)])
     a = lib.gs_bin_sort_workspace_size(1000, ctypes.byref(v), 10000)
-    b = lib.gs_bin_sort_workspace_size(2000, ctypes.byref(v), 10000)
+    b = lib.gs_bin_sort_workspace_size(50000, ctypes.byref(v), 10000)
     c = lib.gs_bin_sort_workspace_size(1000, ctypes.byref(v), 20000)
     assert 0 < a < b and a < c
     assert lib.gs_render_bwd_workspace_size(1000, ctypes.byref(v)) >= 36 * 1000

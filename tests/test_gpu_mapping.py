@@ -12,8 +12,8 @@ pytestmark = pytest.mark.gpu
 def test_mapping_loop_overhead_matches_closed_form(gs):
     from paper_2409_09295_amd.mapping import run_sequence
     W, H, N, n_past, frames = 160, 120, 4, 4, 10
-    out = run_sequence(W, H, frames, N, n_gauss=60000, seed=1, n_past=n_past, stride=4,
-                       local_iters=30, global_iters=50, log=lambda m: print(m, flush=True))
+    out = run_sequence(W, H, frames, N, n_gauss=60000, seed=1, n_past=n_past,
+                       log=lambda m: print(m, flush=True))
     px = W * H
     keyframes = N * 3 * px * 4
     poses = frames * 80
@@ -29,11 +29,11 @@ def test_mapping_loop_overhead_matches_closed_form(gs):
     assert abs(out["overhead_peak_MB"] * 1e6 - expect) < 1.0
     assert out["all_keyframes_MB"] > out["peak_by_category_MB"]["keyframes"]
     # the loop maps: the map renders the last keyframe, and the first (which
-    # left the window long ago), closer than an empty map does
+    # left the window long ago), at least 10 dB closer than an empty map does
     print(f"PSNR last {out['psnr_last']:.2f} dB (empty map {out['psnr_empty_last']:.2f}), first "
           f"{out['psnr_first']:.2f} dB (empty map {out['psnr_empty_first']:.2f}), "
           f"{out['map_gaussians']} Gaussians", flush=True)
-    assert out["psnr_last"] > out["psnr_empty_last"] + 1.0
-    assert out["psnr_first"] > out["psnr_empty_first"] + 1.0
+    assert out["psnr_last"] > out["psnr_empty_last"] + 10.0
+    assert out["psnr_first"] > out["psnr_empty_first"] + 10.0
     fr = [h["active_fraction"] for h in out["history"] if "active_fraction" in h]
     assert fr and max(fr) < 1.0

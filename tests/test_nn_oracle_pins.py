@@ -141,3 +141,60 @@ def test_unet_forward_matches_library_layers():
     d0 = conv("d0b", conv("d0a", torch.cat([up(d1), e0], 1)))
     ref = F.conv2d(d0, p["head.w"][:, :, None, None], p["head.b"])
     torch.testing.assert_close(ours, ref, rtol=1e-10, atol=1e-10)
+
+
+def test_bp_without_smoothness_is_winner_take_all():
+    rng = np.random.default_rng(11)
+    cost = rng.random((16, 7, 9))
+    cost[:, 2, 3] = np.inf
+    labels, _ = N.belief_propagation(cost, lam=0.0, trunc=0.0, iters=5)
+    D = np.where(np.isfinite(cost), cost, N.BP_INVALID)
+    np.testing.assert_array_equal(labels, np.argmin(D, axis=0))
+
+
+def _chain_map(D, lam, trunc):
+    """Exact minimum-energy labelling of a chain by dynamic programming."""
+    L, n = D.shape
+    S = np.minimum(lam * np.abs(np.arange(L)[:, None] - np.arange(L)[None, :]), trunc)
+    acc = D[:, 0].copy()
+    back = np.zeros((L, n), int)
+    for x in range(1, n):
+        tot = acc[:, None] + S                     # [previous label, label]
+        back[:, x] = np.argmin(tot, axis=0)
+        acc = tot.min(axis=0) + D[:, x]
+    lab = np.zeros(n, int)
+    lab[-1] = int(np.argmin(acc))
+    for x in range(n - 1, 0, -1):
+        lab[x - 1] = back[lab[x], x]
+    return lab, acc.min()
+
+
+def test_bp_on_a_chain_reaches_the_exact_map():
+    """On a tree (a one-row image) min-sum belief propagation is exact once
+    messages have crossed the chain: labels equal the dynamic-programming
+    minimum of the same energy (data plus truncated linear smoothness)."""
+    rng = np.random.default_rng(12)
+    L, n = 12, 9
+    D = rng.random((L, n)) * 0.3
+    lam, trunc = 0.05, 0.2
+    labels, belief = N.belief_propagation(D[:, None, :], lam=lam, trunc=trunc, iters=n + 1)
+    ref, energy = _chain_map(D, lam, trunc)
+    np.testing.assert_array_equal(labels[0], ref)
+    # every belief's minimum is the minimum energy, up to the message shifts:
+    # the chosen labelling's energy equals the exact minimum
+    S = np.minimum(lam * np.abs(np.arange(L)[:, None] - np.arange(L)[None, :]), trunc)
+    e = D[labels[0], np.arange(n)].sum() + sum(S[labels[0][x], labels[0][x + 1]] for x in range(n - 1))
+    assert abs(e - energy) < 1e-12
+
+
+def test_bp_smooths_an_outlier():
+    """A constant-depth field with one pixel whose data prefer a far label by
+    a margin smaller than the smoothness it would break: BP restores the
+    neighbours' label, winner-take-all keeps the outlier."""
+    L, H, W = 10, 5, 5
+    D = np.full((L, H, W), 0.5)
+    D[3] = 0.1
+    D[8, 2, 2], D[3, 2, 2] = 0.05, 0.12
+    labels, _ = N.belief_propagation(D, lam=0.05, trunc=0.3, iters=10)
+    assert (labels == 3).all()
+    assert np.argmin(D[:, 2, 2]) == 8
