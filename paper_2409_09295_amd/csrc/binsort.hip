@@ -6,10 +6,14 @@
 // a sort of each tile's own short list.  No step uses global atomics on the
 // tile counters, which contend badly on tiles many splats cover:
 //
-//   hist      workgroups of 512 threads take 2,048 entries of one view
-//             (a chunk) and count, in an LDS histogram over that view's
-//             tiles, the keys their splats emit (each splat's tile rectangle
-//             in float64 from its float32 centre), then store the whole
+//   compact   the splats of each view that touch a tile are appended to a
+//             per-view list as {u, v, radius, depth} records (one global
+//             atomic per workgroup of 1,024 entries); the walks below read
+//             only these (a tenth of the entries in a mapping batch)
+//   hist      each workgroup of 512 threads takes chunks of 1,024 listed
+//             splats of one view and counts, in an LDS histogram over that
+//             view's tiles, the keys they emit (each splat's tile rectangle
+//             in float64 from its float32 centre), then stores the whole
 //             histogram as row `chunk` of a dense chunk x tile matrix.
 //             Splats with large rectangles do not serialise one lane: a
 //             wavefront walks its 64 splats' keys 64 at a time, each lane
@@ -23,10 +27,10 @@
 //             (LDS atomics hand out the slots within a chunk)
 //   segment   one wavefront per tile sorts its segment by (depth bits,
 //             entry) with a bitonic network in registers (lists of up to
-//             kSegShort pairs) and writes the entries (and keys); longer
-//             lists are queued for a second grid that sorts them with four
-//             wavefronts (registers and LDS), or, beyond kSegLong pairs, by
-//             a stable LSD radix sort over the 64-bit pair in the workspace
+//             kSegShort pairs) and writes the entries (and keys); in the
+//             same launch, the first workgroups sort the longer lists with
+//             all their wavefronts (registers and LDS), or, beyond kSegLong
+//             pairs, by a stable LSD radix sort over the 64-bit pair
 //   order     optional: the tiles stably sorted by list length group,
 //             longest first (the launch order of the compositing grids)
 //
@@ -41,12 +45,15 @@ namespace {
 
 constexpr int kBinThreads = 512;                         // threads of a binning workgroup
 constexpr int kBinWaves = kBinThreads / 64;
-constexpr int kWalkBatch = 4;                            // entries per binning thread
-constexpr int kBinChunk = kBinThreads * kWalkBatch;      // entries per binning workgroup
+constexpr int kWalkBatch = 2;                            // splats per binning thread
+constexpr int kBinChunk = kBinThreads * kWalkBatch;      // splats per binning chunk
+constexpr int kBinGrid = 32;                             // binning workgroups per view
 constexpr int kLdsTiles = 8192;                          // largest LDS histogram (tiles)
 constexpr int kSegShort = 1024;                          // longest list of the wavefront sort
 constexpr int kSegLong = 4096;                           // longest list of the workgroup sort
-constexpr int kLongBlocks = 512;                         // workgroups of the long-list grid
+constexpr int kSortThreads = 512;                        // threads of a sort workgroup
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kLongSlots = 256;                          // sort workgroups that take the long lists
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
 
@@ -117,31 +124,29 @@ __device__ __forceinline__ uint32_t div_small(uint32_t jj, uint32_t w) {
 }
 
 // Calls op(view-local tile, entry, depth bits) once for every key that the
-// entries i0 .. i0 + kBinChunk of view v emit.  Each thread takes kWalkBatch
-// entries (stride kBinThreads) and issues their loads together; then, per
-// entry slot, each wavefront walks its 64 entries' keys 64 at a time, every
-// lane taking the key at its position and finding the entry that owns it as
-// the last entry whose first key is at or before it (a prefix maximum over
-// start marks), so large rectangles spread over the lanes.
+// splats j0 .. j0 + kBinChunk of a view's compacted list (count splats in
+// all) emit.  Each thread takes kWalkBatch splats (stride kBinThreads) and
+// issues their loads together; then, per splat slot, each wavefront walks
+// its 64 splats' keys 64 at a time, every lane taking the key at its
+// position and finding the splat that owns it as the last splat whose first
+// key is at or before it (a prefix maximum over start marks), so large
+// rectangles spread over the lanes.
 template <bool kDepth, typename Op>
-__device__ __forceinline__ void walk_keys(const float2* __restrict__ xy,
-                                          const int32_t* __restrict__ radius,
-                                          const float4* __restrict__ rd, int64_t n, int v,
-                                          const ViewInfo& vi, int64_t i0, WalkLds& L, Op op) {
+__device__ __forceinline__ void walk_keys(const uint4* __restrict__ rec,
+                                          const uint32_t* __restrict__ ids, uint32_t count,
+                                          uint32_t j0, const ViewInfo& vi, WalkLds& L, Op op) {
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
   // all loads of the batch first, from clamped indices (no branches between
-  // them, so they are in flight together); entries past n get radius 0
-  float2 c[kWalkBatch];
-  int32_t r[kWalkBatch];
-  float dz[kWalkBatch];
+  // them, so they are in flight together); slots past the list get radius 0
+  uint4 c[kWalkBatch];
+  uint32_t id[kWalkBatch];
 #pragma unroll
   for (int q = 0; q < kWalkBatch; ++q) {
-    const int64_t i = i0 + q * kBinThreads + threadIdx.x;
-    const int64_t e = (int64_t)v * n + (i < n ? i : n - 1);
-    r[q] = radius[e];
-    c[q] = xy[e];
-    if constexpr (kDepth) dz[q] = rd[e].w;
-    if (i >= n) r[q] = 0;
+    const uint32_t j = j0 + q * kBinThreads + threadIdx.x;
+    const uint32_t jc = j < count ? j : count - 1;
+    c[q] = rec[jc];
+    if constexpr (kDepth) id[q] = ids[jc];
+    if (j >= count) c[q].z = 0u;
   }
   // per entry: key count, and first tile | rectangle width << 21 (a view
   // has at most 2^20 tiles, a rectangle at most 1,024 columns)
@@ -152,10 +157,11 @@ __device__ __forceinline__ void walk_keys(const float2* __restrict__ xy,
     cnt[q] = 0;
     rect[q] = 1u << 21;
     dep[q] = 0;
-    if (tile_rect(c[q].x, c[q].y, r[q], vi.width, vi.height, rc)) {
+    if (tile_rect(__uint_as_float(c[q].x), __uint_as_float(c[q].y), (int32_t)c[q].z, vi.width,
+                  vi.height, rc)) {
       cnt[q] = (uint32_t)((rc.x1 - rc.x0) * (rc.y1 - rc.y0));
       rect[q] = (uint32_t)(rc.y0 * vi.tiles_x + rc.x0) | ((uint32_t)(rc.x1 - rc.x0) << 21);
-      if constexpr (kDepth) dep[q] = __float_as_uint(dz[q]);
+      if constexpr (kDepth) dep[q] = c[q].w;
     }
   }
 #pragma unroll
@@ -167,8 +173,10 @@ __device__ __forceinline__ void walk_keys(const float2* __restrict__ xy,
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
     L.rect[w][lane] = make_uint4(start, rect[q] & 0x1FFFFFu, rect[q] >> 21, (uint32_t)vi.tiles_x);
-    L.ent[w][lane] = (uint32_t)((int64_t)v * n + i0 + q * kBinThreads + threadIdx.x);
-    if constexpr (kDepth) L.dep[w][lane] = dep[q];
+    if constexpr (kDepth) {
+      L.ent[w][lane] = id[q];
+      L.dep[w][lane] = dep[q];
+    }
     uint32_t carry = 0;   // 1 + lane of the entry owning the position before the window
     for (uint32_t w0 = 0; w0 < wend; w0 += 64) {
       L.mark[w][lane] = 0;
@@ -184,7 +192,10 @@ __device__ __forceinline__ void walk_keys(const float2* __restrict__ xy,
         const uint4 rc = L.rect[w][m - 1];
         const uint32_t jj = pos - rc.x;
         const uint32_t row = div_small(jj, rc.z);
-        op(rc.y + row * rc.w + (jj - row * rc.z), L.ent[w][m - 1], kDepth ? L.dep[w][m - 1] : 0u);
+        if constexpr (kDepth)
+          op(rc.y + row * rc.w + (jj - row * rc.z), L.ent[w][m - 1], L.dep[w][m - 1]);
+        else
+          op(rc.y + row * rc.w + (jj - row * rc.z), 0u, 0u);
       }
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
@@ -193,13 +204,85 @@ __device__ __forceinline__ void walk_keys(const float2* __restrict__ xy,
 }
 
 // ---------------------------------------------------------------------------
-// counts: chunk x tile matrix, column scan
+// compaction, counts: chunk x tile matrix, column scan
 // ---------------------------------------------------------------------------
 
-// Grid (chunks, views).  Row blockIdx.x of `matrix` ([chunks][n_tiles]), over
-// the columns of view blockIdx.y, receives the keys this chunk emits per tile.
-__global__ __launch_bounds__(kBinThreads) void bin_hist_kernel(const float2* __restrict__ xy,
-                                                               const int32_t* __restrict__ radius,
+constexpr int kCompactItems = 4;                 // entries per thread (256 threads)
+constexpr int kCompactChunk = 256 * kCompactItems;
+
+// Grid (entries / kCompactChunk, views): the splats of view v that touch a
+// tile (stored count > 0, or radius > 0 when counts are not stored) are
+// appended to the view's list, [v n, v n + list_count[v]), as {u, v, radius,
+// depth bits} records with their entries (v n + i) beside them.  One global
+// atomic per workgroup reserves its run; the list order is the order of the
+// reservations, which the per-tile sort makes irrelevant.
+__global__ __launch_bounds__(256) void bin_compact_kernel(const float2* __restrict__ xy,
+                                                          const int32_t* __restrict__ radius,
+                                                          const float4* __restrict__ rd,
+                                                          const uint32_t* __restrict__ stored,
+                                                          int64_t n,
+                                                          uint32_t* __restrict__ list_count,
+                                                          uint4* __restrict__ rec,
+                                                          uint32_t* __restrict__ ids) {
+  __shared__ uint32_t s_wave[4];
+  __shared__ uint32_t s_base;
+  const int v = blockIdx.y;
+  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * kCompactChunk;
+  bool keep[kCompactItems];
+  uint32_t mine = 0;
+#pragma unroll
+  for (int q = 0; q < kCompactItems; ++q) {
+    const int64_t i = i0 + q * 256 + threadIdx.x;
+    const int64_t e = (int64_t)v * n + (i < n ? i : n - 1);
+    const uint32_t x = stored ? stored[e] : (uint32_t)max(radius[e], 0);
+    keep[q] = i < n && x > 0u;
+    mine += keep[q] ? 1u : 0u;
+  }
+  // the kept splats' data, loaded while the run is reserved (entries not
+  // kept read the view's first entry instead, one cached line)
+  float2 c[kCompactItems];
+  int32_t r[kCompactItems];
+  float z[kCompactItems];
+#pragma unroll
+  for (int q = 0; q < kCompactItems; ++q) {
+    const int64_t e = (int64_t)v * n + (keep[q] ? i0 + q * 256 + threadIdx.x : 0);
+    c[q] = xy[e];
+    r[q] = radius[e];
+    z[q] = rd[e].w;
+  }
+  const uint32_t inc = wave_prefix_sum(mine);
+  if (lane == 63) s_wave[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t tot = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    s_base = tot ? atomicAdd(&list_count[v], tot) : 0u;
+  }
+  __syncthreads();
+  uint32_t pos = s_base + inc - mine;
+  for (uint32_t k = 0; k < w; ++k) pos += s_wave[k];
+  uint4* vrec = rec + (int64_t)v * n;
+  uint32_t* vids = ids + (int64_t)v * n;
+#pragma unroll
+  for (int q = 0; q < kCompactItems; ++q) {
+    if (keep[q]) {
+      vrec[pos] = make_uint4(__float_as_uint(c[q].x), __float_as_uint(c[q].y), (uint32_t)r[q],
+                             __float_as_uint(z[q]));
+      vids[pos] = (uint32_t)((int64_t)v * n + i0 + q * 256 + threadIdx.x);
+      ++pos;
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t list_chunks(uint32_t count) {
+  return (count + kBinChunk - 1) / kBinChunk;
+}
+
+// Grid (kBinGrid, views): workgroup x takes chunks x, x + kBinGrid, ... of
+// view y's list; row `chunk` of `matrix` ([chunks][n_tiles]), over the
+// view's columns, receives the keys the chunk emits per tile.
+__global__ __launch_bounds__(kBinThreads) void bin_hist_kernel(const uint4* __restrict__ rec,
+                                                               const uint32_t* __restrict__ list_count,
                                                                int64_t n, ViewTable vt,
                                                                int lds_tiles,
                                                                uint32_t* __restrict__ matrix) {
@@ -207,45 +290,55 @@ __global__ __launch_bounds__(kBinThreads) void bin_hist_kernel(const float2* __r
   __shared__ WalkLds L;
   const int v = blockIdx.y;
   const ViewInfo& vi = vt.v[v];
-  const int64_t i0 = (int64_t)blockIdx.x * kBinChunk;
+  const uint32_t count = list_count[v];
   const int vtiles = vi.tiles_x * vi.tiles_y;
-  uint32_t* row = matrix + (int64_t)blockIdx.x * vt.n_tiles + vi.tile_base;
-  for (int tw = 0; tw < vtiles; tw += lds_tiles) {   // tile windows (one unless the view is huge)
-    const uint32_t span = (uint32_t)min(lds_tiles, vtiles - tw);
-    for (uint32_t t = threadIdx.x; t < span; t += kBinThreads) s_hist[t] = 0u;
-    __syncthreads();
-    walk_keys<false>(xy, radius, nullptr, n, v, vi, i0, L, [&](uint32_t tile, uint32_t, uint32_t) {
-      const uint32_t k = tile - (uint32_t)tw;
-      if (k < span) atomicAdd(&s_hist[k], 1u);
-    });
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t < span; t += kBinThreads) row[tw + t] = s_hist[t];
-    __syncthreads();
+  const uint4* vrec = rec + (int64_t)v * n;
+  for (uint32_t ch = blockIdx.x; ch < list_chunks(count); ch += gridDim.x) {
+    uint32_t* row = matrix + (int64_t)ch * vt.n_tiles + vi.tile_base;
+    for (int tw = 0; tw < vtiles; tw += lds_tiles) {   // tile windows (one unless the view is huge)
+      const uint32_t span = (uint32_t)min(lds_tiles, vtiles - tw);
+      for (uint32_t t = threadIdx.x; t < span; t += kBinThreads) s_hist[t] = 0u;
+      __syncthreads();
+      walk_keys<false>(vrec, nullptr, count, ch * kBinChunk, vi, L,
+                       [&](uint32_t tile, uint32_t, uint32_t) {
+                         const uint32_t k = tile - (uint32_t)tw;
+                         if (k < span) atomicAdd(&s_hist[k], 1u);
+                       });
+      __syncthreads();
+      for (uint32_t t = threadIdx.x; t < span; t += kBinThreads) row[tw + t] = s_hist[t];
+      __syncthreads();
+    }
   }
 }
 
-// One thread per tile: exclusive scan down its column (in place) and the
-// column total in counts.
-__global__ __launch_bounds__(256) void bin_column_kernel(uint32_t* __restrict__ matrix, int chunks,
-                                                         int n_tiles,
+// Grid (view tiles / 256, views), one thread per tile: exclusive scan down
+// its column over the view's chunks (in place) and the column total.
+__global__ __launch_bounds__(256) void bin_column_kernel(uint32_t* __restrict__ matrix,
+                                                         const uint32_t* __restrict__ list_count,
+                                                         ViewTable vt,
                                                          uint32_t* __restrict__ counts) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= n_tiles) return;
+  const int v = blockIdx.y;
+  const ViewInfo& vi = vt.v[v];
+  const int tl = blockIdx.x * 256 + threadIdx.x;
+  if (tl >= vi.tiles_x * vi.tiles_y) return;
+  const int64_t T = vt.n_tiles;
+  const int t = vi.tile_base + tl;
+  const int chunks = (int)list_chunks(list_count[v]);
   uint32_t run = 0;
   int c = 0;
   for (; c + 8 <= chunks; c += 8) {
     uint32_t x[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) x[q] = matrix[(int64_t)(c + q) * n_tiles + t];
+    for (int q = 0; q < 8; ++q) x[q] = matrix[(int64_t)(c + q) * T + t];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      matrix[(int64_t)(c + q) * n_tiles + t] = run;
+      matrix[(int64_t)(c + q) * T + t] = run;
       run += x[q];
     }
   }
   for (; c < chunks; ++c) {
-    const uint32_t x = matrix[(int64_t)c * n_tiles + t];
-    matrix[(int64_t)c * n_tiles + t] = run;
+    const uint32_t x = matrix[(int64_t)c * T + t];
+    matrix[(int64_t)c * T + t] = run;
     run += x;
   }
   counts[t] = run;
@@ -259,7 +352,9 @@ constexpr int kScanBlock = 1024;   // tiles per scan workgroup (256 threads x 4)
 
 __global__ __launch_bounds__(256) void bin_scan_reduce_kernel(const uint32_t* __restrict__ counts,
                                                               int n_tiles,
-                                                              uint64_t* __restrict__ partial) {
+                                                              uint64_t* __restrict__ partial,
+                                                              uint32_t* __restrict__ n_long) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *n_long = 0u;   // the down-sweep queues long lists
   __shared__ uint64_t s_wave[4];
   const int base = blockIdx.x * kScanBlock + threadIdx.x;
   uint64_t acc = 0;
@@ -273,9 +368,9 @@ __global__ __launch_bounds__(256) void bin_scan_reduce_kernel(const uint32_t* __
 
 // Each workgroup adds the totals of the blocks before it and scans its own
 // 1,024 tiles (4 consecutive per thread): ranges [start, end) ([0, 0) for an
-// empty tile, and for all on overflow) and every tile's first slot; block 0 also
-// writes the key count in 64 bits, its 32-bit clamp and a zero long-list
-// count.
+// empty tile, and for all on overflow) and every tile's first slot, and
+// queues the tiles with more than kSegShort keys; block 0 also writes the
+// key count in 64 bits and its 32-bit clamp.
 __global__ __launch_bounds__(256) void bin_scan_down_kernel(const uint32_t* __restrict__ counts,
                                                             int n_tiles,
                                                             const uint64_t* __restrict__ partial,
@@ -284,6 +379,7 @@ __global__ __launch_bounds__(256) void bin_scan_down_kernel(const uint32_t* __re
                                                             uint32_t* __restrict__ starts,
                                                             uint64_t* __restrict__ total,
                                                             uint32_t* __restrict__ n_keys,
+                                                            uint32_t* __restrict__ long_list,
                                                             uint32_t* __restrict__ n_long) {
   __shared__ uint64_t s_red[2][4];
   __shared__ uint32_t s_wave[4];
@@ -318,7 +414,6 @@ __global__ __launch_bounds__(256) void bin_scan_down_kernel(const uint32_t* __re
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *total = tot;
     *n_keys = tot > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)tot;
-    *n_long = 0u;
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -331,19 +426,32 @@ __global__ __launch_bounds__(256) void bin_scan_down_kernel(const uint32_t* __re
     }
     st += c[q];
   }
+  // queue the long lists: one atomic per wavefront and item
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t = t0 + q;
+    const bool lng = ok && t < n_tiles && c[q] > (uint32_t)kSegShort;
+    const uint64_t m = __ballot(lng);
+    if (m) {
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(n_long, (uint32_t)__popcll(m));
+      base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+      if (lng) long_list[base + (uint32_t)__popcll(m & ((uint64_t(1) << lane) - 1))] = (uint32_t)t;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
 // emission
 // ---------------------------------------------------------------------------
 
-// Grid (chunks, views): every key's (depth bits, entry) pair goes to its
-// tile's segment at slot start + (the chunk's offset in the column) + (its
-// rank among the chunk's keys of that tile, in no particular order).
-// Nothing on overflow.
+// Grid (kBinGrid, views), chunks as in the histogram: every key's (depth
+// bits, entry) pair goes to its tile's segment at slot start + (the chunk's
+// offset in the column) + (its rank among the chunk's keys of that tile, in
+// no particular order).  Nothing on overflow.
 __global__ __launch_bounds__(kBinThreads) void bin_emit_kernel(
-    const float2* __restrict__ xy, const int32_t* __restrict__ radius,
-    const float4* __restrict__ rd, int64_t n, ViewTable vt, int lds_tiles,
+    const uint4* __restrict__ rec, const uint32_t* __restrict__ ids,
+    const uint32_t* __restrict__ list_count, int64_t n, ViewTable vt, int lds_tiles,
     const uint32_t* __restrict__ matrix, const uint32_t* __restrict__ starts,
     const uint64_t* __restrict__ total, int64_t capacity, uint64_t* __restrict__ staged) {
   extern __shared__ uint32_t s_slot[];
@@ -351,19 +459,24 @@ __global__ __launch_bounds__(kBinThreads) void bin_emit_kernel(
   if (*total > (uint64_t)capacity) return;
   const int v = blockIdx.y;
   const ViewInfo& vi = vt.v[v];
-  const int64_t i0 = (int64_t)blockIdx.x * kBinChunk;
+  const uint32_t count = list_count[v];
   const int vtiles = vi.tiles_x * vi.tiles_y;
-  const uint32_t* row = matrix + (int64_t)blockIdx.x * vt.n_tiles + vi.tile_base;
+  const uint4* vrec = rec + (int64_t)v * n;
+  const uint32_t* vids = ids + (int64_t)v * n;
   const uint32_t* st = starts + vi.tile_base;
-  for (int tw = 0; tw < vtiles; tw += lds_tiles) {
-    const uint32_t span = (uint32_t)min(lds_tiles, vtiles - tw);
-    for (uint32_t t = threadIdx.x; t < span; t += kBinThreads) s_slot[t] = st[tw + t] + row[tw + t];
-    __syncthreads();
-    walk_keys<true>(xy, radius, rd, n, v, vi, i0, L, [&](uint32_t tile, uint32_t ent, uint32_t dep) {
-      const uint32_t k = tile - (uint32_t)tw;
-      if (k < span) staged[atomicAdd(&s_slot[k], 1u)] = ((uint64_t)dep << 32) | ent;
-    });
-    __syncthreads();
+  for (uint32_t ch = blockIdx.x; ch < list_chunks(count); ch += gridDim.x) {
+    const uint32_t* row = matrix + (int64_t)ch * vt.n_tiles + vi.tile_base;
+    for (int tw = 0; tw < vtiles; tw += lds_tiles) {
+      const uint32_t span = (uint32_t)min(lds_tiles, vtiles - tw);
+      for (uint32_t t = threadIdx.x; t < span; t += kBinThreads) s_slot[t] = st[tw + t] + row[tw + t];
+      __syncthreads();
+      walk_keys<true>(vrec, vids, count, ch * kBinChunk, vi, L,
+                      [&](uint32_t tile, uint32_t ent, uint32_t dep) {
+                        const uint32_t k = tile - (uint32_t)tw;
+                        if (k < span) staged[atomicAdd(&s_slot[k], 1u)] = ((uint64_t)dep << 32) | ent;
+                      });
+      __syncthreads();
+    }
   }
 }
 
@@ -459,9 +572,9 @@ __device__ __forceinline__ void wave_segment_sort(const uint64_t* __restrict__ s
   }
 }
 
-// Four wavefronts sort a list of at most 256 R pairs: wavefront w holds
-// indices w 64 R + lane R + k; partners 64 R or more apart are exchanged
-// through LDS (s_x, 256 R pairs).
+// The kSortWaves wavefronts of a workgroup sort a list of at most
+// kSortWaves 64 R pairs: wavefront w holds indices w 64 R + lane R + k;
+// partners 64 R or more apart are exchanged through LDS (s_x).
 template <int R, typename K>
 __device__ __forceinline__ void block_segment_sort(const uint64_t* __restrict__ staged, uint32_t s,
                                                    int len, uint32_t tile, K* keys, uint32_t* vals,
@@ -475,7 +588,7 @@ __device__ __forceinline__ void block_segment_sort(const uint64_t* __restrict__ 
     x[k] = i < len ? staged[s + i] : ~0ull;
   }
 #pragma unroll
-  for (int kk = 2; kk <= 256 * R; kk <<= 1) {
+  for (int kk = 2; kk <= kSortWaves * 64 * R; kk <<= 1) {
 #pragma unroll
     for (int j = kk >> 1; j > 0; j >>= 1) {
       if (j >= 64 * R) {
@@ -504,17 +617,17 @@ __device__ __forceinline__ void block_segment_sort(const uint64_t* __restrict__ 
 
 // Stable LSD radix sort of a long segment by its 64-bit (depth, entry) pair,
 // one workgroup, 8 passes of 8 bits between buffers a and b (an even number:
-// the result ends in a).  Per 256-key round, keys are ranked within their
-// wavefront by match masks of equal digits and across wavefronts by their
-// digit counts, which keeps equal digits in input order.
+// the result ends in a).  Per kSortThreads-key round, keys are ranked within
+// their wavefront by match masks of equal digits and across wavefronts by
+// their digit counts, which keeps equal digits in input order.
 __device__ void radix_segment_sort(uint64_t* a, uint64_t* b, int64_t len, uint32_t* s_cnt,
-                                   uint32_t* s_wdig) {
+                                   uint32_t* s_wdig /* [kSortWaves][256] */) {
   const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
   for (int pass = 0; pass < 8; ++pass) {
     const int shift = 8 * pass;
-    s_cnt[threadIdx.x] = 0u;
+    if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0u;
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < len; i += 256)
+    for (int64_t i = threadIdx.x; i < len; i += kSortThreads)
       atomicAdd(&s_cnt[(uint32_t)(a[i] >> shift) & 255u], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {   // first output slot of every digit
@@ -526,7 +639,7 @@ __device__ void radix_segment_sort(uint64_t* a, uint64_t* b, int64_t len, uint32
       }
     }
     __syncthreads();
-    for (int64_t c0 = 0; c0 < len; c0 += 256) {
+    for (int64_t c0 = 0; c0 < len; c0 += kSortThreads) {
       const int64_t i = c0 + threadIdx.x;
       const bool valid = i < len;
       const uint64_t k = valid ? a[i] : 0ull;
@@ -538,7 +651,7 @@ __device__ void radix_segment_sort(uint64_t* a, uint64_t* b, int64_t len, uint32
         peers &= ((dig >> bit) & 1u) ? m : ~m;
       }
       const uint32_t below = (uint32_t)__popcll(peers & ((uint64_t(1) << lane) - 1));
-      for (int d = threadIdx.x; d < 4 * 256; d += 256) s_wdig[d] = 0u;
+      for (int d = threadIdx.x; d < kSortWaves * 256; d += kSortThreads) s_wdig[d] = 0u;
       __syncthreads();
       if (valid && below == 0) s_wdig[w * 256 + dig] = (uint32_t)__popcll(peers);
       __syncthreads();
@@ -548,8 +661,11 @@ __device__ void radix_segment_sort(uint64_t* a, uint64_t* b, int64_t len, uint32
         b[off] = k;
       }
       __syncthreads();
-      const uint32_t d = threadIdx.x;
-      s_cnt[d] += s_wdig[d] + s_wdig[256 + d] + s_wdig[512 + d] + s_wdig[768 + d];
+      if (threadIdx.x < 256) {
+        uint32_t add = 0;
+        for (int q = 0; q < kSortWaves; ++q) add += s_wdig[q * 256 + threadIdx.x];
+        s_cnt[threadIdx.x] += add;
+      }
       __syncthreads();
     }
     uint64_t* t = a;
@@ -559,60 +675,54 @@ __device__ void radix_segment_sort(uint64_t* a, uint64_t* b, int64_t len, uint32
   }
 }
 
-// Grid T / 4: one wavefront per tile sorts lists of up to kSegShort pairs
-// in registers; longer ones are queued for the long-list grid.
+// Grid kLongSlots + T / kSortWaves.  The first kLongSlots workgroups take
+// the queued lists longer than kSegShort (all wavefronts of a workgroup up to
+// kSegLong pairs, else the radix sort, whose pair buffers are `staged` itself
+// and `spare`); they are dispatched first, so the long lists run beside the
+// short ones.  In every later workgroup each wavefront sorts one tile's list
+// of up to kSegShort pairs in registers.
 template <typename K>
-__global__ __launch_bounds__(256) void seg_sort_kernel(const uint32_t* __restrict__ ranges,
-                                                       int n_tiles,
-                                                       const uint64_t* __restrict__ staged,
-                                                       K* __restrict__ keys,
-                                                       uint32_t* __restrict__ vals,
-                                                       uint32_t* __restrict__ long_list,
-                                                       uint32_t* __restrict__ n_long) {
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ __launch_bounds__(kSortThreads) void seg_sort_kernel(const uint32_t* __restrict__ ranges,
+                                                                int n_tiles,
+                                                                uint64_t* __restrict__ staged,
+                                                                uint64_t* __restrict__ spare,
+                                                                K* __restrict__ keys,
+                                                                uint32_t* __restrict__ vals,
+                                                                const uint32_t* __restrict__ long_list,
+                                                                const uint32_t* __restrict__ n_long) {
+  __shared__ uint64_t s_mem[kSegLong + 128];   // pairs, or the radix sort's digit counts
+  if (blockIdx.x < (unsigned)kLongSlots) {
+    uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_mem + kSegLong);
+    uint32_t* s_wdig = reinterpret_cast<uint32_t*>(s_mem);
+    const uint32_t count = *n_long;
+    for (uint32_t q = blockIdx.x; q < count; q += kLongSlots) {
+      const uint32_t tile = long_list[q];
+      const uint32_t s = ranges[2 * (int64_t)tile], e = ranges[2 * (int64_t)tile + 1];
+      const int64_t len = (int64_t)e - (int64_t)s;
+      if (len <= kSegLong / 2) {
+        block_segment_sort<kSegLong / (2 * kSortThreads)>(staged, s, (int)len, tile, keys, vals, s_mem);
+      } else if (len <= kSegLong) {
+        block_segment_sort<kSegLong / kSortThreads>(staged, s, (int)len, tile, keys, vals, s_mem);
+      } else {
+        radix_segment_sort(staged + s, spare + s, len, s_cnt, s_wdig);
+        for (int64_t i = threadIdx.x; i < len; i += kSortThreads)
+          seg_store(keys, vals, (int64_t)s + i, tile, staged[s + i]);
+      }
+      __syncthreads();   // LDS reused by the next list
+    }
+    return;
+  }
+  const int tile = (int)(blockIdx.x - kLongSlots) * kSortWaves + (int)(threadIdx.x >> 6);
   if (tile >= n_tiles) return;
   const uint32_t s = ranges[2 * (int64_t)tile], e = ranges[2 * (int64_t)tile + 1];
   const int64_t len = (int64_t)e - (int64_t)s;   // 0 for every tile on overflow
   const uint32_t t = (uint32_t)tile;
-  if (len <= 0) return;
+  if (len <= 0 || len > kSegShort) return;
   if (len <= 64) wave_segment_sort<1>(staged, s, (int)len, t, keys, vals);
   else if (len <= 128) wave_segment_sort<2>(staged, s, (int)len, t, keys, vals);
   else if (len <= 256) wave_segment_sort<4>(staged, s, (int)len, t, keys, vals);
   else if (len <= 512) wave_segment_sort<8>(staged, s, (int)len, t, keys, vals);
-  else if (len <= kSegShort) wave_segment_sort<16>(staged, s, (int)len, t, keys, vals);
-  else if (lane_id() == 0) long_list[atomicAdd(n_long, 1u)] = t;
-}
-
-// Grid kLongBlocks: the queued long lists, by four wavefronts up to kSegLong
-// pairs, else by the radix sort, whose pair buffers are `staged` itself and
-// `spare`.
-template <typename K>
-__global__ __launch_bounds__(256) void long_sort_kernel(const uint32_t* __restrict__ ranges,
-                                                        const uint32_t* __restrict__ long_list,
-                                                        const uint32_t* __restrict__ n_long,
-                                                        uint64_t* __restrict__ staged,
-                                                        uint64_t* __restrict__ spare,
-                                                        K* __restrict__ keys,
-                                                        uint32_t* __restrict__ vals) {
-  __shared__ uint64_t s_x[kSegLong];
-  __shared__ uint32_t s_cnt[256];
-  __shared__ uint32_t s_wdig[4 * 256];
-  const uint32_t count = *n_long;
-  for (uint32_t q = blockIdx.x; q < count; q += gridDim.x) {
-    const uint32_t tile = long_list[q];
-    const uint32_t s = ranges[2 * (int64_t)tile], e = ranges[2 * (int64_t)tile + 1];
-    const int64_t len = (int64_t)e - (int64_t)s;
-    if (len <= kSegLong / 2) {
-      block_segment_sort<kSegLong / 512>(staged, s, (int)len, tile, keys, vals, s_x);
-    } else if (len <= kSegLong) {
-      block_segment_sort<kSegLong / 256>(staged, s, (int)len, tile, keys, vals, s_x);
-    } else {
-      radix_segment_sort(staged + s, spare + s, len, s_cnt, s_wdig);
-      for (int64_t i = threadIdx.x; i < len; i += 256)
-        seg_store(keys, vals, (int64_t)s + i, tile, staged[s + i]);
-    }
-    __syncthreads();   // s_x, s_cnt reused by the next list
-  }
+  else wave_segment_sort<16>(staged, s, (int)len, t, keys, vals);
 }
 
 // Start of a call that ends before the segments exist: all ranges empty and,
@@ -738,7 +848,7 @@ __global__ __launch_bounds__(kOrderBlock) void order_scatter_kernel(
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int64_t bin_chunks(int64_t n) { return (n + kBinChunk - 1) / kBinChunk; }
+int64_t bin_chunks(int64_t n) { return (n + kBinChunk - 1) / kBinChunk; }   // at most
 
 }  // namespace
 
@@ -756,11 +866,17 @@ BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity)
   P.n_tiles = vt.n_tiles;
   P.chunks = bin_chunks(n);
   P.lds_tiles = 1;
-  for (int v = 0; v < vt.n_views; ++v)
+  P.max_view_tiles = 1;
+  for (int v = 0; v < vt.n_views; ++v) {
+    P.max_view_tiles = std::max(P.max_view_tiles, vt.v[v].tiles_x * vt.v[v].tiles_y);
     P.lds_tiles = std::max(P.lds_tiles, std::min(kLdsTiles, vt.v[v].tiles_x * vt.v[v].tiles_y));
+  }
   const size_t nt = sizeof(uint32_t) * (size_t)std::max(vt.n_tiles, 1);
   size_t off = 0;
   P.off_matrix = off;    off += align_up(sizeof(uint32_t) * (size_t)P.chunks * (size_t)vt.n_tiles);
+  P.off_list = off;      off += align_up(sizeof(uint4) * (size_t)P.n_entries);      // compacted splats
+  P.off_ids = off;       off += align_up(sizeof(uint32_t) * (size_t)P.n_entries);   // their entries
+  P.off_list_count = off; off += align_up(sizeof(uint32_t) * GS_MAX_VIEWS);
   P.off_counts = off;    off += align_up(nt);   // keys per tile
   P.off_starts = off;    off += align_up(nt);   // first slot of every tile's segment
   P.off_long = off;      off += align_up(nt);   // tiles whose lists the long grid sorts
@@ -778,6 +894,9 @@ BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity)
 int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs_bins& bins,
                  uint32_t* n_keys_host, char* ws, const BinSortPlan& P, hipStream_t s) {
   auto* matrix = reinterpret_cast<uint32_t*>(ws + P.off_matrix);
+  auto* list = reinterpret_cast<uint4*>(ws + P.off_list);
+  auto* ids = reinterpret_cast<uint32_t*>(ws + P.off_ids);
+  auto* list_count = reinterpret_cast<uint32_t*>(ws + P.off_list_count);
   auto* counts = reinterpret_cast<uint32_t*>(ws + P.off_counts);
   auto* starts = reinterpret_cast<uint32_t*>(ws + P.off_starts);
   auto* long_list = reinterpret_cast<uint32_t*>(ws + P.off_long);
@@ -800,18 +919,27 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
     return (e = hipGetLastError()) == hipSuccess ? GS_OK : hip_fail(e, "bin sort launch");
   }
   const unsigned tblocks = (unsigned)((T + 255) / 256);
-  const dim3 bin_grid((unsigned)P.chunks, (unsigned)vt.n_views);
-  // 1. keys per (chunk, tile), per tile, the segments and the key count
-  if (P.chunks > 0)
-    hipLaunchKernelGGL(bin_hist_kernel, bin_grid, dim3(kBinThreads), lds, s, xy, p.radius, n, vt,
-                       P.lds_tiles, matrix);
-  hipLaunchKernelGGL(bin_column_kernel, dim3(tblocks), dim3(256), 0, s, matrix, (int)P.chunks, T,
-                     counts);
+  const dim3 bin_grid((unsigned)std::min<int64_t>(kBinGrid, std::max<int64_t>(P.chunks, 1)),
+                      (unsigned)vt.n_views);
+  // 1. the splats that touch a tile, per view; keys per (chunk, tile), per
+  // tile, the segments and the key count
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, s, list_count, 0u,
+                     (int64_t)vt.n_views);
+  if (n > 0) {
+    hipLaunchKernelGGL(bin_compact_kernel, dim3((unsigned)((n + kCompactChunk - 1) / kCompactChunk),
+                       (unsigned)vt.n_views), dim3(256), 0, s, xy, p.radius, rd, p.tiles, n,
+                       list_count, list, ids);
+    hipLaunchKernelGGL(bin_hist_kernel, bin_grid, dim3(kBinThreads), lds, s, list, list_count, n,
+                       vt, P.lds_tiles, matrix);
+  }
+  hipLaunchKernelGGL(bin_column_kernel, dim3((unsigned)((P.max_view_tiles + 255) / 256),
+                     (unsigned)vt.n_views), dim3(256), 0, s, matrix, list_count, vt, counts);
   const int nsb = (T + kScanBlock - 1) / kScanBlock;
   hipLaunchKernelGGL(bin_scan_reduce_kernel, dim3((unsigned)nsb), dim3(256), 0, s, counts, T,
-                     partial);
+                     partial, n_long);
   hipLaunchKernelGGL(bin_scan_down_kernel, dim3((unsigned)nsb), dim3(256), 0, s, counts, T,
-                     partial, nsb, P.capacity, bins.ranges, starts, total, bins.n_keys, n_long);
+                     partial, nsb, P.capacity, bins.ranges, starts, total, bins.n_keys, long_list,
+                     n_long);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "bin count launch");
 
   bool empty = false;
@@ -833,22 +961,17 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
     empty = tot == 0;
   }
   // 2. placement into the segments, then each segment sorted by (depth, entry)
-  if (P.chunks > 0 && !empty) {
-    hipLaunchKernelGGL(bin_emit_kernel, bin_grid, dim3(kBinThreads), lds, s, xy, p.radius, rd, n,
-                       vt, P.lds_tiles, matrix, starts, total, P.capacity, staged);
-    const unsigned sblocks = (unsigned)((T + 3) / 4);
-    if (bins.keys) {
-      hipLaunchKernelGGL(seg_sort_kernel<uint64_t>, dim3(sblocks), dim3(256), 0, s, bins.ranges,
-                         T, staged, bins.keys, bins.values, long_list, n_long);
-      hipLaunchKernelGGL(long_sort_kernel<uint64_t>, dim3(kLongBlocks), dim3(256), 0, s,
-                         bins.ranges, long_list, n_long, staged, spare, bins.keys, bins.values);
-    } else {
-      hipLaunchKernelGGL(seg_sort_kernel<uint32_t>, dim3(sblocks), dim3(256), 0, s, bins.ranges,
-                         T, staged, (uint32_t*)nullptr, bins.values, long_list, n_long);
-      hipLaunchKernelGGL(long_sort_kernel<uint32_t>, dim3(kLongBlocks), dim3(256), 0, s,
-                         bins.ranges, long_list, n_long, staged, spare, (uint32_t*)nullptr,
-                         bins.values);
-    }
+  if (n > 0 && !empty) {
+    hipLaunchKernelGGL(bin_emit_kernel, bin_grid, dim3(kBinThreads), lds, s, list, ids, list_count,
+                       n, vt, P.lds_tiles, matrix, starts, total, P.capacity, staged);
+    const unsigned sblocks = (unsigned)(kLongSlots + (T + kSortWaves - 1) / kSortWaves);
+    if (bins.keys)
+      hipLaunchKernelGGL(seg_sort_kernel<uint64_t>, dim3(sblocks), dim3(kSortThreads), 0, s,
+                         bins.ranges, T, staged, spare, bins.keys, bins.values, long_list, n_long);
+    else
+      hipLaunchKernelGGL(seg_sort_kernel<uint32_t>, dim3(sblocks), dim3(kSortThreads), 0, s,
+                         bins.ranges, T, staged, spare, (uint32_t*)nullptr, bins.values, long_list,
+                         n_long);
   }
   // 3. launch order of the compositing grids (from the ranges; on overflow
   // they are all empty and this is the identity)

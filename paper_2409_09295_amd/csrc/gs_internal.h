@@ -213,8 +213,9 @@ struct BinSortPlan {
   int64_t chunks;        // binning workgroups per view
   int32_t n_tiles;
   int32_t lds_tiles;     // LDS histogram bins (largest view, at most the LDS limit)
+  int32_t max_view_tiles;
   // workspace layout (byte offsets)
-  size_t off_matrix, off_counts, off_starts, off_long, off_flag, off_partial, off_order,
+  size_t off_matrix, off_list, off_ids, off_list_count, off_counts, off_starts, off_long, off_flag, off_partial, off_order,
       off_staged, off_spare, total;
 };
 BinSortPlan make_bin_sort_plan(int64_t n, const ViewTable& vt, int64_t capacity);

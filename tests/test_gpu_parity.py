@@ -85,11 +85,12 @@ def test_bin_sort_bit_exact(gs, case, sync, stored, with_keys):
     np.testing.assert_array_equal(u32(bins2.order), u32(bins.order))
 
 
-@pytest.mark.parametrize("n", [700, 3000])
+@pytest.mark.parametrize("n", [700, 1500, 3000, 6000])
 def test_bin_sort_crowded_tiles(gs, n):
-    """Every splat covers the same few tiles: per-tile lists of n keys (above
-    and below the in-LDS limit of the per-tile depth sort), a third of them
-    at repeated depths so that ties fall back to the Gaussian index."""
+    """Every splat covers the same few tiles: per-tile lists of up to n keys
+    (through every per-tile sort: one wavefront, four wavefronts with 8 or 16
+    pairs per lane, and the radix sort past 4,096), a third of them at
+    repeated depths so that ties fall back to the Gaussian index."""
     cams = [scenes.pinhole(48, 40, 40.0)]
     sp = scenes.random_splats(n, cams, seed=33, depth_ties=0.35, cull_frac=0.02)
     rng = np.random.default_rng(34)
