@@ -86,20 +86,45 @@ def unet_layers(in_ch: int = 8, ch=CHANNELS):
             ("d0a", c1 + c0, c0), ("d0b", c0, c0)]
 
 
-def unet_forward(x: torch.Tensor, p: Dict[str, torch.Tensor]) -> torch.Tensor:
+class Bf16Store(torch.autograd.Function):
+    """A tensor held in bfloat16: the value rounded to the nearest bfloat16
+    (ties to even) going forward, and the gradient flowing back rounded the
+    same way (the network keeps activations and their gradients in BF16,
+    with FP32 accumulation in between)."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return x.to(torch.float32).to(torch.bfloat16).to(x.dtype)
+
+    @staticmethod
+    def backward(ctx, g):
+        return g.to(torch.float32).to(torch.bfloat16).to(g.dtype)
+
+
+def bf16_store(x: torch.Tensor) -> torch.Tensor:
+    return Bf16Store.apply(x)
+
+
+def unet_forward(x: torch.Tensor, p: Dict[str, torch.Tensor], store=None) -> torch.Tensor:
     """x [n, h, w, in_ch]; p maps '<layer>.w' [9, cout, cin], '<layer>.b' [cout],
     'head.w' [2, c0], 'head.b' [2].  Encoder: two conv+ReLU per level, 2x2
     average pooling between levels; decoder: nearest upsampling, concatenation
-    [upsampled, skip], two conv+ReLU; 1x1 head."""
+    [upsampled, skip], two conv+ReLU; 1x1 head.
+
+    store (optional, e.g. bf16_store) is applied to every tensor the network
+    holds between layers: each conv+ReLU output, each pooled and upsampled
+    map, and each skip input of a concatenation (which rounds the gradient
+    that flows back into it on its own)."""
+    q = store if store is not None else (lambda t: t)
     r = torch.relu
-    c = lambda name, t: r(conv3x3(t, p[name + ".w"], p[name + ".b"]))
+    c = lambda name, t: q(r(conv3x3(t, p[name + ".w"], p[name + ".b"])))
     e0 = c("e0b", c("e0a", x))
-    e1 = c("e1b", c("e1a", avgpool2(e0)))
-    e2 = c("e2b", c("e2a", avgpool2(e1)))
-    e3 = c("e3b", c("e3a", avgpool2(e2)))
-    d2 = c("d2b", c("d2a", torch.cat([upsample2(e3), e2], dim=3)))
-    d1 = c("d1b", c("d1a", torch.cat([upsample2(d2), e1], dim=3)))
-    d0 = c("d0b", c("d0a", torch.cat([upsample2(d1), e0], dim=3)))
+    e1 = c("e1b", c("e1a", q(avgpool2(e0))))
+    e2 = c("e2b", c("e2a", q(avgpool2(e1))))
+    e3 = c("e3b", c("e3a", q(avgpool2(e2))))
+    d2 = c("d2b", c("d2a", torch.cat([q(upsample2(e3)), q(e2)], dim=3)))
+    d1 = c("d1b", c("d1a", torch.cat([q(upsample2(d2)), q(e1)], dim=3)))
+    d0 = c("d0b", c("d0a", torch.cat([q(upsample2(d1)), q(e0)], dim=3)))
     return head(d0, p["head.w"], p["head.b"])
 
 

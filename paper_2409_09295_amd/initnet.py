@@ -220,6 +220,17 @@ class UNet:
     def predict_depth(self, rgb: torch.Tensor) -> torch.Tensor:
         return torch.exp(self.forward(rgb)[:, 0]).clone()
 
+    def buffer_bytes(self) -> int:
+        """Bytes of the activation, gradient and prediction buffers of the
+        last batch shape."""
+        if self._bufs is None:
+            return 0
+        tot = 0
+        for v in self._bufs.values():
+            t = v.t if isinstance(v, gs.Act) else v
+            tot += t.numel() * t.element_size()
+        return tot
+
 
 # ---------------------------------------------------------------------------
 # data: renders of the map with their depth
@@ -316,6 +327,19 @@ def plain_depth(keyframes: torch.Tensor, cams: Sequence[scenes.Camera], device="
     return low.repeat_interleave(4, 0).repeat_interleave(4, 1)
 
 
+def learned_depth(net: "UNet", keyframes: torch.Tensor, cams: Sequence[scenes.Camera],
+                  device="cuda") -> Tuple[torch.Tensor, Optional[torch.Tensor], bool]:
+    """Depth and log-scale of the newest keyframe from the network
+    (Sec. III-A1); when any of its outputs is not finite, the plain
+    initialiser's depth (Eq. 1, winner-take-all) over the window instead.
+    Returns (depth [h, w], log-scale [h, w] or None, whether the network's
+    output was used)."""
+    pred = net.forward(keyframes[-1:].contiguous())[0]
+    if bool(torch.isfinite(pred).all()):
+        return torch.exp(pred[0]).clone(), pred[1].clone(), True
+    return plain_depth(keyframes, cams, device), None, False
+
+
 def abs_rel(pred: torch.Tensor, gt: torch.Tensor) -> float:
     """Mean |pred - gt| / gt over pixels with gt > 0 (pred <= 0 counts as error 1)."""
     m = gt > 0
@@ -323,21 +347,33 @@ def abs_rel(pred: torch.Tensor, gt: torch.Tensor) -> float:
     return float(err[m].mean())
 
 
-def propose(depth: torch.Tensor, cam: scenes.Camera, stride: int = 4):
+def rmse(pred: torch.Tensor, gt: torch.Tensor) -> float:
+    """Root mean square of (pred - gt) in metres over pixels with gt > 0
+    (a pixel without a prediction, pred <= 0, counts as predicting 0)."""
+    m = gt > 0
+    return float(((pred.clamp(min=0) - gt)[m] ** 2).mean().sqrt())
+
+
+def propose(depth: torch.Tensor, cam: scenes.Camera, stride: int = 4,
+            log_scale: Optional[torch.Tensor] = None):
     """Gaussians at every `stride`-th pixel of a depth image: means on the
-    back-projected rays (world frame) and isotropic log-scales
-    log(depth * stride / fx).  Returns (means [3, m], log_scales [3, m])."""
+    back-projected rays (world frame) and isotropic log-scales, the pixel
+    footprint log(depth / fx) (or the given per-pixel log_scale map) plus
+    log(stride).  Returns (means [3, m], log_scales [3, m])."""
     H, W = depth.shape
     ys, xs = torch.meshgrid(torch.arange(stride // 2, H, stride, device=depth.device),
                             torch.arange(stride // 2, W, stride, device=depth.device), indexing="ij")
     d = depth[ys, xs]
     keep = d > 0
+    foot = log_scale[ys, xs][keep] if log_scale is not None else None
     d, xs, ys = d[keep], xs[keep].float() + 0.5, ys[keep].float() + 0.5
     Xc = torch.stack([(xs - cam.cx) / cam.fx * d, (ys - cam.cy) / cam.fy * d, d])
     R = torch.as_tensor(np.asarray(cam.R), dtype=torch.float32, device=depth.device)
     t = torch.as_tensor(np.asarray(cam.t), dtype=torch.float32, device=depth.device)
     means = R.T @ (Xc - t[:, None])
-    ls = torch.log(d * stride / cam.fx).expand(3, -1)
+    if foot is None:
+        foot = torch.log(d / cam.fx)
+    ls = (foot + math.log(stride)).expand(3, -1)
     return means.contiguous(), ls.contiguous()
 
 
@@ -349,6 +385,8 @@ class InitReport:
     epochs: int
     net_absrel: float
     plain_absrel: float
+    net_rmse: float
+    plain_rmse: float
     final_loss: float
     train_seconds: float
     conv_tflops: float
@@ -356,11 +394,13 @@ class InitReport:
 
 def train_and_compare(n_gauss: int = 200000, W: int = 128, H: int = 96, n_train: int = 600,
                     n_heldout: int = 12, window: int = 8, epochs: int = 15, batch: int = 8,
-                    lr: float = 2e-3, seed: int = 0, device="cuda", log=None) -> Tuple[UNet, InitReport]:
+                    lr: float = 2e-3, seed: int = 0, sh_degree: int = 3, device="cuda",
+                    log=None) -> Tuple[UNet, InitReport]:
     """Renders a procedural room, trains the U-Net on (render, depth) pairs and
-    compares its depth AbsRel with the plain initialiser's on held-out
-    trajectory views (each with the `window` preceding keyframes as its window)."""
-    gmap, boxes = scenes.procedural_room(n_gauss, seed)
+    compares its depth AbsRel and RMSE with the plain initialiser's on
+    held-out trajectory views (each with the `window` preceding keyframes as
+    its window)."""
+    gmap, boxes = scenes.procedural_room(n_gauss, seed, sh_degree=sh_degree)
     train_cams = trajectory_cams(n_train, seed + 101, boxes, W, H)
     test_cams = trajectory_cams(n_heldout + window, seed + 202, boxes, W, H)
     rgb, depth = render_dataset(gmap, train_cams, device=device)
@@ -392,14 +432,48 @@ def train_and_compare(n_gauss: int = 200000, W: int = 128, H: int = 96, n_train:
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     flops = 3.0 * unet_flops(H, W) * steps * batch
-    net_err, plain_err = [], []
+    net_err, plain_err, net_sq, plain_sq = [], [], [], []
     for j in range(n_heldout):
         k = j + window - 1                          # held-out view, with window - 1 predecessors
         gt = tdepth[k]
         pd = net.predict_depth(trgb[k:k + 1].contiguous())[0]
         net_err.append(abs_rel(pd, gt))
+        net_sq.append(rmse(pd, gt) ** 2)
         pl = plain_depth(trgb[j:k + 1].contiguous(), test_cams[j:k + 1], device)
         plain_err.append(abs_rel(pl, gt))
+        plain_sq.append(rmse(pl, gt) ** 2)
     rep = InitReport(n_train, n_heldout, (W, H), epochs, float(np.mean(net_err)),
-                     float(np.mean(plain_err)), last, secs, flops / secs / 1e12)
+                     float(np.mean(plain_err)), float(np.sqrt(np.mean(net_sq))),
+                     float(np.sqrt(np.mean(plain_sq))), last, secs, flops / secs / 1e12)
     return net, rep
+
+
+def main(argv=None) -> None:
+    """Train and judge the initialiser at a chosen size and print one JSON
+    line; the defaults are the full-size run: 640 x 480, 5,000 training
+    renders of a 1,000,000-Gaussian room, 500 held-out views."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--gaussians", type=int, default=1000000)
+    ap.add_argument("--width", type=int, default=640)
+    ap.add_argument("--height", type=int, default=480)
+    ap.add_argument("--train", type=int, default=5000)
+    ap.add_argument("--heldout", type=int, default=500)
+    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    a = ap.parse_args(argv)
+    import sys
+    t0 = time.perf_counter()
+    _, rep = train_and_compare(a.gaussians, a.width, a.height, a.train, a.heldout, epochs=a.epochs,
+                               batch=a.batch, lr=a.lr, seed=a.seed,
+                               log=lambda m: print(m, file=sys.stderr, flush=True))
+    out = dataclasses.asdict(rep)
+    out.update(gaussians=a.gaussians, batch=a.batch, total_seconds=time.perf_counter() - t0)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

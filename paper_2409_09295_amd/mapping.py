@@ -38,7 +38,7 @@ import torch
 
 from . import gs, scenes
 from .global_stage import ISO_WEIGHT, GlobalStage, prune
-from .initnet import plain_depth, propose
+from .initnet import learned_depth, plain_depth, propose
 from .replay import DEFAULT_LR, BatchedStep
 
 Y00 = 0.28209479177387814   # degree-0 real spherical harmonic
@@ -56,12 +56,13 @@ class MappingLoop:
     def __init__(self, width: int, height: int, fx: float, *, window: int = 8, n_past: int = 4,
                  stride: int = 8, local_iters: int = 60, global_iters: int = 100,
                  active_quantile: float = 0.85, sh_degree: int = 0, seed: int = 0,
-                 lrs: Optional[Dict[str, float]] = None, device="cuda"):
+                 lrs: Optional[Dict[str, float]] = None, init_net=None, device="cuda"):
         self.W, self.H, self.fx = width, height, fx
         self.N, self.n_past, self.stride = window, n_past, stride
         self.local_iters, self.global_iters = local_iters, global_iters
         self.q = active_quantile
         self.lrs = dict(MAPPING_LR) if lrs is None else lrs
+        self.init_net = init_net          # learned initialiser (initnet.UNet) or None
         self.sh_degree = sh_degree
         self.device = device
         self.rng = np.random.default_rng(seed)
@@ -83,15 +84,24 @@ class MappingLoop:
         return torch.stack([k["image"] for k in self.window])
 
     def _initialise(self) -> gs.Gaussians:
-        """New Gaussians for the newest keyframe from the window's cost volume
-        (Eq. 1, winner-take-all): one per stride x stride block with a depth,
-        coloured from the keyframe, isotropic, opacity 0.5."""
+        """New Gaussians for the newest keyframe, one per stride x stride block
+        with a depth, coloured from the keyframe, isotropic, opacity 0.5.  The
+        depth (and scale) comes from the learned initialiser when one is
+        given and its output is finite (Sec. III-A1), else from the window's
+        cost volume (Eq. 1, winner-take-all)."""
         kfs = self._window_tensor()
         cams = [k["cam"] for k in self.window]
         k, _, H, W = kfs.shape
-        cv = gs.Tracked(gs.GS_MEM_INIT, gs.gs_cost_volume_workspace_size(k, H, W) + 4 * H * W)
-        depth = plain_depth(kfs, cams, self.device)
-        means, ls = propose(depth, cams[-1], self.stride)
+        lsmap = None
+        if self.init_net is not None:
+            depth, lsmap, used = learned_depth(self.init_net, kfs, cams, self.device)
+            cv = gs.Tracked(gs.GS_MEM_INIT, self.init_net.buffer_bytes())
+            self.init_source = "network" if used else "plain"
+        else:
+            cv = gs.Tracked(gs.GS_MEM_INIT, gs.gs_cost_volume_workspace_size(k, H, W) + 4 * H * W)
+            depth = plain_depth(kfs, cams, self.device)
+            self.init_source = "plain"
+        means, ls = propose(depth, cams[-1], self.stride, lsmap)
         cv.release()
         m = means.shape[1]
         img = self.window[-1]["image"]
@@ -169,6 +179,7 @@ class MappingLoop:
         if len(self.window) >= 2:
             local = self._local_stage(self._initialise())
             info["new_gaussians"] = local.n
+            info["init"] = self.init_source
             if self.map is None:
                 pruned, _ = prune(local)
                 self._set_map(pruned)
@@ -184,6 +195,25 @@ class MappingLoop:
         return r.forward(self.map).view(3, cam.height, cam.width).clone()
 
 
+def local_stage_psnr(frames: List[torch.Tensor], cams: List[scenes.Camera], init_net=None,
+                     iters: int = 30, stride: int = 8, device="cuda") -> float:
+    """The initialisers compared on one window: new Gaussians for the newest
+    keyframe from `init_net` (or the plain initialiser when None), then
+    `iters` local-stage iterations (E_pho + E_iso on the window, Eq. 2); the
+    PSNR of that local map on the newest keyframe."""
+    loop = MappingLoop(cams[0].width, cams[0].height, cams[0].fx, window=len(frames), stride=stride,
+                       local_iters=iters, init_net=init_net, device=device)
+    for f, c in zip(frames, cams):
+        loop.window.append({"image": f.contiguous(), "cam": c,
+                            "track": gs.Tracked(gs.GS_MEM_KEYFRAMES, f)})
+    local = loop._local_stage(loop._initialise())
+    loop.map = local
+    out = psnr(loop.render(cams[-1]), frames[-1])
+    for k in loop.window:
+        k["track"].release()
+    return out
+
+
 def psnr(a: torch.Tensor, b: torch.Tensor) -> float:
     mse = float(((a.clamp(0, 1) - b) ** 2).mean().item())
     return 10.0 * math.log10(1.0 / max(mse, 1e-12))
@@ -193,7 +223,8 @@ def run_sequence(width: int, height: int, n_frames: int, window: int, n_gauss: i
                  seed: int = 0, device="cuda", log=None, **kw) -> Dict:
     """The loop over a procedural-room trajectory whose frames are renders of
     a ground-truth room map; returns the ledger's overhead figures and the
-    map's PSNR on the last frame and on the first (a past view)."""
+    final map's PSNR on the last frame, on the first mapped one (a past
+    view) and averaged over every mapped frame."""
     from .initnet import trajectory_cams
     from .rasterizer import Rasterizer
     gt, boxes = scenes.procedural_room(n_gauss, seed, sh_degree=0)
@@ -218,6 +249,7 @@ def run_sequence(width: int, height: int, n_frames: int, window: int, n_gauss: i
         "map_gaussians": loop.map.n,
         "map_MB": _map_bytes(loop.map) / 1e6,
         "all_keyframes_MB": n_frames * 3 * width * height * 4 / 1e6,
+        "psnr_mean": float(np.mean([psnr(loop.render(c), f) for c, f in zip(cams[1:], frames[1:])])),
         "psnr_last": psnr(loop.render(cams[-1]), frames[-1]),
         "psnr_first": psnr(loop.render(cams[1]), frames[1]),
         "psnr_empty_last": psnr(torch.zeros_like(frames[-1]), frames[-1]),

@@ -192,10 +192,53 @@ def test_cost_volume_matches_oracle(gs):
     assert clear.sum() > 100 and agree.mean() > 0.995, (clear.sum(), agree.mean())
 
 
+class _NoisyBf16Store(torch.autograd.Function):
+    """Bf16Store after a relative perturbation of eps (Gaussian) of the value
+    going forward and of the gradient going back: stands in for the float32
+    accumulation error that precedes every rounding on the GPU."""
+
+    @staticmethod
+    def forward(ctx, x, eps, gen):
+        ctx.eps, ctx.gen = eps, gen
+        n = torch.randn(x.shape, generator=gen, dtype=x.dtype)
+        return N.bf16_store(x * (1 + eps * n))
+
+    @staticmethod
+    def backward(ctx, g):
+        n = torch.randn(g.shape, generator=ctx.gen, dtype=g.dtype)
+        return N.bf16_store(g * (1 + ctx.eps * n)), None, None
+
+
+def _oracle_net(net, rgb_np, dpred_np, store):
+    """The FP64 oracle network with the GPU network's BF16 weights and the
+    given storage rounding of activations and activation gradients:
+    (prediction less the head bias, parameter gradients)."""
+    p = {}
+    for k, v in net.params.items():
+        t = v.detach().cpu()
+        if k.endswith(".w") and not k.startswith("head"):
+            t = t.to(torch.bfloat16).float()
+        p[k] = t.double().requires_grad_(True)
+    x = torch.zeros(1, 24, 32, 8, dtype=torch.float64)
+    x[..., :3] = torch.as_tensor(N.bf16_round(rgb_np[0].transpose(1, 2, 0)))
+    ref = N.unet_forward(x, p, store=store)
+    (ref * torch.as_tensor(dpred_np, dtype=torch.float64)).sum().backward()
+    hb = net.params["head.b"].double().cpu().numpy()[None, :, None, None]
+    return ref.detach().numpy() - hb, {k: v.grad.numpy() for k, v in p.items()}
+
+
 def test_unet_forward_backward_matches_oracle(gs):
     """Whole network at 32 x 24: GPU kernels vs the FP64 oracle network with
-    the same BF16 weights (activations rounded to BF16 on the GPU only, so
-    the comparison is relative)."""
+    the same BF16 weights and the same BF16 storage of every activation and
+    activation gradient (Bf16Store).  What is left is the FP32 accumulation
+    error before each rounding; under BF16 storage a rounding decision it
+    flips in one layer moves values by an ulp in the next, which flips more,
+    so eighteen layers amplify it.  The bound is that amplification, measured
+    on the oracle itself: the largest difference among four runs whose every
+    stored value and gradient is first perturbed by a relative 2^-22
+    (Gaussian), times three (at least 1e-3 on the prediction, 1e-2 on the
+    gradients), for the prediction and for every layer's weight and bias
+    gradients.  Each kernel alone is checked tightly by the tests above."""
     from paper_2409_09295_amd import initnet
     net = initnet.UNet(seed=3)
     rng = np.random.default_rng(2)
@@ -206,26 +249,28 @@ def test_unet_forward_backward_matches_oracle(gs):
     net.zero_grad()
     net.backward(dpred)
     torch.cuda.synchronize()
-    p = {}
-    for k, v in net.params.items():
-        t = v.detach().cpu()
-        if k.endswith(".w") and not k.startswith("head"):
-            t = t.to(torch.bfloat16).float()
-        p[k] = t.double().requires_grad_(True)
-    x = torch.zeros(1, 24, 32, 8, dtype=torch.float64)
-    x[..., :3] = torch.as_tensor(N.bf16_round(np_(rgb)[0].transpose(1, 2, 0)))
-    ref = N.unet_forward(x, p)
-    # the network's part of the output (the head bias is the depth prior)
     hb = net.params["head.b"].double().cpu().numpy()[None, :, None, None]
-    r = ref.detach().numpy() - hb
-    rel = np.linalg.norm(np_(pred) - hb - r) / np.linalg.norm(r)
-    assert rel < 2e-2, rel
-    (ref * torch.as_tensor(np_(dpred)).double()).sum().backward()
-    for k in ("e0a.w", "e3b.w", "d2a.w", "d0b.w", "head.w", "d1a.b"):
-        g = np_(net.grads[k])
-        r = p[k].grad.numpy()
-        rel = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30)
-        assert rel < 1e-1, (k, rel)
+    r0, g0 = _oracle_net(net, np_(rgb), np_(dpred), N.bf16_store)
+    rel = lambda a, b: np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+    sp_pred, sp_grad = 0.0, {k: 0.0 for k in g0}
+    for seed in range(4):
+        gen = torch.Generator().manual_seed(seed)
+        r1, g1 = _oracle_net(net, np_(rgb), np_(dpred),
+                             lambda t: _NoisyBf16Store.apply(t, 2.0 ** -22, gen))
+        sp_pred = max(sp_pred, rel(r1, r0))
+        for k in g0:
+            sp_grad[k] = max(sp_grad[k], rel(g1[k], g0[k]))
+    got = rel(np_(pred) - hb, r0)
+    print(f"  prediction: GPU {got:.2e}, perturbed-oracle spread {sp_pred:.2e}", flush=True)
+    assert got <= max(3 * sp_pred, 1e-3), (got, sp_pred)
+    worst = ("", 0.0)
+    for k in g0:
+        got = rel(np_(net.grads[k]), g0[k])
+        bound = max(3 * sp_grad[k], 1e-2)
+        if got / bound > worst[1]:
+            worst = (f"{k}: GPU {got:.2e}, spread {sp_grad[k]:.2e}", got / bound)
+        assert got <= bound, (k, got, sp_grad[k])
+    print(f"  worst gradient {worst[0]} (error / bound {worst[1]:.2f})", flush=True)
 
 
 def test_learned_initialiser_beats_plain(gs):
@@ -237,3 +282,54 @@ def test_learned_initialiser_beats_plain(gs):
     print(rep, flush=True)
     assert np.isfinite(rep.final_loss)
     assert rep.net_absrel <= rep.plain_absrel, rep
+
+
+def test_learned_depth_falls_back_to_plain_on_non_finite_output(gs):
+    """A network whose output is not finite (here a NaN head bias) gives way
+    to the plain initialiser: the depth is exactly plain_depth's and no
+    log-scale map is returned; a finite network is used as is."""
+    from paper_2409_09295_amd import initnet
+    cams, rgb, _ = _room_window_small()
+    net = initnet.UNet(seed=1)
+    d, ls, used = initnet.learned_depth(net, rgb, cams)
+    assert used and ls is not None and bool(torch.isfinite(d).all())
+    np.testing.assert_allclose(np_(d), np_(net.predict_depth(rgb[-1:].contiguous())[0]), rtol=1e-6)
+    net.params["head.b"][0] = float("nan")
+    d, ls, used = initnet.learned_depth(net, rgb, cams)
+    assert not used and ls is None
+    np.testing.assert_array_equal(np_(d), np_(initnet.plain_depth(rgb, cams)))
+
+
+def _room_window_small(n_keyframes=8, W=160, H=120, seed=4):
+    from paper_2409_09295_amd import initnet
+    gmap, boxes = scenes.procedural_room(60000, seed=seed)
+    cams = initnet.trajectory_cams(n_keyframes, seed + 11, boxes, W, H)
+    rgb, depth = initnet.render_dataset(gmap, cams)
+    return cams, rgb, depth
+
+
+def test_mapping_gains_from_the_learned_initialiser(gs):
+    """Gain test: on six 4-keyframe windows along a held-out trajectory of
+    the room (160 x 120), new Gaussians for the newest keyframe from the
+    network trained on renders of that room, then 30 local-stage
+    iterations, reach a mean PSNR on that keyframe at least the plain
+    initialiser's (less 0.25 dB); the network's depth AbsRel on held-out
+    views is below the plain initialiser's."""
+    from paper_2409_09295_amd import initnet
+    from paper_2409_09295_amd.mapping import local_stage_psnr
+    net, rep = initnet.train_and_compare(n_gauss=60000, W=160, H=120, n_train=1500, n_heldout=8,
+                                         epochs=15, seed=1, sh_degree=0)
+    print(rep, flush=True)
+    assert rep.net_absrel < rep.plain_absrel
+    gmap, boxes = scenes.procedural_room(60000, 1, sh_degree=0)
+    cams = initnet.trajectory_cams(40, 77, boxes, 160, 120)
+    rgb, _ = initnet.render_dataset(gmap, cams)
+    plain, learned = [], []
+    for j in range(0, 36, 6):
+        frames, cs = [rgb[j + i] for i in range(4)], cams[j:j + 4]
+        plain.append(local_stage_psnr(frames, cs, None, iters=30))
+        learned.append(local_stage_psnr(frames, cs, net, iters=30))
+    print(f"PSNR after 30 local iterations: plain init {np.mean(plain):.2f} dB "
+          f"{np.round(plain, 2).tolist()}, learned init {np.mean(learned):.2f} dB "
+          f"{np.round(learned, 2).tolist()}", flush=True)
+    assert np.mean(learned) >= np.mean(plain) - 0.25

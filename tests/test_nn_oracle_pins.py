@@ -198,3 +198,19 @@ def test_bp_smooths_an_outlier():
     labels, _ = N.belief_propagation(D, lam=0.05, trunc=0.3, iters=10)
     assert (labels == 3).all()
     assert np.argmin(D[:, 2, 2]) == 8
+
+
+def test_bf16_store_rounds_values_and_gradients():
+    """The storage rounding used by the network oracle agrees with the
+    bit-level round-to-nearest-even of bf16_round, forward and backward, and
+    leaves values already in bfloat16 unchanged."""
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(4096) * 10.0 ** rng.integers(-3, 3, 4096)
+    w = rng.standard_normal(4096)
+    xt = torch.tensor(x, dtype=torch.float64, requires_grad=True)
+    y = N.bf16_store(xt)
+    np.testing.assert_array_equal(y.detach().numpy(), N.bf16_round(x))
+    (y * torch.tensor(w)).sum().backward()
+    np.testing.assert_array_equal(xt.grad.numpy(), N.bf16_round(w))
+    z = torch.tensor(N.bf16_round(x))
+    np.testing.assert_array_equal(N.bf16_store(z).numpy(), z.numpy())
