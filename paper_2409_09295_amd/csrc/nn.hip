@@ -192,6 +192,131 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(
     }
 }
 
+// Direct 3x3 convolution on spatial tiles.  A workgroup computes a 16 x 16
+// pixel tile of one image for BNT output channels; wavefront w computes
+// output rows 4w .. 4w + 3 (each a 16-pixel MFMA row block) for all BNT
+// channels.  Input channels go in chunks of 32: the chunk's 18 x 18 input
+// patch (the tile and its one-pixel halo; zero outside the image) and its
+// 9 x BNT x 32 weights are staged in LDS once, and every tap's A fragments
+// are read from the patch at the tap's offset, so each input value is loaded
+// from memory about 1.3 times instead of nine.  The next chunk's patch and
+// weights are loaded into registers while this chunk's 9 x 4 x BNT/16 MFMAs
+// per wavefront run.
+constexpr int PT = 16;                  // output tile side
+constexpr int PP = PT + 2;              // patch side (with halo)
+constexpr int PCC = 32;                 // input channels per chunk
+constexpr int PPITCH = PCC + 8;         // LDS pitch in bf16 (80 bytes: 16-byte rows, spread banks)
+constexpr int PATCH_CHUNKS = PP * PP * (PCC / 8);   // 16-byte pieces of a patch (1,296)
+
+template <int BNT>
+__global__ __launch_bounds__(256) void conv3x3_patch_kernel(
+    ActView x1, ActView x2, ActView mask, int N, int H, int W, const uint16_t* __restrict__ wk,
+    int cout, int cin, const float* __restrict__ bias, int relu, uint16_t* __restrict__ y,
+    int y_stride, int y_offset, float* __restrict__ yf, int yf_stride) {
+  constexpr int JN = BNT / 16;
+  constexpr int W_CHUNKS = 9 * BNT * (PCC / 8);     // 16-byte pieces of a chunk's weights
+  constexpr int PA = (PATCH_CHUNKS + 255) / 256;    // per thread
+  constexpr int PB = (W_CHUNKS + 255) / 256;
+  __shared__ __attribute__((aligned(16))) uint16_t sP[PP * PP * PPITCH];
+  __shared__ __attribute__((aligned(16))) uint16_t sW[9 * BNT * PPITCH];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int tiles_x = (W + PT - 1) / PT, tiles_y = (H + PT - 1) / PT;
+  const int img = blockIdx.x / (tiles_x * tiles_y);
+  const int trem = blockIdx.x - img * tiles_x * tiles_y;
+  const int ty0 = (trem / tiles_x) * PT, tx0 = (trem % tiles_x) * PT;
+  const int n0 = blockIdx.y * BNT;
+  const int nchunks = (cin + PCC - 1) / PCC;
+  const bool masked = mask.p != nullptr;
+  const ActView none = {nullptr, 0, 0, 0};
+  uint4 ra[PA], rm[PA], rb[PB];
+  auto fetch = [&](int chunk) {
+    const int c0 = chunk * PCC;
+#pragma unroll
+    for (int u = 0; u < PA; ++u) {
+      const int q = t + 256 * u;            // piece q: patch pixel q / 4, channels 8 (q % 4)
+      const int pp = q >> 2, cc = (q & 3) * 8;
+      const int py = pp / PP, px = pp - py * PP;
+      const int sy = ty0 + py - 1, sx = tx0 + px - 1;
+      const bool inb = q < PATCH_CHUNKS && sy >= 0 && sy < H && sx >= 0 && sx < W &&
+                       c0 + cc < cin;
+      const int64_t pix = ((int64_t)img * H + sy) * W + sx;
+      ra[u] = load8(x1, x2, none, pix, inb, c0 + cc);
+      if (masked) rm[u] = load8(mask, none, none, pix, inb, c0 + cc);
+    }
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      const int q = t + 256 * u;            // piece q: (tap, channel n) = q / 4, inputs 8 (q % 4)
+      const int tn = q >> 2, cc = (q & 3) * 8;
+      const int tap = tn / BNT, co = n0 + (tn - tap * BNT);
+      rb[u] = make_uint4(0, 0, 0, 0);
+      if (q < W_CHUNKS && co < cout && c0 + cc < cin)
+        rb[u] = *reinterpret_cast<const uint4*>(wk + ((int64_t)tap * cout + co) * cin + c0 + cc);
+    }
+  };
+  f32x4 acc[4][JN];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < JN; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  fetch(0);
+  for (int chunk = 0; chunk < nchunks; ++chunk) {
+    __syncthreads();   // the previous chunk's fragments have been read
+#pragma unroll
+    for (int u = 0; u < PA; ++u) {
+      const int q = t + 256 * u;
+      if (q < PATCH_CHUNKS)
+        *reinterpret_cast<uint4*>(&sP[(q >> 2) * PPITCH + (q & 3) * 8]) =
+            masked ? apply_mask8(ra[u], rm[u]) : ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PB; ++u) {
+      const int q = t + 256 * u;
+      if (q < W_CHUNKS) *reinterpret_cast<uint4*>(&sW[(q >> 2) * PPITCH + (q & 3) * 8]) = rb[u];
+    }
+    __syncthreads();
+    if (chunk + 1 < nchunks) fetch(chunk + 1);
+#pragma unroll 1
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap % 3;   // patch offsets of the tap (0 .. 2)
+      bf16x8 a[4], b[JN];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        a[i] = *reinterpret_cast<const bf16x8*>(
+            &sP[((4 * wv + i + dy) * PP + (lane & 15) + dx) * PPITCH + 8 * (lane >> 4)]);
+#pragma unroll
+      for (int j = 0; j < JN; ++j)
+        b[j] = *reinterpret_cast<const bf16x8*>(
+            &sW[(tap * BNT + j * 16 + (lane & 15)) * PPITCH + 8 * (lane >> 4)]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < JN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  // epilogue: bias, ReLU, bf16 (or float32) store; acc[i][j][r] is output
+  // row 4 wv + i, column 4 (lane / 16) + r, channel n0 + 16 j + lane % 16
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int oy = ty0 + 4 * wv + i;
+#pragma unroll
+    for (int j = 0; j < JN; ++j) {
+      const int co = n0 + j * 16 + (lane & 15);
+      if (oy >= H || co >= cout) continue;
+      const float bco = bias ? bias[co] : 0.f;
+      for (int r = 0; r < 4; ++r) {
+        const int ox = tx0 + 4 * (lane >> 4) + r;
+        if (ox >= W) continue;
+        const int64_t p = ((int64_t)img * H + oy) * W + ox;
+        float v = acc[i][j][r] + bco;
+        if (relu) v = fmaxf(v, 0.f);
+        if (y) y[p * y_stride + y_offset + co] = f2bf(v);
+        if (yf) yf[p * yf_stride + co] = v;
+      }
+    }
+  }
+}
+
 // Weight-gradient tile: 64 output channels x 64 input channels for one row
 // of three taps (dy fixed, dx = -1, 0, 1: one load of dz serves three taps),
 // pixels [kbeg, kbeg + kchunk) of the K dimension.  Each stage covers 64
@@ -836,6 +961,18 @@ hipError_t nn_conv3x3(const gs_act* x1, const gs_act* x2, const gs_act* mask, co
   auto* yp = y ? static_cast<uint16_t*>(y->data) : nullptr;
   const int ys = y ? y->stride : 0, yo = y ? y->offset : 0;
   const auto* wp = static_cast<const uint16_t*>(w);
+  if (cin % 8 == 0 && x1->c % 8 == 0) {
+    const unsigned tiles = (unsigned)(x1->n * ((x1->h + PT - 1) / PT) * ((x1->w + PT - 1) / PT));
+    if (cout <= 32)
+      hipLaunchKernelGGL((conv3x3_patch_kernel<32>), dim3(tiles, (unsigned)((cout + 31) / 32)),
+                         dim3(256), 0, s, view(x1), view(x2), view(mask), x1->n, x1->h, x1->w, wp,
+                         cout, cin, bias, relu, yp, ys, yo, yf, yf_stride);
+    else
+      hipLaunchKernelGGL((conv3x3_patch_kernel<64>), dim3(tiles, (unsigned)((cout + 63) / 64)),
+                         dim3(256), 0, s, view(x1), view(x2), view(mask), x1->n, x1->h, x1->w, wp,
+                         cout, cin, bias, relu, yp, ys, yo, yf, yf_stride);
+    return hipGetLastError();
+  }
   const unsigned ntile = (unsigned)((cout + 63) / 64);
   // (the masked backward-data calls measured faster without the large tiles)
   const bool narrow = cout <= 32;
