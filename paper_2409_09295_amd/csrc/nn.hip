@@ -472,6 +472,173 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(
   }
 }
 
+// Weight gradient on spatial tiles: dW[tap][co][ci] = sum over pixels p of
+// dz[p][co] x[p + tap][ci] (dz masked by the ReLU of the layer's output).  A
+// workgroup owns COB output and 32 input channels and all nine taps, and
+// walks a run of 8 x 16-pixel tiles.  Per tile it stages dz transposed to
+// [channel][pixel] and the tile's 10 x 18 input patch transposed to
+// [channel][row][column] in three copies shifted by 0, 1 and 2 columns, so
+// that every tap's operand (8 consecutive pixels of one row per lane) is an
+// aligned 16-byte LDS read; the K dimension of the MFMAs is the tile's 128
+// pixels.  Wavefront w computes input-channel block w % 2 against output
+// blocks (w / 2) and (w / 2) + 2 (COB 64) or block w / 2 (COB 32), for the
+// nine taps.  Partial sums go to dW (and dbias) by float atomics at the end.
+constexpr int WT_H = 8, WT_W = 16, WT_PX = WT_H * WT_W;   // pixels of a tile
+constexpr int WX_H = WT_H + 2, WX_W = WT_W + 2;           // input patch
+constexpr int WZ_PITCH = WT_PX + 8;                       // dz^T row pitch (bf16)
+constexpr int WX_PITCH = WX_H * WT_W + 8;                 // per-channel pitch of a shifted copy
+
+template <int COB>
+__global__ __launch_bounds__(256) void conv3x3_wgrad_patch_kernel(
+    ActView x1, ActView x2, ActView dz, ActView mask, int N, int H, int W, int cout, int cin,
+    int tiles_per_wg, float* __restrict__ dw, float* __restrict__ dbias) {
+  constexpr int NCO = COB / 32;                      // output 16-blocks per wavefront
+  // staging items: two horizontally adjacent pixels x 8 channels, so that
+  // the transposed LDS writes are 32-bit words, consecutive across a wave
+  constexpr int ZI = (COB / 8) * (WT_PX / 2);        // dz items of a tile
+  constexpr int ZIT = ZI / 256;                      // per thread
+  constexpr int XROW = WX_W / 2;                     // pixel pairs per patch row (9)
+  constexpr int XI = 4 * WX_H * XROW;                // input items (32 channels)
+  constexpr int XIT = (XI + 255) / 256;
+  __shared__ __attribute__((aligned(16))) uint16_t sZ[COB * WZ_PITCH];
+  __shared__ __attribute__((aligned(16))) uint16_t sX[3 * 32 * WX_PITCH];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int tiles_x = (W + WT_W - 1) / WT_W, tiles_y = (H + WT_H - 1) / WT_H;
+  const int64_t ntiles = (int64_t)N * tiles_x * tiles_y;
+  const int co0 = blockIdx.y * COB, ci0 = blockIdx.z * 32;
+  const bool do_bias = dbias != nullptr && blockIdx.z == 0;
+  const bool masked = mask.p != nullptr;
+  const ActView none = {nullptr, 0, 0, 0};
+  const int ci_sub = wv & 1, co_blk = wv >> 1;
+  f32x4 acc[NCO][9];
+#pragma unroll
+  for (int c = 0; c < NCO; ++c)
+#pragma unroll
+    for (int u = 0; u < 9; ++u) acc[c][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.f;   // thread t < COB: bias gradient of output channel co0 + t
+  uint4 rz[ZIT][2], rm[ZIT][2], rx[XIT][2];
+  auto fetch = [&](int64_t tile) {
+    const int img = (int)(tile / (tiles_x * tiles_y));
+    const int trem = (int)(tile - (int64_t)img * tiles_x * tiles_y);
+    const int ty0 = (trem / tiles_x) * WT_H, tx0 = (trem % tiles_x) * WT_W;
+#pragma unroll
+    for (int u = 0; u < ZIT; ++u) {            // item: channels 8 (i / 64), pixels 2 (i % 64) + 0, 1
+      const int i = t + 256 * u;
+      const int cg = i >> 6, p = 2 * (i & 63);
+      const int oy = ty0 + p / WT_W, ox = tx0 + p % WT_W;
+      const int64_t pix = ((int64_t)img * H + oy) * W + ox;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool inb = oy < H && ox + h < W;
+        rz[u][h] = load8(dz, none, none, pix + h, inb, co0 + 8 * cg);
+        if (masked) rm[u][h] = load8(mask, none, none, pix + h, inb, co0 + 8 * cg);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < XIT; ++u) {            // item: channels 8 (i / 90), patch row, pixel pair
+      const int i = t + 256 * u;
+      const int cg = i / (WX_H * XROW), pr = i % (WX_H * XROW);
+      const int py = pr / XROW, px = 2 * (pr % XROW);
+      const int sy = ty0 + py - 1, sx = tx0 + px - 1;
+      const int64_t pix = ((int64_t)img * H + sy) * W + sx;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool inb = i < XI && sy >= 0 && sy < H && sx + h >= 0 && sx + h < W;
+        rx[u][h] = load8(x1, x2, none, pix + h, inb, ci0 + 8 * cg);
+      }
+    }
+  };
+  // 32-bit word e of two pixels' 8-channel pieces: (pixel 0, pixel 1) of channel e
+  auto pair_word = [](const uint4& a, const uint4& b, int e) -> uint32_t {
+    const uint32_t wa[4] = {a.x, a.y, a.z, a.w}, wb[4] = {b.x, b.y, b.z, b.w};
+    const uint32_t lo = (wa[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+    const uint32_t hi = (wb[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+    return lo | (hi << 16);
+  };
+  const int64_t t_beg = (int64_t)blockIdx.x * tiles_per_wg;
+  const int64_t t_end = min(ntiles, t_beg + tiles_per_wg);
+  if (t_beg < t_end) fetch(t_beg);
+  for (int64_t tile = t_beg; tile < t_end; ++tile) {
+    __syncthreads();   // the previous tile's fragments have been read
+#pragma unroll
+    for (int u = 0; u < ZIT; ++u) {
+      const int i = t + 256 * u;
+      const int cg = i >> 6, p = 2 * (i & 63);
+      const uint4 v0 = masked ? apply_mask8(rz[u][0], rm[u][0]) : rz[u][0];
+      const uint4 v1 = masked ? apply_mask8(rz[u][1], rm[u][1]) : rz[u][1];
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        *reinterpret_cast<uint32_t*>(&sZ[(8 * cg + e) * WZ_PITCH + p]) = pair_word(v0, v1, e);
+    }
+#pragma unroll
+    for (int u = 0; u < XIT; ++u) {
+      const int i = t + 256 * u;
+      if (i >= XI) continue;
+      const int cg = i / (WX_H * XROW), pr = i % (WX_H * XROW);
+      const int py = pr / XROW, px = 2 * (pr % XROW);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t wd = pair_word(rx[u][0], rx[u][1], e);
+        uint16_t* row0 = &sX[(0 * 32 + 8 * cg + e) * WX_PITCH + py * WT_W];
+        uint16_t* row1 = &sX[(1 * 32 + 8 * cg + e) * WX_PITCH + py * WT_W];
+        uint16_t* row2 = &sX[(2 * 32 + 8 * cg + e) * WX_PITCH + py * WT_W];
+        // copy dx holds patch column c + dx at column c: the pair (px, px + 1)
+        // lands at columns px, px + 1 (dx 0), px - 2, px - 1 (dx 2) as one
+        // word, and at px - 1, px (dx 1) as two halves
+        if (px + 1 < WT_W) *reinterpret_cast<uint32_t*>(row0 + px) = wd;
+        if (px >= 2) *reinterpret_cast<uint32_t*>(row2 + px - 2) = wd;
+        if (px >= 1) row1[px - 1] = (uint16_t)wd;
+        if (px < WT_W) row1[px] = (uint16_t)(wd >> 16);
+      }
+    }
+    __syncthreads();
+    if (tile + 1 < t_end) fetch(tile + 1);
+    if (do_bias && t < COB) {   // the row of dz^T of channel t (zero outside the image)
+#pragma unroll 4
+      for (int k = 0; k < WT_PX; k += 8) {
+        const uint4 v = *reinterpret_cast<const uint4*>(&sZ[t * WZ_PITCH + k]);
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bacc += bf2f((uint16_t)(w4[e >> 1] >> (16 * (e & 1))));
+      }
+    }
+#pragma unroll
+    for (int ks = 0; ks < WT_PX / 32; ++ks) {
+      // this lane's 8 pixels of the K step: tile row r, columns c0 .. c0 + 7
+      const int p = 32 * ks + 8 * (lane >> 4);
+      const int r = p / WT_W, c0 = p % WT_W;
+      bf16x8 a[NCO];
+#pragma unroll
+      for (int c = 0; c < NCO; ++c)
+        a[c] = *reinterpret_cast<const bf16x8*>(
+            &sZ[((co_blk + 2 * c) * 16 + (lane & 15)) * WZ_PITCH + p]);
+#pragma unroll
+      for (int u = 0; u < 9; ++u) {
+        const int dy = u / 3, dx = u % 3;
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(
+            &sX[(dx * 32 + ci_sub * 16 + (lane & 15)) * WX_PITCH + (r + dy) * WT_W + c0]);
+#pragma unroll
+        for (int c = 0; c < NCO; ++c)
+          acc[c][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b, acc[c][u], 0, 0, 0);
+      }
+    }
+  }
+  // dW[tap][co][ci]: acc[c][u][r] is output channel (co_blk + 2 c) 16 +
+  // 4 (lane / 16) + r, input channel ci_sub 16 + lane % 16
+#pragma unroll
+  for (int c = 0; c < NCO; ++c)
+#pragma unroll
+    for (int u = 0; u < 9; ++u) {
+      const int ci = ci0 + ci_sub * 16 + (lane & 15);
+      if (ci >= cin) continue;
+      for (int r = 0; r < 4; ++r) {
+        const int co = co0 + (co_blk + 2 * c) * 16 + 4 * (lane >> 4) + r;
+        if (co < cout) unsafeAtomicAdd(&dw[((int64_t)u * cout + co) * cin + ci], acc[c][u][r]);
+      }
+    }
+  if (do_bias && t < COB && co0 + t < cout) unsafeAtomicAdd(&dbias[co0 + t], bacc);
+}
+
 // Narrow weight gradient (cout <= 32): a 32 x 32 channel tile for one row
 // of three taps (dy fixed, dx = -1, 0, 1), so each stage's dz and mask loads
 // serve three taps.  The four wavefronts split the workgroup's pixels (wave
@@ -1002,6 +1169,21 @@ hipError_t nn_conv3x3_wgrad(const gs_act* x1, const gs_act* x2, const gs_act* dz
   const int cin = x1->c + (x2 ? x2->c : 0);
   const int cout = dz->c;
   const int64_t npix = (int64_t)x1->n * x1->h * x1->w;
+  if (cout <= 32 && cin % 8 == 0 && x1->c % 8 == 0 && cout % 8 == 0) {
+    // narrow layers (the full-resolution ones): spatial tiles; for wider
+    // layers the 64 x 64 channel tiles below measured faster (their MFMA
+    // work per staged byte is larger, and the tile kernel at 64 output
+    // channels holds two workgroups per CU)
+    const int64_t ntiles = (int64_t)x1->n * ((x1->h + WT_H - 1) / WT_H) * ((x1->w + WT_W - 1) / WT_W);
+    const int64_t blocks_ch = (cin + 31) / 32;
+    // runs of tiles: about 1,024 workgroups, each long enough that its
+    // 9 x 32 x 32 closing atomics are few next to its MFMA work
+    const int64_t per = std::max<int64_t>(4, (ntiles * blocks_ch + 1023) / 1024);
+    const dim3 grid((unsigned)((ntiles + per - 1) / per), 1u, (unsigned)blocks_ch);
+    hipLaunchKernelGGL(conv3x3_wgrad_patch_kernel<32>, grid, dim3(256), 0, s, view(x1), view(x2),
+                       view(dz), view(mask), x1->n, x1->h, x1->w, cout, cin, (int)per, dw, dbias);
+    return hipGetLastError();
+  }
   // pixel chunks: enough workgroups to fill the chip, each long enough that
   // its 4096 atomic adds into dw are few next to its MFMA work
   if (cout <= 32) {   // 32 x 32 channel tiles, a row of taps each (see conv3x3_wgrad32_kernel)
