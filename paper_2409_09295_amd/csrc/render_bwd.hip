@@ -461,28 +461,54 @@ __global__ __launch_bounds__(256) void project_bwd_kernel(
     if (G.ok) load_sh<DEG>(sh, n, i, C);
     float c[NC];
     for (int k = 0; k < NC; ++k) c[k] = 0.f;
-    for (int v = 0; v < n_views; ++v) {
-      const int64_t e = (int64_t)v * n + i;
-      bool active = (vis >> v) & 1u;
-      if (!__any(active)) continue;
+    // the views any lane of the wave sees, walked in order; each view's
+    // screen-space records are loaded one view ahead, so the load latency
+    // overlaps the previous view's chain
+    uint64_t wvis = vis;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)wvis, d, 64);
+      const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(wvis >> 32), d, 64);
+      wvis |= ((uint64_t)hi << 32) | lo;
+    }
+    wvis = uniform_u64(wvis);
+    float g2n[9];
+    auto load_rec = [&](int v) {
+      const bool act = (vis >> v) & 1u;
+      const float* src = grad2d + ((int64_t)v * n + i) * 9;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) g2n[k] = act ? src[k] : 0.0f;
+    };
+    int vnext = wvis ? __builtin_ctzll(wvis) : -1;
+    if (vnext >= 0) {
+      wvis &= wvis - 1;
+      load_rec(vnext);
+    }
+    while (vnext >= 0) {
+      const int v = vnext;
       float g2[9];
       bool nz = false;
-      if (active) {
-        float* src = grad2d + e * 9;
-        for (int k = 0; k < 9; ++k) {
-          g2[k] = src[k];
-          nz = nz || g2[k] != 0.0f;
-        }
-        if (keep_clear && nz)   // leave the record clear for the next call
-          for (int k = 0; k < 9; ++k) src[k] = 0.0f;
-        // slots 2-4 hold sum(dL/dpower * (dx^2, dx dy, dy^2)); dL/dQ00,
-        // dL/dQ01, dL/dQ11 are those times -1/2, -1, -1/2 (exact scalings)
-        g2[2] *= -0.5f;
-        g2[3] = -g2[3];
-        g2[4] *= -0.5f;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        g2[k] = g2n[k];
+        nz = nz || g2[k] != 0.0f;
       }
-      active = active && nz;
+      vnext = wvis ? __builtin_ctzll(wvis) : -1;
+      if (vnext >= 0) {
+        wvis &= wvis - 1;
+        load_rec(vnext);
+      }
+      const bool active = ((vis >> v) & 1u) && nz;
       if (!__any(active)) continue;
+      if (keep_clear && active) {   // leave the record clear for the next call
+        float* src = grad2d + ((int64_t)v * n + i) * 9;
+        for (int k = 0; k < 9; ++k) src[k] = 0.0f;
+      }
+      // slots 2-4 hold sum(dL/dpower * (dx^2, dx dy, dy^2)); dL/dQ00,
+      // dL/dQ01, dL/dQ11 are those times -1/2, -1, -1/2 (exact scalings)
+      g2[2] *= -0.5f;
+      g2[3] = -g2[3];
+      g2[4] *= -0.5f;
       float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       if (active) chain_one<DEG>(G, cams[v], C, g2, c, pose);
       if (want_pose) {
