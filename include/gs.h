@@ -147,7 +147,24 @@ typedef struct gs_projected {
  *          non-NULL (the identity when it returns before the ranges exist);
  *          the compositing calls then start the most expensive tiles first,
  *          which shortens the tail of the launch, and their results do not
- *          depend on it. */
+ *          depend on it.
+ *   queue  [GS_QUEUE_WORDS] uint32 (optional, NULL = none): tile counters of
+ *          the persistent schedule (GS_SCHEDULE_PERSISTENT).  Each
+ *          compositing call owns GS_QUEUE_COUNTERS counters, GS_QUEUE_STRIDE
+ *          words apart, from word GS_QUEUE_STRIDE * GS_QUEUE_COUNTERS * call
+ *          (call = GS_QUEUE_FWD, GS_QUEUE_BWD or GS_QUEUE_ERROR).  Must be
+ *          zero before first use: gs_bin_sort zeroes it, and every call that
+ *          uses its counters leaves them zero again.  Calls of the same kind
+ *          that share a queue must not overlap in time.  Without a queue the
+ *          persistent schedule launches one workgroup per tile. */
+enum {
+  GS_QUEUE_FWD = 0,
+  GS_QUEUE_BWD = 1,
+  GS_QUEUE_ERROR = 2,
+  GS_QUEUE_COUNTERS = 8, /* counters per call                   */
+  GS_QUEUE_STRIDE = 32,  /* words between counters (128 bytes)  */
+  GS_QUEUE_WORDS = 1024  /* 4 calls' worth; the fourth is spare  */
+};
 typedef struct gs_bins {
   uint64_t* keys;
   uint32_t* values;
@@ -155,6 +172,7 @@ typedef struct gs_bins {
   uint32_t* n_keys;
   int64_t capacity;
   uint32_t* order;
+  uint32_t* queue;
 } gs_bins;
 
 /* Gradients, same layouts as gs_gaussians, accumulated (+=).  xi [V][6]
@@ -199,14 +217,26 @@ const char* gs_version(void);
 enum {
   GS_TUNE_FWD_PIXELS_PER_LANE = 0, /* gs_render_fwd: pixels per lane, 1 | 2 | 4 (default 1) */
   GS_TUNE_BWD_PIXELS_PER_LANE = 1, /* gs_render_bwd: pixels per lane, 1 | 2 | 4 (default 1) */
-  GS_TUNE_COUNT = 2
+  GS_TUNE_FWD_SCHEDULE = 2,        /* gs_render_fwd(_l1): a GS_SCHEDULE_* value            */
+  GS_TUNE_BWD_SCHEDULE = 3,        /* gs_render_bwd and gs_render_error: GS_SCHEDULE_*     */
+  GS_TUNE_COUNT = 4
 };
 
-/* Process-wide kernel configuration, set by an autotuner.  A 16x16 tile is
- * covered by 256 / value threads.  value 0 restores the default.  Applies to
- * launches enqueued after the call; a captured graph keeps the configuration
- * it was captured with.  Results are identical for every setting up to
- * float32 summation order of the gradient atomics. */
+/* Tile schedules of the compositing kernels (GS_TUNE_*_SCHEDULE). */
+enum {
+  GS_SCHEDULE_HEAVIEST_FIRST = 1, /* one workgroup per tile, launched in bins->order (default;
+                                     tile id order when bins->order is NULL)                  */
+  GS_SCHEDULE_TILE_ID = 2,        /* one workgroup per tile, launched in tile id order        */
+  GS_SCHEDULE_PERSISTENT = 3      /* as many workgroups as the GPU holds at once, each taking
+                                     tiles in bins->order from a counter in bins->queue until
+                                     none is left                                              */
+};
+
+/* Process-wide kernel configuration, set by an autotuner.  Pixels per lane:
+ * a 16x16 tile is covered by 256 / value threads.  value 0 restores the
+ * default.  Applies to launches enqueued after the call; a captured graph
+ * keeps the configuration it was captured with.  Results are identical for
+ * every setting up to float32 summation order of the gradient atomics. */
 int gs_set_tuning(int key, int value);
 /* Current value of a tuning key (< 0 for an unknown key). */
 int gs_get_tuning(int key);

@@ -353,8 +353,12 @@ constexpr int kScanBlock = 1024;   // tiles per scan workgroup (256 threads x 4)
 __global__ __launch_bounds__(256) void bin_scan_reduce_kernel(const uint32_t* __restrict__ counts,
                                                               int n_tiles,
                                                               uint64_t* __restrict__ partial,
-                                                              uint32_t* __restrict__ n_long) {
+                                                              uint32_t* __restrict__ n_long,
+                                                              uint32_t* __restrict__ queue) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *n_long = 0u;   // the down-sweep queues long lists
+  // the compositing calls' tile counters start from zero
+  if (queue && blockIdx.x == 0)
+    for (int w = threadIdx.x; w < GS_QUEUE_WORDS; w += 256) queue[w] = 0u;
   __shared__ uint64_t s_wave[4];
   const int base = blockIdx.x * kScanBlock + threadIdx.x;
   uint64_t acc = 0;
@@ -915,6 +919,9 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
   kernel_event_start(GS_KERNEL_BIN_SORT, s);
   if (T == 0) {
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, s, bins.n_keys, 0u, (int64_t)1);
+    if (bins.queue)
+      hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(256), 0, s, bins.queue, 0u,
+                         (int64_t)GS_QUEUE_WORDS);
     kernel_event_stop(GS_KERNEL_BIN_SORT, s);
     return (e = hipGetLastError()) == hipSuccess ? GS_OK : hip_fail(e, "bin sort launch");
   }
@@ -936,7 +943,7 @@ int run_bin_sort(const gs_projected& p, int64_t n, const ViewTable& vt, const gs
                      (unsigned)vt.n_views), dim3(256), 0, s, matrix, list_count, vt, counts);
   const int nsb = (T + kScanBlock - 1) / kScanBlock;
   hipLaunchKernelGGL(bin_scan_reduce_kernel, dim3((unsigned)nsb), dim3(256), 0, s, counts, T,
-                     partial, n_long);
+                     partial, n_long, bins.queue);
   hipLaunchKernelGGL(bin_scan_down_kernel, dim3((unsigned)nsb), dim3(256), 0, s, counts, T,
                      partial, nsb, P.capacity, bins.ranges, starts, total, bins.n_keys, long_list,
                      n_long);

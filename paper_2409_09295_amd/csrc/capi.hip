@@ -5,6 +5,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "gs_internal.h"
 
@@ -16,10 +18,43 @@ thread_local hipEvent_t g_events[GS_KERNEL_COUNT][2] = {};
 }
 
 namespace {
-std::atomic<int> g_tuning[GS_TUNE_COUNT] = {{1}, {1}};
+std::atomic<int> g_tuning[GS_TUNE_COUNT] = {{1}, {1}, {GS_SCHEDULE_HEAVIEST_FIRST},
+                                            {GS_SCHEDULE_HEAVIEST_FIRST}};
 }
 
 int tuning(int key) { return g_tuning[key].load(std::memory_order_relaxed); }
+
+int resident_workgroups(const void* kernel, int block) {
+  struct Entry {
+    const void* kernel;
+    int dev, block, resident;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> known;   // the query costs microseconds: once per kernel and device
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lock(mu);
+  for (const Entry& k : known)
+    if (k.kernel == kernel && k.dev == dev && k.block == block) return k.resident;
+  int per_cu = 0, cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess)
+    return 0;
+  known.push_back({kernel, dev, block, per_cu * cus});
+  return per_cu * cus;
+}
+
+TileSchedule tile_schedule(int schedule, const gs_bins& bins, int call, int n_tiles,
+                           int resident) {
+  TileSchedule t{bins.order, nullptr, (unsigned)n_tiles};
+  if (schedule == GS_SCHEDULE_TILE_ID) t.order = nullptr;
+  if (schedule == GS_SCHEDULE_PERSISTENT && bins.queue && resident > 0) {
+    t.counter = bins.queue + (size_t)GS_QUEUE_STRIDE * GS_QUEUE_COUNTERS * call;
+    t.grid = (unsigned)std::min(n_tiles, resident);
+  }
+  return t;
+}
 
 void kernel_event_start(int kernel, hipStream_t s) {
   if (g_events[kernel][0]) (void)hipEventRecord(g_events[kernel][0], s);
@@ -169,9 +204,15 @@ int gs_set_kernel_events(int kernel, void* start_event, void* stop_event) {
 
 int gs_set_tuning(int key, int value) {
   if (key < 0 || key >= GS_TUNE_COUNT) return invalid("unknown tuning key %d", key);
-  if (value == 0) value = 1;
-  if (value != 1 && value != 2 && value != 4)
-    return invalid("pixels per lane must be 1, 2 or 4 (got %d)", value);
+  if (key == GS_TUNE_FWD_SCHEDULE || key == GS_TUNE_BWD_SCHEDULE) {
+    if (value == 0) value = GS_SCHEDULE_HEAVIEST_FIRST;
+    if (value < GS_SCHEDULE_HEAVIEST_FIRST || value > GS_SCHEDULE_PERSISTENT)
+      return invalid("unknown tile schedule %d", value);
+  } else {
+    if (value == 0) value = 1;
+    if (value != 1 && value != 2 && value != 4)
+      return invalid("pixels per lane must be 1, 2 or 4 (got %d)", value);
+  }
   g_tuning[key].store(value, std::memory_order_relaxed);
   return GS_OK;
 }

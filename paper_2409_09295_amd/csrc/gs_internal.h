@@ -189,6 +189,57 @@ __device__ __forceinline__ bool eval_alpha_at(const ColumnTerms& ct, const float
   return p2 <= 0.0f && alpha >= kAlphaMin;
 }
 
+// Tile scheduling of the compositing kernels.  With one workgroup per tile
+// the workgroup's slot is its block index; with persistent workgroups each
+// draws slots from a counter until they run out.  Slot i names tile order[i]
+// (longest lists first) or tile i when there is no order.
+//
+// next_slot: the whole workgroup's next slot (>= n_slots: none left).  The
+// slots are dealt to kq = min(GS_QUEUE_COUNTERS, gridDim.x) queues, slot
+// q + kq t to queue q, and workgroup b draws from queue b % kq (the
+// dispatcher places consecutive workgroups on different XCDs, so each XCD
+// drains one queue, and the draws of a launch spread over several counters,
+// each in its own 128-byte line, instead of queueing on one address).  A
+// queue's counter is its next t.  Every workgroup of a queue draws until it
+// gets one past the queue's end, so queue q sees exactly (its slots + its
+// workgroups) draws; the workgroup holding the last one sets the counter
+// back to zero, ready for the next launch.  The draw reaches the other waves
+// and lanes through LDS between two barriers, also with one wavefront per
+// workgroup: a wave-level broadcast of lane 0's draw instead lets the
+// compiler have lanes leave the slot loop separately, and the remaining
+// lanes then broadcast a value they never drew.
+__device__ __forceinline__ uint32_t next_slot(uint32_t* counters, uint32_t n_slots,
+                                              uint32_t* s_slot) {
+  const uint32_t kq = min((uint32_t)GS_QUEUE_COUNTERS, gridDim.x);
+  const uint32_t q = blockIdx.x % kq;
+  __syncthreads();   // every wave has read the previous slot
+  if (threadIdx.x == 0) {
+    const uint32_t n_q = (n_slots + kq - 1 - q) / kq;      // slots q, q + kq, ...
+    const uint32_t g_q = (gridDim.x + kq - 1 - q) / kq;    // workgroups b = q mod kq
+    uint32_t* c = counters + GS_QUEUE_STRIDE * q;
+    const uint32_t t = atomicAdd(c, 1u);
+    if (t == n_q + g_q - 1) atomicExch(c, 0u);
+    *s_slot = t < n_q ? q + kq * t : n_slots;
+  }
+  __syncthreads();
+  return *s_slot;
+}
+
+// Schedule of one compositing launch, from a GS_SCHEDULE_* tuning value:
+// the tile order to follow (NULL: tile id order), the queue counter
+// (non-NULL only for persistent workgroups) and the grid size.
+struct TileSchedule {
+  const uint32_t* order;
+  uint32_t* counter;
+  unsigned grid;
+};
+// resident: workgroups of the kernel that fit on the device at once
+TileSchedule tile_schedule(int schedule, const gs_bins& bins, int call, int n_tiles,
+                           int resident);
+// Workgroups of `kernel` (block threads each, no dynamic LDS) that the
+// current device holds at once; 0 on error.
+int resident_workgroups(const void* kernel, int block);
+
 // Process-wide tuning values (see gs_set_tuning); always a supported value.
 int tuning(int key);
 

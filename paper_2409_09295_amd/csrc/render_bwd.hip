@@ -115,13 +115,14 @@ __device__ __forceinline__ uint32_t stage_splat(uint32_t g, uint32_t n, uint32_t
   return reach;
 }
 
-template <int PPL>
+template <int PPL, bool Q>
 __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     ViewTable vt, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
     const uint32_t* __restrict__ order,
     const float2* __restrict__ xy, const float4* __restrict__ co, const float4* __restrict__ rd,
     float3 bg, const float* __restrict__ dL_dimage, const float* __restrict__ final_T,
-    const uint32_t* __restrict__ n_contrib, uint32_t n_gauss, float* __restrict__ grad2d) {
+    const uint32_t* __restrict__ n_contrib, uint32_t n_gauss, float* __restrict__ grad2d,
+    uint32_t* __restrict__ counter) {
   constexpr int NT = kBlock / PPL;
   // splats staged per batch: with one wavefront per tile (PPL 4) a smaller
   // batch halves the LDS per workgroup, so twice as many fit on a CU
@@ -132,162 +133,168 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
   // s_reach[q][w] bit b: staged splat 64 w + b can reach quadrant q
   __shared__ uint64_t s_reach[4][kWords];
   __shared__ uint32_t s_maxlast;
-  // the tile order (longest lists first) when the binning produced one
-  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
-  if (tile >= vt.n_tiles) return;
-  const int v = find_view(vt, tile);
-  const ViewInfo& vi = vt.v[v];
-  const int lt = tile - vi.tile_base;
-  const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
-  const int lane = threadIdx.x & 63;
-  // where wave_reduce9 leaves each value: row r = lane / 16 of q0 holds value
-  // {0, 2, 1, 3}[r] and of q1 value 4 + {0, 2, 1, 3}[r]; lane 63 of q2 holds
-  // value 8
-  // One atomic instruction adds all nine: lane 16 r takes q0's row total,
-  // lane 16 r + 1 q1's, lane 63 the ninth value.
-  const int row = lane >> 4, col16 = lane & 15;
-  const int red_off0 = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
-  const bool red_q0 = col16 == 0, red_q1 = col16 == 1, red_q2 = lane == 63;
-  const int red_off = red_q0 ? red_off0 : red_q1 ? red_off0 + 4 : 8;
+  __shared__ uint32_t s_slot;
+  // slot i: tile order[i] (longest lists first) when the binning produced
+  // an order; one slot per workgroup, or (Q) slots drawn from `counter`
+  for (uint32_t slot = blockIdx.x;;) {
+    if constexpr (Q) slot = next_slot(counter, (uint32_t)vt.n_tiles, &s_slot);
+    if (slot >= (uint32_t)vt.n_tiles) break;
+    const int tile = order ? (int)order[slot] : (int)slot;
+    const int v = find_view(vt, tile);
+    const ViewInfo& vi = vt.v[v];
+    const int lt = tile - vi.tile_base;
+    const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
+    const int lane = threadIdx.x & 63;
+    // where wave_reduce9 leaves each value: row r = lane / 16 of q0 holds value
+    // {0, 2, 1, 3}[r] and of q1 value 4 + {0, 2, 1, 3}[r]; lane 63 of q2 holds
+    // value 8
+    // One atomic instruction adds all nine: lane 16 r takes q0's row total,
+    // lane 16 r + 1 q1's, lane 63 the ninth value.
+    const int row = lane >> 4, col16 = lane & 15;
+    const int red_off0 = (row == 0) ? 0 : (row == 1) ? 2 : (row == 2) ? 1 : 3;
+    const bool red_q0 = col16 == 0, red_q1 = col16 == 1, red_q2 = lane == 63;
+    const int red_off = red_q0 ? red_off0 : red_q1 ? red_off0 + 4 : 8;
 
-  // pixel k of a lane lies in column k % NC (see the forward kernel)
-  constexpr int NC = PPL == 4 ? 2 : 1;
-  // sdc: (colour behind the current splat) . dL/dC of the pixel
-  float fpx[PPL], fpy[PPL], T[PPL], dC0[PPL], dC1[PPL], dC2[PPL], sdc[PPL];
-  uint32_t last[PPL], qbit[PPL];
-  uint32_t mylast = 0;
-  const int64_t plane = (int64_t)vi.width * vi.height;
-  const float* gimg = dL_dimage + 3 * vi.pix_base;
+    // pixel k of a lane lies in column k % NC (see the forward kernel)
+    constexpr int NC = PPL == 4 ? 2 : 1;
+    // sdc: (colour behind the current splat) . dL/dC of the pixel
+    float fpx[PPL], fpy[PPL], T[PPL], dC0[PPL], dC1[PPL], dC2[PPL], sdc[PPL];
+    uint32_t last[PPL], qbit[PPL];
+    uint32_t mylast = 0;
+    const int64_t plane = (int64_t)vi.width * vi.height;
+    const float* gimg = dL_dimage + 3 * vi.pix_base;
 #pragma unroll
-  for (int k = 0; k < PPL; ++k) {
-    const int i = k * NT + (int)threadIdx.x;
-    const int q = i >> 6, l = i & 63;
-    const int px = tx * kTile + (q & 1) * 8 + (l & 7);
-    const int py = ty * kTile + (q >> 1) * 8 + (l >> 3);
-    qbit[k] = __builtin_amdgcn_readfirstlane(1u << q);   // uniform over the wave
-    fpx[k] = (float)px + 0.5f;
-    fpy[k] = (float)py + 0.5f;
-    T[k] = 1.0f;
-    dC0[k] = dC1[k] = dC2[k] = sdc[k] = 0.f;
-    last[k] = 0;
-    if (px < vi.width && py < vi.height) {
-      const int64_t off = (int64_t)py * vi.width + px;
-      dC0[k] = gimg[off];
-      dC1[k] = gimg[plane + off];
-      dC2[k] = gimg[2 * plane + off];
-      T[k] = final_T[vi.pix_base + off];
-      sdc[k] = bg.x * dC0[k] + bg.y * dC1[k] + bg.z * dC2[k];
-      last[k] = n_contrib[vi.pix_base + off];
-      mylast = max(mylast, last[k]);
-    }
-  }
-  // list positions this wave has to walk: below the largest n_contrib of its pixels
-  uint32_t slot_last[PPL];   // per pixel slot: largest n_contrib over the wave
-  uint32_t wave_last = 0;
-#pragma unroll
-  for (int k = 0; k < PPL; ++k) {
-    uint32_t x = last[k];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, d, 64));
-    slot_last[k] = __builtin_amdgcn_readfirstlane(x);
-    wave_last = max(wave_last, slot_last[k]);
-  }
-  if (threadIdx.x == 0) s_maxlast = 0;
-  __syncthreads();
-  if (lane == 0 && wave_last) atomicMax(&s_maxlast, wave_last);
-  __syncthreads();
-  const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
-  // n_contrib never exceeds the tile's list length for a matching forward;
-  // the clamp keeps every list read inside [s, e) regardless.
-  const int64_t list_len = (int64_t)e - (int64_t)s;
-  const int64_t maxlast = min((int64_t)s_maxlast, max(list_len, (int64_t)0));
-
-  for (int64_t bend = maxlast; bend > 0; bend -= kStage) {
-    const int64_t bstart = max((int64_t)0, bend - kStage);
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kPerThread; ++r) {
-      const int slot = r * NT + (int)threadIdx.x;
-      const int64_t k = bstart + slot;
-      uint32_t reach = 0;
-      if (k < bend)
-        reach = stage_splat(values[s + (uint32_t)k], n_gauss, (uint32_t)vt.n_views, xy, co, rd,
-                            tx * kTile, ty * kTile, vi.width, vi.height, s_splat[slot]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint64_t bq = __ballot((reach >> q) & 1u);
-        if (lane == 0) s_reach[q][slot >> 6] = bq;
+    for (int k = 0; k < PPL; ++k) {
+      const int i = k * NT + (int)threadIdx.x;
+      const int q = i >> 6, l = i & 63;
+      const int px = tx * kTile + (q & 1) * 8 + (l & 7);
+      const int py = ty * kTile + (q >> 1) * 8 + (l >> 3);
+      qbit[k] = __builtin_amdgcn_readfirstlane(1u << q);   // uniform over the wave
+      fpx[k] = (float)px + 0.5f;
+      fpy[k] = (float)py + 0.5f;
+      T[k] = 1.0f;
+      dC0[k] = dC1[k] = dC2[k] = sdc[k] = 0.f;
+      last[k] = 0;
+      if (px < vi.width && py < vi.height) {
+        const int64_t off = (int64_t)py * vi.width + px;
+        dC0[k] = gimg[off];
+        dC1[k] = gimg[plane + off];
+        dC2[k] = gimg[2 * plane + off];
+        T[k] = final_T[vi.pix_base + off];
+        sdc[k] = bg.x * dC0[k] + bg.y * dC1[k] + bg.z * dC2[k];
+        last[k] = n_contrib[vi.pix_base + off];
+        mylast = max(mylast, last[k]);
       }
     }
+    // list positions this wave has to walk: below the largest n_contrib of its pixels
+    uint32_t slot_last[PPL];   // per pixel slot: largest n_contrib over the wave
+    uint32_t wave_last = 0;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      uint32_t x = last[k];
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, d, 64));
+      slot_last[k] = __builtin_amdgcn_readfirstlane(x);
+      wave_last = max(wave_last, slot_last[k]);
+    }
+    if (threadIdx.x == 0) s_maxlast = 0;
     __syncthreads();
-    // Walk, in reverse list order, only the staged splats below this wave's
-    // last blended position that reach one of its quadrants.
-    for (int w = kWords - 1; w >= 0; --w) {
-      const int64_t lim = (int64_t)wave_last - bstart - 64 * w;   // allowed bits: b < lim
-      if (lim <= 0) continue;
-      uint64_t m = 0;
+    if (lane == 0 && wave_last) atomicMax(&s_maxlast, wave_last);
+    __syncthreads();
+    const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
+    // n_contrib never exceeds the tile's list length for a matching forward;
+    // the clamp keeps every list read inside [s, e) regardless.
+    const int64_t list_len = (int64_t)e - (int64_t)s;
+    const int64_t maxlast = min((int64_t)s_maxlast, max(list_len, (int64_t)0));
+
+    for (int64_t bend = maxlast; bend > 0; bend -= kStage) {
+      const int64_t bstart = max((int64_t)0, bend - kStage);
+      __syncthreads();
 #pragma unroll
-      for (int k = 0; k < PPL; ++k) m |= s_reach[__builtin_ctz(qbit[k])][w];
-      m = uniform_u64(m);
-      if (lim < 64) m &= (uint64_t(1) << lim) - 1;
-      while (m) {
-        const int bit = 63 - __builtin_clzll(m);
-        m &= ~(uint64_t(1) << bit);
-        const int j = 64 * w + bit;
-        const uint32_t pos = (uint32_t)(bstart + j);
-        const float4 geo = s_splat[j].geo;
-        const float4 app = s_splat[j].app;
-        const float4 ext = s_splat[j].ext;
-        const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(ext.y)) : ~0u;
-        // Per pixel slot, branch-free over the wave: a lane whose pixel does
-        // not blend this splat takes alpha = 0, which leaves T and S exactly
-        // as they were and contributes exact zeros.
-        float g0 = -0.0f, g1 = -0.0f, g2 = -0.0f, g3 = -0.0f, g4 = -0.0f, g5 = -0.0f,
-              g6 = -0.0f, g7 = -0.0f, g8 = -0.0f;   // -0 + x == x exactly
-        bool started = false;
-        ColumnTerms ct[NC];
+      for (int r = 0; r < kPerThread; ++r) {
+        const int slot = r * NT + (int)threadIdx.x;
+        const int64_t k = bstart + slot;
+        uint32_t reach = 0;
+        if (k < bend)
+          reach = stage_splat(values[s + (uint32_t)k], n_gauss, (uint32_t)vt.n_views, xy, co, rd,
+                              tx * kTile, ty * kTile, vi.width, vi.height, s_splat[slot]);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) ct[c] = column_terms(geo, fpx[c]);
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-          // slot-uniform skips: quadrant not reached, or every pixel of the
-          // slot in this wave already past its last blended splat
-          if (!(reach & qbit[k]) || pos >= slot_last[k]) continue;
-          float alpha, raw, G, dy;
-          const float dx = ct[k % NC].dx;
-          const bool ok =
-              eval_alpha_at<true>(ct[k % NC], geo, app, fpy[k], alpha, raw, G, dy) &&
-              pos < last[k];
-          if (!__ballot(ok)) continue;
-          const float a = ok ? alpha : 0.0f;
-          const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - a);
-          const float wgt = a * Tk;
-          const float dot = (app.z * dC0[k] + app.w * dC1[k] + ext.x * dC2[k]) - sdc[k];
-          const float dalpha = Tk * dot;   // (c - S) . dL/dC
-          // colour behind the next splat in front: S + alpha (c - S)
-          sdc[k] = __builtin_fmaf(a, dot, sdc[k]);
-          T[k] = Tk;
-          // below the 0.99 clamp alpha = o G: d alpha/do = G, d alpha/dpower = alpha
-          const float live = (ok && raw <= kAlphaMax) ? dalpha : 0.0f;
-          const float gP = a * live;   // dL/dpower
-          const float gdx = gP * dx, gdy = gP * dy;
-          // d power/du = Q00 dx + Q01 dy (and likewise v): the conic factor is
-          // the same for every pixel, so only sum(gP d) is accumulated here
-          const float v2 = gdx * dx, v3 = gdx * dy, v4 = gdy * dy, v5 = G * live;
-          const float v6 = wgt * dC0[k], v7 = wgt * dC1[k], v8 = wgt * dC2[k];
-          g0 += gdx; g1 += gdy; g2 += v2; g3 += v3; g4 += v4; g5 += v5; g6 += v6; g7 += v7;
-          g8 += v8;
-          started = true;
+        for (int q = 0; q < 4; ++q) {
+          const uint64_t bq = __ballot((reach >> q) & 1u);
+          if (lane == 0) s_reach[q][slot >> 6] = bq;
         }
-        if (started) {
-          const Reduced9 r = wave_reduce9(g0, g1, g2, g3, g4, g5, g6, g7, g8);
-          const uint32_t acc = __builtin_amdgcn_readfirstlane(__float_as_uint(ext.w));
-          float* dst = grad2d + (int64_t)acc * 9;   // wave-uniform
-          const float val = red_q0 ? r.q0 : red_q1 ? r.q1 : r.q2;
-          if (red_q0 || red_q1 || red_q2) unsafeAtomicAdd(dst + red_off, val);
+      }
+      __syncthreads();
+      // Walk, in reverse list order, only the staged splats below this wave's
+      // last blended position that reach one of its quadrants.
+      for (int w = kWords - 1; w >= 0; --w) {
+        const int64_t lim = (int64_t)wave_last - bstart - 64 * w;   // allowed bits: b < lim
+        if (lim <= 0) continue;
+        uint64_t m = 0;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) m |= s_reach[__builtin_ctz(qbit[k])][w];
+        m = uniform_u64(m);
+        if (lim < 64) m &= (uint64_t(1) << lim) - 1;
+        while (m) {
+          const int bit = 63 - __builtin_clzll(m);
+          m &= ~(uint64_t(1) << bit);
+          const int j = 64 * w + bit;
+          const uint32_t pos = (uint32_t)(bstart + j);
+          const float4 geo = s_splat[j].geo;
+          const float4 app = s_splat[j].app;
+          const float4 ext = s_splat[j].ext;
+          const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(ext.y)) : ~0u;
+          // Per pixel slot, branch-free over the wave: a lane whose pixel does
+          // not blend this splat takes alpha = 0, which leaves T and S exactly
+          // as they were and contributes exact zeros.
+          float g0 = -0.0f, g1 = -0.0f, g2 = -0.0f, g3 = -0.0f, g4 = -0.0f, g5 = -0.0f,
+                g6 = -0.0f, g7 = -0.0f, g8 = -0.0f;   // -0 + x == x exactly
+          bool started = false;
+          ColumnTerms ct[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) ct[c] = column_terms(geo, fpx[c]);
+#pragma unroll
+          for (int k = 0; k < PPL; ++k) {
+            // slot-uniform skips: quadrant not reached, or every pixel of the
+            // slot in this wave already past its last blended splat
+            if (!(reach & qbit[k]) || pos >= slot_last[k]) continue;
+            float alpha, raw, G, dy;
+            const float dx = ct[k % NC].dx;
+            const bool ok =
+                eval_alpha_at<true>(ct[k % NC], geo, app, fpy[k], alpha, raw, G, dy) &&
+                pos < last[k];
+            if (!__ballot(ok)) continue;
+            const float a = ok ? alpha : 0.0f;
+            const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - a);
+            const float wgt = a * Tk;
+            const float dot = (app.z * dC0[k] + app.w * dC1[k] + ext.x * dC2[k]) - sdc[k];
+            const float dalpha = Tk * dot;   // (c - S) . dL/dC
+            // colour behind the next splat in front: S + alpha (c - S)
+            sdc[k] = __builtin_fmaf(a, dot, sdc[k]);
+            T[k] = Tk;
+            // below the 0.99 clamp alpha = o G: d alpha/do = G, d alpha/dpower = alpha
+            const float live = (ok && raw <= kAlphaMax) ? dalpha : 0.0f;
+            const float gP = a * live;   // dL/dpower
+            const float gdx = gP * dx, gdy = gP * dy;
+            // d power/du = Q00 dx + Q01 dy (and likewise v): the conic factor is
+            // the same for every pixel, so only sum(gP d) is accumulated here
+            const float v2 = gdx * dx, v3 = gdx * dy, v4 = gdy * dy, v5 = G * live;
+            const float v6 = wgt * dC0[k], v7 = wgt * dC1[k], v8 = wgt * dC2[k];
+            g0 += gdx; g1 += gdy; g2 += v2; g3 += v3; g4 += v4; g5 += v5; g6 += v6; g7 += v7;
+            g8 += v8;
+            started = true;
+          }
+          if (started) {
+            const Reduced9 r = wave_reduce9(g0, g1, g2, g3, g4, g5, g6, g7, g8);
+            const uint32_t acc = __builtin_amdgcn_readfirstlane(__float_as_uint(ext.w));
+            float* dst = grad2d + (int64_t)acc * 9;   // wave-uniform
+            const float val = red_q0 ? r.q0 : red_q1 ? r.q1 : r.q2;
+            if (red_q0 || red_q1 || red_q2) unsafeAtomicAdd(dst + red_off, val);
+          }
         }
       }
     }
+    if constexpr (!Q) break;
   }
 }
 
@@ -632,6 +639,26 @@ void launch_project_bwd(const gs_gaussians& g, const gs_camera* cams, int V, con
   }
 }
 
+template <int P>
+void launch_bwd(int schedule, const gs_bins& bins, const ViewTable& vt, const float2* xy,
+                const float4* co, const float4* rd, float3 bg, const float* dL_dimage,
+                const float* final_T, const uint32_t* n_contrib, uint32_t n_gauss,
+                float* grad2d, hipStream_t s) {
+  const int resident = schedule == GS_SCHEDULE_PERSISTENT
+                           ? resident_workgroups((const void*)render_bwd_kernel<P, true>,
+                                                 kBlock / P)
+                           : 0;
+  const TileSchedule sc = tile_schedule(schedule, bins, GS_QUEUE_BWD, vt.n_tiles, resident);
+  if (sc.counter)
+    hipLaunchKernelGGL((render_bwd_kernel<P, true>), dim3(sc.grid), dim3(kBlock / P), 0, s, vt,
+                       bins.ranges, bins.values, sc.order, xy, co, rd, bg, dL_dimage, final_T,
+                       n_contrib, n_gauss, grad2d, sc.counter);
+  else
+    hipLaunchKernelGGL((render_bwd_kernel<P, false>), dim3(sc.grid), dim3(kBlock / P), 0, s, vt,
+                       bins.ranges, bins.values, sc.order, xy, co, rd, bg, dL_dimage, final_T,
+                       n_contrib, n_gauss, grad2d, nullptr);
+}
+
 }  // namespace
 
 hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const gs_bins& bins,
@@ -652,20 +679,17 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
     const auto* co = reinterpret_cast<const float4*>(p.conic_opacity);
     const auto* rd = reinterpret_cast<const float4*>(p.rgb_depth);
     const int ppl = tuning(GS_TUNE_BWD_PIXELS_PER_LANE);
-    const dim3 grid((unsigned)vt.n_tiles);
+    const int sched = tuning(GS_TUNE_BWD_SCHEDULE);
     kernel_event_start(GS_KERNEL_RENDER_BWD, s);
     if (ppl == 4)
-      hipLaunchKernelGGL(render_bwd_kernel<4>, grid, dim3(kBlock / 4), 0, s, vt, bins.ranges,
-                         bins.values, bins.order, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
-                         (uint32_t)g.n, grad2d);
+      launch_bwd<4>(sched, bins, vt, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
+                    (uint32_t)g.n, grad2d, s);
     else if (ppl == 2)
-      hipLaunchKernelGGL(render_bwd_kernel<2>, grid, dim3(kBlock / 2), 0, s, vt, bins.ranges,
-                         bins.values, bins.order, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
-                         (uint32_t)g.n, grad2d);
+      launch_bwd<2>(sched, bins, vt, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
+                    (uint32_t)g.n, grad2d, s);
     else
-      hipLaunchKernelGGL(render_bwd_kernel<1>, grid, dim3(kBlock), 0, s, vt, bins.ranges,
-                         bins.values, bins.order, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
-                         (uint32_t)g.n, grad2d);
+      launch_bwd<1>(sched, bins, vt, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
+                    (uint32_t)g.n, grad2d, s);
     kernel_event_stop(GS_KERNEL_RENDER_BWD, s);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -41,14 +41,15 @@ __device__ __forceinline__ uint32_t stage_splat(uint32_t g, const float2* __rest
 
 // L1: also the photometric L1 gradient against `target` and the tile's
 // share of the loss (written to tile_loss[tile]).
-template <int PPL, bool L1>
+template <int PPL, bool L1, bool Q>
 __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
     ViewTable vt, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
     const uint32_t* __restrict__ order,
     const float2* __restrict__ xy, const float4* __restrict__ co, const float4* __restrict__ rd,
     float3 bg, float* __restrict__ image, float* __restrict__ final_T,
     uint32_t* __restrict__ n_contrib, float* __restrict__ depth_out,
-    const float* __restrict__ target, float* __restrict__ dL, float* __restrict__ tile_loss) {
+    const float* __restrict__ target, float* __restrict__ dL, float* __restrict__ tile_loss,
+    uint32_t* __restrict__ counter) {
   constexpr int NT = kBlock / PPL;
   // splats staged per batch: with one wavefront per tile (PPL 4), one splat
   // per lane (a smaller batch takes less LDS per workgroup, and a tile whose
@@ -60,146 +61,152 @@ __global__ __launch_bounds__(kBlock / PPL) void render_fwd_kernel(
   __shared__ StagedSplat s_splat[kStage];
   // s_reach[q][w] bit b: staged splat 64 w + b can reach quadrant q
   __shared__ uint64_t s_reach[4][kWords];
-  // the tile order (longest lists first) when the binning produced one
-  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
-  if (tile >= vt.n_tiles) return;
-  const int v = find_view(vt, tile);
-  const ViewInfo& vi = vt.v[v];
-  const int lt = tile - vi.tile_base;
-  const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
-  const int lane = threadIdx.x & 63;
+  __shared__ uint32_t s_slot;
+  // slot i: tile order[i] (longest lists first) when the binning produced
+  // an order; one slot per workgroup, or (Q) slots drawn from `counter`
+  for (uint32_t slot = blockIdx.x;;) {
+    if constexpr (Q) slot = next_slot(counter, (uint32_t)vt.n_tiles, &s_slot);
+    if (slot >= (uint32_t)vt.n_tiles) break;
+    const int tile = order ? (int)order[slot] : (int)slot;
+    const int v = find_view(vt, tile);
+    const ViewInfo& vi = vt.v[v];
+    const int lt = tile - vi.tile_base;
+    const int tx = lt % vi.tiles_x, ty = lt / vi.tiles_x;
+    const int lane = threadIdx.x & 63;
 
-  // pixel k of a lane lies in column k % NC: with 2 pixels per lane both
-  // share their x, with 4 the even and the odd ones do
-  constexpr int NC = PPL == 4 ? 2 : 1;
-  int px[PPL], py[PPL];
-  uint32_t qbit[PPL];   // quadrant bit of each of the lane's pixels (wave-uniform)
-  // T > 0: transmittance of a live pixel; T < 0: the pixel has terminated
-  // (or lies outside the image) and -T is its final transmittance
-  float fpx[PPL], fpy[PPL], T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL];
-  uint32_t last[PPL];
-  bool inside[PPL];
+    // pixel k of a lane lies in column k % NC: with 2 pixels per lane both
+    // share their x, with 4 the even and the odd ones do
+    constexpr int NC = PPL == 4 ? 2 : 1;
+    int px[PPL], py[PPL];
+    uint32_t qbit[PPL];   // quadrant bit of each of the lane's pixels (wave-uniform)
+    // T > 0: transmittance of a live pixel; T < 0: the pixel has terminated
+    // (or lies outside the image) and -T is its final transmittance
+    float fpx[PPL], fpy[PPL], T[PPL], C0[PPL], C1[PPL], C2[PPL], D[PPL];
+    uint32_t last[PPL];
+    bool inside[PPL];
 #pragma unroll
-  for (int k = 0; k < PPL; ++k) {
-    const int i = k * NT + (int)threadIdx.x;
-    const int q = i >> 6, l = i & 63;
-    px[k] = tx * kTile + (q & 1) * 8 + (l & 7);
-    py[k] = ty * kTile + (q >> 1) * 8 + (l >> 3);
-    qbit[k] = __builtin_amdgcn_readfirstlane(1u << q);
-    inside[k] = px[k] < vi.width && py[k] < vi.height;
-    fpx[k] = (float)px[k] + 0.5f;
-    fpy[k] = (float)py[k] + 0.5f;
-    T[k] = inside[k] ? 1.0f : -1.0f;
-    C0[k] = C1[k] = C2[k] = D[k] = 0.0f;
-    last[k] = 0;
-  }
-
-  const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
-  for (int64_t b = s; b < (int64_t)e; b += kStage) {
-    bool all_done = true;
-#pragma unroll
-    for (int k = 0; k < PPL; ++k) all_done = all_done && !(T[k] > 0.0f);
-    if (__syncthreads_count(all_done ? 0 : 1) == 0) break;
-#pragma unroll
-    for (int r = 0; r < kPerThread; ++r) {
-      const int slot = r * NT + (int)threadIdx.x;
-      const int64_t idx = b + slot;
-      uint32_t reach = 0;
-      if (idx < (int64_t)e)
-        reach = stage_splat(values[idx], xy, co, rd, tx * kTile, ty * kTile, vi.width,
-                            vi.height, s_splat[slot]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint64_t bq = __ballot((reach >> q) & 1u);
-        if (lane == 0) s_reach[q][slot >> 6] = bq;
-      }
+    for (int k = 0; k < PPL; ++k) {
+      const int i = k * NT + (int)threadIdx.x;
+      const int q = i >> 6, l = i & 63;
+      px[k] = tx * kTile + (q & 1) * 8 + (l & 7);
+      py[k] = ty * kTile + (q >> 1) * 8 + (l >> 3);
+      qbit[k] = __builtin_amdgcn_readfirstlane(1u << q);
+      inside[k] = px[k] < vi.width && py[k] < vi.height;
+      fpx[k] = (float)px[k] + 0.5f;
+      fpy[k] = (float)py[k] + 0.5f;
+      T[k] = inside[k] ? 1.0f : -1.0f;
+      C0[k] = C1[k] = C2[k] = D[k] = 0.0f;
+      last[k] = 0;
     }
-    __syncthreads();
-    // Walk, in list order, only the staged splats that reach one of this
-    // wave's quadrants; stop once every pixel of the wave has terminated.
-    if (__all(all_done)) continue;
-    for (int w = 0; w < kWords; ++w) {
-      uint64_t m = 0;
+
+    const uint32_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
+    for (int64_t b = s; b < (int64_t)e; b += kStage) {
+      bool all_done = true;
 #pragma unroll
-      for (int k = 0; k < PPL; ++k) m |= s_reach[__builtin_ctz(qbit[k])][w];
-      m = uniform_u64(m);
-      while (m) {
-        const int j = 64 * w + __builtin_ctzll(m);
-        m &= m - 1;
-        const float4 geo = s_splat[j].geo;
-        const float4 app = s_splat[j].app;
-        const float4 ext = s_splat[j].ext;
-        const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(ext.y)) : ~0u;
-        ColumnTerms ct[NC];
+      for (int k = 0; k < PPL; ++k) all_done = all_done && !(T[k] > 0.0f);
+      if (__syncthreads_count(all_done ? 0 : 1) == 0) break;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) ct[c] = column_terms(geo, fpx[c]);
+      for (int r = 0; r < kPerThread; ++r) {
+        const int slot = r * NT + (int)threadIdx.x;
+        const int64_t idx = b + slot;
+        uint32_t reach = 0;
+        if (idx < (int64_t)e)
+          reach = stage_splat(values[idx], xy, co, rd, tx * kTile, ty * kTile, vi.width,
+                              vi.height, s_splat[slot]);
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-          if (!(reach & qbit[k])) continue;   // slot-uniform
-          float alpha, raw, G, dy;
-          const bool ok = eval_alpha_at<false>(ct[k % NC], geo, app, fpy[k], alpha, raw, G, dy);
-          // a terminated pixel (T < 0) gets Tn <= 0 < kTMin: it never blends again
-          const float Tn = T[k] * (1.0f - alpha);
-          const bool term = ok && Tn < kTMin;   // stops before this splat
-          if (term) T[k] = -fabsf(T[k]);
-          if (!ok || term) continue;
-          const float wgt = alpha * T[k];
-          C0[k] += app.z * wgt;
-          C1[k] += app.w * wgt;
-          C2[k] += ext.x * wgt;
-          D[k] += ext.z * wgt;
-          T[k] = Tn;
-          last[k] = (uint32_t)(b - (int64_t)s) + (uint32_t)j + 1;
-        }
-        // every pixel of the wave has terminated: stop.  Tested after every
-        // fourth splat only (a terminated pixel never blends again, so a
-        // late test changes nothing; measured 2.4% faster than every splat)
-        if ((__popcll(m) & 3) == 0) {
-          bool live = false;
-#pragma unroll
-          for (int k = 0; k < PPL; ++k) live = live || __float_as_int(T[k]) > 0;
-          if (!__any(live)) m = 0;
+        for (int q = 0; q < 4; ++q) {
+          const uint64_t bq = __ballot((reach >> q) & 1u);
+          if (lane == 0) s_reach[q][slot >> 6] = bq;
         }
       }
+      __syncthreads();
+      // Walk, in list order, only the staged splats that reach one of this
+      // wave's quadrants; stop once every pixel of the wave has terminated.
+      if (__all(all_done)) continue;
+      for (int w = 0; w < kWords; ++w) {
+        uint64_t m = 0;
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) m |= s_reach[__builtin_ctz(qbit[k])][w];
+        m = uniform_u64(m);
+        while (m) {
+          const int j = 64 * w + __builtin_ctzll(m);
+          m &= m - 1;
+          const float4 geo = s_splat[j].geo;
+          const float4 app = s_splat[j].app;
+          const float4 ext = s_splat[j].ext;
+          const uint32_t reach = PPL > 1 ? __builtin_amdgcn_readfirstlane(__float_as_uint(ext.y)) : ~0u;
+          ColumnTerms ct[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) ct[c] = column_terms(geo, fpx[c]);
+#pragma unroll
+          for (int k = 0; k < PPL; ++k) {
+            if (!(reach & qbit[k])) continue;   // slot-uniform
+            float alpha, raw, G, dy;
+            const bool ok = eval_alpha_at<false>(ct[k % NC], geo, app, fpy[k], alpha, raw, G, dy);
+            // a terminated pixel (T < 0) gets Tn <= 0 < kTMin: it never blends again
+            const float Tn = T[k] * (1.0f - alpha);
+            const bool term = ok && Tn < kTMin;   // stops before this splat
+            if (term) T[k] = -fabsf(T[k]);
+            if (!ok || term) continue;
+            const float wgt = alpha * T[k];
+            C0[k] += app.z * wgt;
+            C1[k] += app.w * wgt;
+            C2[k] += ext.x * wgt;
+            D[k] += ext.z * wgt;
+            T[k] = Tn;
+            last[k] = (uint32_t)(b - (int64_t)s) + (uint32_t)j + 1;
+          }
+          // every pixel of the wave has terminated: stop.  Tested after every
+          // fourth splat only (a terminated pixel never blends again, so a
+          // late test changes nothing; measured 2.4% faster than every splat)
+          if ((__popcll(m) & 3) == 0) {
+            bool live = false;
+#pragma unroll
+            for (int k = 0; k < PPL; ++k) live = live || __float_as_int(T[k]) > 0;
+            if (!__any(live)) m = 0;
+          }
+        }
+      }
     }
-  }
-  const int64_t plane = (int64_t)vi.width * vi.height;
-  float* img = image + 3 * vi.pix_base;
-  // L1 against the target, as gs_l1_loss_grad computes it from the image
-  const float inv = 1.0f / (float)(3 * plane);
-  float lsum = 0.0f;
+    const int64_t plane = (int64_t)vi.width * vi.height;
+    float* img = image + 3 * vi.pix_base;
+    // L1 against the target, as gs_l1_loss_grad computes it from the image
+    const float inv = 1.0f / (float)(3 * plane);
+    float lsum = 0.0f;
 #pragma unroll
-  for (int k = 0; k < PPL; ++k) {
-    if (!inside[k]) continue;
-    const int64_t off = (int64_t)py[k] * vi.width + px[k];
-    const float Tf = fabsf(T[k]);
-    const float c[3] = {C0[k] + Tf * bg.x, C1[k] + Tf * bg.y, C2[k] + Tf * bg.z};
+    for (int k = 0; k < PPL; ++k) {
+      if (!inside[k]) continue;
+      const int64_t off = (int64_t)py[k] * vi.width + px[k];
+      const float Tf = fabsf(T[k]);
+      const float c[3] = {C0[k] + Tf * bg.x, C1[k] + Tf * bg.y, C2[k] + Tf * bg.z};
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) img[ch * plane + off] = c[ch];
-    final_T[vi.pix_base + off] = Tf;
-    n_contrib[vi.pix_base + off] = last[k];
-    if (!L1 && depth_out) depth_out[vi.pix_base + off] = D[k];
+      for (int ch = 0; ch < 3; ++ch) img[ch * plane + off] = c[ch];
+      final_T[vi.pix_base + off] = Tf;
+      n_contrib[vi.pix_base + off] = last[k];
+      if (!L1 && depth_out) depth_out[vi.pix_base + off] = D[k];
+      if (L1) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          const int64_t o = 3 * vi.pix_base + ch * plane + off;
+          const float d = c[ch] - target[o];
+          dL[o] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
+          lsum += fabsf(d);
+        }
+      }
+    }
     if (L1) {
+      __shared__ float s_l[kBlock / 64];
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        const int64_t o = 3 * vi.pix_base + ch * plane + off;
-        const float d = c[ch] - target[o];
-        dL[o] = d > 0.0f ? inv : (d < 0.0f ? -inv : 0.0f);
-        lsum += fabsf(d);
+      for (int d = 32; d >= 1; d >>= 1) lsum += __shfl_xor(lsum, d, 64);
+      if ((threadIdx.x & 63) == 0) s_l[threadIdx.x >> 6] = lsum;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float t = 0.0f;
+        for (int w = 0; w < NT / 64; ++w) t += s_l[w];
+        tile_loss[tile] = t * inv;
       }
     }
-  }
-  if (L1) {
-    __shared__ float s_l[kBlock / 64];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) lsum += __shfl_xor(lsum, d, 64);
-    if ((threadIdx.x & 63) == 0) s_l[threadIdx.x >> 6] = lsum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      float t = 0.0f;
-      for (int w = 0; w < NT / 64; ++w) t += s_l[w];
-      tile_loss[tile] = t * inv;
-    }
+    if constexpr (!Q) break;
   }
 }
 
@@ -256,6 +263,28 @@ hipError_t noalloc_scratch(float** out) {
   return hipSuccess;
 }
 
+namespace {
+template <int P, bool L>
+void launch_fwd(int schedule, const gs_bins& bins, const ViewTable& vt, const float2* xy,
+                const float4* co, const float4* rd, float3 bg, float* image, float* final_T,
+                uint32_t* n_contrib, float* depth, const float* target, float* dL,
+                float* tile_loss, hipStream_t s) {
+  const int resident = schedule == GS_SCHEDULE_PERSISTENT
+                           ? resident_workgroups((const void*)render_fwd_kernel<P, L, true>,
+                                                 kBlock / P)
+                           : 0;
+  const TileSchedule sc = tile_schedule(schedule, bins, GS_QUEUE_FWD, vt.n_tiles, resident);
+  if (sc.counter)
+    hipLaunchKernelGGL((render_fwd_kernel<P, L, true>), dim3(sc.grid), dim3(kBlock / P), 0, s, vt,
+                       bins.ranges, bins.values, sc.order, xy, co, rd, bg, image, final_T,
+                       n_contrib, depth, target, dL, tile_loss, sc.counter);
+  else
+    hipLaunchKernelGGL((render_fwd_kernel<P, L, false>), dim3(sc.grid), dim3(kBlock / P), 0, s,
+                       vt, bins.ranges, bins.values, sc.order, xy, co, rd, bg, image, final_T,
+                       n_contrib, depth, target, dL, tile_loss, nullptr);
+}
+}  // namespace
+
 hipError_t launch_render_fwd(const gs_projected& p, const gs_bins& bins, const ViewTable& vt,
                              float3 bg, float* image, float* final_T, uint32_t* n_contrib,
                              float* depth, const float* target, float* dL, double* loss,
@@ -265,12 +294,11 @@ hipError_t launch_render_fwd(const gs_projected& p, const gs_bins& bins, const V
   const auto* co = reinterpret_cast<const float4*>(p.conic_opacity);
   const auto* rd = reinterpret_cast<const float4*>(p.rgb_depth);
   const int ppl = tuning(GS_TUNE_FWD_PIXELS_PER_LANE);
-  const dim3 grid((unsigned)vt.n_tiles);
+  const int sched = tuning(GS_TUNE_FWD_SCHEDULE);
   const bool l1 = target != nullptr;
-#define GS_FWD(P, L)                                                                       \
-  hipLaunchKernelGGL((render_fwd_kernel<P, L>), grid, dim3(kBlock / P), 0, s, vt, bins.ranges, \
-                     bins.values, bins.order, xy, co, rd, bg, image, final_T, n_contrib, depth, \
-                     target, dL, tile_loss)
+#define GS_FWD(P, L)                                                                          \
+  launch_fwd<P, L>(sched, bins, vt, xy, co, rd, bg, image, final_T, n_contrib, depth, target, \
+                   dL, tile_loss, s)
   kernel_event_start(GS_KERNEL_RENDER_FWD, s);
   if (ppl == 4) {
     if (l1) GS_FWD(4, true); else GS_FWD(4, false);

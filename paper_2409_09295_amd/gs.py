@@ -42,6 +42,14 @@ GS_KERNEL_RENDER_BWD = 3
 GS_KERNEL_PROJECT_BWD = 4
 GS_TUNE_FWD_PIXELS_PER_LANE = 0
 GS_TUNE_BWD_PIXELS_PER_LANE = 1
+GS_TUNE_FWD_SCHEDULE = 2
+GS_TUNE_BWD_SCHEDULE = 3
+GS_SCHEDULE_HEAVIEST_FIRST = 1
+GS_SCHEDULE_TILE_ID = 2
+GS_SCHEDULE_PERSISTENT = 3
+GS_QUEUE_COUNTERS = 8
+GS_QUEUE_STRIDE = 32
+GS_QUEUE_WORDS = 1024
 GS_MAX_VIEWS = 64
 TILE = 16
 
@@ -79,7 +87,7 @@ class gs_projected(ctypes.Structure):
 
 class gs_bins(ctypes.Structure):
     _fields_ = [("keys", _p), ("values", _p), ("ranges", _p), ("n_keys", _p),
-                ("capacity", ctypes.c_int64), ("order", _p)]
+                ("capacity", ctypes.c_int64), ("order", _p), ("queue", _p)]
 
 
 class gs_grads(ctypes.Structure):
@@ -353,6 +361,7 @@ class Bins:
     n_keys: torch.Tensor   # (1,) int32 storage of uint32
     capacity: int
     order: Optional[torch.Tensor] = None   # (n_tiles,) int32 storage of uint32, or not computed
+    queue: Optional[torch.Tensor] = None   # (GS_QUEUE_WORDS,) int32 storage of uint32 tile counters
 
     @classmethod
     def empty(cls, capacity: int, n_tiles: int, device="cuda", order: bool = True,
@@ -364,11 +373,13 @@ class Bins:
                    torch.empty(cap, dtype=torch.int32, device=device),
                    torch.empty(n_tiles, 2, dtype=torch.int32, device=device),
                    torch.zeros(1, dtype=torch.int32, device=device), int(capacity),
-                   torch.empty(max(n_tiles, 1), dtype=torch.int32, device=device) if order else None)
+                   torch.empty(max(n_tiles, 1), dtype=torch.int32, device=device) if order else None,
+                   torch.zeros(GS_QUEUE_WORDS, dtype=torch.int32, device=device))
 
     def struct(self) -> gs_bins:
         return gs_bins(_ptr(self.keys), _ptr(self.values), _ptr(self.ranges), _ptr(self.n_keys),
-                       self.capacity, _ptr(self.order) if self.order is not None else None)
+                       self.capacity, _ptr(self.order) if self.order is not None else None,
+                       _ptr(self.queue) if self.queue is not None else None)
 
 
 @dataclasses.dataclass

@@ -304,3 +304,40 @@ def test_memory_ledger_tracks_current_and_peak(gs):
     gs.gs_mem_reset_peaks()
     r3 = gs.gs_mem_report()
     assert r3["overhead_peak"] == r3["overhead_current"] == base["overhead_current"]
+
+
+def test_tuning_keys_validate_and_reset(gs):
+    """Pixels per lane takes 1, 2 or 4 and tile schedules their three
+    GS_SCHEDULE_* values; 0 restores each key's default; anything else is
+    rejected and leaves the value as it was.  The header's constants match
+    the binding's."""
+    header = open(os.path.join(ROOT, "include", "gs.h")).read()
+    for name in ("GS_TUNE_FWD_SCHEDULE", "GS_TUNE_BWD_SCHEDULE", "GS_SCHEDULE_HEAVIEST_FIRST",
+                 "GS_SCHEDULE_TILE_ID", "GS_SCHEDULE_PERSISTENT", "GS_QUEUE_WORDS",
+                 "GS_QUEUE_COUNTERS", "GS_QUEUE_STRIDE"):
+        m = re.search(rf"\b{name}\s*=\s*(\d+)", header)
+        assert m and int(m.group(1)) == getattr(gs, name), name
+    try:
+        for key in (gs.GS_TUNE_FWD_SCHEDULE, gs.GS_TUNE_BWD_SCHEDULE):
+            assert gs.gs_get_tuning(key) == gs.GS_SCHEDULE_HEAVIEST_FIRST
+            gs.gs_set_tuning(key, gs.GS_SCHEDULE_PERSISTENT)
+            assert gs.gs_get_tuning(key) == gs.GS_SCHEDULE_PERSISTENT
+            for bad in (-1, 4, 7):
+                with pytest.raises(gs.GsError):
+                    gs.gs_set_tuning(key, bad)
+            assert gs.gs_get_tuning(key) == gs.GS_SCHEDULE_PERSISTENT
+            gs.gs_set_tuning(key, 0)
+            assert gs.gs_get_tuning(key) == gs.GS_SCHEDULE_HEAVIEST_FIRST
+        for key in (gs.GS_TUNE_FWD_PIXELS_PER_LANE, gs.GS_TUNE_BWD_PIXELS_PER_LANE):
+            gs.gs_set_tuning(key, 4)
+            with pytest.raises(gs.GsError):
+                gs.gs_set_tuning(key, 3)
+            assert gs.gs_get_tuning(key) == 4
+            gs.gs_set_tuning(key, 0)
+            assert gs.gs_get_tuning(key) == 1
+        with pytest.raises(gs.GsError):
+            gs.gs_set_tuning(gs.GS_TUNE_BWD_SCHEDULE + 1, 1)
+        assert gs.gs_get_tuning(99) < 0
+    finally:
+        for key in range(4):
+            gs.gs_set_tuning(key, 0)

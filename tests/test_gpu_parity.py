@@ -27,6 +27,8 @@ BIN_CASES = {
     "one_view_160x120": [scenes.pinhole(160, 120, 150.0)],
     "ragged_multi_view": [scenes.pinhole(100, 70, 80.0), scenes.pinhole(320, 240, 300.0),
                           scenes.pinhole(48, 40, 40.0), scenes.pinhole(1200, 680, 984.0)],
+    # 1 + 6 tiles: fewer tiles than the persistent schedule's counters
+    "tiny_views": [scenes.pinhole(16, 16, 14.0), scenes.pinhole(40, 20, 30.0)],
 }
 
 
@@ -214,16 +216,23 @@ def _render_gpu(gs, sp, cams, bg=(0.0, 0.0, 0.0)):
 
 @pytest.fixture
 def ppl_setting(gs, request):
-    """Runs a test under a pixels-per-lane setting of both tile kernels."""
-    fwd, bwd = request.param
+    """Runs a test under a (forward, backward) pixels-per-lane setting of the
+    tile kernels and, when given, a tile schedule for both."""
+    fwd, bwd, *sched = request.param
     gs.gs_set_tuning(gs.GS_TUNE_FWD_PIXELS_PER_LANE, fwd)
     gs.gs_set_tuning(gs.GS_TUNE_BWD_PIXELS_PER_LANE, bwd)
+    for key in (gs.GS_TUNE_FWD_SCHEDULE, gs.GS_TUNE_BWD_SCHEDULE):
+        gs.gs_set_tuning(key, sched[0] if sched else 0)
     yield request.param
-    gs.gs_set_tuning(gs.GS_TUNE_FWD_PIXELS_PER_LANE, 0)
-    gs.gs_set_tuning(gs.GS_TUNE_BWD_PIXELS_PER_LANE, 0)
+    for key in (gs.GS_TUNE_FWD_PIXELS_PER_LANE, gs.GS_TUNE_BWD_PIXELS_PER_LANE,
+                gs.GS_TUNE_FWD_SCHEDULE, gs.GS_TUNE_BWD_SCHEDULE):
+        gs.gs_set_tuning(key, 0)
 
 
-PPL_SETTINGS = [(1, 1), (2, 2), (4, 4)]
+# one workgroup per tile (heaviest first: the default; tile id order), and
+# persistent workgroups drawing tiles from a counter
+_HF, _ID, _PS = 1, 2, 3
+PPL_SETTINGS = [(1, 1), (2, 2), (4, 4), (4, 4, _ID), (1, 1, _PS), (2, 2, _PS), (4, 4, _PS)]
 
 
 @pytest.mark.parametrize("ppl_setting", PPL_SETTINGS, indirect=True)

@@ -91,6 +91,49 @@ def test_graph_replay_with_adam_tracks_eager(gs):
         assert off.mean() < 5e-3, (k, off.mean())
 
 
+@pytest.mark.parametrize("ppl", [1, 4])
+def test_persistent_schedule_matches_per_tile_launch(gs, ppl):
+    """The benchmark's batch (38,400 tiles): persistent workgroups drawing
+    tiles from the bins' counters give the image and n_contrib of one
+    workgroup per tile bit for bit, and its gradients up to the order of the
+    atomic additions, eagerly and over three graph replays with eager work
+    between them (each launch leaves its counter at zero for the next)."""
+    from paper_2409_09295_amd import autotune
+    from paper_2409_09295_amd.replay import BatchedStep
+    wl = scenes.config_metric(0)
+    views = gs.Views(wl.cams)
+    rng = np.random.default_rng(12)
+    targets = torch.from_numpy(rng.random(3 * views.n_pixels).astype(np.float32)).to(DEV)
+    step = BatchedStep(gs.Gaussians.from_map(wl.gmap), views, targets, optimize=False)
+    try:
+        autotune.apply(ppl, ppl, gs.GS_SCHEDULE_HEAVIEST_FIRST, gs.GS_SCHEDULE_HEAVIEST_FIRST)
+        step._body()
+        torch.cuda.synchronize()
+        img0, gr0 = _snap(step)
+        nc0 = step.n_contrib.clone()
+        autotune.apply(ppl, ppl, gs.GS_SCHEDULE_PERSISTENT, gs.GS_SCHEDULE_PERSISTENT)
+
+        def check(label):
+            torch.cuda.synchronize()
+            img, gr = _snap(step)
+            _log(f"ppl {ppl} persistent, {label}: checking against one workgroup per tile")
+            torch.testing.assert_close(img, img0, rtol=0, atol=0)
+            torch.testing.assert_close(step.n_contrib, nc0, rtol=0, atol=0)
+            for k in GROUPS + ("xi",):
+                assert_same_up_to_order(k, np_(gr[k]), np_(gr0[k]))
+            assert int(step.bins.queue.abs().sum().item()) == 0
+
+        step._body()
+        check("eager")
+        step.capture()
+        for rep in range(3):
+            step.step()
+            check(f"replay {rep}")
+            _ = (targets * 2).sum().item()
+    finally:
+        autotune.apply(0, 0)
+
+
 def _pick_tiles(cams, tiles_per_view, seed):
     rng = np.random.default_rng(seed)
     picks = []
@@ -125,7 +168,8 @@ def _timed_step_parity(gs, wl, view_ids, tiles_per_view, seed, max_masked):
     targets = torch.zeros(3 * P, dtype=torch.float32, device=DEV)
     step = BatchedStep(g, views, targets, bg=wl.bg)
     tuned = autotune.tune(step)
-    _log(f"{wl.name}: tuned {tuned['fwd_ppl']}/{tuned['bwd_ppl']}")
+    _log(f"{wl.name}: tuned {tuned['fwd_ppl']}/{tuned['bwd_ppl']} "
+         f"{tuned.get('fwd_schedule_name')}/{tuned.get('bwd_schedule_name')}")
     try:
         snap = step.adam.snapshot()
         step._body()
@@ -306,8 +350,15 @@ def test_autotuner_caches_its_choice(gs, tmp_path):
     try:
         a = autotune.tune(step, cache=cache, reps=1)
         assert not a["cached"] and a["fwd_ppl"] in autotune.CHOICES and a["bwd_ppl"] in autotune.CHOICES
+        assert len(a["table"]) == 2 * len(autotune.CHOICES) * len(autotune.SCHEDULES)
         assert gs.gs_get_tuning(gs.GS_TUNE_FWD_PIXELS_PER_LANE) == a["fwd_ppl"]
+        assert gs.gs_get_tuning(gs.GS_TUNE_FWD_SCHEDULE) == a["fwd_schedule"]
+        assert gs.gs_get_tuning(gs.GS_TUNE_BWD_SCHEDULE) == a["bwd_schedule"]
+        autotune.apply(0, 0)
         b = autotune.tune(step, cache=cache)
-        assert b["cached"] and (b["fwd_ppl"], b["bwd_ppl"]) == (a["fwd_ppl"], a["bwd_ppl"])
+        assert b["cached"]
+        for k in ("fwd_ppl", "bwd_ppl", "fwd_schedule", "bwd_schedule"):
+            assert b[k] == a[k], k
+        assert gs.gs_get_tuning(gs.GS_TUNE_BWD_SCHEDULE) == a["bwd_schedule"]
     finally:
         autotune.apply(0, 0)

@@ -54,8 +54,17 @@ def _near_threshold_masks(gmap, cams, bg):
     return [v["mask"] for v in res["views"]]
 
 
+@pytest.fixture(params=[1, 3], ids=["per_tile", "persistent"])
+def bwd_schedule(gs, request):
+    """The backward tile schedule, which the error walk follows: one
+    workgroup per tile (heaviest first), or persistent workgroups."""
+    gs.gs_set_tuning(gs.GS_TUNE_BWD_SCHEDULE, request.param)
+    yield request.param
+    gs.gs_set_tuning(gs.GS_TUNE_BWD_SCHEDULE, 0)
+
+
 @pytest.mark.parametrize("case", ["c1", "two_views_bg", "c2"])
-def test_render_error_matches_oracle(gs, case):
+def test_render_error_matches_oracle(gs, case, bwd_schedule):
     if case == "c1":
         wl = scenes.config_c1(0)
     elif case == "c2":
@@ -85,6 +94,7 @@ def test_render_error_matches_oracle(gs, case):
     # repeat: only the float32 order of the atomic additions may differ
     err2 = _gpu_error(gs, views, rast, g.n, target)
     np.testing.assert_allclose(np_(err2), np_(err), rtol=1e-5, atol=1e-7 * float(err.max()))
+    assert int(rast.bins.queue.abs().sum().item()) == 0
 
 
 def test_render_error_metric_workload_sampled(gs):
