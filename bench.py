@@ -422,6 +422,8 @@ def main():
         "paper_shaped_12_views": v12,
         "kernel_ms": kms,
         "tuning": {"fwd_pixels_per_lane": tuned["fwd_ppl"], "bwd_pixels_per_lane": tuned["bwd_ppl"],
+                   "fwd_stage_per_thread": tuned.get("fwd_stage"),
+                   "bwd_stage_per_thread": tuned.get("bwd_stage"),
                    "fwd_schedule": tuned.get("fwd_schedule_name"),
                    "bwd_schedule": tuned.get("bwd_schedule_name"),
                    "table_ms": tuned.get("table")},

@@ -219,7 +219,12 @@ enum {
   GS_TUNE_BWD_PIXELS_PER_LANE = 1, /* gs_render_bwd: pixels per lane, 1 | 2 | 4 (default 1) */
   GS_TUNE_FWD_SCHEDULE = 2,        /* gs_render_fwd(_l1): a GS_SCHEDULE_* value            */
   GS_TUNE_BWD_SCHEDULE = 3,        /* gs_render_bwd and gs_render_error: GS_SCHEDULE_*     */
-  GS_TUNE_COUNT = 4
+  GS_TUNE_FWD_STAGE = 4,           /* gs_render_fwd(_l1): splats each thread stages in LDS
+                                      per batch, 1 | 2 (default 0: 1, or 2 at 2 pixels per
+                                      lane)                                                */
+  GS_TUNE_BWD_STAGE = 5,           /* gs_render_bwd: likewise, 1 | 2 (default 0: 2, or 1 at
+                                      1 pixel per lane)                                    */
+  GS_TUNE_COUNT = 6
 };
 
 /* Tile schedules of the compositing kernels (GS_TUNE_*_SCHEDULE). */
@@ -227,14 +232,16 @@ enum {
   GS_SCHEDULE_HEAVIEST_FIRST = 1, /* one workgroup per tile, launched in bins->order (default;
                                      tile id order when bins->order is NULL)                  */
   GS_SCHEDULE_TILE_ID = 2,        /* one workgroup per tile, launched in tile id order        */
-  GS_SCHEDULE_PERSISTENT = 3      /* as many workgroups as the GPU holds at once, each taking
+  GS_SCHEDULE_PERSISTENT = 3,     /* as many workgroups as the GPU holds at once, each taking
                                      tiles in bins->order from a counter in bins->queue until
                                      none is left                                              */
+  GS_SCHEDULE_PERSISTENT_HALF = 4 /* the same with half as many workgroups                    */
 };
 
 /* Process-wide kernel configuration, set by an autotuner.  Pixels per lane:
- * a 16x16 tile is covered by 256 / value threads.  value 0 restores the
- * default.  Applies to launches enqueued after the call; a captured graph
+ * a 16x16 tile is covered by 256 / value threads; a staging batch holds
+ * (splats per thread) x 256 / (pixels per lane) splats.  value 0 restores
+ * the default.  Applies to launches enqueued after the call; a captured graph
  * keeps the configuration it was captured with.  Results are identical for
  * every setting up to float32 summation order of the gradient atomics. */
 int gs_set_tuning(int key, int value);

@@ -2,10 +2,11 @@
 
 For a given batch (device, views, pixel count, Gaussian count, SH degree) it
 times, for the forward and the backward tile kernel separately, every
-pixels-per-lane setting (1, 2 or 4: four, two or one wavefront per 16x16
-tile) under every tile schedule (one workgroup per tile launched heaviest
-first or in tile id order, or persistent workgroups drawing tiles heaviest
-first from a counter) on the real step (eager launches, HIP events,
+combination of pixels per lane (1, 2 or 4: four, two or one wavefront per
+16x16 tile), LDS staging batch (1 or 2 splats per thread) and tile schedule
+(one workgroup per tile launched heaviest first or in tile id order, or
+persistent workgroups, as many as the GPU holds or half that, drawing tiles
+heaviest first from counters) on the real step (eager launches, HIP events,
 optimiser state restored afterwards), keeps the fastest and caches the
 choice in a JSON file keyed by device name, library version and workload
 shape.  Every setting computes the same result (up to the float32 order of
@@ -22,8 +23,10 @@ import torch
 from . import gs
 
 CHOICES = (1, 2, 4)
+STAGES = (1, 2)
 SCHEDULES = {"heaviest_first": gs.GS_SCHEDULE_HEAVIEST_FIRST, "tile_id": gs.GS_SCHEDULE_TILE_ID,
-             "persistent": gs.GS_SCHEDULE_PERSISTENT}
+             "persistent": gs.GS_SCHEDULE_PERSISTENT,
+             "persistent_half": gs.GS_SCHEDULE_PERSISTENT_HALF}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gsmi", "tune.json")
 
 
@@ -49,18 +52,22 @@ def _save(path: str, data: Dict):
     os.replace(tmp, path)
 
 
-def apply(fwd_ppl: int, bwd_ppl: int, fwd_schedule: int = 0, bwd_schedule: int = 0):
+def apply(fwd_ppl: int, bwd_ppl: int, fwd_schedule: int = 0, bwd_schedule: int = 0,
+          fwd_stage: int = 0, bwd_stage: int = 0):
     """Sets the process-wide tuning (0 = the library default)."""
     gs.gs_set_tuning(gs.GS_TUNE_FWD_PIXELS_PER_LANE, fwd_ppl)
     gs.gs_set_tuning(gs.GS_TUNE_BWD_PIXELS_PER_LANE, bwd_ppl)
     gs.gs_set_tuning(gs.GS_TUNE_FWD_SCHEDULE, fwd_schedule)
     gs.gs_set_tuning(gs.GS_TUNE_BWD_SCHEDULE, bwd_schedule)
+    gs.gs_set_tuning(gs.GS_TUNE_FWD_STAGE, fwd_stage)
+    gs.gs_set_tuning(gs.GS_TUNE_BWD_STAGE, bwd_stage)
 
 
 def time_config(step, fwd_ppl: int, bwd_ppl: int, reps: int = 3, fwd_schedule: int = 0,
-                bwd_schedule: int = 0) -> Tuple[float, float]:
+                bwd_schedule: int = 0, fwd_stage: int = 0,
+                bwd_stage: int = 0) -> Tuple[float, float]:
     """Mean (forward, backward) tile-kernel milliseconds for one setting."""
-    apply(fwd_ppl, bwd_ppl, fwd_schedule, bwd_schedule)
+    apply(fwd_ppl, bwd_ppl, fwd_schedule, bwd_schedule, fwd_stage, bwd_stage)
     ev = {}
     for k in (gs.GS_KERNEL_RENDER_FWD, gs.GS_KERNEL_RENDER_BWD):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -88,34 +95,40 @@ def time_config(step, fwd_ppl: int, bwd_ppl: int, reps: int = 3, fwd_schedule: i
 
 
 def _apply_best(best: Dict):
-    apply(best["fwd_ppl"], best["bwd_ppl"], best.get("fwd_schedule", 0), best.get("bwd_schedule", 0))
+    apply(best["fwd_ppl"], best["bwd_ppl"], best.get("fwd_schedule", 0), best.get("bwd_schedule", 0),
+          best.get("fwd_stage", 0), best.get("bwd_stage", 0))
+
+
+def _label(kernel: str, ppl: int, stage: int, schedule: str) -> str:
+    return f"{kernel}{ppl}s{stage}_{schedule}"
 
 
 def tune(step, cache: Optional[str] = None, force: bool = False, reps: int = 3) -> Dict:
     """Pick and apply the fastest setting for ``step`` (a replay.BatchedStep).
-    Returns {"fwd_ppl", "bwd_ppl", "fwd_schedule", "bwd_schedule", "fwd_ms",
-    "bwd_ms", "cached", "table"}; table keys are "fwd<ppl>_<schedule name>"
-    and "bwd<ppl>_<schedule name>"."""
+    Returns {"fwd_ppl", "bwd_ppl", "fwd_stage", "bwd_stage", "fwd_schedule",
+    "bwd_schedule" (GS_SCHEDULE_* values) and their names, "fwd_ms", "bwd_ms",
+    "cached", "table"}; table keys are "<fwd|bwd><ppl>s<stage>_<schedule>"."""
     cache = cache or os.environ.get("GSMI_TUNE_CACHE", DEFAULT_CACHE)
     key = _key(step)
     data = _load(cache)
-    if not force and key in data and "fwd_schedule" in data[key]:
+    if not force and key in data and "fwd_stage" in data[key]:
         best = data[key]
         _apply_best(best)
         return dict(best, cached=True)
+    settings = [(p, st, name) for name in SCHEDULES for p in CHOICES for st in STAGES]
     table = {}
-    for name, sched in SCHEDULES.items():
-        for f in CHOICES:
-            table[f"fwd{f}_{name}"], _ = time_config(step, f, 1, reps, fwd_schedule=sched)
-        for b in CHOICES:
-            _, table[f"bwd{b}_{name}"] = time_config(step, 1, b, reps, bwd_schedule=sched)
-    settings = [(p, name) for name in SCHEDULES for p in CHOICES]
-    bf = min(settings, key=lambda c: table[f"fwd{c[0]}_{c[1]}"])
-    bb = min(settings, key=lambda c: table[f"bwd{c[0]}_{c[1]}"])
-    best = {"fwd_ppl": bf[0], "bwd_ppl": bb[0], "fwd_schedule": SCHEDULES[bf[1]],
-            "bwd_schedule": SCHEDULES[bb[1]], "fwd_schedule_name": bf[1],
-            "bwd_schedule_name": bb[1], "fwd_ms": table[f"fwd{bf[0]}_{bf[1]}"],
-            "bwd_ms": table[f"bwd{bb[0]}_{bb[1]}"], "table": table}
+    for p, st, name in settings:
+        table[_label("fwd", p, st, name)], _ = time_config(
+            step, p, 1, reps, fwd_schedule=SCHEDULES[name], fwd_stage=st)
+        _, table[_label("bwd", p, st, name)] = time_config(
+            step, 1, p, reps, bwd_schedule=SCHEDULES[name], bwd_stage=st)
+    bf = min(settings, key=lambda c: table[_label("fwd", *c)])
+    bb = min(settings, key=lambda c: table[_label("bwd", *c)])
+    best = {"fwd_ppl": bf[0], "bwd_ppl": bb[0], "fwd_stage": bf[1], "bwd_stage": bb[1],
+            "fwd_schedule": SCHEDULES[bf[2]], "bwd_schedule": SCHEDULES[bb[2]],
+            "fwd_schedule_name": bf[2], "bwd_schedule_name": bb[2],
+            "fwd_ms": table[_label("fwd", *bf)], "bwd_ms": table[_label("bwd", *bb)],
+            "table": table}
     data[key] = best
     try:
         _save(cache, data)

@@ -19,7 +19,7 @@ thread_local hipEvent_t g_events[GS_KERNEL_COUNT][2] = {};
 
 namespace {
 std::atomic<int> g_tuning[GS_TUNE_COUNT] = {{1}, {1}, {GS_SCHEDULE_HEAVIEST_FIRST},
-                                            {GS_SCHEDULE_HEAVIEST_FIRST}};
+                                            {GS_SCHEDULE_HEAVIEST_FIRST}, {0}, {0}};
 }
 
 int tuning(int key) { return g_tuning[key].load(std::memory_order_relaxed); }
@@ -49,7 +49,10 @@ TileSchedule tile_schedule(int schedule, const gs_bins& bins, int call, int n_ti
                            int resident) {
   TileSchedule t{bins.order, nullptr, (unsigned)n_tiles};
   if (schedule == GS_SCHEDULE_TILE_ID) t.order = nullptr;
-  if (schedule == GS_SCHEDULE_PERSISTENT && bins.queue && resident > 0) {
+  const bool persistent =
+      schedule == GS_SCHEDULE_PERSISTENT || schedule == GS_SCHEDULE_PERSISTENT_HALF;
+  if (persistent && bins.queue && resident > 0) {
+    if (schedule == GS_SCHEDULE_PERSISTENT_HALF) resident = std::max(1, resident / 2);
     t.counter = bins.queue + (size_t)GS_QUEUE_STRIDE * GS_QUEUE_COUNTERS * call;
     t.grid = (unsigned)std::min(n_tiles, resident);
   }
@@ -206,8 +209,11 @@ int gs_set_tuning(int key, int value) {
   if (key < 0 || key >= GS_TUNE_COUNT) return invalid("unknown tuning key %d", key);
   if (key == GS_TUNE_FWD_SCHEDULE || key == GS_TUNE_BWD_SCHEDULE) {
     if (value == 0) value = GS_SCHEDULE_HEAVIEST_FIRST;
-    if (value < GS_SCHEDULE_HEAVIEST_FIRST || value > GS_SCHEDULE_PERSISTENT)
+    if (value < GS_SCHEDULE_HEAVIEST_FIRST || value > GS_SCHEDULE_PERSISTENT_HALF)
       return invalid("unknown tile schedule %d", value);
+  } else if (key == GS_TUNE_FWD_STAGE || key == GS_TUNE_BWD_STAGE) {
+    if (value < 0 || value > 2)
+      return invalid("splats staged per thread must be 1 or 2 (got %d)", value);
   } else {
     if (value == 0) value = 1;
     if (value != 1 && value != 2 && value != 4)

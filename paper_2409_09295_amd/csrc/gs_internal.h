@@ -243,6 +243,10 @@ int resident_workgroups(const void* kernel, int block);
 // Process-wide tuning values (see gs_set_tuning); always a supported value.
 int tuning(int key);
 
+// Splats per thread and LDS batch from a GS_TUNE_*_STAGE value (0: the
+// kernel's default).
+inline int stage_per_thread(int value, int fallback) { return value == 0 ? fallback : value; }
+
 // Optional per-kernel timing events (see gs_set_kernel_events).
 void kernel_event_start(int kernel, hipStream_t s);
 void kernel_event_stop(int kernel, hipStream_t s);

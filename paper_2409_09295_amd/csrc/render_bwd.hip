@@ -115,7 +115,8 @@ __device__ __forceinline__ uint32_t stage_splat(uint32_t g, uint32_t n, uint32_t
   return reach;
 }
 
-template <int PPL, bool Q>
+// SPL: splats each thread stages per LDS batch (1 or 2).
+template <int PPL, int SPL, bool Q>
 __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     ViewTable vt, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
     const uint32_t* __restrict__ order,
@@ -124,9 +125,7 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     const uint32_t* __restrict__ n_contrib, uint32_t n_gauss, float* __restrict__ grad2d,
     uint32_t* __restrict__ counter) {
   constexpr int NT = kBlock / PPL;
-  // splats staged per batch: with one wavefront per tile (PPL 4) a smaller
-  // batch halves the LDS per workgroup, so twice as many fit on a CU
-  constexpr int kStage = PPL == 4 ? 128 : 256;
+  constexpr int kStage = SPL * NT;   // splats staged per batch
   constexpr int kPerThread = kStage / NT;
   constexpr int kWords = kStage / 64;
   __shared__ StagedSplat s_splat[kStage];
@@ -639,22 +638,22 @@ void launch_project_bwd(const gs_gaussians& g, const gs_camera* cams, int V, con
   }
 }
 
-template <int P>
+template <int P, int S>
 void launch_bwd(int schedule, const gs_bins& bins, const ViewTable& vt, const float2* xy,
                 const float4* co, const float4* rd, float3 bg, const float* dL_dimage,
                 const float* final_T, const uint32_t* n_contrib, uint32_t n_gauss,
                 float* grad2d, hipStream_t s) {
-  const int resident = schedule == GS_SCHEDULE_PERSISTENT
-                           ? resident_workgroups((const void*)render_bwd_kernel<P, true>,
+  const int resident = schedule >= GS_SCHEDULE_PERSISTENT
+                           ? resident_workgroups((const void*)render_bwd_kernel<P, S, true>,
                                                  kBlock / P)
                            : 0;
   const TileSchedule sc = tile_schedule(schedule, bins, GS_QUEUE_BWD, vt.n_tiles, resident);
   if (sc.counter)
-    hipLaunchKernelGGL((render_bwd_kernel<P, true>), dim3(sc.grid), dim3(kBlock / P), 0, s, vt,
+    hipLaunchKernelGGL((render_bwd_kernel<P, S, true>), dim3(sc.grid), dim3(kBlock / P), 0, s, vt,
                        bins.ranges, bins.values, sc.order, xy, co, rd, bg, dL_dimage, final_T,
                        n_contrib, n_gauss, grad2d, sc.counter);
   else
-    hipLaunchKernelGGL((render_bwd_kernel<P, false>), dim3(sc.grid), dim3(kBlock / P), 0, s, vt,
+    hipLaunchKernelGGL((render_bwd_kernel<P, S, false>), dim3(sc.grid), dim3(kBlock / P), 0, s, vt,
                        bins.ranges, bins.values, sc.order, xy, co, rd, bg, dL_dimage, final_T,
                        n_contrib, n_gauss, grad2d, nullptr);
 }
@@ -680,16 +679,21 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
     const auto* rd = reinterpret_cast<const float4*>(p.rgb_depth);
     const int ppl = tuning(GS_TUNE_BWD_PIXELS_PER_LANE);
     const int sched = tuning(GS_TUNE_BWD_SCHEDULE);
+    // splats per thread and batch: 128 per batch at one and two wavefronts
+    // per tile, 256 at four
+    const int spl = stage_per_thread(tuning(GS_TUNE_BWD_STAGE), ppl == 1 ? 1 : 2);
+#define GS_BWD(P, S)                                                                    \
+  launch_bwd<P, S>(sched, bins, vt, xy, co, rd, bg, dL_dimage, final_T, n_contrib, \
+                   (uint32_t)g.n, grad2d, s)
     kernel_event_start(GS_KERNEL_RENDER_BWD, s);
-    if (ppl == 4)
-      launch_bwd<4>(sched, bins, vt, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
-                    (uint32_t)g.n, grad2d, s);
-    else if (ppl == 2)
-      launch_bwd<2>(sched, bins, vt, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
-                    (uint32_t)g.n, grad2d, s);
-    else
-      launch_bwd<1>(sched, bins, vt, xy, co, rd, bg, dL_dimage, final_T, n_contrib,
-                    (uint32_t)g.n, grad2d, s);
+    if (ppl == 4) {
+      if (spl == 2) GS_BWD(4, 2); else GS_BWD(4, 1);
+    } else if (ppl == 2) {
+      if (spl == 2) GS_BWD(2, 2); else GS_BWD(2, 1);
+    } else {
+      if (spl == 2) GS_BWD(1, 2); else GS_BWD(1, 1);
+    }
+#undef GS_BWD
     kernel_event_stop(GS_KERNEL_RENDER_BWD, s);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;

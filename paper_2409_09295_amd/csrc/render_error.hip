@@ -200,7 +200,7 @@ hipError_t launch_render_error(const gs_projected& p, int64_t n, const gs_bins& 
   if (vt.n_tiles > 0 && n > 0) {
     // the backward's schedule: the same reverse walk over the same lists
     const int sched = tuning(GS_TUNE_BWD_SCHEDULE);
-    const int resident = sched == GS_SCHEDULE_PERSISTENT
+    const int resident = sched >= GS_SCHEDULE_PERSISTENT
                              ? resident_workgroups((const void*)render_error_kernel<true>, 64)
                              : 0;
     const TileSchedule sc = tile_schedule(sched, bins, GS_QUEUE_ERROR, vt.n_tiles, resident);

@@ -43,9 +43,10 @@ __device__ __forceinline__ uint32_t stage_splat(uint32_t g, const float2* __rest
 // share of the loss (written to tile_loss[tile]).  The fused pass at one
 // wavefront per tile is held to 72 VGPRs, seven wavefronts per SIMD (from
 // 74 and six; measured 3.5% faster, no spills; the other instances spill at
-// that bound and keep the compiler's choice).
-template <int PPL, bool L1, bool Q>
-__global__ __launch_bounds__(kBlock / PPL, PPL == 4 && L1 && !Q ? 7 : 1) void render_fwd_kernel(
+// that bound and keep the compiler's choice).  SPL: splats each thread
+// stages per LDS batch (1 or 2).
+template <int PPL, int SPL, bool L1, bool Q>
+__global__ __launch_bounds__(kBlock / PPL, PPL == 4 && SPL == 1 && L1 && !Q ? 7 : 1) void render_fwd_kernel(
     ViewTable vt, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ values,
     const uint32_t* __restrict__ order,
     const float2* __restrict__ xy, const float4* __restrict__ co, const float4* __restrict__ rd,
@@ -54,11 +55,10 @@ __global__ __launch_bounds__(kBlock / PPL, PPL == 4 && L1 && !Q ? 7 : 1) void re
     const float* __restrict__ target, float* __restrict__ dL, float* __restrict__ tile_loss,
     uint32_t* __restrict__ counter) {
   constexpr int NT = kBlock / PPL;
-  // splats staged per batch: with one wavefront per tile (PPL 4), one splat
-  // per lane (a smaller batch takes less LDS per workgroup, and a tile whose
-  // pixels all terminate early stages fewer splats it never walks; 64 was
-  // measured 4.5% faster than 128)
-  constexpr int kStage = PPL == 4 ? 64 : 256;
+  // splats staged per batch (a smaller batch takes less LDS per workgroup,
+  // and a tile whose pixels all terminate early stages fewer splats it
+  // never walks)
+  constexpr int kStage = SPL * NT;
   constexpr int kPerThread = kStage / NT;
   constexpr int kWords = kStage / 64;
   __shared__ StagedSplat s_splat[kStage];
@@ -267,22 +267,22 @@ hipError_t noalloc_scratch(float** out) {
 }
 
 namespace {
-template <int P, bool L>
+template <int P, int S, bool L>
 void launch_fwd(int schedule, const gs_bins& bins, const ViewTable& vt, const float2* xy,
                 const float4* co, const float4* rd, float3 bg, float* image, float* final_T,
                 uint32_t* n_contrib, float* depth, const float* target, float* dL,
                 float* tile_loss, hipStream_t s) {
-  const int resident = schedule == GS_SCHEDULE_PERSISTENT
-                           ? resident_workgroups((const void*)render_fwd_kernel<P, L, true>,
+  const int resident = schedule >= GS_SCHEDULE_PERSISTENT
+                           ? resident_workgroups((const void*)render_fwd_kernel<P, S, L, true>,
                                                  kBlock / P)
                            : 0;
   const TileSchedule sc = tile_schedule(schedule, bins, GS_QUEUE_FWD, vt.n_tiles, resident);
   if (sc.counter)
-    hipLaunchKernelGGL((render_fwd_kernel<P, L, true>), dim3(sc.grid), dim3(kBlock / P), 0, s, vt,
+    hipLaunchKernelGGL((render_fwd_kernel<P, S, L, true>), dim3(sc.grid), dim3(kBlock / P), 0, s, vt,
                        bins.ranges, bins.values, sc.order, xy, co, rd, bg, image, final_T,
                        n_contrib, depth, target, dL, tile_loss, sc.counter);
   else
-    hipLaunchKernelGGL((render_fwd_kernel<P, L, false>), dim3(sc.grid), dim3(kBlock / P), 0, s,
+    hipLaunchKernelGGL((render_fwd_kernel<P, S, L, false>), dim3(sc.grid), dim3(kBlock / P), 0, s,
                        vt, bins.ranges, bins.values, sc.order, xy, co, rd, bg, image, final_T,
                        n_contrib, depth, target, dL, tile_loss, nullptr);
 }
@@ -298,18 +298,28 @@ hipError_t launch_render_fwd(const gs_projected& p, const gs_bins& bins, const V
   const auto* rd = reinterpret_cast<const float4*>(p.rgb_depth);
   const int ppl = tuning(GS_TUNE_FWD_PIXELS_PER_LANE);
   const int sched = tuning(GS_TUNE_FWD_SCHEDULE);
+  // splats per thread and batch: 64 per batch at one wavefront per tile was
+  // measured 4.5% faster than 128; 256 at two and four wavefronts
+  const int spl = stage_per_thread(tuning(GS_TUNE_FWD_STAGE), ppl == 2 ? 2 : 1);
   const bool l1 = target != nullptr;
-#define GS_FWD(P, L)                                                                          \
-  launch_fwd<P, L>(sched, bins, vt, xy, co, rd, bg, image, final_T, n_contrib, depth, target, \
-                   dL, tile_loss, s)
+#define GS_FWD(P, S, L)                                                                          \
+  launch_fwd<P, S, L>(sched, bins, vt, xy, co, rd, bg, image, final_T, n_contrib, depth, target, \
+                      dL, tile_loss, s)
+#define GS_FWD_PPL(P)                                     \
+  if (spl == 2) {                                         \
+    if (l1) GS_FWD(P, 2, true); else GS_FWD(P, 2, false); \
+  } else {                                                \
+    if (l1) GS_FWD(P, 1, true); else GS_FWD(P, 1, false); \
+  }
   kernel_event_start(GS_KERNEL_RENDER_FWD, s);
   if (ppl == 4) {
-    if (l1) GS_FWD(4, true); else GS_FWD(4, false);
+    GS_FWD_PPL(4)
   } else if (ppl == 2) {
-    if (l1) GS_FWD(2, true); else GS_FWD(2, false);
+    GS_FWD_PPL(2)
   } else {
-    if (l1) GS_FWD(1, true); else GS_FWD(1, false);
+    GS_FWD_PPL(1)
   }
+#undef GS_FWD_PPL
 #undef GS_FWD
   kernel_event_stop(GS_KERNEL_RENDER_FWD, s);
   if (l1 && loss)

@@ -44,9 +44,12 @@ GS_TUNE_FWD_PIXELS_PER_LANE = 0
 GS_TUNE_BWD_PIXELS_PER_LANE = 1
 GS_TUNE_FWD_SCHEDULE = 2
 GS_TUNE_BWD_SCHEDULE = 3
+GS_TUNE_FWD_STAGE = 4
+GS_TUNE_BWD_STAGE = 5
 GS_SCHEDULE_HEAVIEST_FIRST = 1
 GS_SCHEDULE_TILE_ID = 2
 GS_SCHEDULE_PERSISTENT = 3
+GS_SCHEDULE_PERSISTENT_HALF = 4
 GS_QUEUE_COUNTERS = 8
 GS_QUEUE_STRIDE = 32
 GS_QUEUE_WORDS = 1024

@@ -307,13 +307,15 @@ def test_memory_ledger_tracks_current_and_peak(gs):
 
 
 def test_tuning_keys_validate_and_reset(gs):
-    """Pixels per lane takes 1, 2 or 4 and tile schedules their three
-    GS_SCHEDULE_* values; 0 restores each key's default; anything else is
-    rejected and leaves the value as it was.  The header's constants match
+    """Pixels per lane takes 1, 2 or 4, tile schedules their four
+    GS_SCHEDULE_* values and staging batches 1 or 2 splats per thread; 0
+    restores each key's default; anything else is rejected and leaves the
+    value as it was.  The header's constants match
     the binding's."""
     header = open(os.path.join(ROOT, "include", "gs.h")).read()
     for name in ("GS_TUNE_FWD_SCHEDULE", "GS_TUNE_BWD_SCHEDULE", "GS_SCHEDULE_HEAVIEST_FIRST",
-                 "GS_SCHEDULE_TILE_ID", "GS_SCHEDULE_PERSISTENT", "GS_QUEUE_WORDS",
+                 "GS_SCHEDULE_TILE_ID", "GS_SCHEDULE_PERSISTENT", "GS_SCHEDULE_PERSISTENT_HALF",
+                 "GS_TUNE_FWD_STAGE", "GS_TUNE_BWD_STAGE", "GS_QUEUE_WORDS",
                  "GS_QUEUE_COUNTERS", "GS_QUEUE_STRIDE"):
         m = re.search(rf"\b{name}\s*=\s*(\d+)", header)
         assert m and int(m.group(1)) == getattr(gs, name), name
@@ -322,7 +324,7 @@ def test_tuning_keys_validate_and_reset(gs):
             assert gs.gs_get_tuning(key) == gs.GS_SCHEDULE_HEAVIEST_FIRST
             gs.gs_set_tuning(key, gs.GS_SCHEDULE_PERSISTENT)
             assert gs.gs_get_tuning(key) == gs.GS_SCHEDULE_PERSISTENT
-            for bad in (-1, 4, 7):
+            for bad in (-1, 5, 7):
                 with pytest.raises(gs.GsError):
                     gs.gs_set_tuning(key, bad)
             assert gs.gs_get_tuning(key) == gs.GS_SCHEDULE_PERSISTENT
@@ -335,9 +337,20 @@ def test_tuning_keys_validate_and_reset(gs):
             assert gs.gs_get_tuning(key) == 4
             gs.gs_set_tuning(key, 0)
             assert gs.gs_get_tuning(key) == 1
+        gs.gs_set_tuning(gs.GS_TUNE_FWD_SCHEDULE, gs.GS_SCHEDULE_PERSISTENT_HALF)
+        assert gs.gs_get_tuning(gs.GS_TUNE_FWD_SCHEDULE) == gs.GS_SCHEDULE_PERSISTENT_HALF
+        for key in (gs.GS_TUNE_FWD_STAGE, gs.GS_TUNE_BWD_STAGE):
+            assert gs.gs_get_tuning(key) == 0          # the kernels' own default
+            gs.gs_set_tuning(key, 2)
+            for bad in (-1, 3, 64):
+                with pytest.raises(gs.GsError):
+                    gs.gs_set_tuning(key, bad)
+            assert gs.gs_get_tuning(key) == 2
+            gs.gs_set_tuning(key, 0)
+            assert gs.gs_get_tuning(key) == 0
         with pytest.raises(gs.GsError):
-            gs.gs_set_tuning(gs.GS_TUNE_BWD_SCHEDULE + 1, 1)
+            gs.gs_set_tuning(gs.GS_TUNE_BWD_STAGE + 1, 1)
         assert gs.gs_get_tuning(99) < 0
     finally:
-        for key in range(4):
+        for key in range(6):
             gs.gs_set_tuning(key, 0)

@@ -218,21 +218,29 @@ def _render_gpu(gs, sp, cams, bg=(0.0, 0.0, 0.0)):
 def ppl_setting(gs, request):
     """Runs a test under a (forward, backward) pixels-per-lane setting of the
     tile kernels and, when given, a tile schedule for both."""
-    fwd, bwd, *sched = request.param
+    fwd, bwd, *rest = request.param
+    sched = rest[0] if rest else 0
+    stage = rest[1] if len(rest) > 1 else 0
     gs.gs_set_tuning(gs.GS_TUNE_FWD_PIXELS_PER_LANE, fwd)
     gs.gs_set_tuning(gs.GS_TUNE_BWD_PIXELS_PER_LANE, bwd)
     for key in (gs.GS_TUNE_FWD_SCHEDULE, gs.GS_TUNE_BWD_SCHEDULE):
-        gs.gs_set_tuning(key, sched[0] if sched else 0)
+        gs.gs_set_tuning(key, sched)
+    for key in (gs.GS_TUNE_FWD_STAGE, gs.GS_TUNE_BWD_STAGE):
+        gs.gs_set_tuning(key, stage)
     yield request.param
     for key in (gs.GS_TUNE_FWD_PIXELS_PER_LANE, gs.GS_TUNE_BWD_PIXELS_PER_LANE,
-                gs.GS_TUNE_FWD_SCHEDULE, gs.GS_TUNE_BWD_SCHEDULE):
+                gs.GS_TUNE_FWD_SCHEDULE, gs.GS_TUNE_BWD_SCHEDULE, gs.GS_TUNE_FWD_STAGE,
+                gs.GS_TUNE_BWD_STAGE):
         gs.gs_set_tuning(key, 0)
 
 
-# one workgroup per tile (heaviest first: the default; tile id order), and
-# persistent workgroups drawing tiles from a counter
-_HF, _ID, _PS = 1, 2, 3
-PPL_SETTINGS = [(1, 1), (2, 2), (4, 4), (4, 4, _ID), (1, 1, _PS), (2, 2, _PS), (4, 4, _PS)]
+# (forward, backward pixels per lane[, tile schedule[, splats staged per
+# thread]]): one workgroup per tile (heaviest first: the default; tile id
+# order), persistent workgroups drawing tiles from counters (as many as fit,
+# or half), and both LDS batch sizes
+_HF, _ID, _PS, _PH = 1, 2, 3, 4
+PPL_SETTINGS = [(1, 1), (2, 2), (4, 4), (4, 4, _ID), (1, 1, _PS), (2, 2, _PS), (4, 4, _PS),
+                (4, 4, _HF, 2), (4, 4, _HF, 1), (2, 2, _HF, 1), (1, 1, _PH, 2)]
 
 
 @pytest.mark.parametrize("ppl_setting", PPL_SETTINGS, indirect=True)

@@ -350,14 +350,15 @@ def test_autotuner_caches_its_choice(gs, tmp_path):
     try:
         a = autotune.tune(step, cache=cache, reps=1)
         assert not a["cached"] and a["fwd_ppl"] in autotune.CHOICES and a["bwd_ppl"] in autotune.CHOICES
-        assert len(a["table"]) == 2 * len(autotune.CHOICES) * len(autotune.SCHEDULES)
+        assert len(a["table"]) == 2 * len(autotune.CHOICES) * len(autotune.STAGES) * len(autotune.SCHEDULES)
+        assert gs.gs_get_tuning(gs.GS_TUNE_BWD_STAGE) == a["bwd_stage"]
         assert gs.gs_get_tuning(gs.GS_TUNE_FWD_PIXELS_PER_LANE) == a["fwd_ppl"]
         assert gs.gs_get_tuning(gs.GS_TUNE_FWD_SCHEDULE) == a["fwd_schedule"]
         assert gs.gs_get_tuning(gs.GS_TUNE_BWD_SCHEDULE) == a["bwd_schedule"]
         autotune.apply(0, 0)
         b = autotune.tune(step, cache=cache)
         assert b["cached"]
-        for k in ("fwd_ppl", "bwd_ppl", "fwd_schedule", "bwd_schedule"):
+        for k in ("fwd_ppl", "bwd_ppl", "fwd_schedule", "bwd_schedule", "fwd_stage", "bwd_stage"):
             assert b[k] == a[k], k
         assert gs.gs_get_tuning(gs.GS_TUNE_BWD_SCHEDULE) == a["bwd_schedule"]
     finally:
