@@ -150,9 +150,10 @@ def _cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def _traffic():
+def _traffic(variant: str):
     """HBM bytes per launch of the reverse tile walk from the committed
-    counter summary, or None when the kernel's sources changed since."""
+    counter summary, or None when the kernel's sources changed since or the
+    summary was taken on another tuned variant of it."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -164,12 +165,18 @@ def _traffic():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_sha256") != h.hexdigest():
+    if vals.get("source_sha256") != h.hexdigest() or vals.get("kernel_variant") != variant:
         return None
     try:
         return float(vals["fetch_bytes"]) + float(vals["write_bytes"])
     except (KeyError, ValueError):
         return None
+
+
+def _bwd_variant(tuned) -> str:
+    """The tuned backward tile kernel, as the traffic summary names it."""
+    return (f"ppl={tuned['bwd_ppl']} stage={tuned.get('bwd_stage')} "
+            f"schedule={tuned.get('bwd_schedule_name')}")
 
 
 def _time_batched(step, steps, warmup):
@@ -372,7 +379,7 @@ def main():
         achieved = pairs_bwd * per / (kms[dom] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                 "unit": "T VALU lane-ops/s", "frac": achieved / VALU_PEAK_TOPS,
-                "traffic": _traffic() if dom == "render_bwd" else None,
+                "traffic": _traffic(_bwd_variant(tuned)) if dom == "render_bwd" else None,
                 "units": pairs_bwd, "unit_name": "walked (pixel, splat) pairs",
                 "per_unit": per, "blend_fraction": blend_frac, "kernel_ms": kms[dom]}
     else:

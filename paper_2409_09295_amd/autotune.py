@@ -9,7 +9,9 @@ persistent workgroups, as many as the GPU holds or half that, drawing tiles
 heaviest first from counters) on the real step (eager launches, HIP events,
 optimiser state restored afterwards), keeps the fastest and caches the
 choice in a JSON file keyed by device name, library version and workload
-shape.  Every setting computes the same result (up to the float32 order of
+shape (settings within 1% of the fastest count as tied and the one closest
+to the kernel's defaults wins, so that noise does not flip the choice).
+Every setting computes the same result (up to the float32 order of
 gradient atomics), so tuning changes speed only.
 """
 from __future__ import annotations
@@ -103,6 +105,22 @@ def _label(kernel: str, ppl: int, stage: int, schedule: str) -> str:
     return f"{kernel}{ppl}s{stage}_{schedule}"
 
 
+# Each kernel's own staging batch per pixels-per-lane setting (the library
+# default for GS_TUNE_*_STAGE = 0).
+DEFAULT_STAGE = {"fwd": {1: 1, 2: 2, 4: 1}, "bwd": {1: 1, 2: 2, 4: 2}}
+TIE = 0.01   # settings within 1% of the fastest count as tied
+
+
+def _pick(settings, table, kernel: str):
+    """The fastest setting; among those within TIE of it, the one that
+    departs least from the kernel's defaults (its staging batch, heaviest
+    first), so that run-to-run noise does not flip the choice."""
+    best = min(table[_label(kernel, *c)] for c in settings)
+    tied = [c for c in settings if table[_label(kernel, *c)] <= best * (1.0 + TIE)]
+    return min(tied, key=lambda c: ((c[1] != DEFAULT_STAGE[kernel][c[0]]) +
+                                    (c[2] != "heaviest_first"), table[_label(kernel, *c)]))
+
+
 def tune(step, cache: Optional[str] = None, force: bool = False, reps: int = 3) -> Dict:
     """Pick and apply the fastest setting for ``step`` (a replay.BatchedStep).
     Returns {"fwd_ppl", "bwd_ppl", "fwd_stage", "bwd_stage", "fwd_schedule",
@@ -122,8 +140,8 @@ def tune(step, cache: Optional[str] = None, force: bool = False, reps: int = 3) 
             step, p, 1, reps, fwd_schedule=SCHEDULES[name], fwd_stage=st)
         _, table[_label("bwd", p, st, name)] = time_config(
             step, 1, p, reps, bwd_schedule=SCHEDULES[name], bwd_stage=st)
-    bf = min(settings, key=lambda c: table[_label("fwd", *c)])
-    bb = min(settings, key=lambda c: table[_label("bwd", *c)])
+    bf = _pick(settings, table, "fwd")
+    bb = _pick(settings, table, "bwd")
     best = {"fwd_ppl": bf[0], "bwd_ppl": bb[0], "fwd_stage": bf[1], "bwd_stage": bb[1],
             "fwd_schedule": SCHEDULES[bf[2]], "bwd_schedule": SCHEDULES[bb[2]],
             "fwd_schedule_name": bf[2], "bwd_schedule_name": bb[2],
