@@ -577,6 +577,11 @@ __global__ __launch_bounds__(256) void zero_visible_kernel(const int32_t* __rest
   for (int k = 0; k < 9; ++k) d[k] = 0.0f;
 }
 
+// An empty map under GS_BWD_OVERWRITE: the pose gradient is zero.
+__global__ __launch_bounds__(256) void zero_f32_kernel(float* __restrict__ p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0f;
+}
+
 // One workgroup per (view, component): strided float64 sum over the
 // per-workgroup partials, then a tree reduction in LDS (fixed order).
 __global__ __launch_bounds__(256) void pose_reduce_kernel(const double* __restrict__ pose_part,
@@ -697,7 +702,11 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
     kernel_event_stop(GS_KERNEL_RENDER_BWD, s);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (g.n == 0) return hipSuccess;
+  if (g.n == 0) {   // nothing to chain; an overwritten pose gradient is zero
+    if (!(flags & GS_BWD_NO_POSE) && (flags & GS_BWD_OVERWRITE) && vt.n_views > 0)
+      hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(256), 0, s, grads.xi, vt.n_views * 6);
+    return hipGetLastError();
+  }
   const int64_t nblocks = proj_bwd_blocks(g.n, vt.n_views);
   const dim3 grid((unsigned)nblocks), block(256);
   kernel_event_start(GS_KERNEL_PROJECT_BWD, s);

@@ -607,3 +607,83 @@ def test_l1_loss_grad(gs):
         np.testing.assert_allclose(np_(dl)[3 * off:3 * (off + w * h)], g.reshape(-1), rtol=1e-6)
         off += w * h
     np.testing.assert_allclose(float(np_(loss)[0]), L_ref, rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# degenerate batches
+# ---------------------------------------------------------------------------
+
+def _degenerate_workload(case, max_views):
+    rng = np.random.default_rng(77)
+    if case == "thin_views":
+        # 1x1, 17x1 and 1x33 images: tiles that are almost all outside the image
+        g = scenes.random_cloud(400, 1, 3, box=((-0.5, 0.5), (-0.5, 0.5), (2, 3)), log_scale_mu=-2.0)
+        cams = [scenes.pinhole(1, 1, 2.0), scenes.pinhole(17, 1, 15.0), scenes.pinhole(1, 33, 30.0)]
+    elif case == "max_views":
+        # as many views as one batch takes, each a small perturbed pinhole
+        g = scenes.random_cloud(600, 1, 4)
+        cams = [scenes.perturb_pose(scenes.pinhole(24, 16, 20.0), rng) for _ in range(max_views)]
+    elif case == "one_gaussian":
+        g = scenes.random_cloud(1, 3, 5, box=((-0.1, 0.1), (-0.1, 0.1), (2.5, 3)), log_scale_mu=-1.5)
+        cams = [scenes.pinhole(48, 40, 40.0)]
+    else:   # opaque_stack: clamped alphas, every pixel terminating early
+        g = scenes.random_cloud(300, 0, 6, box=((-0.3, 0.3), (-0.3, 0.3), (2, 4)), log_scale_mu=-1.0)
+        g.opacity_logits[:] = 8.0
+        cams = [scenes.pinhole(64, 48, 60.0)]
+    targets = [np.zeros((3, c.height, c.width), np.float32) for c in cams]
+    return scenes.Workload(f"degenerate_{case}", g, cams, targets, bg=(0.25, 0.5, 0.75))
+
+
+@pytest.mark.parametrize("case", ["thin_views", "max_views", "one_gaussian", "opaque_stack"])
+def test_degenerate_batches(gs, case):
+    """Images, n_contrib and every gradient against the oracle on batches at
+    the edges of the method: images a pixel wide, the largest view count a
+    batch takes, a single Gaussian, and a stack of clamped (alpha = 0.99)
+    splats under which every pixel stops early."""
+    wl = _degenerate_workload(case, gs.GS_MAX_VIEWS)
+    out, res = _grad_parity(gs, wl, seed=11)
+    for v, r in enumerate(res["views"]):
+        nc = np_(out["views"].split_maps(out["nc"])[v])
+        m = ~r["mask"]
+        np.testing.assert_array_equal(nc[m], r["n_contrib"][m])
+    for v, r in enumerate(res["views"]):
+        T = np_(out["views"].split_maps(out["T"])[v])
+        m = ~r["mask"]
+        np.testing.assert_allclose(T[m], r["T_final"][m], rtol=1e-3, atol=1e-7)
+    if case == "opaque_stack":   # most pixels stop just before T would fall below 1e-4
+        assert (np_(out["T"]) < 1e-3).mean() > 0.5
+
+
+def test_empty_map_renders_background(gs):
+    """No Gaussians at all: the image is the background, T = 1 and
+    n_contrib = 0 everywhere, and the backward adds nothing to the pose
+    gradient, or writes zero under GS_BWD_OVERWRITE (closed form; the oracle
+    is not needed)."""
+    from paper_2409_09295_amd.rasterizer import Rasterizer
+    g0 = scenes.random_cloud(1, 0, 1)
+    empty = scenes.GaussianMap(g0.means[:, :0].copy(), g0.log_scales[:, :0].copy(),
+                               g0.quats[:, :0].copy(), g0.opacity_logits[:0].copy(),
+                               g0.sh[:, :, :0].copy(), 0)
+    cams = [scenes.pinhole(40, 30, 30.0), scenes.pinhole(17, 5, 12.0)]
+    g = gs.Gaussians.from_map(empty)
+    views = gs.Views(cams)
+    rast = Rasterizer(g.n, views)
+    bg = (0.25, 0.5, 0.75)
+    img = np_(rast.forward(g, bg))
+    P = views.n_pixels
+    off = 0
+    for (w, h) in views.sizes:
+        blk = img[3 * off:3 * (off + w * h)].reshape(3, h, w)
+        for ch in range(3):
+            assert (blk[ch] == np.float32(bg[ch])).all()
+        off += w * h
+    assert (np_(rast.final_T) == 1.0).all() and (np_(rast.n_contrib) == 0).all()
+    grads = gs.Grads.zeros_like(g, views.n_views)
+    dl = torch.ones(3 * P, device=DEV)
+    grads.xi.fill_(7.0)
+    rast.backward(g, dl, grads, 0, bg)                      # accumulate: unchanged
+    torch.cuda.synchronize()
+    assert (np_(grads.xi) == 7.0).all()
+    rast.backward(g, dl, grads, gs.GS_BWD_OVERWRITE, bg)    # overwrite: zero
+    torch.cuda.synchronize()
+    assert (np_(grads.xi) == 0.0).all()
