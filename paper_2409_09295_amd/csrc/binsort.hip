@@ -430,16 +430,18 @@ __global__ __launch_bounds__(256) void bin_scan_down_kernel(const uint32_t* __re
     }
     st += c[q];
   }
-  // queue the long lists: one atomic per wavefront and item
+  // queue the long lists: one atomic per wavefront and item; lane 0's
+  // reservation reaches the other lanes through LDS (every lane reads what
+  // lane 0 wrote, whatever the compiler does with the lanes' control flow)
+  __shared__ uint32_t s_qbase[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int t = t0 + q;
     const bool lng = ok && t < n_tiles && c[q] > (uint32_t)kSegShort;
     const uint64_t m = __ballot(lng);
     if (m) {
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(n_long, (uint32_t)__popcll(m));
-      base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+      if (lane == 0) s_qbase[w] = atomicAdd(n_long, (uint32_t)__popcll(m));
+      const uint32_t base = s_qbase[w];
       if (lng) long_list[base + (uint32_t)__popcll(m & ((uint64_t(1) << lane) - 1))] = (uint32_t)t;
     }
   }
