@@ -1130,7 +1130,11 @@ hipError_t nn_conv3x3(const gs_act* x1, const gs_act* x2, const gs_act* mask, co
   const auto* wp = static_cast<const uint16_t*>(w);
   if (cin % 8 == 0 && x1->c % 8 == 0) {
     const unsigned tiles = (unsigned)(x1->n * ((x1->h + PT - 1) / PT) * ((x1->w + PT - 1) / PT));
-    if (cout <= 32)
+    // 32 output channels per workgroup up to 32 channels, and also where
+    // 64-channel workgroups would number fewer than 1,024: twice the
+    // workgroups, and at 49 KB of LDS three fit a CU (72 KB: two); measured
+    // 3% faster on the forward pass of four 640x480 images
+    if (cout <= 32 || tiles * (unsigned)((cout + 63) / 64) < 1024u)
       hipLaunchKernelGGL((conv3x3_patch_kernel<32>), dim3(tiles, (unsigned)((cout + 31) / 32)),
                          dim3(256), 0, s, view(x1), view(x2), view(mask), x1->n, x1->h, x1->w, wp,
                          cout, cin, bias, relu, yp, ys, yo, yf, yf_stride);
