@@ -151,6 +151,42 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t x) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// x of another lane by DPP (0 where the source lane is out of its row).
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ float dpp_or_zero(float x) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, BANK_MASK, false));
+}
+
+// Sum over the 64 lanes of a wavefront; the total lands in lane 63.
+__device__ __forceinline__ float wave_sum_to_lane63(float x) {
+  x += dpp_or_zero<0xb1, 0xf, 0xf>(x);   // quad_perm [1,0,3,2]
+  x += dpp_or_zero<0x4e, 0xf, 0xf>(x);   // quad_perm [2,3,0,1]
+  x += dpp_or_zero<0x124, 0xf, 0xf>(x);  // row_ror:4
+  x += dpp_or_zero<0x128, 0xf, 0xf>(x);  // row_ror:8 -> every lane holds its row sum
+  x += dpp_or_zero<0x142, 0xa, 0xf>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_or_zero<0x143, 0xc, 0xf>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+// Stages splat g (index view * n + Gaussian into the [V][n] splat arrays,
+// also the index of its accumulator in the [V][n][9] gradient buffer) as
+// the tile kernels' LDS record and returns the quadrants of the tile whose
+// top-left pixel is (tx0, ty0) it can reach.
+__device__ __forceinline__ uint32_t stage_splat(uint32_t g, const float2* __restrict__ xy,
+                                                const float4* __restrict__ co,
+                                                const float4* __restrict__ rd, int tx0, int ty0,
+                                                int W, int H, StagedSplat& out) {
+  const float2 m = xy[g];
+  const float4 c = co[g];
+  const float4 r = rd[g];
+  const uint32_t reach = quadrant_mask(m.x, m.y, c.x, c.y, c.z, c.w, tx0, ty0, W, H);
+  out.geo = make_float4(m.x, m.y, -0.5f * kLog2e * c.x, -kLog2e * c.y);
+  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.x, r.y);
+  out.ext = make_float4(r.z, __uint_as_float(reach), r.w, __uint_as_float(g));
+  return reach;
+}
+
 // Blending decision shared bit-for-bit by the forward and backward kernels.
 // The exponent (log2 units) at pixel (px, py) is
 //   power = a dx^2 + dy (c dy + b dx),   dx = px - u, dy = py - v,

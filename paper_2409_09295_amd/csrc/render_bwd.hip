@@ -25,23 +25,6 @@ namespace gsmi {
 
 namespace {
 
-template <int CTRL, int ROW_MASK, int BANK_MASK>
-__device__ __forceinline__ float dpp_or_zero(float x) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, BANK_MASK, false));
-}
-
-// Sum over the 64 lanes of a wavefront; the total lands in lane 63.
-__device__ __forceinline__ float wave_sum_to_lane63(float x) {
-  x += dpp_or_zero<0xb1, 0xf, 0xf>(x);   // quad_perm [1,0,3,2]
-  x += dpp_or_zero<0x4e, 0xf, 0xf>(x);   // quad_perm [2,3,0,1]
-  x += dpp_or_zero<0x124, 0xf, 0xf>(x);  // row_ror:4
-  x += dpp_or_zero<0x128, 0xf, 0xf>(x);  // row_ror:8 -> every lane holds its row sum
-  x += dpp_or_zero<0x142, 0xa, 0xf>(x);  // row_bcast:15 into rows 1 and 3
-  x += dpp_or_zero<0x143, 0xc, 0xf>(x);  // row_bcast:31 into rows 2 and 3
-  return x;
-}
-
 __device__ __forceinline__ float lane63(float x) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
@@ -98,23 +81,6 @@ __device__ __forceinline__ Reduced9 wave_reduce9(float v0, float v1, float v2, f
   return r;
 }
 
-// Stages splat `g` (index view * n + Gaussian into the [V][n] splat arrays,
-// also the index of its accumulator in the [V][n][9] gradient buffer).
-__device__ __forceinline__ uint32_t stage_splat(uint32_t g, uint32_t n, uint32_t n_views,
-                                                const float2* __restrict__ xy,
-                                                const float4* __restrict__ co,
-                                                const float4* __restrict__ rd, int tx0, int ty0,
-                                                int W, int H, StagedSplat& out) {
-  const float2 m = xy[g];
-  const float4 c = co[g];
-  const float4 r = rd[g];
-  const uint32_t reach = quadrant_mask(m.x, m.y, c.x, c.y, c.z, c.w, tx0, ty0, W, H);
-  out.geo = make_float4(m.x, m.y, -0.5f * kLog2e * c.x, -kLog2e * c.y);
-  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.x, r.y);
-  out.ext = make_float4(r.z, __uint_as_float(reach), r.w, __uint_as_float(g));
-  return reach;
-}
-
 // SPL: splats each thread stages per LDS batch (1 or 2).
 template <int PPL, int SPL, bool Q>
 __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
@@ -122,7 +88,7 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
     const uint32_t* __restrict__ order,
     const float2* __restrict__ xy, const float4* __restrict__ co, const float4* __restrict__ rd,
     float3 bg, const float* __restrict__ dL_dimage, const float* __restrict__ final_T,
-    const uint32_t* __restrict__ n_contrib, uint32_t n_gauss, float* __restrict__ grad2d,
+    const uint32_t* __restrict__ n_contrib, float* __restrict__ grad2d,
     uint32_t* __restrict__ counter) {
   constexpr int NT = kBlock / PPL;
   constexpr int kStage = SPL * NT;   // splats staged per batch
@@ -215,7 +181,7 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
         const int64_t k = bstart + slot;
         uint32_t reach = 0;
         if (k < bend)
-          reach = stage_splat(values[s + (uint32_t)k], n_gauss, (uint32_t)vt.n_views, xy, co, rd,
+          reach = stage_splat(values[s + (uint32_t)k], xy, co, rd,
                               tx * kTile, ty * kTile, vi.width, vi.height, s_splat[slot]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -646,7 +612,7 @@ void launch_project_bwd(const gs_gaussians& g, const gs_camera* cams, int V, con
 template <int P, int S>
 void launch_bwd(int schedule, const gs_bins& bins, const ViewTable& vt, const float2* xy,
                 const float4* co, const float4* rd, float3 bg, const float* dL_dimage,
-                const float* final_T, const uint32_t* n_contrib, uint32_t n_gauss,
+                const float* final_T, const uint32_t* n_contrib,
                 float* grad2d, hipStream_t s) {
   const int resident = schedule >= GS_SCHEDULE_PERSISTENT
                            ? resident_workgroups((const void*)render_bwd_kernel<P, S, true>,
@@ -656,11 +622,11 @@ void launch_bwd(int schedule, const gs_bins& bins, const ViewTable& vt, const fl
   if (sc.counter)
     hipLaunchKernelGGL((render_bwd_kernel<P, S, true>), dim3(sc.grid), dim3(kBlock / P), 0, s, vt,
                        bins.ranges, bins.values, sc.order, xy, co, rd, bg, dL_dimage, final_T,
-                       n_contrib, n_gauss, grad2d, sc.counter);
+                       n_contrib, grad2d, sc.counter);
   else
     hipLaunchKernelGGL((render_bwd_kernel<P, S, false>), dim3(sc.grid), dim3(kBlock / P), 0, s, vt,
                        bins.ranges, bins.values, sc.order, xy, co, rd, bg, dL_dimage, final_T,
-                       n_contrib, n_gauss, grad2d, nullptr);
+                       n_contrib, grad2d, nullptr);
 }
 
 }  // namespace
@@ -687,9 +653,8 @@ hipError_t launch_render_bwd(const gs_gaussians& g, const gs_projected& p, const
     // splats per thread and batch: 128 per batch at one and two wavefronts
     // per tile, 256 at four
     const int spl = stage_per_thread(tuning(GS_TUNE_BWD_STAGE), ppl == 1 ? 1 : 2);
-#define GS_BWD(P, S)                                                                    \
-  launch_bwd<P, S>(sched, bins, vt, xy, co, rd, bg, dL_dimage, final_T, n_contrib, \
-                   (uint32_t)g.n, grad2d, s)
+#define GS_BWD(P, S) \
+  launch_bwd<P, S>(sched, bins, vt, xy, co, rd, bg, dL_dimage, final_T, n_contrib, grad2d, s)
     kernel_event_start(GS_KERNEL_RENDER_BWD, s);
     if (ppl == 4) {
       if (spl == 2) GS_BWD(4, 2); else GS_BWD(4, 1);

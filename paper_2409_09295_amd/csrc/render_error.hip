@@ -20,37 +20,6 @@ namespace gsmi {
 
 namespace {
 
-template <int CTRL, int ROW_MASK, int BANK_MASK>
-__device__ __forceinline__ float dpp_or_zero(float x) {
-  return __int_as_float(
-      __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, BANK_MASK, false));
-}
-
-// Sum over the 64 lanes of a wavefront; the total lands in lane 63.
-__device__ __forceinline__ float wave_sum_to_lane63(float x) {
-  x += dpp_or_zero<0xb1, 0xf, 0xf>(x);   // quad_perm [1,0,3,2]
-  x += dpp_or_zero<0x4e, 0xf, 0xf>(x);   // quad_perm [2,3,0,1]
-  x += dpp_or_zero<0x124, 0xf, 0xf>(x);  // row_ror:4
-  x += dpp_or_zero<0x128, 0xf, 0xf>(x);  // row_ror:8 -> every lane holds its row sum
-  x += dpp_or_zero<0x142, 0xa, 0xf>(x);  // row_bcast:15 into rows 1 and 3
-  x += dpp_or_zero<0x143, 0xc, 0xf>(x);  // row_bcast:31 into rows 2 and 3
-  return x;
-}
-
-__device__ __forceinline__ uint32_t stage_splat(uint32_t g, const float2* __restrict__ xy,
-                                                const float4* __restrict__ co,
-                                                const float4* __restrict__ rd, int tx0, int ty0,
-                                                int W, int H, StagedSplat& out) {
-  const float2 m = xy[g];
-  const float4 c = co[g];
-  const float4 r = rd[g];
-  const uint32_t reach = quadrant_mask(m.x, m.y, c.x, c.y, c.z, c.w, tx0, ty0, W, H);
-  out.geo = make_float4(m.x, m.y, -0.5f * kLog2e * c.x, -kLog2e * c.y);
-  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.x, r.y);
-  out.ext = make_float4(r.z, __uint_as_float(reach), r.w, __uint_as_float(g));
-  return reach;
-}
-
 constexpr int kStage = 64;   // splats staged per batch: one per lane
 constexpr int kPPL = 4;      // pixels per lane: one wavefront covers the tile
 

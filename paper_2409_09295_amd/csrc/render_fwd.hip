@@ -24,21 +24,6 @@ static __device__ __align__(256) float scratch[GS_NOALLOC_MAX_TILES];
 
 namespace {
 
-// Stages splat g and returns the quadrants of the tile it can reach.
-__device__ __forceinline__ uint32_t stage_splat(uint32_t g, const float2* __restrict__ xy,
-                                                const float4* __restrict__ co,
-                                                const float4* __restrict__ rd, int tx0, int ty0,
-                                                int W, int H, StagedSplat& out) {
-  const float2 m = xy[g];
-  const float4 c = co[g];
-  const float4 r = rd[g];
-  const uint32_t reach = quadrant_mask(m.x, m.y, c.x, c.y, c.z, c.w, tx0, ty0, W, H);
-  out.geo = make_float4(m.x, m.y, -0.5f * kLog2e * c.x, -kLog2e * c.y);
-  out.app = make_float4(-0.5f * kLog2e * c.z, c.w, r.x, r.y);
-  out.ext = make_float4(r.z, __uint_as_float(reach), r.w, __uint_as_float(g));
-  return reach;
-}
-
 // L1: also the photometric L1 gradient against `target` and the tile's
 // share of the loss (written to tile_loss[tile]).  The fused pass at one
 // wavefront per tile is held to 72 VGPRs, seven wavefronts per SIMD (from
