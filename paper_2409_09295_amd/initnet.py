@@ -449,7 +449,7 @@ def train_and_compare(n_gauss: int = 200000, W: int = 128, H: int = 96, n_train:
 
 
 def main(argv=None) -> None:
-    """Train and judge the initialiser at a chosen size and print one JSON
+    """Train and evaluate the initialiser at a chosen size and print one JSON
     line; the defaults are the full-size run: 640 x 480, 5,000 training
     renders of a 1,000,000-Gaussian room, 500 held-out views."""
     import argparse
