@@ -78,6 +78,8 @@ def _args():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--retune", action="store_true", help="ignore the tuning cache")
     ap.add_argument("--no-v12", action="store_true", help="skip the 12-view (8 window + 4 past) line")
+    ap.add_argument("--no-initialiser", action="store_true",
+                    help="skip the initialisers' timing (cost volume, belief propagation, U-Net)")
     ap.add_argument("--no-mapping", action="store_true",
                     help="skip the mapping-loop overhead-memory measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -293,6 +295,36 @@ def main():
     except Exception as exc:   # reported, never fatal to the headline line
         selective = {"error": repr(exc)}
 
+    # ---------------- initialisers (Sec. III-A): the last of 8 rendered views ------------
+    init_ms = None
+    if not args.no_initialiser:
+        try:
+            from paper_2409_09295_amd import initnet
+            imgs = views.split_images(step.image)[:8]
+            kf = torch.stack([im.view(3, *im.shape[-2:]) for im in imgs]).clamp(0.0, 1.0).contiguous()
+            cams8 = wl.cams[:8]
+
+            def timed_ms(fn, reps=5):
+                fn()
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(reps):
+                    fn()
+                b.record()
+                torch.cuda.synchronize()
+                return a.elapsed_time(b) / reps
+
+            net = initnet.UNet(seed=args.seed)
+            one = kf[-1:].contiguous()
+            init_ms = {"keyframes": 8, "resolution": list(kf.shape[-1:-3:-1]),
+                       "cost_volume_wta": timed_ms(lambda: initnet.plain_depth(kf, cams8)),
+                       "cost_volume_bp": timed_ms(lambda: initnet.plain_depth(kf, cams8, method="bp")),
+                       "unet_forward": timed_ms(lambda: net.forward(one))}
+            del net, kf, one
+        except Exception as exc:   # reported, never fatal to the headline line
+            init_ms = {"error": repr(exc)}
+
     # algorithmic work of the reverse tile walk: list positions each pixel walks
     pairs_bwd = int(step.n_contrib.to(torch.int64).sum().item())
     n_visible = int((step.proj.radius > 0).sum().item())
@@ -437,6 +469,7 @@ def main():
         "roofline": roof,
         "hbm_kernels": hbm,
         "selective": selective,
+        "initialiser_ms": init_ms,
         "mapping_memory": memory,
         "cpu_baseline": cpu,
     }

@@ -20,7 +20,7 @@ def test_fastest_setting_wins_outside_the_tie_margin():
 
 
 def test_ties_resolve_to_the_kernel_defaults():
-    # within 1%: the backward's default batch at 4 pixels per lane is 2 splats
+    # within the margin: the backward's default batch at 4 pixels per lane is 2 splats
     t = _table("bwd", {(4, 1, "heaviest_first"): 0.700, (4, 2, "heaviest_first"): 0.705})
     assert A._pick(_settings(), t, "bwd") == (4, 2, "heaviest_first")
     # the forward's default at 4 pixels per lane is 1 splat; heaviest first beats persistent
