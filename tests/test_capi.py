@@ -354,3 +354,17 @@ def test_tuning_keys_validate_and_reset(gs):
     finally:
         for key in range(6):
             gs.gs_set_tuning(key, 0)
+
+
+def test_binding_constants_match_the_headers(gs):
+    """Every enum constant the Python binding re-declares has the header's
+    value (the binding marshals these numbers straight into the C ABI)."""
+    text = "".join(open(os.path.join(ROOT, "include", h)).read() for h in ("gs.h", "gs_nn.h"))
+    declared = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(GS_[A-Z0-9_]+)\s*=\s*(\d+)", text)}
+    defines = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(GS_[A-Z0-9_]+)\s+(\d+)", text)}
+    declared.update(defines)
+    bound = {k: v for k, v in vars(gs).items() if k.startswith("GS_") and isinstance(v, int)}
+    common = sorted(set(declared) & set(bound))
+    assert len(common) >= 20, common
+    for name in common:
+        assert bound[name] == declared[name], (name, bound[name], declared[name])

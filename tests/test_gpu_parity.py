@@ -687,3 +687,32 @@ def test_empty_map_renders_background(gs):
     rast.backward(g, dl, grads, gs.GS_BWD_OVERWRITE, bg)    # overwrite: zero
     torch.cuda.synchronize()
     assert (np_(grads.xi) == 0.0).all()
+
+
+def test_persistent_schedule_without_a_queue(gs):
+    """The persistent schedule needs the bins' counters; without a queue it
+    launches one workgroup per tile instead.  Both give the default
+    schedule's image, final T and n_contrib bit for bit."""
+    cams = BIN_CASES["ragged_multi_view"]
+    sp = scenes.random_splats(3000, cams, seed=43)
+    views, proj, bins, nk = _gpu_bins(gs, sp, cams)
+    P = views.n_pixels
+    N = sp.radius.shape[1]
+
+    def render(b):
+        out = [torch.empty(3 * P, device=DEV), torch.empty(P, device=DEV),
+               torch.empty(P, dtype=torch.int32, device=DEV)]
+        gs.gs_render_fwd(proj, N, b, views, (0.1, 0.2, 0.3), out[0], out[1], out[2])
+        torch.cuda.synchronize()
+        return out
+
+    ref = render(bins)
+    no_queue = gs.Bins(bins.keys, bins.values, bins.ranges, bins.n_keys, bins.capacity, bins.order, None)
+    try:
+        gs.gs_set_tuning(gs.GS_TUNE_FWD_SCHEDULE, gs.GS_SCHEDULE_PERSISTENT)
+        for b in (bins, no_queue):
+            for x, y in zip(render(b), ref):
+                torch.testing.assert_close(x, y, rtol=0, atol=0)
+        assert int(bins.queue.abs().sum().item()) == 0
+    finally:
+        gs.gs_set_tuning(gs.GS_TUNE_FWD_SCHEDULE, 0)
