@@ -6,9 +6,9 @@
 // per pixel, one label per lane, so a pixel's data costs and messages are one
 // 256-byte coalesced row each.  A message is the lower envelope of the
 // sender's costs under the cone lam |l - l'|, computed as a prefix minimum of
-// h(l) - lam l and a suffix minimum of h(l) + lam l across the lanes (six
-// shuffle steps each) instead of the 64 x 64 minimum, then cut at
-// min h + trunc and shifted to a zero minimum.  Iterations are synchronous
+// h(l) - lam l and a suffix minimum of h(l) + lam l across the lanes (DPP row
+// shifts and broadcasts, no LDS round trips) instead of the 64 x 64 minimum,
+// then cut at min h + trunc and shifted to a zero minimum.  Iterations are synchronous
 // (every message of an iteration from the previous iteration's), with two
 // message buffers in turn.
 #include "gs_internal.h"
@@ -20,24 +20,62 @@ namespace {
 
 constexpr int kL = 64;   // labels = hypotheses = lanes
 
+// x of another lane by DPP; lanes whose source lies outside the pattern
+// keep +inf (the identity of min)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_or_inf(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(INFINITY), __float_as_int(x), CTRL,
+                                                    ROW_MASK, 0xf, false));
+}
+
+// Minimum over the 64 lanes, in every lane: DPP within the 16-lane rows,
+// then the four row minima.
 __device__ __forceinline__ float wave_min(float x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x = fminf(x, __shfl_xor(x, d, 64));
+  x = fminf(x, dpp_or_inf<0xb1, 0xf>(x));    // quad_perm [1,0,3,2]
+  x = fminf(x, dpp_or_inf<0x4e, 0xf>(x));    // quad_perm [2,3,0,1]
+  x = fminf(x, dpp_or_inf<0x124, 0xf>(x));   // row_ror:4
+  x = fminf(x, dpp_or_inf<0x128, 0xf>(x));   // row_ror:8: every lane holds its row minimum
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+  return fminf(fminf(r0, r1), fminf(r2, r3));
+}
+
+// Inclusive minimum over lanes 0 .. lane (Hillis-Steele within the rows by
+// row shifts, then the previous rows' minima by row broadcasts).
+__device__ __forceinline__ float prefix_min(float x) {
+  x = fminf(x, dpp_or_inf<0x111, 0xf>(x));   // row_shr:1
+  x = fminf(x, dpp_or_inf<0x112, 0xf>(x));   // row_shr:2
+  x = fminf(x, dpp_or_inf<0x114, 0xf>(x));   // row_shr:4
+  x = fminf(x, dpp_or_inf<0x118, 0xf>(x));   // row_shr:8
+  x = fminf(x, dpp_or_inf<0x142, 0xa>(x));   // row_bcast:15 into rows 1 and 3
+  x = fminf(x, dpp_or_inf<0x143, 0xc>(x));   // row_bcast:31 into rows 2 and 3
   return x;
+}
+
+// Inclusive minimum over lanes lane .. 63: row shifts the other way, then
+// the later rows' minima (each row's first lane holds its row minimum).
+__device__ __forceinline__ float suffix_min(float x, int lane) {
+  x = fminf(x, dpp_or_inf<0x101, 0xf>(x));   // row_shl:1
+  x = fminf(x, dpp_or_inf<0x102, 0xf>(x));   // row_shl:2
+  x = fminf(x, dpp_or_inf<0x104, 0xf>(x));   // row_shl:4
+  x = fminf(x, dpp_or_inf<0x108, 0xf>(x));   // row_shl:8
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+  const float s2 = r3, s1 = fminf(r2, r3), s0 = fminf(r1, s1);
+  const int row = lane >> 4;
+  const float later = row == 0 ? s0 : row == 1 ? s1 : row == 2 ? s2 : INFINITY;
+  return fminf(x, later);
 }
 
 // min over l of h(l) + min(lam |l - l'|, trunc) for l' = this lane, shifted
 // so that its minimum over l' is 0.
 __device__ __forceinline__ float send(float h, int lane, float lam, float trunc) {
   const float fl = (float)lane * lam;
-  float a = h - fl, b = h + fl;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const float up = __shfl_up(a, d, 64);
-    const float dn = __shfl_down(b, d, 64);
-    if (lane >= d) a = fminf(a, up);
-    if (lane + d < 64) b = fminf(b, dn);
-  }
+  const float a = prefix_min(h - fl);
+  const float b = suffix_min(h + fl, lane);
   float r = fminf(a + fl, b - fl);
   r = fminf(r, wave_min(h) + trunc);
   return r - wave_min(r);
