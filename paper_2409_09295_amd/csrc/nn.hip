@@ -981,6 +981,36 @@ __global__ void head_fwd_kernel(ActView f, int N, int H, int W, const float* __r
   out[((int64_t)n * 2 + 1) * H * W + r] = o1;
 }
 
+// The same with 16-byte loads when the channels come in whole groups of 8
+// (count, stride and offset multiples of 8): a thread reads its pixel's
+// features 8 at a time, the sums run over the channels in the same order.
+__global__ __launch_bounds__(256) void head_fwd8_kernel(ActView f, int N, int H, int W,
+                                                        const float* __restrict__ w,
+                                                        const float* __restrict__ b,
+                                                        float* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t npix = (int64_t)N * H * W;
+  if (p >= npix) return;
+  const uint16_t* src = f.p + p * f.stride + f.offset;
+  float o0 = b[0], o1 = b[1];
+  for (int c = 0; c < f.c; c += 8) {
+    const uint4 v = *reinterpret_cast<const uint4*>(src + c);
+    const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float lo = __uint_as_float(wd[i] << 16), hi = __uint_as_float(wd[i] & 0xFFFF0000u);
+      o0 += w[c + 2 * i] * lo;
+      o1 += w[f.c + c + 2 * i] * lo;
+      o0 += w[c + 2 * i + 1] * hi;
+      o1 += w[f.c + c + 2 * i + 1] * hi;
+    }
+  }
+  const int n = (int)(p / ((int64_t)H * W));
+  const int64_t r = p - (int64_t)n * H * W;
+  out[((int64_t)n * 2 + 0) * H * W + r] = o0;
+  out[((int64_t)n * 2 + 1) * H * W + r] = o1;
+}
+
 // Head backward: dF[p][c] = sum_k w[k][c] dout[k][p] masked by the feature's
 // ReLU (f > 0); dW, db accumulated with per-block reductions and atomics.
 // Threads (channel lane t % 32, pixel group t / 32): each thread walks every
@@ -1049,6 +1079,86 @@ __global__ __launch_bounds__(256) void head_bwd_kernel(ActView f, int N, int H, 
       unsafeAtomicAdd(&dw[k], sum);
     else
       unsafeAtomicAdd(&db[k - 2 * f.c], sum);
+  }
+}
+
+// Head backward with 16-byte accesses (channel counts, strides and offsets
+// multiples of 8): thread t owns channel group t % G (8 channels, G = C / 8)
+// of pixel t / G of each 256 / G-pixel step (grid-stride), loads and stores
+// its 8 features and gradients at once, and keeps 16 weight partials in
+// registers; the partials of a group are summed over the workgroup in LDS
+// once, then added with one atomic per weight.
+constexpr int kHead8Groups = 8;   // up to 64 channels
+
+__global__ __launch_bounds__(256) void head_bwd8_kernel(ActView f, int N, int H, int W,
+                                                        const float* __restrict__ w,
+                                                        const float* __restrict__ dout,
+                                                        uint16_t* __restrict__ df, int df_stride,
+                                                        float* __restrict__ dw,
+                                                        float* __restrict__ db) {
+  __shared__ float s_red[256][19];
+  const int t = threadIdx.x;
+  const int G = f.c / 8;
+  const int per = 256 / G;          // pixels per step
+  const int cg = t % G, pix = t / G;
+  const bool active = pix < per;    // 256 not a multiple of G: the last threads idle
+  const int64_t npix = (int64_t)N * H * W;
+  const int64_t hw = (int64_t)H * W;
+  float w0[8], w1[8], a0[8], a1[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    w0[i] = w[8 * cg + i];
+    w1[i] = w[f.c + 8 * cg + i];
+    a0[i] = a1[i] = 0.f;
+  }
+  float b0 = 0.f, b1 = 0.f;
+  if (active) {
+    for (int64_t p = (int64_t)blockIdx.x * per + pix; p < npix; p += (int64_t)gridDim.x * per) {
+      const int n = (int)(p / hw);
+      const int64_t r = p - (int64_t)n * hw;
+      const float g0 = dout[((int64_t)n * 2 + 0) * hw + r];
+      const float g1 = dout[((int64_t)n * 2 + 1) * hw + r];
+      if (cg == 0) {
+        b0 += g0;
+        b1 += g1;
+      }
+      const uint4 v = *reinterpret_cast<const uint4*>(f.p + p * f.stride + f.offset + 8 * cg);
+      const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+      uint32_t od[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float lo = __uint_as_float(wd[i] << 16), hi = __uint_as_float(wd[i] & 0xFFFF0000u);
+        a0[2 * i] += g0 * lo;
+        a1[2 * i] += g1 * lo;
+        a0[2 * i + 1] += g0 * hi;
+        a1[2 * i + 1] += g1 * hi;
+        const uint16_t dlo = f2bf(lo > 0.f ? (w0[2 * i] * g0 + w1[2 * i] * g1) : 0.f);
+        const uint16_t dhi = f2bf(hi > 0.f ? (w0[2 * i + 1] * g0 + w1[2 * i + 1] * g1) : 0.f);
+        od[i] = (uint32_t)dlo | ((uint32_t)dhi << 16);
+      }
+      *reinterpret_cast<uint4*>(df + p * df_stride + 8 * cg) = make_uint4(od[0], od[1], od[2], od[3]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    s_red[t][i] = a0[i];
+    s_red[t][8 + i] = a1[i];
+  }
+  s_red[t][16] = b0;   // nonzero in the group-0 threads only
+  s_red[t][17] = b1;
+  __syncthreads();
+  // weight (row, channel 8 g + i): the sum over the threads of group g;
+  // bias k: the sum over the group-0 threads
+  for (int k = t; k < 2 * f.c + 2; k += 256) {
+    float sum = 0.f;
+    if (k < 2 * f.c) {
+      const int row = k / f.c, c = k - row * f.c, g = c / 8, i = c % 8;
+      for (int u = g; u < per * G; u += G) sum += s_red[u][8 * row + i];
+      unsafeAtomicAdd(&dw[k], sum);
+    } else {
+      for (int u = 0; u < per * G; u += G) sum += s_red[u][16 + (k - 2 * f.c)];
+      unsafeAtomicAdd(&db[k - 2 * f.c], sum);
+    }
   }
 }
 
@@ -1264,8 +1374,12 @@ hipError_t nn_f32_to_bf16(const float* src, void* dst, int64_t n, hipStream_t s)
 
 hipError_t nn_head(const gs_act* f, const float* w, const float* b, float* out, hipStream_t s) {
   const int64_t npix = (int64_t)f->n * f->h * f->w;
-  hipLaunchKernelGGL(head_fwd_kernel, dim3(blocks(npix)), dim3(256), 0, s, view(f), f->n, f->h,
-                     f->w, w, b, out);
+  if (f->c % 8 == 0 && f->stride % 8 == 0 && f->offset % 8 == 0)
+    hipLaunchKernelGGL(head_fwd8_kernel, dim3(blocks(npix)), dim3(256), 0, s, view(f), f->n, f->h,
+                       f->w, w, b, out);
+  else
+    hipLaunchKernelGGL(head_fwd_kernel, dim3(blocks(npix)), dim3(256), 0, s, view(f), f->n, f->h,
+                       f->w, w, b, out);
   return hipGetLastError();
 }
 
@@ -1273,6 +1387,14 @@ hipError_t nn_head_bwd(const gs_act* f, const float* w, const float* dout, gs_ac
                        float* db, hipStream_t s) {
   const int64_t npix = (int64_t)f->n * f->h * f->w;
   if (f->c > 32 * kHeadMaxSlots) return hipErrorInvalidValue;
+  if (f->c % 8 == 0 && f->c <= 8 * kHead8Groups && f->stride % 8 == 0 && f->offset % 8 == 0 &&
+      df->stride % 8 == 0 && df->offset % 8 == 0) {
+    const int per = 256 / (f->c / 8);
+    const unsigned nb = (unsigned)std::min<int64_t>((npix + per - 1) / per, 2048);
+    hipLaunchKernelGGL(head_bwd8_kernel, dim3(nb), dim3(256), 0, s, view(f), f->n, f->h, f->w, w,
+                       dout, static_cast<uint16_t*>(df->data) + df->offset, df->stride, dw, db);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(head_bwd_kernel, dim3(std::min<unsigned>(blocks(npix), 1024u)), dim3(256), 0,
                      s, view(f), f->n, f->h,
                      f->w, w, dout, static_cast<uint16_t*>(df->data) + df->offset, df->stride, dw,

@@ -129,9 +129,14 @@ def test_pool_upsample_exact(gs):
     np.testing.assert_array_equal(np_(du.values()), N.bf16_round(sums))
 
 
-def test_head_and_loss(gs):
+@pytest.mark.parametrize("n,h,w,c", [(2, 8, 8, 32), (1, 40, 56, 24), (1, 16, 24, 12), (1, 400, 400, 32)],
+                         ids=["c32", "c24_partial_workgroups", "c12_scalar_path", "c32_grid_stride"])
+def test_head_and_loss(gs, n, h, w, c):
+    """The 1x1 head and its backward against the oracle: channel counts in
+    groups of 8 (16-byte accesses, a workgroup whose 256 threads do not
+    divide into the groups), not (the scalar kernels), and an image large
+    enough that the backward's workgroups loop over several steps."""
     rng = np.random.default_rng(5)
-    n, h, w, c = 2, 8, 8, 32
     f = _bf16(np.maximum(rng.normal(size=(n, h, w, c)), 0))
     hw = torch.as_tensor(rng.normal(size=(2, c)).astype(np.float32))
     hb = torch.as_tensor(np.array([1.0, -5.0], np.float32))
