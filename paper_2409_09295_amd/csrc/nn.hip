@@ -192,24 +192,28 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(
     }
 }
 
-// Direct 3x3 convolution on spatial tiles.  A workgroup computes a 16 x 16
-// pixel tile of one image for BNT output channels; wavefront w computes
+// Direct 3x3 convolution on spatial tiles.  A workgroup computes 16 x 16
+// pixel tiles of one image for BNT output channels; wavefront w computes
 // output rows 4w .. 4w + 3 (each a 16-pixel MFMA row block) for all BNT
 // channels.  Input channels go in chunks of 32: the chunk's 18 x 18 input
 // patch (the tile and its one-pixel halo; zero outside the image) and its
 // 9 x BNT x 32 weights are staged in LDS once, and every tap's A fragments
 // are read from the patch at the tap's offset, so each input value is loaded
-// from memory about 1.3 times instead of nine.  The next chunk's patch and
-// weights are loaded into registers while this chunk's 9 x 4 x BNT/16 MFMAs
-// per wavefront run.
+// from memory about 1.3 times instead of nine.  Workgroups are persistent:
+// workgroup b takes tiles b, b + gridDim.x, ..., and the next (tile, chunk)
+// pair's patch and weights are loaded into registers while this pair's
+// 9 x 4 x BNT/16 MFMAs per wavefront run, so a layer with a single chunk
+// overlaps the next tile's loads with this tile's products and stores.  With
+// a single chunk the weights stay in LDS for all of a workgroup's tiles.
 constexpr int PT = 16;                  // output tile side
 constexpr int PP = PT + 2;              // patch side (with halo)
 constexpr int PCC = 32;                 // input channels per chunk
 constexpr int PPITCH = PCC + 8;         // LDS pitch in bf16 (80 bytes: 16-byte rows, spread banks)
 constexpr int PATCH_CHUNKS = PP * PP * (PCC / 8);   // 16-byte pieces of a patch (1,296)
 
-template <int BNT>
-__global__ __launch_bounds__(256) void conv3x3_patch_kernel(
+// MASKED: the input is multiplied by a ReLU mask (mask > 0) as it is staged.
+template <int BNT, bool MASKED>
+__global__ __launch_bounds__(256, BNT == 32 ? 3 : 2) void conv3x3_patch_kernel(
     ActView x1, ActView x2, ActView mask, int N, int H, int W, const uint16_t* __restrict__ wk,
     int cout, int cin, const float* __restrict__ bias, int relu, uint16_t* __restrict__ y,
     int y_stride, int y_offset, float* __restrict__ yf, int yf_stride) {
@@ -221,15 +225,16 @@ __global__ __launch_bounds__(256) void conv3x3_patch_kernel(
   __shared__ __attribute__((aligned(16))) uint16_t sW[9 * BNT * PPITCH];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int tiles_x = (W + PT - 1) / PT, tiles_y = (H + PT - 1) / PT;
-  const int img = blockIdx.x / (tiles_x * tiles_y);
-  const int trem = blockIdx.x - img * tiles_x * tiles_y;
-  const int ty0 = (trem / tiles_x) * PT, tx0 = (trem % tiles_x) * PT;
+  const int n_tiles = N * tiles_x * tiles_y;
   const int n0 = blockIdx.y * BNT;
   const int nchunks = (cin + PCC - 1) / PCC;
-  const bool masked = mask.p != nullptr;
+  const bool w_resident = nchunks == 1;   // the weights are loaded once per workgroup
   const ActView none = {nullptr, 0, 0, 0};
-  uint4 ra[PA], rm[PA], rb[PB];
-  auto fetch = [&](int chunk) {
+  uint4 ra[PA], rm[MASKED ? PA : 1], rb[PB];
+  auto fetch = [&](int tile, int chunk, bool weights) {
+    const int img = tile / (tiles_x * tiles_y);
+    const int trem = tile - img * tiles_x * tiles_y;
+    const int ty0 = (trem / tiles_x) * PT, tx0 = (trem % tiles_x) * PT;
     const int c0 = chunk * PCC;
 #pragma unroll
     for (int u = 0; u < PA; ++u) {
@@ -241,8 +246,9 @@ __global__ __launch_bounds__(256) void conv3x3_patch_kernel(
                        c0 + cc < cin;
       const int64_t pix = ((int64_t)img * H + sy) * W + sx;
       ra[u] = load8(x1, x2, none, pix, inb, c0 + cc);
-      if (masked) rm[u] = load8(mask, none, none, pix, inb, c0 + cc);
+      if constexpr (MASKED) rm[u] = load8(mask, none, none, pix, inb, c0 + cc);
     }
+    if (!weights) return;
 #pragma unroll
     for (int u = 0; u < PB; ++u) {
       const int q = t + 256 * u;            // piece q: (tap, channel n) = q / 4, inputs 8 (q % 4)
@@ -258,23 +264,25 @@ __global__ __launch_bounds__(256) void conv3x3_patch_kernel(
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < JN; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  fetch(0);
-  for (int chunk = 0; chunk < nchunks; ++chunk) {
-    __syncthreads();   // the previous chunk's fragments have been read
+  // registers -> LDS: the patch, and the weights when they are (re)loaded
+  auto stage = [&](bool weights) {
 #pragma unroll
     for (int u = 0; u < PA; ++u) {
       const int q = t + 256 * u;
-      if (q < PATCH_CHUNKS)
-        *reinterpret_cast<uint4*>(&sP[(q >> 2) * PPITCH + (q & 3) * 8]) =
-            masked ? apply_mask8(ra[u], rm[u]) : ra[u];
+      if (q < PATCH_CHUNKS) {
+        uint4 v = ra[u];
+        if constexpr (MASKED) v = apply_mask8(v, rm[u]);
+        *reinterpret_cast<uint4*>(&sP[(q >> 2) * PPITCH + (q & 3) * 8]) = v;
+      }
     }
+    if (!weights) return;
 #pragma unroll
     for (int u = 0; u < PB; ++u) {
       const int q = t + 256 * u;
       if (q < W_CHUNKS) *reinterpret_cast<uint4*>(&sW[(q >> 2) * PPITCH + (q & 3) * 8]) = rb[u];
     }
-    __syncthreads();
-    if (chunk + 1 < nchunks) fetch(chunk + 1);
+  };
+  auto multiply = [&]() {
 #pragma unroll 1
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap % 3;   // patch offsets of the tap (0 .. 2)
@@ -293,26 +301,67 @@ __global__ __launch_bounds__(256) void conv3x3_patch_kernel(
         for (int j = 0; j < JN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-  }
-  // epilogue: bias, ReLU, bf16 (or float32) store; acc[i][j][r] is output
-  // row 4 wv + i, column 4 (lane / 16) + r, channel n0 + 16 j + lane % 16
+  };
+  // bias, ReLU, bf16 (or float32) store, accumulators cleared; acc[i][j][r] is
+  // output row 4 wv + i, column 4 (lane / 16) + r, channel n0 + 16 j + lane % 16
+  auto epilogue = [&](int tile) {
+    const int img = tile / (tiles_x * tiles_y);
+    const int trem = tile - img * tiles_x * tiles_y;
+    const int ty0 = (trem / tiles_x) * PT, tx0 = (trem % tiles_x) * PT;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int oy = ty0 + 4 * wv + i;
+    for (int i = 0; i < 4; ++i) {
+      const int oy = ty0 + 4 * wv + i;
 #pragma unroll
-    for (int j = 0; j < JN; ++j) {
-      const int co = n0 + j * 16 + (lane & 15);
-      if (oy >= H || co >= cout) continue;
-      const float bco = bias ? bias[co] : 0.f;
-      for (int r = 0; r < 4; ++r) {
-        const int ox = tx0 + 4 * (lane >> 4) + r;
-        if (ox >= W) continue;
-        const int64_t p = ((int64_t)img * H + oy) * W + ox;
-        float v = acc[i][j][r] + bco;
-        if (relu) v = fmaxf(v, 0.f);
-        if (y) y[p * y_stride + y_offset + co] = f2bf(v);
-        if (yf) yf[p * yf_stride + co] = v;
+      for (int j = 0; j < JN; ++j) {
+        const int co = n0 + j * 16 + (lane & 15);
+        if (oy < H && co < cout) {
+          const float bco = bias ? bias[co] : 0.f;
+          for (int r = 0; r < 4; ++r) {
+            const int ox = tx0 + 4 * (lane >> 4) + r;
+            if (ox >= W) continue;
+            const int64_t p = ((int64_t)img * H + oy) * W + ox;
+            float v = acc[i][j][r] + bco;
+            if (relu) v = fmaxf(v, 0.f);
+            if (y) y[p * y_stride + y_offset + co] = f2bf(v);
+            if (yf) yf[p * yf_stride + co] = v;
+          }
+        }
+        acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
       }
+    }
+  };
+  int tile = blockIdx.x;
+  if (tile >= n_tiles) return;   // the grid never exceeds the tiles; uniform over the workgroup
+  fetch(tile, 0, true);
+  if constexpr (MASKED) {
+    // one tile per workgroup: the next chunk's loads overlap this chunk's products
+    for (int chunk = 0; chunk < nchunks; ++chunk) {
+      __syncthreads();   // the previous chunk's fragments have been read
+      stage(true);
+      __syncthreads();
+      if (chunk + 1 < nchunks) fetch(tile, chunk + 1, true);
+      multiply();
+    }
+    epilogue(tile);
+  } else {
+    int chunk = 0;
+    for (bool first = true;; first = false) {
+      __syncthreads();   // the previous pair's fragments have been read
+      stage(first || !w_resident);
+      __syncthreads();
+      // the next (tile, chunk) pair, loaded while this one is multiplied
+      int next_tile = tile, next_chunk = chunk + 1;
+      if (next_chunk == nchunks) {
+        next_chunk = 0;
+        next_tile = tile + (int)gridDim.x;
+      }
+      const bool more = next_tile < n_tiles;
+      if (more) fetch(next_tile, next_chunk, !w_resident);
+      multiply();
+      if (chunk == nchunks - 1) epilogue(tile);
+      if (!more) break;
+      tile = next_tile;
+      chunk = next_chunk;
     }
   }
 }
@@ -1224,6 +1273,24 @@ ActView view(const gs_act* a) {
 
 unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// The unmasked patch convolution is persistent: as many workgroups as the
+// device holds at once (split over the channel tiles), never more than there
+// are tiles.
+template <int BNT, bool MASKED>
+hipError_t launch_patch(ActView x1, ActView x2, ActView mask, int n, int h, int w,
+                        const uint16_t* wp, int cout, int cin, const float* bias, int relu,
+                        uint16_t* yp, int ys, int yo, float* yf, int yf_stride, unsigned tiles,
+                        hipStream_t s) {
+  const unsigned gy = (unsigned)((cout + BNT - 1) / BNT);
+  const int resident = resident_workgroups((const void*)conv3x3_patch_kernel<BNT, MASKED>, 256);
+  unsigned gx = tiles;   // masked calls: one tile per workgroup
+  if (!MASKED && resident > 0)
+    gx = std::min(tiles, std::max(1u, ((unsigned)resident + gy - 1) / gy));
+  hipLaunchKernelGGL((conv3x3_patch_kernel<BNT, MASKED>), dim3(gx, gy), dim3(256), 0, s, x1, x2,
+                     mask, n, h, w, wp, cout, cin, bias, relu, yp, ys, yo, yf, yf_stride);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t nn_conv3x3(const gs_act* x1, const gs_act* x2, const gs_act* mask, const void* w,
@@ -1244,15 +1311,13 @@ hipError_t nn_conv3x3(const gs_act* x1, const gs_act* x2, const gs_act* mask, co
     // 64-channel workgroups would number fewer than 1,024: twice the
     // workgroups, and at 49 KB of LDS three fit a CU (72 KB: two); measured
     // 3% faster on the forward pass of four 640x480 images
-    if (cout <= 32 || tiles * (unsigned)((cout + 63) / 64) < 1024u)
-      hipLaunchKernelGGL((conv3x3_patch_kernel<32>), dim3(tiles, (unsigned)((cout + 31) / 32)),
-                         dim3(256), 0, s, view(x1), view(x2), view(mask), x1->n, x1->h, x1->w, wp,
-                         cout, cin, bias, relu, yp, ys, yo, yf, yf_stride);
-    else
-      hipLaunchKernelGGL((conv3x3_patch_kernel<64>), dim3(tiles, (unsigned)((cout + 63) / 64)),
-                         dim3(256), 0, s, view(x1), view(x2), view(mask), x1->n, x1->h, x1->w, wp,
-                         cout, cin, bias, relu, yp, ys, yo, yf, yf_stride);
-    return hipGetLastError();
+    const bool narrow = cout <= 32 || tiles * (unsigned)((cout + 63) / 64) < 1024u;
+#define GS_PATCH(B, M)                                                                     \
+  launch_patch<B, M>(view(x1), view(x2), view(mask), x1->n, x1->h, x1->w, wp, cout, cin, bias, \
+                     relu, yp, ys, yo, yf, yf_stride, tiles, s)
+    if (narrow) return mask ? GS_PATCH(32, true) : GS_PATCH(32, false);
+    return mask ? GS_PATCH(64, true) : GS_PATCH(64, false);
+#undef GS_PATCH
   }
   const unsigned ntile = (unsigned)((cout + 63) / 64);
   // (the masked backward-data calls measured faster without the large tiles)
