@@ -1307,11 +1307,14 @@ hipError_t nn_conv3x3(const gs_act* x1, const gs_act* x2, const gs_act* mask, co
   const auto* wp = static_cast<const uint16_t*>(w);
   if (cin % 8 == 0 && x1->c % 8 == 0) {
     const unsigned tiles = (unsigned)(x1->n * ((x1->h + PT - 1) / PT) * ((x1->w + PT - 1) / PT));
-    // 32 output channels per workgroup up to 32 channels, and also where
-    // 64-channel workgroups would number fewer than 1,024: twice the
-    // workgroups, and at 49 KB of LDS three fit a CU (72 KB: two); measured
-    // 3% faster on the forward pass of four 640x480 images
-    const bool narrow = cout <= 32 || tiles * (unsigned)((cout + 63) / 64) < 1024u;
+    // 32 output channels per workgroup up to 32 channels, for an odd number
+    // of 32-channel groups (96 channels in 64-channel tiles would waste a
+    // quarter of the products), and also where 64-channel workgroups would
+    // number fewer than 1,024: twice the workgroups, and at 49 KB of LDS three
+    // fit a CU (72 KB: two); measured 3% faster on the forward pass of four
+    // 640x480 images, and the 96-channel backward-data call 2% of the backward
+    const bool narrow =
+        cout <= 32 || cout % 64 == 32 || tiles * (unsigned)((cout + 63) / 64) < 1024u;
 #define GS_PATCH(B, M)                                                                     \
   launch_patch<B, M>(view(x1), view(x2), view(mask), x1->n, x1->h, x1->w, wp, cout, cin, bias, \
                      relu, yp, ys, yo, yf, yf_stride, tiles, s)
