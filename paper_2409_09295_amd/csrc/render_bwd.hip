@@ -232,7 +232,8 @@ __global__ __launch_bounds__(kBlock / PPL) void render_bwd_kernel(
             const float a = ok ? alpha : 0.0f;
             const float Tk = T[k] * __builtin_amdgcn_rcpf(1.0f - a);
             const float wgt = a * Tk;
-            const float dot = (app.z * dC0[k] + app.w * dC1[k] + ext.x * dC2[k]) - sdc[k];
+            const float dot = __builtin_fmaf(
+                ext.x, dC2[k], __builtin_fmaf(app.w, dC1[k], __builtin_fmaf(app.z, dC0[k], -sdc[k])));
             const float dalpha = Tk * dot;   // (c - S) . dL/dC
             // colour behind the next splat in front: S + alpha (c - S)
             sdc[k] = __builtin_fmaf(a, dot, sdc[k]);

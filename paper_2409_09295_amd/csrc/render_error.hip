@@ -115,7 +115,7 @@ __global__ __launch_bounds__(64) void render_error_kernel(
               eval_alpha_at<false>(ct[kk % NC], geo, app, fpy[kk], alpha, raw, G, dy) && pos < last[kk];
           if (ok) {
             part += (alpha * T[kk]) * resid[kk];
-            T[kk] = T[kk] * (1.0f - alpha);
+            T[kk] = __builtin_fmaf(-T[kk], alpha, T[kk]);   // as the forward computes it
           }
         }
         if (!__ballot(part != 0.0f)) continue;

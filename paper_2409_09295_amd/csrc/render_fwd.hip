@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kBlock / PPL, PPL == 4 && SPL == 1 && L1 && !Q ? 7 
             float alpha, raw, G, dy;
             const bool ok = eval_alpha_at<false>(ct[k % NC], geo, app, fpy[k], alpha, raw, G, dy);
             // a terminated pixel (T < 0) gets Tn <= 0 < kTMin: it never blends again
-            const float Tn = T[k] * (1.0f - alpha);
+            const float Tn = __builtin_fmaf(-T[k], alpha, T[k]);   // T (1 - alpha), one rounding
             const bool term = ok && Tn < kTMin;   // stops before this splat
             if (term) T[k] = -fabsf(T[k]);
             if (!ok || term) continue;
