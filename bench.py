@@ -55,8 +55,8 @@ VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 # Wave-level overheads (LDS staging, the 9-value reduction and its atomics,
 # loop control) are not counted: they are what separates the achieved rate
 # from the peak.
-BWD_VALU_EVAL, BWD_VALU_BLEND = 12, 27
-FWD_VALU_EVAL, FWD_VALU_BLEND = 16, 4
+BWD_VALU_EVAL, BWD_VALU_BLEND = 12, 26
+FWD_VALU_EVAL, FWD_VALU_BLEND = 15, 4
 # Fraction of walked pairs that are blended, measured by the oracle on the
 # 200k-Gaussian room at 640x480 (used when the oracle leg is skipped).
 DEFAULT_BLEND_FRACTION = 0.44
