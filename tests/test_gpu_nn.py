@@ -61,6 +61,46 @@ def test_conv3x3_forward(gs, case):
     np.testing.assert_array_equal(np_(ry.values()), expect)
 
 
+# More 16 x 16 tiles than the device holds workgroups, so each workgroup of the
+# (unmasked, persistent) convolution loops over several tiles: one 32-channel
+# chunk (weights kept in LDS), two chunks (weights reloaded per chunk), and
+# 64-channel tiles over two channel blocks.
+PERSISTENT_CASES = [
+    # (n, h, w, cin, cout)
+    (8, 160, 400, 32, 32),
+    (4, 160, 400, 64, 64),
+    (4, 160, 400, 32, 128),
+]
+
+
+@pytest.mark.parametrize("case", PERSISTENT_CASES)
+def test_conv3x3_forward_many_tiles(gs, case):
+    n, h, w, cin, cout = case
+    rng = np.random.default_rng(sum(case))
+    x = _bf16(rng.normal(size=(n, h, w, cin)))
+    wt = _bf16(rng.normal(size=(9, cout, cin)) / np.sqrt(9 * cin))
+    b = torch.as_tensor(rng.normal(size=cout).astype(np.float32))
+    yf = torch.zeros(n * h * w, cout, device=DEV)
+    y = gs.Act.empty(n, h, w, cout, DEV)
+    gs.gs_nn_conv3x3(_act(gs, x), None, None, wt.to(DEV), cout, b.to(DEV), False, y, yf, cout)
+    torch.cuda.synchronize()
+    got = np_(yf).reshape(n, h, w, cout)
+    xd, wd, bd = _f64(x), _f64(wt), b.double()
+    # the oracle on bands of rows (each with its true neighbour rows), the
+    # image's first and last rows included, in the first and last images
+    for img in (0, n - 1):
+        for r0 in (0, 72, h - 8):
+            r1 = r0 + 8
+            lo, hi = max(r0 - 1, 0), min(r1 + 1, h)
+            crop = xd[img:img + 1, lo:hi]
+            ref = N.conv3x3(crop, wd, bd)[0, r0 - lo:r1 - lo].numpy()
+            scale = (N.conv3x3(crop.abs(), wd.abs()) + bd.abs())[0, r0 - lo:r1 - lo].numpy()
+            assert (np.abs(got[img, r0:r1] - ref) <= 1e-5 * scale + 1e-7).all(), (case, img, r0)
+    # every tile was written (the float32 output started at zero; a pixel with
+    # no tile would keep exact zeros in all channels)
+    assert (np.abs(got).sum(axis=3) > 0).all()
+
+
 BWD_CASES = [
     # (n, h, w, cin1, cin2, cout)
     (1, 12, 10, 64, 0, 32),     # rows narrower than one 64-pixel stage
