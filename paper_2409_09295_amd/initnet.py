@@ -460,7 +460,7 @@ def main(argv=None) -> None:
     ap.add_argument("--height", type=int, default=480)
     ap.add_argument("--train", type=int, default=5000)
     ap.add_argument("--heldout", type=int, default=500)
-    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
